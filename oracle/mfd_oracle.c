@@ -1,0 +1,766 @@
+/*
+ * FP64 CPU oracle for the explicit EDF-based MesoFD / MMFD time step
+ * (Shi, Du & Chai, "Equilibrium-distribution-function based mesoscopic
+ * finite-difference methods for partial differential equations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; it is used by the test suite, by the smoke check and by the
+ * CPU-baseline leg of the benchmark.  It shares no code, header, table or
+ * constant generator with the GPU library.
+ *
+ * It is deliberately plain: whole-grid loops in IEEE binary64, no blocking,
+ * no fusion, periodic wrap by modular indexing.  Build with
+ *   gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
+ * so that every a*b+c below is a rounded multiply followed by a rounded add.
+ * OpenMP only splits the outer node loop; every node's arithmetic is the same
+ * with any thread count, so results are bitwise independent of threads.
+ *
+ * Notation (lattice units, c = dx/dt = 1, c_s^2 = d0):
+ *   e_j, w_j      lattice velocities and weights (Appendix A; D1Q3 from the
+ *                 pattern w_j = d0/2, w_0 = 1 - 2 sum w_j of Eq. (LMMFD-4))
+ *   a_k, ah_k     scheme coefficients at time levels t and t-dt, k = -1,0,+1
+ *                 (three-level notation of Eq. (3layer-1)); a two-level
+ *                 explicit scheme is the case ah = 0.
+ *   g_j(A,B,C)    quadratic EDF of Eqs. (3-3)/(3-4):
+ *                 w_j [ A + e_j.B/d0 + sum_a C_aa (e_ja^2-d0)/(d0(1-d0))
+ *                       + sum_{a!=b} C_ab e_ja e_jb /(2 d0^2) ]
+ *   g+_p, g-_p    even / odd parts of g over an opposite pair p=(j, jbar),
+ *                 Eq. (2-5): g+ = w (A + Q:C), g- = w e.B/d0 (the split of
+ *                 Eq. (TforMMFD-2) applied to the general EDF).
+ *
+ * Every floating-point expression is evaluated left to right in the order
+ * written; sums over lattice directions run in Appendix-A order, over k in
+ * the order -1, 0, +1, level t before level t-dt.
+ *
+ * Parity status: every function below is pinned by a CPU test (Fourier
+ * symbol, FTCS identity, textbook LBGK equilibrium, EDF moment identities,
+ * exact rational brute force, conservation, convergence to analytic
+ * solutions).  The paper's Table 2/3 error values are NOT reproduced and are
+ * not used as pins.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_D1Q3 = 1, ORC_D2Q5 = 2, ORC_D2Q9 = 3, ORC_D3Q19 = 4 };
+enum { ORC_LCDE = 0, ORC_BURGERS = 1, ORC_NSE = 2 };
+
+#define ORC_MAXQ 19
+#define ORC_MAXP 9
+
+typedef struct {
+    int32_t lattice;      /* ORC_D1Q3 ...                                    */
+    int32_t eq;           /* ORC_LCDE / ORC_BURGERS / ORC_NSE                */
+    int32_t levels;       /* 2: two-level explicit, 3: three-level explicit  */
+    int32_t lambda_bar;   /* LCDE: 1 adds u u to C (Eq. TforMMFD-0)          */
+    int32_t he_luo;       /* NSE: C = j j / rho0 (Remark 4)                  */
+    int32_t nthreads;     /* 0: OpenMP default                               */
+    int32_t theta_iters;  /* Jacobi sweeps per theta step                    */
+    int32_t pad_;
+    int64_t n[3];         /* nodes along x, y, z (x fastest)                 */
+    double d0, dx, dt;
+    double u[3];          /* LCDE advection velocity (physical)              */
+    double K[9];          /* LCDE diffusion tensor (physical, row major)     */
+    double beta;          /* NCDE: D = phi I scaled by beta (Eq. NCDEfeq)    */
+    double rho0;          /* NSE: reference density; the state holds rho-rho0*/
+    double a[3], ah[3];   /* k = -1, 0, +1 at level t and t-dt               */
+    double ab[3], abh[3]; /* momentum parameter set of Eq. (2-4)             */
+    double theta;         /* weight of the old level, Eq. (GCN)              */
+} orc_params;
+
+typedef struct {
+    int dim, b, npair;
+    int e[ORC_MAXQ][3];
+    double w[ORC_MAXQ];
+    int opp[ORC_MAXQ];
+    int pair[ORC_MAXP];   /* representative direction of each opposite pair */
+} orc_lattice;
+
+/* ---------------------------------------------------------------- lattices */
+
+static void set_e(orc_lattice *L, int j, int x, int y, int z)
+{
+    L->e[j][0] = x; L->e[j][1] = y; L->e[j][2] = z;
+}
+
+/* Appendix A with d0_alpha = d0 on every axis (square / cubic grids). */
+static int build_lattice(int lattice, double d0, orc_lattice *L)
+{
+    memset(L, 0, sizeof(*L));
+    if (lattice == ORC_D1Q3) {
+        L->dim = 1; L->b = 3;
+        set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, -1, 0, 0);
+        L->w[0] = 1.0 - d0;
+        L->w[1] = d0 / 2.0;
+        L->w[2] = d0 / 2.0;
+    } else if (lattice == ORC_D2Q5) {
+        L->dim = 2; L->b = 5;
+        set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
+        set_e(L, 3, -1, 0, 0); set_e(L, 4, 0, -1, 0);
+        L->w[0] = 1.0 - d0 - d0;
+        L->w[1] = d0 / 2.0; L->w[3] = L->w[1];
+        L->w[2] = d0 / 2.0; L->w[4] = L->w[2];
+    } else if (lattice == ORC_D2Q9) {
+        L->dim = 2; L->b = 9;
+        set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
+        set_e(L, 3, -1, 0, 0); set_e(L, 4, 0, -1, 0); set_e(L, 5, 1, 1, 0);
+        set_e(L, 6, -1, 1, 0); set_e(L, 7, -1, -1, 0); set_e(L, 8, 1, -1, 0);
+        L->w[0] = (1.0 - d0) * (1.0 - d0);
+        L->w[1] = d0 * (1.0 - d0) / 2.0; L->w[3] = L->w[1];
+        L->w[2] = (1.0 - d0) * d0 / 2.0; L->w[4] = L->w[2];
+        L->w[5] = d0 * d0 / 4.0;
+        L->w[6] = L->w[5]; L->w[7] = L->w[5]; L->w[8] = L->w[5];
+    } else if (lattice == ORC_D3Q19) {
+        /* The xz-edge block of the printed table repeats two velocities; the
+         * edge sets here follow the xy pattern (+,+),(-,+),(-,-),(+,-). */
+        static const int E[19][3] = {
+            {0,0,0}, {1,0,0}, {0,1,0}, {0,0,1}, {-1,0,0}, {0,-1,0}, {0,0,-1},
+            {1,1,0}, {-1,1,0}, {-1,-1,0}, {1,-1,0},
+            {1,0,1}, {-1,0,1}, {-1,0,-1}, {1,0,-1},
+            {0,1,1}, {0,-1,1}, {0,-1,-1}, {0,1,-1}};
+        L->dim = 3; L->b = 19;
+        for (int j = 0; j < 19; ++j) set_e(L, j, E[j][0], E[j][1], E[j][2]);
+        L->w[0] = 1.0 - d0 - d0 - d0 + d0 * d0 + d0 * d0 + d0 * d0;
+        double w1 = d0 * (1.0 - d0 - d0) / 2.0;
+        double we = d0 * d0 / 4.0;
+        for (int j = 1; j <= 6; ++j) L->w[j] = w1;
+        for (int j = 7; j <= 18; ++j) L->w[j] = we;
+    } else {
+        return -1;
+    }
+    /* opposite directions and pair representatives (first of each pair) */
+    for (int j = 0; j < L->b; ++j) {
+        L->opp[j] = -1;
+        for (int i = 0; i < L->b; ++i)
+            if (L->e[i][0] == -L->e[j][0] && L->e[i][1] == -L->e[j][1] &&
+                L->e[i][2] == -L->e[j][2])
+                L->opp[j] = i;
+    }
+    for (int j = 1; j < L->b; ++j)
+        if (L->opp[j] > j) L->pair[L->npair++] = j;
+    return 0;
+}
+
+/* ------------------------------------------------- derived constant tables */
+
+typedef struct {
+    orc_lattice L;
+    int dim;
+    int64_t n[3], N;
+    double inv_d0;
+    double qd[ORC_MAXQ][3];   /* (e_a^2 - d0) / (d0 (1 - d0))                */
+    double qo[ORC_MAXQ][3];   /* e_a e_b / d0^2 for (a,b) = (0,1),(0,2),(1,2)*/
+    double w1[ORC_MAXQ];      /* w_j / d0                                    */
+    /* scheme */
+    double A0, Ah0, Ab0, Abh0;
+    double ap, am, ahp, ahm;      /* a+ = a_1 + a_-1, a- = a_1 - a_-1       */
+    double abp, abm, abhp, abhm;  /* same for the momentum set              */
+    /* LCDE */
+    double uh[3], kh[9], Ch[9];
+    double ubar[ORC_MAXQ];        /* full  g_j(1, uh, Ch)                    */
+    double ubp[ORC_MAXP], ubm[ORC_MAXP];   /* even / odd parts per pair      */
+    double Cp[ORC_MAXP], Cm[ORC_MAXP], Chp[ORC_MAXP], Chm[ORC_MAXP];
+    /* Burgers */
+    double bh, cbeta;
+    int beta_one;
+    /* NSE */
+    double rho0, rinv0;
+    int he_luo;
+} orc_ctx;
+
+static const int OFF_A[3] = {0, 0, 1};
+static const int OFF_B[3] = {1, 2, 2};
+
+/* sum_a qd_ja C_aa + sum_{a<b} qo_jab C_ab, accumulated left to right */
+static double quad_term(const orc_ctx *c, int j, const double *C)
+{
+    int d = c->dim;
+    double t = c->qd[j][0] * C[0];
+    for (int a = 1; a < d; ++a) t = t + c->qd[j][a] * C[a * 3 + a];
+    int no = d == 1 ? 0 : (d == 2 ? 1 : 3);
+    for (int o = 0; o < no; ++o) {
+        if (c->qo[j][o] != 0.0) t = t + c->qo[j][o] * C[OFF_A[o] * 3 + OFF_B[o]];
+    }
+    return t;
+}
+
+/* e_j . B with e in {-1,0,1}: signed accumulation from zero */
+static double edot(const orc_ctx *c, int j, const double *B)
+{
+    double s = 0.0;
+    for (int a = 0; a < c->dim; ++a) {
+        int e = c->L.e[j][a];
+        if (e == 1) s = s + B[a];
+        else if (e == -1) s = s - B[a];
+    }
+    return s;
+}
+
+static int make_ctx(const orc_params *P, orc_ctx *c)
+{
+    memset(c, 0, sizeof(*c));
+    if (build_lattice(P->lattice, P->d0, &c->L)) return -1;
+    c->dim = c->L.dim;
+    c->N = 1;
+    for (int a = 0; a < 3; ++a) {
+        c->n[a] = a < c->dim ? P->n[a] : 1;
+        if (c->n[a] < 1) return -2;
+        c->N *= c->n[a];
+    }
+    const double d0 = P->d0;
+    c->inv_d0 = 1.0 / d0;
+    for (int j = 0; j < c->L.b; ++j) {
+        for (int a = 0; a < 3; ++a) {
+            double ea = (double)c->L.e[j][a];
+            c->qd[j][a] = (ea * ea - d0) / (d0 * (1.0 - d0));
+        }
+        for (int o = 0; o < 3; ++o)
+            c->qo[j][o] = (double)(c->L.e[j][OFF_A[o]] * c->L.e[j][OFF_B[o]]) / (d0 * d0);
+        c->w1[j] = c->L.w[j] * c->inv_d0;
+    }
+    /* scheme sums, Eq. (2-7-1) */
+    c->A0 = P->a[0] + P->a[1] + P->a[2];
+    c->Ah0 = P->ah[0] + P->ah[1] + P->ah[2];
+    c->Ab0 = P->ab[0] + P->ab[1] + P->ab[2];
+    c->Abh0 = P->abh[0] + P->abh[1] + P->abh[2];
+    c->ap = P->a[2] + P->a[0];    c->am = P->a[2] - P->a[0];
+    c->ahp = P->ah[2] + P->ah[0]; c->ahm = P->ah[2] - P->ah[0];
+    c->abp = P->ab[2] + P->ab[0]; c->abm = P->ab[2] - P->ab[0];
+    c->abhp = P->abh[2] + P->abh[0]; c->abhm = P->abh[2] - P->abh[0];
+
+    if (P->eq == ORC_LCDE) {
+        /* Eq. (4-2-00a): A10 = -(ah sum) - 1, A22 = (a+ + ah+)/2; the EDF
+         * diffusion tensor follows alpha = -(A22/A10) dt beta c_s^2. */
+        double A10 = -c->Ah0 - 1.0;
+        double A22 = 0.5 * (c->ap + c->ahp);
+        double ratio = -A10 / A22;
+        for (int a = 0; a < 3; ++a) c->uh[a] = P->u[a] * P->dt / P->dx;
+        for (int i = 0; i < 9; ++i) c->kh[i] = P->K[i] * P->dt / (P->dx * P->dx);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double v = ratio * c->kh[a * 3 + b];
+                if (a == b) v = v - d0;
+                if (P->lambda_bar) v = v + c->uh[a] * c->uh[b];
+                c->Ch[a * 3 + b] = v;
+            }
+        for (int j = 0; j < c->L.b; ++j) {
+            double eu = edot(c, j, c->uh);
+            c->ubar[j] = c->L.w[j] * ((1.0 + eu * c->inv_d0) + quad_term(c, j, c->Ch));
+        }
+        for (int p = 0; p < c->L.npair; ++p) {
+            int j = c->L.pair[p];
+            c->ubp[p] = c->L.w[j] * (1.0 + quad_term(c, j, c->Ch));
+            c->ubm[p] = c->w1[j] * edot(c, j, c->uh);
+            c->Cp[p] = c->ap * c->ubp[p];
+            c->Cm[p] = c->am * c->ubm[p];
+            c->Chp[p] = c->ahp * c->ubp[p];
+            c->Chm[p] = c->ahm * c->ubm[p];
+        }
+    } else if (P->eq == ORC_BURGERS) {
+        c->bh = 0.5 * P->dt / P->dx;
+        c->beta_one = P->beta == 1.0;
+        c->cbeta = (P->beta - 1.0) * d0;
+    } else if (P->eq == ORC_NSE) {
+        c->rho0 = P->rho0;
+        c->he_luo = P->he_luo;
+        c->rinv0 = 1.0 / P->rho0;
+    } else {
+        return -3;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ grid helpers */
+
+static inline int64_t wrap(int64_t i, int64_t n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* index of node (x,y,z) shifted by k*e_j, periodic */
+static inline int64_t nb(const orc_ctx *c, int64_t x, int64_t y, int64_t z, int j, int k)
+{
+    int64_t xs = wrap(x + k * c->L.e[j][0], c->n[0]);
+    int64_t ys = wrap(y + k * c->L.e[j][1], c->n[1]);
+    int64_t zs = wrap(z + k * c->L.e[j][2], c->n[2]);
+    return (zs * c->n[1] + ys) * c->n[0] + xs;
+}
+
+static int nfields(const orc_params *P, const orc_ctx *c)
+{
+    return P->eq == ORC_NSE ? 1 + c->dim : 1;
+}
+
+/* EDF arguments (A, B, C) at one node from its moments m[0..nf-1] */
+static void edf_args(const orc_ctx *c, int eq, const double *m, double *A,
+                     double B[3], double C[9], int *hasC)
+{
+    memset(C, 0, 9 * sizeof(double));
+    B[0] = B[1] = B[2] = 0.0;
+    *A = m[0];
+    *hasC = 1;
+    if (eq == ORC_BURGERS) {
+        double bh = (m[0] * m[0]) * c->bh;
+        for (int a = 0; a < c->dim; ++a) B[a] = bh;
+        if (c->beta_one) {
+            *hasC = 0;
+        } else {
+            for (int a = 0; a < c->dim; ++a) C[a * 3 + a] = c->cbeta * m[0];
+        }
+    } else { /* NSE: A = rho - rho0, B = j, C = j j / rho */
+        double r = c->he_luo ? c->rinv0 : 1.0 / (c->rho0 + m[0]);
+        for (int a = 0; a < c->dim; ++a) B[a] = m[1 + a];
+        for (int a = 0; a < c->dim; ++a)
+            for (int b = 0; b < c->dim; ++b)
+                C[a * 3 + b] = (B[a] * B[b]) * r;
+    }
+}
+
+/* full EDF g_j(A,B,C), Eq. (3-3) */
+static double edf_full(const orc_ctx *c, int j, double A, const double *B,
+                       const double *C, int hasC)
+{
+    double t = A + edot(c, j, B) * c->inv_d0;
+    if (hasC) t = t + quad_term(c, j, C);
+    return c->L.w[j] * t;
+}
+
+/* ------------------------------------------------------------------- MMFD */
+
+static double d2(const double *g, int64_t ip, int64_t i0, int64_t im)
+{
+    return (g[ip] - 2.0 * g[i0]) + g[im];
+}
+
+static double d1(const double *g, int64_t ip, int64_t im)
+{
+    return g[ip] - g[im];
+}
+
+/* even / odd pair EDF parts of one level over the whole grid:
+ * Fp[p*N + i] = w_p (A + Q_p:C),  Fm[p*N + i] = (w_p/d0) e_p.B              */
+static void pair_parts(const orc_params *P, const orc_ctx *c, const double *lev,
+                       double *Fp, double *Fm)
+{
+    const int64_t N = c->N;
+    const int nf = nfields(P, c);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double m[4], A, B[3], C[9];
+        int hasC;
+        for (int f = 0; f < nf; ++f) m[f] = lev[f * N + i];
+        edf_args(c, P->eq, m, &A, B, C, &hasC);
+        for (int p = 0; p < c->L.npair; ++p) {
+            int j = c->L.pair[p];
+            double t = A;
+            if (hasC) t = t + quad_term(c, j, C);
+            Fp[p * N + i] = c->L.w[j] * t;
+            Fm[p * N + i] = c->w1[j] * edot(c, j, B);
+        }
+    }
+}
+
+/*
+ * One MMFD step, central form Eq. (2-2-1) / (2-4-1), three-level form
+ * Eq. (3layerMMFD-2); the LCDE uses the linear pair form Eq. (LMMFD-1/3)
+ * with the constants (a_1 +- a_-1) ubar+-_p folded per pair.
+ *   cur  : level t      (nf fields, field-major)
+ *   prev : level t - dt (ignored for two-level)
+ *   out  : level t + dt
+ */
+int orc_mmfd_step(const orc_params *P, const double *cur, const double *prev, double *out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    const int64_t N = c.N;
+    const int three = P->levels == 3;
+    const int np = c.L.npair;
+
+    if (P->eq == ORC_LCDE) {
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int64_t z = 0; z < c.n[2]; ++z)
+            for (int64_t y = 0; y < c.n[1]; ++y)
+                for (int64_t x = 0; x < c.n[0]; ++x) {
+                    int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                    double acc = 0.0;
+                    for (int p = 0; p < np; ++p) {
+                        int j = c.L.pair[p];
+                        int64_t ip = nb(&c, x, y, z, j, 1), im = nb(&c, x, y, z, j, -1);
+                        acc = acc + c.Cp[p] * d2(cur, ip, i, im);
+                        acc = acc + c.Cm[p] * d1(cur, ip, im);
+                    }
+                    if (three) {
+                        for (int p = 0; p < np; ++p) {
+                            int j = c.L.pair[p];
+                            int64_t ip = nb(&c, x, y, z, j, 1), im = nb(&c, x, y, z, j, -1);
+                            acc = acc + c.Chp[p] * d2(prev, ip, i, im);
+                            acc = acc + c.Chm[p] * d1(prev, ip, im);
+                        }
+                    }
+                    double base = c.A0 * cur[i];
+                    if (three) base = base + c.Ah0 * prev[i];
+                    out[i] = base + acc;
+                }
+        return 0;
+    }
+
+    /* nonlinear EDFs: pair parts of each level, then central differences */
+    double *Fp = malloc(sizeof(double) * np * N), *Fm = malloc(sizeof(double) * np * N);
+    double *Hp = NULL, *Hm = NULL;
+    if (!Fp || !Fm) { free(Fp); free(Fm); return -4; }
+    pair_parts(P, &c, cur, Fp, Fm);
+    /* a level-(t-dt) stencil exists only if one of its pair sums is nonzero;
+     * skipping an all-zero term leaves every finite value unchanged */
+    const int three_st = three && (c.ahp != 0.0 || c.ahm != 0.0 ||
+                                   c.abhp != 0.0 || c.abhm != 0.0);
+    if (three_st) {
+        Hp = malloc(sizeof(double) * np * N);
+        Hm = malloc(sizeof(double) * np * N);
+        if (!Hp || !Hm) { free(Fp); free(Fm); free(Hp); free(Hm); return -4; }
+        pair_parts(P, &c, prev, Hp, Hm);
+    }
+    const int nf = nfields(P, &c);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                int64_t ip[ORC_MAXP], im[ORC_MAXP];
+                for (int p = 0; p < np; ++p) {
+                    ip[p] = nb(&c, x, y, z, c.L.pair[p], 1);
+                    im[p] = nb(&c, x, y, z, c.L.pair[p], -1);
+                }
+                /* zeroth moment: a+ D2 F+ + a- D1 F- */
+                double acc = 0.0;
+                for (int p = 0; p < np; ++p) {
+                    acc = acc + c.ap * d2(Fp + p * N, ip[p], i, im[p]);
+                    acc = acc + c.am * d1(Fm + p * N, ip[p], im[p]);
+                }
+                if (three_st)
+                    for (int p = 0; p < np; ++p) {
+                        acc = acc + c.ahp * d2(Hp + p * N, ip[p], i, im[p]);
+                        acc = acc + c.ahm * d1(Hm + p * N, ip[p], im[p]);
+                    }
+                double base = c.A0 * cur[i];
+                if (three) base = base + c.Ah0 * prev[i];
+                out[i] = base + acc;
+                /* first moments (NSE): e_p [ab+ D2 F- + ab- D1 F+] */
+                for (int f = 1; f < nf; ++f) {
+                    int a = f - 1;
+                    double m = 0.0;
+                    for (int p = 0; p < np; ++p) {
+                        int e = c.L.e[c.L.pair[p]][a];
+                        if (e == 0) continue;
+                        double t1 = c.abp * d2(Fm + p * N, ip[p], i, im[p]);
+                        double t2 = c.abm * d1(Fp + p * N, ip[p], im[p]);
+                        if (e == 1) { m = m + t1; m = m + t2; }
+                        else        { m = m - t1; m = m - t2; }
+                    }
+                    if (three_st)
+                        for (int p = 0; p < np; ++p) {
+                            int e = c.L.e[c.L.pair[p]][a];
+                            if (e == 0) continue;
+                            double t1 = c.abhp * d2(Hm + p * N, ip[p], i, im[p]);
+                            double t2 = c.abhm * d1(Hp + p * N, ip[p], im[p]);
+                            if (e == 1) { m = m + t1; m = m + t2; }
+                            else        { m = m - t1; m = m - t2; }
+                        }
+                    double bj = c.Ab0 * cur[f * N + i];
+                    if (three) bj = bj + c.Abh0 * prev[f * N + i];
+                    out[f * N + i] = bj + m;
+                }
+            }
+    free(Fp); free(Fm); free(Hp); free(Hm);
+    return 0;
+}
+
+/* ----------------------------------------------------------------- LITERAL */
+
+/* full EDF of every direction of one level over the grid: G[j*N + i] */
+static void full_edf(const orc_params *P, const orc_ctx *c, const double *lev, double *G)
+{
+    const int64_t N = c->N;
+    const int nf = nfields(P, c);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        if (P->eq == ORC_LCDE) {
+            for (int j = 0; j < c->L.b; ++j) G[j * N + i] = c->ubar[j] * lev[i];
+            continue;
+        }
+        double m[4], A, B[3], C[9];
+        int hasC;
+        for (int f = 0; f < nf; ++f) m[f] = lev[f * N + i];
+        edf_args(c, P->eq, m, &A, B, C, &hasC);
+        for (int j = 0; j < c->L.b; ++j) G[j * N + i] = edf_full(c, j, A, B, C, hasC);
+    }
+}
+
+/*
+ * The scheme taken literally, Eqs. (2-2)/(2-3)/(2-4)/(3layerMMFD-1):
+ *   phi(x, t+dt) = sum_j sum_(k,level) a_k f_j^eq(x + k e_j, level)
+ * and for the NSE first moments the same with e_j and the momentum set.
+ */
+int orc_literal_step(const orc_params *P, const double *cur, const double *prev, double *out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    const int64_t N = c.N;
+    const int three = P->levels == 3;
+    const int b = c.L.b;
+    const int nf = nfields(P, &c);
+    double *G = malloc(sizeof(double) * b * N), *H = NULL;
+    if (!G) return -4;
+    full_edf(P, &c, cur, G);
+    if (three) {
+        H = malloc(sizeof(double) * b * N);
+        if (!H) { free(G); return -4; }
+        full_edf(P, &c, prev, H);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                for (int f = 0; f < nf; ++f) {
+                    const double *ak = f == 0 ? P->a : P->ab;
+                    const double *ahk = f == 0 ? P->ah : P->abh;
+                    double s = 0.0;
+                    for (int j = 0; j < b; ++j) {
+                        int e = f == 0 ? 1 : c.L.e[j][f - 1];
+                        if (e == 0) continue;
+                        double fj = 0.0;
+                        for (int k = -1; k <= 1; ++k)
+                            if (ak[k + 1] != 0.0) fj = fj + ak[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
+                        if (three)
+                            for (int k = -1; k <= 1; ++k)
+                                if (ahk[k + 1] != 0.0) fj = fj + ahk[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                        s = e == 1 ? s + fj : s - fj;
+                    }
+                    out[f * N + i] = s;
+                }
+            }
+    free(G); free(H);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ MesoFD */
+
+/* populations of the EDF of a moment state: pop[j*N + i] = f_j^eq(i) */
+int orc_init_populations(const orc_params *P, const double *mom, double *pop)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    full_edf(P, &c, mom, pop);
+    return 0;
+}
+
+/* moments of populations, Eq. (2-1-1): phi = sum_j f_j, j = sum_j e_j f_j */
+int orc_moments(const orc_params *P, const double *pop, double *mom)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    const int64_t N = c.N;
+    const int nf = nfields(P, &c);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        for (int f = 0; f < nf; ++f) {
+            double s = 0.0;
+            for (int j = 0; j < c.L.b; ++j) {
+                int e = f == 0 ? 1 : c.L.e[j][f - 1];
+                if (e == 1) s = s + pop[j * N + i];
+                else if (e == -1) s = s - pop[j * N + i];
+            }
+            mom[f * N + i] = s;
+        }
+    }
+    return 0;
+}
+
+/*
+ * One MesoFD step, Eq. (2-1) / (3layer-1):
+ *   f_j(x, t+dt) = sum_k a_k f_j^eq(x + k e_j, t) + sum_k ah_k f_j^eq(x + k e_j, t-dt)
+ * with f^eq at level t built from the moments of the populations `pop` and
+ * at level t-dt from the stored moments `prev_mom` (three-level only).
+ * Writes the new populations and, for three-level schemes, the moments of
+ * level t (the t-dt level of the next step) into `mom_out`.
+ */
+int orc_mesofd_step(const orc_params *P, const double *pop, const double *prev_mom,
+                    double *pop_out, double *mom_out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+    const int64_t N = c.N;
+    const int b = c.L.b;
+    const int nf = nfields(P, &c);
+    const int three = P->levels == 3;
+    double *mom = malloc(sizeof(double) * nf * N);
+    double *G = malloc(sizeof(double) * b * N), *H = NULL;
+    if (!mom || !G) { free(mom); free(G); return -4; }
+    orc_moments(P, pop, mom);
+    full_edf(P, &c, mom, G);
+    if (three) {
+        H = malloc(sizeof(double) * b * N);
+        if (!H) { free(mom); free(G); return -4; }
+        full_edf(P, &c, prev_mom, H);
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                for (int j = 0; j < b; ++j) {
+                    double fj = 0.0;
+                    for (int k = -1; k <= 1; ++k)
+                        if (P->a[k + 1] != 0.0) fj = fj + P->a[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
+                    if (three)
+                        for (int k = -1; k <= 1; ++k)
+                            if (P->ah[k + 1] != 0.0) fj = fj + P->ah[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                    pop_out[j * N + i] = fj;
+                }
+            }
+    if (mom_out) memcpy(mom_out, mom, sizeof(double) * nf * N);
+    free(mom); free(G); free(H);
+    return 0;
+}
+
+/* --------------------------------------------------------- theta (linear) */
+
+/*
+ * Two-level theta scheme for the LCDE, Eq. (GCN):
+ *   (I - (1-theta) L) phi(t+dt) = (A0 I + theta L) phi(t),   A0 = sum_k a_k,
+ * L = the explicit increment of Eq. (LMMFD-3).  Solved by `theta_iters`
+ * Jacobi sweeps started from phi(t).
+ */
+int orc_theta_step(const orc_params *P, const double *cur, double *out, double *work)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c) || P->eq != ORC_LCDE) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    const int64_t N = c.N;
+    const int np = c.L.npair;
+    const double th = P->theta, th1 = 1.0 - P->theta;
+    double sp = 0.0;
+    for (int p = 0; p < np; ++p) sp = sp + c.Cp[p];
+    const double inv_den = 1.0 / (1.0 + th1 * (2.0 * sp));
+    double *rhs = malloc(sizeof(double) * N);
+    if (!rhs) return -4;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                double acc = 0.0;
+                for (int p = 0; p < np; ++p) {
+                    int j = c.L.pair[p];
+                    int64_t ip = nb(&c, x, y, z, j, 1), im = nb(&c, x, y, z, j, -1);
+                    acc = acc + c.Cp[p] * d2(cur, ip, i, im);
+                    acc = acc + c.Cm[p] * d1(cur, ip, im);
+                }
+                rhs[i] = c.A0 * cur[i] + th * acc;
+            }
+    /* Jacobi sweeps, iterate k in `work` / `out` alternately, ends in out */
+    const double *src = cur;
+    for (int it = 0; it < P->theta_iters; ++it) {
+        double *dst = ((P->theta_iters - it) % 2 == 1) ? out : work;
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int64_t z = 0; z < c.n[2]; ++z)
+            for (int64_t y = 0; y < c.n[1]; ++y)
+                for (int64_t x = 0; x < c.n[0]; ++x) {
+                    int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                    double acc = 0.0;
+                    for (int p = 0; p < np; ++p) {
+                        int j = c.L.pair[p];
+                        int64_t ip = nb(&c, x, y, z, j, 1), im = nb(&c, x, y, z, j, -1);
+                        acc = acc + c.Cp[p] * (src[ip] + src[im]);
+                        acc = acc + c.Cm[p] * (src[ip] - src[im]);
+                    }
+                    dst[i] = (rhs[i] + th1 * acc) * inv_den;
+                }
+        src = dst;
+    }
+    if (P->theta_iters == 0) memcpy(out, cur, sizeof(double) * N);
+    free(rhs);
+    return 0;
+}
+
+/* ---------------------------------------------------------- tables / sums */
+
+/* constant tables for cross-checks: w[b], ubar[b], ubp/ubm/Cp/Cm/Chp/Chm[np] */
+int orc_tables(const orc_params *P, double *w, double *ubar, double *pairs6)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+    for (int j = 0; j < c.L.b; ++j) {
+        if (w) w[j] = c.L.w[j];
+        if (ubar) ubar[j] = c.ubar[j];
+    }
+    if (pairs6)
+        for (int p = 0; p < c.L.npair; ++p) {
+            pairs6[0 * ORC_MAXP + p] = c.ubp[p];
+            pairs6[1 * ORC_MAXP + p] = c.ubm[p];
+            pairs6[2 * ORC_MAXP + p] = c.Cp[p];
+            pairs6[3 * ORC_MAXP + p] = c.Cm[p];
+            pairs6[4 * ORC_MAXP + p] = c.Chp[p];
+            pairs6[5 * ORC_MAXP + p] = c.Chm[p];
+        }
+    return c.L.b;
+}
+
+/* lattice velocities (b x 3) and weights */
+int orc_lattice_info(int lattice, double d0, int *e, double *w, int *npair, int *pairs)
+{
+    orc_lattice L;
+    if (build_lattice(lattice, d0, &L)) return -1;
+    for (int j = 0; j < L.b; ++j) {
+        for (int a = 0; a < 3; ++a) e[j * 3 + a] = L.e[j][a];
+        w[j] = L.w[j];
+    }
+    *npair = L.npair;
+    for (int p = 0; p < L.npair; ++p) pairs[p] = L.pair[p];
+    return L.b;
+}
+
+/* EDF g_j(A,B,C) of Eq. (3-3) for every direction (used by identity pins) */
+int orc_edf(int lattice, double d0, double A, const double *B, const double *C, double *g)
+{
+    orc_params P;
+    memset(&P, 0, sizeof(P));
+    P.lattice = lattice; P.d0 = d0; P.eq = ORC_NSE; P.rho0 = 1.0;
+    P.n[0] = P.n[1] = P.n[2] = 1;
+    orc_ctx c;
+    if (make_ctx(&P, &c)) return -1;
+    for (int j = 0; j < c.L.b; ++j) g[j] = edf_full(&c, j, A, B, C, 1);
+    return c.L.b;
+}
+
+/* Neumaier-compensated sum of n values */
+double orc_sum(const double *v, int64_t n)
+{
+    double s = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = s + v[i];
+        if (fabs(s) >= fabs(v[i])) comp += (s - t) + v[i];
+        else comp += (v[i] - t) + s;
+        s = t;
+    }
+    return s + comp;
+}

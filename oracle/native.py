@@ -1,0 +1,243 @@
+"""ctypes binding of the plain-C FP64 oracle (``mfd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+Arrays are numpy float64, field-major ``[field][z][y][x]`` (x fastest), the
+same layout for moments (``nf`` fields) and populations (``b`` fields).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mfd_oracle.c")
+LIB = os.path.join(HERE, "libmfd_oracle.so")
+
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
+EQS = {"lcde": 0, "burgers": 1, "nse": 2}
+MAXP = 9
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: no fast-math, no FMA contraction."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+             "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("eq", C.c_int32), ("levels", C.c_int32),
+        ("lambda_bar", C.c_int32), ("he_luo", C.c_int32), ("nthreads", C.c_int32),
+        ("theta_iters", C.c_int32), ("pad_", C.c_int32),
+        ("n", C.c_int64 * 3),
+        ("d0", C.c_double), ("dx", C.c_double), ("dt", C.c_double),
+        ("u", C.c_double * 3), ("K", C.c_double * 9),
+        ("beta", C.c_double), ("rho0", C.c_double),
+        ("a", C.c_double * 3), ("ah", C.c_double * 3),
+        ("ab", C.c_double * 3), ("abh", C.c_double * 3),
+        ("theta", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        P = C.POINTER(Params)
+        D = C.POINTER(C.c_double)
+        for name, args in [
+            ("orc_mmfd_step", [P, D, D, D]),
+            ("orc_literal_step", [P, D, D, D]),
+            ("orc_init_populations", [P, D, D]),
+            ("orc_moments", [P, D, D]),
+            ("orc_mesofd_step", [P, D, D, D, D]),
+            ("orc_theta_step", [P, D, D, D]),
+            ("orc_tables", [P, D, D, D]),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.orc_lattice_info.argtypes = [C.c_int, C.c_double, C.POINTER(C.c_int), D,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_lattice_info.restype = C.c_int
+        L.orc_edf.argtypes = [C.c_int, C.c_double, C.c_double, D, D, D]
+        L.orc_edf.restype = C.c_int
+        L.orc_sum.argtypes = [D, C.c_int64]
+        L.orc_sum.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _triple(v, fill=0.0):
+    v = list(v) + [fill] * (3 - len(v))
+    return (C.c_double * 3)(*v)
+
+
+def make_params(spec: dict) -> Params:
+    """Build the C parameter block from a plain problem description.
+
+    spec keys: lattice, n (tuple), d0, dx, dt, eq ('lcde'|'burgers'|'nse'),
+    levels (2|3), a (k=-1,0,1), ah, ab, abh (default: a, ah), u, K (dim x dim),
+    lambda_bar, beta, rho0, he_luo, theta, theta_iters, nthreads.
+    """
+    P = Params()
+    lat = spec["lattice"]
+    P.lattice = LATTICES[lat]
+    P.eq = EQS[spec.get("eq", "lcde")]
+    P.levels = int(spec.get("levels", 2))
+    P.lambda_bar = int(spec.get("lambda_bar", 0))
+    P.he_luo = int(spec.get("he_luo", 0))
+    P.nthreads = int(spec.get("nthreads", 0))
+    P.theta_iters = int(spec.get("theta_iters", 0))
+    n = list(spec["n"]) + [1] * (3 - len(spec["n"]))
+    P.n = (C.c_int64 * 3)(*n)
+    P.d0 = float(spec.get("d0", 1.0 / 3.0))
+    P.dx = float(spec.get("dx", 1.0))
+    P.dt = float(spec.get("dt", 1.0))
+    P.u = _triple([float(x) for x in spec.get("u", ())])
+    Kd = np.zeros((3, 3))
+    K = np.asarray(spec.get("K", np.zeros((1, 1))), dtype=np.float64)
+    Kd[: K.shape[0], : K.shape[1]] = K
+    P.K = (C.c_double * 9)(*Kd.ravel().tolist())
+    P.beta = float(spec.get("beta", 1.0))
+    P.rho0 = float(spec.get("rho0", 0.0))
+    a = [float(x) for x in spec["a"]]
+    ah = [float(x) for x in spec.get("ah", (0.0, 0.0, 0.0))]
+    P.a = _triple(a)
+    P.ah = _triple(ah)
+    P.ab = _triple([float(x) for x in spec.get("ab", a)])
+    P.abh = _triple([float(x) for x in spec.get("abh", ah)])
+    P.theta = float(spec.get("theta", 1.0))
+    return P
+
+
+def nfields(spec) -> int:
+    return 1 + DIMS[spec["lattice"]] if spec.get("eq", "lcde") == "nse" else 1
+
+
+def npoints(spec) -> int:
+    return int(np.prod(spec["n"]))
+
+
+def _check(rc, name):
+    if rc < 0:
+        raise RuntimeError("%s failed (%d)" % (name, rc))
+
+
+def mmfd_step(spec, cur, prev=None):
+    P = make_params(spec)
+    out = np.empty_like(cur)
+    prev = cur if prev is None else prev
+    _check(lib().orc_mmfd_step(C.byref(P), _ptr(cur), _ptr(prev), _ptr(out)), "mmfd_step")
+    return out
+
+
+def literal_step(spec, cur, prev=None):
+    P = make_params(spec)
+    out = np.empty_like(cur)
+    prev = cur if prev is None else prev
+    _check(lib().orc_literal_step(C.byref(P), _ptr(cur), _ptr(prev), _ptr(out)), "literal_step")
+    return out
+
+
+def init_populations(spec, mom):
+    P = make_params(spec)
+    pop = np.empty((QS[spec["lattice"]] * npoints(spec),))
+    _check(lib().orc_init_populations(C.byref(P), _ptr(mom), _ptr(pop)), "init_populations")
+    return pop
+
+
+def moments(spec, pop):
+    P = make_params(spec)
+    mom = np.empty((nfields(spec) * npoints(spec),))
+    _check(lib().orc_moments(C.byref(P), _ptr(pop), _ptr(mom)), "moments")
+    return mom
+
+
+def mesofd_step(spec, pop, prev_mom=None):
+    """Returns (new populations, moments of the input level)."""
+    P = make_params(spec)
+    out = np.empty_like(pop)
+    mom_out = np.empty((nfields(spec) * npoints(spec),))
+    if prev_mom is None:
+        prev_mom = np.zeros_like(mom_out)  # read only by three-level schemes
+    _check(lib().orc_mesofd_step(C.byref(P), _ptr(pop), _ptr(prev_mom), _ptr(out), _ptr(mom_out)),
+           "mesofd_step")
+    return out, mom_out
+
+
+def theta_step(spec, cur):
+    P = make_params(spec)
+    out = np.empty_like(cur)
+    work = np.empty_like(cur)
+    _check(lib().orc_theta_step(C.byref(P), _ptr(cur), _ptr(out), _ptr(work)), "theta_step")
+    return out
+
+
+def tables(spec):
+    """(w[b], ubar[b], dict of per-pair ubp, ubm, Cp, Cm, Chp, Chm)."""
+    P = make_params(spec)
+    b = QS[spec["lattice"]]
+    w = np.zeros(b)
+    ub = np.zeros(b)
+    p6 = np.zeros(6 * MAXP)
+    _check(lib().orc_tables(C.byref(P), _ptr(w), _ptr(ub), _ptr(p6)), "tables")
+    npair = (b - 1) // 2
+    p6 = p6.reshape(6, MAXP)[:, :npair]
+    names = ["ubp", "ubm", "Cp", "Cm", "Chp", "Chm"]
+    return w, ub, {k: p6[i].copy() for i, k in enumerate(names)}
+
+
+def lattice_info(lattice, d0=1.0 / 3.0):
+    """(e[b,3] int, w[b], pair representatives)."""
+    e = (C.c_int * 57)()
+    w = np.zeros(19)
+    npair = C.c_int()
+    pairs = (C.c_int * 9)()
+    b = lib().orc_lattice_info(LATTICES[lattice], d0, e, _ptr(w), C.byref(npair), pairs)
+    _check(b, "lattice_info")
+    E = np.array(e[: 3 * b], dtype=np.int64).reshape(b, 3)
+    return E, w[:b].copy(), [pairs[i] for i in range(npair.value)]
+
+
+def edf(lattice, d0, A, B, Cm):
+    """g_j(A, B, C) of Eq. (3-3) in lattice units, all j."""
+    B3 = np.zeros(3)
+    B3[: len(B)] = B
+    C9 = np.zeros((3, 3))
+    Cm = np.asarray(Cm, dtype=np.float64)
+    C9[: Cm.shape[0], : Cm.shape[1]] = Cm
+    C9 = np.ascontiguousarray(C9.ravel())
+    g = np.zeros(19)
+    b = lib().orc_edf(LATTICES[lattice], d0, float(A), _ptr(np.ascontiguousarray(B3)), _ptr(C9), _ptr(g))
+    _check(b, "edf")
+    return g[:b].copy()
+
+
+def csum(v) -> float:
+    """Neumaier-compensated FP64 sum."""
+    v = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    return lib().orc_sum(_ptr(v), v.size)
