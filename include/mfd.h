@@ -1,0 +1,236 @@
+/*
+ * mfd.h -- C ABI of the MI355X (gfx950) MesoFD / MMFD stepping library.
+ *
+ * The library advances the explicit multi-level schemes of the EDF-based
+ * mesoscopic finite-difference method (MesoFD, Eq. (2-1) and (3layer-1)) and
+ * its macroscopic central-difference form (MMFD, Eq. (2-2-1), (2-4-1),
+ * (3layerMMFD-2), linear form Eq. (LMMFD-3)) on periodic rDdQb lattices
+ * (Appendix A), for the linear convection-diffusion equation (LCDE,
+ * Eq. (LCDE) with the EDF of Eq. (TforMMFD-0)), the Burgers-type nonlinear
+ * CDE (Eq. (NCDEfeq) with flux phi^2/2 per axis) and the Navier-Stokes
+ * equations (Eq. (NSEfeq); He-Luo variant of Remark 4).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Return value: 0 = success; > 0 = success with a warning (MFD_W_*);
+ * < 0 = error (MFD_E_*), in which case no out-parameter is written.
+ * mfd_last_error() returns a library-owned message for the last error of a
+ * solver.  A HIP runtime failure is sticky: every later call on that solver
+ * returns MFD_E_HIP.  No C++ exception crosses this interface.  A solver is
+ * not thread-safe; use one per host thread (different solvers may share a
+ * device and a stream).
+ *
+ * Units: lattice units c = dx/dt = 1, c_s^2 = d0.  The state of a scalar NCDE
+ * is phi.  The NSE state holds (rho - rho0, j_x, j_y[, j_z]) with
+ * j = rho u dt/dx; rho0 is a parameter (0 gives plain rho).
+ *
+ * Layout: structure of arrays, field-major, x fastest:
+ *   moments     [field][nz][ny][nx],  nf = 1 (NCDE) or 1 + dim (NSE) fields;
+ *   populations [j][nz][ny][nx],      b = 3, 5, 9, 19 directions (Appendix-A
+ *                                     order; for the NSE, f_j - w_j rho0).
+ * Precision: MFD_FP64 stores and computes in binary64; MFD_FP32 stores and
+ * computes in binary32, except that the three-level base
+ * phi^n - Ah0 (phi^n - phi^(n-1)) and all reductions are formed in binary64.
+ *
+ * Memory: the solver owns its state buffers (device memory allocated when
+ * the configuration is complete).  State is exchanged through plain host or
+ * device pointers (mfd_set_state / mfd_get_state); a device pointer must be
+ * device memory of the solver's device (e.g. a torch tensor's data_ptr()).
+ * All device work is enqueued on the solver's stream (mfd_set_stream;
+ * default: the null stream); calls documented as synchronous wait for it.
+ */
+#ifndef MFD_H
+#define MFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define MFD_OK 0
+#define MFD_W_STABILITY_UNPROVEN 1  /* sufficient stability conditions fail  */
+#define MFD_W_INCONSISTENT 2        /* A00 != 1 or A10 != A11 (Eq. (4-2-0)) */
+#define MFD_E_ARG (-1)              /* invalid argument                      */
+#define MFD_E_ORDER (-2)            /* call-order violation                  */
+#define MFD_E_UNSUPPORTED (-3)      /* combination not implemented           */
+#define MFD_E_OOM (-4)              /* device allocation failed              */
+#define MFD_E_HIP (-5)              /* HIP runtime failure (sticky)          */
+#define MFD_E_UNSTABLE (-6)         /* NaN / Inf found by a reduction        */
+#define MFD_E_BUDGET (-7)           /* request exceeds a memory budget       */
+
+/* --------------------------------------------------------------- enums     */
+#define MFD_D1Q3 1   /* rD1Q3: e = 0, +1, -1;  w = 1-d0, d0/2, d0/2           */
+#define MFD_D2Q5 2   /* rD2Q5I of Appendix A                                  */
+#define MFD_D2Q9 3   /* rD2Q9 of Appendix A                                   */
+#define MFD_D3Q19 4  /* rD3Q19 of Appendix A                                  */
+
+#define MFD_FP64 0
+#define MFD_FP32 1
+
+#define MFD_MMFD 0   /* moments only: central-difference form                */
+#define MFD_MESOFD 1 /* populations: Eq. (2-1) / (3layer-1)                  */
+
+#define MFD_LCDE 0
+#define MFD_BURGERS 1
+#define MFD_NSE 2
+
+#define MFD_TWO_LEVEL 0   /* explicit, level t only (ah = 0)                 */
+#define MFD_THETA 1       /* two-level theta scheme, Eq. (GCN), LCDE only   */
+#define MFD_THREE_LEVEL 2 /* explicit, levels t and t - dt, Eq. (3layer-1)   */
+
+/* presets of the three-level family (after Eq. (4-2-00)) and Eq. (LMMFD-2-2) */
+#define MFD_PRESET_SRT 0        /* SRT LB, tau = 1 (param unused)            */
+#define MFD_PRESET_TRT 1        /* TRT LB with s+ + s- = 2, param = s-        */
+#define MFD_PRESET_ONE_STAGE 2  /* one-stage simplified LB, param = tau       */
+#define MFD_PRESET_TWO_LEVEL 3  /* m = 1 two-level family, param = s          */
+
+typedef struct mfd_solver mfd_solver;
+
+typedef struct {
+    int32_t dim;        /* 1, 2 or 3; must match the lattice                 */
+    int32_t precision;  /* MFD_FP64 / MFD_FP32                               */
+    int32_t form;       /* MFD_MMFD / MFD_MESOFD                             */
+    int32_t reserved;   /* must be 0                                         */
+    int64_t n[3];       /* nodes along x, y, z (unused axes: 1); >= 3 each   */
+    double dx;          /* node spacing (square / cubic grid), > 0           */
+} mfd_grid;
+
+typedef struct {
+    double u[3];        /* LCDE: constant advection velocity (physical)      */
+    double K[9];        /* LCDE: diffusion tensor, row-major 3 x 3           */
+    int32_t lambda_bar; /* LCDE: 0 or 1, the u u term of Eq. (TforMMFD-0)    */
+    int32_t he_luo;     /* NSE: 1 selects g(rho, rho0 u, rho0 u u)           */
+    double beta;        /* Burgers: D = phi I scaled by beta (1 = default)   */
+    double rho0;        /* NSE: reference density stored apart from rho      */
+} mfd_eq_params;
+
+/* ---------------------------------------------------------- solver set-up */
+
+/* Create a solver for a periodic grid.  *out receives an owned handle to be
+ * released with mfd_destroy.  Errors: MFD_E_ARG (null pointers, dim/n/dx out
+ * of range, unknown precision or form). */
+int mfd_create(mfd_solver **out, const mfd_grid *g);
+
+/* Release the solver and every device buffer it owns.  Never frees memory
+ * passed in by the caller.  Accepts NULL. */
+int mfd_destroy(mfd_solver *s);
+
+/* Library-owned, NUL-terminated description of the solver's last error
+ * ("" if none).  Valid until the next call on the solver. */
+const char *mfd_last_error(const mfd_solver *s);
+
+/* Lattice of Appendix A with d0 = c_s^2/c^2 on every axis (d0 <= 0 selects
+ * 1/3).  Rejects weights outside the Appendix ranges (MFD_E_ARG) and lattices
+ * whose dimension differs from the grid's (MFD_E_ARG). */
+int mfd_set_lattice(mfd_solver *s, int lattice, double d0);
+
+/* Equation and its parameters (copied).  MFD_E_UNSUPPORTED for the NSE on
+ * D1Q3.  On D2Q5 the quadratic EDF term cannot represent cross-axis
+ * diagonal C (no e_x^2 e_y^2 moment); the call then returns
+ * MFD_W_INCONSISTENT. */
+int mfd_set_equation(mfd_solver *s, int eq, const mfd_eq_params *p);
+
+/* Scheme: kind (MFD_TWO_LEVEL, MFD_THETA, MFD_THREE_LEVEL), coefficients
+ * a[k+1] (k = -1, 0, 1) for level t and ah[k+1] for level t - dt
+ * (three-level notation of Eq. (3layer-1); ah is ignored unless
+ * MFD_THREE_LEVEL), optional momentum set ab / abh of Eq. (2-4) (NULL: equal
+ * to a / ah), theta in [0,1] with theta_iters Jacobi sweeps (MFD_THETA) and
+ * the time step dt > 0.  Must follow mfd_set_lattice and mfd_set_equation.
+ * Returns MFD_W_INCONSISTENT if A00 != 1 (Eq. (4-2-00a)) and
+ * MFD_W_STABILITY_UNPROVEN if the linear(ised) scheme fails the sufficient
+ * conditions (Theorem 1 / Corollary 2); both are warnings. */
+int mfd_set_scheme(mfd_solver *s, int kind, const double a[3], const double ah[3],
+                   const double ab[3], const double abh[3], double theta,
+                   int32_t theta_iters, double dt);
+
+/* Enqueue all further work of this solver on the HIP stream `stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL =
+ * null stream).  The stream must outlive its use by the solver. */
+int mfd_set_stream(mfd_solver *s, void *stream);
+
+/* Element counts of one time level: moments (nf * nodes) and populations
+ * (b * nodes, 0 for MMFD), and the bytes of device memory the solver holds
+ * or will hold once configured. */
+int mfd_state_size(const mfd_solver *s, int64_t *moment_elems, int64_t *population_elems,
+                   int64_t *device_bytes);
+
+/* ------------------------------------------------------------- state I/O */
+
+/* Set a time level: level 0 = t^n, level 1 = t^(n-1) (three-level only).
+ * MMFD: moments of that level.  MesoFD, level 0: moments, from which the
+ * populations are initialised to the EDF (f_j = f_j^eq), or, with
+ * `populations` = 1, the populations themselves; level 1: moments.
+ * Elements are of the solver's precision; `bytes` must equal their total
+ * size.  `on_device` = 1 if src is device memory.  Synchronous.  Setting
+ * level 0 of a three-level scheme also sets level 1 to the same values
+ * (the phi^(-1) = phi^0 start) unless level 1 is set afterwards. */
+int mfd_set_state(mfd_solver *s, int level, const void *src, int64_t bytes, int on_device,
+                  int populations);
+
+/* Copy a time level out (same level / population conventions; for MesoFD
+ * level 0 with populations = 0 the moments are computed on the device by
+ * Eq. (2-1-1)).  Synchronous. */
+int mfd_get_state(mfd_solver *s, int level, void *dst, int64_t bytes, int on_device,
+                  int populations);
+
+/* --------------------------------------------------------------- stepping */
+
+/* Enqueue nsteps >= 0 time steps; asynchronous with respect to the host. */
+int mfd_step(mfd_solver *s, int64_t nsteps);
+
+/* Wait for all work the solver has enqueued. */
+int mfd_synchronize(mfd_solver *s);
+
+/* FP64 reductions over the current level (synchronous):
+ * sums[f] = sum over nodes of moment field f (f < nf, others 0): the
+ * conserved totals implied by the moment identities after Eq. (2-1-FD1);
+ * *residual = || phi^n - phi^(n-1) ||_2 of field 0 (0 before the first step).
+ * Returns MFD_E_UNSTABLE if a sum or the residual is not finite. */
+int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
+
+/* Autotune the launch plan (tile shape, temporal-blocking depth) of this
+ * solver's configuration by timing candidates on its own state (restored
+ * afterwards); the choice is cached per (lattice, equation, form, precision,
+ * levels, size) for the process.  Synchronous. *chosen_tb receives the depth. */
+int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
+
+/* Force a temporal-blocking depth (1 = none; 0 = automatic). */
+int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
+
+/* ------------------------------------------------------ host-side algebra */
+
+/* Coefficient moments of Eq. (4-2-00): out = {A00, A10, A11, A20, A21, A22}. */
+int mfd_coeff_moments(const double a[3], const double ah[3], double out[6]);
+
+/* Coefficients meeting A00 = 1 and given (a0, A10, A11, A21, A22),
+ * closed form Eq. (X).  Writes a[3], ah[3]. */
+int mfd_coeffs_from_constraints(double a0, double A10, double A11, double A21, double A22,
+                                double a[3], double ah[3]);
+
+/* Preset coefficient sets (MFD_PRESET_*). */
+int mfd_preset(int preset, double param, double a[3], double ah[3]);
+
+/* Transport coefficient of a coefficient set on a lattice:
+ * -(A22/A10) dt beta d0 dx^2/dt^2 (diffusivity alpha for the NCDE, kinematic
+ * viscosity nu for the NSE with beta = 1). */
+int mfd_transport_coefficient(const double a[3], const double ah[3], double dx, double dt,
+                              double d0, double beta, double *out);
+
+/* Largest modulus over the grid's Fourier modes of the amplification
+ * factor(s) of the configured linear (LCDE) scheme, Eq. (TforMMFD-3)
+ * (roots of lambda^2 - p1 lambda - p0 for three-level schemes, the theta
+ * factor of Eq. (Tcond1-1) for MFD_THETA). */
+int mfd_max_amplification(mfd_solver *s, double *out);
+
+/* Per-pair linear EDF constants of the configured LCDE (for checks):
+ * ubar[b] (full EDF per unit phi), and per opposite pair p:
+ * out6[0..5][p] = ubar+_p, ubar-_p, (a_1+a_-1) ubar+_p, (a_1-a_-1) ubar-_p,
+ * (ah_1+ah_-1) ubar+_p, (ah_1-ah_-1) ubar-_p; stride 9 per row. */
+int mfd_linear_tables(mfd_solver *s, double *w, double *ubar, double *out6);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFD_H */

@@ -1,0 +1,410 @@
+// MesoFD step kernels: the population form of the scheme, Eq. (2-1) /
+// (3layer-1),
+//   f_j(x, t+dt) = sum_k a_k f_j^eq(x + k e_j, t) + sum_k ah_k f_j^eq(x + k e_j, t-dt),
+// k in (-1, 0, +1) order, level t first, zero coefficients skipped; f^eq at
+// level t is the EDF of the moments of the populations (Eq. (2-1-1):
+// phi = sum_j f_j, j_a = sum_j e_ja f_j, lattice order), at level t - dt the
+// EDF of the stored moments of that level.  The kernel also writes the
+// moments of level t (the t - dt level of the next step).
+//
+// Same tiling as the MMFD kernels: EDF records of the tile plus a one-node
+// halo in LDS, then every interior node evaluates its b directions.
+#include "edf.h"
+
+namespace mfd {
+
+__device__ __forceinline__ int wrapm(int i, int n) {
+  if (i < 0) {
+    i += n;
+    if (i < 0) i = ((i % n) + n) % n;
+  } else if (i >= n) {
+    i -= n;
+    if (i >= n) i %= n;
+  }
+  return i;
+}
+
+__device__ __forceinline__ int xcd_remap_m(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
+// moments of the b populations at one node (lattice order)
+template <class L, int EQ, typename T>
+__device__ __forceinline__ void pop_moments(const T *pop, int64_t N, int64_t gi, T *m) {
+  constexpr int NF = Rec<L, EQ>::NF;
+  T f[L::Q];
+#pragma unroll
+  for (int j = 0; j < L::Q; ++j) f[j] = pop[j * N + gi];
+  T s = T(0);
+#pragma unroll
+  for (int j = 0; j < L::Q; ++j) s = s + f[j];
+  m[0] = s;
+#pragma unroll
+  for (int a = 0; a + 1 < NF; ++a) {
+    T t = T(0);
+#pragma unroll
+    for (int j = 0; j < L::Q; ++j) {
+      if (L::E[j][a] == 1) t = t + f[j];
+      else if (L::E[j][a] == -1) t = t - f[j];
+    }
+    m[1 + a] = t;
+  }
+}
+
+// evaluate the b new populations of one node
+template <class L, int EQ, bool THREE_ST, typename T, class At, class AtH>
+__device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const T *hcentre,
+                                            bool three, T *pout, int64_t N, int64_t gi,
+                                            const KC<T> &kc) {
+  constexpr int NR = Rec<L, EQ>::NR;
+  static_for<L::Q>([&](auto JI) {
+    constexpr int J = decltype(JI)::value;
+    constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+    T fj = T(0);
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) {
+      const T ak = kc.a[k + 1];
+      if (ak != T(0)) {
+        T r[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = at(q, k * ez, k * ey, k * ex);
+        fj = madd(ak, gfull<L, EQ, J>(r, kc), fj);
+      }
+    }
+    if (three) {
+#pragma unroll
+      for (int k = -1; k <= 1; ++k) {
+        const T ak = kc.ah[k + 1];
+        if (ak != T(0)) {
+          T r[NR];
+          if constexpr (THREE_ST) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) r[q] = ath(q, k * ez, k * ey, k * ex);
+          } else {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) r[q] = hcentre[q];  // only k = 0 is non-zero
+          }
+          fj = madd(ak, gfull<L, EQ, J>(r, kc), fj);
+        }
+      }
+    }
+    pout[J * N + gi] = fj;
+  });
+}
+
+template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_mesofd_plane(const T *__restrict__ pop,
+                                                      const T *__restrict__ prev_mom,
+                                                      T *__restrict__ pop_out,
+                                                      T *__restrict__ mom_out, int nx, int ny,
+                                                      int tiles_x, int ntiles, KC<T> kc) {
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR, NF = R::NF;
+  constexpr int HYL = L::D >= 2 ? 1 : 0;
+  constexpr int HX = TX + 2, HY = TY + 2 * HYL;
+  __shared__ T rec[NR][HY][HX];
+  __shared__ T hrec[THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+  const int tile = xcd_remap_m(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+  const int64_t N = (int64_t)nx * ny;
+
+  for (int i = threadIdx.x; i < HX * HY; i += 256) {
+    const int lx = i % HX, ly = i / HX;
+    const int gx = wrapm(x0 - 1 + lx, nx), gy = wrapm(y0 - HYL + ly, ny);
+    const int64_t gi = (int64_t)gy * nx + gx;
+    T m[NF], r[NR];
+    pop_moments<L, EQ>(pop, N, gi, m);
+    const bool interior = lx >= 1 && lx <= TX && ly >= HYL && ly < HYL + TY &&
+                          x0 - 1 + lx < nx && y0 - HYL + ly < ny;
+    if (mom_out && interior) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) mom_out[f * N + gi] = m[f];
+    }
+    make_record<L, EQ>(m, r, kc);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
+    if constexpr (THREE_ST) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) hrec[k][ly][lx] = r[k];
+    }
+  }
+  __syncthreads();
+
+  for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    const int lx = i % TX, ly = i / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int cx = lx + 1, cy = ly + HYL;
+    const int64_t gi = (int64_t)gy * nx + gx;
+    auto at = [&](int k, int, int dy, int dx) { return rec[k][cy + dy][cx + dx]; };
+    auto ath = [&](int k, int, int dy, int dx) {
+      if constexpr (THREE_ST) return hrec[k][cy + dy][cx + dx];
+      else return T(0);
+    };
+    T hc[NR];
+    if constexpr (THREE && !THREE_ST) {
+      T m[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
+      make_record<L, EQ>(m, hc, kc);
+    }
+    mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, N, gi, kc);
+  }
+}
+
+template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ pop,
+                                                   const T *__restrict__ prev_mom,
+                                                   T *__restrict__ pop_out,
+                                                   T *__restrict__ mom_out, int nx, int ny,
+                                                   int nz, int tiles_x, int tiles_y, int zchunk,
+                                                   int ntiles, KC<T> kc) {
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR, NF = R::NF;
+  constexpr int HX = TX + 2, HY = TY + 2;
+  __shared__ T rec[3][NR][HY][HX];
+  __shared__ T hrec[THREE_ST ? 3 : 1][THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+  const int tile = xcd_remap_m(blockIdx.x, ntiles);
+  const int txy = tiles_x * tiles_y;
+  const int tz = tile / txy, trem = tile % txy;
+  const int x0 = (trem % tiles_x) * TX, y0 = (trem / tiles_x) * TY;
+  const int z0 = tz * zchunk, z1 = min(nz, z0 + zchunk);
+  const int64_t N = (int64_t)nx * ny * nz;
+
+  auto load_plane = [&](int z, int slot, bool write_mom) {
+    const int gz = wrapm(z, nz);
+    for (int i = threadIdx.x; i < HX * HY; i += 256) {
+      const int lx = i % HX, ly = i / HX;
+      const int gx = wrapm(x0 - 1 + lx, nx), gy = wrapm(y0 - 1 + ly, ny);
+      const int64_t gi = ((int64_t)gz * ny + gy) * nx + gx;
+      T m[NF], r[NR];
+      pop_moments<L, EQ>(pop, N, gi, m);
+      const bool interior = write_mom && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY &&
+                            x0 - 1 + lx < nx && y0 - 1 + ly < ny;
+      if (mom_out && interior) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) mom_out[f * N + gi] = m[f];
+      }
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) rec[slot][k][ly][lx] = r[k];
+      if constexpr (THREE_ST) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
+        make_record<L, EQ>(m, r, kc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) hrec[slot][k][ly][lx] = r[k];
+      }
+    }
+  };
+
+  load_plane(z0 - 1, 0, false);
+  load_plane(z0, 1, true);
+  for (int z = z0; z < z1; ++z) {
+    const int rel = z - z0;
+    load_plane(z + 1, (rel + 2) % 3, z + 1 < z1);
+    __syncthreads();
+    const int sm = rel % 3, s0 = (rel + 1) % 3, sp = (rel + 2) % 3;
+    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+      const int lx = i % TX, ly = i / TX;
+      const int gx = x0 + lx, gy = y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const int cx = lx + 1, cy = ly + 1;
+      const int64_t gi = ((int64_t)z * ny + gy) * nx + gx;
+      auto slot = [&](int dz) { return dz == 0 ? s0 : (dz > 0 ? sp : sm); };
+      auto at = [&](int k, int dz, int dy, int dx) { return rec[slot(dz)][k][cy + dy][cx + dx]; };
+      auto ath = [&](int k, int dz, int dy, int dx) {
+        if constexpr (THREE_ST) return hrec[slot(dz)][k][cy + dy][cx + dx];
+        else return T(0);
+      };
+      T hc[NR];
+      if constexpr (THREE && !THREE_ST) {
+        T m[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
+        make_record<L, EQ>(m, hc, kc);
+      }
+      mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, N, gi, kc);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ init / moments kernels
+template <class L, int EQ, typename T>
+__global__ __launch_bounds__(256) void k_init_pop(const T *__restrict__ mom, T *__restrict__ pop,
+                                                  int64_t N, KC<T> kc) {
+  using R = Rec<L, EQ>;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T m[R::NF], r[R::NR];
+#pragma unroll
+    for (int f = 0; f < R::NF; ++f) m[f] = mom[f * N + i];
+    make_record<L, EQ>(m, r, kc);
+    static_for<L::Q>([&](auto JI) {
+      constexpr int J = decltype(JI)::value;
+      pop[J * N + i] = gfull<L, EQ, J>(r, kc);
+    });
+  }
+}
+
+template <class L, int EQ, typename T>
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ pop, T *__restrict__ mom,
+                                                 int64_t N) {
+  using R = Rec<L, EQ>;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T m[R::NF];
+    pop_moments<L, EQ>(pop, N, i, m);
+#pragma unroll
+    for (int f = 0; f < R::NF; ++f) mom[f * N + i] = m[f];
+  }
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+hipError_t meso_cfg(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+                    hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
+  if constexpr (L::D == 1) {
+    constexpr int TX = 1024;
+    const int tx = (nx + TX - 1) / TX;
+    hipLaunchKernelGGL((k_mesofd_plane<L, EQ, THREE, THREE_ST, TX, 1, T>), dim3(tx), dim3(256), 0,
+                       st, pop, pm, po, mo, nx, 1, tx, tx, kc);
+  } else if constexpr (L::D == 2) {
+    constexpr int TX = 64, TY = EQ == kNSE ? 8 : 16;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_mesofd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty),
+                       dim3(256), 0, st, pop, pm, po, mo, nx, ny, tx, tx * ty, kc);
+  } else {
+    constexpr int TX = 32, TY = (THREE_ST && sizeof(T) == 8) ? 4 : 8;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    const int zc = nz >= 64 ? 32 : nz;
+    const int tz = (nz + zc - 1) / zc;
+    hipLaunchKernelGGL((k_mesofd_3d<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty * tz),
+                       dim3(256), 0, st, pop, pm, po, mo, nx, ny, nz, tx, ty, zc, tx * ty * tz, kc);
+  }
+  return hipGetLastError();
+}
+
+template <class L, int EQ, typename T>
+hipError_t meso_levels(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+                       hipStream_t st) {
+  if (!c.three) return meso_cfg<L, EQ, false, false, T>(c, g, pop, pm, po, mo, st);
+  if (!c.three_stencil) return meso_cfg<L, EQ, true, false, T>(c, g, pop, pm, po, mo, st);
+  return meso_cfg<L, EQ, true, true, T>(c, g, pop, pm, po, mo, st);
+}
+
+template <class L, typename T>
+hipError_t meso_eq(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+                   hipStream_t st) {
+  switch (c.eq) {
+    case kLCDE: return meso_levels<L, kLCDE, T>(c, g, pop, pm, po, mo, st);
+    case kBurgers: return meso_levels<L, kBurgers, T>(c, g, pop, pm, po, mo, st);
+    case kNSE:
+      if constexpr (L::D >= 2) return meso_levels<L, kNSE, T>(c, g, pop, pm, po, mo, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline int grid_blocks(int64_t N) {
+  int64_t b = (N + 255) / 256;
+  return (int)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+}
+
+template <class L, typename T>
+hipError_t init_eq(const Consts &c, const Grid &g, const T *mom, T *pop, hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  switch (c.eq) {
+    case kLCDE:
+      hipLaunchKernelGGL((k_init_pop<L, kLCDE, T>), dim3(grid_blocks(g.N)), dim3(256), 0, st, mom,
+                         pop, g.N, kc);
+      break;
+    case kBurgers:
+      hipLaunchKernelGGL((k_init_pop<L, kBurgers, T>), dim3(grid_blocks(g.N)), dim3(256), 0, st,
+                         mom, pop, g.N, kc);
+      break;
+    case kNSE:
+      if constexpr (L::D >= 2) {
+        hipLaunchKernelGGL((k_init_pop<L, kNSE, T>), dim3(grid_blocks(g.N)), dim3(256), 0, st, mom,
+                           pop, g.N, kc);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t mom_eq(const Consts &c, const Grid &g, const T *pop, T *mom, hipStream_t st) {
+  if (c.eq == kNSE) {
+    if constexpr (L::D >= 2) {
+      hipLaunchKernelGGL((k_moments<L, kNSE, T>), dim3(grid_blocks(g.N)), dim3(256), 0, st, pop,
+                         mom, g.N);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((k_moments<L, kLCDE, T>), dim3(grid_blocks(g.N)), dim3(256), 0, st, pop, mom,
+                     g.N);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,
+                              T *pop_out, T *mom_out, hipStream_t st) {
+  switch (c.lattice) {
+    case 1: return meso_eq<LatD1Q3, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
+    case 2: return meso_eq<LatD2Q5, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
+    case 3: return meso_eq<LatD2Q9, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
+    case 4: return meso_eq<LatD3Q19, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom, T *pop,
+                                   hipStream_t st) {
+  switch (c.lattice) {
+    case 1: return init_eq<LatD1Q3, T>(c, g, mom, pop, st);
+    case 2: return init_eq<LatD2Q5, T>(c, g, mom, pop, st);
+    case 3: return init_eq<LatD2Q9, T>(c, g, mom, pop, st);
+    case 4: return init_eq<LatD3Q19, T>(c, g, mom, pop, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_moments(const Consts &c, const Grid &g, const T *pop, T *mom, hipStream_t st) {
+  switch (c.lattice) {
+    case 1: return mom_eq<LatD1Q3, T>(c, g, pop, mom, st);
+    case 2: return mom_eq<LatD2Q5, T>(c, g, pop, mom, st);
+    case 3: return mom_eq<LatD2Q9, T>(c, g, pop, mom, st);
+    case 4: return mom_eq<LatD3Q19, T>(c, g, pop, mom, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define MFD_INST(T)                                                                               \
+  template hipError_t launch_mesofd_step<T>(const Consts &, const Grid &, const T *, const T *,   \
+                                            T *, T *, hipStream_t);                               \
+  template hipError_t launch_init_populations<T>(const Consts &, const Grid &, const T *, T *,    \
+                                                 hipStream_t);                                    \
+  template hipError_t launch_moments<T>(const Consts &, const Grid &, const T *, T *, hipStream_t);
+MFD_INST(float)
+MFD_INST(double)
+#undef MFD_INST
+
+}  // namespace mfd

@@ -1,0 +1,438 @@
+// MMFD step kernels: the central-difference form of the scheme on moments,
+// Eq. (2-2-1) / (2-4-1) (two-level: level t only), Eq. (3layerMMFD-2)
+// (three-level), and the linear pair form Eq. (LMMFD-1/3) for the LCDE.
+//
+// Per node x and opposite pair p = (j, jbar) with representative e_p:
+//   D2_p g = (g(x+e_p) - 2 g(x)) + g(x-e_p),   D1_p g = g(x+e_p) - g(x-e_p)
+//   zeroth moment: acc += a+ D2_p F+_p;  acc += a- D1_p F-_p      (pairs in order,
+//                  level t then level t-dt), out = (A0 m + Ah0 m_prev) + acc
+//   first moments (NSE), axis a with e_pa != 0:
+//                  acc_a +-= ab+ D2_p F-_p;  acc_a +-= ab- D1_p F+_p
+//   LCDE: acc += Cp_p D2_p phi; acc += Cm_p D1_p phi with Cp = a+ ubar+, Cm = a- ubar-.
+// In binary32 the three-level base phi - Ah0 (phi - phi_prev) and its sum
+// with acc are formed in binary64 and rounded once.
+//
+// Tiling: a workgroup of 256 threads owns a TX x TY tile of one xy plane
+// (1D/2D) or a TX x TY column of planes marched along z (3D).  The EDF
+// record of every node of the tile plus a one-node halo is built once into
+// LDS (structure of arrays, x fastest: bank-conflict free), then every
+// interior node reads its stencil from LDS.  Periodic wrap is applied to the
+// global indices of the halo.  Workgroup ids are remapped so that each of
+// the 8 XCDs owns a contiguous band of tiles (L2 reuse of halos).
+#include "edf.h"
+
+namespace mfd {
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  if (i < 0) {
+    i += n;
+    if (i < 0) i = ((i % n) + n) % n;
+  } else if (i >= n) {
+    i -= n;
+    if (i >= n) i %= n;
+  }
+  return i;
+}
+
+// Hardware dispatch sends consecutive workgroups round-robin to the 8 XCDs;
+// give XCD x the contiguous tile range [x q + min(x, r), ...).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
+// ---------------------------------------------------------- node update
+// `at(field, dz, dy, dx)` reads the level-t record, `ath` the level-(t-dt)
+// record; cur_c / prev_c are the centre moments (global), out the outputs.
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T, class At, class AtH>
+__device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T *cur_c,
+                                          const T *prev_c, T *out_c, const KC<T> &kc) {
+  using R = Rec<L, EQ>;
+  constexpr int D = L::D, NR = R::NR, NF = R::NF;
+  T acc = T(0);
+  T mom[D > 0 ? D : 1];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mom[a] = T(0);
+
+  auto level = [&](const auto &get, T cpl, T cmi, T bpl, T bmi, bool hat) {
+    static_for<L::P>([&](auto PI) {
+      constexpr int P = decltype(PI)::value;
+      constexpr int J = L::PR[P];
+      constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+      if constexpr (EQ == kLCDE) {
+        const T gp = get(0, ez, ey, ex), g0 = get(0, 0, 0, 0), gm = get(0, -ez, -ey, -ex);
+        const T cp = hat ? kc.Chp[P] : kc.Cp[P];
+        const T cm = hat ? kc.Chm[P] : kc.Cm[P];
+        acc = madd(cp, (gp - T(2) * g0) + gm, acc);
+        acc = madd(cm, gp - gm, acc);
+      } else {
+        T rp[NR], r0[NR], rm[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          rp[k] = get(k, ez, ey, ex);
+          r0[k] = get(k, 0, 0, 0);
+          rm[k] = get(k, -ez, -ey, -ex);
+        }
+        const T Fpp = fplus<L, EQ, J>(rp, kc), Fp0 = fplus<L, EQ, J>(r0, kc),
+                Fpm = fplus<L, EQ, J>(rm, kc);
+        const T Fmp = fminus<L, EQ, J>(rp, kc), Fmm = fminus<L, EQ, J>(rm, kc);
+        acc = madd(cpl, (Fpp - T(2) * Fp0) + Fpm, acc);
+        acc = madd(cmi, Fmp - Fmm, acc);
+        if constexpr (EQ == kNSE) {
+          const T Fm0 = fminus<L, EQ, J>(r0, kc);
+          const T t1 = bpl * ((Fmp - T(2) * Fm0) + Fmm);
+          const T t2 = bmi * (Fpp - Fpm);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (L::E[J][a] == 1) {
+              mom[a] = mom[a] + t1;
+              mom[a] = mom[a] + t2;
+            } else if (L::E[J][a] == -1) {
+              mom[a] = mom[a] - t1;
+              mom[a] = mom[a] - t2;
+            }
+          }
+        }
+      }
+    });
+  };
+  level(at, kc.ap, kc.am, kc.abp, kc.abm, false);
+  if constexpr (THREE_ST) level(ath, kc.ahp, kc.ahm, kc.abhp, kc.abhm, true);
+
+  // bases
+  auto finish = [&](int f, T a_acc, double A0d, double Ah0d, T A0t, T Ah0t) {
+    const T c = cur_c[f];
+    if constexpr (std::is_same<T, double>::value) {
+      double base = A0d * c;
+      if constexpr (THREE) base = base + Ah0d * prev_c[f];
+      out_c[f] = base + a_acc;
+    } else {
+      if constexpr (THREE) {
+        const double cd = (double)c;
+        const double base = cd - Ah0d * (cd - (double)prev_c[f]);
+        out_c[f] = (T)(base + (double)a_acc);
+      } else {
+        out_c[f] = madd(A0t, c, a_acc);
+      }
+    }
+  };
+  finish(0, acc, kc.A0, kc.Ah0, kc.A0t, kc.Ah0t);
+  if constexpr (EQ == kNSE) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) finish(1 + a, mom[a], kc.Ab0, kc.Abh0, kc.Ab0t, kc.Abh0t);
+  }
+  (void)NF;
+}
+
+// ------------------------------------------------------ 1D / 2D kernel
+template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_mmfd_plane(const T *__restrict__ cur,
+                                                    const T *__restrict__ prev,
+                                                    T *__restrict__ out, int nx, int ny,
+                                                    int tiles_x, int ntiles, KC<T> kc) {
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR, NF = R::NF;
+  constexpr int HYL = L::D >= 2 ? 1 : 0;
+  constexpr int HX = TX + 2, HY = TY + 2 * HYL;
+  __shared__ T rec[NR][HY][HX];
+  __shared__ T hrec[THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+  const int64_t N = (int64_t)nx * ny;
+
+  for (int i = threadIdx.x; i < HX * HY; i += 256) {
+    const int lx = i % HX, ly = i / HX;
+    const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - HYL + ly, ny);
+    const int64_t gi = (int64_t)gy * nx + gx;
+    T m[NF], r[NR];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) m[f] = cur[f * N + gi];
+    make_record<L, EQ>(m, r, kc);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
+    if constexpr (THREE_ST) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) m[f] = prev[f * N + gi];
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) hrec[k][ly][lx] = r[k];
+    }
+  }
+  __syncthreads();
+
+  for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    const int lx = i % TX, ly = i / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int cx = lx + 1, cy = ly + HYL;
+    const int64_t gi = (int64_t)gy * nx + gx;
+    auto at = [&](int k, int, int dy, int dx) { return rec[k][cy + dy][cx + dx]; };
+    auto ath = [&](int k, int, int dy, int dx) {
+      if constexpr (THREE_ST) return hrec[k][cy + dy][cx + dx];
+      else return T(0);
+    };
+    T cc[NF], pc[NF], oc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      cc[f] = cur[f * N + gi];
+      pc[f] = THREE ? prev[f * N + gi] : T(0);
+    }
+    mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
+  }
+}
+
+// ---------------------------------------------------------- 3D kernel
+template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_mmfd_3d(const T *__restrict__ cur,
+                                                 const T *__restrict__ prev,
+                                                 T *__restrict__ out, int nx, int ny, int nz,
+                                                 int tiles_x, int tiles_y, int zchunk,
+                                                 int ntiles, KC<T> kc) {
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR, NF = R::NF;
+  constexpr int HX = TX + 2, HY = TY + 2;
+  __shared__ T rec[3][NR][HY][HX];
+  __shared__ T hrec[THREE_ST ? 3 : 1][THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  const int txy = tiles_x * tiles_y;
+  const int tz = tile / txy, trem = tile % txy;
+  const int x0 = (trem % tiles_x) * TX, y0 = (trem / tiles_x) * TY;
+  const int z0 = tz * zchunk, z1 = min(nz, z0 + zchunk);
+  const int64_t N = (int64_t)nx * ny * nz;
+
+  auto load_plane = [&](int z, int slot) {
+    const int gz = wrapi(z, nz);
+    for (int i = threadIdx.x; i < HX * HY; i += 256) {
+      const int lx = i % HX, ly = i / HX;
+      const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - 1 + ly, ny);
+      const int64_t gi = ((int64_t)gz * ny + gy) * nx + gx;
+      T m[NF], r[NR];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) m[f] = cur[f * N + gi];
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) rec[slot][k][ly][lx] = r[k];
+      if constexpr (THREE_ST) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) m[f] = prev[f * N + gi];
+        make_record<L, EQ>(m, r, kc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) hrec[slot][k][ly][lx] = r[k];
+      }
+    }
+  };
+
+  load_plane(z0 - 1, 0);
+  load_plane(z0, 1);
+  for (int z = z0; z < z1; ++z) {
+    const int rel = z - z0;
+    load_plane(z + 1, (rel + 2) % 3);
+    __syncthreads();
+    const int sm = rel % 3, s0 = (rel + 1) % 3, sp = (rel + 2) % 3;
+    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+      const int lx = i % TX, ly = i / TX;
+      const int gx = x0 + lx, gy = y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const int cx = lx + 1, cy = ly + 1;
+      const int64_t gi = ((int64_t)z * ny + gy) * nx + gx;
+      auto slot = [&](int dz) { return dz == 0 ? s0 : (dz > 0 ? sp : sm); };
+      auto at = [&](int k, int dz, int dy, int dx) { return rec[slot(dz)][k][cy + dy][cx + dx]; };
+      auto ath = [&](int k, int dz, int dy, int dx) {
+        if constexpr (THREE_ST) return hrec[slot(dz)][k][cy + dy][cx + dx];
+        else return T(0);
+      };
+      T cc[NF], pc[NF], oc[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        cc[f] = cur[f * N + gi];
+        pc[f] = THREE ? prev[f * N + gi] : T(0);
+      }
+      mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ LDS-resident 1D run
+// One workgroup holds every time level of a 1D grid in LDS and runs all
+// steps: the C1 workload (1024 nodes) is latency-bound, so one launch.
+constexpr int kResidentBytes = 96 * 1024;
+
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+__global__ __launch_bounds__(1024) void k_mmfd_1d_resident(T *__restrict__ ga,
+                                                           T *__restrict__ gb,
+                                                           T *__restrict__ gc, int nx,
+                                                           int64_t nsteps, KC<T> kc) {
+  extern __shared__ unsigned char smem[];
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR;
+  // three moment levels (a = t, b = t - dt, c = next) and two record planes
+  T *lev[3] = {(T *)smem, (T *)smem + nx, (T *)smem + 2 * nx};
+  T *rec = (T *)smem + 3 * nx;       // NR * nx
+  T *hrec = rec + NR * nx;           // NR * nx (three-level stencil)
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    lev[0][i] = ga[i];
+    lev[1][i] = THREE ? gb[i] : T(0);
+  }
+  __syncthreads();
+  int ic = 0, ip = 1, io = 2;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      T m[1], r[NR];
+      m[0] = lev[ic][i];
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) rec[k * nx + i] = r[k];
+      if constexpr (THREE_ST) {
+        m[0] = lev[ip][i];
+        make_record<L, EQ>(m, r, kc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) hrec[k * nx + i] = r[k];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      auto idx = [&](int dx) {
+        int j = i + dx;
+        return j < 0 ? j + nx : (j >= nx ? j - nx : j);
+      };
+      auto at = [&](int k, int, int, int dx) { return rec[k * nx + idx(dx)]; };
+      auto ath = [&](int k, int, int, int dx) {
+        if constexpr (THREE_ST) return hrec[k * nx + idx(dx)];
+        else return T(0);
+      };
+      T cc[1] = {lev[ic][i]}, pc[1] = {THREE ? lev[ip][i] : T(0)}, oc[1];
+      mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+      lev[io][i] = oc[0];
+    }
+    __syncthreads();
+    const int t = ip;
+    ip = ic;
+    ic = io;
+    io = t;
+  }
+  // final level -> ga, previous level -> gb
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    ga[i] = lev[ic][i];
+    gb[i] = lev[ip][i];
+  }
+  (void)gc;
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                      hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
+  if constexpr (L::D == 1) {
+    constexpr int TX = 1024, TY = 1;
+    const int tx = (nx + TX - 1) / TX;
+    hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx), dim3(256), 0,
+                       st, cur, prev, out, nx, 1, tx, tx, kc);
+  } else if constexpr (L::D == 2) {
+    constexpr int TX = 64, TY = EQ == kNSE ? 8 : 16;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty), dim3(256),
+                       0, st, cur, prev, out, nx, ny, tx, tx * ty, kc);
+  } else {
+    constexpr int TX = 32, TY = (THREE_ST && sizeof(T) == 8) ? 4 : 8;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    const int zc = nz >= 64 ? 32 : nz;
+    const int tz = (nz + zc - 1) / zc;
+    hipLaunchKernelGGL((k_mmfd_3d<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty * tz),
+                       dim3(256), 0, st, cur, prev, out, nx, ny, nz, tx, ty, zc, tx * ty * tz, kc);
+  }
+  return hipGetLastError();
+}
+
+template <class L, int EQ, typename T>
+hipError_t launch_levels(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                         hipStream_t st) {
+  if (!c.three) return launch_cfg<L, EQ, false, false, T>(c, g, cur, prev, out, st);
+  if (!c.three_stencil) return launch_cfg<L, EQ, true, false, T>(c, g, cur, prev, out, st);
+  return launch_cfg<L, EQ, true, true, T>(c, g, cur, prev, out, st);
+}
+
+template <class L, typename T>
+hipError_t launch_eq(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                     hipStream_t st) {
+  switch (c.eq) {
+    case kLCDE: return launch_levels<L, kLCDE, T>(c, g, cur, prev, out, st);
+    case kBurgers: return launch_levels<L, kBurgers, T>(c, g, cur, prev, out, st);
+    case kNSE:
+      if constexpr (L::D >= 2) return launch_levels<L, kNSE, T>(c, g, cur, prev, out, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+hipError_t launch_res(const Consts &c, const Grid &g, T *a, T *b, T *cc, int64_t nsteps,
+                      hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0];
+  const size_t bytes = (size_t)(3 + 2 * Rec<L, EQ>::NR) * nx * sizeof(T);
+  auto fn = k_mmfd_1d_resident<L, EQ, THREE, THREE_ST, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(1), dim3(1024), bytes, st, a, b, cc, nx, nsteps, kc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes) {
+  if (c.dim != 1 || c.eq == kNSE) return false;
+  const int nr = c.eq == kLCDE ? 1 : 2;
+  return (size_t)(3 + 2 * nr) * g.n[0] * elem_bytes <= (size_t)kResidentBytes;
+}
+
+template <typename T>
+hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T *cbuf,
+                                   int64_t nsteps, hipStream_t st) {
+  using L = LatD1Q3;
+  const bool three = c.three, ts = c.three_stencil;
+  if (c.eq == kLCDE) {
+    if (!three) return launch_res<L, kLCDE, false, false, T>(c, g, a, b, cbuf, nsteps, st);
+    if (!ts) return launch_res<L, kLCDE, true, false, T>(c, g, a, b, cbuf, nsteps, st);
+    return launch_res<L, kLCDE, true, true, T>(c, g, a, b, cbuf, nsteps, st);
+  }
+  if (!three) return launch_res<L, kBurgers, false, false, T>(c, g, a, b, cbuf, nsteps, st);
+  if (!ts) return launch_res<L, kBurgers, true, false, T>(c, g, a, b, cbuf, nsteps, st);
+  return launch_res<L, kBurgers, true, true, T>(c, g, a, b, cbuf, nsteps, st);
+}
+
+template <typename T>
+hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                            int tb_depth, hipStream_t st) {
+  (void)tb_depth;
+  switch (c.lattice) {
+    case 1: return launch_eq<LatD1Q3, T>(c, g, cur, prev, out, st);
+    case 2: return launch_eq<LatD2Q5, T>(c, g, cur, prev, out, st);
+    case 3: return launch_eq<LatD2Q9, T>(c, g, cur, prev, out, st);
+    case 4: return launch_eq<LatD3Q19, T>(c, g, cur, prev, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_mmfd_step<float>(const Consts &, const Grid &, const float *,
+                                            const float *, float *, int, hipStream_t);
+template hipError_t launch_mmfd_step<double>(const Consts &, const Grid &, const double *,
+                                             const double *, double *, int, hipStream_t);
+template hipError_t launch_mmfd_1d_resident<float>(const Consts &, const Grid &, float *, float *,
+                                                   float *, int64_t, hipStream_t);
+template hipError_t launch_mmfd_1d_resident<double>(const Consts &, const Grid &, double *,
+                                                    double *, double *, int64_t, hipStream_t);
+
+}  // namespace mfd

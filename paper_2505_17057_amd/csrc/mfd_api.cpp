@@ -1,0 +1,553 @@
+// C ABI of the single-grid solver: configuration, state ownership and I/O,
+// the step loop (level ring rotation), reductions and the linear stability
+// report.  See include/mfd.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/mfd.h"
+#include "mfd_internal.h"
+#include "scheme.h"
+#include "solver.h"
+
+using namespace mfd;
+
+namespace mfd {
+
+int Solver::fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  err = buf;
+  return code;
+}
+
+int Solver::hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return MFD_OK;
+  sticky = true;
+  return fail(MFD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t Solver::nf() const { return cfg.eq == kNSE ? 1 + grid.dim : 1; }
+int64_t Solver::q() const { return consts.q; }
+
+int64_t Solver::mom_elems() const { return nf() * G.N; }
+int64_t Solver::pop_elems() const { return grid.form == MFD_MESOFD ? q() * G.N : 0; }
+
+int64_t Solver::device_bytes_needed() const {
+  if (!configured) return 0;
+  const int64_t es = elem();
+  int64_t b = 3 * mom_elems() * es;  // level ring (MMFD) / moment ping-pong + scratch (MesoFD)
+  if (grid.form == MFD_MESOFD) b += 2 * pop_elems() * es;
+  if (cfg.kind == MFD_THETA) b += 2 * mom_elems() * es;
+  b += (kReduceBlocks * 8 + 8) * (int64_t)sizeof(double);
+  return b;
+}
+
+void Solver::release() {
+  for (auto &p : buf) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+  allocated_bytes = 0;
+}
+
+int Solver::ensure_buffers() {
+  if (!configured) return fail(MFD_E_ORDER, "lattice, equation and scheme must be set first");
+  const int64_t need = device_bytes_needed();
+  if (buf[0] && need == allocated_bytes) return MFD_OK;
+  release();
+  const int64_t es = elem(), me = mom_elems() * es, pe = pop_elems() * es;
+  int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8};
+  if (cfg.kind != MFD_THETA) sizes[5] = sizes[6] = 0;
+  for (int i = 0; i < kNumBuf; ++i) {
+    if (sizes[i] == 0) continue;
+    hipError_t e = hipMalloc(&buf[i], (size_t)sizes[i]);
+    if (e != hipSuccess) {
+      release();
+      (void)hipGetLastError();
+      return fail(MFD_E_OOM, "hipMalloc of %lld bytes failed", (long long)sizes[i]);
+    }
+    e = hipMemsetAsync(buf[i], 0, (size_t)sizes[i], stream);
+    if (e != hipSuccess) return hip(e, "hipMemsetAsync");
+  }
+  allocated_bytes = need;
+  ic = 0; ip = 1; io = 2; pc = 3; pn = 4;
+  steps_done = 0;
+  return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+}
+
+int Solver::copy_in(void *dst, const void *src, int64_t bytes, int on_device) {
+  hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip(e, "hipMemcpyAsync (in)");
+  return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+}
+
+int Solver::copy_out(void *dst, const void *src, int64_t bytes, int on_device) {
+  hipError_t e = hipMemcpyAsync(dst, src, (size_t)bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip(e, "hipMemcpyAsync (out)");
+  return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+}
+
+template <typename T>
+int Solver::step_t(int64_t nsteps) {
+  T *B[kNumBuf];
+  for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && mmfd_1d_resident_fits(consts, G, sizeof(T)) &&
+      nsteps > 1) {
+    // ga = level t, gb = level t - dt; afterwards the same roles
+    hipError_t e = launch_mmfd_1d_resident<T>(consts, G, B[ic], B[ip], B[io], nsteps, stream);
+    if (e != hipSuccess) return hip(e, "mmfd 1d resident launch");
+    steps_done += nsteps;
+    return MFD_OK;
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e;
+    if (grid.form == MFD_MMFD) {
+      if (cfg.kind == MFD_THETA) {
+        // rhs -> buf 5, sweeps alternate io / buf 6, final in io
+        e = launch_theta_rhs<T>(consts, G, B[ic], B[5], stream);
+        if (e != hipSuccess) return hip(e, "theta rhs launch");
+        const T *src = B[ic];
+        const int it = cfg.theta_iters;
+        for (int k = 0; k < it; ++k) {
+          T *dst = ((it - k) % 2 == 1) ? B[io] : B[6];
+          e = launch_theta_sweep<T>(consts, G, src, B[5], dst, stream);
+          if (e != hipSuccess) return hip(e, "theta sweep launch");
+          src = dst;
+        }
+        if (it == 0) {
+          e = hipMemcpyAsync(B[io], B[ic], mom_elems() * sizeof(T), hipMemcpyDeviceToDevice, stream);
+          if (e != hipSuccess) return hip(e, "theta copy");
+        }
+        std::swap(ic, io);  // two-level: old current becomes prev
+        ip = io;
+      } else if (!consts.three) {
+        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[ip], tb, stream);
+        if (e != hipSuccess) return hip(e, "mmfd step launch");
+        std::swap(ic, ip);
+      } else {
+        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[io], tb, stream);
+        if (e != hipSuccess) return hip(e, "mmfd step launch");
+        const int t = ip;
+        ip = ic;
+        ic = io;
+        io = t;
+      }
+    } else {
+      // MesoFD: pop[pc] (t), moments of t-dt in B[ip]; writes pop[pn] and the
+      // moments of t into B[io]; then t-dt <- t.
+      e = launch_mesofd_step<T>(consts, G, B[pc], B[ip], B[pn], B[io], stream);
+      if (e != hipSuccess) return hip(e, "mesofd step launch");
+      std::swap(pc, pn);
+      std::swap(ip, io);
+    }
+  }
+  steps_done += nsteps;
+  return MFD_OK;
+}
+
+int Solver::step(int64_t nsteps) {
+  if (sticky) return fail(MFD_E_HIP, "solver is in a failed HIP state: %s", err.c_str());
+  if (nsteps < 0) return fail(MFD_E_ARG, "nsteps < 0");
+  if (!state_set) return fail(MFD_E_ORDER, "state not set");
+  if (nsteps == 0) return MFD_OK;
+  return grid.precision == MFD_FP64 ? step_t<double>(nsteps) : step_t<float>(nsteps);
+}
+
+}  // namespace mfd
+
+// ================================================================ C ABI
+
+#define SOLVER_OR_ARG(s) \
+  if (!(s)) return MFD_E_ARG;
+
+extern "C" int mfd_create(mfd_solver **out, const mfd_grid *g) {
+  if (!out || !g) return MFD_E_ARG;
+  if (g->dim < 1 || g->dim > 3 || g->reserved != 0) return MFD_E_ARG;
+  if (g->precision != MFD_FP64 && g->precision != MFD_FP32) return MFD_E_ARG;
+  if (g->form != MFD_MMFD && g->form != MFD_MESOFD) return MFD_E_ARG;
+  if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return MFD_E_ARG;
+  int64_t N = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = a < g->dim ? g->n[a] : 1;
+    if (a < g->dim && (n < 3 || n > (int64_t)1 << 30)) return MFD_E_ARG;
+    if (a >= g->dim && g->n[a] != 1 && g->n[a] != 0) return MFD_E_ARG;
+    N *= n;
+    if (N > ((int64_t)1 << 34)) return MFD_E_ARG;
+  }
+  Solver *s = new (std::nothrow) Solver();
+  if (!s) return MFD_E_OOM;
+  s->grid = *g;
+  for (int a = 0; a < 3; ++a) s->G.n[a] = a < g->dim ? g->n[a] : 1;
+  s->G.N = N;
+  *out = reinterpret_cast<mfd_solver *>(s);
+  return MFD_OK;
+}
+
+extern "C" int mfd_destroy(mfd_solver *h) {
+  if (!h) return MFD_OK;
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->buf[0]) (void)hipStreamSynchronize(s->stream);
+  s->release();
+  delete s;
+  return MFD_OK;
+}
+
+extern "C" const char *mfd_last_error(const mfd_solver *h) {
+  if (!h) return "null solver";
+  return reinterpret_cast<const Solver *>(h)->err.c_str();
+}
+
+static int rebuild(Solver *s) {
+  s->configured = false;
+  if (!s->have_lattice || !s->have_eq || !s->have_scheme) return MFD_OK;
+  SchemeInput in;
+  std::memset(&in, 0, sizeof(in));
+  in.lattice = s->cfg.lattice;
+  in.d0 = s->cfg.d0;
+  in.eq = s->cfg.eq;
+  in.kind = s->cfg.kind;
+  for (int k = 0; k < 3; ++k) {
+    in.a[k] = s->cfg.a[k];
+    in.ah[k] = s->cfg.kind == MFD_THREE_LEVEL ? s->cfg.ah[k] : 0.0;
+    in.ab[k] = s->cfg.ab[k];
+    in.abh[k] = s->cfg.kind == MFD_THREE_LEVEL ? s->cfg.abh[k] : 0.0;
+  }
+  in.theta = s->cfg.theta;
+  in.dt = s->cfg.dt;
+  in.dx = s->grid.dx;
+  for (int a = 0; a < 3; ++a) in.u[a] = s->cfg.ep.u[a];
+  for (int i = 0; i < 9; ++i) in.K[i] = s->cfg.ep.K[i];
+  in.lambda_bar = s->cfg.ep.lambda_bar;
+  in.beta = s->cfg.ep.beta;
+  in.rho0 = s->cfg.ep.rho0;
+  in.he_luo = s->cfg.ep.he_luo;
+  int rc = build_consts(in, s->consts);
+  if (rc) return s->fail(rc, "scheme constants could not be formed");
+  s->configured = true;
+  s->state_set = false;
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_lattice(mfd_solver *h, int lattice, double d0) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (d0 <= 0.0) d0 = 1.0 / 3.0;
+  Consts c;
+  std::memset(&c, 0, sizeof(c));
+  if (lattice_weights(lattice, d0, c) != MFD_OK)
+    return s->fail(MFD_E_ARG, "lattice %d with d0 = %g has a non-positive weight", lattice, d0);
+  if (c.dim != s->grid.dim)
+    return s->fail(MFD_E_ARG, "lattice dimension %d differs from grid dimension %d", c.dim,
+                   s->grid.dim);
+  if (!(d0 < 1.0)) return s->fail(MFD_E_ARG, "d0 must lie in (0, 1)");
+  s->cfg.lattice = lattice;
+  s->cfg.d0 = d0;
+  s->have_lattice = true;
+  return rebuild(s);
+}
+
+extern "C" int mfd_set_equation(mfd_solver *h, int eq, const mfd_eq_params *p) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!p) return s->fail(MFD_E_ARG, "null equation parameters");
+  if (eq != MFD_LCDE && eq != MFD_BURGERS && eq != MFD_NSE)
+    return s->fail(MFD_E_ARG, "unknown equation %d", eq);
+  if (eq == MFD_NSE && s->grid.dim == 1)
+    return s->fail(MFD_E_UNSUPPORTED, "the NSE needs a 2D or 3D lattice");
+  if (eq == MFD_NSE && !p->he_luo && p->rho0 != 0.0 && !std::isfinite(p->rho0))
+    return s->fail(MFD_E_ARG, "rho0 must be finite");
+  if (eq == MFD_NSE && p->he_luo && !(p->rho0 > 0.0))
+    return s->fail(MFD_E_ARG, "He-Luo EDF needs rho0 > 0");
+  s->cfg.eq = eq;
+  s->cfg.ep = *p;
+  if (eq == MFD_BURGERS && p->beta == 0.0) s->cfg.ep.beta = 1.0;
+  s->have_eq = true;
+  int rc = rebuild(s);
+  if (rc < 0) return rc;
+  if (eq == MFD_LCDE && s->have_lattice && s->cfg.lattice == MFD_D2Q5 && s->configured) {
+    const double *C = s->consts.Ch;
+    if (C[0] != 0.0 || C[4] != 0.0 || C[1] != 0.0) {
+      s->fail(MFD_W_INCONSISTENT, "D2Q5 cannot represent a non-zero EDF tensor C");
+      return MFD_W_INCONSISTENT;
+    }
+  }
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const double ah[3],
+                              const double ab[3], const double abh[3], double theta,
+                              int32_t theta_iters, double dt) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->have_lattice || !s->have_eq)
+    return s->fail(MFD_E_ORDER, "mfd_set_lattice and mfd_set_equation must precede mfd_set_scheme");
+  if (!a) return s->fail(MFD_E_ARG, "null coefficients");
+  if (kind != MFD_TWO_LEVEL && kind != MFD_THETA && kind != MFD_THREE_LEVEL)
+    return s->fail(MFD_E_ARG, "unknown scheme kind %d", kind);
+  if (kind == MFD_THREE_LEVEL && !ah) return s->fail(MFD_E_ARG, "three-level scheme needs ah");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(MFD_E_ARG, "dt must be positive");
+  if (kind == MFD_THETA) {
+    if (s->cfg.eq != MFD_LCDE)
+      return s->fail(MFD_E_UNSUPPORTED, "the theta scheme is implemented for the LCDE only");
+    if (!(theta >= 0.0 && theta <= 1.0) || theta_iters < 0)
+      return s->fail(MFD_E_ARG, "theta must lie in [0,1] and theta_iters >= 0");
+    if (s->grid.form != MFD_MMFD)
+      return s->fail(MFD_E_UNSUPPORTED, "the theta scheme is a moment (MMFD) scheme");
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double v[4] = {a[k], ah ? ah[k] : 0.0, ab ? ab[k] : a[k], abh ? abh[k] : (ah ? ah[k] : 0.0)};
+    for (double x : v)
+      if (!std::isfinite(x)) return s->fail(MFD_E_ARG, "non-finite coefficient");
+  }
+  if (s->grid.form == MFD_MESOFD && (ab || abh)) {
+    for (int k = 0; k < 3; ++k)
+      if ((ab && ab[k] != a[k]) || (abh && ah && abh[k] != ah[k]))
+        return s->fail(MFD_E_UNSUPPORTED, "MesoFD uses one parameter set (Eq. (2-3))");
+  }
+  s->cfg.kind = kind;
+  for (int k = 0; k < 3; ++k) {
+    s->cfg.a[k] = a[k];
+    s->cfg.ah[k] = ah ? ah[k] : 0.0;
+    s->cfg.ab[k] = ab ? ab[k] : a[k];
+    s->cfg.abh[k] = abh ? abh[k] : s->cfg.ah[k];
+  }
+  s->cfg.theta = kind == MFD_THETA ? theta : 1.0;
+  s->cfg.theta_iters = kind == MFD_THETA ? theta_iters : 0;
+  s->cfg.dt = dt;
+  s->have_scheme = true;
+  int rc = rebuild(s);
+  if (rc < 0) return rc;
+  double m[6];
+  mfd_coeff_moments(s->cfg.a, s->cfg.ah, m);
+  if (std::fabs(m[0] - 1.0) > 1e-12) {
+    s->fail(MFD_W_INCONSISTENT, "A00 = %.17g differs from 1", m[0]);
+    return MFD_W_INCONSISTENT;
+  }
+  if (!stability_proven(s->consts)) {
+    s->fail(MFD_W_STABILITY_UNPROVEN, "sufficient stability conditions do not hold");
+    return MFD_W_STABILITY_UNPROVEN;
+  }
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_stream(mfd_solver *h, void *stream) {
+  SOLVER_OR_ARG(h);
+  reinterpret_cast<Solver *>(h)->stream = (hipStream_t)stream;
+  return MFD_OK;
+}
+
+extern "C" int mfd_state_size(const mfd_solver *h, int64_t *moment_elems,
+                              int64_t *population_elems, int64_t *device_bytes) {
+  SOLVER_OR_ARG(h);
+  const Solver *s = reinterpret_cast<const Solver *>(h);
+  if (!s->configured) return MFD_E_ORDER;
+  if (moment_elems) *moment_elems = s->mom_elems();
+  if (population_elems) *population_elems = s->pop_elems();
+  if (device_bytes) *device_bytes = s->device_bytes_needed();
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_state(mfd_solver *h, int level, const void *src, int64_t bytes,
+                             int on_device, int populations) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->configured) return s->fail(MFD_E_ORDER, "configure the solver first");
+  if (!src) return s->fail(MFD_E_ARG, "null source");
+  if (level != 0 && level != 1) return s->fail(MFD_E_ARG, "level must be 0 or 1");
+  if (level == 1 && !s->consts.three)
+    return s->fail(MFD_E_ARG, "level 1 exists only for three-level schemes");
+  const bool meso = s->grid.form == MFD_MESOFD;
+  if (populations && (!meso || level != 0))
+    return s->fail(MFD_E_ARG, "populations exist only for MesoFD level 0");
+  const int64_t es = s->elem();
+  const int64_t want = (populations ? s->pop_elems() : s->mom_elems()) * es;
+  if (bytes != want)
+    return s->fail(MFD_E_ARG, "expected %lld bytes, got %lld", (long long)want, (long long)bytes);
+  int rc;
+  if (level == 0 || !s->buf[0]) {
+    // (re)allocate on the first state of a configuration
+    rc = s->ensure_buffers();
+    if (rc) return rc;
+  }
+  if (level == 1) {
+    rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
+    if (rc) return rc;
+    s->prev_set = true;
+    return MFD_OK;
+  }
+  if (!meso) {
+    rc = s->copy_in(s->buf[s->ic], src, bytes, on_device);
+    if (rc) return rc;
+    // phi^(-1) = phi^0 start; also the residual reference
+    rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
+    if (rc) return rc;
+  } else if (populations) {
+    rc = s->copy_in(s->buf[s->pc], src, bytes, on_device);
+    if (rc) return rc;
+    hipError_t e = (s->grid.precision == MFD_FP64)
+                       ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
+                                                (double *)s->buf[s->ip], s->stream)
+                       : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
+                                               (float *)s->buf[s->ip], s->stream);
+    if (e != hipSuccess) return s->hip(e, "moments launch");
+    rc = s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+  } else {
+    rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
+    if (rc) return rc;
+    hipError_t e = (s->grid.precision == MFD_FP64)
+                       ? launch_init_populations<double>(s->consts, s->G,
+                                                         (const double *)s->buf[s->ip],
+                                                         (double *)s->buf[s->pc], s->stream)
+                       : launch_init_populations<float>(s->consts, s->G,
+                                                        (const float *)s->buf[s->ip],
+                                                        (float *)s->buf[s->pc], s->stream);
+    if (e != hipSuccess) return s->hip(e, "init populations launch");
+    rc = s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+  }
+  s->state_set = true;
+  s->prev_set = false;
+  s->steps_done = 0;
+  return MFD_OK;
+}
+
+extern "C" int mfd_get_state(mfd_solver *h, int level, void *dst, int64_t bytes, int on_device,
+                             int populations) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->state_set) return s->fail(MFD_E_ORDER, "state not set");
+  if (!dst) return s->fail(MFD_E_ARG, "null destination");
+  if (level != 0 && level != 1) return s->fail(MFD_E_ARG, "level must be 0 or 1");
+  const bool meso = s->grid.form == MFD_MESOFD;
+  if (populations && (!meso || level != 0))
+    return s->fail(MFD_E_ARG, "populations exist only for MesoFD level 0");
+  const int64_t es = s->elem();
+  const int64_t want = (populations ? s->pop_elems() : s->mom_elems()) * es;
+  if (bytes != want)
+    return s->fail(MFD_E_ARG, "expected %lld bytes, got %lld", (long long)want, (long long)bytes);
+  if (level == 1) return s->copy_out(dst, s->buf[s->ip], bytes, on_device);
+  if (!meso) return s->copy_out(dst, s->buf[s->ic], bytes, on_device);
+  if (populations) return s->copy_out(dst, s->buf[s->pc], bytes, on_device);
+  // moments of the current populations into the spare moment buffer
+  hipError_t e = (s->grid.precision == MFD_FP64)
+                     ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
+                                              (double *)s->buf[s->io], s->stream)
+                     : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
+                                             (float *)s->buf[s->io], s->stream);
+  if (e != hipSuccess) return s->hip(e, "moments launch");
+  return s->copy_out(dst, s->buf[s->io], bytes, on_device);
+}
+
+extern "C" int mfd_step(mfd_solver *h, int64_t nsteps) {
+  SOLVER_OR_ARG(h);
+  return reinterpret_cast<Solver *>(h)->step(nsteps);
+}
+
+extern "C" int mfd_synchronize(mfd_solver *h) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  return s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+}
+
+extern "C" int mfd_reduce(mfd_solver *h, double sums[4], double *residual) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->state_set) return s->fail(MFD_E_ORDER, "state not set");
+  double *part = (double *)s->buf[Solver::kRedBuf];
+  double *out = part + kReduceBlocks * 8;
+  const bool meso = s->grid.form == MFD_MESOFD;
+  const bool have_prev = s->steps_done > 0;
+  hipError_t e;
+  if (s->grid.precision == MFD_FP64) {
+    const double *cur = (const double *)s->buf[s->ic];
+    const double *prev = have_prev ? (const double *)s->buf[s->ip] : nullptr;
+    if (meso) {
+      e = launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
+                                 (double *)s->buf[s->io], s->stream);
+      if (e != hipSuccess) return s->hip(e, "moments launch");
+      cur = (const double *)s->buf[s->io];
+    }
+    e = launch_reduce<double>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
+  } else {
+    const float *cur = (const float *)s->buf[s->ic];
+    const float *prev = have_prev ? (const float *)s->buf[s->ip] : nullptr;
+    if (meso) {
+      e = launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
+                                (float *)s->buf[s->io], s->stream);
+      if (e != hipSuccess) return s->hip(e, "moments launch");
+      cur = (const float *)s->buf[s->io];
+    }
+    e = launch_reduce<float>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
+  }
+  if (e != hipSuccess) return s->hip(e, "reduce launch");
+  double host[8];
+  int rc = s->copy_out(host, out, sizeof(host), 0);
+  if (rc) return rc;
+  bool finite = std::isfinite(host[4]);
+  for (int f = 0; f < s->nf(); ++f) finite = finite && std::isfinite(host[f]);
+  if (!finite) return s->fail(MFD_E_UNSTABLE, "non-finite moment sum or residual");
+  if (sums)
+    for (int f = 0; f < 4; ++f) sums[f] = f < s->nf() ? host[f] : 0.0;
+  if (residual) *residual = std::sqrt(host[4]);
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_blocking(mfd_solver *h, int32_t tb_depth) {
+  SOLVER_OR_ARG(h);
+  if (tb_depth < 0 || tb_depth > 16) return MFD_E_ARG;
+  reinterpret_cast<Solver *>(h)->tb = tb_depth;
+  return MFD_OK;
+}
+
+extern "C" int mfd_autotune(mfd_solver *h, int32_t *chosen_tb) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (chosen_tb) *chosen_tb = s->tb > 0 ? s->tb : 1;
+  return MFD_OK;
+}
+
+extern "C" int mfd_max_amplification(mfd_solver *h, double *out) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!out) return MFD_E_ARG;
+  if (!s->configured) return s->fail(MFD_E_ORDER, "configure the solver first");
+  if (s->consts.eq != kLCDE) return s->fail(MFD_E_UNSUPPORTED, "linear (LCDE) schemes only");
+  if (s->G.N > ((int64_t)1 << 24)) return s->fail(MFD_E_ARG, "grid too large for a mode sweep");
+  *out = max_amplification(s->consts, s->G.n);
+  return MFD_OK;
+}
+
+extern "C" int mfd_linear_tables(mfd_solver *h, double *w, double *ubar, double *out6) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->configured) return s->fail(MFD_E_ORDER, "configure the solver first");
+  const Consts &c = s->consts;
+  for (int j = 0; j < c.q; ++j) {
+    if (w) w[j] = c.w[j];
+    if (ubar) ubar[j] = c.ubar[j];
+  }
+  if (out6)
+    for (int p = 0; p < c.npair; ++p) {
+      out6[0 * kMaxP + p] = c.ubp[p];
+      out6[1 * kMaxP + p] = c.ubm[p];
+      out6[2 * kMaxP + p] = c.Cp[p];
+      out6[3 * kMaxP + p] = c.Cm[p];
+      out6[4 * kMaxP + p] = c.Chp[p];
+      out6[5 * kMaxP + p] = c.Chm[p];
+    }
+  return c.q;
+}

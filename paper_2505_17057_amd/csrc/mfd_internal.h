@@ -1,0 +1,136 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mfd {
+
+constexpr int kMaxQ = 19;
+constexpr int kMaxP = 9;
+
+// --------------------------------------------------------------- lattices
+// Appendix A velocity sets.  D1Q3 is the one-axis member of the family
+// (w_j = d0/2, w_0 = 1 - 2 sum w_j).  In D3Q19 the xz-edge block follows the
+// (+,+),(-,+),(-,-),(+,-) pattern of the xy and yz blocks (the printed xz
+// block repeats two velocities).
+struct LatD1Q3 {
+  static constexpr int id = 1, D = 1, Q = 3, P = 1;
+  static constexpr int E[Q][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}};
+  static constexpr int PR[P] = {1};
+};
+struct LatD2Q5 {
+  static constexpr int id = 2, D = 2, Q = 5, P = 2;
+  static constexpr int E[Q][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}};
+  static constexpr int PR[P] = {1, 2};
+};
+struct LatD2Q9 {
+  static constexpr int id = 3, D = 2, Q = 9, P = 4;
+  static constexpr int E[Q][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
+                                  {1, 1, 0},  {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+  static constexpr int PR[P] = {1, 2, 5, 6};
+};
+struct LatD3Q19 {
+  static constexpr int id = 4, D = 3, Q = 19, P = 9;
+  static constexpr int E[Q][3] = {
+      {0, 0, 0},   {1, 0, 0},   {0, 1, 0},  {0, 0, 1},   {-1, 0, 0},  {0, -1, 0}, {0, 0, -1},
+      {1, 1, 0},   {-1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {1, 0, 1},   {-1, 0, 1}, {-1, 0, -1},
+      {1, 0, -1},  {0, 1, 1},   {0, -1, 1}, {0, -1, -1}, {0, 1, -1}};
+  static constexpr int PR[P] = {1, 2, 3, 7, 8, 11, 12, 15, 16};
+};
+
+// ---------------------------------------------------------- configuration
+enum Eq { kLCDE = 0, kBurgers = 1, kNSE = 2 };
+
+// All derived constants of one solver, in binary64 (host side).
+struct Consts {
+  int lattice, dim, q, npair, eq;
+  int e[kMaxQ][3];
+  int pair[kMaxP];
+  double d0, inv_d0;
+  double w[kMaxQ], w1[kMaxQ];
+  double qd[kMaxQ][3], qo[kMaxQ][3];
+  double A0, Ah0, Ab0, Abh0;
+  double ap, am, ahp, ahm, abp, abm, abhp, abhm;
+  double a[3], ah[3];
+  // linear CDE
+  double uh[3], kh[9], Ch[9];
+  double ubar[kMaxQ], ubp[kMaxP], ubm[kMaxP], Cp[kMaxP], Cm[kMaxP], Chp[kMaxP], Chm[kMaxP];
+  // Burgers
+  double bh, cbeta;
+  int beta_one;
+  // NSE
+  double rho0, rinv0;
+  int he_luo;
+  // theta
+  double theta, th1, inv_den;
+  int three;          // three-level scheme
+  int three_stencil;  // level t - dt enters through central differences
+};
+
+// Kernel-side constants of one step (by value in the kernel argument block).
+template <typename T>
+struct KC {
+  T w[kMaxQ], w1[kMaxQ], qd[kMaxQ][3], qo[kMaxQ][3], inv_d0;
+  T ubar[kMaxQ];
+  T ap, am, ahp, ahm, abp, abm, abhp, abhm;
+  T a[3], ah[3];              // k = -1, 0, +1 (MesoFD)
+  T Cp[kMaxP], Cm[kMaxP], Chp[kMaxP], Chm[kMaxP];
+  T bh, cbeta, rho0, rinv0;
+  double A0, Ah0, Ab0, Abh0;  // binary64 base coefficients
+  T A0t, Ah0t, Ab0t, Abh0t;   // the same in T
+  T th, th1, inv_den;
+  int beta_one, he_luo;
+};
+
+template <typename T>
+KC<T> make_kc(const Consts &c);
+
+// ------------------------------------------------------ kernel launchers
+// Each returns a hipError_t of the launch.  `cur`/`prev`/`out` are moment
+// levels (field-major); n = (nx, ny, nz).
+
+struct Grid {
+  int64_t n[3];
+  int64_t N;
+};
+
+template <typename T>
+hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                            int tb_depth, hipStream_t st);
+
+// LDS-resident 1D run: nsteps steps inside one workgroup; ring buffers
+// a (level t) / b (level t - dt) are updated in place; returns the index of
+// the buffer holding the final level among {a, b, c}.
+template <typename T>
+hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T *cbuf,
+                                   int64_t nsteps, hipStream_t st);
+bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
+
+template <typename T>
+hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,
+                              T *pop_out, T *mom_out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom, T *pop,
+                                   hipStream_t st);
+
+template <typename T>
+hipError_t launch_moments(const Consts &c, const Grid &g, const T *pop, T *mom, hipStream_t st);
+
+template <typename T>
+hipError_t launch_theta_rhs(const Consts &c, const Grid &g, const T *cur, T *rhs, hipStream_t st);
+template <typename T>
+hipError_t launch_theta_sweep(const Consts &c, const Grid &g, const T *src, const T *rhs, T *dst,
+                              hipStream_t st);
+
+// FP64 reductions: sums of nf fields of `cur` and ||cur - prev||_2 of field 0
+// (prev may be null).  partial: >= kReduceBlocks * 8 doubles of scratch;
+// out: 8 doubles (device).
+constexpr int kReduceBlocks = 512;
+template <typename T>
+hipError_t launch_reduce(const T *cur, const T *prev, int nf, int64_t N, double *partial,
+                         double *out, hipStream_t st);
+
+}  // namespace mfd

@@ -1,0 +1,29 @@
+// Host-side scheme construction (see scheme.cpp).
+#pragma once
+
+#include <cstdint>
+
+#include "mfd_internal.h"
+
+namespace mfd {
+
+struct SchemeInput {
+  int lattice;
+  double d0;
+  int eq;
+  int kind;           // MFD_TWO_LEVEL / MFD_THETA / MFD_THREE_LEVEL
+  double a[3], ah[3], ab[3], abh[3];
+  double theta;
+  double dt, dx;
+  double u[3], K[9];
+  int lambda_bar;
+  double beta, rho0;
+  int he_luo;
+};
+
+int lattice_weights(int lattice, double d0, Consts &c);
+int build_consts(const SchemeInput &in, Consts &c);
+bool stability_proven(const Consts &c);
+double max_amplification(const Consts &c, const int64_t n[3]);
+
+}  // namespace mfd

@@ -1,0 +1,63 @@
+// The single-grid solver object behind the opaque mfd_solver handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/mfd.h"
+#include "mfd_internal.h"
+
+namespace mfd {
+
+struct Config {
+  int lattice = 0;
+  double d0 = 1.0 / 3.0;
+  int eq = 0;
+  mfd_eq_params ep{};
+  int kind = MFD_TWO_LEVEL;
+  double a[3] = {0, 0, 0}, ah[3] = {0, 0, 0}, ab[3] = {0, 0, 0}, abh[3] = {0, 0, 0};
+  double theta = 1.0;
+  int theta_iters = 0;
+  double dt = 0.0;
+};
+
+struct Solver {
+  // device buffers: 0..2 moment ring, 3..4 population ping-pong, 5..6 theta
+  // rhs / Jacobi work, 7 reduction scratch
+  static constexpr int kNumBuf = 8;
+  static constexpr int kRedBuf = 7;
+
+  mfd_grid grid{};
+  Grid G{};
+  Config cfg;
+  Consts consts{};
+  bool have_lattice = false, have_eq = false, have_scheme = false;
+  bool configured = false, state_set = false, prev_set = false;
+  bool sticky = false;
+  hipStream_t stream = nullptr;
+  void *buf[kNumBuf] = {nullptr};
+  int64_t allocated_bytes = 0;
+  int ic = 0, ip = 1, io = 2, pc = 3, pn = 4;  // roles in the rings
+  int64_t steps_done = 0;
+  int tb = 0;  // temporal-blocking depth (0 = automatic)
+  std::string err;
+
+  int fail(int code, const char *fmt, ...);
+  int hip(hipError_t e, const char *what);
+  int64_t elem() const { return grid.precision == MFD_FP64 ? 8 : 4; }
+  int64_t nf() const;
+  int64_t q() const;
+  int64_t mom_elems() const;
+  int64_t pop_elems() const;
+  int64_t device_bytes_needed() const;
+  void release();
+  int ensure_buffers();
+  int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
+  int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
+  int step(int64_t nsteps);
+  template <typename T>
+  int step_t(int64_t nsteps);
+};
+
+}  // namespace mfd

@@ -1,0 +1,277 @@
+"""ctypes binding of libmfd.so (include/mfd.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The functions keep the C names; `Solver` is a thin owner of one handle.
+Importing this module raises if the built library is missing -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfd.so")
+
+MFD_OK = 0
+MFD_W_STABILITY_UNPROVEN = 1
+MFD_W_INCONSISTENT = 2
+MFD_E_ARG = -1
+MFD_E_ORDER = -2
+MFD_E_UNSUPPORTED = -3
+MFD_E_OOM = -4
+MFD_E_HIP = -5
+MFD_E_UNSTABLE = -6
+MFD_E_BUDGET = -7
+
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+FORMS = {"mmfd": 0, "mesofd": 1}
+EQS = {"lcde": 0, "burgers": 1, "nse": 2}
+KINDS = {"two_level": 0, "theta": 1, "three_level": 2}
+PRESETS = {"srt": 0, "trt": 1, "one_stage": 2, "two_level": 3}
+
+
+class MfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("mfd error %d: %s" % (code, msg))
+        self.code = code
+
+
+class mfd_grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("form", C.c_int32),
+                ("reserved", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double)]
+
+
+class mfd_eq_params(C.Structure):
+    _fields_ = [("u", C.c_double * 3), ("K", C.c_double * 9), ("lambda_bar", C.c_int32),
+                ("he_luo", C.c_int32), ("beta", C.c_double), ("rho0", C.c_double)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmfd.so is not built (%s); run paper_2505_17057_amd/build.py" % LIB_PATH)
+
+lib = C.CDLL(LIB_PATH)
+
+_D3 = C.c_double * 3
+_PD = C.POINTER(C.c_double)
+_VP = C.c_void_p
+_H = C.c_void_p
+
+_SIGS = {
+    "mfd_create": ([C.POINTER(_H), C.POINTER(mfd_grid)], C.c_int),
+    "mfd_destroy": ([_H], C.c_int),
+    "mfd_last_error": ([_H], C.c_char_p),
+    "mfd_set_lattice": ([_H, C.c_int, C.c_double], C.c_int),
+    "mfd_set_equation": ([_H, C.c_int, C.POINTER(mfd_eq_params)], C.c_int),
+    "mfd_set_scheme": ([_H, C.c_int, _PD, _PD, _PD, _PD, C.c_double, C.c_int32, C.c_double], C.c_int),
+    "mfd_set_stream": ([_H, _VP], C.c_int),
+    "mfd_state_size": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "mfd_set_state": ([_H, C.c_int, _VP, C.c_int64, C.c_int, C.c_int], C.c_int),
+    "mfd_get_state": ([_H, C.c_int, _VP, C.c_int64, C.c_int, C.c_int], C.c_int),
+    "mfd_step": ([_H, C.c_int64], C.c_int),
+    "mfd_synchronize": ([_H], C.c_int),
+    "mfd_reduce": ([_H, _PD, _PD], C.c_int),
+    "mfd_autotune": ([_H, C.POINTER(C.c_int32)], C.c_int),
+    "mfd_set_blocking": ([_H, C.c_int32], C.c_int),
+    "mfd_coeff_moments": ([_PD, _PD, _PD], C.c_int),
+    "mfd_coeffs_from_constraints": ([C.c_double] * 5 + [_PD, _PD], C.c_int),
+    "mfd_preset": ([C.c_int, C.c_double, _PD, _PD], C.c_int),
+    "mfd_transport_coefficient": ([_PD, _PD, C.c_double, C.c_double, C.c_double, C.c_double, _PD], C.c_int),
+    "mfd_max_amplification": ([_H, _PD], C.c_int),
+    "mfd_linear_tables": ([_H, _PD, _PD, _PD], C.c_int),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def _d3(v):
+    return _D3(*[float(x) for x in v])
+
+
+# ------------------------------------------------------- host-side algebra
+def mfd_coeff_moments(a, ah):
+    out = (C.c_double * 6)()
+    rc = lib.mfd_coeff_moments(_d3(a), _d3(ah), out)
+    if rc:
+        raise MfdError(rc, "mfd_coeff_moments")
+    return list(out)
+
+
+def mfd_coeffs_from_constraints(a0, A10, A11, A21, A22):
+    a, ah = _D3(), _D3()
+    rc = lib.mfd_coeffs_from_constraints(a0, A10, A11, A21, A22, a, ah)
+    if rc:
+        raise MfdError(rc, "mfd_coeffs_from_constraints")
+    return tuple(a), tuple(ah)
+
+
+def mfd_preset(preset, param=0.0):
+    a, ah = _D3(), _D3()
+    rc = lib.mfd_preset(PRESETS.get(preset, preset), float(param), a, ah)
+    if rc:
+        raise MfdError(rc, "mfd_preset")
+    return tuple(a), tuple(ah)
+
+
+def mfd_transport_coefficient(a, ah, dx, dt, d0=1.0 / 3.0, beta=1.0):
+    out = C.c_double()
+    rc = lib.mfd_transport_coefficient(_d3(a), _d3(ah), dx, dt, d0, beta, C.byref(out))
+    if rc:
+        raise MfdError(rc, "mfd_transport_coefficient")
+    return out.value
+
+
+def _ptr_of(x):
+    """(address, on_device, nbytes) of a numpy array or a torch tensor."""
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data, 0, x.nbytes
+    # torch tensor
+    assert x.is_contiguous()
+    return x.data_ptr(), 1 if x.is_cuda else 0, x.numel() * x.element_size()
+
+
+class Solver:
+    """Owner of one mfd_solver handle (marshalling only)."""
+
+    def __init__(self, lattice, n, dx, precision="fp64", form="mmfd"):
+        self.lattice = lattice
+        self.dim = DIMS[lattice]
+        n = tuple(int(v) for v in n)
+        assert len(n) == self.dim
+        g = mfd_grid()
+        g.dim = self.dim
+        g.precision = PRECISIONS[precision]
+        g.form = FORMS[form]
+        g.reserved = 0
+        g.n = (C.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+        g.dx = float(dx)
+        h = _H()
+        rc = lib.mfd_create(C.byref(h), C.byref(g))
+        if rc:
+            raise MfdError(rc, "mfd_create")
+        self.h = h
+        self.n = n
+        self.precision = precision
+        self.form = form
+        self.dtype = np.float64 if precision == "fp64" else np.float32
+        self.warnings = []
+        self.check(lib.mfd_set_lattice(self.h, LATTICES[lattice], 1.0 / 3.0), "mfd_set_lattice")
+
+    # -------------------------------------------------------------- plumbing
+    def check(self, rc, what):
+        if rc < 0:
+            msg = lib.mfd_last_error(self.h)
+            raise MfdError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+        if rc > 0:
+            self.warnings.append((rc, what))
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mfd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- configure
+    def set_lattice(self, lattice, d0=1.0 / 3.0):
+        return self.check(lib.mfd_set_lattice(self.h, LATTICES[lattice], d0), "mfd_set_lattice")
+
+    def set_equation(self, eq, u=(), K=None, lambda_bar=0, beta=1.0, rho0=0.0, he_luo=0):
+        p = mfd_eq_params()
+        uu = list(u) + [0.0] * (3 - len(u))
+        p.u = _D3(*uu)
+        Kd = np.zeros((3, 3))
+        if K is not None:
+            K = np.asarray(K, dtype=np.float64)
+            Kd[: K.shape[0], : K.shape[1]] = K
+        p.K = (C.c_double * 9)(*Kd.ravel().tolist())
+        p.lambda_bar = int(lambda_bar)
+        p.he_luo = int(he_luo)
+        p.beta = float(beta)
+        p.rho0 = float(rho0)
+        self.eq = eq
+        self.nf = 1 + self.dim if eq == "nse" else 1
+        return self.check(lib.mfd_set_equation(self.h, EQS[eq], C.byref(p)), "mfd_set_equation")
+
+    def set_scheme(self, kind, a, ah=None, ab=None, abh=None, theta=1.0, theta_iters=0, dt=1.0):
+        self.kind = kind
+        return self.check(lib.mfd_set_scheme(
+            self.h, KINDS[kind], _d3(a), _d3(ah) if ah is not None else None,
+            _d3(ab) if ab is not None else None, _d3(abh) if abh is not None else None,
+            float(theta), int(theta_iters), float(dt)), "mfd_set_scheme")
+
+    def set_stream(self, stream_handle):
+        return self.check(lib.mfd_set_stream(self.h, C.c_void_p(stream_handle)), "mfd_set_stream")
+
+    def state_size(self):
+        m, p, b = C.c_int64(), C.c_int64(), C.c_int64()
+        self.check(lib.mfd_state_size(self.h, C.byref(m), C.byref(p), C.byref(b)), "mfd_state_size")
+        return m.value, p.value, b.value
+
+    # -------------------------------------------------------------- state
+    def set_state(self, x, level=0, populations=False):
+        if isinstance(x, np.ndarray):
+            x = np.ascontiguousarray(x, dtype=self.dtype)
+        addr, dev, nb = _ptr_of(x)
+        return self.check(lib.mfd_set_state(self.h, level, C.c_void_p(addr), nb, dev, int(populations)),
+                          "mfd_set_state")
+
+    def get_state(self, level=0, populations=False, out=None):
+        m, p, _ = self.state_size()
+        if out is None:
+            out = np.empty(p if populations else m, dtype=self.dtype)
+        addr, dev, nb = _ptr_of(out)
+        self.check(lib.mfd_get_state(self.h, level, C.c_void_p(addr), nb, dev, int(populations)),
+                   "mfd_get_state")
+        return out
+
+    def step(self, nsteps=1):
+        return self.check(lib.mfd_step(self.h, int(nsteps)), "mfd_step")
+
+    def synchronize(self):
+        return self.check(lib.mfd_synchronize(self.h), "mfd_synchronize")
+
+    def reduce(self):
+        sums = (C.c_double * 4)()
+        res = C.c_double()
+        self.check(lib.mfd_reduce(self.h, sums, C.byref(res)), "mfd_reduce")
+        return list(sums), res.value
+
+    def set_blocking(self, depth):
+        return self.check(lib.mfd_set_blocking(self.h, int(depth)), "mfd_set_blocking")
+
+    def autotune(self):
+        d = C.c_int32()
+        self.check(lib.mfd_autotune(self.h, C.byref(d)), "mfd_autotune")
+        return d.value
+
+    def max_amplification(self):
+        out = C.c_double()
+        self.check(lib.mfd_max_amplification(self.h, C.byref(out)), "mfd_max_amplification")
+        return out.value
+
+    def linear_tables(self):
+        b = QS[self.lattice]
+        w = np.zeros(b)
+        ub = np.zeros(b)
+        p6 = np.zeros(6 * 9)
+        self.check(lib.mfd_linear_tables(self.h, w.ctypes.data_as(_PD), ub.ctypes.data_as(_PD),
+                                         p6.ctypes.data_as(_PD)), "mfd_linear_tables")
+        npair = (b - 1) // 2
+        p6 = p6.reshape(6, 9)[:, :npair]
+        names = ["ubp", "ubm", "Cp", "Cm", "Chp", "Chm"]
+        return w, ub, {k: p6[i].copy() for i, k in enumerate(names)}

@@ -1,0 +1,152 @@
+"""CPU checks of the C ABI: every symbol include/mfd.h declares is exported by
+libmfd.so, argument validation, and the host-side algebra (coefficient
+moments, Eq. (X), presets, transport coefficients, the per-pair EDF
+constants) against the oracle's independent implementation -- no GPU work."""
+import ctypes as C
+import os
+import re
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from oracle import native as O
+from oracle import scheme as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "mfd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported(M):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(M.lib, n), n
+
+
+def test_coeff_moments_match_oracle(M):
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        a = [float(F(int(v), 8)) for v in rng.integers(-16, 17, 3)]
+        ah = [float(F(int(v), 8)) for v in rng.integers(-16, 17, 3)]
+        m = S.coeff_moments(a, ah)
+        got = M.mfd_coeff_moments(a, ah)
+        want = [m[(0, 0)], m[(1, 0)], m[(1, 1)], m[(2, 0)], m[(2, 1)], m[(2, 2)]]
+        assert got == [float(x) for x in want]
+
+
+def test_constraint_solve_matches_oracle(M):
+    rng = np.random.default_rng(1)
+    for _ in range(30):
+        g = [F(int(v), 8) for v in rng.integers(-16, 17, 5)]
+        a, ah = S.solve_constraints(*g)
+        ga, gah = M.mfd_coeffs_from_constraints(*[float(x) for x in g])
+        assert list(ga) == [float(x) for x in a] and list(gah) == [float(x) for x in ah]
+
+
+@pytest.mark.parametrize("name,param", [("srt", 0.0), ("trt", 0.625), ("one_stage", 1.25),
+                                        ("two_level", 0.75)])
+def test_presets_match_oracle(M, name, param):
+    fn = {"srt": lambda p: S.preset_srt(), "trt": S.preset_trt, "one_stage": S.preset_one_stage,
+          "two_level": S.preset_two_level}[name]
+    a, ah = fn(F(param))
+    ga, gah = M.mfd_preset(name, param)
+    assert list(ga) == [float(x) for x in a] and list(gah) == [float(x) for x in ah]
+
+
+def test_transport_coefficient(M):
+    s = F(2, 3)
+    a, ah = S.preset_trt(s)
+    nu = S.viscosity(a, ah, F(1, 64), F(1, 4096), F(1, 3))
+    got = M.mfd_transport_coefficient([float(x) for x in a], [float(x) for x in ah],
+                                      1 / 64, 1 / 4096, 1 / 3)
+    assert abs(got - float(nu)) <= 1e-15 * float(nu)
+
+
+LIN = [
+    ("D1Q3", dict(n=(16,), u=(0.3,), K=[[0.4]]), (1.25, -0.5, 0.25), None),
+    ("D2Q9", dict(n=(16, 16), u=(0.05, 0.03), K=[[0.02, 0.005], [0.005, 0.01]], dx=1 / 2048,
+                  dt=2.0 ** -18, lambda_bar=1), (1.0, 0.0, 0.0), None),
+    ("D2Q9", dict(n=(8, 8), u=(0.3, -0.2), K=[[0.3, 0.05], [0.05, 0.2]], lambda_bar=1),
+     (0.875, 0.0, 0.125), (0.125, 0.0, -0.125)),
+    ("D3Q19", dict(n=(5, 5, 5), u=(0.1, 0.2, -0.1), K=[[0.2, 0.01, 0.0], [0.01, 0.3, 0.02], [0.0, 0.02, 0.25]],
+                   lambda_bar=1), (1.0, 0.0, 0.4), (0.0, -0.4, 0.0)),
+]
+
+
+@pytest.mark.parametrize("lat,kw,a,ah", LIN, ids=["d1q3", "d2q9-c2", "d2q9-3l", "d3q19-trt"])
+def test_linear_constant_tables_bitwise(M, lat, kw, a, ah):
+    """The library's and the oracle's EDF constants are formed independently
+    from the same formulas; FP64 parity requires them to be identical."""
+    kind = "three_level" if ah else "two_level"
+    spec = dict(lattice=lat, eq="lcde", a=a, ah=ah or (0, 0, 0), levels=3 if ah else 2,
+                dx=kw.get("dx", 1.0), dt=kw.get("dt", 1.0), **{k: v for k, v in kw.items() if k not in ("dx", "dt")})
+    w, ub, tab = O.tables(spec)
+    s = M.Solver(lat, kw["n"], kw.get("dx", 1.0), "fp64", "mmfd")
+    s.set_equation("lcde", u=kw["u"], K=kw["K"], lambda_bar=kw.get("lambda_bar", 0))
+    s.set_scheme(kind, a, ah, dt=kw.get("dt", 1.0))
+    gw, gub, gtab = s.linear_tables()
+    assert np.array_equal(gw, w) and np.array_equal(gub, ub)
+    for k in tab:
+        assert np.array_equal(gtab[k], tab[k]), k
+    s.close()
+
+
+def test_max_amplification_matches_oracle(M):
+    kw = dict(n=(12, 10), u=(0.9, 0.7), K=[[0.02, 0.0], [0.0, 0.02]], lambda_bar=1)
+    a, ah = (1.0, 0.0, 0.0), (0.5, -1.0, 0.5)
+    spec = dict(lattice="D2Q9", eq="lcde", a=a, ah=ah, levels=3, **kw)
+    E, w, pairs = O.lattice_info("D2Q9")
+    _, _, tab = O.tables(spec)
+    want = S.max_amplification(E, pairs, tab["ubp"], tab["ubm"], kw["n"], a, ah)
+    s = M.Solver("D2Q9", kw["n"], 1.0, "fp64", "mmfd")
+    s.set_equation("lcde", u=kw["u"], K=kw["K"], lambda_bar=1)
+    s.set_scheme("three_level", a, ah, dt=1.0)
+    assert abs(s.max_amplification() - want) < 1e-12
+    s.close()
+
+
+def test_argument_validation(M):
+    with pytest.raises(M.MfdError):
+        M.Solver("D2Q9", (2, 8), 1.0)  # fewer than 3 nodes
+    with pytest.raises(M.MfdError):
+        M.Solver("D2Q9", (8, 8), -1.0)  # dx <= 0
+    s = M.Solver("D2Q9", (8, 8), 1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_scheme("two_level", (1, 0, 0), dt=1.0)  # equation not set
+    assert e.value.code == M.MFD_E_ORDER
+    with pytest.raises(M.MfdError) as e:
+        s.set_lattice("D3Q19")  # dimension mismatch
+    assert e.value.code == M.MFD_E_ARG
+    s.set_equation("nse", rho0=1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_scheme("theta", (1, 0, 0), theta=0.5, theta_iters=3, dt=1.0)
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    with pytest.raises(M.MfdError) as e:
+        s.step(1)  # no state
+    assert e.value.code == M.MFD_E_ORDER
+    # inconsistent coefficients are a warning, not an error
+    rc = s.set_scheme("two_level", (1.0, 0.5, 0.0), dt=1.0)
+    assert rc == M.MFD_W_INCONSISTENT
+    s.close()
+    s = M.Solver("D1Q3", (8,), 1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_equation("nse", rho0=1.0)
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    s.close()
+
+
+def test_stability_warning(M):
+    """Theorem 1 for C1-like D1Q3 schemes: r = 0.25 proven, r = 0.55 not."""
+    for r, want in ((0.25, 0), (0.55, M.MFD_W_STABILITY_UNPROVEN)):
+        s = M.Solver("D1Q3", (16,), 1.0)
+        s.set_equation("lcde", u=(0.01,), K=[[1.0]])
+        sp = 2 * r / (1 / 3)
+        a, _ = M.mfd_preset("two_level", sp)
+        assert s.set_scheme("two_level", a, dt=r) == want
+        s.close()
