@@ -186,7 +186,10 @@ int mfd_synchronize(mfd_solver *s);
 /* FP64 reductions over the current level (synchronous):
  * sums[f] = sum over nodes of moment field f (f < nf, others 0): the
  * conserved totals implied by the moment identities after Eq. (2-1-FD1);
- * *residual = || phi^n - phi^(n-1) ||_2 of field 0 (0 before the first step).
+ * *residual = || phi^n - phi^(n-m) ||_2 / m of field 0, where m is the number
+ * of steps between the current level and the previous level the solver holds
+ * (m = 1 except after a temporally blocked two-level launch of depth m);
+ * 0 before the first step.
  * Returns MFD_E_UNSTABLE if a sum or the residual is not finite. */
 int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
 

@@ -22,6 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = [
     "scheme.cpp",
     "mfd_api.cpp",
+    "autotune.cpp",
     "batch.cpp",
     "server.cpp",
     "kernels_mmfd.hip",

@@ -53,6 +53,30 @@ __device__ __forceinline__ void pop_moments(const T *pop, int64_t N, int64_t gi,
   }
 }
 
+// Rest-direction EDF.  binary64: g_0 of Eq. (3-3) like every direction.
+// binary32: g_0 = A - sum_{j>=1} g_j, so that the populations of one node sum
+// to A without the drift that the binary32-rounded weights (whose sum is not
+// exactly 1) would add to the zeroth moment at every step.
+template <class L, int EQ, typename T>
+__device__ __forceinline__ T g_rest(const T *r, const KC<T> &kc) {
+  if constexpr (std::is_same<T, double>::value) {
+    return gfull<L, EQ, 0>(r, kc);
+  } else {
+    T s = T(0);
+    static_for<L::Q - 1>([&](auto JI) {
+      constexpr int J = decltype(JI)::value + 1;
+      s = s + gfull<L, EQ, J>(r, kc);
+    });
+    return r[0] - s;
+  }
+}
+
+template <class L, int EQ, int J, typename T>
+__device__ __forceinline__ T g_dir(const T *r, const KC<T> &kc) {
+  if constexpr (J == 0) return g_rest<L, EQ>(r, kc);
+  else return gfull<L, EQ, J>(r, kc);
+}
+
 // evaluate the b new populations of one node
 template <class L, int EQ, bool THREE_ST, typename T, class At, class AtH>
 __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const T *hcentre,
@@ -70,7 +94,7 @@ __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const 
         T r[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) r[q] = at(q, k * ez, k * ey, k * ex);
-        fj = madd(ak, gfull<L, EQ, J>(r, kc), fj);
+        fj = madd(ak, g_dir<L, EQ, J>(r, kc), fj);
       }
     }
     if (three) {
@@ -86,7 +110,7 @@ __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const 
 #pragma unroll
             for (int q = 0; q < NR; ++q) r[q] = hcentre[q];  // only k = 0 is non-zero
           }
-          fj = madd(ak, gfull<L, EQ, J>(r, kc), fj);
+          fj = madd(ak, g_dir<L, EQ, J>(r, kc), fj);
         }
       }
     }
@@ -248,7 +272,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const T *__restrict__ mom, T *
     make_record<L, EQ>(m, r, kc);
     static_for<L::Q>([&](auto JI) {
       constexpr int J = decltype(JI)::value;
-      pop[J * N + i] = gfull<L, EQ, J>(r, kc);
+      pop[J * N + i] = g_dir<L, EQ, J>(r, kc);
     });
   }
 }

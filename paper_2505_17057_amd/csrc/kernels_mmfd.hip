@@ -19,7 +19,7 @@
 // interior node reads its stencil from LDS.  Periodic wrap is applied to the
 // global indices of the halo.  Workgroup ids are remapped so that each of
 // the 8 XCDs owns a contiguous band of tiles (L2 reuse of halos).
-#include "edf.h"
+#include "mmfd_node.h"
 
 namespace mfd {
 
@@ -40,89 +40,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
   const int x = bid & 7, k = bid >> 3;
   return x * q + min(x, r) + k;
-}
-
-// ---------------------------------------------------------- node update
-// `at(field, dz, dy, dx)` reads the level-t record, `ath` the level-(t-dt)
-// record; cur_c / prev_c are the centre moments (global), out the outputs.
-template <class L, int EQ, bool THREE, bool THREE_ST, typename T, class At, class AtH>
-__device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T *cur_c,
-                                          const T *prev_c, T *out_c, const KC<T> &kc) {
-  using R = Rec<L, EQ>;
-  constexpr int D = L::D, NR = R::NR, NF = R::NF;
-  T acc = T(0);
-  T mom[D > 0 ? D : 1];
-#pragma unroll
-  for (int a = 0; a < D; ++a) mom[a] = T(0);
-
-  auto level = [&](const auto &get, T cpl, T cmi, T bpl, T bmi, bool hat) {
-    static_for<L::P>([&](auto PI) {
-      constexpr int P = decltype(PI)::value;
-      constexpr int J = L::PR[P];
-      constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
-      if constexpr (EQ == kLCDE) {
-        const T gp = get(0, ez, ey, ex), g0 = get(0, 0, 0, 0), gm = get(0, -ez, -ey, -ex);
-        const T cp = hat ? kc.Chp[P] : kc.Cp[P];
-        const T cm = hat ? kc.Chm[P] : kc.Cm[P];
-        acc = madd(cp, (gp - T(2) * g0) + gm, acc);
-        acc = madd(cm, gp - gm, acc);
-      } else {
-        T rp[NR], r0[NR], rm[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          rp[k] = get(k, ez, ey, ex);
-          r0[k] = get(k, 0, 0, 0);
-          rm[k] = get(k, -ez, -ey, -ex);
-        }
-        const T Fpp = fplus<L, EQ, J>(rp, kc), Fp0 = fplus<L, EQ, J>(r0, kc),
-                Fpm = fplus<L, EQ, J>(rm, kc);
-        const T Fmp = fminus<L, EQ, J>(rp, kc), Fmm = fminus<L, EQ, J>(rm, kc);
-        acc = madd(cpl, (Fpp - T(2) * Fp0) + Fpm, acc);
-        acc = madd(cmi, Fmp - Fmm, acc);
-        if constexpr (EQ == kNSE) {
-          const T Fm0 = fminus<L, EQ, J>(r0, kc);
-          const T t1 = bpl * ((Fmp - T(2) * Fm0) + Fmm);
-          const T t2 = bmi * (Fpp - Fpm);
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            if (L::E[J][a] == 1) {
-              mom[a] = mom[a] + t1;
-              mom[a] = mom[a] + t2;
-            } else if (L::E[J][a] == -1) {
-              mom[a] = mom[a] - t1;
-              mom[a] = mom[a] - t2;
-            }
-          }
-        }
-      }
-    });
-  };
-  level(at, kc.ap, kc.am, kc.abp, kc.abm, false);
-  if constexpr (THREE_ST) level(ath, kc.ahp, kc.ahm, kc.abhp, kc.abhm, true);
-
-  // bases
-  auto finish = [&](int f, T a_acc, double A0d, double Ah0d, T A0t, T Ah0t) {
-    const T c = cur_c[f];
-    if constexpr (std::is_same<T, double>::value) {
-      double base = A0d * c;
-      if constexpr (THREE) base = base + Ah0d * prev_c[f];
-      out_c[f] = base + a_acc;
-    } else {
-      if constexpr (THREE) {
-        const double cd = (double)c;
-        const double base = cd - Ah0d * (cd - (double)prev_c[f]);
-        out_c[f] = (T)(base + (double)a_acc);
-      } else {
-        out_c[f] = madd(A0t, c, a_acc);
-      }
-    }
-  };
-  finish(0, acc, kc.A0, kc.Ah0, kc.A0t, kc.Ah0t);
-  if constexpr (EQ == kNSE) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) finish(1 + a, mom[a], kc.Ab0, kc.Abh0, kc.Ab0t, kc.Abh0t);
-  }
-  (void)NF;
 }
 
 // ------------------------------------------------------ 1D / 2D kernel
@@ -176,7 +93,7 @@ __global__ __launch_bounds__(256) void k_mmfd_plane(const T *__restrict__ cur,
     T cc[NF], pc[NF], oc[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      cc[f] = cur[f * N + gi];
+      cc[f] = at(f, 0, 0, 0);  // record fields 0..NF-1 are the moments
       pc[f] = THREE ? prev[f * N + gi] : T(0);
     }
     mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
@@ -249,7 +166,7 @@ __global__ __launch_bounds__(256) void k_mmfd_3d(const T *__restrict__ cur,
       T cc[NF], pc[NF], oc[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        cc[f] = cur[f * N + gi];
+        cc[f] = at(f, 0, 0, 0);
         pc[f] = THREE ? prev[f * N + gi] : T(0);
       }
       mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);

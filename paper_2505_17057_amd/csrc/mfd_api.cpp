@@ -46,6 +46,8 @@ int64_t Solver::device_bytes_needed() const {
   int64_t b = 3 * mom_elems() * es;  // level ring (MMFD) / moment ping-pong + scratch (MesoFD)
   if (grid.form == MFD_MESOFD) b += 2 * pop_elems() * es;
   if (cfg.kind == MFD_THETA) b += 2 * mom_elems() * es;
+  if (grid.form == MFD_MMFD && consts.three && consts.eq == kLCDE && consts.dim == 2)
+    b += mom_elems() * es;
   b += (kReduceBlocks * 8 + 8) * (int64_t)sizeof(double);
   return b;
 }
@@ -64,8 +66,9 @@ int Solver::ensure_buffers() {
   if (buf[0] && need == allocated_bytes) return MFD_OK;
   release();
   const int64_t es = elem(), me = mom_elems() * es, pe = pop_elems() * es;
-  int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8};
+  int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8, me};
   if (cfg.kind != MFD_THETA) sizes[5] = sizes[6] = 0;
+  if (!(grid.form == MFD_MMFD && consts.three && consts.eq == kLCDE && consts.dim == 2)) sizes[8] = 0;
   for (int i = 0; i < kNumBuf; ++i) {
     if (sizes[i] == 0) continue;
     hipError_t e = hipMalloc(&buf[i], (size_t)sizes[i]);
@@ -78,7 +81,7 @@ int Solver::ensure_buffers() {
     if (e != hipSuccess) return hip(e, "hipMemsetAsync");
   }
   allocated_bytes = need;
-  ic = 0; ip = 1; io = 2; pc = 3; pn = 4;
+  ic = 0; ip = 1; io = 2; pc = 3; pn = 4; ix = 8;
   steps_done = 0;
   return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
 }
@@ -109,6 +112,33 @@ int Solver::step_t(int64_t nsteps) {
     steps_done += nsteps;
     return MFD_OK;
   }
+  const int d = effective_tb();
+  if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 && lcde_tb_supported(consts, G, d)) {
+    // blocks of d steps, then single steps for the remainder.  A two-level
+    // block returns only its last level, so after it the held previous level
+    // is d steps old (prev_gap = d), which the residual accounts for.
+    const int64_t nblk = nsteps / d;
+    for (int64_t b = 0; b < nblk; ++b) {
+      hipError_t e;
+      if (!consts.three) {
+        e = launch_lcde_tb<T>(consts, G, d, B[ic], nullptr, B[ip], nullptr, stream);
+        if (e != hipSuccess) return hip(e, "blocked step launch");
+        std::swap(ic, ip);
+      } else {
+        e = launch_lcde_tb<T>(consts, G, d, B[ic], B[ip], B[io], B[ix], stream);
+        if (e != hipSuccess) return hip(e, "blocked step launch");
+        const int oc = ic, op = ip;
+        ic = io;
+        ip = ix;
+        io = oc;
+        ix = op;
+      }
+    }
+    nsteps -= nblk * d;
+    steps_done += nblk * d;
+    if (nblk > 0) prev_gap = consts.three ? 1 : d;
+  }
+  if (nsteps > 0) prev_gap = 1;
   for (int64_t s = 0; s < nsteps; ++s) {
     hipError_t e;
     if (grid.form == MFD_MMFD) {
@@ -502,7 +532,7 @@ extern "C" int mfd_reduce(mfd_solver *h, double sums[4], double *residual) {
   if (!finite) return s->fail(MFD_E_UNSTABLE, "non-finite moment sum or residual");
   if (sums)
     for (int f = 0; f < 4; ++f) sums[f] = f < s->nf() ? host[f] : 0.0;
-  if (residual) *residual = std::sqrt(host[4]);
+  if (residual) *residual = std::sqrt(host[4]) / (double)s->prev_gap;
   return MFD_OK;
 }
 
@@ -515,9 +545,7 @@ extern "C" int mfd_set_blocking(mfd_solver *h, int32_t tb_depth) {
 
 extern "C" int mfd_autotune(mfd_solver *h, int32_t *chosen_tb) {
   SOLVER_OR_ARG(h);
-  Solver *s = reinterpret_cast<Solver *>(h);
-  if (chosen_tb) *chosen_tb = s->tb > 0 ? s->tb : 1;
-  return MFD_OK;
+  return reinterpret_cast<Solver *>(h)->autotune(chosen_tb);
 }
 
 extern "C" int mfd_max_amplification(mfd_solver *h, double *out) {

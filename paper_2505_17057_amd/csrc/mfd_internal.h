@@ -108,6 +108,14 @@ hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T
                                    int64_t nsteps, hipStream_t st);
 bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
 
+// Temporally blocked LCDE step on D2Q5 / D2Q9 (tb in {2, 4, 6, 8}): reads
+// levels t (cur) and t - dt (prev, three-level), writes t + tb (out_cur) and,
+// for three-level schemes, t + tb - 1 (out_prev).
+bool lcde_tb_supported(const Consts &c, const Grid &g, int tb);
+template <typename T>
+hipError_t launch_lcde_tb(const Consts &c, const Grid &g, int tb, const T *cur, const T *prev,
+                          T *out_cur, T *out_prev, hipStream_t st);
+
 template <typename T>
 hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,
                               T *pop_out, T *mom_out, hipStream_t st);

@@ -24,8 +24,9 @@ struct Config {
 
 struct Solver {
   // device buffers: 0..2 moment ring, 3..4 population ping-pong, 5..6 theta
-  // rhs / Jacobi work, 7 reduction scratch
-  static constexpr int kNumBuf = 8;
+  // rhs / Jacobi work, 7 reduction scratch, 8 fourth moment buffer (blocked
+  // three-level steps write two levels)
+  static constexpr int kNumBuf = 9;
   static constexpr int kRedBuf = 7;
 
   mfd_grid grid{};
@@ -38,9 +39,11 @@ struct Solver {
   hipStream_t stream = nullptr;
   void *buf[kNumBuf] = {nullptr};
   int64_t allocated_bytes = 0;
-  int ic = 0, ip = 1, io = 2, pc = 3, pn = 4;  // roles in the rings
+  int ic = 0, ip = 1, io = 2, pc = 3, pn = 4, ix = 8;  // roles in the rings
   int64_t steps_done = 0;
-  int tb = 0;  // temporal-blocking depth (0 = automatic)
+  int prev_gap = 1;  // steps between the current and the held previous level
+  int tb = 0;        // temporal-blocking depth requested (0 = automatic)
+  int tb_tuned = 0;  // depth chosen by the autotuner (0 = not tuned)
   std::string err;
 
   int fail(int code, const char *fmt, ...);
@@ -56,6 +59,8 @@ struct Solver {
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
   int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
   int step(int64_t nsteps);
+  int effective_tb() const;
+  int autotune(int32_t *chosen);
   template <typename T>
   int step_t(int64_t nsteps);
 };

@@ -1,0 +1,135 @@
+"""GPU: temporal blocking, autotuning, reductions and the binary32 MesoFD
+mass balance.
+
+* Blocked LCDE steps (depth 2, 4, 6, 8) equal the FP64 oracle value for
+  value and equal the unblocked binary32 run bit for bit (one expression tree).
+* Autotuning leaves the state untouched.
+* FP64 reductions (mass, residual) agree with the oracle's compensated sums.
+"""
+import numpy as np
+import pytest
+
+from parity_util import rand_state, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+K2 = [[0.3, 0.04], [0.04, 0.2]]
+BASE = dict(lattice="D2Q9", eq="lcde", u=(0.1, -0.07), K=K2, lambda_bar=1)
+SCHEMES = {
+    "2l": dict(a=(1.0, 0.0, 0.0)),
+    "3l-trt": dict(kind="three_level", a=(1.0, 0.0, 0.4), ah=(0.0, -0.4, 0.0)),
+    "3l-stencil": dict(kind="three_level", a=(0.875, 0.0, 0.125), ah=(0.125, 0.0, -0.125)),
+}
+
+
+def _case(name, n):
+    return dict(BASE, n=n, name=name, **SCHEMES[name])
+
+
+@pytest.mark.parametrize("tb", [2, 4, 6, 8])
+@pytest.mark.parametrize("name", list(SCHEMES))
+@pytest.mark.parametrize("n", [(150, 77), (64, 32)])
+def test_blocked_fp64_bitwise(M, tb, name, n):
+    case = _case(name, n)
+    print("case", name, tb, n, flush=True)
+    rng = np.random.default_rng(5)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    steps = 3 * tb + 2
+    want = run_oracle(case, cur, prev, steps)
+    from parity_util import make_solver
+    s = make_solver(M, case, "fp64")
+    s.set_blocking(tb)
+    s.set_state(cur)
+    if case.get("kind") == "three_level":
+        s.set_state(prev, level=1)
+    s.step(steps)
+    got = s.get_state()
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+@pytest.mark.parametrize("name", list(SCHEMES))
+def test_blocked_fp32_equals_unblocked(M, name):
+    from parity_util import make_solver
+    case = _case(name, (300, 140))
+    rng = np.random.default_rng(6)
+    cur = rand_state(case, rng).astype(np.float32)
+    prev = rand_state(case, rng).astype(np.float32)
+    outs = []
+    for tb in (1, 4, 8):
+        s = make_solver(M, case, "fp32")
+        s.set_blocking(tb)
+        s.set_state(cur)
+        if case.get("kind") == "three_level":
+            s.set_state(prev, level=1)
+        s.step(37)
+        outs.append(s.get_state())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_autotune_preserves_state(M):
+    from parity_util import make_solver
+    case = _case("2l", (256, 128))
+    rng = np.random.default_rng(7)
+    cur = rand_state(case, rng)
+    s = make_solver(M, case, "fp64")
+    s.set_state(cur)
+    s.step(5)
+    before = s.get_state()
+    d = s.autotune()
+    assert d in (1, 2, 4, 6, 8)
+    assert np.array_equal(s.get_state(), before)
+    s.step(9)
+    ref = make_solver(M, case, "fp64")
+    ref.set_blocking(1)
+    ref.set_state(cur)
+    ref.step(14)
+    assert np.array_equal(s.get_state(), ref.get_state())
+    s.close()
+    ref.close()
+
+
+@pytest.mark.parametrize("form", ["mmfd", "mesofd"])
+def test_reductions_match_oracle(M, form):
+    from oracle import native as O
+    from parity_util import make_solver
+    case = dict(lattice="D2Q9", eq="nse", n=(70, 37), rho0=1.0, kind="three_level",
+                a=(1.0, 0.0, 0.4), ah=(0.0, -0.4, 0.0), form=form)
+    rng = np.random.default_rng(8)
+    cur = rand_state(case, rng)
+    s = make_solver(M, case, "fp64")
+    s.set_state(cur)
+    sums0, res0 = s.reduce()
+    assert res0 == 0.0
+    s.step(5)
+    sums, res = s.reduce()
+    want = run_oracle(case, cur, cur, 5)
+    prev = run_oracle(case, cur, cur, 4)
+    N = 70 * 37
+    for f in range(3):
+        w = O.csum(want[f * N:(f + 1) * N])
+        assert abs(sums[f] - w) <= 1e-12 * (1 + np.abs(want[f * N:(f + 1) * N]).sum())
+        # mass / momentum conserved over the run (prev == cur start)
+        assert abs(sums[f] - sums0[f]) <= 1e-12 * (1 + np.abs(cur[f * N:(f + 1) * N]).sum())
+    wres = float(np.linalg.norm(want[:N] - prev[:N]))
+    assert abs(res - wres) <= 1e-12 * wres
+    s.close()
+
+
+def test_fp32_mesofd_mass_balance(M):
+    """binary32 MesoFD keeps the zeroth moment: the rest population closes
+    the EDF sum, so the mass drift is round-off noise, not a per-step bias."""
+    from parity_util import make_solver
+    n = 256
+    case = dict(lattice="D2Q9", eq="lcde", n=(n, n), u=(0.05, 0.03), K=[[0.02, 0.005], [0.005, 0.01]],
+                dx=1.0 / n, dt=16.0 / n ** 2, lambda_bar=1, a=(1.0, 0.0, 0.0), form="mesofd")
+    rng = np.random.default_rng(9)
+    phi = 1.0 + 0.1 * rng.standard_normal(n * n)
+    s = make_solver(M, case, "fp32")
+    s.set_state(phi.astype(np.float32))
+    m0 = s.reduce()[0][0]
+    s.step(2000)
+    m1 = s.reduce()[0][0]
+    s.close()
+    assert abs(m1 - m0) / abs(m0) < 2e-5
