@@ -199,7 +199,9 @@ int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
  * levels, size) for the process.  Synchronous. *chosen_tb receives the depth. */
 int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
 
-/* Force a temporal-blocking depth (1 = none; 0 = automatic). */
+/* Force a temporal-blocking depth (1 = none; 0 = automatic).  Blocking is
+ * implemented for the MMFD form of the LCDE on D2Q5 / D2Q9 grids of at least
+ * 64 x (2 depth + 4) nodes; MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
 /* ------------------------------------------------------ host-side algebra */

@@ -1,10 +1,10 @@
-// Launch-plan autotuner: picks the temporal-blocking depth of a solver's
-// configuration by timing every supported candidate on the solver's own
-// state (saved before and restored after), and caches the choice for the
-// process under a key of (lattice, equation, form, precision, levels, grid).
+// Launch-plan autotuner: picks the temporal-blocking plan (steps per launch,
+// window height) of a solver's configuration by timing every supported
+// candidate on the solver's own state (saved before and restored after), and
+// caches the choice for the process under a key of (lattice, equation, form,
+// precision, levels, grid).
 #include <hip/hip_runtime.h>
 
-#include <cstdio>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -19,7 +19,7 @@ namespace {
 
 using Key = std::tuple<int, int, int, int, int, int, int64_t, int64_t, int64_t>;
 std::mutex g_mu;
-std::map<Key, int> g_cache;
+std::map<Key, TbPlan> g_cache;
 
 Key key_of(const Solver &s) {
   return Key(s.consts.lattice, s.consts.eq, s.grid.form, s.grid.precision, s.consts.three,
@@ -31,30 +31,51 @@ bool tunable(const Solver &s) {
          s.consts.dim == 2 && (s.consts.lattice == MFD_D2Q5 || s.consts.lattice == MFD_D2Q9);
 }
 
+// default window height for a requested depth: the tallest window whose
+// levels leave room for three workgroups per CU
+int default_h(const Solver &s, int tb) {
+  static const int hs[] = {96, 80, 64, 48, 32};
+  for (int h : hs) {
+    const TbPlan p{tb, h};
+    if (lcde_tb_lds_bytes(s.consts, h, (int)s.elem()) * 3 <= 160 * 1024 &&
+        lcde_tb_supported(s.consts, s.G, p, (int)s.elem()))
+      return h;
+  }
+  return 0;
+}
+
 }  // namespace
 
-int Solver::effective_tb() const {
-  if (tb > 0) return tb;
-  if (tb_tuned > 0) return tb_tuned;
-  if (!tunable(*this)) return 1;
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_cache.find(key_of(*this));
-  if (it != g_cache.end()) return it->second;
-  return 4;  // default depth before tuning
+TbPlan Solver::effective_plan() const {
+  if (!tunable(*this)) return TbPlan{1, 0};
+  if (tb == 1) return TbPlan{1, 0};
+  if (tb > 1) {
+    if (tuned.tb == tb) return tuned;
+    const int h = default_h(*this, tb);
+    return h ? TbPlan{tb, h} : TbPlan{1, 0};
+  }
+  if (tuned.tb > 0) return tuned;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key_of(*this));
+    if (it != g_cache.end()) return it->second;
+  }
+  const int h = default_h(*this, 4);
+  return h ? TbPlan{4, h} : TbPlan{1, 0};
 }
 
 int Solver::autotune(int32_t *chosen) {
   if (sticky) return fail(MFD_E_HIP, "solver is in a failed HIP state");
   if (!tunable(*this) || !state_set) {
-    if (chosen) *chosen = effective_tb();
+    if (chosen) *chosen = effective_plan().tb;
     return MFD_OK;
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key_of(*this));
     if (it != g_cache.end()) {
-      tb_tuned = it->second;
-      if (chosen) *chosen = tb > 0 ? tb : tb_tuned;
+      tuned = it->second;
+      if (chosen) *chosen = effective_plan().tb;
       return MFD_OK;
     }
   }
@@ -72,51 +93,62 @@ int Solver::autotune(int32_t *chosen) {
   int rc = hip(hipMemcpyAsync(save[0], buf[ic], bytes, hipMemcpyDeviceToDevice, stream), "copy");
   if (!rc) rc = hip(hipMemcpyAsync(save[1], buf[ip], bytes, hipMemcpyDeviceToDevice, stream), "copy");
   const int saved_tb = tb;
+  const TbPlan saved_tuned = tuned;
   const int64_t saved_steps = steps_done;
+  const int saved_gap = prev_gap;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) rc = hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = hip(hipEventCreate(&e1), "hipEventCreate");
-  const int cands[5] = {1, 2, 4, 6, 8};
-  // enough steps per trial that every candidate runs whole blocks
-  const int64_t trial = G.N >= (1 << 20) ? 241 : 481;
+  // trial length: whole blocks for every depth, ~2^29 node updates
+  int64_t trial = ((int64_t)1 << 29) / G.N;
+  trial = trial < 24 ? 24 : (trial > 480 ? 480 : trial);
+  trial = (trial / 24) * 24;
+  const int depths[] = {1, 2, 4, 6, 8};
+  const int heights[] = {48, 64, 80, 96, 112, 128};
   float best_ms = 1e30f;
-  int best = 1;
-  for (int ci = 0; ci < 5 && !rc; ++ci) {
-    const int d = cands[ci];
-    if (d > 1 && !lcde_tb_supported(consts, G, d)) continue;
-    tb = d;
-    rc = step(trial);  // warm-up (also instantiates code objects)
-    if (rc) break;
-    rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
-    if (!rc) rc = step(trial);
-    if (!rc) rc = hip(hipEventRecord(e1, stream), "hipEventRecord");
-    if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
-    float ms = 0.f;
-    if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-    if (!rc && ms < best_ms) {
-      best_ms = ms;
-      best = d;
+  TbPlan best{1, 0};
+  for (int d : depths) {
+    for (int h : heights) {
+      if (rc) break;
+      TbPlan p{d, d == 1 ? 0 : h};
+      if (d == 1 && h != heights[0]) continue;
+      if (d > 1 && !lcde_tb_supported(consts, G, p, (int)elem())) continue;
+      tb = d;
+      tuned = p;
+      rc = step(trial);  // warm-up
+      if (rc) break;
+      rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
+      if (!rc) rc = step(trial);
+      if (!rc) rc = hip(hipEventRecord(e1, stream), "hipEventRecord");
+      if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best = p;
+      }
     }
   }
   tb = saved_tb;
+  tuned = saved_tuned;
   if (!rc) {
-    // restore the levels into the current roles
     rc = hip(hipMemcpyAsync(buf[ic], save[0], bytes, hipMemcpyDeviceToDevice, stream), "copy");
     if (!rc) rc = hip(hipMemcpyAsync(buf[ip], save[1], bytes, hipMemcpyDeviceToDevice, stream), "copy");
     if (!rc) rc = hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
   }
   steps_done = saved_steps;
+  prev_gap = saved_gap;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(save[0]);
   (void)hipFree(save[1]);
   if (rc) return rc;
-  tb_tuned = best;
+  tuned = best;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[key_of(*this)] = best;
   }
-  if (chosen) *chosen = tb > 0 ? tb : best;
+  if (chosen) *chosen = effective_plan().tb;
   return MFD_OK;
 }
 

@@ -112,8 +112,10 @@ int Solver::step_t(int64_t nsteps) {
     steps_done += nsteps;
     return MFD_OK;
   }
-  const int d = effective_tb();
-  if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 && lcde_tb_supported(consts, G, d)) {
+  const TbPlan pl = effective_plan();
+  const int d = pl.tb;
+  if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 &&
+      lcde_tb_supported(consts, G, pl, (int)sizeof(T))) {
     // blocks of d steps, then single steps for the remainder.  A two-level
     // block returns only its last level, so after it the held previous level
     // is d steps old (prev_gap = d), which the residual accounts for.
@@ -121,11 +123,11 @@ int Solver::step_t(int64_t nsteps) {
     for (int64_t b = 0; b < nblk; ++b) {
       hipError_t e;
       if (!consts.three) {
-        e = launch_lcde_tb<T>(consts, G, d, B[ic], nullptr, B[ip], nullptr, stream);
+        e = launch_lcde_tb<T>(consts, G, pl, B[ic], nullptr, B[ip], nullptr, stream);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         std::swap(ic, ip);
       } else {
-        e = launch_lcde_tb<T>(consts, G, d, B[ic], B[ip], B[io], B[ix], stream);
+        e = launch_lcde_tb<T>(consts, G, pl, B[ic], B[ip], B[io], B[ix], stream);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         const int oc = ic, op = ip;
         ic = io;
@@ -538,8 +540,14 @@ extern "C" int mfd_reduce(mfd_solver *h, double sums[4], double *residual) {
 
 extern "C" int mfd_set_blocking(mfd_solver *h, int32_t tb_depth) {
   SOLVER_OR_ARG(h);
-  if (tb_depth < 0 || tb_depth > 16) return MFD_E_ARG;
-  reinterpret_cast<Solver *>(h)->tb = tb_depth;
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (tb_depth < 0 || tb_depth > 16) return s->fail(MFD_E_ARG, "blocking depth out of range");
+  const int old = s->tb;
+  s->tb = tb_depth;
+  if (tb_depth > 1 && s->configured && s->effective_plan().tb != tb_depth) {
+    s->tb = old;
+    return s->fail(MFD_E_UNSUPPORTED, "depth %d cannot be used by this configuration", tb_depth);
+  }
   return MFD_OK;
 }
 

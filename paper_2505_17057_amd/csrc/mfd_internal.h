@@ -77,6 +77,7 @@ struct KC {
   T ap, am, ahp, ahm, abp, abm, abhp, abhm;
   T a[3], ah[3];              // k = -1, 0, +1 (MesoFD)
   T Cp[kMaxP], Cm[kMaxP], Chp[kMaxP], Chm[kMaxP];
+  T Ap[kMaxP], Am[kMaxP], Ahp[kMaxP], Ahm[kMaxP];  // Cp +- Cm, Chp +- Chm (binary32 form)
   T bh, cbeta, rho0, rinv0;
   double A0, Ah0, Ab0, Abh0;  // binary64 base coefficients
   T A0t, Ah0t, Ab0t, Abh0t;   // the same in T
@@ -108,13 +109,19 @@ hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T
                                    int64_t nsteps, hipStream_t st);
 bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
 
-// Temporally blocked LCDE step on D2Q5 / D2Q9 (tb in {2, 4, 6, 8}): reads
-// levels t (cur) and t - dt (prev, three-level), writes t + tb (out_cur) and,
-// for three-level schemes, t + tb - 1 (out_prev).
-bool lcde_tb_supported(const Consts &c, const Grid &g, int tb);
+// Temporally blocked LCDE step on D2Q5 / D2Q9: one launch advances tb steps
+// over windows of 64 x h nodes.  Reads levels t (cur) and t - dt (prev,
+// three-level), writes t + tb (out_cur) and, for three-level schemes,
+// t + tb - 1 (out_prev).
+struct TbPlan {
+  int tb;  // steps per launch
+  int h;   // window rows
+};
+size_t lcde_tb_lds_bytes(const Consts &c, int h, int elem);
+bool lcde_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 template <typename T>
-hipError_t launch_lcde_tb(const Consts &c, const Grid &g, int tb, const T *cur, const T *prev,
-                          T *out_cur, T *out_prev, hipStream_t st);
+hipError_t launch_lcde_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                          const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 
 template <typename T>
 hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,

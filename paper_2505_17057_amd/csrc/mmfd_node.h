@@ -26,10 +26,20 @@ __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T 
       constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
       if constexpr (EQ == kLCDE) {
         const T gp = get(0, ez, ey, ex), g0 = get(0, 0, 0, 0), gm = get(0, -ez, -ey, -ex);
-        const T cp = hat ? kc.Chp[P] : kc.Cp[P];
-        const T cm = hat ? kc.Chm[P] : kc.Cm[P];
-        acc = madd(cp, (gp - T(2) * g0) + gm, acc);
-        acc = madd(cm, gp - gm, acc);
+        if constexpr (std::is_same<T, double>::value) {
+          const T cp = hat ? kc.Chp[P] : kc.Cp[P];
+          const T cm = hat ? kc.Chm[P] : kc.Cm[P];
+          acc = madd(cp, (gp - T(2) * g0) + gm, acc);
+          acc = madd(cm, gp - gm, acc);
+        } else {
+          // binary32: Cp D2 g + Cm D1 g = (Cp + Cm)(g+ - g0) + (Cp - Cm)(g- - g0);
+          // the differences of neighbouring values are exact or nearly so,
+          // and the pair costs two subtractions and two fused multiply-adds
+          const T al = hat ? kc.Ahp[P] : kc.Ap[P];
+          const T be = hat ? kc.Ahm[P] : kc.Am[P];
+          acc = madd(al, gp - g0, acc);
+          acc = madd(be, gm - g0, acc);
+        }
       } else {
         T rp[NR], r0[NR], rm[NR];
 #pragma unroll

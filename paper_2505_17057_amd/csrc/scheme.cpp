@@ -207,6 +207,10 @@ KC<T> make_kc(const Consts &c) {
     k.Cm[p] = (T)c.Cm[p];
     k.Chp[p] = (T)c.Chp[p];
     k.Chm[p] = (T)c.Chm[p];
+    k.Ap[p] = (T)(c.Cp[p] + c.Cm[p]);
+    k.Am[p] = (T)(c.Cp[p] - c.Cm[p]);
+    k.Ahp[p] = (T)(c.Chp[p] + c.Chm[p]);
+    k.Ahm[p] = (T)(c.Chp[p] - c.Chm[p]);
   }
   k.bh = (T)c.bh;
   k.cbeta = (T)c.cbeta;

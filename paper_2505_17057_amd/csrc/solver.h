@@ -42,8 +42,8 @@ struct Solver {
   int ic = 0, ip = 1, io = 2, pc = 3, pn = 4, ix = 8;  // roles in the rings
   int64_t steps_done = 0;
   int prev_gap = 1;  // steps between the current and the held previous level
-  int tb = 0;        // temporal-blocking depth requested (0 = automatic)
-  int tb_tuned = 0;  // depth chosen by the autotuner (0 = not tuned)
+  int tb = 0;           // temporal-blocking depth requested (0 = automatic)
+  TbPlan tuned{0, 0};   // plan chosen by the autotuner (tb = 0: not tuned)
   std::string err;
 
   int fail(int code, const char *fmt, ...);
@@ -59,7 +59,7 @@ struct Solver {
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
   int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
   int step(int64_t nsteps);
-  int effective_tb() const;
+  TbPlan effective_plan() const;
   int autotune(int32_t *chosen);
   template <typename T>
   int step_t(int64_t nsteps);
