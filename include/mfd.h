@@ -204,6 +204,107 @@ int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
  * 64 x (2 depth + 4) nodes; MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
+/* ---------------------------------------------------------------- batches */
+
+/* A batch advances many solvers (independent periodic grids of any sizes,
+ * coefficients and step counts) together: each time step of all solvers of
+ * one kind (lattice, equation, levels, precision) is one kernel launch over
+ * the tiles of the solvers still running, and the whole step sequence is
+ * captured once into a hipGraph and replayed by every mfd_batch_run.  Each
+ * solver's result equals the one of stepping it alone (same kernels, same
+ * arithmetic).  Only 2D explicit MMFD solvers (D2Q5, D2Q9) can be batched.
+ * A batch references its solvers: they must outlive it, must not be
+ * stepped by other calls while a run is in flight, and their own streams
+ * must be idle when a run is enqueued. */
+typedef struct mfd_batch mfd_batch;
+
+int mfd_batch_create(mfd_batch **out);
+int mfd_batch_destroy(mfd_batch *b);
+const char *mfd_batch_last_error(const mfd_batch *b);
+
+/* Stream the runs are enqueued on (non-null: graph capture needs one; default
+ * is a stream the batch creates). */
+int mfd_batch_set_stream(mfd_batch *b, void *stream);
+
+/* 1 (default): capture the step sequence in a hipGraph; 0: plain launches. */
+int mfd_batch_set_graph(mfd_batch *b, int use_graph);
+
+/* Add a configured solver with its state set, to be advanced nsteps >= 0 per
+ * run.  *slot receives its index.  MFD_E_UNSUPPORTED for solvers that are not
+ * 2D explicit MMFD. */
+int mfd_batch_add(mfd_batch *b, mfd_solver *s, int64_t nsteps, int32_t *slot);
+
+/* Remove every solver. */
+int mfd_batch_clear(mfd_batch *b);
+
+/* Enqueue one run (asynchronous); afterwards each solver holds its advanced
+ * state as if mfd_step(s, nsteps) had been called. */
+int mfd_batch_run(mfd_batch *b);
+
+/* Wait for the batch's stream. */
+int mfd_batch_wait(mfd_batch *b);
+
+/* Kernel launches per run, lattice-node updates per run, tiles. */
+int mfd_batch_stats(const mfd_batch *b, int64_t *launches, int64_t *lups, int64_t *tiles);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A server runs MMFD solves submitted by any thread with continuous
+ * batching: a scheduler thread advances all admitted requests together in
+ * quanta of `quantum_steps` steps (one batched launch per step), admits
+ * queued requests (arrival order) whenever a slot and the HBM budget allow,
+ * while the previous quantum is on the GPU, and retires finished requests by
+ * copying their final level to the caller's buffer.  Each request's result
+ * equals the solve of the same request alone. */
+typedef struct mfd_server mfd_server;
+
+typedef struct {
+    int32_t lattice;          /* MFD_D2Q9 or MFD_D2Q5                          */
+    int32_t eq;               /* MFD_LCDE, MFD_BURGERS, MFD_NSE                */
+    int32_t precision;        /* MFD_FP32 / MFD_FP64                           */
+    int32_t kind;             /* MFD_TWO_LEVEL or MFD_THREE_LEVEL              */
+    int64_t n[2];             /* grid nodes (x, y), >= 3                       */
+    double d0;                /* lattice parameter (<= 0: 1/3)                 */
+    double dx, dt;
+    mfd_eq_params ep;
+    double a[3], ah[3];       /* coefficients as for mfd_set_scheme            */
+    int64_t nsteps;
+    const void *state0;       /* level t moments (host, solver precision);     */
+    const void *prev0;        /* level t - dt or NULL; both must stay valid    */
+                              /* until the request has left the queue          */
+    void *result_out;         /* host buffer for the final moments, or NULL    */
+    int64_t result_bytes;
+    int32_t exclude_from_stats; /* 1: not counted in the latency percentiles  */
+    int32_t reserved;
+} mfd_request;
+
+/* Create a server with a device-memory budget (bytes of solver state held at
+ * once), a slot limit and a quantum.  Starts the scheduler thread. */
+int mfd_server_create(mfd_server **out, int64_t hbm_budget_bytes, int32_t max_slots,
+                      int64_t quantum_steps);
+
+/* Queue a request (thread-safe, non-blocking); *ticket identifies it.  A
+ * request whose state can never fit the budget fails with MFD_E_BUDGET. */
+int mfd_server_submit(mfd_server *srv, const mfd_request *req, int64_t *ticket);
+
+/* State of a ticket: 0 queued, 1 running, 2 done (result written), -1 failed
+ * (the return value is then the error).  *latency_s: submission to result,
+ * or -1 if not done. */
+int mfd_server_poll(mfd_server *srv, int64_t ticket, int32_t *state, double *latency_s);
+
+/* Block until every submitted request is done or failed (MFD_E_ORDER on
+ * timeout). */
+int mfd_server_drain(mfd_server *srv, double timeout_s);
+
+/* Latency percentiles of the completed requests, completed requests per
+ * second and lattice-node updates per second over the span from the first
+ * counted submission to the last completion. */
+int mfd_server_stats(mfd_server *srv, double *p50_s, double *p99_s, double *req_per_s,
+                     int64_t *completed, double *glups);
+
+/* Stop accepting work, finish the running requests, free everything. */
+int mfd_server_destroy(mfd_server *srv);
+
 /* ------------------------------------------------------ host-side algebra */
 
 /* Coefficient moments of Eq. (4-2-00): out = {A00, A10, A11, A20, A21, A22}. */

@@ -1,0 +1,330 @@
+// Batched stepping of many solvers: groups, tile tables, the step sequence
+// captured once into a hipGraph and replayed, and the level-ring hand-back
+// to each solver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mfd.h"
+#include "batch.h"
+#include "batch_kernels.h"
+#include "mfd_internal.h"
+#include "solver.h"
+
+namespace mfd {
+
+int Batch::fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  err = buf;
+  return code;
+}
+
+int Batch::hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return MFD_OK;
+  sticky = true;
+  return fail(MFD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void Batch::free_graph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+}
+
+void Batch::free_groups() {
+  for (auto &g : groups) {
+    if (g.d_inst) (void)hipFree(g.d_inst);
+    if (g.d_tile_inst) (void)hipFree(g.d_tile_inst);
+  }
+  groups.clear();
+}
+
+static int tile_ty(int eq) { return eq == kNSE ? kBatchTYNse : kBatchTY; }
+
+int Batch::build() {
+  free_graph();
+  free_groups();
+  if (!stream) {
+    int rc = hip(hipStreamCreate(&own_stream), "hipStreamCreate");
+    if (rc) return rc;
+    stream = own_stream;
+  }
+  std::map<BatchKey, std::vector<int>> by_key;
+  for (int i = 0; i < (int)entries.size(); ++i) {
+    Solver *s = entries[i].s;
+    BatchKey k{s->consts.lattice, s->consts.eq, s->consts.three, s->consts.three_stencil,
+               s->grid.precision};
+    by_key[k].push_back(i);
+  }
+  max_steps = 0;
+  lups_per_run = 0;
+  for (auto &kv : by_key) {
+    Group g;
+    g.key = kv.first;
+    g.order = kv.second;
+    std::stable_sort(g.order.begin(), g.order.end(),
+                     [&](int a, int b) { return entries[a].nsteps > entries[b].nsteps; });
+    const int ty = tile_ty(g.key.eq);
+    std::vector<int> tile_inst;
+    for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+      const Solver *s = entries[g.order[slot]].s;
+      const int tx = (int)((s->G.n[0] + kBatchTX - 1) / kBatchTX);
+      const int tyc = (int)((s->G.n[1] + ty - 1) / ty);
+      g.tile0.push_back((int)tile_inst.size());
+      g.tiles_x.push_back(tx);
+      for (int k = 0; k < tx * tyc; ++k) tile_inst.push_back(slot);
+      g.steps.push_back(entries[g.order[slot]].nsteps);
+      max_steps = std::max(max_steps, entries[g.order[slot]].nsteps);
+      lups_per_run += s->G.N * entries[g.order[slot]].nsteps;
+    }
+    g.ntiles = (int)tile_inst.size();
+    const size_t isz = g.key.precision == MFD_FP64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
+    g.inst_bytes = isz * g.order.size();
+    int rc = hip(hipMalloc(&g.d_inst, g.inst_bytes), "hipMalloc (instances)");
+    if (!rc) rc = hip(hipMalloc((void **)&g.d_tile_inst, sizeof(int) * std::max(1, g.ntiles)),
+                      "hipMalloc (tiles)");
+    if (!rc && g.ntiles)
+      rc = hip(hipMemcpyAsync(g.d_tile_inst, tile_inst.data(), sizeof(int) * g.ntiles,
+                              hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync (tiles)");
+    if (rc) {
+      groups.push_back(g);
+      return rc;
+    }
+    g.h_inst.resize(g.inst_bytes);
+    groups.push_back(std::move(g));
+  }
+  return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+}
+
+// active tiles of a group at step s: instances are sorted by decreasing step
+// count, so those with steps > s are a prefix
+static int active_tiles(const Group &g, int64_t s) {
+  int m = 0;
+  while (m < (int)g.steps.size() && g.steps[m] > s) ++m;
+  if (m == (int)g.steps.size()) return g.ntiles;
+  return g.tile0[m];
+}
+
+int Batch::enqueue_steps() {
+  launches_per_run = 0;
+  for (int64_t s = 0; s < max_steps; ++s) {
+    for (auto &g : groups) {
+      const int nt = active_tiles(g, s);
+      if (nt == 0) continue;
+      hipError_t e;
+      if (g.key.precision == MFD_FP64)
+        e = launch_batch_step<double>(g.key, (const BatchInst<double> *)g.d_inst, g.d_tile_inst,
+                                      nt, s, stream);
+      else
+        e = launch_batch_step<float>(g.key, (const BatchInst<float> *)g.d_inst, g.d_tile_inst,
+                                     nt, s, stream);
+      if (e != hipSuccess) return hip(e, "batch step launch");
+      ++launches_per_run;
+    }
+  }
+  return MFD_OK;
+}
+
+template <typename T>
+static void fill_inst(const Group &g, const std::vector<BatchEntry> &entries,
+                      std::vector<unsigned char> &h) {
+  BatchInst<T> *bi = reinterpret_cast<BatchInst<T> *>(h.data());
+  for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+    const Solver *s = entries[g.order[slot]].s;
+    BatchInst<T> b;
+    std::memset(&b, 0, sizeof(b));
+    if (s->consts.three) {
+      b.ring[0] = (T *)s->buf[s->ic];
+      b.ring[1] = (T *)s->buf[s->io];
+      b.ring[2] = (T *)s->buf[s->ip];
+      b.ring_len = 3;
+    } else {
+      b.ring[0] = (T *)s->buf[s->ic];
+      b.ring[1] = (T *)s->buf[s->ip];
+      b.ring_len = 2;
+    }
+    b.nx = (int)s->G.n[0];
+    b.ny = (int)s->G.n[1];
+    b.c0 = 0;
+    b.tiles_x = g.tiles_x[slot];
+    b.tile0 = g.tile0[slot];
+    b.kc = make_kc<T>(s->consts);
+    bi[slot] = b;
+  }
+}
+
+int Batch::run() {
+  if (sticky) return fail(MFD_E_HIP, "batch is in a failed HIP state");
+  if (entries.empty()) return MFD_OK;
+  for (auto &e : entries) {
+    Solver *s = e.s;
+    if (s->sticky || !s->state_set || !s->configured)
+      return fail(MFD_E_ORDER, "a batched solver is not ready (configure it and set its state)");
+  }
+  int rc;
+  if (dirty) {
+    rc = build();
+    if (rc) return rc;
+  }
+  // instance tables from the solvers' current level roles
+  for (auto &g : groups) {
+    if (g.key.precision == MFD_FP64) fill_inst<double>(g, entries, g.h_inst);
+    else fill_inst<float>(g, entries, g.h_inst);
+    rc = hip(hipMemcpyAsync(g.d_inst, g.h_inst.data(), g.inst_bytes, hipMemcpyHostToDevice, stream),
+             "hipMemcpyAsync (instances)");
+    if (rc) return rc;
+  }
+  if (use_graph) {
+    if (dirty || !exec) {
+      free_graph();
+      rc = hip(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      if (rc) return rc;
+      rc = enqueue_steps();
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(stream, &gr);
+      if (rc) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      rc = hip(e, "hipStreamEndCapture");
+      if (rc) return rc;
+      graph = gr;
+      rc = hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+      if (rc) return rc;
+    }
+    rc = hip(hipGraphLaunch(exec, stream), "hipGraphLaunch");
+    if (rc) return rc;
+  } else {
+    rc = enqueue_steps();
+    if (rc) return rc;
+  }
+  dirty = false;
+  // hand the rotated level roles back to the solvers
+  for (auto &e : entries) {
+    Solver *s = e.s;
+    const int64_t n = e.nsteps;
+    if (n == 0) continue;
+    if (s->consts.three) {
+      const int ring[3] = {s->ic, s->io, s->ip};
+      s->ic = ring[n % 3];
+      s->io = ring[(n + 1) % 3];
+      s->ip = ring[(n + 2) % 3];
+    } else {
+      const int ring[2] = {s->ic, s->ip};
+      s->ic = ring[n % 2];
+      s->ip = ring[(n + 1) % 2];
+    }
+    s->steps_done += n;
+    s->prev_gap = 1;
+  }
+  return MFD_OK;
+}
+
+}  // namespace mfd
+
+using namespace mfd;
+
+extern "C" int mfd_batch_create(mfd_batch **out) {
+  if (!out) return MFD_E_ARG;
+  Batch *b = new (std::nothrow) Batch();
+  if (!b) return MFD_E_OOM;
+  *out = reinterpret_cast<mfd_batch *>(b);
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_destroy(mfd_batch *h) {
+  if (!h) return MFD_OK;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  b->free_graph();
+  b->free_groups();
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  delete b;
+  return MFD_OK;
+}
+
+extern "C" const char *mfd_batch_last_error(const mfd_batch *h) {
+  if (!h) return "null batch";
+  return reinterpret_cast<const Batch *>(h)->err.c_str();
+}
+
+extern "C" int mfd_batch_set_stream(mfd_batch *h, void *stream) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  if (!stream) return b->fail(MFD_E_ARG, "a batch needs a non-null stream (graph capture)");
+  b->stream = (hipStream_t)stream;
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_set_graph(mfd_batch *h, int use_graph) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  b->use_graph = use_graph != 0;
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_add(mfd_batch *h, mfd_solver *sh, int64_t nsteps, int32_t *slot) {
+  if (!h || !sh) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  Solver *s = reinterpret_cast<Solver *>(sh);
+  if (nsteps < 0) return b->fail(MFD_E_ARG, "nsteps < 0");
+  if (!s->configured || !s->state_set)
+    return b->fail(MFD_E_ORDER, "configure the solver and set its state before batching it");
+  if (s->grid.form != MFD_MMFD || s->grid.dim != 2 || s->cfg.kind == MFD_THETA ||
+      (s->consts.lattice != MFD_D2Q9 && s->consts.lattice != MFD_D2Q5))
+    return b->fail(MFD_E_UNSUPPORTED, "batches hold 2D explicit MMFD solvers (D2Q5 / D2Q9)");
+  for (auto &e : b->entries)
+    if (e.s == s) return b->fail(MFD_E_ARG, "solver already in the batch");
+  if (slot) *slot = (int32_t)b->entries.size();
+  b->entries.push_back(BatchEntry{s, nsteps});
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_clear(mfd_batch *h) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  b->entries.clear();
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_run(mfd_batch *h) {
+  if (!h) return MFD_E_ARG;
+  return reinterpret_cast<Batch *>(h)->run();
+}
+
+extern "C" int mfd_batch_wait(mfd_batch *h) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  if (!b->stream) return MFD_OK;
+  return b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+}
+
+extern "C" int mfd_batch_stats(const mfd_batch *h, int64_t *launches, int64_t *lups,
+                               int64_t *tiles) {
+  if (!h) return MFD_E_ARG;
+  const Batch *b = reinterpret_cast<const Batch *>(h);
+  if (launches) *launches = b->launches_per_run;
+  if (lups) *lups = b->lups_per_run;
+  if (tiles) {
+    int64_t t = 0;
+    for (auto &g : b->groups) t += g.ntiles;
+    *tiles = t;
+  }
+  return MFD_OK;
+}

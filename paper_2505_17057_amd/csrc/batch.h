@@ -1,0 +1,51 @@
+// The batch object behind the opaque mfd_batch handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "batch_kernels.h"
+#include "solver.h"
+
+namespace mfd {
+
+struct BatchEntry {
+  Solver *s;
+  int64_t nsteps;
+};
+
+struct Group {
+  BatchKey key{};
+  std::vector<int> order;       // entry indices, decreasing step count
+  std::vector<int> tile0;       // first tile of each instance (sorted order)
+  std::vector<int> tiles_x;
+  std::vector<int64_t> steps;   // step count of each instance (sorted order)
+  int ntiles = 0;
+  void *d_inst = nullptr;       // BatchInst<T>[instances]
+  int *d_tile_inst = nullptr;   // instance slot of every tile
+  size_t inst_bytes = 0;
+  std::vector<unsigned char> h_inst;
+};
+
+struct Batch {
+  std::vector<BatchEntry> entries;
+  std::vector<Group> groups;
+  hipStream_t stream = nullptr, own_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true, dirty = true, sticky = false;
+  int64_t max_steps = 0, launches_per_run = 0, lups_per_run = 0;
+  std::string err;
+
+  int fail(int code, const char *fmt, ...);
+  int hip(hipError_t e, const char *what);
+  void free_graph();
+  void free_groups();
+  int build();
+  int enqueue_steps();
+  int run();
+};
+
+}  // namespace mfd

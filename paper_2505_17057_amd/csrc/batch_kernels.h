@@ -1,0 +1,38 @@
+// Device descriptors of the batched step (see kernels_batch.hip).
+#pragma once
+
+#include "mfd_internal.h"
+
+namespace mfd {
+
+constexpr int kBatchTX = 64, kBatchTY = 16, kBatchTYNse = 8;
+
+// one instance of a batch group, as the kernel reads it
+template <typename T>
+struct BatchInst {
+  T *ring[3];     // level buffers (two-level groups use ring[0..1])
+  int nx, ny;
+  int ring_len;   // 2 or 3
+  int c0;         // ring index of level t at the first step of the run
+  int tiles_x;
+  int tile0;      // first tile of this instance in the group's tile table
+  KC<T> kc;       // the instance's step constants
+};
+
+// what selects the kernel of a group
+struct BatchKey {
+  int lattice, eq, three, three_st, precision;
+  bool operator<(const BatchKey &o) const {
+    if (lattice != o.lattice) return lattice < o.lattice;
+    if (eq != o.eq) return eq < o.eq;
+    if (three != o.three) return three < o.three;
+    if (three_st != o.three_st) return three_st < o.three_st;
+    return precision < o.precision;
+  }
+};
+
+template <typename T>
+hipError_t launch_batch_step(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
+                             int ntiles, int64_t s, hipStream_t st);
+
+}  // namespace mfd

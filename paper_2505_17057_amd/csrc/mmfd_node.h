@@ -99,4 +99,81 @@ __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T 
   (void)NF;
 }
 
+__device__ __forceinline__ int wrapi(int i, int n) {
+  if (i < 0) {
+    i += n;
+    if (i < 0) i = ((i % n) + n) % n;
+  } else if (i >= n) {
+    i -= n;
+    if (i >= n) i %= n;
+  }
+  return i;
+}
+
+// Hardware dispatch sends consecutive workgroups round-robin to the 8 XCDs;
+// give XCD x the contiguous tile range [x q + min(x, r), ...).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
+// One TX x TY tile (origin x0, y0) of a 1D / 2D grid: EDF records of the tile
+// and a one-node halo into LDS (periodic wrap), then the node updates.
+template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
+                                                const T *__restrict__ prev,
+                                                T *__restrict__ out, int nx, int ny, int x0,
+                                                int y0, const KC<T> &kc) {
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR, NF = R::NF;
+  constexpr int HYL = L::D >= 2 ? 1 : 0;
+  constexpr int HX = TX + 2, HY = TY + 2 * HYL;
+  __shared__ T rec[NR][HY][HX];
+  __shared__ T hrec[THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+  const int64_t N = (int64_t)nx * ny;
+
+  for (int i = threadIdx.x; i < HX * HY; i += 256) {
+    const int lx = i % HX, ly = i / HX;
+    const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - HYL + ly, ny);
+    const int64_t gi = (int64_t)gy * nx + gx;
+    T m[NF], r[NR];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) m[f] = cur[f * N + gi];
+    make_record<L, EQ>(m, r, kc);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
+    if constexpr (THREE_ST) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) m[f] = prev[f * N + gi];
+      make_record<L, EQ>(m, r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) hrec[k][ly][lx] = r[k];
+    }
+  }
+  __syncthreads();
+
+  for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    const int lx = i % TX, ly = i / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int cx = lx + 1, cy = ly + HYL;
+    const int64_t gi = (int64_t)gy * nx + gx;
+    auto at = [&](int k, int, int dy, int dx) { return rec[k][cy + dy][cx + dx]; };
+    auto ath = [&](int k, int, int dy, int dx) {
+      if constexpr (THREE_ST) return hrec[k][cy + dy][cx + dx];
+      else return T(0);
+    };
+    T cc[NF], pc[NF], oc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      cc[f] = at(f, 0, 0, 0);  // record fields 0..NF-1 are the moments
+      pc[f] = THREE ? prev[f * N + gi] : T(0);
+    }
+    mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
+  }
+}
+
 }  // namespace mfd

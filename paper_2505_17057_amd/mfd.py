@@ -52,6 +52,15 @@ class mfd_eq_params(C.Structure):
                 ("he_luo", C.c_int32), ("beta", C.c_double), ("rho0", C.c_double)]
 
 
+class mfd_request(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("eq", C.c_int32), ("precision", C.c_int32),
+                ("kind", C.c_int32), ("n", C.c_int64 * 2), ("d0", C.c_double), ("dx", C.c_double),
+                ("dt", C.c_double), ("ep", mfd_eq_params), ("a", C.c_double * 3),
+                ("ah", C.c_double * 3), ("nsteps", C.c_int64), ("state0", C.c_void_p),
+                ("prev0", C.c_void_p), ("result_out", C.c_void_p), ("result_bytes", C.c_int64),
+                ("exclude_from_stats", C.c_int32), ("reserved", C.c_int32)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmfd.so is not built (%s); run paper_2505_17057_amd/build.py" % LIB_PATH)
 
@@ -83,6 +92,22 @@ _SIGS = {
     "mfd_preset": ([C.c_int, C.c_double, _PD, _PD], C.c_int),
     "mfd_transport_coefficient": ([_PD, _PD, C.c_double, C.c_double, C.c_double, C.c_double, _PD], C.c_int),
     "mfd_max_amplification": ([_H, _PD], C.c_int),
+    "mfd_batch_create": ([C.POINTER(_H)], C.c_int),
+    "mfd_batch_destroy": ([_H], C.c_int),
+    "mfd_batch_last_error": ([_H], C.c_char_p),
+    "mfd_batch_set_stream": ([_H, _VP], C.c_int),
+    "mfd_batch_set_graph": ([_H, C.c_int], C.c_int),
+    "mfd_batch_add": ([_H, _H, C.c_int64, C.POINTER(C.c_int32)], C.c_int),
+    "mfd_batch_clear": ([_H], C.c_int),
+    "mfd_batch_run": ([_H], C.c_int),
+    "mfd_batch_wait": ([_H], C.c_int),
+    "mfd_batch_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+    "mfd_server_create": ([C.POINTER(_H), C.c_int64, C.c_int32, C.c_int64], C.c_int),
+    "mfd_server_submit": ([_H, C.POINTER(mfd_request), C.POINTER(C.c_int64)], C.c_int),
+    "mfd_server_poll": ([_H, C.c_int64, C.POINTER(C.c_int32), _PD], C.c_int),
+    "mfd_server_drain": ([_H, C.c_double], C.c_int),
+    "mfd_server_stats": ([_H, _PD, _PD, _PD, C.POINTER(C.c_int64), _PD], C.c_int),
+    "mfd_server_destroy": ([_H], C.c_int),
     "mfd_linear_tables": ([_H, _PD, _PD, _PD], C.c_int),
 }
 
@@ -275,3 +300,143 @@ class Solver:
         p6 = p6.reshape(6, 9)[:, :npair]
         names = ["ubp", "ubm", "Cp", "Cm", "Chp", "Chm"]
         return w, ub, {k: p6[i].copy() for i, k in enumerate(names)}
+
+
+class Batch:
+    """Owner of one mfd_batch handle (marshalling only)."""
+
+    def __init__(self, stream_handle=None, use_graph=True):
+        h = _H()
+        rc = lib.mfd_batch_create(C.byref(h))
+        if rc:
+            raise MfdError(rc, "mfd_batch_create")
+        self.h = h
+        self.members = []
+        if stream_handle:
+            self.check(lib.mfd_batch_set_stream(self.h, C.c_void_p(stream_handle)), "mfd_batch_set_stream")
+        self.check(lib.mfd_batch_set_graph(self.h, 1 if use_graph else 0), "mfd_batch_set_graph")
+
+    def check(self, rc, what):
+        if rc < 0:
+            msg = lib.mfd_batch_last_error(self.h)
+            raise MfdError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+        return rc
+
+    def add(self, solver, nsteps):
+        slot = C.c_int32()
+        self.check(lib.mfd_batch_add(self.h, solver.h, int(nsteps), C.byref(slot)), "mfd_batch_add")
+        self.members.append(solver)
+        return slot.value
+
+    def clear(self):
+        self.members = []
+        return self.check(lib.mfd_batch_clear(self.h), "mfd_batch_clear")
+
+    def run(self):
+        return self.check(lib.mfd_batch_run(self.h), "mfd_batch_run")
+
+    def wait(self):
+        return self.check(lib.mfd_batch_wait(self.h), "mfd_batch_wait")
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self.check(lib.mfd_batch_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "mfd_batch_stats")
+        return dict(launches=a.value, lups=b.value, tiles=c.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mfd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_request(lattice, eq, n, dx, dt, a, nsteps, state0, ah=None, kind="two_level",
+                 precision="fp32", u=(), K=None, lambda_bar=0, beta=1.0, rho0=0.0, he_luo=0,
+                 result_out=None, prev0=None, exclude=False, d0=1.0 / 3.0):
+    """Fill an mfd_request; the arrays must stay alive until the request is done."""
+    r = mfd_request()
+    r.lattice = LATTICES[lattice]
+    r.eq = EQS[eq]
+    r.precision = PRECISIONS[precision]
+    r.kind = KINDS[kind]
+    r.n = (C.c_int64 * 2)(int(n[0]), int(n[1]))
+    r.d0 = d0
+    r.dx = float(dx)
+    r.dt = float(dt)
+    p = mfd_eq_params()
+    uu = list(u) + [0.0] * (3 - len(u))
+    p.u = _D3(*uu)
+    Kd = np.zeros((3, 3))
+    if K is not None:
+        K = np.asarray(K, dtype=np.float64)
+        Kd[: K.shape[0], : K.shape[1]] = K
+    p.K = (C.c_double * 9)(*Kd.ravel().tolist())
+    p.lambda_bar = int(lambda_bar)
+    p.he_luo = int(he_luo)
+    p.beta = float(beta)
+    p.rho0 = float(rho0)
+    r.ep = p
+    r.a = _d3(a)
+    r.ah = _d3(ah if ah is not None else (0.0, 0.0, 0.0))
+    r.nsteps = int(nsteps)
+    r.state0 = state0.ctypes.data
+    r.prev0 = prev0.ctypes.data if prev0 is not None else None
+    r.result_out = result_out.ctypes.data if result_out is not None else None
+    r.result_bytes = result_out.nbytes if result_out is not None else 0
+    r.exclude_from_stats = 1 if exclude else 0
+    return r
+
+
+class Server:
+    """Owner of one mfd_server handle (marshalling only)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=256, quantum_steps=50):
+        h = _H()
+        rc = lib.mfd_server_create(C.byref(h), int(hbm_budget_bytes), int(max_slots), int(quantum_steps))
+        if rc:
+            raise MfdError(rc, "mfd_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, req, keep=()):
+        t = C.c_int64()
+        rc = lib.mfd_server_submit(self.h, C.byref(req), C.byref(t))
+        if rc:
+            raise MfdError(rc, "mfd_server_submit")
+        self._keep[t.value] = (req, keep)
+        return t.value
+
+    def poll(self, ticket):
+        st = C.c_int32()
+        lat = C.c_double()
+        rc = lib.mfd_server_poll(self.h, int(ticket), C.byref(st), C.byref(lat))
+        return st.value, lat.value, rc
+
+    def drain(self, timeout_s=600.0):
+        rc = lib.mfd_server_drain(self.h, float(timeout_s))
+        if rc:
+            raise MfdError(rc, "mfd_server_drain")
+
+    def stats(self):
+        p50, p99, rps, g = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        n = C.c_int64()
+        lib.mfd_server_stats(self.h, C.byref(p50), C.byref(p99), C.byref(rps), C.byref(n), C.byref(g))
+        return dict(p50_s=p50.value, p99_s=p99.value, req_per_s=rps.value, completed=n.value,
+                    glups=g.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mfd_server_destroy(self.h)
+            self.h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,169 @@
+"""GPU: batched stepping and continuous-batching serving.
+
+* A batch of uneven grids (sizes, coefficients, equations, step counts) gives
+  every instance exactly its solo result: FP64 equal to the oracle value for
+  value, FP32 bit-identical to the solo FP32 run; graph replay and plain
+  launches agree.
+* The server returns, for each request of a mixed stream, exactly the result
+  of the same request solved alone; admission respects the memory budget and
+  a request larger than the budget fails cleanly.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from parity_util import make_solver, rand_state, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TRT = ((1.0, 0.0, 0.4), (0.0, -0.4, 0.0))
+
+
+def batch_cases():
+    rng = np.random.default_rng(44)
+    cases = []
+    for i in range(9):
+        n = (int(rng.integers(20, 150)), int(rng.integers(12, 90)))
+        dx = 1.0 / n[0]
+        nu = float(rng.uniform(1e-3, 1e-2))
+        dt = 0.5 * min(0.3 * dx * dx / nu, nu / 0.01)
+        s = 2 * nu * dt / ((1.0 / 3.0) * dx * dx)
+        a = ((s + 1) / 2, 1 - s, (s - 1) / 2)
+        cases.append(dict(name="burgers%d" % i, lattice="D2Q9", eq="burgers", n=n, dx=dx, dt=dt, a=a,
+                          steps=int(rng.integers(3, 19))))
+    cases.append(dict(name="lcde", lattice="D2Q9", eq="lcde", n=(70, 37), u=(0.1, -0.07),
+                      K=[[0.3, 0.04], [0.04, 0.2]], lambda_bar=1, a=(1.0, 0.0, 0.0), steps=11))
+    cases.append(dict(name="nse-trt", lattice="D2Q9", eq="nse", n=(70, 37), rho0=1.0,
+                      kind="three_level", a=TRT[0], ah=TRT[1], steps=9))
+    cases.append(dict(name="nse-trt-b", lattice="D2Q9", eq="nse", n=(33, 65), rho0=1.0,
+                      kind="three_level", a=TRT[0], ah=TRT[1], steps=4))
+    return cases
+
+
+def _states(cases, seed=3):
+    rng = np.random.default_rng(seed)
+    return [(rand_state(c, rng), rand_state(c, rng)) for c in cases]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_fp64_matches_oracle(M, use_graph):
+    cases = batch_cases()
+    states = _states(cases)
+    solvers = []
+    b = M.Batch(use_graph=use_graph)
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp64")
+        s.set_state(cur)
+        if c.get("kind") == "three_level":
+            s.set_state(prev, level=1)
+        b.add(s, c["steps"])
+        solvers.append(s)
+    b.run()
+    b.wait()
+    b.run()  # a second run continues from the advanced states (graph replay)
+    b.wait()
+    st = b.stats()
+    # one launch per step of each group (burgers, lcde, nse) while any member runs
+    groups = {}
+    for c in cases:
+        groups[c["eq"]] = max(groups.get(c["eq"], 0), c["steps"])
+    assert st["launches"] == sum(groups.values())
+    for c, (cur, prev), s in zip(cases, states, solvers):
+        want = run_oracle(c, cur, prev, 2 * c["steps"])
+        got = s.get_state()
+        assert np.array_equal(got, want), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_fp32_equals_solo(M):
+    cases = batch_cases()
+    states = _states(cases, seed=4)
+    solo = []
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_state(cur.astype(np.float32))
+        if c.get("kind") == "three_level":
+            s.set_state(prev.astype(np.float32), level=1)
+        s.step(c["steps"])
+        solo.append(s.get_state())
+        s.close()
+    b = M.Batch()
+    solvers = []
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_state(cur.astype(np.float32))
+        if c.get("kind") == "three_level":
+            s.set_state(prev.astype(np.float32), level=1)
+        b.add(s, c["steps"])
+        solvers.append(s)
+    b.run()
+    b.wait()
+    for c, s, want in zip(cases, solvers, solo):
+        assert np.array_equal(s.get_state(), want), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def _request(M, c, state, out, exclude=False):
+    return M.make_request(c["lattice"], c["eq"], c["n"], c.get("dx", 1.0), c.get("dt", 1.0), c["a"],
+                          c["steps"], state, ah=c.get("ah"), kind=c.get("kind", "two_level"),
+                          precision="fp32", u=c.get("u", ()), K=c.get("K"),
+                          lambda_bar=c.get("lambda_bar", 0), rho0=c.get("rho0", 0.0),
+                          result_out=out, exclude=exclude)
+
+
+def test_server_alone_equals_mixed(M):
+    cases = batch_cases()
+    states = [s.astype(np.float32) for s, _ in _states(cases, seed=5)]
+    # alone: one request at a time through its own server
+    alone = []
+    for c, st in zip(cases, states):
+        srv = M.Server(hbm_budget_bytes=1 << 30, max_slots=4, quantum_steps=5)
+        out = np.empty_like(st)
+        srv.submit(_request(M, c, st, out), keep=(st, out))
+        srv.drain(60)
+        alone.append(out)
+        srv.close()
+    # mixed: all requests, staggered arrivals, small quantum so they overlap
+    srv = M.Server(hbm_budget_bytes=1 << 30, max_slots=64, quantum_steps=3)
+    outs = []
+    tickets = []
+    for c, st in zip(cases, states):
+        out = np.empty_like(st)
+        outs.append(out)
+        tickets.append(srv.submit(_request(M, c, st, out), keep=(st, out)))
+        time.sleep(0.002)
+    srv.drain(60)
+    for t in tickets:
+        state, lat, rc = srv.poll(t)
+        assert state == 2 and rc == 0 and lat > 0
+    stats = srv.stats()
+    assert stats["completed"] == len(cases) and stats["p99_s"] >= stats["p50_s"] > 0
+    srv.close()
+    for c, a, m in zip(cases, alone, outs):
+        assert np.array_equal(a, m), c["name"]
+
+
+def test_server_budget(M):
+    c = batch_cases()[0]
+    st = np.random.default_rng(1).uniform(-0.5, 0.5, c["n"][0] * c["n"][1]).astype(np.float32)
+    one = 3 * st.nbytes + (64 << 10)
+    srv = M.Server(hbm_budget_bytes=2 * one, max_slots=16, quantum_steps=2)
+    outs = [np.empty_like(st) for _ in range(6)]
+    ts = [srv.submit(_request(M, c, st, o), keep=(st, o)) for o in outs]
+    big = dict(c, n=(400, 400))
+    bst = np.zeros(400 * 400, dtype=np.float32)
+    bout = np.empty_like(bst)
+    tb = srv.submit(_request(M, big, bst, bout), keep=(bst, bout))
+    srv.drain(60)
+    for t in ts:
+        assert srv.poll(t)[0] == 2
+    state, _, rc = srv.poll(tb)
+    assert state == -1 and rc == M.MFD_E_BUDGET
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    srv.close()
