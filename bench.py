@@ -1,14 +1,23 @@
 """Benchmark of the MesoFD / MMFD time step on one MI355X.
 
-Workload (the one the headline metric is quoted on): 2D anisotropic linear
+Headline workload (the one the metric is quoted on): 2D anisotropic linear
 CDE, D2Q9, periodic 2048 x 2048, K = [[0.02,0.005],[0.005,0.01]],
 u = (0.05, 0.03), dt = 2^-18, SRT coefficients, Gaussian hill + seeded noise,
 10 000 time steps per solve.  One benchmark "step" is one full solve
-(10 000 time steps of the MMFD form in FP32 plus an FP64 mass reduction);
-the other forms/precisions of the same workload and an HBM-resident 8192^2
-point are reported beside it.
+(10 000 time steps of the MMFD form in FP32, then an FP64 mass reduction).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Beside it the same JSON line reports
+* the other forms / precisions of that workload and an HBM-resident 8192^2 point,
+* the FP32 error of the full run against the FP64 run,
+* the 1D D1Q3 workload (1024 nodes, 1000 steps, LDS-resident),
+* the NSE three-level MMFD workloads (4096^2 D2Q9, 512^3 D3Q19),
+* the batched workload: 256 Burgers grids, one graph launch in FP32, against
+  plain per-instance FP64 stepping,
+* the serving workload: Poisson arrivals of mixed Burgers / NSE solves,
+  p50 / p99 latency and throughput,
+* the oracle on the host cores (CPU baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -16,9 +25,9 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -29,6 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TIME_STEPS = 10000
 N_SIDE = 2048
+D0 = 1.0 / 3.0
 
 
 def parse():
@@ -38,62 +48,66 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a 256 MiB device copy (HBM counter calibration)")
+    p.add_argument("--serve-requests", type=int, default=300)
     return p.parse_args()
 
 
-def c2_solver(M, cfg, precision, form, torch_stream):
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------- helpers
+def c2_solver(M, cfg, precision, form, stream):
     s = M.Solver("D2Q9", cfg["n"], cfg["dx"], precision, form)
     s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
-    a, ah = M.mfd_preset("srt")
+    a, _ = M.mfd_preset("srt")
     s.set_scheme("two_level", a, dt=cfg["dt"])
-    s.set_stream(torch_stream.cuda_stream)
+    s.set_stream(stream.cuda_stream)
     s.set_state(cfg["phi0"].astype(s.dtype))
     return s
 
 
-def timed_steps(torch, s, nsteps, reps=1, reduce_each=True):
-    """Wall time (ms) of `reps` x `nsteps` time steps on the solver's stream,
-    bracketed by events and synchronisation on both sides."""
+def timed(torch, fn):
+    """GPU time (ms) of fn's work on the current stream, synchronised on both sides."""
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
-    for _ in range(reps):
-        s.step(nsteps)
+    fn()
     t1.record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    if reduce_each:
-        s.reduce()
-    return ms
+    return t0.elapsed_time(t1)
 
 
-def launch_durations(torch, s, tb, n=200):
-    """Mean GPU duration of one launch of the step kernel: events recorded on
-    the solver's stream around each of n calls that advance `tb` steps (one
-    blocked launch, or one single-step launch when tb = 1)."""
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+def launch_durations(torch, s, tb, n=1000):
+    """Mean GPU duration of one launch of the step kernel, from HIP events
+    recorded on the solver's stream around n back-to-back launches that each
+    advance `tb` time steps."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    for a, b in evs:
-        a.record()
-        s.step(tb)
-        b.record()
+    a.record()
+    s.step(tb * n)
+    b.record()
     torch.cuda.synchronize()
-    d = [a.elapsed_time(b) for a, b in evs]
-    return float(np.mean(d)), float(np.median(d))
+    return a.elapsed_time(b) / n
 
 
-def stored_traffic(kernel_src):
+def stored_traffic(kernel_src, tb, h):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel source with the same launch plan."""
     path = os.path.join(ROOT, "profiles", "traffic_mmfd_lcde_d2q9_2048_fp32.json")
     if not os.path.exists(path):
-        return None, None
+        return None
     info = json.load(open(path))
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     if info.get("kernel_source_sha256") != sha:
-        return None, info
-    return info.get("hbm_bytes_per_launch"), info
+        return None
+    if (info.get("time_steps_per_launch"), info.get("window_rows")) != (tb, h):
+        return None
+    return info.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(cfg, budget_s=15.0):
@@ -115,8 +129,202 @@ def cpu_baseline(cfg, budget_s=15.0):
         el = time.perf_counter() - t0
         if el > budget_s or steps >= 2000:
             break
-    return dict(value=N * steps / el / 1e9, unit="GLUPS", cores=threads, kind="oracle",
-                sample="%d MMFD FP64 time steps of the 2048^2 D2Q9 LCDE workload (%.1f s)" % (steps, el))
+    return dict(value=round(N * steps / el / 1e9, 4), unit="GLUPS", cores=threads, kind="oracle",
+                sample="%d MMFD FP64 time steps of the 2048^2 D2Q9 linear-CDE workload (%.1f s)"
+                       % (steps, el))
+
+
+def two_level_a(M, nu, dx, dt):
+    s = 2.0 * nu * dt / (D0 * dx * dx)
+    return M.mfd_preset("two_level", s)[0]
+
+
+def trt_coeffs(M, nu, dx, dt):
+    s = 1.0 / (nu / (dt * D0 * (dx / dt) ** 2) + 0.5)
+    return M.mfd_preset("trt", s)
+
+
+# ----------------------------------------------------------- workloads
+def bench_variants(M, torch, cfg, stream, N):
+    out, finals = {}, {}
+    for prec, form, bpl in (("fp64", "mmfd", 16), ("fp32", "mesofd", 72), ("fp64", "mesofd", 144)):
+        sv = c2_solver(M, cfg, prec, form, stream)
+        sv.autotune()
+        ms = timed(torch, lambda: sv.step(TIME_STEPS))
+        g = N * TIME_STEPS / (ms * 1e-3) / 1e9
+        out["%s_%s" % (form, prec)] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                                          frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
+                                          bytes_per_lup=bpl, ms_per_solve=round(ms, 3))
+        finals[(prec, form)] = sv.get_state().astype(np.float64)
+        sv.close()
+    s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
+    s32.step(TIME_STEPS)
+    f32 = s32.get_state().astype(np.float64)
+    s32.close()
+    f64 = finals[("fp64", "mmfd")]
+    err = dict(mmfd=float(np.linalg.norm(f32 - f64) / np.linalg.norm(f64)),
+               mesofd=float(np.linalg.norm(finals[("fp32", "mesofd")] - finals[("fp64", "mesofd")])
+                            / np.linalg.norm(finals[("fp64", "mesofd")])))
+    meso_vs_mmfd = float(np.abs(finals[("fp64", "mesofd")] - f64).max())
+    return out, err, meso_vs_mmfd
+
+
+def bench_big(M, torch, I, stream):
+    big = I.c2_hill_2d(n=8192)
+    sb = c2_solver(M, big, "fp32", "mmfd", stream)
+    sb.autotune()
+    ms = timed(torch, lambda: sb.step(1000))
+    g = 8192 * 8192 * 1000 / (ms * 1e-3) / 1e9
+    sb.close()
+    return dict(glups=round(g, 2), alg_gbs=round(g * 8, 1), frac_hbm=round(g * 8 / HBM_PEAK_GBS, 4))
+
+
+def bench_c1(M, torch, I, stream):
+    c1 = I.c1_linear_1d()
+    res = {}
+    for form in ("mmfd", "mesofd"):
+        s = M.Solver("D1Q3", c1["n"], c1["dx"], "fp64", form)
+        s.set_equation("lcde", u=c1["u"], K=c1["K"])
+        sp = 2 * c1["D"] * c1["dt"] / (D0 * c1["dx"] ** 2)
+        s.set_scheme("two_level", M.mfd_preset("two_level", sp)[0], dt=c1["dt"])
+        s.set_stream(stream.cuda_stream)
+        s.set_state(c1["phi0"])
+        s.step(c1["steps"])  # warm-up
+        s.set_state(c1["phi0"])
+        ms = timed(torch, lambda: s.step(c1["steps"]))
+        res[form + "_fp64_us_per_1000_steps"] = round(ms * 1e3, 1)
+        s.close()
+    return res
+
+
+def bench_nse(M, torch, I, stream):
+    res = {}
+    c3 = I.tgv_2d(n=4096)
+    a, ah = trt_coeffs(M, c3["nu"], c3["dx"], c3["dt"])
+    s = M.Solver("D2Q9", c3["n"], c3["dx"], "fp32", "mmfd")
+    s.set_equation("nse", rho0=c3["rho0"])
+    s.set_scheme("three_level", a, ah, dt=c3["dt"])
+    s.set_stream(stream.cuda_stream)
+    s.set_state(c3["state0"].astype(np.float32))
+    s.step(20)
+    ms = timed(torch, lambda: s.step(200))
+    g = 4096 * 4096 * 200 / (ms * 1e-3) / 1e9
+    res["d2q9_4096_three_level_fp32"] = dict(glups=round(g, 2), alg_gbs=round(g * 36, 1),
+                                             frac_hbm=round(g * 36 / HBM_PEAK_GBS, 4), bytes_per_lup=36)
+    s.close()
+    del c3
+    c3d = I.tgv_3d(n=512, dtype=np.float32)
+    a, ah = trt_coeffs(M, c3d["nu"], c3d["dx"], c3d["dt"])
+    s = M.Solver("D3Q19", c3d["n"], c3d["dx"], "fp32", "mmfd")
+    s.set_equation("nse", rho0=c3d["rho0"])
+    s.set_scheme("three_level", a, ah, dt=c3d["dt"])
+    s.set_stream(stream.cuda_stream)
+    s.set_state(c3d["state0"])
+    del c3d
+    s.step(2)
+    ms = timed(torch, lambda: s.step(20))
+    g = 512 ** 3 * 20 / (ms * 1e-3) / 1e9
+    res["d3q19_512_three_level_fp32"] = dict(glups=round(g, 2), alg_gbs=round(g * 48, 1),
+                                             frac_hbm=round(g * 48 / HBM_PEAK_GBS, 4), bytes_per_lup=48)
+    s.close()
+    return res
+
+
+def bench_batched(M, torch, I, stream):
+    insts = I.c4_batch(256, seed=4)
+    lups = sum(int(np.prod(c["n"])) * c["steps"] for c in insts)
+
+    def make(c, prec):
+        s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        s.set_equation("burgers")
+        s.set_scheme("two_level", two_level_a(M, c["nu"], c["dx"], c["dt"]), dt=c["dt"])
+        s.set_stream(stream.cuda_stream)
+        s.set_state(c["phi0"].astype(s.dtype))
+        return s
+
+    s32 = [make(c, "fp32") for c in insts]
+    b = M.Batch(stream.cuda_stream, use_graph=True)
+    for s, c in zip(s32, insts):
+        b.add(s, c["steps"])
+    t0 = time.perf_counter()
+    b.run()
+    b.wait()
+    first_s = time.perf_counter() - t0  # includes graph capture + instantiation
+    for s, c in zip(s32, insts):
+        s.set_state(c["phi0"].astype(np.float32))
+    ms32 = timed(torch, lambda: b.run())
+    st = b.stats()
+    # plain per-instance FP64 stepping: one launch per step per instance
+    s64 = [make(c, "fp64") for c in insts]
+    ms64 = timed(torch, lambda: [s.step(c["steps"]) for s, c in zip(s64, insts)])
+    errs, errs0, decay = [], [], []
+    for a32, a64, c in zip(s32, s64, insts):
+        x = a32.get_state().astype(np.float64)
+        y = a64.get_state()
+        n0 = np.linalg.norm(c["phi0"])
+        errs.append(float(np.linalg.norm(x - y) / np.linalg.norm(y)))
+        errs0.append(float(np.linalg.norm(x - y) / n0))
+        decay.append(float(np.linalg.norm(y) / n0))
+    worst = int(np.argmax(errs))
+    for s in s32 + s64:
+        s.close()
+    b.close()
+    g32 = lups / (ms32 * 1e-3) / 1e9
+    g64 = lups / (ms64 * 1e-3) / 1e9
+    return dict(instances=len(insts), lups=lups, graph_launches=st["launches"], tiles=st["tiles"],
+                fp32_graph_ms=round(ms32, 2), fp32_glups=round(g32, 2),
+                fp32_first_run_incl_capture_s=round(first_s, 3),
+                fp64_per_instance_ms=round(ms64, 2), fp64_glups=round(g64, 2),
+                speedup_vs_fp64_per_instance=round(ms64 / ms32, 2),
+                fp32_rel_l2_vs_fp64_max=max(errs), fp32_rel_l2_vs_fp64_median=float(np.median(errs)),
+                fp32_err_over_initial_norm_max=max(errs0),
+                worst_instance=dict(side=insts[worst]["n"][0], steps=insts[worst]["steps"],
+                                    final_over_initial_norm=decay[worst]))
+
+
+def bench_serving(M, I, n_total, rate=200.0, warm=50, quantum=50):
+    trace = I.serving_trace(count=n_total - warm, warmup=warm, rate=rate)
+    reqs = []
+    t0 = time.perf_counter()
+    for r in trace:
+        inst = I.serving_request_state(r)
+        dx, dt = inst["dx"], inst["dt"]
+        if r["kind"] == "burgers":
+            st = inst["phi0"].astype(np.float32)
+            a, ah, kind, eq, rho0 = two_level_a(M, inst["nu"], dx, dt), None, "two_level", "burgers", 0.0
+        else:
+            st = inst["state0"].astype(np.float32)
+            a, ah = trt_coeffs(M, inst["nu"], dx, dt)
+            kind, eq, rho0 = "three_level", "nse", inst["rho0"]
+        out = np.empty_like(st)
+        req = M.make_request("D2Q9", eq, inst["n"], dx, dt, a, r["steps"], st, ah=ah, kind=kind,
+                             precision="fp32", rho0=rho0, result_out=out, exclude=r["warmup"])
+        reqs.append((r, req, st, out))
+    gen_s = time.perf_counter() - t0
+    srv = M.Server(hbm_budget_bytes=200 * 10 ** 9, max_slots=1024, quantum_steps=quantum)
+    tickets = []
+
+    def submitter():
+        start = time.perf_counter()
+        for r, req, st, out in reqs:
+            delay = start + r["arrival"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(req, keep=(st, out)))
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    srv.drain(600)
+    stats = srv.stats()
+    fails = sum(1 for t in tickets if srv.poll(t)[0] != 2)
+    srv.close()
+    lups = sum(r["side"] * r["side"] * r["steps"] for r, _, _, _ in reqs)
+    return dict(requests=len(reqs), warmup_excluded=warm, rate_per_s=rate, quantum_steps=quantum,
+                hbm_budget_bytes=200 * 10 ** 9, p50_s=round(stats["p50_s"], 4),
+                p99_s=round(stats["p99_s"], 4), completed_per_s=round(stats["req_per_s"], 2),
+                glups=round(stats["glups"], 2), failed=fails, offered_glup=round(lups / 1e9, 1),
+                input_generation_s=round(gen_s, 1), precision="fp32")
 
 
 def main():
@@ -137,68 +345,70 @@ def main():
     N = N_SIDE * N_SIDE
 
     # ---------------------------------------------------------- headline
+    log("headline: 2048^2 MMFD FP32")
     s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
-    tb = s32.autotune()
+    s32.autotune()
+    tb, h = s32.launch_plan()
     for _ in range(args.warmup):
-        timed_steps(torch, s32, TIME_STEPS)
-    total_ms = 0.0
-    for _ in range(args.steps):
-        total_ms += timed_steps(torch, s32, TIME_STEPS)
-    ms_per_step = total_ms / args.steps
+        timed(torch, lambda: s32.step(TIME_STEPS))
+        s32.reduce()
+    # Timed region: K solves, each TIME_STEPS time steps then the FP64 mass /
+    # residual reduction; events on the solver's stream split off the step
+    # kernels' share to give the mean launch duration.
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e0, e1, e2 in ev:
+        e0.record()
+        s32.step(TIME_STEPS)
+        e1.record()
+        s32.reduce()  # synchronous
+        e2.record()
+    torch.cuda.synchronize()
+    ms_per_step = sum(e0.elapsed_time(e2) for e0, _, e2 in ev) / args.steps
+    kernel_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
     glups = N * TIME_STEPS / (ms_per_step * 1e-3) / 1e9
-
-    # dominant kernel: one launch advances `tb` time steps of N nodes
-    mean_ms, med_ms = launch_durations(torch, s32, tb, 200)
+    if TIME_STEPS % tb == 0:
+        launches = TIME_STEPS // tb
+        mean_ms = kernel_ms / launches
+        how = "HIP events over the timed region: %d launches per solve" % launches
+    else:
+        mean_ms = launch_durations(torch, s32, tb)
+        how = "HIP events around 1000 back-to-back launches"
     alg_bytes = 8.0 * N * tb  # read phi^n, write phi^(n+1): 8 B per LUP in FP32
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
-    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc", "kernels_tb.hip" if tb > 1 else "kernels_mmfd.hip")
-    traffic, tinfo = stored_traffic(kernel_src)
+    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc",
+                              "kernels_tb.hip" if tb > 1 else "kernels_mmfd.hip")
+    traffic = stored_traffic(kernel_src, tb, h)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=("mmfd_tb" if tb > 1 else "mmfd_plane") + " D2Q9 LCDE FP32",
-                    launch_ms_mean=round(mean_ms, 5), launch_ms_median=round(med_ms, 5),
-                    time_steps_per_launch=tb, algorithmic_bytes_per_launch=alg_bytes)
+                    kernel=("k_lcde_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
+                    launch_ms_mean=round(mean_ms, 5), launch_timing=how,
+                    time_steps_per_launch=tb, window_rows=h, algorithmic_bytes_per_launch=alg_bytes,
+                    measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None))
+    s32.close()
 
     extra = {}
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        extra["copy_calibration_bytes"] = x.numel() * 4  # read once and written once
     if not args.quick:
-        # ------------------------------------------------------ variants
-        variants = {}
-        finals = {}
-        for prec, form, nsteps in (("fp64", "mmfd", TIME_STEPS), ("fp32", "mesofd", TIME_STEPS),
-                                   ("fp64", "mesofd", TIME_STEPS)):
-            sv = c2_solver(M, cfg, prec, form, stream)
-            sv.autotune()
-            ms = timed_steps(torch, sv, nsteps, reduce_each=False)
-            bpl = {("fp64", "mmfd"): 16, ("fp32", "mesofd"): 72, ("fp64", "mesofd"): 144}[(prec, form)]
-            g = N * nsteps / (ms * 1e-3) / 1e9
-            variants["%s_%s" % (form, prec)] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
-                                                    frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
-                                                    bytes_per_lup=bpl, ms_per_solve=round(ms, 3))
-            finals[(prec, form)] = sv.get_state().astype(np.float64)
-            sv.close()
-        # FP32 error of the full 10 000-step run against the FP64 run
-        s32b = c2_solver(M, cfg, "fp32", "mmfd", stream)
-        s32b.step(TIME_STEPS)
-        f32 = s32b.get_state().astype(np.float64)
-        s32b.close()
-        f64 = finals[("fp64", "mmfd")]
-        rel = float(np.linalg.norm(f32 - f64) / np.linalg.norm(f64))
-        relm = float(np.linalg.norm(finals[("fp32", "mesofd")] - finals[("fp64", "mesofd")])
-                     / np.linalg.norm(finals[("fp64", "mesofd")]))
-        meso_vs_mmfd = float(np.abs(finals[("fp64", "mesofd")] - f64).max())
-        extra["variants"] = variants
-        extra["fp32_rel_l2_vs_fp64_after_10000"] = {"mmfd": rel, "mesofd": relm}
-        extra["mesofd_vs_mmfd_fp64_max_abs"] = meso_vs_mmfd
-
-        # HBM-resident point: 8192^2 (2 x 256 MiB > 256 MB Infinity Cache)
-        big = I.c2_hill_2d(n=8192)
-        sb = c2_solver(M, big, "fp32", "mmfd", stream)
-        sb.autotune()
-        ms = timed_steps(torch, sb, 1000, reduce_each=False)
-        gb = 8192 * 8192 * 1000 / (ms * 1e-3) / 1e9
-        extra["hbm_resident_8192_mmfd_fp32"] = dict(glups=round(gb, 2), alg_gbs=round(gb * 8, 1),
-                                                    frac_hbm=round(gb * 8 / HBM_PEAK_GBS, 4))
-        sb.close()
+        log("variants")
+        extra["variants"], extra["fp32_rel_l2_vs_fp64_after_10000"], extra["mesofd_vs_mmfd_fp64_max_abs"] = \
+            bench_variants(M, torch, cfg, stream, N)
+        log("8192^2")
+        extra["hbm_resident_8192_mmfd_fp32"] = bench_big(M, torch, I, stream)
+        log("1D")
+        extra["c1_d1q3_1024"] = bench_c1(M, torch, I, stream)
+        log("NSE")
+        extra["nse"] = bench_nse(M, torch, I, stream)
+        log("batched")
+        extra["batched_256_burgers"] = bench_batched(M, torch, I, stream)
+        log("serving")
+        extra["serving"] = bench_serving(M, I, args.serve_requests)
 
     cpu = None if args.no_cpu else cpu_baseline(cfg)
 
@@ -223,7 +433,6 @@ def main():
         "cpu_baseline": cpu,
     }
     line.update(extra)
-    s32.close()
     print(json.dumps(line))
 
 

@@ -204,6 +204,12 @@ int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
  * 64 x (2 depth + 4) nodes; MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
+/* The launch plan mfd_step uses now: *tb_depth time steps per launch of the
+ * step kernel (1 = one launch per step) and *window_rows, the height of the
+ * temporally blocked kernel's LDS window (0 when tb_depth is 1).  Either
+ * pointer may be NULL.  MFD_E_ORDER before the scheme is set. */
+int mfd_launch_plan(const mfd_solver *s, int32_t *tb_depth, int32_t *window_rows);
+
 /* ---------------------------------------------------------------- batches */
 
 /* A batch advances many solvers (independent periodic grids of any sizes,

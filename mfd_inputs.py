@@ -144,28 +144,36 @@ def tgv_2d_exact_velocity(n, t, U0=1.0, nu=0.01):
     return -U0 * np.cos(X) * np.sin(Y) * f, U0 * np.sin(X) * np.cos(Y) * f
 
 
-def tgv_3d(n=512, seed=3, U0=1.0, rho0=1.0, nu=None, courant=0.05, noise=1e-4):
+def tgv_3d(n=512, seed=3, U0=1.0, rho0=1.0, nu=None, courant=0.05, noise=1e-4, dtype=np.float64):
     """3D Taylor-Green vortex on [0, 2 pi)^3:
     u = U0 (sin x cos y cos z, -cos x sin y cos z, 0),
     p = rho0 U0^2/16 (cos 2x + cos 2y)(cos 2z + 2), rho = rho0 + p / c_s^2.
-    Default nu from lattice viscosity 0.04074 at courant 0.05 (nu = 0.04074 dx^2/dt)."""
+    Default nu from lattice viscosity 0.04074 at courant 0.05 (nu = 0.04074 dx^2/dt).
+    Built by broadcasting 1D factors (no full coordinate grids)."""
     x, dx = _grid(n, 2 * np.pi)
     dt = courant * dx / U0
     cs2 = (dx / dt) ** 2 / 3.0
     if nu is None:
         nu = 0.04074 * dx * dx / dt
-    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    sx, cx = np.sin(x).astype(dtype), np.cos(x).astype(dtype)
+    c2 = np.cos(2 * x).astype(dtype)
     rng = np.random.default_rng(seed)
     shape = (n, n, n)
-    u = U0 * np.sin(X) * np.cos(Y) * np.cos(Z) + noise * U0 * rng.uniform(-1, 1, shape)
-    v = -U0 * np.cos(X) * np.sin(Y) * np.cos(Z) + noise * U0 * rng.uniform(-1, 1, shape)
-    w = noise * U0 * rng.uniform(-1, 1, shape)
-    p = rho0 * U0 * U0 / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
-    drho = p / cs2
-    rho = rho0 + drho
     s = dt / dx
-    state = np.concatenate([drho.ravel(), (rho * u * s).ravel(), (rho * v * s).ravel(),
-                            (rho * w * s).ravel()])
+    p = (rho0 * U0 * U0 / 16.0) * (c2[None, None, :] + c2[None, :, None]) * (c2[:, None, None] + 2.0)
+    drho = (p / cs2).astype(dtype)
+    del p
+    rho = rho0 + drho
+    u = (U0 * sx[None, None, :] * cx[None, :, None] * cx[:, None, None]
+         + (noise * U0) * rng.uniform(-1, 1, shape).astype(dtype))
+    ju = (rho * u * s).astype(dtype)
+    del u
+    v = (-U0 * cx[None, None, :] * sx[None, :, None] * cx[:, None, None]
+         + (noise * U0) * rng.uniform(-1, 1, shape).astype(dtype))
+    jv = (rho * v * s).astype(dtype)
+    del v
+    jw = (rho * ((noise * U0) * rng.uniform(-1, 1, shape).astype(dtype)) * s).astype(dtype)
+    state = np.concatenate([drho.ravel(), ju.ravel(), jv.ravel(), jw.ravel()])
     return dict(lattice="D3Q19", eq="nse", n=(n, n, n), dx=dx, dt=dt, nu=nu, rho0=rho0,
                 U0=U0, steps=1000, state0=state)
 

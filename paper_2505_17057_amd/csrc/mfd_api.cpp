@@ -551,6 +551,16 @@ extern "C" int mfd_set_blocking(mfd_solver *h, int32_t tb_depth) {
   return MFD_OK;
 }
 
+extern "C" int mfd_launch_plan(const mfd_solver *h, int32_t *tb_depth, int32_t *window_rows) {
+  if (!h) return MFD_E_ARG;
+  const Solver *s = reinterpret_cast<const Solver *>(h);
+  if (!s->configured) return MFD_E_ORDER;
+  const TbPlan p = s->effective_plan();
+  if (tb_depth) *tb_depth = p.tb;
+  if (window_rows) *window_rows = p.tb > 1 ? p.h : 0;
+  return MFD_OK;
+}
+
 extern "C" int mfd_autotune(mfd_solver *h, int32_t *chosen_tb) {
   SOLVER_OR_ARG(h);
   return reinterpret_cast<Solver *>(h)->autotune(chosen_tb);

@@ -1,0 +1,29 @@
+#!/bin/bash
+# rocprofv3 evidence for the headline step kernel (run from the repository
+# root on a machine with the GPU; writes raw results under gpurun_out/):
+#   1. kernel trace + stats of the headline benchmark,
+#   2. FETCH_SIZE and 3. WRITE_SIZE counters, each in a run of its own, with a
+#      256 MiB device copy as the counter calibration,
+# then summarises them into profiles/ with paper_2505_17057_amd.profiling.
+set -u
+R=$(pwd)
+O=$R/gpurun_out
+mkdir -p "$O"
+export TMPDIR=/tmp
+echo "profile: kernel trace"
+(cd /tmp && timeout -k 10 240 rocprofv3 --kernel-trace --stats -d "$O/prof_kt" -o kt -- python3 $R/bench.py --quick --steps 5 --warmup 1 --no-cpu --copy-calibration > "$O/prof_kt.txt" 2>&1) || exit 2
+echo "profile: FETCH_SIZE"
+(cd /tmp && timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --kernel-trace -d "$O/prof_fetch" -o f -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration > "$O/prof_fetch.txt" 2>&1) || exit 3
+echo "profile: WRITE_SIZE"
+(cd /tmp && timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --kernel-trace -d "$O/prof_write" -o w -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration > "$O/prof_write.txt" 2>&1) || exit 4
+N=4194304
+python3 -m paper_2505_17057_amd.profiling --trace "$O/prof_kt/kt_results.db" \
+  --fetch "$O/prof_fetch/f_results.db" --write "$O/prof_write/w_results.db" \
+  --kernel k_lcde_tb --copy-bytes 268435456 \
+  --kernel-source paper_2505_17057_amd/csrc/kernels_tb.hip --bench-log "$O/prof_kt.txt" \
+  --algorithmic-bytes-per-step $((8 * N)) --pass-bytes $((8 * N)) \
+  --workload "2D linear CDE, D2Q9, 2048x2048, MMFD FP32 (bench.py headline)" \
+  --out-md profiles/mmfd_lcde_d2q9_2048_fp32.md --out-json profiles/traffic_mmfd_lcde_d2q9_2048_fp32.json \
+  --command "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_kt -o kt -- python3 bench.py --quick --steps 5 --warmup 1 --no-cpu --copy-calibration" \
+  --command "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d gpurun_out/prof_fetch -o f -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration" \
+  --command "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d gpurun_out/prof_write -o w -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration"

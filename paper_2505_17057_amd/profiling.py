@@ -1,0 +1,174 @@
+"""Summaries of rocprofv3 result databases (SQLite, ``*_results.db``).
+
+Turns one kernel-trace run and two counter runs (``--pmc FETCH_SIZE`` and
+``--pmc WRITE_SIZE``, each with ``--kernel-trace``) of the same program into
+* a short text summary (per-kernel call count and durations, per-dispatch
+  HBM counters of the step kernel and of a device copy of known size), and
+* a JSON record of the step kernel's HBM bytes per launch, scaled by what the
+  same counters read for the copy, keyed by the SHA-256 of the kernel source so
+  that a reader can tell when the figures are stale.
+
+The copy calibrates the counters: a device-to-device copy of B bytes moves
+exactly B bytes in and B bytes out of HBM, so counter_bytes * (B / reading) is
+the HBM traffic.  On gfx950 FETCH_SIZE reads half the bytes a copy fetches and
+WRITE_SIZE reads them exactly; the factors are measured, not assumed.
+
+Usage:
+  python -m paper_2505_17057_amd.profiling --trace T.db --fetch F.db --write W.db \
+      --kernel k_lcde_tb --copy-bytes 268435456 --kernel-source SRC --bench-log LOG \
+      --algorithmic-bytes-per-step B --pass-bytes P --workload TEXT \
+      --out-md profiles/X.md --out-json profiles/X.json --command "..." ...
+(paper_2505_17057_amd/profile_headline.sh runs the three profiles and this.)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import shlex
+import sqlite3
+import sys
+import statistics
+from collections import defaultdict
+
+
+def kernel_stats(db_path):
+    """[(name, calls, total_ns, mean_ns, min_ns, max_ns)] sorted by total time."""
+    db = sqlite3.connect(db_path)
+    rows = defaultdict(list)
+    for name, dur in db.execute("select name, duration from kernels"):
+        rows[name].append(int(dur))
+    out = [(n, len(d), sum(d), sum(d) / len(d), min(d), max(d)) for n, d in rows.items()]
+    out.sort(key=lambda r: -r[2])
+    return out
+
+
+def kernel_grids(db_path, kernel):
+    """{grid_x: (calls, mean_ns)} of dispatches whose name contains `kernel`."""
+    db = sqlite3.connect(db_path)
+    g = defaultdict(list)
+    for name, grid, dur in db.execute("select name, grid_x, duration from kernels"):
+        if kernel in name:
+            g[int(grid)].append(int(dur))
+    return {k: (len(v), sum(v) / len(v)) for k, v in g.items()}
+
+
+def counter_by_grid(db_path, counter, kernel):
+    """{grid: [value per dispatch]} (KiB) for dispatches whose name contains `kernel`."""
+    db = sqlite3.connect(db_path)
+    g = defaultdict(list)
+    q = "select kernel_name, grid_size, value from counters_collection where counter_name = ?"
+    for name, grid, val in db.execute(q, (counter,)):
+        if kernel in name:
+            g[int(grid)].append(float(val))
+    return g
+
+
+def copy_factor(db_path, counter, copy_bytes):
+    """Scale factor bytes / (counter KiB * 1024) from the copy dispatches of
+    `copy_bytes` bytes (those whose counter reads at least a quarter of it)."""
+    vals = []
+    for vs in counter_by_grid(db_path, counter, "copyBuffer").values():
+        vals += [v for v in vs if v * 1024.0 >= copy_bytes / 4]
+    if not vals:
+        raise SystemExit("no copy dispatch of %d bytes found for %s" % (copy_bytes, counter))
+    return copy_bytes / (statistics.fmean(vals) * 1024.0), vals
+
+
+def bench_plan(log_path):
+    """(tb, h, launch_ms_mean) from the JSON line a bench run printed."""
+    for line in open(log_path):
+        line = line.strip()
+        if line.startswith("{") and '"roofline"' in line:
+            r = json.loads(line)["roofline"]
+            return r["time_steps_per_launch"], r.get("window_rows", 0), r.get("launch_ms_mean")
+    raise SystemExit("no bench JSON line in " + log_path)
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser()
+    p.add_argument("--trace", required=True)
+    p.add_argument("--fetch", required=True)
+    p.add_argument("--write", required=True)
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--copy-bytes", type=int, required=True, help="bytes copied by one calibration copy")
+    p.add_argument("--kernel-source", required=True)
+    p.add_argument("--bench-log", required=True)
+    p.add_argument("--algorithmic-bytes-per-step", type=float, required=True,
+                   help="algorithmic bytes of one time step over the grid (x time steps per launch)")
+    p.add_argument("--pass-bytes", type=float, required=True,
+                   help="bytes of one read and one write of every stored field (the least any launch moves)")
+    p.add_argument("--workload", required=True)
+    p.add_argument("--out-md", required=True)
+    p.add_argument("--out-json", required=True)
+    p.add_argument("--command", action="append", default=[], help="command that produced an input")
+    argv = sys.argv[1:] if argv is None else argv
+    a = p.parse_args(argv)
+    a.command = a.command + ["python -m paper_2505_17057_amd.profiling " + shlex.join(argv)]
+
+    stats = kernel_stats(a.trace)
+    grids = kernel_grids(a.trace, a.kernel)
+    tb, h, ev_ms = bench_plan(a.bench_log)
+    a.algorithmic_bytes = a.algorithmic_bytes_per_step * tb
+    main_grid = max(grids, key=lambda g: grids[g][0])  # the timed plan launches most often
+    ff, fvals = copy_factor(a.fetch, "FETCH_SIZE", a.copy_bytes)
+    wf, wvals = copy_factor(a.write, "WRITE_SIZE", a.copy_bytes)
+    fk = counter_by_grid(a.fetch, "FETCH_SIZE", a.kernel)[main_grid]
+    wk = counter_by_grid(a.write, "WRITE_SIZE", a.kernel)[main_grid]
+    fetch_b = statistics.fmean(fk) * 1024.0 * ff
+    write_b = statistics.fmean(wk) * 1024.0 * wf
+    traffic = fetch_b + write_b
+    sha = hashlib.sha256(open(a.kernel_source, "rb").read()).hexdigest()
+    calls, mean_ns = grids[main_grid]
+    rec = dict(kernel=a.kernel, workload=a.workload, kernel_source=a.kernel_source,
+               kernel_source_sha256=sha, time_steps_per_launch=tb, window_rows=h,
+               grid_threads=main_grid, dispatches=calls, trace_mean_us=round(mean_ns / 1e3, 3),
+               fetch_kib_raw=statistics.fmean(fk), write_kib_raw=statistics.fmean(wk),
+               fetch_factor=round(ff, 5), write_factor=round(wf, 5),
+               hbm_bytes_per_launch=round(traffic), algorithmic_bytes_per_launch=a.algorithmic_bytes,
+               one_pass_bytes=a.pass_bytes,
+               commands=a.command)
+    with open(a.out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+
+    L = []
+    L.append("# rocprofv3 summary: %s, %s\n" % (a.kernel, a.workload))
+    L.append("Commands (from the repository root on the GPU box; `cd /tmp && export TMPDIR=/tmp` "
+             "first, output directories under gpurun_out/):\n")
+    for c in a.command:
+        L.append("    " + c)
+    L.append("")
+    L.append("## Kernel trace (`--kernel-trace --stats`)\n")
+    L.append("| kernel | calls | mean us | min us | max us | share |")
+    L.append("|---|---|---|---|---|---|")
+    total = sum(r[2] for r in stats) or 1
+    for n, c, t, m, lo, hi in stats[:10]:
+        L.append("| %s | %d | %.3f | %.3f | %.3f | %.1f%% |" % (n[:90], c, m / 1e3, lo / 1e3, hi / 1e3,
+                                                               100.0 * t / total))
+    L.append("")
+    L.append("Timed plan of `%s`: %d time steps per launch, LDS window %d rows, grid %d threads, "
+             "%d dispatches, mean %.3f us (trace); the bench's own HIP-event mean over its timed "
+             "region: %s us.\n" % (a.kernel, tb, h, main_grid, calls, mean_ns / 1e3,
+                                  "%.3f" % (ev_ms * 1e3) if ev_ms else "n/a"))
+    L.append("## HBM counters (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, KiB per dispatch)\n")
+    L.append("| dispatch | FETCH_SIZE KiB | WRITE_SIZE KiB |")
+    L.append("|---|---|---|")
+    L.append("| copy of %d B (mean of %d/%d) | %.1f | %.1f |" % (a.copy_bytes, len(fvals), len(wvals),
+                                                             statistics.fmean(fvals), statistics.fmean(wvals)))
+    L.append("| %s, timed plan (mean of %d/%d) | %.1f | %.1f |" % (a.kernel, len(fk), len(wk),
+                                                                 statistics.fmean(fk), statistics.fmean(wk)))
+    L.append("")
+    L.append("Copy calibration: FETCH factor %.4f, WRITE factor %.4f (bytes moved / counter bytes)." % (ff, wf))
+    L.append("Scaled HBM traffic per launch: read %.0f B + write %.0f B = %.0f B, i.e. %.3f x one pass "
+             "over the stored fields (%.0f B) and %.3f x the algorithmic bytes of the launch's time steps "
+             "(%.0f B)." % (fetch_b, write_b, traffic, traffic / a.pass_bytes, a.pass_bytes,
+                            traffic / a.algorithmic_bytes, a.algorithmic_bytes))
+    L.append("Kernel source SHA-256: `%s` (%s)." % (sha, a.kernel_source))
+    with open(a.out_md, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -79,6 +79,8 @@ def test_autotune_preserves_state(M):
     before = s.get_state()
     d = s.autotune()
     assert d in (1, 2, 4, 6, 8)
+    tb, h = s.launch_plan()
+    assert tb == d and (h == 0) == (d == 1)
     assert np.array_equal(s.get_state(), before)
     s.step(9)
     ref = make_solver(M, case, "fp64")
