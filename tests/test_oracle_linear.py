@@ -219,3 +219,27 @@ def test_three_level_growth_matches_max_root():
     rate = np.exp(np.mean(logs[-100:]))
     assert lam > 1.0
     assert abs(rate - lam) < 1e-4 * lam
+
+
+def test_table3_stability_bracket():
+    """Table 3 (Example 2, Case 1: SRT, D = 0.01, u = (1, 1), periodic [0,2)^2):
+    the runs at |u|^2/c_s^2 = 50/3 and 25/6 diverge, those at 25/24 and 25/96
+    stay bounded.  The exact max |lambda| over the grid's Fourier modes of the
+    oracle's linear step must fall on the same sides of 1."""
+    import json
+    import os
+    from fractions import Fraction as F
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "printed_values.json")))
+    E, w, pairs = O.lattice_info("D2Q9")
+    for i, (sdx, sdt, sratio) in enumerate(gold["stability_ratio_table3"]["rows"]):
+        dx, dt = F(sdx), F(sdt)
+        assert 2 / ((dx / dt) ** 2 / 3) == F(sratio)  # |u|^2 / c_s^2 with u = (1, 1)
+        nx = int(2 / dx)
+        spec = dict(lattice="D2Q9", n=(nx, nx), dx=float(dx), dt=float(dt), u=(1.0, 1.0),
+                    K=[[0.01, 0.0], [0.0, 0.01]], lambda_bar=1, a=S.preset_srt()[0])
+        _, _, tab = O.tables(spec)
+        lam = S.max_amplification(E, pairs, tab["ubp"], tab["ubm"], spec["n"], spec["a"], (0, 0, 0))
+        if i < 2:
+            assert lam > 1.5, (sratio, lam)
+        else:
+            assert lam < 1.0 + 1e-12, (sratio, lam)
