@@ -4,11 +4,18 @@
 // k in (-1, 0, +1) order, level t first, zero coefficients skipped; f^eq at
 // level t is the EDF of the moments of the populations (Eq. (2-1-1):
 // phi = sum_j f_j, j_a = sum_j e_ja f_j, lattice order), at level t - dt the
-// EDF of the stored moments of that level.  The kernel also writes the
-// moments of level t (the t - dt level of the next step).
+// EDF of the stored moments of that level.
+//
+// The new populations depend on the old ones only through their moments.  So
+// each launch reads the moments of level t (one to d+1 fields, not b
+// populations), writes the b populations of level t+1 and, summed from the
+// same values in registers in lattice order, the moments of level t+1: the
+// input of the next launch.  Those sums are the ones a read-back of the
+// populations would give, value for value.
 //
 // Same tiling as the MMFD kernels: EDF records of the tile plus a one-node
 // halo in LDS, then every interior node evaluates its b directions.
+
 #include "edf.h"
 
 namespace mfd {
@@ -30,13 +37,10 @@ __device__ __forceinline__ int xcd_remap_m(int bid, int nblk) {
   return x * q + min(x, r) + k;
 }
 
-// moments of the b populations at one node (lattice order)
+// moments of the b populations f[] of one node (lattice order)
 template <class L, int EQ, typename T>
-__device__ __forceinline__ void pop_moments(const T *pop, int64_t N, int64_t gi, T *m) {
+__device__ __forceinline__ void moments_of(const T *f, T *m) {
   constexpr int NF = Rec<L, EQ>::NF;
-  T f[L::Q];
-#pragma unroll
-  for (int j = 0; j < L::Q; ++j) f[j] = pop[j * N + gi];
   T s = T(0);
 #pragma unroll
   for (int j = 0; j < L::Q; ++j) s = s + f[j];
@@ -51,6 +55,14 @@ __device__ __forceinline__ void pop_moments(const T *pop, int64_t N, int64_t gi,
     }
     m[1 + a] = t;
   }
+}
+
+template <class L, int EQ, typename T>
+__device__ __forceinline__ void pop_moments(const T *pop, int64_t N, int64_t gi, T *m) {
+  T f[L::Q];
+#pragma unroll
+  for (int j = 0; j < L::Q; ++j) f[j] = pop[j * N + gi];
+  moments_of<L, EQ>(f, m);
 }
 
 // Rest-direction EDF.  binary64: g_0 of Eq. (3-3) like every direction.
@@ -77,12 +89,14 @@ __device__ __forceinline__ T g_dir(const T *r, const KC<T> &kc) {
   else return gfull<L, EQ, J>(r, kc);
 }
 
-// evaluate the b new populations of one node
+// evaluate the b new populations of one node, store them and the moments of
+// the new level
 template <class L, int EQ, bool THREE_ST, typename T, class At, class AtH>
 __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const T *hcentre,
-                                            bool three, T *pout, int64_t N, int64_t gi,
+                                            bool three, T *pout, T *mout, int64_t N, int64_t gi,
                                             const KC<T> &kc) {
-  constexpr int NR = Rec<L, EQ>::NR;
+  constexpr int NR = Rec<L, EQ>::NR, NF = Rec<L, EQ>::NF;
+  T fo[L::Q];
   static_for<L::Q>([&](auto JI) {
     constexpr int J = decltype(JI)::value;
     constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
@@ -115,11 +129,16 @@ __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const 
       }
     }
     pout[J * N + gi] = fj;
+    fo[J] = fj;
   });
+  T m[NF];
+  moments_of<L, EQ>(fo, m);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) mout[f * N + gi] = m[f];
 }
 
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
-__global__ __launch_bounds__(256) void k_mesofd_plane(const T *__restrict__ pop,
+__global__ __launch_bounds__(256) void k_mesofd_plane(const T *__restrict__ mom,
                                                       const T *__restrict__ prev_mom,
                                                       T *__restrict__ pop_out,
                                                       T *__restrict__ mom_out, int nx, int ny,
@@ -139,13 +158,8 @@ __global__ __launch_bounds__(256) void k_mesofd_plane(const T *__restrict__ pop,
     const int gx = wrapm(x0 - 1 + lx, nx), gy = wrapm(y0 - HYL + ly, ny);
     const int64_t gi = (int64_t)gy * nx + gx;
     T m[NF], r[NR];
-    pop_moments<L, EQ>(pop, N, gi, m);
-    const bool interior = lx >= 1 && lx <= TX && ly >= HYL && ly < HYL + TY &&
-                          x0 - 1 + lx < nx && y0 - HYL + ly < ny;
-    if (mom_out && interior) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) mom_out[f * N + gi] = m[f];
-    }
+    for (int f = 0; f < NF; ++f) m[f] = mom[f * N + gi];
     make_record<L, EQ>(m, r, kc);
 #pragma unroll
     for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
@@ -177,12 +191,12 @@ __global__ __launch_bounds__(256) void k_mesofd_plane(const T *__restrict__ pop,
       for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
       make_record<L, EQ>(m, hc, kc);
     }
-    mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, N, gi, kc);
+    mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, mom_out, N, gi, kc);
   }
 }
 
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
-__global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ pop,
+__global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ mom,
                                                    const T *__restrict__ prev_mom,
                                                    T *__restrict__ pop_out,
                                                    T *__restrict__ mom_out, int nx, int ny,
@@ -200,20 +214,15 @@ __global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ pop,
   const int z0 = tz * zchunk, z1 = min(nz, z0 + zchunk);
   const int64_t N = (int64_t)nx * ny * nz;
 
-  auto load_plane = [&](int z, int slot, bool write_mom) {
+  auto load_plane = [&](int z, int slot) {
     const int gz = wrapm(z, nz);
     for (int i = threadIdx.x; i < HX * HY; i += 256) {
       const int lx = i % HX, ly = i / HX;
       const int gx = wrapm(x0 - 1 + lx, nx), gy = wrapm(y0 - 1 + ly, ny);
       const int64_t gi = ((int64_t)gz * ny + gy) * nx + gx;
       T m[NF], r[NR];
-      pop_moments<L, EQ>(pop, N, gi, m);
-      const bool interior = write_mom && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY &&
-                            x0 - 1 + lx < nx && y0 - 1 + ly < ny;
-      if (mom_out && interior) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) mom_out[f * N + gi] = m[f];
-      }
+      for (int f = 0; f < NF; ++f) m[f] = mom[f * N + gi];
       make_record<L, EQ>(m, r, kc);
 #pragma unroll
       for (int k = 0; k < NR; ++k) rec[slot][k][ly][lx] = r[k];
@@ -227,11 +236,11 @@ __global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ pop,
     }
   };
 
-  load_plane(z0 - 1, 0, false);
-  load_plane(z0, 1, true);
+  load_plane(z0 - 1, 0);
+  load_plane(z0, 1);
   for (int z = z0; z < z1; ++z) {
     const int rel = z - z0;
-    load_plane(z + 1, (rel + 2) % 3, z + 1 < z1);
+    load_plane(z + 1, (rel + 2) % 3);
     __syncthreads();
     const int sm = rel % 3, s0 = (rel + 1) % 3, sp = (rel + 2) % 3;
     for (int i = threadIdx.x; i < TX * TY; i += 256) {
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ pop,
         for (int f = 0; f < NF; ++f) m[f] = prev_mom[f * N + gi];
         make_record<L, EQ>(m, hc, kc);
       }
-      mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, N, gi, kc);
+      mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop_out, mom_out, N, gi, kc);
     }
     __syncthreads();
   }
@@ -294,7 +303,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ pop, T *_
 namespace {
 
 template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
-hipError_t meso_cfg(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+hipError_t meso_cfg(const Consts &c, const Grid &g, const T *mc, const T *pm, T *po, T *mo,
                     hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
   const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
@@ -302,39 +311,39 @@ hipError_t meso_cfg(const Consts &c, const Grid &g, const T *pop, const T *pm, T
     constexpr int TX = 1024;
     const int tx = (nx + TX - 1) / TX;
     hipLaunchKernelGGL((k_mesofd_plane<L, EQ, THREE, THREE_ST, TX, 1, T>), dim3(tx), dim3(256), 0,
-                       st, pop, pm, po, mo, nx, 1, tx, tx, kc);
+                       st, mc, pm, po, mo, nx, 1, tx, tx, kc);
   } else if constexpr (L::D == 2) {
     constexpr int TX = 64, TY = EQ == kNSE ? 8 : 16;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_mesofd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty),
-                       dim3(256), 0, st, pop, pm, po, mo, nx, ny, tx, tx * ty, kc);
+                       dim3(256), 0, st, mc, pm, po, mo, nx, ny, tx, tx * ty, kc);
   } else {
     constexpr int TX = 32, TY = (THREE_ST && sizeof(T) == 8) ? 4 : 8;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     const int zc = nz >= 64 ? 32 : nz;
     const int tz = (nz + zc - 1) / zc;
     hipLaunchKernelGGL((k_mesofd_3d<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty * tz),
-                       dim3(256), 0, st, pop, pm, po, mo, nx, ny, nz, tx, ty, zc, tx * ty * tz, kc);
+                       dim3(256), 0, st, mc, pm, po, mo, nx, ny, nz, tx, ty, zc, tx * ty * tz, kc);
   }
   return hipGetLastError();
 }
 
 template <class L, int EQ, typename T>
-hipError_t meso_levels(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+hipError_t meso_levels(const Consts &c, const Grid &g, const T *mc, const T *pm, T *po, T *mo,
                        hipStream_t st) {
-  if (!c.three) return meso_cfg<L, EQ, false, false, T>(c, g, pop, pm, po, mo, st);
-  if (!c.three_stencil) return meso_cfg<L, EQ, true, false, T>(c, g, pop, pm, po, mo, st);
-  return meso_cfg<L, EQ, true, true, T>(c, g, pop, pm, po, mo, st);
+  if (!c.three) return meso_cfg<L, EQ, false, false, T>(c, g, mc, pm, po, mo, st);
+  if (!c.three_stencil) return meso_cfg<L, EQ, true, false, T>(c, g, mc, pm, po, mo, st);
+  return meso_cfg<L, EQ, true, true, T>(c, g, mc, pm, po, mo, st);
 }
 
 template <class L, typename T>
-hipError_t meso_eq(const Consts &c, const Grid &g, const T *pop, const T *pm, T *po, T *mo,
+hipError_t meso_eq(const Consts &c, const Grid &g, const T *mc, const T *pm, T *po, T *mo,
                    hipStream_t st) {
   switch (c.eq) {
-    case kLCDE: return meso_levels<L, kLCDE, T>(c, g, pop, pm, po, mo, st);
-    case kBurgers: return meso_levels<L, kBurgers, T>(c, g, pop, pm, po, mo, st);
+    case kLCDE: return meso_levels<L, kLCDE, T>(c, g, mc, pm, po, mo, st);
+    case kBurgers: return meso_levels<L, kBurgers, T>(c, g, mc, pm, po, mo, st);
     case kNSE:
-      if constexpr (L::D >= 2) return meso_levels<L, kNSE, T>(c, g, pop, pm, po, mo, st);
+      if constexpr (L::D >= 2) return meso_levels<L, kNSE, T>(c, g, mc, pm, po, mo, st);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -387,13 +396,13 @@ hipError_t mom_eq(const Consts &c, const Grid &g, const T *pop, T *mom, hipStrea
 }  // namespace
 
 template <typename T>
-hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,
+hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, const T *prev_mom,
                               T *pop_out, T *mom_out, hipStream_t st) {
   switch (c.lattice) {
-    case 1: return meso_eq<LatD1Q3, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
-    case 2: return meso_eq<LatD2Q5, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
-    case 3: return meso_eq<LatD2Q9, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
-    case 4: return meso_eq<LatD3Q19, T>(c, g, pop, prev_mom, pop_out, mom_out, st);
+    case 1: return meso_eq<LatD1Q3, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 2: return meso_eq<LatD2Q5, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 3: return meso_eq<LatD2Q9, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 4: return meso_eq<LatD3Q19, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
     default: return hipErrorInvalidValue;
   }
 }

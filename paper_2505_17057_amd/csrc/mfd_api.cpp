@@ -175,12 +175,15 @@ int Solver::step_t(int64_t nsteps) {
         io = t;
       }
     } else {
-      // MesoFD: pop[pc] (t), moments of t-dt in B[ip]; writes pop[pn] and the
-      // moments of t into B[io]; then t-dt <- t.
-      e = launch_mesofd_step<T>(consts, G, B[pc], B[ip], B[pn], B[io], stream);
+      // MesoFD: moments of t in B[ic] (those of pop[pc]) and of t-dt in
+      // B[ip]; writes pop[pn] and its moments into B[io]; then rotate.
+      e = launch_mesofd_step<T>(consts, G, B[ic], B[ip], B[pn], B[io], stream);
       if (e != hipSuccess) return hip(e, "mesofd step launch");
       std::swap(pc, pn);
-      std::swap(ip, io);
+      const int t = ip;
+      ip = ic;
+      ic = io;
+      io = t;
     }
   }
   steps_done += nsteps;
@@ -424,28 +427,33 @@ extern "C" int mfd_set_state(mfd_solver *h, int level, const void *src, int64_t 
     // phi^(-1) = phi^0 start; also the residual reference
     rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
     if (rc) return rc;
-  } else if (populations) {
-    rc = s->copy_in(s->buf[s->pc], src, bytes, on_device);
-    if (rc) return rc;
-    hipError_t e = (s->grid.precision == MFD_FP64)
-                       ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
-                                                (double *)s->buf[s->ip], s->stream)
-                       : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
-                                               (float *)s->buf[s->ip], s->stream);
-    if (e != hipSuccess) return s->hip(e, "moments launch");
-    rc = s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    if (rc) return rc;
   } else {
-    rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
-    if (rc) return rc;
-    hipError_t e = (s->grid.precision == MFD_FP64)
-                       ? launch_init_populations<double>(s->consts, s->G,
-                                                         (const double *)s->buf[s->ip],
-                                                         (double *)s->buf[s->pc], s->stream)
-                       : launch_init_populations<float>(s->consts, s->G,
-                                                        (const float *)s->buf[s->ip],
-                                                        (float *)s->buf[s->pc], s->stream);
-    if (e != hipSuccess) return s->hip(e, "init populations launch");
+    // MesoFD level t: populations pop[pc] and their moments B[ic]; level
+    // t-dt: B[ip] = the moments given (or those of the populations given).
+    hipError_t e;
+    const bool f64 = s->grid.precision == MFD_FP64;
+    if (populations) {
+      rc = s->copy_in(s->buf[s->pc], src, bytes, on_device);
+      if (rc) return rc;
+      e = f64 ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
+                                       (double *)s->buf[s->ip], s->stream)
+              : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
+                                      (float *)s->buf[s->ip], s->stream);
+      if (e != hipSuccess) return s->hip(e, "moments launch");
+    } else {
+      rc = s->copy_in(s->buf[s->ip], src, bytes, on_device);
+      if (rc) return rc;
+      e = f64 ? launch_init_populations<double>(s->consts, s->G, (const double *)s->buf[s->ip],
+                                                (double *)s->buf[s->pc], s->stream)
+              : launch_init_populations<float>(s->consts, s->G, (const float *)s->buf[s->ip],
+                                               (float *)s->buf[s->pc], s->stream);
+      if (e != hipSuccess) return s->hip(e, "init populations launch");
+    }
+    e = f64 ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
+                                     (double *)s->buf[s->ic], s->stream)
+            : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
+                                    (float *)s->buf[s->ic], s->stream);
+    if (e != hipSuccess) return s->hip(e, "moments launch");
     rc = s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     if (rc) return rc;
   }
@@ -471,16 +479,10 @@ extern "C" int mfd_get_state(mfd_solver *h, int level, void *dst, int64_t bytes,
   if (bytes != want)
     return s->fail(MFD_E_ARG, "expected %lld bytes, got %lld", (long long)want, (long long)bytes);
   if (level == 1) return s->copy_out(dst, s->buf[s->ip], bytes, on_device);
-  if (!meso) return s->copy_out(dst, s->buf[s->ic], bytes, on_device);
   if (populations) return s->copy_out(dst, s->buf[s->pc], bytes, on_device);
-  // moments of the current populations into the spare moment buffer
-  hipError_t e = (s->grid.precision == MFD_FP64)
-                     ? launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
-                                              (double *)s->buf[s->io], s->stream)
-                     : launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
-                                             (float *)s->buf[s->io], s->stream);
-  if (e != hipSuccess) return s->hip(e, "moments launch");
-  return s->copy_out(dst, s->buf[s->io], bytes, on_device);
+  // MMFD state, or the moments of the current MesoFD populations (kept
+  // beside them by every step)
+  return s->copy_out(dst, s->buf[s->ic], bytes, on_device);
 }
 
 extern "C" int mfd_step(mfd_solver *h, int64_t nsteps) {
@@ -501,28 +503,15 @@ extern "C" int mfd_reduce(mfd_solver *h, double sums[4], double *residual) {
   if (!s->state_set) return s->fail(MFD_E_ORDER, "state not set");
   double *part = (double *)s->buf[Solver::kRedBuf];
   double *out = part + kReduceBlocks * 8;
-  const bool meso = s->grid.form == MFD_MESOFD;
   const bool have_prev = s->steps_done > 0;
   hipError_t e;
   if (s->grid.precision == MFD_FP64) {
     const double *cur = (const double *)s->buf[s->ic];
     const double *prev = have_prev ? (const double *)s->buf[s->ip] : nullptr;
-    if (meso) {
-      e = launch_moments<double>(s->consts, s->G, (const double *)s->buf[s->pc],
-                                 (double *)s->buf[s->io], s->stream);
-      if (e != hipSuccess) return s->hip(e, "moments launch");
-      cur = (const double *)s->buf[s->io];
-    }
     e = launch_reduce<double>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
   } else {
     const float *cur = (const float *)s->buf[s->ic];
     const float *prev = have_prev ? (const float *)s->buf[s->ip] : nullptr;
-    if (meso) {
-      e = launch_moments<float>(s->consts, s->G, (const float *)s->buf[s->pc],
-                                (float *)s->buf[s->io], s->stream);
-      if (e != hipSuccess) return s->hip(e, "moments launch");
-      cur = (const float *)s->buf[s->io];
-    }
     e = launch_reduce<float>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
   }
   if (e != hipSuccess) return s->hip(e, "reduce launch");

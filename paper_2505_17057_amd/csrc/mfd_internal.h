@@ -123,8 +123,10 @@ template <typename T>
 hipError_t launch_lcde_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 
+// MesoFD step: moments of level t (mom) and t-dt (prev_mom) in; populations
+// and moments of level t+1 out.
 template <typename T>
-hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *pop, const T *prev_mom,
+hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, const T *prev_mom,
                               T *pop_out, T *mom_out, hipStream_t st);
 
 template <typename T>
