@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    p.add_argument("--sections", default="variants,big,c1,nse,burgers,batched,serving",
+                   help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
     p.add_argument("--serve-requests", type=int, default=300)
@@ -230,6 +232,26 @@ def bench_nse(M, torch, I, stream):
     return res
 
 
+def bench_burgers_single(M, torch, I, stream):
+    """One 2048^2 Burgers grid (the batched workload's recipe at its largest
+    side class), FP32 MMFD, 1000 steps."""
+    rng = np.random.default_rng(6)
+    c = I.burgers_instance(rng, side_lo=2048, side_hi=2048, steps_lo=1000, steps_hi=1000)
+    s = M.Solver("D2Q9", c["n"], c["dx"], "fp32", "mmfd")
+    s.set_equation("burgers")
+    s.set_scheme("two_level", two_level_a(M, c["nu"], c["dx"], c["dt"]), dt=c["dt"])
+    s.set_stream(stream.cuda_stream)
+    s.set_state(c["phi0"].astype(np.float32))
+    s.autotune()
+    tb, h = s.launch_plan()
+    s.step(50)
+    ms = timed(torch, lambda: s.step(1000))
+    s.close()
+    g = 2048 * 2048 * 1000 / (ms * 1e-3) / 1e9
+    return dict(glups=round(g, 2), alg_gbs=round(g * 8, 1), frac_hbm=round(g * 8 / HBM_PEAK_GBS, 4),
+                bytes_per_lup=8, time_steps_per_launch=tb, window_rows=h)
+
+
 def bench_batched(M, torch, I, stream):
     insts = I.c4_batch(256, seed=4)
     lups = sum(int(np.prod(c["n"])) * c["steps"] for c in insts)
@@ -247,6 +269,9 @@ def bench_batched(M, torch, I, stream):
     for s, c in zip(s32, insts):
         b.add(s, c["steps"])
     t0 = time.perf_counter()
+    b.autotune()  # launch plan of the group (steps per launch, window rows)
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     b.run()
     b.wait()
     first_s = time.perf_counter() - t0  # includes graph capture + instantiation
@@ -254,8 +279,11 @@ def bench_batched(M, torch, I, stream):
         s.set_state(c["phi0"].astype(np.float32))
     ms32 = timed(torch, lambda: b.run())
     st = b.stats()
+    plan = b.plan(0)
     # plain per-instance FP64 stepping: one launch per step per instance
     s64 = [make(c, "fp64") for c in insts]
+    for s in s64:
+        s.set_blocking(1)
     ms64 = timed(torch, lambda: [s.step(c["steps"]) for s, c in zip(s64, insts)])
     errs, errs0, decay = [], [], []
     for a32, a64, c in zip(s32, s64, insts):
@@ -272,6 +300,8 @@ def bench_batched(M, torch, I, stream):
     g32 = lups / (ms32 * 1e-3) / 1e9
     g64 = lups / (ms64 * 1e-3) / 1e9
     return dict(instances=len(insts), lups=lups, graph_launches=st["launches"], tiles=st["tiles"],
+                plan=dict(time_steps_per_launch=plan[0], window_rows=plan[1]),
+                autotune_s=round(tune_s, 3),
                 fp32_graph_ms=round(ms32, 2), fp32_glups=round(g32, 2),
                 fp32_first_run_incl_capture_s=round(first_s, 3),
                 fp64_per_instance_ms=round(ms64, 2), fp64_glups=round(g64, 2),
@@ -395,18 +425,27 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         extra["copy_calibration_bytes"] = x.numel() * 4  # read once and written once
-    if not args.quick:
+    sections = set() if args.quick else set(x for x in args.sections.split(",") if x)
+    if "variants" in sections:
         log("variants")
         extra["variants"], extra["fp32_rel_l2_vs_fp64_after_10000"], extra["mesofd_vs_mmfd_fp64_max_abs"] = \
             bench_variants(M, torch, cfg, stream, N)
+    if "big" in sections:
         log("8192^2")
         extra["hbm_resident_8192_mmfd_fp32"] = bench_big(M, torch, I, stream)
+    if "c1" in sections:
         log("1D")
         extra["c1_d1q3_1024"] = bench_c1(M, torch, I, stream)
+    if "nse" in sections:
         log("NSE")
         extra["nse"] = bench_nse(M, torch, I, stream)
+    if "burgers" in sections:
+        log("burgers 2048^2")
+        extra["burgers_2048_mmfd_fp32"] = bench_burgers_single(M, torch, I, stream)
+    if "batched" in sections:
         log("batched")
         extra["batched_256_burgers"] = bench_batched(M, torch, I, stream)
+    if "serving" in sections:
         log("serving")
         extra["serving"] = bench_serving(M, I, args.serve_requests)
 

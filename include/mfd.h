@@ -200,8 +200,9 @@ int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
 int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
 
 /* Force a temporal-blocking depth (1 = none; 0 = automatic).  Blocking is
- * implemented for the MMFD form of the LCDE on D2Q5 / D2Q9 grids of at least
- * 64 x (2 depth + 4) nodes; MFD_E_UNSUPPORTED for other configured solvers. */
+ * implemented for the MMFD form of the linear CDE and Burgers' equation on
+ * D2Q5 / D2Q9 grids of at least 64 x (2 depth + 4) nodes (depth <= 16, window
+ * LDS <= 160 KiB); MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
 /* The launch plan mfd_step uses now: *tb_depth time steps per launch of the
@@ -213,12 +214,14 @@ int mfd_launch_plan(const mfd_solver *s, int32_t *tb_depth, int32_t *window_rows
 /* ---------------------------------------------------------------- batches */
 
 /* A batch advances many solvers (independent periodic grids of any sizes,
- * coefficients and step counts) together: each time step of all solvers of
- * one kind (lattice, equation, levels, precision) is one kernel launch over
- * the tiles of the solvers still running, and the whole step sequence is
- * captured once into a hipGraph and replayed by every mfd_batch_run.  Each
- * solver's result equals the one of stepping it alone (same kernels, same
- * arithmetic).  Only 2D explicit MMFD solvers (D2Q5, D2Q9) can be batched.
+ * coefficients and step counts) together: the solvers of one kind (lattice,
+ * equation, levels, precision) form a group, each time step of a group is one
+ * kernel launch over the tiles of the solvers still running (or, under a
+ * temporally blocked plan, each launch advances every running solver by up to
+ * tb steps), and the whole launch sequence is captured once into a hipGraph
+ * and replayed by every mfd_batch_run.  Each solver's result equals the one
+ * of stepping it alone (the same node update, value for value).  Only 2D
+ * explicit MMFD solvers (D2Q5, D2Q9) can be batched.
  * A batch references its solvers: they must outlive it, must not be
  * stepped by other calls while a run is in flight, and their own streams
  * must be idle when a run is enqueued. */
@@ -252,6 +255,26 @@ int mfd_batch_wait(mfd_batch *b);
 
 /* Kernel launches per run, lattice-node updates per run, tiles. */
 int mfd_batch_stats(const mfd_batch *b, int64_t *launches, int64_t *lups, int64_t *tiles);
+
+/* Launch plan of the groups that can be temporally blocked (two-level linear
+ * CDE and Burgers groups; others always take one launch per step):
+ * tb_depth = 1 one launch per step, tb_depth > 1 up to tb_depth steps per
+ * launch over windows of 64 x window_rows nodes, 0 automatic (the plan chosen
+ * by mfd_batch_autotune, else one launch per step).  Any grid size can be
+ * blocked in a batch (the window wraps periodically).  MFD_E_ARG for a plan
+ * beyond the kernel's limits: depth <= 16, 64 - 2 depth >= 8,
+ * window_rows >= 2 depth + 4, two window levels within 160 KiB of LDS. */
+int mfd_batch_set_plan(mfd_batch *b, int32_t tb_depth, int32_t window_rows);
+
+/* Pick the plan of every blockable group by timing each candidate's first
+ * launch over all the group's instances (their current states; the spare
+ * level each trial overwrites is restored).  Synchronous; the choice holds
+ * for later runs of groups of the same kind. */
+int mfd_batch_autotune(mfd_batch *b);
+
+/* Plan of group `group` (groups in a fixed order of kind) after the last
+ * run or autotune. */
+int mfd_batch_plan(const mfd_batch *b, int32_t group, int32_t *tb_depth, int32_t *window_rows);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -27,8 +27,7 @@ Key key_of(const Solver &s) {
 }
 
 bool tunable(const Solver &s) {
-  return s.grid.form == MFD_MMFD && s.cfg.kind != MFD_THETA && s.consts.eq == kLCDE &&
-         s.consts.dim == 2 && (s.consts.lattice == MFD_D2Q5 || s.consts.lattice == MFD_D2Q9);
+  return s.grid.form == MFD_MMFD && s.cfg.kind != MFD_THETA && tb_equation_supported(s.consts);
 }
 
 // default window height for a requested depth: the tallest window whose
@@ -37,8 +36,8 @@ int default_h(const Solver &s, int tb) {
   static const int hs[] = {96, 80, 64, 48, 32};
   for (int h : hs) {
     const TbPlan p{tb, h};
-    if (lcde_tb_lds_bytes(s.consts, h, (int)s.elem()) * 3 <= 160 * 1024 &&
-        lcde_tb_supported(s.consts, s.G, p, (int)s.elem()))
+    if (tb_lds_bytes(s.consts, h, (int)s.elem()) * 3 <= 160 * 1024 &&
+        tb_supported(s.consts, s.G, p, (int)s.elem()))
       return h;
   }
   return 0;
@@ -112,7 +111,7 @@ int Solver::autotune(int32_t *chosen) {
       if (rc) break;
       TbPlan p{d, d == 1 ? 0 : h};
       if (d == 1 && h != heights[0]) continue;
-      if (d > 1 && !lcde_tb_supported(consts, G, p, (int)elem())) continue;
+      if (d > 1 && !tb_supported(consts, G, p, (int)elem())) continue;
       tb = d;
       tuned = p;
       rc = step(trial);  // warm-up

@@ -52,6 +52,50 @@ void Batch::free_groups() {
 
 static int tile_ty(int eq) { return eq == kNSE ? kBatchTYNse : kBatchTY; }
 
+static int elem_of(const BatchKey &k) { return k.precision == MFD_FP64 ? 8 : 4; }
+
+// tile shape of a group under its plan
+static void tile_shape(const Group &g, int *tx, int *ty) {
+  if (g.plan.tb > 1) {
+    *tx = tb_window_cols() - 2 * g.plan.tb;
+    *ty = g.plan.h - 2 * g.plan.tb;
+  } else {
+    *tx = kBatchTX;
+    *ty = tile_ty(g.key.eq);
+  }
+}
+
+// tile table of a group for its current plan (host and device)
+int Batch::make_tables(Group &g) {
+  int TX, TY;
+  tile_shape(g, &TX, &TY);
+  std::vector<int> tile_inst;
+  g.tile0.clear();
+  g.tiles_x.clear();
+  for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+    const Solver *s = entries[g.order[slot]].s;
+    const int tx = (int)((s->G.n[0] + TX - 1) / TX);
+    const int tyc = (int)((s->G.n[1] + TY - 1) / TY);
+    g.tile0.push_back((int)tile_inst.size());
+    g.tiles_x.push_back(tx);
+    for (int k = 0; k < tx * tyc; ++k) tile_inst.push_back(slot);
+  }
+  g.ntiles = (int)tile_inst.size();
+  if (g.ntiles > g.tile_cap) {
+    if (g.d_tile_inst) (void)hipFree(g.d_tile_inst);
+    g.d_tile_inst = nullptr;
+    g.tile_cap = 0;
+    int rc = hip(hipMalloc((void **)&g.d_tile_inst, sizeof(int) * (size_t)g.ntiles), "hipMalloc (tiles)");
+    if (rc) return rc;
+    g.tile_cap = g.ntiles;
+  }
+  if (g.ntiles)
+    return hip(hipMemcpyAsync(g.d_tile_inst, tile_inst.data(), sizeof(int) * g.ntiles,
+                              hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync (tiles)");
+  return MFD_OK;
+}
+
 int Batch::build() {
   free_graph();
   free_groups();
@@ -64,46 +108,37 @@ int Batch::build() {
   for (int i = 0; i < (int)entries.size(); ++i) {
     Solver *s = entries[i].s;
     BatchKey k{s->consts.lattice, s->consts.eq, s->consts.three, s->consts.three_stencil,
-               s->grid.precision};
+               s->grid.precision, s->consts.eq == kBurgers && s->consts.beta_one ? 1 : 0};
     by_key[k].push_back(i);
   }
   max_steps = 0;
   lups_per_run = 0;
   for (auto &kv : by_key) {
-    Group g;
+    groups.emplace_back();
+    Group &g = groups.back();
     g.key = kv.first;
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(),
                      [&](int a, int b) { return entries[a].nsteps > entries[b].nsteps; });
-    const int ty = tile_ty(g.key.eq);
-    std::vector<int> tile_inst;
-    for (int slot = 0; slot < (int)g.order.size(); ++slot) {
-      const Solver *s = entries[g.order[slot]].s;
-      const int tx = (int)((s->G.n[0] + kBatchTX - 1) / kBatchTX);
-      const int tyc = (int)((s->G.n[1] + ty - 1) / ty);
-      g.tile0.push_back((int)tile_inst.size());
-      g.tiles_x.push_back(tx);
-      for (int k = 0; k < tx * tyc; ++k) tile_inst.push_back(slot);
-      g.steps.push_back(entries[g.order[slot]].nsteps);
-      max_steps = std::max(max_steps, entries[g.order[slot]].nsteps);
-      lups_per_run += s->G.N * entries[g.order[slot]].nsteps;
+    g.tb_ok = !g.key.three && tb_equation_supported(entries[g.order[0]].s->consts);
+    if (g.tb_ok) {
+      auto it = tuned.find(g.key);
+      if (req.tb > 0) g.plan = req;
+      else if (it != tuned.end()) g.plan = it->second;
+      if (g.plan.tb > 1 && !tb_plan_valid(g.plan, 2, elem_of(g.key))) g.plan = TbPlan{1, 0};
     }
-    g.ntiles = (int)tile_inst.size();
+    for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+      const BatchEntry &e = entries[g.order[slot]];
+      g.steps.push_back(e.nsteps);
+      max_steps = std::max(max_steps, e.nsteps);
+      lups_per_run += e.s->G.N * e.nsteps;
+    }
     const size_t isz = g.key.precision == MFD_FP64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
     g.inst_bytes = isz * g.order.size();
     int rc = hip(hipMalloc(&g.d_inst, g.inst_bytes), "hipMalloc (instances)");
-    if (!rc) rc = hip(hipMalloc((void **)&g.d_tile_inst, sizeof(int) * std::max(1, g.ntiles)),
-                      "hipMalloc (tiles)");
-    if (!rc && g.ntiles)
-      rc = hip(hipMemcpyAsync(g.d_tile_inst, tile_inst.data(), sizeof(int) * g.ntiles,
-                              hipMemcpyHostToDevice, stream),
-               "hipMemcpyAsync (tiles)");
-    if (rc) {
-      groups.push_back(g);
-      return rc;
-    }
+    if (!rc) rc = make_tables(g);
+    if (rc) return rc;
     g.h_inst.resize(g.inst_bytes);
-    groups.push_back(std::move(g));
   }
   return hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
 }
@@ -119,8 +154,26 @@ static int active_tiles(const Group &g, int64_t s) {
 
 int Batch::enqueue_steps() {
   launches_per_run = 0;
-  for (int64_t s = 0; s < max_steps; ++s) {
-    for (auto &g : groups) {
+  for (auto &g : groups) {
+    const int64_t gmax = g.steps.empty() ? 0 : g.steps[0];
+    if (g.plan.tb > 1) {
+      const int64_t nl = (gmax + g.plan.tb - 1) / g.plan.tb;
+      for (int64_t l = 0; l < nl; ++l) {
+        const int nt = active_tiles(g, l * g.plan.tb);
+        if (nt == 0) continue;
+        hipError_t e;
+        if (g.key.precision == MFD_FP64)
+          e = launch_batch_tb<double>(g.key, (const BatchInst<double> *)g.d_inst, g.d_tile_inst, nt,
+                                      l, g.plan, stream);
+        else
+          e = launch_batch_tb<float>(g.key, (const BatchInst<float> *)g.d_inst, g.d_tile_inst, nt,
+                                     l, g.plan, stream);
+        if (e != hipSuccess) return hip(e, "blocked batch launch");
+        ++launches_per_run;
+      }
+      continue;
+    }
+    for (int64_t s = 0; s < gmax; ++s) {
       const int nt = active_tiles(g, s);
       if (nt == 0) continue;
       hipError_t e;
@@ -160,32 +213,44 @@ static void fill_inst(const Group &g, const std::vector<BatchEntry> &entries,
     b.c0 = 0;
     b.tiles_x = g.tiles_x[slot];
     b.tile0 = g.tile0[slot];
+    b.nsteps = g.steps[slot];
     b.kc = make_kc<T>(s->consts);
     bi[slot] = b;
   }
 }
 
+int Batch::upload_instances() {
+  for (auto &g : groups) {
+    if (g.key.precision == MFD_FP64) fill_inst<double>(g, entries, g.h_inst);
+    else fill_inst<float>(g, entries, g.h_inst);
+    int rc = hip(hipMemcpyAsync(g.d_inst, g.h_inst.data(), g.inst_bytes, hipMemcpyHostToDevice, stream),
+                 "hipMemcpyAsync (instances)");
+    if (rc) return rc;
+  }
+  return MFD_OK;
+}
+
+static int check_ready(Batch &b) {
+  for (auto &e : b.entries) {
+    Solver *s = e.s;
+    if (s->sticky || !s->state_set || !s->configured)
+      return b.fail(MFD_E_ORDER, "a batched solver is not ready (configure it and set its state)");
+  }
+  return MFD_OK;
+}
+
 int Batch::run() {
   if (sticky) return fail(MFD_E_HIP, "batch is in a failed HIP state");
   if (entries.empty()) return MFD_OK;
-  for (auto &e : entries) {
-    Solver *s = e.s;
-    if (s->sticky || !s->state_set || !s->configured)
-      return fail(MFD_E_ORDER, "a batched solver is not ready (configure it and set its state)");
-  }
-  int rc;
+  int rc = check_ready(*this);
+  if (rc) return rc;
   if (dirty) {
     rc = build();
     if (rc) return rc;
   }
   // instance tables from the solvers' current level roles
-  for (auto &g : groups) {
-    if (g.key.precision == MFD_FP64) fill_inst<double>(g, entries, g.h_inst);
-    else fill_inst<float>(g, entries, g.h_inst);
-    rc = hip(hipMemcpyAsync(g.d_inst, g.h_inst.data(), g.inst_bytes, hipMemcpyHostToDevice, stream),
-             "hipMemcpyAsync (instances)");
-    if (rc) return rc;
-  }
+  rc = upload_instances();
+  if (rc) return rc;
   if (use_graph) {
     if (dirty || !exec) {
       free_graph();
@@ -211,6 +276,8 @@ int Batch::run() {
     if (rc) return rc;
   }
   dirty = false;
+  for (auto &g : groups)
+    for (int i : g.order) entries[i].tb = g.plan.tb;
   // hand the rotated level roles back to the solvers
   for (auto &e : entries) {
     Solver *s = e.s;
@@ -221,15 +288,127 @@ int Batch::run() {
       s->ic = ring[n % 3];
       s->io = ring[(n + 1) % 3];
       s->ip = ring[(n + 2) % 3];
+      s->prev_gap = 1;
+    } else if (e.tb > 1) {
+      // one ping-pong swap per blocked launch; the last launch advanced the
+      // remainder, so the held previous level is that many steps old
+      const int64_t nl = (n + e.tb - 1) / e.tb;
+      const int ring[2] = {s->ic, s->ip};
+      s->ic = ring[nl % 2];
+      s->ip = ring[(nl + 1) % 2];
+      s->prev_gap = (int)(n - (nl - 1) * e.tb);
     } else {
       const int ring[2] = {s->ic, s->ip};
       s->ic = ring[n % 2];
       s->ip = ring[(n + 1) % 2];
+      s->prev_gap = 1;
     }
     s->steps_done += n;
-    s->prev_gap = 1;
   }
   return MFD_OK;
+}
+
+// Batch autotuner: for every group that can use the blocked kernel, time one
+// launch of each candidate plan over all its instances (the first launch of a
+// run: it reads each instance's level t and overwrites only its spare level,
+// so repeating it is harmless), keep the fastest per node update, and restore
+// the spare levels afterwards.
+int Batch::autotune() {
+  if (sticky) return fail(MFD_E_HIP, "batch is in a failed HIP state");
+  if (entries.empty()) return MFD_OK;
+  int rc = check_ready(*this);
+  if (rc) return rc;
+  const TbPlan saved_req = req;
+  req = TbPlan{0, 0};
+  rc = build();
+  if (rc) {
+    req = saved_req;
+    return rc;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rc = hip(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = hip(hipEventCreate(&e1), "hipEventCreate");
+  for (auto &g : groups) {
+    if (rc) break;
+    if (!g.tb_ok) continue;
+    const int es = elem_of(g.key);
+    // save the spare level of every instance
+    int64_t total = 0;
+    for (int i : g.order) total += entries[i].s->mom_elems();
+    void *save = nullptr;
+    rc = hip(hipMalloc(&save, (size_t)total * es), "hipMalloc (autotune copy)");
+    if (rc) break;
+    int64_t off = 0;
+    for (int i : g.order) {
+      Solver *s = entries[i].s;
+      const size_t b = (size_t)s->mom_elems() * es;
+      if (!rc) rc = hip(hipMemcpyAsync((char *)save + off, s->buf[s->ip], b, hipMemcpyDeviceToDevice, stream),
+                        "hipMemcpyAsync (save)");
+      off += (int64_t)b;
+    }
+    std::vector<TbPlan> cands{TbPlan{1, 0}};
+    for (int d : {2, 4, 6, 8})
+      for (int h : {32, 48, 64, 96, 128})
+        if (tb_plan_valid(TbPlan{d, h}, 2, es)) cands.push_back(TbPlan{d, h});
+    float best = 1e30f;
+    TbPlan best_p{1, 0};
+    for (const TbPlan &p : cands) {
+      if (rc) break;
+      g.plan = p;
+      rc = make_tables(g);
+      if (!rc) rc = upload_instances();
+      if (rc) break;
+      double lups = 0;
+      for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+        const int64_t n = std::min<int64_t>(g.steps[slot], p.tb);
+        lups += (double)entries[g.order[slot]].s->G.N * (double)n;
+      }
+      const int nt = active_tiles(g, 0);
+      if (nt == 0 || lups == 0) continue;
+      auto launch = [&]() -> hipError_t {
+        if (p.tb > 1)
+          return g.key.precision == MFD_FP64
+                     ? launch_batch_tb<double>(g.key, (const BatchInst<double> *)g.d_inst,
+                                               g.d_tile_inst, nt, 0, p, stream)
+                     : launch_batch_tb<float>(g.key, (const BatchInst<float> *)g.d_inst,
+                                              g.d_tile_inst, nt, 0, p, stream);
+        return g.key.precision == MFD_FP64
+                   ? launch_batch_step<double>(g.key, (const BatchInst<double> *)g.d_inst,
+                                               g.d_tile_inst, nt, 0, stream)
+                   : launch_batch_step<float>(g.key, (const BatchInst<float> *)g.d_inst,
+                                              g.d_tile_inst, nt, 0, stream);
+      };
+      rc = hip(launch(), "autotune launch");
+      if (!rc) rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
+      for (int k = 0; k < 3 && !rc; ++k) rc = hip(launch(), "autotune launch");
+      if (!rc) rc = hip(hipEventRecord(e1, stream), "hipEventRecord");
+      if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      const float per = (float)(ms / (3.0 * lups));
+      if (!rc && per < best) {
+        best = per;
+        best_p = p;
+      }
+    }
+    // restore the spare levels
+    off = 0;
+    for (int i : g.order) {
+      Solver *s = entries[i].s;
+      const size_t b = (size_t)s->mom_elems() * es;
+      if (!rc) rc = hip(hipMemcpyAsync(s->buf[s->ip], (char *)save + off, b, hipMemcpyDeviceToDevice, stream),
+                        "hipMemcpyAsync (restore)");
+      off += (int64_t)b;
+    }
+    if (!rc) rc = hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    (void)hipFree(save);
+    if (!rc) tuned[g.key] = best_p;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  req = saved_req;
+  dirty = true;
+  return rc;
 }
 
 }  // namespace mfd
@@ -313,6 +492,34 @@ extern "C" int mfd_batch_wait(mfd_batch *h) {
   Batch *b = reinterpret_cast<Batch *>(h);
   if (!b->stream) return MFD_OK;
   return b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+}
+
+extern "C" int mfd_batch_set_plan(mfd_batch *h, int32_t tb_depth, int32_t window_rows) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  if (tb_depth < 0) return b->fail(MFD_E_ARG, "negative depth");
+  if (tb_depth > 1 && !tb_plan_valid(TbPlan{tb_depth, window_rows}, 2, 8) &&
+      !tb_plan_valid(TbPlan{tb_depth, window_rows}, 2, 4))
+    return b->fail(MFD_E_ARG, "plan (%d, %d) exceeds the blocked kernel's limits", tb_depth,
+                   window_rows);
+  b->req = TbPlan{tb_depth, tb_depth > 1 ? window_rows : 0};
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_autotune(mfd_batch *h) {
+  if (!h) return MFD_E_ARG;
+  return reinterpret_cast<Batch *>(h)->autotune();
+}
+
+extern "C" int mfd_batch_plan(const mfd_batch *h, int32_t group, int32_t *tb_depth,
+                              int32_t *window_rows) {
+  if (!h) return MFD_E_ARG;
+  const Batch *b = reinterpret_cast<const Batch *>(h);
+  if (group < 0 || group >= (int32_t)b->groups.size()) return MFD_E_ARG;
+  if (tb_depth) *tb_depth = b->groups[group].plan.tb;
+  if (window_rows) *window_rows = b->groups[group].plan.h;
+  return MFD_OK;
 }
 
 extern "C" int mfd_batch_stats(const mfd_batch *h, int64_t *launches, int64_t *lups,

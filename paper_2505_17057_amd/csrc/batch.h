@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -14,17 +15,20 @@ namespace mfd {
 struct BatchEntry {
   Solver *s;
   int64_t nsteps;
+  int tb = 1;  // steps per launch of its group in the last run
 };
 
 struct Group {
   BatchKey key{};
+  bool tb_ok = false;           // two-level LCDE / Burgers: blocked kernel usable
+  TbPlan plan{1, 0};            // tb = 1: one launch per step (k_batch_step)
   std::vector<int> order;       // entry indices, decreasing step count
   std::vector<int> tile0;       // first tile of each instance (sorted order)
   std::vector<int> tiles_x;
   std::vector<int64_t> steps;   // step count of each instance (sorted order)
-  int ntiles = 0;
+  int ntiles = 0, tile_cap = 0;
   void *d_inst = nullptr;       // BatchInst<T>[instances]
-  int *d_tile_inst = nullptr;   // instance slot of every tile
+  int *d_tile_inst = nullptr;   // instance slot of every tile (capacity tile_cap)
   size_t inst_bytes = 0;
   std::vector<unsigned char> h_inst;
 };
@@ -36,6 +40,8 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = true, dirty = true, sticky = false;
+  TbPlan req{0, 0};                     // plan set by the caller (tb = 0: automatic)
+  std::map<BatchKey, TbPlan> tuned;     // plans chosen by autotune()
   int64_t max_steps = 0, launches_per_run = 0, lups_per_run = 0;
   std::string err;
 
@@ -44,8 +50,11 @@ struct Batch {
   void free_graph();
   void free_groups();
   int build();
+  int make_tables(Group &g);
+  int upload_instances();
   int enqueue_steps();
   int run();
+  int autotune();
 };
 
 }  // namespace mfd

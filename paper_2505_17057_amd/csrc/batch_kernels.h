@@ -16,13 +16,16 @@ struct BatchInst {
   int c0;         // ring index of level t at the first step of the run
   int tiles_x;
   int tile0;      // first tile of this instance in the group's tile table
+  int64_t nsteps; // steps of this instance in the run
   KC<T> kc;       // the instance's step constants
 };
 
 // what selects the kernel of a group
 struct BatchKey {
   int lattice, eq, three, three_st, precision;
+  int b1;  // Burgers with beta = 1 (no quadratic EDF term)
   bool operator<(const BatchKey &o) const {
+    if (b1 != o.b1) return b1 < o.b1;
     if (lattice != o.lattice) return lattice < o.lattice;
     if (eq != o.eq) return eq < o.eq;
     if (three != o.three) return three < o.three;
@@ -34,5 +37,10 @@ struct BatchKey {
 template <typename T>
 hipError_t launch_batch_step(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                              int ntiles, int64_t s, hipStream_t st);
+
+// temporally blocked batched launch `launch` (two-level LCDE / Burgers groups)
+template <typename T>
+hipError_t launch_batch_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
+                           int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
 
 }  // namespace mfd

@@ -111,12 +111,16 @@ __device__ __forceinline__ T edotB(const T *r) {
   return s;
 }
 
-// even pair part F+ of direction J (nonlinear EDFs)
-template <class L, int EQ, int J, typename T>
+// even pair part F+ of direction J (nonlinear EDFs).  B1: the caller knows
+// that beta = 1 (Burgers), so the quadratic term, which is then absent, is
+// not even tested for.
+template <class L, int EQ, int J, bool B1 = false, typename T>
 __device__ __forceinline__ T fplus(const T *r, const KC<T> &kc) {
   T t = r[0];
   if constexpr (EQ == kBurgers) {
-    if (!kc.beta_one) t = t + quad<L, EQ, J>(r, kc);
+    if constexpr (!B1) {
+      if (!kc.beta_one) t = t + quad<L, EQ, J>(r, kc);
+    }
   } else {
     t = t + quad<L, EQ, J>(r, kc);
   }

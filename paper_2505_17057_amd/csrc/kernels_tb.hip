@@ -1,18 +1,26 @@
-// Temporally blocked MMFD kernel for the linear CDE on 2D lattices
-// (D2Q5, D2Q9): one launch advances TB time steps.
+// Temporally blocked MMFD kernels for the two-level / three-level scheme on
+// 2D lattices (D2Q5, D2Q9) for the linear CDE and Burgers' equation: one
+// launch advances several time steps.
 //
-// A workgroup loads a (TX + 2 TB) x (TY + 2 TB) window of level t (and t-dt
-// for three-level schemes) into LDS, then performs TB updates in LDS, each on
-// a region one node smaller on every side (the stencil reaches one node), and
-// finally stores the TX x TY interior of the last level (and of the level
-// before it, which the next three-level launch needs).  Every node update is
-// the same expression as the single-step kernel (mmfd_node), so results are
-// bitwise independent of TB.
+// A workgroup loads a W x H window of level t (and t-dt for three-level
+// schemes) into LDS, then performs TB updates in LDS, each on a region one
+// node smaller on every side (the stencil reaches one node), and finally
+// stores the (W - 2 TB) x (H - 2 TB) interior of the last level (and of the
+// level before it, which the next three-level launch needs).  Every node
+// update is the same expression as the single-step kernel (mmfd_node), so
+// results are bitwise independent of TB.
 //
 // Inside a step each thread owns one column of the window (a 64-wide
 // wavefront reads one LDS row: no bank conflicts) and a contiguous segment of
 // rows, and slides a 3 x 3 register window down it: 3 LDS reads per node
-// instead of 9.  The window loads are all issued before the first LDS store.
+// instead of 9.  For Burgers' equation the window also carries the second
+// record field phi^2 dt/(2 dx), formed from phi as each row enters.  The
+// window loads are all issued before the first LDS store.
+//
+// The batched kernel runs the same window body for every tile of a table of
+// independent grids; each instance advances min(TB, its remaining steps) in a
+// window sized for TB.
+#include "batch_kernels.h"
 #include "mmfd_node.h"
 
 namespace mfd {
@@ -23,26 +31,21 @@ __device__ __forceinline__ int xcd_remap_tb(int bid, int nblk) {
   return x * q + min(x, r) + k;
 }
 
-template <class L, bool THREE, bool THREE_ST, int W, int RG, typename T>
-__global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
-                                                  const T *__restrict__ prev,
-                                                  T *__restrict__ out_cur,
-                                                  T *__restrict__ out_prev, int nx, int ny,
-                                                  int H, int TB, int tiles_x, int ntiles,
-                                                  KC<T> kc) {
+// Window whose origin is (x0, y0) (global, may be negative): load, TBS steps,
+// store of the interior that starts TBW nodes in.  WRAP_ANY: grids of any
+// size (modular wrap); otherwise nx >= W and ny >= H (one conditional wrap).
+template <class L, int EQ, bool THREE, bool THREE_ST, int W, int RG, bool WRAP_ANY, bool B1,
+          typename T>
+__device__ __forceinline__ void tb_window(const T *__restrict__ cur, const T *__restrict__ prev,
+                                          T *__restrict__ out_cur, T *__restrict__ out_prev,
+                                          int nx, int ny, int H, int TBW, int TBS, int x0, int y0,
+                                          const KC<T> &kc, T *lds) {
   constexpr int NT = W * RG;
-  constexpr int NB = THREE ? 3 : 2;
   constexpr int KB = 8;  // window loads in flight per thread
-  extern __shared__ unsigned char smem_tb[];
-  T *lds = reinterpret_cast<T *>(smem_tb);  // [NB][H][W]
-  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  constexpr bool BURG = EQ == kBurgers;
   const int WH = W * H;
 
-  const int tile = xcd_remap_tb(blockIdx.x, ntiles);
-  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
-
-  // ---- load level t (buffer 0) and t - dt (buffer 1), KB loads in flight;
-  // the host guarantees nx >= W and ny >= H, so one conditional wrap suffices
+  // ---- load level t (buffer 0) and t - dt (buffer 1)
   for (int base = 0; base < WH; base += KB * NT) {
     T v[KB], vp[THREE ? KB : 1];
 #pragma unroll
@@ -50,8 +53,13 @@ __global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
       const int i = base + threadIdx.x + k * NT;
       if (i < WH) {
         int gx = x0 + (i % W), gy = y0 + i / W;
-        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        if constexpr (WRAP_ANY) {
+          gx = wrapi(gx, nx);
+          gy = wrapi(gy, ny);
+        } else {
+          gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+          gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+        }
         const int64_t gi = (int64_t)gy * nx + gx;
         v[k] = cur[gi];
         if constexpr (THREE) vp[k] = prev[gi];
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
   const int xx = threadIdx.x % W, rg = threadIdx.x / W;
   int ic = 0, ip = 1, io = THREE ? 2 : 1;
 #pragma unroll 1
-  for (int t = 1; t <= TB; ++t) {
+  for (int t = 1; t <= TBS; ++t) {
     const T *A = lds + ic * WH;
     const T *P = lds + ip * WH;
     T *O = lds + io * WH;
@@ -80,14 +88,24 @@ __global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
     const int seg = (Hr + RG - 1) / RG;
     const int ya = t + rg * seg, yb = min(ya + seg, H - t);
     if (xx >= t && xx < W - t && ya < yb) {
-      T w[3][3], h[3][3];
+      // phi (w, h) and, for Burgers, the second record field (wb, hb)
+      T w[3][3], h[3][3], wb[BURG ? 3 : 1][3], hb[BURG && THREE_ST ? 3 : 1][3];
+      auto second = [&](T v) { return (v * v) * kc.bh; };
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         w[0][c] = A[(ya - 1) * W + xx - 1 + c];
         w[1][c] = A[ya * W + xx - 1 + c];
+        if constexpr (BURG) {
+          wb[0][c] = second(w[0][c]);
+          wb[1][c] = second(w[1][c]);
+        }
         if constexpr (THREE_ST) {
           h[0][c] = P[(ya - 1) * W + xx - 1 + c];
           h[1][c] = P[ya * W + xx - 1 + c];
+          if constexpr (BURG) {
+            hb[0][c] = second(h[0][c]);
+            hb[1][c] = second(h[1][c]);
+          }
         }
       }
 #pragma unroll 2
@@ -95,25 +113,44 @@ __global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           w[2][c] = A[(y + 1) * W + xx - 1 + c];
-          if constexpr (THREE_ST) h[2][c] = P[(y + 1) * W + xx - 1 + c];
+          if constexpr (BURG) wb[2][c] = second(w[2][c]);
+          if constexpr (THREE_ST) {
+            h[2][c] = P[(y + 1) * W + xx - 1 + c];
+            if constexpr (BURG) hb[2][c] = second(h[2][c]);
+          }
         }
-        auto at = [&](int, int, int dy, int dx) { return w[1 + dy][1 + dx]; };
-        auto ath = [&](int, int, int dy, int dx) {
-          if constexpr (THREE_ST) return h[1 + dy][1 + dx];
-          else return T(0);
+        auto at = [&](int k, int, int dy, int dx) {
+          if constexpr (BURG) return k == 0 ? w[1 + dy][1 + dx] : wb[1 + dy][1 + dx];
+          else return w[1 + dy][1 + dx];
+        };
+        auto ath = [&](int k, int, int dy, int dx) {
+          if constexpr (THREE_ST) {
+            if constexpr (BURG) return k == 0 ? h[1 + dy][1 + dx] : hb[1 + dy][1 + dx];
+            else return h[1 + dy][1 + dx];
+          } else {
+            return T(0);
+          }
         };
         T cc[1] = {w[1][1]};
         T pc[1] = {THREE ? P[y * W + xx] : T(0)};
         T oc[1];
-        mmfd_node<L, kLCDE, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+        mmfd_node<L, EQ, THREE, THREE_ST, T, B1>(at, ath, cc, pc, oc, kc);
         O[y * W + xx] = oc[0];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           w[0][c] = w[1][c];
           w[1][c] = w[2][c];
+          if constexpr (BURG) {
+            wb[0][c] = wb[1][c];
+            wb[1][c] = wb[2][c];
+          }
           if constexpr (THREE_ST) {
             h[0][c] = h[1][c];
             h[1][c] = h[2][c];
+            if constexpr (BURG) {
+              hb[0][c] = hb[1][c];
+              hb[1][c] = hb[2][c];
+            }
           }
         }
       }
@@ -134,14 +171,53 @@ __global__ __launch_bounds__(W *RG) void k_lcde_tb(const T *__restrict__ cur,
   // ---- store the interior of the last level (and the one before it)
   const T *C = lds + ic * WH;
   const T *Pv = lds + ip * WH;
+  const int TX = W - 2 * TBW, TY = H - 2 * TBW;
   for (int i = threadIdx.x; i < TX * TY; i += NT) {
     const int lx = i % TX, ly = i / TX;
-    const int gx = x0 + TB + lx, gy = y0 + TB + ly;
+    const int gx = x0 + TBW + lx, gy = y0 + TBW + ly;
     if (gx >= nx || gy >= ny) continue;
     const int64_t gi = (int64_t)gy * nx + gx;
-    out_cur[gi] = C[(TB + ly) * W + TB + lx];
-    if constexpr (THREE) out_prev[gi] = Pv[(TB + ly) * W + TB + lx];
+    out_cur[gi] = C[(TBW + ly) * W + TBW + lx];
+    if constexpr (THREE) out_prev[gi] = Pv[(TBW + ly) * W + TBW + lx];
   }
+}
+
+template <class L, int EQ, bool THREE, bool THREE_ST, int W, int RG, bool B1, typename T>
+__global__ __launch_bounds__(W *RG) void k_mmfd_tb(const T *__restrict__ cur,
+                                                  const T *__restrict__ prev,
+                                                  T *__restrict__ out_cur,
+                                                  T *__restrict__ out_prev, int nx, int ny,
+                                                  int H, int TB, int tiles_x, int ntiles,
+                                                  KC<T> kc) {
+  extern __shared__ unsigned char smem_tb[];
+  T *lds = reinterpret_cast<T *>(smem_tb);  // [levels][H][W]
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int tile = xcd_remap_tb(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
+  tb_window<L, EQ, THREE, THREE_ST, W, RG, false, B1, T>(cur, prev, out_cur, out_prev, nx, ny, H,
+                                                         TB, TB, x0, y0, kc, lds);
+}
+
+// Batched two-level variant: launch `launch` of a run whose launches advance
+// TB steps; tiles of instances with steps left form the prefix [0, ntiles).
+template <class L, int EQ, int W, int RG, bool B1, typename T>
+__global__ __launch_bounds__(W *RG) void k_batch_tb(const BatchInst<T> *__restrict__ inst,
+                                                   const int *__restrict__ tile_inst, int ntiles,
+                                                   int64_t launch, int H, int TB) {
+  extern __shared__ unsigned char smem_btb[];
+  T *lds = reinterpret_cast<T *>(smem_btb);
+  const int t = xcd_remap_tb(blockIdx.x, ntiles);
+  const BatchInst<T> &I = inst[tile_inst[t]];
+  const int64_t left = I.nsteps - launch * TB;
+  const int TBS = left < TB ? (int)left : TB;
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int lt = t - I.tile0;
+  const int x0 = (lt % I.tiles_x) * TX - TB, y0 = (lt / I.tiles_x) * TY - TB;
+  const int64_t r = I.c0 + launch;
+  const T *cur = I.ring[r & 1];
+  T *out = I.ring[(r + 1) & 1];
+  tb_window<L, EQ, false, false, W, RG, true, B1, T>(cur, nullptr, out, nullptr, I.nx, I.ny, H,
+                                                     TB, TBS, x0, y0, I.kc, lds);
 }
 
 namespace {
@@ -150,7 +226,7 @@ namespace {
 // H rows in RG = 4 row groups; the tile advanced is (W - 2 TB) x (H - 2 TB).
 constexpr int kTbW = 64, kTbRG = 4;
 
-template <class L, bool THREE, bool THREE_ST, typename T>
+template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, typename T>
 hipError_t tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
                   T *oc, T *op, hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
@@ -158,7 +234,7 @@ hipError_t tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur
   const int TX = kTbW - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
   const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
   const size_t lds = (size_t)(THREE ? 3 : 2) * pl.h * kTbW * sizeof(T);
-  auto fn = k_lcde_tb<L, THREE, THREE_ST, kTbW, kTbRG, T>;
+  auto fn = k_mmfd_tb<L, EQ, THREE, THREE_ST, kTbW, kTbRG, B1, T>;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -167,43 +243,100 @@ hipError_t tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur
   return hipGetLastError();
 }
 
-template <class L, typename T>
+template <class L, int EQ, bool B1, typename T>
 hipError_t tb_levels(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                      const T *prev, T *oc, T *op, hipStream_t st) {
-  if (!c.three) return tb_cfg<L, false, false, T>(c, g, pl, cur, prev, oc, op, st);
-  if (!c.three_stencil) return tb_cfg<L, true, false, T>(c, g, pl, cur, prev, oc, op, st);
-  return tb_cfg<L, true, true, T>(c, g, pl, cur, prev, oc, op, st);
+  if (!c.three) return tb_cfg<L, EQ, false, false, B1, T>(c, g, pl, cur, prev, oc, op, st);
+  if (!c.three_stencil) return tb_cfg<L, EQ, true, false, B1, T>(c, g, pl, cur, prev, oc, op, st);
+  return tb_cfg<L, EQ, true, true, B1, T>(c, g, pl, cur, prev, oc, op, st);
+}
+
+template <class L, typename T>
+hipError_t tb_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
+                 T *oc, T *op, hipStream_t st) {
+  if (c.eq == kLCDE) return tb_levels<L, kLCDE, false, T>(c, g, pl, cur, prev, oc, op, st);
+  if (c.eq == kBurgers) {
+    if (c.beta_one) return tb_levels<L, kBurgers, true, T>(c, g, pl, cur, prev, oc, op, st);
+    return tb_levels<L, kBurgers, false, T>(c, g, pl, cur, prev, oc, op, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class L, int EQ, bool B1, typename T>
+hipError_t btb_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, int64_t launch,
+                   const TbPlan &pl, hipStream_t st) {
+  const size_t lds = (size_t)2 * pl.h * kTbW * sizeof(T);
+  auto fn = k_batch_tb<L, EQ, kTbW, kTbRG, B1, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(kTbW * kTbRG), lds, st, inst, tile_inst, ntiles,
+                     launch, pl.h, pl.tb);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-size_t lcde_tb_lds_bytes(const Consts &c, int h, int elem) {
+size_t tb_lds_bytes(const Consts &c, int h, int elem) {
   return (size_t)(c.three ? 3 : 2) * h * kTbW * elem;
 }
 
-bool lcde_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
-  if (c.eq != kLCDE || c.dim != 2) return false;
-  if (c.lattice != 2 && c.lattice != 3) return false;
+bool tb_plan_valid(const TbPlan &pl, int levels, int elem) {
   if (pl.tb < 1 || pl.tb > 16 || pl.h < 2 * pl.tb + 4) return false;
   if (kTbW - 2 * pl.tb < 8) return false;
-  if (lcde_tb_lds_bytes(c, pl.h, elem) > 160 * 1024) return false;
+  return (size_t)levels * pl.h * kTbW * elem <= 160 * 1024;
+}
+
+bool tb_equation_supported(const Consts &c) {
+  return (c.eq == kLCDE || c.eq == kBurgers) && c.dim == 2 && (c.lattice == 2 || c.lattice == 3);
+}
+
+bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
+  if (!tb_equation_supported(c)) return false;
+  if (!tb_plan_valid(pl, c.three ? 3 : 2, elem)) return false;
   // one conditional wrap per coordinate covers the window
   return g.n[0] >= kTbW && g.n[1] >= pl.h;
 }
 
 template <typename T>
-hipError_t launch_lcde_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st) {
-  if (c.lattice == 3) return tb_levels<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
-  if (c.lattice == 2) return tb_levels<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
+  if (c.lattice == 3) return tb_eq<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
+  if (c.lattice == 2) return tb_eq<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_lcde_tb<float>(const Consts &, const Grid &, const TbPlan &,
-                                          const float *, const float *, float *, float *,
-                                          hipStream_t);
-template hipError_t launch_lcde_tb<double>(const Consts &, const Grid &, const TbPlan &,
-                                           const double *, const double *, double *, double *,
-                                           hipStream_t);
+int tb_window_cols() { return kTbW; }
+
+template <typename T>
+hipError_t launch_batch_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
+                           int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st) {
+  if (k.three) return hipErrorInvalidValue;
+  if (k.lattice == 3) {
+    if (k.eq == kLCDE)
+      return btb_cfg<LatD2Q9, kLCDE, false, T>(inst, tile_inst, ntiles, launch, pl, st);
+    if (k.eq == kBurgers && k.b1)
+      return btb_cfg<LatD2Q9, kBurgers, true, T>(inst, tile_inst, ntiles, launch, pl, st);
+    if (k.eq == kBurgers)
+      return btb_cfg<LatD2Q9, kBurgers, false, T>(inst, tile_inst, ntiles, launch, pl, st);
+  } else if (k.lattice == 2) {
+    if (k.eq == kLCDE)
+      return btb_cfg<LatD2Q5, kLCDE, false, T>(inst, tile_inst, ntiles, launch, pl, st);
+    if (k.eq == kBurgers && k.b1)
+      return btb_cfg<LatD2Q5, kBurgers, true, T>(inst, tile_inst, ntiles, launch, pl, st);
+    if (k.eq == kBurgers)
+      return btb_cfg<LatD2Q5, kBurgers, false, T>(inst, tile_inst, ntiles, launch, pl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define MFD_INST(T)                                                                               \
+  template hipError_t launch_mmfd_tb<T>(const Consts &, const Grid &, const TbPlan &, const T *, \
+                                        const T *, T *, T *, hipStream_t);                        \
+  template hipError_t launch_batch_tb<T>(const BatchKey &, const BatchInst<T> *, const int *,    \
+                                         int, int64_t, const TbPlan &, hipStream_t);
+MFD_INST(float)
+MFD_INST(double)
+#undef MFD_INST
 
 }  // namespace mfd

@@ -46,7 +46,7 @@ int64_t Solver::device_bytes_needed() const {
   int64_t b = 3 * mom_elems() * es;  // level ring (MMFD) / moment ping-pong + scratch (MesoFD)
   if (grid.form == MFD_MESOFD) b += 2 * pop_elems() * es;
   if (cfg.kind == MFD_THETA) b += 2 * mom_elems() * es;
-  if (grid.form == MFD_MMFD && consts.three && consts.eq == kLCDE && consts.dim == 2)
+  if (grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))
     b += mom_elems() * es;
   b += (kReduceBlocks * 8 + 8) * (int64_t)sizeof(double);
   return b;
@@ -68,7 +68,7 @@ int Solver::ensure_buffers() {
   const int64_t es = elem(), me = mom_elems() * es, pe = pop_elems() * es;
   int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8, me};
   if (cfg.kind != MFD_THETA) sizes[5] = sizes[6] = 0;
-  if (!(grid.form == MFD_MMFD && consts.three && consts.eq == kLCDE && consts.dim == 2)) sizes[8] = 0;
+  if (!(grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))) sizes[8] = 0;
   for (int i = 0; i < kNumBuf; ++i) {
     if (sizes[i] == 0) continue;
     hipError_t e = hipMalloc(&buf[i], (size_t)sizes[i]);
@@ -115,7 +115,7 @@ int Solver::step_t(int64_t nsteps) {
   const TbPlan pl = effective_plan();
   const int d = pl.tb;
   if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 &&
-      lcde_tb_supported(consts, G, pl, (int)sizeof(T))) {
+      tb_supported(consts, G, pl, (int)sizeof(T))) {
     // blocks of d steps, then single steps for the remainder.  A two-level
     // block returns only its last level, so after it the held previous level
     // is d steps old (prev_gap = d), which the residual accounts for.
@@ -123,11 +123,11 @@ int Solver::step_t(int64_t nsteps) {
     for (int64_t b = 0; b < nblk; ++b) {
       hipError_t e;
       if (!consts.three) {
-        e = launch_lcde_tb<T>(consts, G, pl, B[ic], nullptr, B[ip], nullptr, stream);
+        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], nullptr, B[ip], nullptr, stream);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         std::swap(ic, ip);
       } else {
-        e = launch_lcde_tb<T>(consts, G, pl, B[ic], B[ip], B[io], B[ix], stream);
+        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], B[ip], B[io], B[ix], stream);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         const int oc = ic, op = ip;
         ic = io;

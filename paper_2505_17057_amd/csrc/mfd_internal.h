@@ -109,7 +109,8 @@ hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T
                                    int64_t nsteps, hipStream_t st);
 bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
 
-// Temporally blocked LCDE step on D2Q5 / D2Q9: one launch advances tb steps
+// Temporally blocked MMFD step (linear CDE, Burgers) on D2Q5 / D2Q9: one
+// launch advances tb steps
 // over windows of 64 x h nodes.  Reads levels t (cur) and t - dt (prev,
 // three-level), writes t + tb (out_cur) and, for three-level schemes,
 // t + tb - 1 (out_prev).
@@ -117,10 +118,16 @@ struct TbPlan {
   int tb;  // steps per launch
   int h;   // window rows
 };
-size_t lcde_tb_lds_bytes(const Consts &c, int h, int elem);
-bool lcde_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
+size_t tb_lds_bytes(const Consts &c, int h, int elem);
+// plan limits (depth, window height, LDS) for `levels` LDS levels
+bool tb_plan_valid(const TbPlan &pl, int levels, int elem);
+// equations / lattices the blocked kernels implement
+bool tb_equation_supported(const Consts &c);
+// the single-grid blocked kernel can run this plan on this grid
+bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
+int tb_window_cols();
 template <typename T>
-hipError_t launch_lcde_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 
 // MesoFD step: moments of level t (mom) and t-dt (prev_mom) in; populations

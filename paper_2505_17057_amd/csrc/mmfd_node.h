@@ -9,7 +9,9 @@ namespace mfd {
 // ---------------------------------------------------------- node update
 // `at(field, dz, dy, dx)` reads the level-t record, `ath` the level-(t-dt)
 // record; cur_c / prev_c are the centre moments (global), out the outputs.
-template <class L, int EQ, bool THREE, bool THREE_ST, typename T, class At, class AtH>
+// B1: Burgers with beta = 1 known at compile time (see fplus).
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T, bool B1 = false, class At,
+          class AtH>
 __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T *cur_c,
                                           const T *prev_c, T *out_c, const KC<T> &kc) {
   using R = Rec<L, EQ>;
@@ -48,8 +50,8 @@ __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T 
           r0[k] = get(k, 0, 0, 0);
           rm[k] = get(k, -ez, -ey, -ex);
         }
-        const T Fpp = fplus<L, EQ, J>(rp, kc), Fp0 = fplus<L, EQ, J>(r0, kc),
-                Fpm = fplus<L, EQ, J>(rm, kc);
+        const T Fpp = fplus<L, EQ, J, B1>(rp, kc), Fp0 = fplus<L, EQ, J, B1>(r0, kc),
+                Fpm = fplus<L, EQ, J, B1>(rm, kc);
         const T Fmp = fminus<L, EQ, J>(rp, kc), Fmm = fminus<L, EQ, J>(rm, kc);
         acc = madd(cpl, (Fpp - T(2) * Fp0) + Fpm, acc);
         acc = madd(cmi, Fmp - Fmm, acc);

@@ -85,7 +85,23 @@ def bench_plan(log_path):
     raise SystemExit("no bench JSON line in " + log_path)
 
 
+def stats_table(db_path, top=15):
+    """Markdown table of the `top` kernels by total time."""
+    stats = kernel_stats(db_path)
+    total = sum(r[2] for r in stats) or 1
+    L = ["| kernel | calls | total ms | mean us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for n, c, t, m, lo, hi in stats[:top]:
+        L.append("| %s | %d | %.3f | %.3f | %.3f | %.3f | %.1f%% |" % (n[:100], c, t / 1e6, m / 1e3, lo / 1e3,
+                                                                    hi / 1e3, 100.0 * t / total))
+    return "\n".join(L)
+
+
 def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "stats":
+        # python -m paper_2505_17057_amd.profiling stats RESULTS.db [TOP]
+        print(stats_table(argv[1], int(argv[2]) if len(argv) > 2 else 15))
+        return
     p = argparse.ArgumentParser()
     p.add_argument("--trace", required=True)
     p.add_argument("--fetch", required=True)
@@ -102,7 +118,6 @@ def main(argv=None):
     p.add_argument("--out-md", required=True)
     p.add_argument("--out-json", required=True)
     p.add_argument("--command", action="append", default=[], help="command that produced an input")
-    argv = sys.argv[1:] if argv is None else argv
     a = p.parse_args(argv)
     a.command = a.command + ["python -m paper_2505_17057_amd.profiling " + shlex.join(argv)]
 

@@ -167,3 +167,77 @@ def test_server_budget(M):
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     srv.close()
+
+
+@pytest.mark.parametrize("plan", [(4, 32), (6, 48), (2, 128)])
+def test_batch_blocked_fp64_matches_oracle(M, plan):
+    """Blocked batch launches (the two-level Burgers and LCDE groups; NSE keeps
+    one launch per step) give every instance its oracle result, across two
+    runs (graph replay), with launches = sum over groups of ceil(steps / tb)."""
+    print("plan", plan, flush=True)
+    cases = batch_cases()
+    states = _states(cases, seed=9)
+    solvers = []
+    b = M.Batch(use_graph=True)
+    b.set_plan(*plan)
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp64")
+        s.set_state(cur)
+        if c.get("kind") == "three_level":
+            s.set_state(prev, level=1)
+        b.add(s, c["steps"])
+        solvers.append(s)
+    b.run()
+    b.wait()
+    b.run()
+    b.wait()
+    groups = {}
+    for c in cases:
+        groups[c["eq"]] = max(groups.get(c["eq"], 0), c["steps"])
+    tb = plan[0]
+    want_launches = sum(-(-m // tb) if eq != "nse" else m for eq, m in groups.items())
+    assert b.stats()["launches"] == want_launches
+    for c, (cur, prev), s in zip(cases, states, solvers):
+        want = run_oracle(c, cur, prev, 2 * c["steps"])
+        assert np.array_equal(s.get_state(), want), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_autotune_fp32_equals_solo(M):
+    """The batch autotuner leaves every state as it was, and the run under the
+    plan it picks equals each instance stepped alone, bit for bit."""
+    cases = batch_cases()
+    states = _states(cases, seed=10)
+    solo = []
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_blocking(1)
+        s.set_state(cur.astype(np.float32))
+        if c.get("kind") == "three_level":
+            s.set_state(prev.astype(np.float32), level=1)
+        s.step(c["steps"])
+        solo.append(s.get_state())
+        s.close()
+    b = M.Batch()
+    solvers = []
+    for c, (cur, prev) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_state(cur.astype(np.float32))
+        if c.get("kind") == "three_level":
+            s.set_state(prev.astype(np.float32), level=1)
+        b.add(s, c["steps"])
+        solvers.append(s)
+    before = [(s.get_state(), s.reduce()) for s in solvers]
+    b.autotune()
+    for s, (st, red) in zip(solvers, before):
+        assert np.array_equal(s.get_state(), st)
+        assert s.reduce() == red
+    b.run()
+    b.wait()
+    for c, s, want in zip(cases, solvers, solo):
+        assert np.array_equal(s.get_state(), want), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()

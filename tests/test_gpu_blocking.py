@@ -1,8 +1,9 @@
 """GPU: temporal blocking, autotuning, reductions and the binary32 MesoFD
 mass balance.
 
-* Blocked LCDE steps (depth 2, 4, 6, 8) equal the FP64 oracle value for
-  value and equal the unblocked binary32 run bit for bit (one expression tree).
+* Blocked LCDE and Burgers steps (depth 2, 4, 6, 8) equal the FP64 oracle
+  value for value and equal the unblocked binary32 run bit for bit (one
+  expression tree).
 * Autotuning leaves the state untouched.
 * FP64 reductions (mass, residual) agree with the oracle's compensated sums.
 """
@@ -22,12 +23,27 @@ SCHEMES = {
 }
 
 
+def _burgers_a(n0, nu=5e-3):
+    dx = 1.0 / n0
+    dt = 0.5 * min(0.3 * dx * dx / nu, nu / 0.25)
+    s = 2 * nu * dt / ((1.0 / 3.0) * dx * dx)
+    return dict(dx=dx, dt=dt, a=((s + 1) / 2, 1 - s, (s - 1) / 2))
+
+
 def _case(name, n):
+    if name.startswith("burgers"):
+        c = dict(lattice="D2Q9", eq="burgers", n=n, name=name, **_burgers_a(n[0]))
+        if name == "burgers-3l":
+            c.update(kind="three_level", a=(0.875, 0.0, 0.125), ah=(0.125, 0.0, -0.125))
+        return c
     return dict(BASE, n=n, name=name, **SCHEMES[name])
 
 
+ALL = list(SCHEMES) + ["burgers-2l", "burgers-3l"]
+
+
 @pytest.mark.parametrize("tb", [2, 4, 6, 8])
-@pytest.mark.parametrize("name", list(SCHEMES))
+@pytest.mark.parametrize("name", ALL)
 @pytest.mark.parametrize("n", [(150, 77), (64, 32)])
 def test_blocked_fp64_bitwise(M, tb, name, n):
     case = _case(name, n)
@@ -48,7 +64,7 @@ def test_blocked_fp64_bitwise(M, tb, name, n):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
-@pytest.mark.parametrize("name", list(SCHEMES))
+@pytest.mark.parametrize("name", ALL)
 def test_blocked_fp32_equals_unblocked(M, name):
     from parity_util import make_solver
     case = _case(name, (300, 140))
