@@ -199,36 +199,53 @@ def bench_c1(M, torch, I, stream):
     return res
 
 
+def _nse_solver(M, lat, c, precision, stream):
+    a, ah = trt_coeffs(M, c["nu"], c["dx"], c["dt"])
+    s = M.Solver(lat, c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("nse", rho0=c["rho0"])
+    s.set_scheme("three_level", a, ah, dt=c["dt"])
+    s.set_stream(stream.cuda_stream)
+    return s
+
+
+def _rel_l2_dev(torch, a, b):
+    """Relative L2 distance of two device tensors, in binary64."""
+    a = a.double()
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
 def bench_nse(M, torch, I, stream):
+    """Three-level TRT NSE: FP32 timing, and the FP32 error against the FP64
+    run of the same steps from the same (binary32-rounded) start."""
     res = {}
-    c3 = I.tgv_2d(n=4096)
-    a, ah = trt_coeffs(M, c3["nu"], c3["dx"], c3["dt"])
-    s = M.Solver("D2Q9", c3["n"], c3["dx"], "fp32", "mmfd")
-    s.set_equation("nse", rho0=c3["rho0"])
-    s.set_scheme("three_level", a, ah, dt=c3["dt"])
-    s.set_stream(stream.cuda_stream)
-    s.set_state(c3["state0"].astype(np.float32))
-    s.step(20)
-    ms = timed(torch, lambda: s.step(200))
-    g = 4096 * 4096 * 200 / (ms * 1e-3) / 1e9
-    res["d2q9_4096_three_level_fp32"] = dict(glups=round(g, 2), alg_gbs=round(g * 36, 1),
-                                             frac_hbm=round(g * 36 / HBM_PEAK_GBS, 4), bytes_per_lup=36)
-    s.close()
-    del c3
-    c3d = I.tgv_3d(n=512, dtype=np.float32)
-    a, ah = trt_coeffs(M, c3d["nu"], c3d["dx"], c3d["dt"])
-    s = M.Solver("D3Q19", c3d["n"], c3d["dx"], "fp32", "mmfd")
-    s.set_equation("nse", rho0=c3d["rho0"])
-    s.set_scheme("three_level", a, ah, dt=c3d["dt"])
-    s.set_stream(stream.cuda_stream)
-    s.set_state(c3d["state0"])
-    del c3d
-    s.step(2)
-    ms = timed(torch, lambda: s.step(20))
-    g = 512 ** 3 * 20 / (ms * 1e-3) / 1e9
-    res["d3q19_512_three_level_fp32"] = dict(glups=round(g, 2), alg_gbs=round(g * 48, 1),
-                                             frac_hbm=round(g * 48 / HBM_PEAK_GBS, 4), bytes_per_lup=48)
-    s.close()
+    for lat, c, warm, steps, bpl, key in (
+            ("D2Q9", I.tgv_2d(n=4096), 20, 200, 36, "d2q9_4096_three_level_fp32"),
+            ("D3Q19", I.tgv_3d(n=512, dtype=np.float32), 2, 20, 48, "d3q19_512_three_level_fp32")):
+        x0 = torch.from_numpy(np.ascontiguousarray(c["state0"], dtype=np.float32)).to("cuda")
+        del c["state0"]
+        nodes = int(np.prod(c["n"]))
+        s = _nse_solver(M, lat, c, "fp32", stream)
+        s.set_state(x0)
+        s.step(warm)
+        ms = timed(torch, lambda: s.step(steps))
+        g = nodes * steps / (ms * 1e-3) / 1e9
+        y32 = torch.empty_like(x0)
+        s.get_state(out=y32)
+        s.close()
+        s64 = _nse_solver(M, lat, c, "fp64", stream)
+        x64 = x0.double()
+        s64.set_state(x64)
+        s64.step(warm + steps)
+        y64 = torch.empty_like(x64)
+        s64.get_state(out=y64)
+        s64.close()
+        torch.cuda.synchronize()
+        res[key] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                        frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl,
+                        steps=warm + steps,
+                        fp32_rel_l2_vs_fp64=_rel_l2_dev(torch, y32, y64))
+        del x0, x64, y32, y64
+        torch.cuda.empty_cache()
     return res
 
 

@@ -32,6 +32,12 @@ __device__ __forceinline__ float madd<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
+// 1/x: binary64 a correctly rounded division (the oracle's operation);
+// binary32 the hardware reciprocal (error within 1 ulp), an order of
+// magnitude fewer instructions than the IEEE division sequence.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <class L, int EQ>
 struct Rec {
   static constexpr int D = L::D;
@@ -59,7 +65,7 @@ __device__ __forceinline__ void make_record(const T *m, T *r, const KC<T> &kc) {
     r[0] = m[0];
     T rinv;
     if (kc.he_luo) rinv = kc.rinv0;
-    else rinv = T(1) / (kc.rho0 + m[0]);
+    else rinv = recip(kc.rho0 + m[0]);
 #pragma unroll
     for (int a = 0; a < D; ++a) r[1 + a] = m[1 + a];
 #pragma unroll

@@ -34,6 +34,37 @@ __global__ __launch_bounds__(256) void k_mmfd_plane(const T *__restrict__ cur,
   mmfd_plane_tile<L, EQ, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc);
 }
 
+// ------------------------------------- 2D NSE, persistent workgroups
+// Each workgroup walks a contiguous run of tiles (XCD-aware: the runs of one
+// XCD are adjacent, so halo rows are shared in its L2) and loads the next
+// tile's moments while it updates the current one.
+template <class L, bool THREE, bool THREE_ST, int TX, int TY, bool FAST, typename T>
+__global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
+                                                      const T *__restrict__ prev,
+                                                      T *__restrict__ out, int nx, int ny,
+                                                      int tiles_x, int ntiles, KC<T> kc) {
+  using P = PfTile<L, THREE, THREE_ST, TX, TY, T, FAST>;
+  __shared__ typename P::Lds sm;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int t0 = w * per, t1 = min(ntiles, t0 + per);
+  if (t0 >= t1) return;  // the whole workgroup: no barrier is skipped by part of it
+  typename P::Regs g;
+  P::load(cur, prev, nx, ny, (t0 % tiles_x) * TX, (t0 / tiles_x) * TY, g);
+  for (int t = t0; t < t1; ++t) {
+    P::stage(g, sm, kc);
+    T pcv[P::KI][P::NF];
+#pragma unroll
+    for (int k = 0; k < P::KI; ++k)
+#pragma unroll
+      for (int q = 0; q < P::NF; ++q) pcv[k][q] = g.pcv[k][q];
+    __syncthreads();
+    if (t + 1 < t1) P::load(cur, prev, nx, ny, ((t + 1) % tiles_x) * TX, ((t + 1) / tiles_x) * TY, g);
+    P::update(sm, pcv, out, nx, ny, (t % tiles_x) * TX, (t / tiles_x) * TY, kc);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------- 3D kernel
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
 __global__ __launch_bounds__(256) void k_mmfd_3d(const T *__restrict__ cur,
@@ -178,6 +209,9 @@ __global__ __launch_bounds__(1024) void k_mmfd_1d_resident(T *__restrict__ ga,
 // ------------------------------------------------------------ launchers
 namespace {
 
+// compute units of an MI355X (persistent grids)
+constexpr int kNumCUs = 256;
+
 template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
 hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
                       hipStream_t st) {
@@ -188,8 +222,22 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     const int tx = (nx + TX - 1) / TX;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx), dim3(256), 0,
                        st, cur, prev, out, nx, 1, tx, tx, kc);
+  } else if constexpr (L::D == 2 && EQ == kNSE) {
+    constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    const int ntiles = tx * ty;
+    // persistent groups: as many as the tile's LDS lets reside on each CU
+    constexpr int per_cu = (int)((160 * 1024) / sizeof(typename PfTile<L, THREE, THREE_ST, TX, TY, T>::Lds));
+    constexpr int groups = kNumCUs * (per_cu < 1 ? 1 : per_cu);
+    const int grid = ntiles < groups ? ntiles : groups;
+    if (nx >= TX + 2 && ny >= TY + 2)
+      hipLaunchKernelGGL((k_nse_plane_pp<L, THREE, THREE_ST, TX, TY, true, T>), dim3(grid),
+                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc);
+    else
+      hipLaunchKernelGGL((k_nse_plane_pp<L, THREE, THREE_ST, TX, TY, false, T>), dim3(grid),
+                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc);
   } else if constexpr (L::D == 2) {
-    constexpr int TX = 64, TY = EQ == kNSE ? 8 : 16;
+    constexpr int TX = 64, TY = 16;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty), dim3(256),
                        0, st, cur, prev, out, nx, ny, tx, tx * ty, kc);

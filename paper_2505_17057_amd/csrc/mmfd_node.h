@@ -10,8 +10,11 @@ namespace mfd {
 // `at(field, dz, dy, dx)` reads the level-t record, `ath` the level-(t-dt)
 // record; cur_c / prev_c are the centre moments (global), out the outputs.
 // B1: Burgers with beta = 1 known at compile time (see fplus).
-template <class L, int EQ, bool THREE, bool THREE_ST, typename T, bool B1 = false, class At,
-          class AtH>
+// PF: the accessors return precomputed pair parts instead of records:
+// at(2p, ...) = F+_p, at(2p + 1, ...) = F-_p of pair p at that offset (the
+// same values fplus / fminus give for the node's record).
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T, bool B1 = false,
+          bool PF = false, class At, class AtH>
 __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T *cur_c,
                                           const T *prev_c, T *out_c, const KC<T> &kc) {
   using R = Rec<L, EQ>;
@@ -43,20 +46,32 @@ __device__ __forceinline__ void mmfd_node(const At &at, const AtH &ath, const T 
           acc = madd(be, gm - g0, acc);
         }
       } else {
-        T rp[NR], r0[NR], rm[NR];
+        T Fpp, Fp0, Fpm, Fmp, Fmm, Fm0;
+        if constexpr (PF) {
+          Fpp = get(2 * P, ez, ey, ex);
+          Fp0 = get(2 * P, 0, 0, 0);
+          Fpm = get(2 * P, -ez, -ey, -ex);
+          Fmp = get(2 * P + 1, ez, ey, ex);
+          Fmm = get(2 * P + 1, -ez, -ey, -ex);
+          if constexpr (EQ == kNSE) Fm0 = get(2 * P + 1, 0, 0, 0);
+        } else {
+          T rp[NR], r0[NR], rm[NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          rp[k] = get(k, ez, ey, ex);
-          r0[k] = get(k, 0, 0, 0);
-          rm[k] = get(k, -ez, -ey, -ex);
+          for (int k = 0; k < NR; ++k) {
+            rp[k] = get(k, ez, ey, ex);
+            r0[k] = get(k, 0, 0, 0);
+            rm[k] = get(k, -ez, -ey, -ex);
+          }
+          Fpp = fplus<L, EQ, J, B1>(rp, kc);
+          Fp0 = fplus<L, EQ, J, B1>(r0, kc);
+          Fpm = fplus<L, EQ, J, B1>(rm, kc);
+          Fmp = fminus<L, EQ, J>(rp, kc);
+          Fmm = fminus<L, EQ, J>(rm, kc);
+          if constexpr (EQ == kNSE) Fm0 = fminus<L, EQ, J>(r0, kc);
         }
-        const T Fpp = fplus<L, EQ, J, B1>(rp, kc), Fp0 = fplus<L, EQ, J, B1>(r0, kc),
-                Fpm = fplus<L, EQ, J, B1>(rm, kc);
-        const T Fmp = fminus<L, EQ, J>(rp, kc), Fmm = fminus<L, EQ, J>(rm, kc);
         acc = madd(cpl, (Fpp - T(2) * Fp0) + Fpm, acc);
         acc = madd(cmi, Fmp - Fmm, acc);
         if constexpr (EQ == kNSE) {
-          const T Fm0 = fminus<L, EQ, J>(r0, kc);
           const T t1 = bpl * ((Fmp - T(2) * Fm0) + Fmm);
           const T t2 = bmi * (Fpp - Fpm);
 #pragma unroll
@@ -120,6 +135,154 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   return x * q + min(x, r) + k;
 }
 
+// pair parts F+_p, F-_p of every opposite pair of one node record (lattice
+// pair order), out[2p] = F+_p, out[2p + 1] = F-_p
+template <class L, int EQ, typename T>
+__device__ __forceinline__ void pair_parts(const T *r, T *out, const KC<T> &kc) {
+  static_for<L::P>([&](auto PI) {
+    constexpr int P = decltype(PI)::value;
+    constexpr int J = L::PR[P];
+    out[2 * P] = fplus<L, EQ, J>(r, kc);
+    out[2 * P + 1] = fminus<L, EQ, J>(r, kc);
+  });
+}
+
+// One TX x TY tile of a 2D grid for the NSE, in three parts so that a
+// persistent kernel can overlap the next tile's loads with this tile's work:
+//   load   the moments of the tile and a one-node halo (both levels when the
+//          older one has a stencil) and the older level at the interior
+//          nodes, into registers (all loads of a thread in flight at once);
+//   stage  the pair parts of every loaded node (each evaluated once, not once
+//          per neighbour that uses it) and the tile's moments into LDS;
+//   update the node updates of the interior, reading LDS.
+// periodic index for i in [-n, 2n)
+__device__ __forceinline__ int wrap1(int i, int n) {
+  i += i < 0 ? n : 0;
+  return i - (i >= n ? n : 0);
+}
+
+// FAST: nx >= TX + 2 and ny >= TY + 2, so every halo index is within one
+// period of the grid (cheap wrap); otherwise the general wrap.
+template <class L, bool THREE, bool THREE_ST, int TX, int TY, typename T, bool FAST = false>
+struct PfTile {
+  using R = Rec<L, kNSE>;
+  static constexpr int NR = R::NR, NF = R::NF, NPF = 2 * L::P;
+  static constexpr int HX = TX + 2, HY = TY + 2;
+  static constexpr int KH = (HX * HY + 255) / 256;  // halo-tile nodes per thread
+  static constexpr int KI = (TX * TY + 255) / 256;  // interior nodes per thread
+  struct Lds {
+    T pf[NPF][HY][HX];
+    T hpf[THREE_ST ? NPF : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+    T mc[NF][TY][TX];
+  };
+  struct Regs {
+    T mv[KH][NF];
+    T hv[THREE_ST ? KH : 1][NF];
+    T pcv[KI][NF];
+  };
+
+  static __device__ __forceinline__ void load(const T *__restrict__ cur,
+                                              const T *__restrict__ prev, int nx, int ny, int x0,
+                                              int y0, Regs &g) {
+    const int64_t N = (int64_t)nx * ny;
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < HX * HY) {
+        const int lx = i % HX, ly = i / HX;
+        const int gx = FAST ? wrap1(x0 - 1 + lx, nx) : wrapi(x0 - 1 + lx, nx);
+        const int gy = FAST ? wrap1(y0 - 1 + ly, ny) : wrapi(y0 - 1 + ly, ny);
+        const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) g.mv[k][q] = cur[q * N + gi];
+        if constexpr (THREE_ST) {
+#pragma unroll
+          for (int q = 0; q < NF; ++q) g.hv[k][q] = prev[q * N + gi];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int gx = x0 + i % TX, gy = y0 + i / TX;
+      if (THREE && i < TX * TY && gx < nx && gy < ny) {
+        const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) g.pcv[k][q] = prev[q * N + gi];
+      }
+    }
+  }
+
+  static __device__ __forceinline__ void stage(const Regs &g, Lds &s, const KC<T> &kc) {
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < HX * HY) {
+        const int lx = i % HX, ly = i / HX;
+        T r[NR], f[NPF];
+        if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY) {
+#pragma unroll
+          for (int q = 0; q < NF; ++q) s.mc[q][ly - 1][lx - 1] = g.mv[k][q];
+        }
+        make_record<L, kNSE>(g.mv[k], r, kc);
+        pair_parts<L, kNSE>(r, f, kc);
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) s.pf[q][ly][lx] = f[q];
+        if constexpr (THREE_ST) {
+          make_record<L, kNSE>(g.hv[k], r, kc);
+          pair_parts<L, kNSE>(r, f, kc);
+#pragma unroll
+          for (int q = 0; q < NPF; ++q) s.hpf[q][ly][lx] = f[q];
+        }
+      }
+    }
+  }
+
+  static __device__ __forceinline__ void update(const Lds &s, const T (&pcv)[KI][NF],
+                                                T *__restrict__ out, int nx, int ny, int x0,
+                                                int y0, const KC<T> &kc) {
+    const int64_t N = (int64_t)nx * ny;
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i >= TX * TY) break;
+      const int lx = i % TX, ly = i / TX;
+      const int gx = x0 + lx, gy = y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const int cx = lx + 1, cy = ly + 1;
+      const int64_t gi = (int64_t)gy * nx + gx;
+      auto at = [&](int q, int, int dy, int dx) { return s.pf[q][cy + dy][cx + dx]; };
+      auto ath = [&](int q, int, int dy, int dx) {
+        if constexpr (THREE_ST) return s.hpf[q][cy + dy][cx + dx];
+        else return T(0);
+      };
+      T cc[NF], pc[NF], oc[NF];
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        cc[q] = s.mc[q][ly][lx];
+        pc[q] = THREE ? pcv[k][q] : T(0);
+      }
+      mmfd_node<L, kNSE, THREE, THREE_ST, T, false, true>(at, ath, cc, pc, oc, kc);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) out[q * N + gi] = oc[q];
+    }
+  }
+};
+
+template <class L, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__device__ __forceinline__ void mmfd_plane_tile_pf(const T *__restrict__ cur,
+                                                   const T *__restrict__ prev,
+                                                   T *__restrict__ out, int nx, int ny, int x0,
+                                                   int y0, const KC<T> &kc) {
+  using P = PfTile<L, THREE, THREE_ST, TX, TY, T>;
+  __shared__ typename P::Lds sm;
+  typename P::Regs g;
+  P::load(cur, prev, nx, ny, x0, y0, g);
+  P::stage(g, sm, kc);
+  __syncthreads();
+  P::update(sm, g.pcv, out, nx, ny, x0, y0, kc);
+}
+
 // One TX x TY tile (origin x0, y0) of a 1D / 2D grid: EDF records of the tile
 // and a one-node halo into LDS (periodic wrap), then the node updates.
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
@@ -127,6 +290,9 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
                                                 const T *__restrict__ prev,
                                                 T *__restrict__ out, int nx, int ny, int x0,
                                                 int y0, const KC<T> &kc) {
+  if constexpr (EQ == kNSE && L::D == 2) {
+    mmfd_plane_tile_pf<L, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc);
+  } else {
   using R = Rec<L, EQ>;
   constexpr int NR = R::NR, NF = R::NF;
   constexpr int HYL = L::D >= 2 ? 1 : 0;
@@ -175,6 +341,7 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
     mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
+  }
   }
 }
 

@@ -56,6 +56,10 @@ CASES = [
     dict(name="d2q9-nse-3l-stencil-2set", lattice="D2Q9", n=(70, 37), eq="nse", rho0=1.0,
          kind="three_level", a=EX13[0], ah=EX13[1], ab=TRT[0], abh=TRT[1]),
     dict(name="d2q9-nse-plain-rho", lattice="D2Q9", n=(66, 20), eq="nse", rho0=0.0, a=(1.0, 0.0, 0.0)),
+    dict(name="d2q9-nse-trt-narrow", lattice="D2Q9", n=(40, 9), eq="nse", rho0=1.0, kind="three_level",
+         a=TRT[0], ah=TRT[1]),
+    dict(name="d2q9-nse-3l-stencil-small", lattice="D2Q9", n=(7, 5), eq="nse", rho0=1.0,
+         kind="three_level", a=EX13[0], ah=EX13[1], ab=TRT[0], abh=TRT[1]),
     dict(name="d2q9-nse-heluo", lattice="D2Q9", n=(66, 20), eq="nse", rho0=1.0, he_luo=1,
          kind="three_level", a=TRT[0], ah=TRT[1]),
     dict(name="d2q9-nse-mesofd-trt", lattice="D2Q9", n=(70, 37), eq="nse", rho0=1.0,
