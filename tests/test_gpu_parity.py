@@ -69,6 +69,9 @@ CASES = [
          kind="three_level", a=TRT[0], ah=TRT[1]),
     dict(name="d3q19-nse-trt-zchunks", lattice="D3Q19", n=(34, 10, 70), eq="nse", rho0=1.0,
          kind="three_level", a=TRT[0], ah=TRT[1]),
+    dict(name="d3q19-nse-2l-srt", lattice="D3Q19", n=(9, 7, 5), eq="nse", rho0=1.0, a=(1.0, 0.0, 0.0)),
+    dict(name="d3q19-nse-trt-wide", lattice="D3Q19", n=(70, 33, 6), eq="nse", rho0=1.0,
+         kind="three_level", a=TRT[0], ah=TRT[1]),
     dict(name="d3q19-nse-3l-stencil", lattice="D3Q19", n=(35, 19, 13), eq="nse", rho0=1.0,
          kind="three_level", a=EX13[0], ah=EX13[1]),
     dict(name="d3q19-nse-mesofd", lattice="D3Q19", n=(35, 19, 13), eq="nse", rho0=1.0,
