@@ -428,7 +428,7 @@ def main():
     traffic = stored_traffic(kernel_src, tb, h)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=("k_lcde_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
+                    kernel=("k_mmfd_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
                     launch_ms_mean=round(mean_ms, 5), launch_timing=how,
                     time_steps_per_launch=tb, window_rows=h, algorithmic_bytes_per_launch=alg_bytes,
                     measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None))

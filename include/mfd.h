@@ -280,11 +280,13 @@ int mfd_batch_plan(const mfd_batch *b, int32_t group, int32_t *tb_depth, int32_t
 
 /* A server runs MMFD solves submitted by any thread with continuous
  * batching: a scheduler thread advances all admitted requests together in
- * quanta of `quantum_steps` steps (one batched launch per step), admits
- * queued requests (arrival order) whenever a slot and the HBM budget allow,
- * while the previous quantum is on the GPU, and retires finished requests by
- * copying their final level to the caller's buffer.  Each request's result
- * equals the solve of the same request alone. */
+ * quanta of `quantum_steps` steps (a batch run per quantum: one launch per
+ * step, or per blocked group of steps for two-level linear CDE / Burgers
+ * kinds, whose plan the batch autotuner picks on the first quantum that holds
+ * the kind), admits queued requests (arrival order) whenever a slot and the
+ * HBM budget allow, while the previous quantum is on the GPU, and retires
+ * finished requests by copying their final level to the caller's buffer.
+ * Each request's result equals the solve of the same request alone. */
 typedef struct mfd_server mfd_server;
 
 typedef struct {

@@ -50,6 +50,15 @@ void Batch::free_groups() {
   groups.clear();
 }
 
+BatchKey batch_key_of(const Solver *s) {
+  return BatchKey{s->consts.lattice, s->consts.eq, s->consts.three, s->consts.three_stencil,
+                  s->grid.precision, s->consts.eq == kBurgers && s->consts.beta_one ? 1 : 0};
+}
+
+bool batch_blockable(const BatchKey &k) {
+  return !k.three && (k.eq == kLCDE || k.eq == kBurgers) && (k.lattice == MFD_D2Q5 || k.lattice == MFD_D2Q9);
+}
+
 static int tile_ty(int eq) { return eq == kNSE ? kBatchTYNse : kBatchTY; }
 
 static int elem_of(const BatchKey &k) { return k.precision == MFD_FP64 ? 8 : 4; }
@@ -106,10 +115,7 @@ int Batch::build() {
   }
   std::map<BatchKey, std::vector<int>> by_key;
   for (int i = 0; i < (int)entries.size(); ++i) {
-    Solver *s = entries[i].s;
-    BatchKey k{s->consts.lattice, s->consts.eq, s->consts.three, s->consts.three_stencil,
-               s->grid.precision, s->consts.eq == kBurgers && s->consts.beta_one ? 1 : 0};
-    by_key[k].push_back(i);
+    by_key[batch_key_of(entries[i].s)].push_back(i);
   }
   max_steps = 0;
   lups_per_run = 0;
@@ -120,7 +126,7 @@ int Batch::build() {
     g.order = kv.second;
     std::stable_sort(g.order.begin(), g.order.end(),
                      [&](int a, int b) { return entries[a].nsteps > entries[b].nsteps; });
-    g.tb_ok = !g.key.three && tb_equation_supported(entries[g.order[0]].s->consts);
+    g.tb_ok = batch_blockable(g.key);
     if (g.tb_ok) {
       auto it = tuned.find(g.key);
       if (req.tb > 0) g.plan = req;

@@ -33,6 +33,10 @@ struct Group {
   std::vector<unsigned char> h_inst;
 };
 
+// group kind of a solver, and whether such groups can be temporally blocked
+BatchKey batch_key_of(const Solver *s);
+bool batch_blockable(const BatchKey &k);
+
 struct Batch {
   std::vector<BatchEntry> entries;
   std::vector<Group> groups;

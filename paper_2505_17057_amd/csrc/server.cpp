@@ -10,6 +10,8 @@
 //      the caller's buffer, stamps its completion time and frees its memory.
 // Requests that arrive while others are on the GPU therefore join at the next
 // quantum and their steps run in the same launches as the older requests.
+// The first quantum that holds a kind the blocked batch kernel takes runs the
+// batch autotuner once for that kind.
 // Latency is measured from submission to the moment the result is in the
 // caller's buffer.
 #include <hip/hip_runtime.h>
@@ -148,11 +150,17 @@ struct Server {
       std::vector<std::pair<Ticket *, int64_t>> advanced;  // (slot, steps)
       if (!active.empty()) {
         mfd_batch_clear(batch);
+        Batch *bp = reinterpret_cast<Batch *>(batch);
+        bool untuned = false;
         for (Ticket *t : active) {
           const int64_t k = std::min(quantum, t->remaining);
           mfd_batch_add(batch, t->solver, k, nullptr);
           advanced.push_back({t, k});
+          const BatchKey key = batch_key_of(reinterpret_cast<Solver *>(t->solver));
+          if (batch_blockable(key) && !bp->tuned.count(key)) untuned = true;
         }
+        // the first quantum holding a blockable kind picks its launch plan
+        if (untuned) mfd_batch_autotune(batch);
         if (mfd_batch_run(batch) == MFD_OK) ran = true;
       }
       // ---- admit while the quantum runs

@@ -19,7 +19,7 @@ echo "profile: WRITE_SIZE"
 N=4194304
 python3 -m paper_2505_17057_amd.profiling --trace "$O/prof_kt/kt_results.db" \
   --fetch "$O/prof_fetch/f_results.db" --write "$O/prof_write/w_results.db" \
-  --kernel k_lcde_tb --copy-bytes 268435456 \
+  --kernel k_mmfd_tb --copy-bytes 268435456 \
   --kernel-source paper_2505_17057_amd/csrc/kernels_tb.hip --bench-log "$O/prof_kt.txt" \
   --algorithmic-bytes-per-step $((8 * N)) --pass-bytes $((8 * N)) \
   --workload "2D linear CDE, D2Q9, 2048x2048, MMFD FP32 (bench.py headline)" \
