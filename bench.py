@@ -97,7 +97,7 @@ def launch_durations(torch, s, tb, n=1000):
     return a.elapsed_time(b) / n
 
 
-def stored_traffic(kernel_src, tb, h):
+def stored_traffic(kernel_src, tb, h, w):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source with the same launch plan."""
     path = os.path.join(ROOT, "profiles", "traffic_mmfd_lcde_d2q9_2048_fp32.json")
@@ -107,7 +107,7 @@ def stored_traffic(kernel_src, tb, h):
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     if info.get("kernel_source_sha256") != sha:
         return None
-    if (info.get("time_steps_per_launch"), info.get("window_rows")) != (tb, h):
+    if (info.get("time_steps_per_launch"), info.get("window_rows"), info.get("window_cols")) != (tb, h, w):
         return None
     return info.get("hbm_bytes_per_launch")
 
@@ -260,13 +260,13 @@ def bench_burgers_single(M, torch, I, stream):
     s.set_stream(stream.cuda_stream)
     s.set_state(c["phi0"].astype(np.float32))
     s.autotune()
-    tb, h = s.launch_plan()
+    tb, h, w = s.launch_plan()
     s.step(50)
     ms = timed(torch, lambda: s.step(1000))
     s.close()
     g = 2048 * 2048 * 1000 / (ms * 1e-3) / 1e9
     return dict(glups=round(g, 2), alg_gbs=round(g * 8, 1), frac_hbm=round(g * 8 / HBM_PEAK_GBS, 4),
-                bytes_per_lup=8, time_steps_per_launch=tb, window_rows=h)
+                bytes_per_lup=8, time_steps_per_launch=tb, window_rows=h, window_cols=w)
 
 
 def bench_batched(M, torch, I, stream):
@@ -395,7 +395,7 @@ def main():
     log("headline: 2048^2 MMFD FP32")
     s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
     s32.autotune()
-    tb, h = s32.launch_plan()
+    tb, h, w = s32.launch_plan()
     for _ in range(args.warmup):
         timed(torch, lambda: s32.step(TIME_STEPS))
         s32.reduce()
@@ -425,12 +425,13 @@ def main():
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc",
                               "kernels_tb.hip" if tb > 1 else "kernels_mmfd.hip")
-    traffic = stored_traffic(kernel_src, tb, h)
+    traffic = stored_traffic(kernel_src, tb, h, w)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=("k_mmfd_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
                     launch_ms_mean=round(mean_ms, 5), launch_timing=how,
-                    time_steps_per_launch=tb, window_rows=h, algorithmic_bytes_per_launch=alg_bytes,
+                    time_steps_per_launch=tb, window_rows=h, window_cols=w,
+                    algorithmic_bytes_per_launch=alg_bytes,
                     measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None))
     s32.close()
 

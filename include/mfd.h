@@ -205,11 +205,20 @@ int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
  * LDS <= 160 KiB); MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
+/* Force a full launch plan: tb_depth steps per launch over windows of
+ * window_rows x window_cols (64 or 128) nodes; tb_depth = 1 is one launch per
+ * step.  MFD_E_UNSUPPORTED when the blocked kernel cannot run it on this
+ * solver (see mfd_set_blocking; the grid needs at least window_cols x
+ * window_rows nodes), MFD_E_ORDER before the scheme is set. */
+int mfd_set_plan(mfd_solver *s, int32_t tb_depth, int32_t window_rows, int32_t window_cols);
+
 /* The launch plan mfd_step uses now: *tb_depth time steps per launch of the
- * step kernel (1 = one launch per step) and *window_rows, the height of the
- * temporally blocked kernel's LDS window (0 when tb_depth is 1).  Either
- * pointer may be NULL.  MFD_E_ORDER before the scheme is set. */
-int mfd_launch_plan(const mfd_solver *s, int32_t *tb_depth, int32_t *window_rows);
+ * step kernel (1 = one launch per step), *window_rows and *window_cols, the
+ * height and width of the temporally blocked kernel's LDS window (0 when
+ * tb_depth is 1).  Any pointer may be NULL.  MFD_E_ORDER before the scheme
+ * is set. */
+int mfd_launch_plan(const mfd_solver *s, int32_t *tb_depth, int32_t *window_rows,
+                    int32_t *window_cols);
 
 /* ---------------------------------------------------------------- batches */
 

@@ -36,7 +36,7 @@ int default_h(const Solver &s, int tb) {
   static const int hs[] = {96, 80, 64, 48, 32};
   for (int h : hs) {
     const TbPlan p{tb, h};
-    if (tb_lds_bytes(s.consts, h, (int)s.elem()) * 3 <= 160 * 1024 &&
+    if (tb_lds_bytes(s.consts, p, (int)s.elem()) * 3 <= 160 * 1024 &&
         tb_supported(s.consts, s.G, p, (int)s.elem()))
       return h;
   }
@@ -103,14 +103,16 @@ int Solver::autotune(int32_t *chosen) {
   trial = trial < 24 ? 24 : (trial > 480 ? 480 : trial);
   trial = (trial / 24) * 24;
   const int depths[] = {1, 2, 4, 6, 8};
-  const int heights[] = {48, 64, 80, 96, 112, 128};
+  const int heights[] = {32, 48, 64, 80, 96, 112, 128};
+  const int widths[] = {64, 128};
   float best_ms = 1e30f;
   TbPlan best{1, 0};
   for (int d : depths) {
+    for (int w : widths)
     for (int h : heights) {
       if (rc) break;
-      TbPlan p{d, d == 1 ? 0 : h};
-      if (d == 1 && h != heights[0]) continue;
+      TbPlan p{d, d == 1 ? 0 : h, w};
+      if (d == 1 && (h != heights[0] || w != widths[0])) continue;
       if (d > 1 && !tb_supported(consts, G, p, (int)elem())) continue;
       tb = d;
       tuned = p;

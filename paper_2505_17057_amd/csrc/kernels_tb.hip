@@ -222,25 +222,34 @@ __global__ __launch_bounds__(W *RG) void k_batch_tb(const BatchInst<T> *__restri
 
 namespace {
 
-// Window: W = 64 columns (one per thread, a wavefront reads one LDS row),
-// H rows in RG = 4 row groups; the tile advanced is (W - 2 TB) x (H - 2 TB).
+// Window: W = 64 or 128 columns (one per thread; a wavefront reads 64
+// consecutive LDS words of a row), H rows in RG = 4 row groups; the tile
+// advanced is (W - 2 TB) x (H - 2 TB).  The batched kernel uses W = 64.
 constexpr int kTbW = 64, kTbRG = 4;
+
+template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, int W, typename T>
+hipError_t tb_cfg_w(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
+                    T *oc, T *op, hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  const int TX = W - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = (size_t)(THREE ? 3 : 2) * pl.h * W * sizeof(T);
+  auto fn = k_mmfd_tb<L, EQ, THREE, THREE_ST, W, kTbRG, B1, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(W * kTbRG), lds, st, cur, prev, oc, op, nx, ny,
+                     pl.h, pl.tb, tx, tx * ty, kc);
+  return hipGetLastError();
+}
 
 template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, typename T>
 hipError_t tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
                   T *oc, T *op, hipStream_t st) {
-  const KC<T> kc = make_kc<T>(c);
-  const int nx = (int)g.n[0], ny = (int)g.n[1];
-  const int TX = kTbW - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
-  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
-  const size_t lds = (size_t)(THREE ? 3 : 2) * pl.h * kTbW * sizeof(T);
-  auto fn = k_mmfd_tb<L, EQ, THREE, THREE_ST, kTbW, kTbRG, B1, T>;
-  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kTbW * kTbRG), lds, st, cur, prev, oc, op, nx, ny,
-                     pl.h, pl.tb, tx, tx * ty, kc);
-  return hipGetLastError();
+  if (pl.w == 128)
+    return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 128, T>(c, g, pl, cur, prev, oc, op, st);
+  return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 64, T>(c, g, pl, cur, prev, oc, op, st);
 }
 
 template <class L, int EQ, bool B1, typename T>
@@ -277,14 +286,15 @@ hipError_t btb_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, i
 
 }  // namespace
 
-size_t tb_lds_bytes(const Consts &c, int h, int elem) {
-  return (size_t)(c.three ? 3 : 2) * h * kTbW * elem;
+size_t tb_lds_bytes(const Consts &c, const TbPlan &pl, int elem) {
+  return (size_t)(c.three ? 3 : 2) * pl.h * pl.w * elem;
 }
 
 bool tb_plan_valid(const TbPlan &pl, int levels, int elem) {
+  if (pl.w != 64 && pl.w != 128) return false;
   if (pl.tb < 1 || pl.tb > 16 || pl.h < 2 * pl.tb + 4) return false;
-  if (kTbW - 2 * pl.tb < 8) return false;
-  return (size_t)levels * pl.h * kTbW * elem <= 160 * 1024;
+  if (pl.w - 2 * pl.tb < 8) return false;
+  return (size_t)levels * pl.h * pl.w * elem <= 160 * 1024;
 }
 
 bool tb_equation_supported(const Consts &c) {
@@ -295,7 +305,7 @@ bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
   if (!tb_equation_supported(c)) return false;
   if (!tb_plan_valid(pl, c.three ? 3 : 2, elem)) return false;
   // one conditional wrap per coordinate covers the window
-  return g.n[0] >= kTbW && g.n[1] >= pl.h;
+  return g.n[0] >= pl.w && g.n[1] >= pl.h;
 }
 
 template <typename T>
@@ -311,7 +321,7 @@ int tb_window_cols() { return kTbW; }
 template <typename T>
 hipError_t launch_batch_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                            int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st) {
-  if (k.three) return hipErrorInvalidValue;
+  if (k.three || pl.w != kTbW) return hipErrorInvalidValue;
   if (k.lattice == 3) {
     if (k.eq == kLCDE)
       return btb_cfg<LatD2Q9, kLCDE, false, T>(inst, tile_inst, ntiles, launch, pl, st);

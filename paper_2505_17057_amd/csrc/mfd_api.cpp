@@ -540,13 +540,34 @@ extern "C" int mfd_set_blocking(mfd_solver *h, int32_t tb_depth) {
   return MFD_OK;
 }
 
-extern "C" int mfd_launch_plan(const mfd_solver *h, int32_t *tb_depth, int32_t *window_rows) {
+extern "C" int mfd_set_plan(mfd_solver *h, int32_t tb_depth, int32_t window_rows,
+                            int32_t window_cols) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->configured) return s->fail(MFD_E_ORDER, "set the scheme first");
+  if (tb_depth == 1) {
+    s->tb = 1;
+    return MFD_OK;
+  }
+  const TbPlan p{tb_depth, window_rows, window_cols};
+  if (s->grid.form != MFD_MMFD || s->cfg.kind == MFD_THETA ||
+      !tb_supported(s->consts, s->G, p, (int)s->elem()))
+    return s->fail(MFD_E_UNSUPPORTED, "plan (%d, %d, %d) cannot be used by this configuration",
+                   tb_depth, window_rows, window_cols);
+  s->tb = tb_depth;
+  s->tuned = p;
+  return MFD_OK;
+}
+
+extern "C" int mfd_launch_plan(const mfd_solver *h, int32_t *tb_depth, int32_t *window_rows,
+                               int32_t *window_cols) {
   if (!h) return MFD_E_ARG;
   const Solver *s = reinterpret_cast<const Solver *>(h);
   if (!s->configured) return MFD_E_ORDER;
   const TbPlan p = s->effective_plan();
   if (tb_depth) *tb_depth = p.tb;
   if (window_rows) *window_rows = p.tb > 1 ? p.h : 0;
+  if (window_cols) *window_cols = p.tb > 1 ? p.w : 0;
   return MFD_OK;
 }
 

@@ -115,10 +115,11 @@ bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
 // three-level), writes t + tb (out_cur) and, for three-level schemes,
 // t + tb - 1 (out_prev).
 struct TbPlan {
-  int tb;  // steps per launch
-  int h;   // window rows
+  int tb;       // steps per launch
+  int h;        // window rows
+  int w = 64;   // window columns: 64 or 128 (one thread per column)
 };
-size_t tb_lds_bytes(const Consts &c, int h, int elem);
+size_t tb_lds_bytes(const Consts &c, const TbPlan &pl, int elem);
 // plan limits (depth, window height, LDS) for `levels` LDS levels
 bool tb_plan_valid(const TbPlan &pl, int levels, int elem);
 // equations / lattices the blocked kernels implement

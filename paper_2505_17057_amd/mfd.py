@@ -87,7 +87,8 @@ _SIGS = {
     "mfd_reduce": ([_H, _PD, _PD], C.c_int),
     "mfd_autotune": ([_H, C.POINTER(C.c_int32)], C.c_int),
     "mfd_set_blocking": ([_H, C.c_int32], C.c_int),
-    "mfd_launch_plan": ([_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "mfd_set_plan": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "mfd_launch_plan": ([_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "mfd_coeff_moments": ([_PD, _PD, _PD], C.c_int),
     "mfd_coeffs_from_constraints": ([C.c_double] * 5 + [_PD, _PD], C.c_int),
     "mfd_preset": ([C.c_int, C.c_double, _PD, _PD], C.c_int),
@@ -283,11 +284,15 @@ class Solver:
     def set_blocking(self, depth):
         return self.check(lib.mfd_set_blocking(self.h, int(depth)), "mfd_set_blocking")
 
+    def set_plan(self, tb_depth, window_rows=0, window_cols=64):
+        return self.check(lib.mfd_set_plan(self.h, int(tb_depth), int(window_rows), int(window_cols)),
+                          "mfd_set_plan")
+
     def launch_plan(self):
-        """(time steps per launch, LDS window rows) of the current plan."""
-        tb, h = C.c_int32(), C.c_int32()
-        self.check(lib.mfd_launch_plan(self.h, C.byref(tb), C.byref(h)), "mfd_launch_plan")
-        return tb.value, h.value
+        """(time steps per launch, LDS window rows, LDS window columns)."""
+        tb, h, w = C.c_int32(), C.c_int32(), C.c_int32()
+        self.check(lib.mfd_launch_plan(self.h, C.byref(tb), C.byref(h), C.byref(w)), "mfd_launch_plan")
+        return tb.value, h.value, w.value
 
     def autotune(self):
         d = C.c_int32()

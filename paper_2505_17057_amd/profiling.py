@@ -76,12 +76,13 @@ def copy_factor(db_path, counter, copy_bytes):
 
 
 def bench_plan(log_path):
-    """(tb, h, launch_ms_mean) from the JSON line a bench run printed."""
+    """(tb, h, w, launch_ms_mean) from the JSON line a bench run printed."""
     for line in open(log_path):
         line = line.strip()
         if line.startswith("{") and '"roofline"' in line:
             r = json.loads(line)["roofline"]
-            return r["time_steps_per_launch"], r.get("window_rows", 0), r.get("launch_ms_mean")
+            return (r["time_steps_per_launch"], r.get("window_rows", 0), r.get("window_cols", 64),
+                    r.get("launch_ms_mean"))
     raise SystemExit("no bench JSON line in " + log_path)
 
 
@@ -123,7 +124,7 @@ def main(argv=None):
 
     stats = kernel_stats(a.trace)
     grids = kernel_grids(a.trace, a.kernel)
-    tb, h, ev_ms = bench_plan(a.bench_log)
+    tb, h, w, ev_ms = bench_plan(a.bench_log)
     a.algorithmic_bytes = a.algorithmic_bytes_per_step * tb
     main_grid = max(grids, key=lambda g: grids[g][0])  # the timed plan launches most often
     ff, fvals = copy_factor(a.fetch, "FETCH_SIZE", a.copy_bytes)
@@ -136,7 +137,7 @@ def main(argv=None):
     sha = hashlib.sha256(open(a.kernel_source, "rb").read()).hexdigest()
     calls, mean_ns = grids[main_grid]
     rec = dict(kernel=a.kernel, workload=a.workload, kernel_source=a.kernel_source,
-               kernel_source_sha256=sha, time_steps_per_launch=tb, window_rows=h,
+               kernel_source_sha256=sha, time_steps_per_launch=tb, window_rows=h, window_cols=w,
                grid_threads=main_grid, dispatches=calls, trace_mean_us=round(mean_ns / 1e3, 3),
                fetch_kib_raw=statistics.fmean(fk), write_kib_raw=statistics.fmean(wk),
                fetch_factor=round(ff, 5), write_factor=round(wf, 5),
@@ -162,9 +163,9 @@ def main(argv=None):
         L.append("| %s | %d | %.3f | %.3f | %.3f | %.1f%% |" % (n[:90], c, m / 1e3, lo / 1e3, hi / 1e3,
                                                                100.0 * t / total))
     L.append("")
-    L.append("Timed plan of `%s`: %d time steps per launch, LDS window %d rows, grid %d threads, "
-             "%d dispatches, mean %.3f us (trace); the bench's own HIP-event mean over its timed "
-             "region: %s us.\n" % (a.kernel, tb, h, main_grid, calls, mean_ns / 1e3,
+    L.append("Timed plan of `%s`: %d time steps per launch, LDS window %d x %d (rows x columns), "
+             "grid %d threads, %d dispatches, mean %.3f us (trace); the bench's own HIP-event mean "
+             "over its timed region: %s us.\n" % (a.kernel, tb, h, w, main_grid, calls, mean_ns / 1e3,
                                   "%.3f" % (ev_ms * 1e3) if ev_ms else "n/a"))
     L.append("## HBM counters (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, KiB per dispatch)\n")
     L.append("| dispatch | FETCH_SIZE KiB | WRITE_SIZE KiB |")

@@ -64,6 +64,40 @@ def test_blocked_fp64_bitwise(M, tb, name, n):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
+@pytest.mark.parametrize("plan", [(4, 40, 128), (8, 48, 128), (2, 50, 128), (3, 32, 64)])
+@pytest.mark.parametrize("name", ALL)
+def test_explicit_plans_fp64_bitwise(M, plan, name):
+    """Explicit launch plans, including 128-column windows, equal the oracle."""
+    from parity_util import make_solver
+    case = _case(name, (150, 77))
+    print("case", name, plan, flush=True)
+    rng = np.random.default_rng(15)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    steps = 2 * plan[0] + 3
+    want = run_oracle(case, cur, prev, steps)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    assert s.launch_plan() == plan
+    s.set_state(cur)
+    if case.get("kind") == "three_level":
+        s.set_state(prev, level=1)
+    s.step(steps)
+    got = s.get_state()
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+def test_plan_rejections(M):
+    from parity_util import make_solver
+    s = make_solver(M, _case("2l", (100, 77)), "fp32")
+    for plan in ((4, 40, 128), (4, 80, 64), (4, 40, 96), (30, 80, 64), (4, 9, 64)):
+        with pytest.raises(M.MfdError):
+            s.set_plan(*plan)
+    s.set_plan(1)
+    assert s.launch_plan() == (1, 0, 0)
+    s.close()
+
+
 @pytest.mark.parametrize("name", ALL)
 def test_blocked_fp32_equals_unblocked(M, name):
     from parity_util import make_solver
@@ -95,8 +129,8 @@ def test_autotune_preserves_state(M):
     before = s.get_state()
     d = s.autotune()
     assert d in (1, 2, 4, 6, 8)
-    tb, h = s.launch_plan()
-    assert tb == d and (h == 0) == (d == 1)
+    tb, h, w = s.launch_plan()
+    assert tb == d and (h == 0) == (d == 1) and w in ((0,) if d == 1 else (64, 128))
     assert np.array_equal(s.get_state(), before)
     s.step(9)
     ref = make_solver(M, case, "fp64")
