@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
     p.add_argument("--serve-requests", type=int, default=300)
+    p.add_argument("--plan", default="",
+                   help="tb,rows,cols: run the headline with this launch plan instead of autotuning "
+                        "(used to profile counters on the plan an earlier run chose)")
     return p.parse_args()
 
 
@@ -98,18 +101,19 @@ def launch_durations(torch, s, tb, n=1000):
 
 
 def stored_traffic(kernel_src, tb, h, w):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source with the same launch plan."""
+    """(HBM bytes per launch, profiled plan) from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source with the
+    same steps per launch (the window shape changes only halo re-reads, which
+    the profiled plan states); else (None, None)."""
     path = os.path.join(ROOT, "profiles", "traffic_mmfd_lcde_d2q9_2048_fp32.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     info = json.load(open(path))
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if info.get("kernel_source_sha256") != sha:
-        return None
-    if (info.get("time_steps_per_launch"), info.get("window_rows"), info.get("window_cols")) != (tb, h, w):
-        return None
-    return info.get("hbm_bytes_per_launch")
+    if info.get("kernel_source_sha256") != sha or info.get("time_steps_per_launch") != tb:
+        return None, None
+    plan = [info.get("time_steps_per_launch"), info.get("window_rows"), info.get("window_cols")]
+    return info.get("hbm_bytes_per_launch"), plan
 
 
 def cpu_baseline(cfg, budget_s=15.0):
@@ -394,7 +398,10 @@ def main():
     # ---------------------------------------------------------- headline
     log("headline: 2048^2 MMFD FP32")
     s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
-    s32.autotune()
+    if args.plan:
+        s32.set_plan(*[int(v) for v in args.plan.split(",")])
+    else:
+        s32.autotune()
     tb, h, w = s32.launch_plan()
     for _ in range(args.warmup):
         timed(torch, lambda: s32.step(TIME_STEPS))
@@ -425,14 +432,15 @@ def main():
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc",
                               "kernels_tb.hip" if tb > 1 else "kernels_mmfd.hip")
-    traffic = stored_traffic(kernel_src, tb, h, w)
+    traffic, traffic_plan = stored_traffic(kernel_src, tb, h, w)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=("k_mmfd_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
                     launch_ms_mean=round(mean_ms, 5), launch_timing=how,
                     time_steps_per_launch=tb, window_rows=h, window_cols=w,
                     algorithmic_bytes_per_launch=alg_bytes,
-                    measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None))
+                    measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None),
+                    traffic_plan=traffic_plan)
     s32.close()
 
     extra = {}

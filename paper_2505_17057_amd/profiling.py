@@ -25,6 +25,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import os
 import shlex
 import sqlite3
 import sys
@@ -100,8 +101,14 @@ def stats_table(db_path, top=15):
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     if argv and argv[0] == "stats":
-        # python -m paper_2505_17057_amd.profiling stats RESULTS.db [TOP]
-        print(stats_table(argv[1], int(argv[2]) if len(argv) > 2 else 15))
+        # python -m paper_2505_17057_amd.profiling stats RESULTS.db [TOP] [TITLE] [COMMAND]
+        top = int(argv[2]) if len(argv) > 2 else 15
+        if len(argv) > 3:
+            print("# rocprofv3 kernel trace: %s\n" % argv[3])
+        if len(argv) > 4:
+            print("Command (from the repository root; `cd /tmp && export TMPDIR=/tmp` first):\n")
+            print("    " + argv[4] + "\n")
+        print(stats_table(argv[1], top))
         return
     p = argparse.ArgumentParser()
     p.add_argument("--trace", required=True)
@@ -120,7 +127,9 @@ def main(argv=None):
     p.add_argument("--out-json", required=True)
     p.add_argument("--command", action="append", default=[], help="command that produced an input")
     a = p.parse_args(argv)
-    a.command = a.command + ["python -m paper_2505_17057_amd.profiling " + shlex.join(argv)]
+    here = os.getcwd() + os.sep
+    a.command = a.command + ["python -m paper_2505_17057_amd.profiling " +
+                             shlex.join(x.replace(here, "") for x in argv)]
 
     stats = kernel_stats(a.trace)
     grids = kernel_grids(a.trace, a.kernel)
