@@ -4,6 +4,12 @@ Argument marshalling only: every step of the method runs in the HIP library.
 The functions keep the C names; `Solver` is a thin owner of one handle.
 Importing this module raises if the built library is missing -- there is no
 fallback path.
+
+PyTorch, when installed, is imported before the library is loaded: PyTorch
+ships its own HIP runtime, and the library must resolve to that same runtime
+instance so that torch's streams and device pointers are valid in its calls
+(two HIP runtimes in one process do not share stream objects, and whichever
+initialises the GPU second may find no device).
 """
 from __future__ import annotations
 
@@ -11,6 +17,11 @@ import ctypes as C
 import os
 
 import numpy as np
+
+try:  # share PyTorch's HIP runtime (see above)
+    import torch  # noqa: F401
+except ImportError:  # the library then uses the system HIP runtime
+    torch = None
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmfd.so")

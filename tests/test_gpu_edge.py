@@ -1,0 +1,137 @@
+"""GPU: checkpoint / resume, degenerate calls and ordering errors.
+
+* A run of N steps equals k steps, a checkpoint of the live levels (and the
+  MesoFD populations) into host memory, a fresh solver restored from it, and
+  N - k more steps: bit for bit, in every form and level count.
+* Zero steps change nothing; empty batches and zero-step batch members run;
+  a zero-step request comes back unchanged from the server.
+* Calls out of order fail with MFD_E_ORDER, bad sizes with MFD_E_ARG.
+"""
+import numpy as np
+import pytest
+
+from parity_util import make_solver, rand_state, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+K2 = [[0.3, 0.04], [0.04, 0.2]]
+TRT = ((1.0, 0.0, 0.4), (0.0, -0.4, 0.0))
+EX13 = ((0.875, 0.0, 0.125), (0.125, 0.0, -0.125))
+
+CASES = [
+    dict(name="lcde-2l-blocked", lattice="D2Q9", n=(150, 77), eq="lcde", u=(0.1, -0.07), K=K2,
+         lambda_bar=1, a=(1.0, 0.0, 0.0), plan=(4, 40, 64)),
+    dict(name="lcde-3l-blocked", lattice="D2Q9", n=(150, 77), eq="lcde", u=(0.1, -0.07), K=K2,
+         lambda_bar=1, kind="three_level", a=EX13[0], ah=EX13[1], plan=(6, 48, 128)),
+    dict(name="nse-trt", lattice="D2Q9", n=(70, 37), eq="nse", rho0=1.0, kind="three_level",
+         a=TRT[0], ah=TRT[1]),
+    dict(name="nse-d3q19", lattice="D3Q19", n=(20, 13, 9), eq="nse", rho0=1.0, kind="three_level",
+         a=TRT[0], ah=TRT[1]),
+    dict(name="mesofd-nse-3l", lattice="D2Q9", n=(40, 33), eq="nse", rho0=1.0, kind="three_level",
+         a=TRT[0], ah=TRT[1], form="mesofd"),
+    dict(name="mesofd-lcde", lattice="D2Q9", n=(40, 33), eq="lcde", u=(0.1, -0.07), K=K2,
+         lambda_bar=1, a=(1.0, 0.0, 0.0), form="mesofd"),
+]
+
+
+def _new(M, case, precision):
+    s = make_solver(M, case, precision)
+    if "plan" in case:
+        s.set_plan(*case["plan"])
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c["name"])
+def test_checkpoint_resume(M, case, precision):
+    print("case", case["name"], precision, flush=True)
+    rng = np.random.default_rng(21)
+    dt = np.float64 if precision == "fp64" else np.float32
+    cur, prev = rand_state(case, rng).astype(dt), rand_state(case, rng).astype(dt)
+    three = case.get("kind") == "three_level"
+    meso = case.get("form") == "mesofd"
+    N, k = 23, 9
+    a = _new(M, case, precision)
+    a.set_state(cur)
+    if three:
+        a.set_state(prev, level=1)
+    a.step(N)
+    want = a.get_state()
+    a.close()
+    b = _new(M, case, precision)
+    b.set_state(cur)
+    if three:
+        b.set_state(prev, level=1)
+    b.step(k)
+    ck0 = b.get_state(populations=meso)
+    ck1 = b.get_state(level=1) if three else None
+    b.close()
+    c = _new(M, case, precision)
+    c.set_state(ck0, populations=meso)
+    if three:
+        c.set_state(ck1, level=1)
+    c.step(N - k)
+    got = c.get_state()
+    c.close()
+    assert np.array_equal(got, want)
+    if precision == "fp64":
+        assert np.array_equal(got, run_oracle(case, cur.astype(np.float64), prev.astype(np.float64), N))
+
+
+def test_zero_steps_and_order_errors(M):
+    case = CASES[0]
+    s = make_solver(M, case, "fp64")
+    with pytest.raises(M.MfdError) as e:
+        s.step(1)
+    assert e.value.code == M.MFD_E_ORDER
+    with pytest.raises(M.MfdError) as e:
+        s.get_state()
+    assert e.value.code == M.MFD_E_ORDER
+    with pytest.raises(M.MfdError) as e:
+        s.set_state(np.zeros(7))
+    assert e.value.code == M.MFD_E_ARG
+    with pytest.raises(M.MfdError) as e:
+        s.set_state(np.zeros(150 * 77), level=1)  # two-level schemes hold one level
+    assert e.value.code == M.MFD_E_ARG
+    x = np.random.default_rng(3).standard_normal(150 * 77)
+    s.set_state(x)
+    s.step(0)
+    assert np.array_equal(s.get_state(), x)
+    with pytest.raises(M.MfdError) as e:
+        s.step(-1)
+    assert e.value.code == M.MFD_E_ARG
+    s.close()
+
+
+def test_empty_and_zero_step_batches(M):
+    b = M.Batch()
+    b.run()
+    b.autotune()
+    b.wait()
+    assert b.stats()["launches"] == 0
+    case = CASES[0]
+    s = make_solver(M, case, "fp32")
+    x = np.random.default_rng(4).standard_normal(150 * 77).astype(np.float32)
+    s.set_state(x)
+    b.add(s, 0)
+    b.run()
+    b.wait()
+    assert np.array_equal(s.get_state(), x)
+    assert b.stats()["launches"] == 0
+    b.close()
+    s.close()
+
+
+def test_server_zero_step_request(M):
+    case = dict(lattice="D2Q9", eq="burgers", n=(40, 30), dx=0.025, dt=0.01, a=(0.6, 0.1, 0.3))
+    st = np.random.default_rng(5).uniform(-0.5, 0.5, 1200).astype(np.float32)
+    out = np.full_like(st, np.nan)
+    srv = M.Server(hbm_budget_bytes=1 << 28, max_slots=4, quantum_steps=8)
+    req = M.make_request("D2Q9", "burgers", case["n"], case["dx"], case["dt"], case["a"], 0, st,
+                         precision="fp32", result_out=out)
+    t = srv.submit(req, keep=(st, out))
+    srv.drain(30)
+    state, _, rc = srv.poll(t)
+    assert state == 2 and rc == 0
+    assert np.array_equal(out, st)
+    srv.close()

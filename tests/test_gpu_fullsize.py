@@ -1,0 +1,214 @@
+"""GPU: parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (autotuned plans), on prefixes of the runs the oracle can
+afford, and properties that hold at any size where it cannot.
+
+* 2048^2 linear CDE (the headline workload): FP64 bit-exact with the oracle
+  after two blocked launches' worth of steps plus a ragged remainder; FP32
+  within 1e-5 (rel. L2) of the oracle.
+* 2048^2 MesoFD FP64: populations-carried moments bit-exact with the oracle.
+* 4096^2 NSE three-level TRT: FP64 bit-exact, FP32 within 1e-5.
+* 512^3 NSE (D3Q19): mass and momentum conserved by the FP64 step (the
+  periodic sum of the central-difference form), FP32 within 1e-6 of FP64.
+* 256 Burgers grids: the autotuned blocked batch equals every grid stepped
+  alone (FP32, bit for bit), and the smallest grids equal the oracle (FP64).
+"""
+import numpy as np
+import pytest
+
+import mfd_inputs as I
+from oracle import native as O
+from oracle import scheme as S
+
+pytestmark = pytest.mark.gpu
+
+D0 = 1.0 / 3.0
+
+
+def _c2_spec(c):
+    return dict(lattice="D2Q9", n=c["n"], dx=c["dx"], dt=c["dt"], u=c["u"], K=c["K"], lambda_bar=1,
+                a=S.preset_srt()[0])
+
+
+def _c2_solver(M, c, precision, form="mmfd"):
+    s = M.Solver("D2Q9", c["n"], c["dx"], precision, form)
+    s.set_equation("lcde", u=c["u"], K=c["K"], lambda_bar=1)
+    s.set_scheme("two_level", M.mfd_preset("srt")[0], dt=c["dt"])
+    return s
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return I.c2_hill_2d(n=2048)
+
+
+def test_headline_fp64_bitwise(M, c2):
+    steps = 19
+    want = c2["phi0"]
+    spec = _c2_spec(c2)
+    for _ in range(steps):
+        want = O.mmfd_step(spec, want)
+    s = _c2_solver(M, c2, "fp64")
+    s.set_state(c2["phi0"])
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got = s.get_state()
+    s.close()
+    assert np.array_equal(got, want)
+
+
+def test_headline_fp32_within_tolerance(M, c2):
+    steps = 19
+    x32 = c2["phi0"].astype(np.float32)
+    want = x32.astype(np.float64)
+    spec = _c2_spec(c2)
+    for _ in range(steps):
+        want = O.mmfd_step(spec, want)
+    s = _c2_solver(M, c2, "fp32")
+    s.set_state(x32)
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    assert _rel(got, want) <= 1e-5
+
+
+def test_mesofd_fp64_bitwise(M, c2):
+    steps = 3
+    spec = _c2_spec(c2)
+    pop = O.init_populations(spec, c2["phi0"])
+    for _ in range(steps):
+        pop, _ = O.mesofd_step(spec, pop, None)
+    want = O.moments(spec, pop)
+    s = _c2_solver(M, c2, "fp64", "mesofd")
+    s.set_state(c2["phi0"])
+    s.step(steps)
+    assert np.array_equal(s.get_state(), want)
+    assert np.array_equal(s.get_state(populations=True), pop)
+    s.close()
+
+
+def _nse(M, lat, c, precision):
+    s_ = 1.0 / (c["nu"] / (c["dt"] * D0 * (c["dx"] / c["dt"]) ** 2) + 0.5)
+    a, ah = M.mfd_preset("trt", s_)
+    s = M.Solver(lat, c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("nse", rho0=c["rho0"])
+    s.set_scheme("three_level", a, ah, dt=c["dt"])
+    spec = dict(lattice=lat, eq="nse", n=c["n"], dx=c["dx"], dt=c["dt"], rho0=c["rho0"], a=a, ah=ah,
+                levels=3)
+    return s, spec
+
+
+def test_nse_2d_4096(M):
+    c = I.tgv_2d(n=4096)
+    x32 = c["state0"].astype(np.float32)
+    x = x32.astype(np.float64)
+    s, spec = _nse(M, "D2Q9", c, "fp64")
+    steps = 2
+    cur, prev = x, x
+    for _ in range(steps):
+        cur, prev = O.mmfd_step(spec, cur, prev), cur
+    s.set_state(x)
+    s.step(steps)
+    assert np.array_equal(s.get_state(), cur)
+    assert np.array_equal(s.get_state(level=1), prev)
+    s.close()
+    s32, _ = _nse(M, "D2Q9", c, "fp32")
+    s32.set_state(x32)
+    s32.step(steps)
+    assert _rel(s32.get_state().astype(np.float64), cur) <= 1e-5
+    s32.close()
+
+
+def test_nse_3d_512_conservation(M):
+    import torch
+    c = I.tgv_3d(n=512, dtype=np.float32)
+    x32 = torch.from_numpy(c["state0"]).to("cuda")
+    del c["state0"]
+    N = 512 ** 3
+    s64, _ = _nse(M, "D3Q19", c, "fp64")
+    x64 = x32.double()
+    s64.set_state(x64)
+    sums0, _ = s64.reduce()
+    s64.step(2)
+    sums2, _ = s64.reduce()
+    y64 = torch.empty_like(x64)
+    s64.get_state(out=y64)
+    s64.close()
+    for f in range(4):
+        scale = float(x64[f * N:(f + 1) * N].abs().sum())
+        assert abs(sums2[f] - sums0[f]) <= 1e-12 * scale, (f, sums0[f], sums2[f])
+    s32, _ = _nse(M, "D3Q19", c, "fp32")
+    s32.set_state(x32)
+    s32.step(2)
+    y32 = torch.empty_like(x32)
+    s32.get_state(out=y32)
+    s32.close()
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(y32.double() - y64) / torch.linalg.vector_norm(y64))
+    assert err <= 1e-6, err
+
+
+def _burgers(M, c, precision):
+    s = M.Solver("D2Q9", c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("burgers")
+    sp = 2 * c["nu"] * c["dt"] / (D0 * c["dx"] ** 2)
+    a = ((sp + 1) / 2, 1 - sp, (sp - 1) / 2)
+    s.set_scheme("two_level", a, dt=c["dt"])
+    return s, a
+
+
+def test_batched_256_burgers(M):
+    insts = I.c4_batch(256, seed=4)
+    steps = [min(c["steps"], 13 + (i % 7)) for i, c in enumerate(insts)]  # ragged prefixes
+    solo = []
+    for c, n in zip(insts, steps):
+        s, _ = _burgers(M, c, "fp32")
+        s.set_blocking(1)
+        s.set_state(c["phi0"].astype(np.float32))
+        s.step(n)
+        solo.append(s.get_state())
+        s.close()
+    b = M.Batch()
+    solvers = []
+    for c, n in zip(insts, steps):
+        s, _ = _burgers(M, c, "fp32")
+        s.set_state(c["phi0"].astype(np.float32))
+        b.add(s, n)
+        solvers.append(s)
+    b.autotune()
+    b.run()
+    b.wait()
+    print("plan", b.plan(0), flush=True)
+    for i, (s, want) in enumerate(zip(solvers, solo)):
+        assert np.array_equal(s.get_state(), want), i
+    b.close()
+    for s in solvers:
+        s.close()
+    # FP64 batch against the oracle on the four smallest grids
+    small = sorted(range(256), key=lambda i: insts[i]["n"][0])[:4]
+    b = M.Batch()
+    b.set_plan(4, 48)
+    keep = []
+    for i in small:
+        c = insts[i]
+        s, a = _burgers(M, c, "fp64")
+        s.set_state(c["phi0"])
+        b.add(s, steps[i])
+        keep.append((i, s, a))
+    b.run()
+    b.wait()
+    for i, s, a in keep:
+        c = insts[i]
+        spec = dict(lattice="D2Q9", eq="burgers", n=c["n"], dx=c["dx"], dt=c["dt"], a=a)
+        want = c["phi0"]
+        for _ in range(steps[i]):
+            want = O.mmfd_step(spec, want)
+        assert np.array_equal(s.get_state(), want), i
+        s.close()
+    b.close()
