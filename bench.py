@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    p.add_argument("--sections", default="variants,big,c1,nse,burgers,batched,serving",
+    p.add_argument("--sections", default="variants,theta,big,c1,nse,burgers,batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
@@ -173,6 +173,33 @@ def bench_variants(M, torch, cfg, stream, N):
                             / np.linalg.norm(finals[("fp64", "mesofd")])))
     meso_vs_mmfd = float(np.abs(finals[("fp64", "mesofd")] - f64).max())
     return out, err, meso_vs_mmfd
+
+
+def bench_theta(M, torch, cfg, stream, N, theta=0.5, sweeps=4, steps=1000):
+    """theta scheme (linear CDE) on the headline grid: right-hand side plus
+    `sweeps` Jacobi sweeps per time step, FP32, and its error against the
+    FP64 run of the same steps."""
+    out = {}
+    finals = {}
+    for prec in ("fp32", "fp64"):
+        s = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
+        s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
+        s.set_scheme("theta", M.mfd_preset("srt")[0], theta=theta, theta_iters=sweeps, dt=cfg["dt"])
+        s.set_stream(stream.cuda_stream)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        s.step(10)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        ms = timed(torch, lambda: s.step(steps))
+        finals[prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = N * steps / (ms * 1e-3) / 1e9
+        bpl = (2 + 3 * sweeps) * (4 if prec == "fp32" else 8)  # rhs: read + write; sweep: 2 reads + write
+        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1), frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
+                         bytes_per_lup=bpl)
+    out.update(theta=theta, jacobi_sweeps=sweeps, steps=steps,
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
+                                         / np.linalg.norm(finals["fp64"])))
+    return out
 
 
 def bench_big(M, torch, I, stream):
@@ -456,6 +483,9 @@ def main():
         log("variants")
         extra["variants"], extra["fp32_rel_l2_vs_fp64_after_10000"], extra["mesofd_vs_mmfd_fp64_max_abs"] = \
             bench_variants(M, torch, cfg, stream, N)
+    if "theta" in sections:
+        log("theta")
+        extra["theta_d2q9_2048"] = bench_theta(M, torch, cfg, stream, N)
     if "big" in sections:
         log("8192^2")
         extra["hbm_resident_8192_mmfd_fp32"] = bench_big(M, torch, I, stream)

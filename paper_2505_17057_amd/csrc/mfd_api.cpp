@@ -144,7 +144,12 @@ int Solver::step_t(int64_t nsteps) {
   for (int64_t s = 0; s < nsteps; ++s) {
     hipError_t e;
     if (grid.form == MFD_MMFD) {
-      if (cfg.kind == MFD_THETA) {
+      if (cfg.kind == MFD_THETA && theta_fused_rows(consts, G, cfg.theta_iters, (int)sizeof(T))) {
+        e = launch_theta_fused<T>(consts, G, cfg.theta_iters, B[ic], B[io], stream);
+        if (e != hipSuccess) return hip(e, "fused theta launch");
+        std::swap(ic, io);
+        ip = io;
+      } else if (cfg.kind == MFD_THETA) {
         // rhs -> buf 5, sweeps alternate io / buf 6, final in io
         e = launch_theta_rhs<T>(consts, G, B[ic], B[5], stream);
         if (e != hipSuccess) return hip(e, "theta rhs launch");

@@ -144,6 +144,13 @@ hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom,
 template <typename T>
 hipError_t launch_moments(const Consts &c, const Grid &g, const T *pop, T *mom, hipStream_t st);
 
+// Fused theta step (2D): right-hand side and K Jacobi sweeps in one launch;
+// theta_fused_rows gives its window height, 0 when it cannot run.
+int theta_fused_rows(const Consts &c, const Grid &g, int K, int elem);
+template <typename T>
+hipError_t launch_theta_fused(const Consts &c, const Grid &g, int K, const T *cur, T *out,
+                              hipStream_t st);
+
 template <typename T>
 hipError_t launch_theta_rhs(const Consts &c, const Grid &g, const T *cur, T *rhs, hipStream_t st);
 template <typename T>
@@ -153,7 +160,7 @@ hipError_t launch_theta_sweep(const Consts &c, const Grid &g, const T *src, cons
 // FP64 reductions: sums of nf fields of `cur` and ||cur - prev||_2 of field 0
 // (prev may be null).  partial: >= kReduceBlocks * 8 doubles of scratch;
 // out: 8 doubles (device).
-constexpr int kReduceBlocks = 512;
+constexpr int kReduceBlocks = 2048;
 template <typename T>
 hipError_t launch_reduce(const T *cur, const T *prev, int nf, int64_t N, double *partial,
                          double *out, hipStream_t st);

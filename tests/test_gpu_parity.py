@@ -44,6 +44,13 @@ CASES = [
          lambda_bar=1, kind="three_level", a=EX13[0], ah=EX13[1], form="mesofd"),
     dict(name="d2q9-lcde-theta", lattice="D2Q9", n=(70, 37), eq="lcde", u=(0.05, -0.03), K=K2,
          lambda_bar=1, a=(0.8, -0.2, 0.4), kind="theta", theta=0.5, theta_iters=12),
+    dict(name="d2q9-lcde-theta-fused", lattice="D2Q9", n=(150, 77), eq="lcde", u=(0.05, -0.03), K=K2,
+         lambda_bar=1, a=(0.8, -0.2, 0.4), kind="theta", theta=0.5, theta_iters=4),
+    dict(name="d2q9-lcde-theta-fused-1", lattice="D2Q9", n=(64, 64), eq="lcde", u=(0.05, -0.03), K=K2,
+         lambda_bar=1, a=(0.8, -0.2, 0.4), kind="theta", theta=0.25, theta_iters=1),
+    dict(name="d2q5-lcde-theta-fused", lattice="D2Q5", n=(100, 70), eq="lcde", u=(0.1, 0.05),
+         K=[[0.2, 0.0], [0.0, 0.2]], lambda_bar=0, a=(0.8, -0.2, 0.4), kind="theta", theta=0.75,
+         theta_iters=3),
     # --- 2D nonlinear
     dict(name="d2q9-burgers-2l", lattice="D2Q9", n=(70, 37), eq="burgers", dx=0.05, dt=0.01,
          a=(0.8, -0.6, -0.2)),
