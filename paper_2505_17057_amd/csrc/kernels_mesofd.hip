@@ -268,6 +268,89 @@ __global__ __launch_bounds__(256) void k_mesofd_3d(const T *__restrict__ mom,
   }
 }
 
+// ------------------------------------------------ LDS-resident 1D run
+// One workgroup holds every level of a 1D grid in LDS and runs all steps (the
+// 1024-node workload is latency-bound): each step evaluates all b
+// populations of every node with the same node function as the tiled kernel,
+// into LDS, sums their moments into the next level, and on the last step
+// writes the populations to `pop`.  ga / gb: moments of levels t and t - dt
+// in, of the last two levels out.
+constexpr int kMesoResidentBytes = 96 * 1024;
+
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+__global__ __launch_bounds__(1024) void k_mesofd_1d_resident(T *__restrict__ ga,
+                                                             T *__restrict__ gb,
+                                                             T *__restrict__ pop, int nx,
+                                                             int64_t nsteps, KC<T> kc) {
+  extern __shared__ unsigned char smem_m1[];
+  using R = Rec<L, EQ>;
+  constexpr int NR = R::NR;
+  static_assert(R::NF == 1, "1D equations carry one moment");
+  // level k at L0 + k * nx (arithmetic on the LDS base keeps every access a
+  // local-data-share access)
+  T *const L0 = (T *)smem_m1;
+  auto lev = [&](int k) { return L0 + k * nx; };
+  T *rec = (T *)smem_m1 + 3 * nx;      // NR * nx
+  T *hrec = rec + NR * nx;             // NR * nx (older level with a stencil)
+  T *pl = hrec + NR * nx;              // Q * nx populations of the step
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    lev(0)[i] = ga[i];
+    lev(1)[i] = gb[i];
+  }
+  __syncthreads();
+  // the linear CDE's record is the moment itself (one barrier per step)
+  constexpr bool LIN = EQ == kLCDE;
+  int ic = 0, ip = 1, io = 2;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if constexpr (!LIN) {
+      for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        T m[1] = {lev(ic)[i]}, r[NR];
+        make_record<L, EQ>(m, r, kc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rec[k * nx + i] = r[k];
+        if constexpr (THREE_ST) {
+          m[0] = lev(ip)[i];
+          make_record<L, EQ>(m, r, kc);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) hrec[k * nx + i] = r[k];
+        }
+      }
+      __syncthreads();
+    }
+    const T *rc = LIN ? lev(ic) : rec;
+    const T *rh = LIN ? lev(ip) : hrec;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      auto idx = [&](int dx) {
+        const int j = i + dx;
+        return j < 0 ? j + nx : (j >= nx ? j - nx : j);
+      };
+      auto at = [&](int k, int, int, int dx) { return rc[k * nx + idx(dx)]; };
+      auto ath = [&](int k, int, int, int dx) {
+        if constexpr (THREE_ST) return rh[k * nx + idx(dx)];
+        else return T(0);
+      };
+      T hc[NR];
+      if constexpr (THREE && !THREE_ST) {
+        T m[1] = {lev(ip)[i]};
+        make_record<L, EQ>(m, hc, kc);
+      }
+      if (s + 1 < nsteps)  // populations of the step stay in LDS
+        mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pl, lev(io), nx, i, kc);
+      else  // the last step's go to HBM
+        mesofd_node<L, EQ, THREE_ST, T>(at, ath, hc, THREE, pop, lev(io), nx, i, kc);
+    }
+    __syncthreads();
+    const int t = ip;
+    ip = ic;
+    ic = io;
+    io = t;
+  }
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+    ga[i] = lev(ic)[i];
+    gb[i] = lev(ip)[i];
+  }
+}
+
 // ------------------------------------------------ init / moments kernels
 template <class L, int EQ, typename T>
 __global__ __launch_bounds__(256) void k_init_pop(const T *__restrict__ mom, T *__restrict__ pop,
@@ -407,6 +490,44 @@ hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, cons
   }
 }
 
+bool mesofd_1d_resident_fits(const Consts &c, const Grid &g, int elem) {
+  if (c.dim != 1 || c.eq == kNSE) return false;
+  const int nr = c.eq == kLCDE ? 1 : 2;
+  return (size_t)(3 + 2 * nr + 3) * g.n[0] * elem <= (size_t)kMesoResidentBytes;
+}
+
+namespace {
+template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
+hipError_t meso_res(const Consts &c, const Grid &g, T *ga, T *gb, T *pop, int64_t nsteps,
+                    hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0];
+  const size_t bytes = (size_t)(3 + 2 * Rec<L, EQ>::NR + L::Q) * nx * sizeof(T);
+  auto fn = k_mesofd_1d_resident<L, EQ, THREE, THREE_ST, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(1), dim3(1024), bytes, st, ga, gb, pop, nx, nsteps, kc);
+  return hipGetLastError();
+}
+template <int EQ, typename T>
+hipError_t meso_res_levels(const Consts &c, const Grid &g, T *ga, T *gb, T *pop, int64_t n,
+                           hipStream_t st) {
+  using L = LatD1Q3;
+  if (!c.three) return meso_res<L, EQ, false, false, T>(c, g, ga, gb, pop, n, st);
+  if (!c.three_stencil) return meso_res<L, EQ, true, false, T>(c, g, ga, gb, pop, n, st);
+  return meso_res<L, EQ, true, true, T>(c, g, ga, gb, pop, n, st);
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_mesofd_1d_resident(const Consts &c, const Grid &g, T *ga, T *gb, T *pop,
+                                     int64_t nsteps, hipStream_t st) {
+  if (c.eq == kLCDE) return meso_res_levels<kLCDE, T>(c, g, ga, gb, pop, nsteps, st);
+  if (c.eq == kBurgers) return meso_res_levels<kBurgers, T>(c, g, ga, gb, pop, nsteps, st);
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom, T *pop,
                                    hipStream_t st) {
@@ -435,7 +556,9 @@ hipError_t launch_moments(const Consts &c, const Grid &g, const T *pop, T *mom, 
                                             T *, T *, hipStream_t);                               \
   template hipError_t launch_init_populations<T>(const Consts &, const Grid &, const T *, T *,    \
                                                  hipStream_t);                                    \
-  template hipError_t launch_moments<T>(const Consts &, const Grid &, const T *, T *, hipStream_t);
+  template hipError_t launch_moments<T>(const Consts &, const Grid &, const T *, T *, hipStream_t); \
+  template hipError_t launch_mesofd_1d_resident<T>(const Consts &, const Grid &, T *, T *, T *,   \
+                                                   int64_t, hipStream_t);
 MFD_INST(float)
 MFD_INST(double)
 #undef MFD_INST

@@ -154,43 +154,53 @@ __global__ __launch_bounds__(1024) void k_mmfd_1d_resident(T *__restrict__ ga,
   using R = Rec<L, EQ>;
   constexpr int NR = R::NR;
   // three moment levels (a = t, b = t - dt, c = next) and two record planes
-  T *lev[3] = {(T *)smem, (T *)smem + nx, (T *)smem + 2 * nx};
+  // level k at L0 + k * nx (arithmetic on the LDS base keeps every access a
+  // local-data-share access)
+  T *const L0 = (T *)smem;
+  auto lev = [&](int k) { return L0 + k * nx; };
   T *rec = (T *)smem + 3 * nx;       // NR * nx
   T *hrec = rec + NR * nx;           // NR * nx (three-level stencil)
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-    lev[0][i] = ga[i];
-    lev[1][i] = THREE ? gb[i] : T(0);
+    lev(0)[i] = ga[i];
+    lev(1)[i] = THREE ? gb[i] : T(0);
   }
   __syncthreads();
+  // the linear CDE's record is the moment itself: it reads the levels
+  // directly (one barrier per step instead of two)
+  constexpr bool LIN = EQ == kLCDE;
   int ic = 0, ip = 1, io = 2;
   for (int64_t s = 0; s < nsteps; ++s) {
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-      T m[1], r[NR];
-      m[0] = lev[ic][i];
-      make_record<L, EQ>(m, r, kc);
-#pragma unroll
-      for (int k = 0; k < NR; ++k) rec[k * nx + i] = r[k];
-      if constexpr (THREE_ST) {
-        m[0] = lev[ip][i];
+    if constexpr (!LIN) {
+      for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        T m[1], r[NR];
+        m[0] = lev(ic)[i];
         make_record<L, EQ>(m, r, kc);
 #pragma unroll
-        for (int k = 0; k < NR; ++k) hrec[k * nx + i] = r[k];
+        for (int k = 0; k < NR; ++k) rec[k * nx + i] = r[k];
+        if constexpr (THREE_ST) {
+          m[0] = lev(ip)[i];
+          make_record<L, EQ>(m, r, kc);
+#pragma unroll
+          for (int k = 0; k < NR; ++k) hrec[k * nx + i] = r[k];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+    const T *rc = LIN ? lev(ic) : rec;
+    const T *rh = LIN ? lev(ip) : hrec;
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
       auto idx = [&](int dx) {
         int j = i + dx;
         return j < 0 ? j + nx : (j >= nx ? j - nx : j);
       };
-      auto at = [&](int k, int, int, int dx) { return rec[k * nx + idx(dx)]; };
+      auto at = [&](int k, int, int, int dx) { return rc[k * nx + idx(dx)]; };
       auto ath = [&](int k, int, int, int dx) {
-        if constexpr (THREE_ST) return hrec[k * nx + idx(dx)];
+        if constexpr (THREE_ST) return rh[k * nx + idx(dx)];
         else return T(0);
       };
-      T cc[1] = {lev[ic][i]}, pc[1] = {THREE ? lev[ip][i] : T(0)}, oc[1];
+      T cc[1] = {lev(ic)[i]}, pc[1] = {THREE ? lev(ip)[i] : T(0)}, oc[1];
       mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
-      lev[io][i] = oc[0];
+      lev(io)[i] = oc[0];
     }
     __syncthreads();
     const int t = ip;
@@ -200,8 +210,8 @@ __global__ __launch_bounds__(1024) void k_mmfd_1d_resident(T *__restrict__ ga,
   }
   // final level -> ga, previous level -> gb
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-    ga[i] = lev[ic][i];
-    gb[i] = lev[ip][i];
+    ga[i] = lev(ic)[i];
+    gb[i] = lev(ip)[i];
   }
   (void)gc;
 }

@@ -112,6 +112,14 @@ int Solver::step_t(int64_t nsteps) {
     steps_done += nsteps;
     return MFD_OK;
   }
+  if (grid.form == MFD_MESOFD && mesofd_1d_resident_fits(consts, G, sizeof(T)) && nsteps > 1) {
+    // levels stay in place: B[ic] / B[ip] in and out, final populations in pop[pc]
+    hipError_t e = launch_mesofd_1d_resident<T>(consts, G, B[ic], B[ip], B[pc], nsteps, stream);
+    if (e != hipSuccess) return hip(e, "mesofd 1d resident launch");
+    steps_done += nsteps;
+    prev_gap = 1;
+    return MFD_OK;
+  }
   const TbPlan pl = effective_plan();
   const int d = pl.tb;
   if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 &&

@@ -137,6 +137,13 @@ template <typename T>
 hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, const T *prev_mom,
                               T *pop_out, T *mom_out, hipStream_t st);
 
+// MesoFD 1D grids that fit in LDS: all steps in one workgroup (ga / gb:
+// moments of levels t and t - dt, in and out; pop: final populations)
+bool mesofd_1d_resident_fits(const Consts &c, const Grid &g, int elem);
+template <typename T>
+hipError_t launch_mesofd_1d_resident(const Consts &c, const Grid &g, T *ga, T *gb, T *pop,
+                                     int64_t nsteps, hipStream_t st);
+
 template <typename T>
 hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom, T *pop,
                                    hipStream_t st);

@@ -29,6 +29,12 @@ CASES = [
          kind="three_level", a=EX13[0], ah=EX13[1]),
     dict(name="d1q3-lcde-mesofd", lattice="D1Q3", n=(1030,), eq="lcde", u=(0.2,), K=[[0.25]],
          a=(1.25, -0.5, 0.25), form="mesofd"),
+    dict(name="d1q3-lcde-mesofd-tiled", lattice="D1Q3", n=(5003,), eq="lcde", u=(0.2,), K=[[0.25]],
+         a=(1.25, -0.5, 0.25), form="mesofd"),
+    dict(name="d1q3-burgers-mesofd-3l", lattice="D1Q3", n=(999,), eq="burgers", dx=0.1, dt=0.02,
+         kind="three_level", a=EX13[0], ah=EX13[1], form="mesofd"),
+    dict(name="d1q3-burgers-mesofd-trt", lattice="D1Q3", n=(777,), eq="burgers", dx=0.1, dt=0.02,
+         kind="three_level", a=(1.0, 0.0, 0.4), ah=(0.0, -0.4, 0.0), form="mesofd"),
     # --- 2D linear
     dict(name="d2q9-lcde-srt", lattice="D2Q9", n=(70, 37), eq="lcde", u=(0.1, -0.07), K=K2,
          lambda_bar=1, a=(1.0, 0.0, 0.0)),
