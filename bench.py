@@ -257,6 +257,8 @@ def bench_nse(M, torch, I, stream):
         nodes = int(np.prod(c["n"]))
         s = _nse_solver(M, lat, c, "fp32", stream)
         s.set_state(x0)
+        s.autotune()
+        plan = s.launch_plan()
         s.step(warm)
         ms = timed(torch, lambda: s.step(steps))
         g = nodes * steps / (ms * 1e-3) / 1e9
@@ -273,7 +275,7 @@ def bench_nse(M, torch, I, stream):
         torch.cuda.synchronize()
         res[key] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
                         frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl,
-                        steps=warm + steps,
+                        steps=warm + steps, plan=list(plan),
                         fp32_rel_l2_vs_fp64=_rel_l2_dev(torch, y32, y64))
         del x0, x64, y32, y64
         torch.cuda.empty_cache()

@@ -31,8 +31,12 @@ bool tunable(const Solver &s) {
 }
 
 // default window height for a requested depth: the tallest window whose
-// levels leave room for three workgroups per CU
+// levels leave room for three workgroups per CU (NSE: the 32-row window)
 int default_h(const Solver &s, int tb) {
+  if (s.consts.eq == kNSE) {
+    const TbPlan p{tb, 32};
+    return tb_supported(s.consts, s.G, p, (int)s.elem()) ? 32 : 0;
+  }
   static const int hs[] = {96, 80, 64, 48, 32};
   for (int h : hs) {
     const TbPlan p{tb, h};

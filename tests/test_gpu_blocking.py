@@ -87,6 +87,67 @@ def test_explicit_plans_fp64_bitwise(M, plan, name):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
+NSE = {
+    "nse-srt": dict(lattice="D2Q9", eq="nse", rho0=1.0, a=(1.0, 0.0, 0.0)),
+    "nse-trt": dict(lattice="D2Q9", eq="nse", rho0=1.0, kind="three_level", a=(1.0, 0.0, 0.4),
+                    ah=(0.0, -0.4, 0.0)),
+    "nse-trt-heluo": dict(lattice="D2Q9", eq="nse", rho0=1.0, he_luo=1, kind="three_level",
+                          a=(1.0, 0.0, 0.4), ah=(0.0, -0.4, 0.0)),
+    "nse-d2q5-trt": dict(lattice="D2Q5", eq="nse", rho0=1.0, kind="three_level", a=(1.0, 0.0, 0.4),
+                         ah=(0.0, -0.4, 0.0)),
+}
+
+
+@pytest.mark.parametrize("plan", [(2, 32, 64), (5, 32, 64), (12, 32, 64), (4, 64, 64), (28, 64, 64)])
+@pytest.mark.parametrize("name", list(NSE))
+@pytest.mark.parametrize("n", [(150, 77), (64, 64)])
+def test_nse_blocked_fp64_bitwise(M, plan, name, n):
+    """Blocked NSE launches (pair parts in LDS, moments in registers) equal
+    the oracle value for value."""
+    from parity_util import make_solver
+    case = dict(NSE[name], n=n, name=name)
+    print("case", name, plan, n, flush=True)
+    rng = np.random.default_rng(17)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    pairs = 4 if case["lattice"] == "D2Q9" else 2
+    if 2 * pairs * plan[1] * plan[2] * 8 > 160 * 1024:
+        pytest.skip("window beyond the LDS in binary64")
+    steps = 2 * plan[0] + 1
+    want = run_oracle(case, cur, prev, steps)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    s.set_state(cur)
+    if case.get("kind") == "three_level":
+        s.set_state(prev, level=1)
+    s.step(steps)
+    got = s.get_state()
+    if case.get("kind") == "three_level":
+        want_prev = run_oracle(case, cur, prev, steps - 1)
+        assert np.array_equal(s.get_state(level=1), want_prev)
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+@pytest.mark.parametrize("name", list(NSE))
+def test_nse_blocked_fp32_equals_unblocked(M, name):
+    from parity_util import make_solver
+    case = dict(NSE[name], n=(300, 140), name=name)
+    rng = np.random.default_rng(18)
+    cur = rand_state(case, rng).astype(np.float32)
+    prev = rand_state(case, rng).astype(np.float32)
+    outs = []
+    for plan in ((1,), (4, 32, 64), (6, 64, 64)):
+        s = make_solver(M, case, "fp32")
+        s.set_plan(*plan)
+        s.set_state(cur)
+        if case.get("kind") == "three_level":
+            s.set_state(prev, level=1)
+        s.step(29)
+        outs.append(s.get_state())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_plan_rejections(M):
     from parity_util import make_solver
     s = make_solver(M, _case("2l", (100, 77)), "fp32")
