@@ -27,6 +27,7 @@ SOURCES = [
     "server.cpp",
     "kernels_mmfd.hip",
     "kernels_tb.hip",
+    "kernels_nse_tb.hip",
     "kernels_mesofd.hip",
     "kernels_misc.hip",
     "kernels_batch.hip",

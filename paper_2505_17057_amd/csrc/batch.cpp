@@ -56,12 +56,20 @@ BatchKey batch_key_of(const Solver *s) {
 }
 
 bool batch_blockable(const BatchKey &k) {
-  return !k.three && (k.eq == kLCDE || k.eq == kBurgers) && (k.lattice == MFD_D2Q5 || k.lattice == MFD_D2Q9);
+  if (k.lattice != MFD_D2Q5 && k.lattice != MFD_D2Q9) return false;
+  if (k.eq == kNSE) return !k.three_st;
+  return !k.three && (k.eq == kLCDE || k.eq == kBurgers);
+}
+
+static int elem_of(const BatchKey &k) { return k.precision == MFD_FP64 ? 8 : 4; }
+
+// a blocked plan the group's kernel can run
+static bool group_plan_valid(const BatchKey &k, const TbPlan &p) {
+  if (k.eq == kNSE) return nse_tb_plan_valid(p, k.lattice == MFD_D2Q9 ? 4 : 2, elem_of(k));
+  return tb_plan_valid(p, 2, elem_of(k));
 }
 
 static int tile_ty(int eq) { return eq == kNSE ? kBatchTYNse : kBatchTY; }
-
-static int elem_of(const BatchKey &k) { return k.precision == MFD_FP64 ? 8 : 4; }
 
 // tile shape of a group under its plan
 static void tile_shape(const Group &g, int *tx, int *ty) {
@@ -131,7 +139,7 @@ int Batch::build() {
       auto it = tuned.find(g.key);
       if (req.tb > 0) g.plan = req;
       else if (it != tuned.end()) g.plan = it->second;
-      if (g.plan.tb > 1 && !tb_plan_valid(g.plan, 2, elem_of(g.key))) g.plan = TbPlan{1, 0};
+      if (g.plan.tb > 1 && !group_plan_valid(g.key, g.plan)) g.plan = TbPlan{1, 0};
     }
     for (int slot = 0; slot < (int)g.order.size(); ++slot) {
       const BatchEntry &e = entries[g.order[slot]];
@@ -158,6 +166,23 @@ static int active_tiles(const Group &g, int64_t s) {
   return g.tile0[m];
 }
 
+// one blocked launch of a group (its `l`-th) over the first nt tiles
+static hipError_t launch_group_tb_impl(const Group &g, int nt, int64_t l, const TbPlan &p,
+                                       hipStream_t stream) {
+  if (g.key.precision == MFD_FP64) {
+    const BatchInst<double> *in = (const BatchInst<double> *)g.d_inst;
+    return g.key.eq == kNSE ? launch_batch_nse_tb<double>(g.key, in, g.d_tile_inst, nt, l, p, stream)
+                            : launch_batch_tb<double>(g.key, in, g.d_tile_inst, nt, l, p, stream);
+  }
+  const BatchInst<float> *in = (const BatchInst<float> *)g.d_inst;
+  return g.key.eq == kNSE ? launch_batch_nse_tb<float>(g.key, in, g.d_tile_inst, nt, l, p, stream)
+                          : launch_batch_tb<float>(g.key, in, g.d_tile_inst, nt, l, p, stream);
+}
+
+hipError_t Batch::launch_group_tb(const Group &g, int nt, int64_t l) {
+  return launch_group_tb_impl(g, nt, l, g.plan, stream);
+}
+
 int Batch::enqueue_steps() {
   launches_per_run = 0;
   for (auto &g : groups) {
@@ -167,13 +192,7 @@ int Batch::enqueue_steps() {
       for (int64_t l = 0; l < nl; ++l) {
         const int nt = active_tiles(g, l * g.plan.tb);
         if (nt == 0) continue;
-        hipError_t e;
-        if (g.key.precision == MFD_FP64)
-          e = launch_batch_tb<double>(g.key, (const BatchInst<double> *)g.d_inst, g.d_tile_inst, nt,
-                                      l, g.plan, stream);
-        else
-          e = launch_batch_tb<float>(g.key, (const BatchInst<float> *)g.d_inst, g.d_tile_inst, nt,
-                                     l, g.plan, stream);
+        const hipError_t e = launch_group_tb(g, nt, l);
         if (e != hipSuccess) return hip(e, "blocked batch launch");
         ++launches_per_run;
       }
@@ -204,7 +223,14 @@ static void fill_inst(const Group &g, const std::vector<BatchEntry> &entries,
     const Solver *s = entries[g.order[slot]].s;
     BatchInst<T> b;
     std::memset(&b, 0, sizeof(b));
-    if (s->consts.three) {
+    if (s->consts.three && g.plan.tb > 1) {
+      // blocked three-level: launches move between the pairs (t, t - dt)
+      b.ring[0] = (T *)s->buf[s->ic];
+      b.ring[1] = (T *)s->buf[s->ip];
+      b.ring[2] = (T *)s->buf[s->io];
+      b.ring[3] = (T *)s->buf[s->ix];
+      b.ring_len = 4;
+    } else if (s->consts.three) {
       b.ring[0] = (T *)s->buf[s->ic];
       b.ring[1] = (T *)s->buf[s->io];
       b.ring[2] = (T *)s->buf[s->ip];
@@ -289,7 +315,18 @@ int Batch::run() {
     Solver *s = e.s;
     const int64_t n = e.nsteps;
     if (n == 0) continue;
-    if (s->consts.three) {
+    if (s->consts.three && e.tb > 1) {
+      // each blocked launch moves to the other (t, t - dt) pair
+      const int64_t nl = (n + e.tb - 1) / e.tb;
+      if (nl & 1) {
+        const int oc = s->ic, op = s->ip;
+        s->ic = s->io;
+        s->ip = s->ix;
+        s->io = oc;
+        s->ix = op;
+      }
+      s->prev_gap = 1;
+    } else if (s->consts.three) {
       const int ring[3] = {s->ic, s->io, s->ip};
       s->ic = ring[n % 3];
       s->io = ring[(n + 1) % 3];
@@ -353,9 +390,9 @@ int Batch::autotune() {
       off += (int64_t)b;
     }
     std::vector<TbPlan> cands{TbPlan{1, 0}};
-    for (int d : {2, 4, 6, 8})
+    for (int d : {2, 3, 4, 6, 8})
       for (int h : {32, 48, 64, 96, 128})
-        if (tb_plan_valid(TbPlan{d, h}, 2, es)) cands.push_back(TbPlan{d, h});
+        if (group_plan_valid(g.key, TbPlan{d, h})) cands.push_back(TbPlan{d, h});
     float best = 1e30f;
     TbPlan best_p{1, 0};
     for (const TbPlan &p : cands) {
@@ -372,12 +409,7 @@ int Batch::autotune() {
       const int nt = active_tiles(g, 0);
       if (nt == 0 || lups == 0) continue;
       auto launch = [&]() -> hipError_t {
-        if (p.tb > 1)
-          return g.key.precision == MFD_FP64
-                     ? launch_batch_tb<double>(g.key, (const BatchInst<double> *)g.d_inst,
-                                               g.d_tile_inst, nt, 0, p, stream)
-                     : launch_batch_tb<float>(g.key, (const BatchInst<float> *)g.d_inst,
-                                              g.d_tile_inst, nt, 0, p, stream);
+        if (p.tb > 1) return launch_group_tb(g, nt, 0);
         return g.key.precision == MFD_FP64
                    ? launch_batch_step<double>(g.key, (const BatchInst<double> *)g.d_inst,
                                                g.d_tile_inst, nt, 0, stream)

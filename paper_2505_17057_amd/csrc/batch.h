@@ -57,6 +57,7 @@ struct Batch {
   int make_tables(Group &g);
   int upload_instances();
   int enqueue_steps();
+  hipError_t launch_group_tb(const Group &g, int nt, int64_t l);
   int run();
   int autotune();
 };

@@ -10,7 +10,8 @@ constexpr int kBatchTX = 64, kBatchTY = 16, kBatchTYNse = 8;
 // one instance of a batch group, as the kernel reads it
 template <typename T>
 struct BatchInst {
-  T *ring[3];     // level buffers (two-level groups use ring[0..1])
+  T *ring[4];     // level buffers: two-level ring[0..1]; three-level ring[0..2], or
+                  // (t, t - dt) pairs ring[0..1] / ring[2..3] under a blocked plan
   int nx, ny;
   int ring_len;   // 2 or 3
   int c0;         // ring index of level t at the first step of the run
@@ -38,9 +39,13 @@ template <typename T>
 hipError_t launch_batch_step(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                              int ntiles, int64_t s, hipStream_t st);
 
-// temporally blocked batched launch `launch` (two-level LCDE / Burgers groups)
+// temporally blocked batched launch `launch` (two-level LCDE / Burgers groups;
+// NSE groups: launch_batch_nse_tb)
 template <typename T>
 hipError_t launch_batch_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                            int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_nse_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
+                               int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
 
 }  // namespace mfd

@@ -1,0 +1,267 @@
+// Temporally blocked NSE step (D2Q5 / D2Q9, two-level or three-level without
+// an older-level stencil): one launch advances several time steps.
+//
+// Each thread owns one column of a W x H window and a fixed run of R rows,
+// and keeps the moments of its nodes at levels t and t - dt in registers for
+// the whole launch.  Every step:
+//   A  each node one beyond the update region evaluates its pair parts F+-_p
+//      (record, then the even / odd parts of Eq. (3-3) over the opposite pair,
+//      Eq. (2-5)) into LDS;
+//   B  each node of the update region reads its neighbours' pair parts and
+//      updates its own moments with the single-step node function.
+// The store writes the interior of the last two levels (the next three-level
+// launch needs both).  Results equal the single-step kernel's value for value.
+//
+// The batched kernel runs the same window for every tile of a batch group's
+// table; each instance advances min(TB, its remaining steps).
+#include "batch_kernels.h"
+#include "mmfd_node.h"
+
+namespace mfd {
+
+namespace {
+constexpr int kNseW = 64;  // window columns (one per thread)
+constexpr int kNseR = 8;   // window rows per thread; H = 8 RG
+
+__device__ __forceinline__ int xcd_remap_nse(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+}  // namespace
+
+// Window with origin (x0, y0): load, TBS steps, store of the interior that
+// starts TBW nodes in.  WRAP_ANY: grids of any size; otherwise nx >= W and
+// ny >= H (one conditional wrap).
+template <class L, bool THREE, int W, int RG, int R, bool WRAP_ANY, typename T>
+__device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *__restrict__ prev,
+                                           T *__restrict__ out_cur, T *__restrict__ out_prev,
+                                           int nx, int ny, int TBW, int TBS, int x0, int y0,
+                                           const KC<T> &kc, T *pf) {
+  using Rc = Rec<L, kNSE>;
+  constexpr int NR = Rc::NR, NF = Rc::NF, NPF = 2 * L::P;
+  constexpr int H = R * RG;
+  const int64_t N = (int64_t)nx * ny;
+  const int xx = threadIdx.x % W, rg = threadIdx.x / W;
+  const int yr = rg * R;  // first row of this thread
+  auto wrap = [&](int i, int n) {
+    if constexpr (WRAP_ANY) return wrapi(i, n);
+    else return i < 0 ? i + n : (i >= n ? i - n : i);
+  };
+
+  T cm[R][NF], pm[R][NF];
+  {
+    const int gx = wrap(x0 + xx, nx);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int gy = wrap(y0 + yr + r, ny);
+      const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        cm[r][q] = cur[q * N + gi];
+        pm[r][q] = THREE ? prev[q * N + gi] : T(0);
+      }
+    }
+  }
+#pragma unroll 1
+  for (int t = 1; t <= TBS; ++t) {
+    // A: pair parts on the region t - 1 nodes in
+    if (xx >= t - 1 && xx < W - t + 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = yr + r;
+        if (y >= t - 1 && y < H - t + 1) {
+          T rec[NR], f[NPF];
+          make_record<L, kNSE>(cm[r], rec, kc);
+          pair_parts<L, kNSE>(rec, f, kc);
+#pragma unroll
+          for (int q = 0; q < NPF; ++q) pf[(q * H + y) * W + xx] = f[q];
+        }
+      }
+    }
+    __syncthreads();
+    // B: node updates on the region t nodes in
+    if (xx >= t && xx < W - t) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = yr + r;
+        if (y >= t && y < H - t) {
+          auto at = [&](int q, int, int dy, int dx) { return pf[(q * H + y + dy) * W + xx + dx]; };
+          auto ath = [&](int, int, int, int) { return T(0); };
+          T oc[NF];
+          mmfd_node<L, kNSE, THREE, false, T, false, true>(at, ath, cm[r], pm[r], oc, kc);
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            pm[r][q] = cm[r][q];
+            cm[r][q] = oc[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // store the interior of the last level (and the one before it)
+  if (xx >= TBW && xx < W - TBW) {
+    const int gx = x0 + xx;
+    if (gx < nx) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = yr + r;
+        const int gy = y0 + y;
+        if (y >= TBW && y < H - TBW && gy < ny) {
+          const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            out_cur[q * N + gi] = cm[r][q];
+            if constexpr (THREE) out_prev[q * N + gi] = pm[r][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class L, bool THREE, int W, int RG, int R, typename T>
+__global__ __launch_bounds__(W *RG) void k_nse_tb(const T *__restrict__ cur,
+                                                 const T *__restrict__ prev,
+                                                 T *__restrict__ out_cur, T *__restrict__ out_prev,
+                                                 int nx, int ny, int TB, int tiles_x, int ntiles,
+                                                 KC<T> kc) {
+  extern __shared__ unsigned char smem_nse[];
+  constexpr int H = R * RG;
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int tile = xcd_remap_nse(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
+  nse_window<L, THREE, W, RG, R, false, T>(cur, prev, out_cur, out_prev, nx, ny, TB, TB, x0, y0, kc,
+                                           reinterpret_cast<T *>(smem_nse));
+}
+
+// Batched: launch `launch` of a run whose launches advance TB steps; the
+// ring holds (t, t - dt) in ring[0..1] and the other pair in ring[2..3]
+// (three-level), or t and the spare level in ring[0..1] (two-level).
+template <class L, bool THREE, int W, int RG, int R, typename T>
+__global__ __launch_bounds__(W *RG) void k_batch_nse_tb(const BatchInst<T> *__restrict__ inst,
+                                                       const int *__restrict__ tile_inst,
+                                                       int ntiles, int64_t launch, int TB) {
+  extern __shared__ unsigned char smem_bnse[];
+  constexpr int H = R * RG;
+  const int t = xcd_remap_nse(blockIdx.x, ntiles);
+  const BatchInst<T> &I = inst[tile_inst[t]];
+  const int64_t left = I.nsteps - launch * TB;
+  const int TBS = left < TB ? (int)left : TB;
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int lt = t - I.tile0;
+  const int x0 = (lt % I.tiles_x) * TX - TB, y0 = (lt / I.tiles_x) * TY - TB;
+  const int64_t r = I.c0 + launch;
+  const T *cur, *prev;
+  T *oc, *op;
+  if constexpr (THREE) {
+    const int a = (int)(r & 1) * 2, b = 2 - a;
+    cur = I.ring[a];
+    prev = I.ring[a + 1];
+    oc = I.ring[b];
+    op = I.ring[b + 1];
+  } else {
+    cur = I.ring[r & 1];
+    prev = nullptr;
+    oc = I.ring[(r + 1) & 1];
+    op = nullptr;
+  }
+  nse_window<L, THREE, W, RG, R, true, T>(cur, prev, oc, op, I.nx, I.ny, TB, TBS, x0, y0, I.kc,
+                                          reinterpret_cast<T *>(smem_bnse));
+}
+
+// ------------------------------------------------------------ host side
+bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem) {
+  // 64 x 32 or 64 x 64 windows (8 rows per thread)
+  if (pl.w != kNseW || (pl.h != 32 && pl.h != 64)) return false;
+  if (pl.tb < 1 || pl.h - 2 * pl.tb < 8 || pl.w - 2 * pl.tb < 8) return false;
+  return (size_t)2 * npair * pl.h * pl.w * elem <= 160 * 1024;
+}
+
+namespace {
+
+template <class L, bool THREE, int RG, typename T>
+hipError_t nse_tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                      const T *prev, T *oc, T *op, hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  constexpr int H = kNseR * RG;
+  const int TX = kNseW - 2 * pl.tb, TY = H - 2 * pl.tb;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = (size_t)2 * L::P * H * kNseW * sizeof(T);  // the pair parts
+  auto fn = k_nse_tb<L, THREE, kNseW, RG, kNseR, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kNseW * RG), lds, st, cur, prev, oc, op, nx, ny,
+                     pl.tb, tx, tx * ty, kc);
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t nse_tb_l(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
+                    T *oc, T *op, hipStream_t st) {
+  if (pl.h == 32) {
+    if (c.three) return nse_tb_cfg<L, true, 4, T>(c, g, pl, cur, prev, oc, op, st);
+    return nse_tb_cfg<L, false, 4, T>(c, g, pl, cur, prev, oc, op, st);
+  }
+  if (c.three) return nse_tb_cfg<L, true, 8, T>(c, g, pl, cur, prev, oc, op, st);
+  return nse_tb_cfg<L, false, 8, T>(c, g, pl, cur, prev, oc, op, st);
+}
+
+template <class L, bool THREE, int RG, typename T>
+hipError_t bnse_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, int64_t launch,
+                    const TbPlan &pl, hipStream_t st) {
+  constexpr int H = kNseR * RG;
+  const size_t lds = (size_t)2 * L::P * H * kNseW * sizeof(T);
+  auto fn = k_batch_nse_tb<L, THREE, kNseW, RG, kNseR, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(kNseW * RG), lds, st, inst, tile_inst, ntiles, launch,
+                     pl.tb);
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t bnse_l(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst, int ntiles,
+                  int64_t launch, const TbPlan &pl, hipStream_t st) {
+  if (pl.h == 32) {
+    if (k.three) return bnse_cfg<L, true, 4, T>(inst, tile_inst, ntiles, launch, pl, st);
+    return bnse_cfg<L, false, 4, T>(inst, tile_inst, ntiles, launch, pl, st);
+  }
+  if (k.three) return bnse_cfg<L, true, 8, T>(inst, tile_inst, ntiles, launch, pl, st);
+  return bnse_cfg<L, false, 8, T>(inst, tile_inst, ntiles, launch, pl, st);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_nse_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                         const T *prev, T *out_cur, T *out_prev, hipStream_t st) {
+  if (c.three_stencil) return hipErrorInvalidValue;
+  if (c.lattice == 3) return nse_tb_l<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
+  if (c.lattice == 2) return nse_tb_l<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_batch_nse_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
+                               int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st) {
+  if (k.three_st || k.eq != kNSE) return hipErrorInvalidValue;
+  if (k.lattice == 3) return bnse_l<LatD2Q9, T>(k, inst, tile_inst, ntiles, launch, pl, st);
+  if (k.lattice == 2) return bnse_l<LatD2Q5, T>(k, inst, tile_inst, ntiles, launch, pl, st);
+  return hipErrorInvalidValue;
+}
+
+#define MFD_INST(T)                                                                               \
+  template hipError_t launch_nse_tb<T>(const Consts &, const Grid &, const TbPlan &, const T *,  \
+                                       const T *, T *, T *, hipStream_t);                         \
+  template hipError_t launch_batch_nse_tb<T>(const BatchKey &, const BatchInst<T> *, const int *, \
+                                             int, int64_t, const TbPlan &, hipStream_t);
+MFD_INST(float)
+MFD_INST(double)
+#undef MFD_INST
+
+}  // namespace mfd

@@ -198,108 +198,6 @@ __global__ __launch_bounds__(W *RG) void k_mmfd_tb(const T *__restrict__ cur,
                                                          TB, TB, x0, y0, kc, lds);
 }
 
-// Temporally blocked NSE step (D2Q5 / D2Q9, two-level or three-level without
-// an older-level stencil).  Each thread owns one column of the W x H window
-// and a fixed run of R rows, and keeps the moments of its nodes at levels t
-// and t - dt in registers for the whole launch.  Every step:
-//   A  each node one beyond the update region evaluates its pair parts F+-_p
-//      (record, then Eq. (2-5) parts of Eq. (3-3)) into LDS;
-//   B  each node of the update region reads its neighbours' pair parts and
-//      updates its own moments (the single-step node function).
-// The store writes the interior of the last two levels.  Results equal the
-// single-step kernel's value for value.
-template <class L, bool THREE, int W, int RG, int R, typename T>
-__global__ __launch_bounds__(W *RG) void k_nse_tb(const T *__restrict__ cur,
-                                                 const T *__restrict__ prev,
-                                                 T *__restrict__ out_cur, T *__restrict__ out_prev,
-                                                 int nx, int ny, int TB, int tiles_x, int ntiles,
-                                                 KC<T> kc) {
-  using Rc = Rec<L, kNSE>;
-  constexpr int NR = Rc::NR, NF = Rc::NF, NPF = 2 * L::P;
-  constexpr int H = R * RG;
-  extern __shared__ unsigned char smem_nse[];
-  T *pf = reinterpret_cast<T *>(smem_nse);  // [NPF][H][W]
-  const int TX = W - 2 * TB, TY = H - 2 * TB;
-  const int tile = xcd_remap_tb(blockIdx.x, ntiles);
-  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
-  const int64_t N = (int64_t)nx * ny;
-  const int xx = threadIdx.x % W, rg = threadIdx.x / W;
-  const int yr = rg * R;  // first row of this thread
-
-  T cm[R][NF], pm[R][NF];
-  {
-    int gx = x0 + xx;
-    gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int gy = y0 + yr + r;
-      gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-      const int64_t gi = (int64_t)gy * nx + gx;
-#pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        cm[r][q] = cur[q * N + gi];
-        pm[r][q] = THREE ? prev[q * N + gi] : T(0);
-      }
-    }
-  }
-#pragma unroll 1
-  for (int t = 1; t <= TB; ++t) {
-    // A: pair parts on the region t - 1 nodes in
-    if (xx >= t - 1 && xx < W - t + 1) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = yr + r;
-        if (y >= t - 1 && y < H - t + 1) {
-          T rec[NR], f[NPF];
-          make_record<L, kNSE>(cm[r], rec, kc);
-          pair_parts<L, kNSE>(rec, f, kc);
-#pragma unroll
-          for (int q = 0; q < NPF; ++q) pf[(q * H + y) * W + xx] = f[q];
-        }
-      }
-    }
-    __syncthreads();
-    // B: node updates on the region t nodes in
-    if (xx >= t && xx < W - t) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = yr + r;
-        if (y >= t && y < H - t) {
-          auto at = [&](int q, int, int dy, int dx) { return pf[(q * H + y + dy) * W + xx + dx]; };
-          auto ath = [&](int, int, int, int) { return T(0); };
-          T oc[NF];
-          mmfd_node<L, kNSE, THREE, false, T, false, true>(at, ath, cm[r], pm[r], oc, kc);
-#pragma unroll
-          for (int q = 0; q < NF; ++q) {
-            pm[r][q] = cm[r][q];
-            cm[r][q] = oc[q];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // store the interior of the last level (and the one before it)
-  if (xx >= TB && xx < W - TB) {
-    const int gx = x0 + xx;
-    if (gx < nx) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int y = yr + r;
-        const int gy = y0 + y;
-        if (y >= TB && y < H - TB && gy < ny) {
-          const int64_t gi = (int64_t)gy * nx + gx;
-#pragma unroll
-          for (int q = 0; q < NF; ++q) {
-            out_cur[q * N + gi] = cm[r][q];
-            if constexpr (THREE) out_prev[q * N + gi] = pm[r][q];
-          }
-        }
-      }
-    }
-  }
-}
-
 // Batched two-level variant: launch `launch` of a run whose launches advance
 // TB steps; tiles of instances with steps left form the prefix [0, ntiles).
 template <class L, int EQ, int W, int RG, bool B1, typename T>
@@ -362,42 +260,10 @@ hipError_t tb_levels(const Consts &c, const Grid &g, const TbPlan &pl, const T *
   return tb_cfg<L, EQ, true, true, B1, T>(c, g, pl, cur, prev, oc, op, st);
 }
 
-// NSE windows: 64 columns, R = 8 rows per thread, H = 8 RG rows
-constexpr int kNseR = 8;
-
-template <class L, bool THREE, int RG, typename T>
-hipError_t nse_tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
-                      const T *prev, T *oc, T *op, hipStream_t st) {
-  const KC<T> kc = make_kc<T>(c);
-  const int nx = (int)g.n[0], ny = (int)g.n[1];
-  constexpr int H = kNseR * RG;
-  const int TX = kTbW - 2 * pl.tb, TY = H - 2 * pl.tb;
-  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
-  const size_t lds = (size_t)2 * L::P * H * kTbW * sizeof(T);  // 2P pair parts
-  auto fn = k_nse_tb<L, THREE, kTbW, RG, kNseR, T>;
-  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kTbW * RG), lds, st, cur, prev, oc, op, nx, ny, pl.tb,
-                     tx, tx * ty, kc);
-  return hipGetLastError();
-}
-
-template <class L, typename T>
-hipError_t nse_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
-                  T *oc, T *op, hipStream_t st) {
-  if (pl.h == 32) {
-    if (c.three) return nse_tb_cfg<L, true, 4, T>(c, g, pl, cur, prev, oc, op, st);
-    return nse_tb_cfg<L, false, 4, T>(c, g, pl, cur, prev, oc, op, st);
-  }
-  if (c.three) return nse_tb_cfg<L, true, 8, T>(c, g, pl, cur, prev, oc, op, st);
-  return nse_tb_cfg<L, false, 8, T>(c, g, pl, cur, prev, oc, op, st);
-}
-
 template <class L, typename T>
 hipError_t tb_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
                  T *oc, T *op, hipStream_t st) {
-  if (c.eq == kNSE) return nse_tb<L, T>(c, g, pl, cur, prev, oc, op, st);
+  if (c.eq == kNSE) return launch_nse_tb<T>(c, g, pl, cur, prev, oc, op, st);
   if (c.eq == kLCDE) return tb_levels<L, kLCDE, false, T>(c, g, pl, cur, prev, oc, op, st);
   if (c.eq == kBurgers) {
     if (c.beta_one) return tb_levels<L, kBurgers, true, T>(c, g, pl, cur, prev, oc, op, st);
@@ -442,10 +308,7 @@ bool tb_equation_supported(const Consts &c) {
 bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
   if (!tb_equation_supported(c)) return false;
   if (c.eq == kNSE) {
-    // 64 x 32 or 64 x 64 windows (8 rows per thread)
-    if (pl.w != kTbW || (pl.h != 32 && pl.h != 64)) return false;
-    if (pl.tb < 1 || pl.h - 2 * pl.tb < 8 || pl.w - 2 * pl.tb < 8) return false;
-    if (tb_lds_bytes(c, pl, elem) > 160 * 1024) return false;
+    if (!nse_tb_plan_valid(pl, c.npair, elem)) return false;
   } else if (!tb_plan_valid(pl, c.three ? 3 : 2, elem)) {
     return false;
   }

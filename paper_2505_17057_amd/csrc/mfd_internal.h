@@ -127,6 +127,11 @@ bool tb_equation_supported(const Consts &c);
 // the single-grid blocked kernel can run this plan on this grid
 bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 int tb_window_cols();
+// blocked NSE step (kernels_nse_tb.hip): 64 x 32 or 64 x 64 windows
+bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem);
+template <typename T>
+hipError_t launch_nse_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                         const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st);
