@@ -246,3 +246,39 @@ def test_batch_autotune_fp32_equals_solo(M):
     b.close()
     for s in solvers:
         s.close()
+
+
+def test_server_concurrent_submitters(M):
+    """Requests submitted from four threads at once each come back equal to
+    the same request solved alone."""
+    import threading
+    cases = batch_cases()
+    states = [s.astype(np.float32) for s, _ in _states(cases, seed=12)]
+    alone = []
+    for c, st in zip(cases, states):
+        srv = M.Server(hbm_budget_bytes=1 << 30, max_slots=4, quantum_steps=4)
+        out = np.empty_like(st)
+        srv.submit(_request(M, c, st, out), keep=(st, out))
+        srv.drain(60)
+        alone.append(out)
+        srv.close()
+    srv = M.Server(hbm_budget_bytes=1 << 30, max_slots=64, quantum_steps=3)
+    outs = [np.empty_like(st) for st in states]
+    tickets = [None] * len(cases)
+
+    def submit(idx):
+        for i in idx:
+            tickets[i] = srv.submit(_request(M, cases[i], states[i], outs[i]), keep=(states[i], outs[i]))
+
+    parts = [list(range(k, len(cases), 4)) for k in range(4)]
+    threads = [threading.Thread(target=submit, args=(p,)) for p in parts]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    srv.drain(60)
+    for t in tickets:
+        assert srv.poll(t)[0] == 2
+    srv.close()
+    for c, a, m in zip(cases, alone, outs):
+        assert np.array_equal(a, m), c["name"]
