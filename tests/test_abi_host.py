@@ -150,3 +150,17 @@ def test_stability_warning(M):
         a, _ = M.mfd_preset("two_level", sp)
         assert s.set_scheme("two_level", a, dt=r) == want
         s.close()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The binding has no fallback: loaded from a directory without
+    libmfd.so it raises at import."""
+    import importlib.util
+    import shutil
+    src = os.path.join(os.path.dirname(__file__), "..", "paper_2505_17057_amd", "mfd.py")
+    dst = tmp_path / "mfd_copy.py"
+    shutil.copy(src, dst)
+    spec = importlib.util.spec_from_file_location("mfd_copy", dst)
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="libmfd.so is not built"):
+        spec.loader.exec_module(mod)
