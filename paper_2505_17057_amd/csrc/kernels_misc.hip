@@ -122,47 +122,62 @@ __global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur
   __syncthreads();
 
   const int xx = threadIdx.x % W, rg = threadIdx.x / W;
-  // apply f(y) to the rows of this thread's column in the region t nodes in
-  auto region = [&](int t, auto &&f) {
+  // Walk this thread's column segment of the region t nodes in with a 3 x 3
+  // register window of `src` (three LDS reads per node instead of nine);
+  // f(y, w) gets the window centred on row y.
+  auto slide = [&](const T *src, int t, auto &&f) {
     if (xx < t || xx >= W - t) return;
     const int Hr = H - 2 * t;
     const int seg = (Hr + RG - 1) / RG;
     const int ya = t + rg * seg, yb = min(ya + seg, H - t);
-    for (int y = ya; y < yb; ++y) f(y);
+    if (ya >= yb) return;
+    T w[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      w[0][c] = src[(ya - 1) * W + xx - 1 + c];
+      w[1][c] = src[ya * W + xx - 1 + c];
+    }
+#pragma unroll 2
+    for (int y = ya; y < yb; ++y) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[2][c] = src[(y + 1) * W + xx - 1 + c];
+      f(y, w);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        w[0][c] = w[1][c];
+        w[1][c] = w[2][c];
+      }
+    }
   };
   T *R = lds + WH;
-  {
-    const T *A = lds;
-    region(1, [&](int y) {
-      T acc = T(0);
-      const T g0 = A[y * W + xx];
-      static_for<L::P>([&](auto PI) {
-        constexpr int P = decltype(PI)::value;
-        constexpr int J = L::PR[P];
-        constexpr int ex = L::E[J][0], ey = L::E[J][1];
-        const T gp = A[(y + ey) * W + xx + ex];
-        const T gm = A[(y - ey) * W + xx - ex];
-        acc = madd(kc.Cp[P], (gp - T(2) * g0) + gm, acc);
-        acc = madd(kc.Cm[P], gp - gm, acc);
-      });
-      const T b = kc.A0t * g0;
-      R[y * W + xx] = madd(kc.th, acc, b);
+  slide(lds, 1, [&](int y, const T (&w)[3][3]) {
+    T acc = T(0);
+    const T g0 = w[1][1];
+    static_for<L::P>([&](auto PI) {
+      constexpr int P = decltype(PI)::value;
+      constexpr int J = L::PR[P];
+      constexpr int ex = L::E[J][0], ey = L::E[J][1];
+      const T gp = w[1 + ey][1 + ex];
+      const T gm = w[1 - ey][1 - ex];
+      acc = madd(kc.Cp[P], (gp - T(2) * g0) + gm, acc);
+      acc = madd(kc.Cm[P], gp - gm, acc);
     });
-  }
+    const T b = kc.A0t * g0;
+    R[y * W + xx] = madd(kc.th, acc, b);
+  });
   __syncthreads();
   int src = 0;
 #pragma unroll 1
   for (int k = 1; k <= K; ++k) {
-    const T *S = lds + src * WH;
     T *D = lds + (src == 0 ? 2 : 0) * WH;
-    region(1 + k, [&](int y) {
+    slide(lds + src * WH, 1 + k, [&](int y, const T (&w)[3][3]) {
       T acc = T(0);
       static_for<L::P>([&](auto PI) {
         constexpr int P = decltype(PI)::value;
         constexpr int J = L::PR[P];
         constexpr int ex = L::E[J][0], ey = L::E[J][1];
-        const T gp = S[(y + ey) * W + xx + ex];
-        const T gm = S[(y - ey) * W + xx - ex];
+        const T gp = w[1 + ey][1 + ex];
+        const T gm = w[1 - ey][1 - ex];
         acc = madd(kc.Cp[P], gp + gm, acc);
         acc = madd(kc.Cm[P], gp - gm, acc);
       });
