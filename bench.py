@@ -158,9 +158,16 @@ def bench_variants(M, torch, cfg, stream, N):
         sv.autotune()
         ms = timed(torch, lambda: sv.step(TIME_STEPS))
         g = N * TIME_STEPS / (ms * 1e-3) / 1e9
-        out["%s_%s" % (form, prec)] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
-                                          frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
-                                          bytes_per_lup=bpl, ms_per_solve=round(ms, 3))
+        r = dict(glups=round(g, 2), ms_per_solve=round(ms, 3), plan=list(sv.launch_plan()))
+        if form == "mmfd":
+            r.update(alg_gbs=round(g * bpl, 1), frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
+                     bytes_per_lup=bpl)
+        else:
+            # population form: Q populations in and out per update; a blocked
+            # launch carries moments between its steps, so this is a rate
+            # the population layout would need, not bytes moved
+            r.update(pop_form_bytes_per_lup=bpl, pop_form_equiv_gbs=round(g * bpl, 1))
+        out["%s_%s" % (form, prec)] = r
         finals[(prec, form)] = sv.get_state().astype(np.float64)
         sv.close()
     s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)

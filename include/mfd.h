@@ -200,9 +200,14 @@ int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
 int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
 
 /* Force a temporal-blocking depth (1 = none; 0 = automatic).  Blocking is
- * implemented for the MMFD form of the linear CDE and Burgers' equation on
- * D2Q5 / D2Q9 grids of at least 64 x (2 depth + 4) nodes (depth <= 16, window
- * LDS <= 160 KiB); MFD_E_UNSUPPORTED for other configured solvers. */
+ * implemented on D2Q5 / D2Q9 grids of at least 64 x (2 depth + 4) nodes
+ * (depth <= 16, window LDS <= 160 KiB) for the MMFD form of the linear CDE,
+ * Burgers' equation (two- and three-level) and the NSE (without an older-level
+ * stencil), and for the two-level MesoFD form of the linear CDE and Burgers'
+ * equation (the populations are then written at the last step of each launch
+ * only: every step depends on the one before through its moments alone, and
+ * the populations read back after mfd_step are those of the final step);
+ * MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 
 /* Force a full launch plan: tb_depth steps per launch over windows of

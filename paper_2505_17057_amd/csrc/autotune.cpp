@@ -27,7 +27,10 @@ Key key_of(const Solver &s) {
 }
 
 bool tunable(const Solver &s) {
-  return s.grid.form == MFD_MMFD && s.cfg.kind != MFD_THETA && tb_equation_supported(s.consts);
+  if (s.cfg.kind == MFD_THETA) return false;
+  if (s.grid.form == MFD_MESOFD)
+    return s.consts.dim == 2 && !s.consts.three && (s.consts.eq == kLCDE || s.consts.eq == kBurgers);
+  return tb_equation_supported(s.consts);
 }
 
 // default window height for a requested depth: the tallest window whose
@@ -35,19 +38,23 @@ bool tunable(const Solver &s) {
 int default_h(const Solver &s, int tb) {
   if (s.consts.eq == kNSE) {
     const TbPlan p{tb, 32};
-    return tb_supported(s.consts, s.G, p, (int)s.elem()) ? 32 : 0;
+    return s.plan_supported(p) ? 32 : 0;
   }
   static const int hs[] = {96, 80, 64, 48, 32};
   for (int h : hs) {
     const TbPlan p{tb, h};
-    if (tb_lds_bytes(s.consts, p, (int)s.elem()) * 3 <= 160 * 1024 &&
-        tb_supported(s.consts, s.G, p, (int)s.elem()))
-      return h;
+    if (tb_lds_bytes(s.consts, p, (int)s.elem()) * 3 <= 160 * 1024 && s.plan_supported(p)) return h;
   }
   return 0;
 }
 
 }  // namespace
+
+bool Solver::plan_supported(const TbPlan &p) const {
+  if (cfg.kind == MFD_THETA) return false;
+  if (grid.form == MFD_MESOFD) return mesofd_tb_supported(consts, G, p, (int)elem());
+  return tb_supported(consts, G, p, (int)elem());
+}
 
 TbPlan Solver::effective_plan() const {
   if (!tunable(*this)) return TbPlan{1, 0};
@@ -82,19 +89,23 @@ int Solver::autotune(int32_t *chosen) {
       return MFD_OK;
     }
   }
-  // save the live levels
+  // save the live levels (MesoFD: and the current populations)
+  const bool meso = grid.form == MFD_MESOFD;
   const size_t bytes = (size_t)(mom_elems() * elem());
-  void *save[2] = {nullptr, nullptr};
-  for (int k = 0; k < 2; ++k) {
-    hipError_t e = hipMalloc(&save[k], bytes);
+  const size_t pbytes = meso ? (size_t)(pop_elems() * elem()) : 0;
+  void *save[3] = {nullptr, nullptr, nullptr};
+  for (int k = 0; k < (meso ? 3 : 2); ++k) {
+    hipError_t e = hipMalloc(&save[k], k == 2 ? pbytes : bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      if (save[0]) (void)hipFree(save[0]);
+      for (int j = 0; j < k; ++j) (void)hipFree(save[j]);
       return fail(MFD_E_OOM, "autotune: no memory for the state copy");
     }
   }
   int rc = hip(hipMemcpyAsync(save[0], buf[ic], bytes, hipMemcpyDeviceToDevice, stream), "copy");
   if (!rc) rc = hip(hipMemcpyAsync(save[1], buf[ip], bytes, hipMemcpyDeviceToDevice, stream), "copy");
+  if (!rc && meso)
+    rc = hip(hipMemcpyAsync(save[2], buf[pc], pbytes, hipMemcpyDeviceToDevice, stream), "copy");
   const int saved_tb = tb;
   const TbPlan saved_tuned = tuned;
   const int64_t saved_steps = steps_done;
@@ -117,7 +128,7 @@ int Solver::autotune(int32_t *chosen) {
       if (rc) break;
       TbPlan p{d, d == 1 ? 0 : h, w};
       if (d == 1 && (h != heights[0] || w != widths[0])) continue;
-      if (d > 1 && !tb_supported(consts, G, p, (int)elem())) continue;
+      if (d > 1 && !plan_supported(p)) continue;
       tb = d;
       tuned = p;
       rc = step(trial);  // warm-up
@@ -139,14 +150,16 @@ int Solver::autotune(int32_t *chosen) {
   if (!rc) {
     rc = hip(hipMemcpyAsync(buf[ic], save[0], bytes, hipMemcpyDeviceToDevice, stream), "copy");
     if (!rc) rc = hip(hipMemcpyAsync(buf[ip], save[1], bytes, hipMemcpyDeviceToDevice, stream), "copy");
+    if (!rc && meso)
+      rc = hip(hipMemcpyAsync(buf[pc], save[2], pbytes, hipMemcpyDeviceToDevice, stream), "copy");
     if (!rc) rc = hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
   }
   steps_done = saved_steps;
   prev_gap = saved_gap;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(save[0]);
-  (void)hipFree(save[1]);
+  for (void *p : save)
+    if (p) (void)hipFree(p);
   if (rc) return rc;
   tuned = best;
   {

@@ -139,15 +139,17 @@ __device__ __forceinline__ T fminus(const T *r, const KC<T> &kc) {
   return kc.w1[J] * edotB<L, EQ, J>(r);
 }
 
-// full EDF g_J (MesoFD)
-template <class L, int EQ, int J, typename T>
+// full EDF g_J (MesoFD); B1 as for fplus
+template <class L, int EQ, int J, bool B1 = false, typename T>
 __device__ __forceinline__ T gfull(const T *r, const KC<T> &kc) {
   if constexpr (EQ == kLCDE) {
     return kc.ubar[J] * r[0];
   } else {
     T t = madd(edotB<L, EQ, J>(r), kc.inv_d0, r[0]);
     if constexpr (EQ == kBurgers) {
-      if (!kc.beta_one) t = t + quad<L, EQ, J>(r, kc);
+      if constexpr (!B1) {
+        if (!kc.beta_one) t = t + quad<L, EQ, J>(r, kc);
+      }
     } else {
       t = t + quad<L, EQ, J>(r, kc);
     }

@@ -187,6 +187,18 @@ int Solver::step_t(int64_t nsteps) {
         ic = io;
         io = t;
       }
+    } else if (d > 1 && plan_supported(pl) && s + d <= nsteps) {
+      // blocked MesoFD: d steps; moments of t + d into B[io], populations of
+      // t + d into pop[pn]; the held previous level is d steps old
+      e = launch_mesofd_tb<T>(consts, G, pl, B[ic], B[io], B[pn], stream);
+      if (e != hipSuccess) return hip(e, "blocked mesofd launch");
+      std::swap(pc, pn);
+      const int t = ip;
+      ip = ic;
+      ic = io;
+      io = t;
+      s += d - 1;
+      prev_gap = d;
     } else {
       // MesoFD: moments of t in B[ic] (those of pop[pc]) and of t-dt in
       // B[ip]; writes pop[pn] and its moments into B[io]; then rotate.
@@ -197,6 +209,7 @@ int Solver::step_t(int64_t nsteps) {
       ip = ic;
       ic = io;
       io = t;
+      prev_gap = 1;
     }
   }
   steps_done += nsteps;
@@ -563,8 +576,7 @@ extern "C" int mfd_set_plan(mfd_solver *h, int32_t tb_depth, int32_t window_rows
     return MFD_OK;
   }
   const TbPlan p{tb_depth, window_rows, window_cols};
-  if (s->grid.form != MFD_MMFD || s->cfg.kind == MFD_THETA ||
-      !tb_supported(s->consts, s->G, p, (int)s->elem()))
+  if (!s->plan_supported(p))
     return s->fail(MFD_E_UNSUPPORTED, "plan (%d, %d, %d) cannot be used by this configuration",
                    tb_depth, window_rows, window_cols);
   s->tb = tb_depth;

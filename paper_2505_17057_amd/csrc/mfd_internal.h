@@ -127,6 +127,12 @@ bool tb_equation_supported(const Consts &c);
 // the single-grid blocked kernel can run this plan on this grid
 bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 int tb_window_cols();
+// blocked MesoFD step, two-level linear CDE / Burgers (kernels_mesofd_tb.hip):
+// moments of level t in, moments and populations of level t + tb out
+bool mesofd_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
+template <typename T>
+hipError_t launch_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                            T *mom_out, T *pop_out, hipStream_t st);
 // blocked NSE step (kernels_nse_tb.hip): 64 x 32 or 64 x 64 windows
 bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem);
 template <typename T>

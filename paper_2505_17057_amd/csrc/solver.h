@@ -60,6 +60,7 @@ struct Solver {
   int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
   int step(int64_t nsteps);
   TbPlan effective_plan() const;
+  bool plan_supported(const TbPlan &p) const;  // the blocked kernel of this form can run p
   int autotune(int32_t *chosen);
   template <typename T>
   int step_t(int64_t nsteps);

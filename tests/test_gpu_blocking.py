@@ -1,4 +1,4 @@
-"""GPU: temporal blocking, autotuning, reductions and the binary32 MesoFD
+"""GPU: temporal blocking (MMFD and MesoFD), autotuning, reductions and the binary32 MesoFD
 mass balance.
 
 * Blocked LCDE and Burgers steps (depth 2, 4, 6, 8) equal the FP64 oracle
@@ -177,6 +177,91 @@ def test_blocked_fp32_equals_unblocked(M, name):
         outs.append(s.get_state())
         s.close()
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+MESO = {
+    "lcde-d2q9": dict(BASE, a=(1.0, 0.0, 0.0)),
+    "lcde-d2q9-a": dict(BASE, a=(0.9, 0.05, 0.1)),
+    "lcde-d2q5": dict(BASE, lattice="D2Q5", K=[[0.3, 0.0], [0.0, 0.2]], a=(1.0, 0.0, 0.0)),
+    "burgers-d2q9": dict(lattice="D2Q9", eq="burgers", **_burgers_a(150)),
+    "burgers-beta-d2q9": dict(lattice="D2Q9", eq="burgers", beta=0.6, **_burgers_a(150)),
+    "burgers-d2q5": dict(lattice="D2Q5", eq="burgers", **_burgers_a(150)),
+}
+
+
+def _meso_oracle(case, cur, steps):
+    from oracle import native as O
+    from parity_util import oracle_spec
+    spec = oracle_spec(case)
+    pop = O.init_populations(spec, cur)
+    for _ in range(steps):
+        pop, _ = O.mesofd_step(spec, pop, None)
+    return pop, O.moments(spec, pop)
+
+
+@pytest.mark.parametrize("plan", [(2, 32, 64), (3, 48, 64), (4, 40, 128), (8, 48, 128)])
+@pytest.mark.parametrize("name", list(MESO))
+@pytest.mark.parametrize("n", [(150, 77), (64, 32)])
+def test_mesofd_blocked_fp64_bitwise(M, plan, name, n):
+    """Blocked MesoFD launches (moments carried in the window, populations of
+    the last step written out) equal the oracle: moments and populations,
+    value for value, also after a ragged remainder of single steps."""
+    from parity_util import make_solver
+    if plan[1] > n[1] or plan[2] > n[0]:
+        pytest.skip("window larger than the grid")
+    case = dict(MESO[name], n=n, name=name, form="mesofd")
+    print("case", name, plan, n, flush=True)
+    rng = np.random.default_rng(19)
+    cur = rand_state(case, rng)
+    steps = 2 * plan[0] + 3
+    pop, want = _meso_oracle(case, cur, steps)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    assert s.launch_plan() == plan
+    s.set_state(cur)
+    s.step(steps)
+    got = s.get_state()
+    gpop = s.get_state(populations=True)
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    assert np.array_equal(gpop, pop), np.abs(gpop - pop).max()
+
+
+@pytest.mark.parametrize("name", list(MESO))
+def test_mesofd_blocked_fp32_equals_unblocked(M, name):
+    from parity_util import make_solver
+    case = dict(MESO[name], n=(300, 140), name=name, form="mesofd")
+    rng = np.random.default_rng(20)
+    cur = rand_state(case, rng).astype(np.float32)
+    outs = []
+    for plan in ((1,), (4, 32, 64), (6, 64, 128)):
+        s = make_solver(M, case, "fp32")
+        s.set_plan(*plan)
+        s.set_state(cur)
+        s.step(10)
+        s.step(27)
+        outs.append((s.get_state(), s.get_state(populations=True)))
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
+
+
+def test_mesofd_autotune_preserves_state(M):
+    from parity_util import make_solver
+    case = dict(MESO["lcde-d2q9"], n=(256, 128), form="mesofd")
+    rng = np.random.default_rng(22)
+    cur = rand_state(case, rng)
+    s = make_solver(M, case, "fp64")
+    s.set_state(cur)
+    s.step(3)
+    before = s.get_state(populations=True)
+    s.autotune()
+    assert np.array_equal(s.get_state(populations=True), before)
+    s.step(11)
+    pop, want = _meso_oracle(case, cur, 14)
+    assert np.array_equal(s.get_state(), want)
+    assert np.array_equal(s.get_state(populations=True), pop)
+    s.close()
 
 
 def test_autotune_preserves_state(M):
