@@ -103,14 +103,15 @@ def launch_durations(torch, s, tb, n=1000):
 def stored_traffic(kernel_src, tb, h, w):
     """(HBM bytes per launch, profiled plan) from the committed rocprofv3
     counter summary, if it was taken on the current kernel source with the
-    same steps per launch (the window shape changes only halo re-reads, which
-    the profiled plan states); else (None, None)."""
+    same steps per launch and window width (the window height changes only
+    halo re-reads, which the profiled plan states); else (None, None)."""
     path = os.path.join(ROOT, "profiles", "traffic_mmfd_lcde_d2q9_2048_fp32.json")
     if not os.path.exists(path):
         return None, None
     info = json.load(open(path))
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if info.get("kernel_source_sha256") != sha or info.get("time_steps_per_launch") != tb:
+    if (info.get("kernel_source_sha256") != sha or info.get("time_steps_per_launch") != tb
+            or info.get("window_cols") != w):
         return None, None
     plan = [info.get("time_steps_per_launch"), info.get("window_rows"), info.get("window_cols")]
     return info.get("hbm_bytes_per_launch"), plan
@@ -466,12 +467,17 @@ def main():
         how = "HIP events around 1000 back-to-back launches"
     alg_bytes = 8.0 * N * tb  # read phi^n, write phi^(n+1): 8 B per LUP in FP32
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
-    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc",
-                              "kernels_tb.hip" if tb > 1 else "kernels_mmfd.hip")
+    # the step kernel of this plan: the lane-shared LCDE window (64 or 126
+    # columns), the general blocked window (128 columns), or one step a launch
+    kname, ksrc = (("k_lcde_tb", "kernels_lcde_tb.hip") if tb > 1 and w in (64, 126) else
+                   ("k_mmfd_tb", "kernels_tb.hip") if tb > 1 else
+                   ("k_mmfd_plane", "kernels_mmfd.hip"))
+    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc", ksrc)
     traffic, traffic_plan = stored_traffic(kernel_src, tb, h, w)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=("k_mmfd_tb" if tb > 1 else "k_mmfd_plane") + " D2Q9 LCDE FP32",
+                    kernel=kname + " D2Q9 LCDE FP32",
+                    kernel_source="paper_2505_17057_amd/csrc/" + ksrc,
                     launch_ms_mean=round(mean_ms, 5), launch_timing=how,
                     time_steps_per_launch=tb, window_rows=h, window_cols=w,
                     algorithmic_bytes_per_launch=alg_bytes,

@@ -113,13 +113,15 @@ int Solver::autotune(int32_t *chosen) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) rc = hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = hip(hipEventCreate(&e1), "hipEventCreate");
-  // trial length: whole blocks for every depth, ~2^29 node updates
+  // trial length: whole blocks for every depth (a multiple of 120), ~2^29
+  // node updates
   int64_t trial = ((int64_t)1 << 29) / G.N;
-  trial = trial < 24 ? 24 : (trial > 480 ? 480 : trial);
-  trial = (trial / 24) * 24;
-  const int depths[] = {1, 2, 4, 6, 8};
-  const int heights[] = {32, 48, 64, 80, 96, 112, 128};
-  const int widths[] = {64, 128};
+  trial = trial < 120 ? 120 : (trial > 480 ? 480 : trial);
+  trial = (trial / 120) * 120;
+  const int depths[] = {1, 2, 4, 6, 8, 10, 12};
+  int heights[25];
+  for (int i = 0; i < 25; ++i) heights[i] = 32 + 4 * i;  // 32 .. 128
+  const int widths[] = {64, 126, 128};
   float best_ms = 1e30f;
   TbPlan best{1, 0};
   for (int d : depths) {

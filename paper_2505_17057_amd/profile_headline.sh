@@ -13,12 +13,15 @@ mkdir -p "$O"
 export TMPDIR=/tmp
 echo "profile: kernel trace"
 (cd /tmp && timeout -k 10 240 rocprofv3 --kernel-trace --stats -d "$O/prof_kt" -o kt -- python3 $R/bench.py --quick --steps 5 --warmup 1 --no-cpu --copy-calibration > "$O/prof_kt.txt" 2>&1) || exit 2
-# the counter runs use the plan the autotuner chose in the traced run
-PLAN=$(python3 -c "import json,sys
+# the counter runs use the plan the autotuner chose in the traced run, and
+# the summary takes the kernel that plan runs
+read PLAN KNAME KSRC < <(python3 -c "import json,sys
 for l in open(sys.argv[1]):
     if l.startswith('{'):
-        r = json.loads(l)['roofline']; print('%d,%d,%d' % (r['time_steps_per_launch'], r['window_rows'], r['window_cols']))" "$O/prof_kt.txt")
-echo "plan $PLAN"
+        r = json.loads(l)['roofline']
+        print('%d,%d,%d' % (r['time_steps_per_launch'], r['window_rows'], r['window_cols']),
+              r['kernel'].split()[0], r['kernel_source'])" "$O/prof_kt.txt")
+echo "plan $PLAN kernel $KNAME ($KSRC)"
 echo "profile: FETCH_SIZE"
 (cd /tmp && timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --kernel-trace -d "$O/prof_fetch" -o f -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration --plan $PLAN > "$O/prof_fetch.txt" 2>&1) || exit 3
 echo "profile: WRITE_SIZE"
@@ -26,8 +29,8 @@ echo "profile: WRITE_SIZE"
 N=4194304
 python3 -m paper_2505_17057_amd.profiling --trace "$O/prof_kt/kt_results.db" \
   --fetch "$O/prof_fetch/f_results.db" --write "$O/prof_write/w_results.db" \
-  --kernel k_mmfd_tb --copy-bytes 268435456 \
-  --kernel-source paper_2505_17057_amd/csrc/kernels_tb.hip --bench-log "$O/prof_kt.txt" \
+  --kernel "$KNAME" --copy-bytes 268435456 \
+  --kernel-source "$KSRC" --bench-log "$O/prof_kt.txt" \
   --algorithmic-bytes-per-step $((8 * N)) --pass-bytes $((8 * N)) \
   --workload "2D linear CDE, D2Q9, 2048x2048, MMFD FP32 (bench.py headline)" \
   --out-md "$O/mmfd_lcde_d2q9_2048_fp32.md" --out-json "$O/traffic_mmfd_lcde_d2q9_2048_fp32.json" \

@@ -264,6 +264,40 @@ def test_mesofd_autotune_preserves_state(M):
     s.close()
 
 
+@pytest.mark.parametrize("plan", [(4, 40, 126), (8, 48, 126), (2, 20, 126), (16, 40, 126),
+                                  (3, 32, 64), (8, 64, 64), (16, 36, 64)])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q5"])
+def test_lcde_lane_shared_fp32_equals_unblocked(M, plan, lattice):
+    """The binary32 two-level LCDE window whose lanes share neighbour values
+    (64 or 126 columns) equals the single-step kernel bit for bit, on a grid
+    with ragged tiles in both directions."""
+    from parity_util import make_solver
+    K = K2 if lattice == "D2Q9" else [[0.3, 0.0], [0.0, 0.2]]
+    case = dict(BASE, lattice=lattice, K=K, n=(301, 139), a=(1.0, 0.0, 0.0))
+    print("case", lattice, plan, flush=True)
+    rng = np.random.default_rng(23)
+    cur = rand_state(case, rng).astype(np.float32)
+    outs = []
+    for p in ((1,), plan):
+        s = make_solver(M, case, "fp32")
+        s.set_plan(*p)
+        assert s.launch_plan()[0] == p[0]
+        s.set_state(cur)
+        s.step(3 * plan[0] + 1)
+        outs.append(s.get_state())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]), np.abs(outs[0] - outs[1]).max()
+
+
+def test_lane_shared_width_only_for_binary32_lcde(M):
+    from parity_util import make_solver
+    for name, prec in (("2l", "fp64"), ("3l-trt", "fp32"), ("burgers-2l", "fp32")):
+        s = make_solver(M, _case(name, (200, 100)), prec)
+        with pytest.raises(M.MfdError):
+            s.set_plan(4, 40, 126)
+        s.close()
+
+
 def test_autotune_preserves_state(M):
     from parity_util import make_solver
     case = _case("2l", (256, 128))
@@ -274,9 +308,9 @@ def test_autotune_preserves_state(M):
     s.step(5)
     before = s.get_state()
     d = s.autotune()
-    assert d in (1, 2, 4, 6, 8)
+    assert d in (1, 2, 4, 6, 8, 10, 12)
     tb, h, w = s.launch_plan()
-    assert tb == d and (h == 0) == (d == 1) and w in ((0,) if d == 1 else (64, 128))
+    assert tb == d and (h == 0) == (d == 1) and w in ((0,) if d == 1 else (64, 126, 128))
     assert np.array_equal(s.get_state(), before)
     s.step(9)
     ref = make_solver(M, case, "fp64")
