@@ -467,9 +467,9 @@ def main():
         how = "HIP events around 1000 back-to-back launches"
     alg_bytes = 8.0 * N * tb  # read phi^n, write phi^(n+1): 8 B per LUP in FP32
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
-    # the step kernel of this plan: the lane-shared LCDE window (64 or 126
-    # columns), the general blocked window (128 columns), or one step a launch
-    kname, ksrc = (("k_lcde_tb", "kernels_lcde_tb.hip") if tb > 1 and w in (64, 126) else
+    # the step kernel of this plan: the in-place lane-shared LCDE window (128
+    # columns), the general blocked window (64 columns), or one step a launch
+    kname, ksrc = (("k_lane_tb", "kernels_lane_tb.hip") if tb > 1 and w == 128 else
                    ("k_mmfd_tb", "kernels_tb.hip") if tb > 1 else
                    ("k_mmfd_plane", "kernels_mmfd.hip"))
     kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc", ksrc)

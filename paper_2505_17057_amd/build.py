@@ -28,7 +28,7 @@ SOURCES = [
     "kernels_mmfd.hip",
     "kernels_tb.hip",
     "kernels_nse_tb.hip",
-    "kernels_lcde_tb.hip",
+    "kernels_lane_tb.hip",
     "kernels_mesofd_tb.hip",
     "kernels_mesofd.hip",
     "kernels_misc.hip",

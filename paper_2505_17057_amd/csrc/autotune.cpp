@@ -113,15 +113,14 @@ int Solver::autotune(int32_t *chosen) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) rc = hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = hip(hipEventCreate(&e1), "hipEventCreate");
-  // trial length: whole blocks for every depth (a multiple of 120), ~2^29
-  // node updates
-  int64_t trial = ((int64_t)1 << 29) / G.N;
-  trial = trial < 120 ? 120 : (trial > 480 ? 480 : trial);
-  trial = (trial / 120) * 120;
-  const int depths[] = {1, 2, 4, 6, 8, 10, 12};
+  // trial length: ~2^29 node updates, in whole blocks of each depth; the
+  // candidates are compared by time per step
+  int64_t trial0 = ((int64_t)1 << 29) / G.N;
+  trial0 = trial0 < 96 ? 96 : (trial0 > 480 ? 480 : trial0);
+  const int depths[] = {1, 2, 4, 6, 8, 10, 12, 14, 16};
   int heights[25];
   for (int i = 0; i < 25; ++i) heights[i] = 32 + 4 * i;  // 32 .. 128
-  const int widths[] = {64, 126, 128};
+  const int widths[] = {64, 128};
   float best_ms = 1e30f;
   TbPlan best{1, 0};
   for (int d : depths) {
@@ -133,6 +132,7 @@ int Solver::autotune(int32_t *chosen) {
       if (d > 1 && !plan_supported(p)) continue;
       tb = d;
       tuned = p;
+      const int64_t trial = d * ((trial0 + d - 1) / d);
       rc = step(trial);  // warm-up
       if (rc) break;
       rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
@@ -141,6 +141,7 @@ int Solver::autotune(int32_t *chosen) {
       if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
       float ms = 0.f;
       if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      ms /= (float)trial;
       if (!rc && ms < best_ms) {
         best_ms = ms;
         best = p;

@@ -1,0 +1,498 @@
+// Temporally blocked binary32 MMFD steps of the two-level linear CDE and of
+// Burgers' equation (beta = 1) on D2Q5 / D2Q9: one launch advances TB time
+// steps of a 128-column window updated in place, with neighbour values
+// shared across the lanes of a wavefront instead of formed again or read
+// again from LDS.  Results equal the single-step kernel's value for value.
+//
+// Linear CDE (Eq. (LMMFD-3)): the binary32 pair form of the single-step
+// kernel (mmfd_node): acc = sum over pairs p of A+_p (phi(x + e_p) - phi(x))
+// and A-_p (phi(x - e_p) - phi(x)), in pair order, then phi' = A0 phi + acc.
+// Each difference phi(x - e_p) - phi(x) is the negative of a difference
+// phi(y + e_p) - phi(y) that the node y = x - e_p forms for its own first
+// term, so every node forms one difference per pair (4 on D2Q9) and takes
+// the other from where it was formed: from the lane to its left or right by
+// a DPP lane shift fused into the subtraction or multiply-add, from the
+// lane's other column, or for the row below from its own registers of the
+// previous row.  Negation is exact.
+//
+// Burgers' equation (Eq. (2-2-1) with the EDF of Eq. (3-4)): each node forms
+// its pair parts F+-_p once and shares them the same way (see BurgSeg).
+#include <map>
+#include <type_traits>
+#include <mutex>
+#include <tuple>
+
+#include "mfd_internal.h"
+
+namespace mfd {
+
+namespace {
+
+struct LinC {
+  float ap[4], nam[4];  // A+_p and -A-_p
+  float a0;
+};
+
+__device__ __forceinline__ int xcd_remap_l(int bid, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
+// value of the lane one above (lane + 1) / one below (lane - 1) in the
+// wavefront; lanes without a source read 0
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+
+// acc + x[lane - 1] * c and acc + x[lane + 1] * c, one fused multiply-add with
+// the lane shift on its first source.  The two wait states before it let a
+// value written by the instruction just before be read through the shift.
+__device__ __forceinline__ float fmac_from_left(float acc, float x, float c) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(x), "v"(c));
+  return acc;
+}
+__device__ __forceinline__ float fmac_from_right(float acc, float x, float c) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(x), "v"(c));
+  return acc;
+}
+
+// LDS-only barrier: waits for this wavefront's LDS operations, not for its
+// global loads (the next window's loads stay in flight across the steps)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+}  // namespace
+
+// Lane l owns columns 2l and 2l + 1 of a 128-column window (one wavefront
+// spans it; its first and last columns, whose neighbours lie outside the
+// wavefront, are never updated: every step updates a region one node smaller
+// than the last), and the window lives in one LDS buffer updated in place.
+// Wavefront g owns a segment of rows; it reads each row before it overwrites
+// the row above it, and its two boundary rows (the row above its segment and
+// the one below, which the neighbouring segments overwrite) are read into
+// registers before a barrier at the start of every step.  Every lane computes
+// its columns in every step; values outside the step's region are not used
+// by any later update of the region.  The last step writes the tile's
+// interior straight to global memory.
+//
+// Workgroups are persistent: workgroup b takes the tiles of the virtual
+// blocks b, b + G, b + 2G, ... (G = gridDim.x, a multiple of 8, so that every
+// virtual block of a workgroup maps to tiles of its own XCD).  While a tile's
+// steps run, the next tile's window is loaded into registers, and it goes to
+// the buffer after the last step.
+template <int P>
+struct PairNode {
+  // rc: row y, rn: row y + 1 of this lane's two columns; d*: the differences
+  // of row y - 1 (e: column 2l, o: column 2l + 1); returns the new values
+  // and leaves the differences of row y in d*.
+  float ap[4], nam[4], a0;
+  __device__ __forceinline__ float2 operator()(float2 rc, float2 rn, float &dye, float &dyo,
+                                               float &dde, float &ddo, float &dae,
+                                               float &dao) const {
+    // x differences: phi(x+1, y) - phi(x, y)
+    const float dxe = rc.y - rc.x;
+    const float dxo = from_right(rc.x) - rc.y;
+    const float nye = rn.x - rc.x, nyo = rn.y - rc.y;
+    // column 2l: left neighbour's x difference from lane l - 1
+    float ae = __builtin_fmaf(ap[0], dxe, 0.0f);
+    ae = fmac_from_left(ae, dxo, nam[0]);
+    ae = __builtin_fmaf(ap[1], nye, ae);
+    ae = __builtin_fmaf(nam[1], dye, ae);
+    // column 2l + 1: its left neighbour is column 2l of this lane
+    float ao = __builtin_fmaf(ap[0], dxo, 0.0f);
+    ao = __builtin_fmaf(nam[0], dxe, ao);
+    ao = __builtin_fmaf(ap[1], nyo, ao);
+    ao = __builtin_fmaf(nam[1], dyo, ao);
+    dye = nye;
+    dyo = nyo;
+    if constexpr (P == 4) {
+      // (1, 1): phi(x+1, y+1) - phi(x, y); (-1, 1): phi(x-1, y+1) - phi(x, y)
+      const float nde = rn.y - rc.x, ndo = from_right(rn.x) - rc.y;
+      const float nae = from_left(rn.y) - rc.x, nao = rn.x - rc.y;
+      ae = __builtin_fmaf(ap[2], nde, ae);
+      ae = fmac_from_left(ae, ddo, nam[2]);  // (2l-1, y-1): lane l - 1
+      ae = __builtin_fmaf(ap[3], nae, ae);
+      ae = __builtin_fmaf(nam[3], dao, ae);  // (2l+1, y-1): this lane
+      ao = __builtin_fmaf(ap[2], ndo, ao);
+      ao = __builtin_fmaf(nam[2], dde, ao);  // (2l, y-1): this lane
+      ao = __builtin_fmaf(ap[3], nao, ao);
+      ao = fmac_from_right(ao, dae, nam[3]);  // (2l+2, y-1): lane l + 1
+      dde = nde;
+      ddo = ndo;
+      dae = nae;
+      dao = nao;
+    }
+    return make_float2(__builtin_fmaf(a0, rc.x, ae), __builtin_fmaf(a0, rc.y, ao));
+  }
+};
+
+// Row segment of the linear CDE: rows [ya, yb) of the window, `top` the row
+// above, `bot` the row below (both read before the step's first barrier).
+template <int P>
+struct LinSeg {
+  using Params = LinC;
+  static constexpr int kRG = 8, kNPF = 32;  // 8 wavefronts, 16 rows each
+  PairNode<P> node;
+  __device__ __forceinline__ explicit LinSeg(const LinC &kc) {
+    node.a0 = kc.a0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      node.ap[p] = kc.ap[p];
+      node.nam[p] = kc.nam[p];
+      // in vector registers, so that the lane shifts fuse into the
+      // multiply-adds
+      asm("" : "+v"(node.ap[p]));
+      asm("" : "+v"(node.nam[p]));
+    }
+  }
+  template <class Emit>
+  __device__ __forceinline__ void operator()(const float2 *lds, int lane, int ya, int yb,
+                                             float2 top, float2 bot, const Emit &emit) const {
+    float2 rc = lds[ya * 64 + lane];
+    // differences of row ya - 1
+    float dye = rc.x - top.x, dyo = rc.y - top.y;
+    float dde = rc.y - top.x, ddo = from_right(rc.x) - top.y;
+    float dae = from_left(rc.y) - top.x, dao = rc.x - top.y;
+    int y = ya;
+    // two rows per pass: both rows are read before either is written
+    for (; y + 2 < yb; y += 2) {
+      const float2 r1 = lds[(y + 1) * 64 + lane];
+      const float2 r2 = lds[(y + 2) * 64 + lane];
+      const float2 o1 = node(rc, r1, dye, dyo, dde, ddo, dae, dao);
+      const float2 o2 = node(r1, r2, dye, dyo, dde, ddo, dae, dao);
+      emit(y, o1);
+      emit(y + 1, o2);
+      rc = r2;
+    }
+    if (y + 1 < yb) {
+      const float2 r1 = lds[(y + 1) * 64 + lane];
+      const float2 o1 = node(rc, r1, dye, dyo, dde, ddo, dae, dao);
+      const float2 o2 = node(r1, bot, dye, dyo, dde, ddo, dae, dao);
+      emit(y, o1);
+      emit(y + 1, o2);
+    } else {
+      emit(y, node(rc, bot, dye, dyo, dde, ddo, dae, dao));
+    }
+  }
+};
+
+// Burgers' equation with beta = 1 (D2Q9 or D2Q5), binary32: the node update
+// of the single-step kernel (mmfd_node with the records phi and
+// s = phi^2 dt / (2 dx)), whose pair parts are F+_p = w_p phi and
+// F-_p = w1_p (e_p . (s, s)).  By the lattice symmetry they take four values
+// per node: fa = w_a phi (axis pairs), fd = w_d phi (diagonal pairs),
+// ga = w1_a s (axis pairs), gd = w1_d (s + s) (the (1, 1) pair; the (-1, 1)
+// pair's is 0).  Each node forms its four once, when its row enters, and its
+// neighbours take them from its lane (DPP) or from their own registers of
+// the rows above and below, instead of forming them again from records.
+struct BurgC {
+  float wa, wd, w1a, w1d, bh, cpl, cmi, a0;
+};
+
+struct PP {  // pair parts of a lane's two columns
+  float fae, fao, fde, fdo, gae, gao, gde, gdo;
+};
+
+template <int P>
+struct BurgSeg {
+  using Params = BurgC;
+  static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
+  BurgC k;
+  __device__ __forceinline__ explicit BurgSeg(const BurgC &kc) : k(kc) {}
+  __device__ __forceinline__ PP parts(float2 r) const {
+    PP q;
+    const float se = (r.x * r.x) * k.bh, so = (r.y * r.y) * k.bh;
+    q.fae = k.wa * r.x;
+    q.fao = k.wa * r.y;
+    q.gae = k.w1a * se;
+    q.gao = k.w1a * so;
+    if constexpr (P == 4) {
+      q.fde = k.wd * r.x;
+      q.fdo = k.wd * r.y;
+      q.gde = k.w1d * (se + se);
+      q.gdo = k.w1d * (so + so);
+    } else {
+      q.fde = q.fdo = q.gde = q.gdo = 0.0f;
+    }
+    return q;
+  }
+  // node update of row y: c, n, p the pair parts of rows y, y + 1, y - 1
+  __device__ __forceinline__ float2 node(float2 rc, const PP &c, const PP &n,
+                                         const PP &p) const {
+    const float two = 2.0f;
+    // column 2l: x - 1 is lane l - 1's column 2l - 1
+    const float t2ae = two * c.fae;
+    float ae = __builtin_fmaf(k.cpl, (c.fao - t2ae) + from_left(c.fao), 0.0f);
+    ae = __builtin_fmaf(k.cmi, c.gao - from_left(c.gao), ae);
+    ae = __builtin_fmaf(k.cpl, (n.fae - t2ae) + p.fae, ae);
+    ae = __builtin_fmaf(k.cmi, n.gae - p.gae, ae);
+    // column 2l + 1: x + 1 is lane l + 1's column 2l + 2
+    const float t2ao = two * c.fao;
+    float ao = __builtin_fmaf(k.cpl, (from_right(c.fae) - t2ao) + c.fae, 0.0f);
+    ao = __builtin_fmaf(k.cmi, from_right(c.gae) - c.gae, ao);
+    ao = __builtin_fmaf(k.cpl, (n.fao - t2ao) + p.fao, ao);
+    ao = __builtin_fmaf(k.cmi, n.gao - p.gao, ao);
+    if constexpr (P == 4) {
+      // (1, 1): x + e = (x+1, y+1), x - e = (x-1, y-1)
+      const float t2de = two * c.fde;
+      ae = __builtin_fmaf(k.cpl, (n.fdo - t2de) + from_left(p.fdo), ae);
+      ae = __builtin_fmaf(k.cmi, n.gdo - from_left(p.gdo), ae);
+      // (-1, 1): x + e = (x-1, y+1), x - e = (x+1, y-1); its F- is 0
+      ae = __builtin_fmaf(k.cpl, (from_left(n.fdo) - t2de) + p.fdo, ae);
+      ae = __builtin_fmaf(k.cmi, 0.0f, ae);
+      const float t2do = two * c.fdo;
+      ao = __builtin_fmaf(k.cpl, (from_right(n.fde) - t2do) + p.fde, ao);
+      ao = __builtin_fmaf(k.cmi, from_right(n.gde) - p.gde, ao);
+      ao = __builtin_fmaf(k.cpl, (n.fde - t2do) + from_right(p.fde), ao);
+      ao = __builtin_fmaf(k.cmi, 0.0f, ao);
+    }
+    return make_float2(__builtin_fmaf(k.a0, rc.x, ae), __builtin_fmaf(k.a0, rc.y, ao));
+  }
+  template <class Emit>
+  __device__ __forceinline__ void operator()(const float2 *lds, int lane, int ya, int yb,
+                                             float2 top, float2 bot, const Emit &emit) const {
+    float2 rc = lds[ya * 64 + lane];
+    PP pp = parts(top), pc = parts(rc);
+    int y = ya;
+    for (; y + 2 < yb; y += 2) {
+      const float2 r1 = lds[(y + 1) * 64 + lane];
+      const float2 r2 = lds[(y + 2) * 64 + lane];
+      const PP p1 = parts(r1);
+      const float2 o1 = node(rc, pc, p1, pp);
+      const PP p2 = parts(r2);
+      const float2 o2 = node(r1, p1, p2, pc);
+      emit(y, o1);
+      emit(y + 1, o2);
+      rc = r2;
+      pp = p1;
+      pc = p2;
+    }
+    if (y + 1 < yb) {
+      const float2 r1 = lds[(y + 1) * 64 + lane];
+      const PP p1 = parts(r1);
+      const float2 o1 = node(rc, pc, p1, pp);
+      const float2 o2 = node(r1, p1, parts(bot), pc);
+      emit(y, o1);
+      emit(y + 1, o2);
+    } else {
+      emit(y, node(rc, pc, parts(bot), pp));
+    }
+  }
+};
+
+// One kernel for every lane-shared segment type Seg; RG wavefronts of row
+// segments; NPF prefetch values per thread (NPF / 2 rows of the next window).
+template <class Seg, int RG, int NPF>
+__global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ cur,
+                                                    float *__restrict__ out, int nx, int ny, int H,
+                                                    int TB, int tiles_x, int ntiles,
+                                                    typename Seg::Params kc) {
+  constexpr int W = 128, ROWS = NPF / 2;
+  extern __shared__ unsigned char smem_lane[];
+  float2 *lds = reinterpret_cast<float2 *>(smem_lane);  // [H][64]
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int G = gridDim.x;
+  if ((int)blockIdx.x >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Seg seg_run(kc);
+
+  // window rows rg, rg + RG, ... of the tile whose origin is (x0, y0)
+  float pf[NPF];
+  auto fetch = [&](int x0, int y0) {
+    int ge = x0 + 2 * lane, go = ge + 1;
+    ge = ge < 0 ? ge + nx : (ge >= nx ? ge - nx : ge);
+    go = go < 0 ? go + nx : (go >= nx ? go - nx : go);
+    // byte offsets within a row (a row is far below 4 GiB): each load is a
+    // row base in scalar registers plus one of these two offsets
+    const uint32_t be = (uint32_t)ge * 4u, bo = (uint32_t)go * 4u;
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      const int r = min(rg + RG * j, H - 1);
+      int y = y0 + r;
+      y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+      const char *row = reinterpret_cast<const char *>(cur + (int64_t)y * nx);
+      pf[2 * j] = *reinterpret_cast<const float *>(row + be);
+      pf[2 * j + 1] = *reinterpret_cast<const float *>(row + bo);
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      const int r = rg + RG * j;
+      if (r < H) lds[r * 64 + lane] = make_float2(pf[2 * j], pf[2 * j + 1]);
+    }
+  };
+
+  int v = blockIdx.x;
+  int tile = xcd_remap_l(v, ntiles);
+  int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
+  fetch(x0, y0);
+  put();
+  lds_barrier();
+  while (true) {
+    const int vn = v + G;
+    const bool more = vn < ntiles;
+    int xn = 0, yn = 0;
+    if (more) {
+      const int tn = xcd_remap_l(vn, ntiles);
+      xn = (tn % tiles_x) * TX - TB;
+      yn = (tn / tiles_x) * TY - TB;
+      fetch(xn, yn);
+    }
+    // this lane's columns inside the tile's interior (last step's stores)
+    const int c0 = 2 * lane;
+    const bool se = c0 >= TB && c0 < W - TB && x0 + c0 < nx;
+    const bool so = c0 + 1 >= TB && c0 + 1 < W - TB && x0 + c0 + 1 < nx;
+#pragma unroll 1
+    for (int t = 1; t <= TB; ++t) {
+      const int Hr = H - 2 * t;
+      const int seg = (Hr + RG - 1) / RG;
+      const int ya = t + rg * seg, yb = min(ya + seg, H - t);
+      const bool act = ya < yb;  // uniform across the wavefront
+      float2 top = make_float2(0.f, 0.f), bot = top;
+      if (act) {
+        top = lds[(ya - 1) * 64 + lane];
+        bot = lds[yb * 64 + lane];
+      }
+      lds_barrier();
+      if (act) {
+        if (t < TB) {
+          seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) { lds[y * 64 + lane] = o; });
+        } else {
+          seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) {
+            const int gy = y0 + y;
+            if (gy < ny) {
+              float *row = out + (int64_t)gy * nx + x0 + c0;
+              if (se) row[0] = o.x;
+              if (so) row[1] = o.y;
+            }
+          });
+        }
+      }
+      lds_barrier();
+    }
+    if (!more) break;
+    put();
+    lds_barrier();
+    v = vn;
+    x0 = xn;
+    y0 = yn;
+  }
+}
+
+// ------------------------------------------------------------ host side
+namespace {
+// Burgers' pair parts take one value per weight class only when the
+// directions of a class carry equal weights in binary32
+bool burgers_weights_symmetric(const KC<float> &k, int lattice) {
+  if (k.w[1] != k.w[2] || k.w1[1] != k.w1[2]) return false;
+  return lattice != 3 || k.w[5] == k.w[6];
+}
+}  // namespace
+
+bool lane_tb_applies(const Consts &c, int elem) {
+  if (elem != 4 || c.three || c.dim != 2 || (c.lattice != 2 && c.lattice != 3)) return false;
+  if (c.eq == kLCDE) return true;
+  if (c.eq != kBurgers || !c.beta_one) return false;
+  return burgers_weights_symmetric(make_kc<float>(c), c.lattice);
+}
+
+bool lane_tb_window_fits(const TbPlan &pl) {
+  return pl.w == 128 && pl.h <= 128;  // RG NPF / 2 = 128 rows of prefetch
+}
+
+namespace {
+// resident workgroups per CU and CUs of the current device (cached)
+int lane_slots(const void *fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void *, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_tuple(dev, fn, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int slots = (per_cu < 1 ? 1 : per_cu) * cus;
+  cache[key] = slots;
+  return slots;
+}
+
+// 128-column window in place: RG wavefronts, NPF / 2 rows of the next
+// window each (RG NPF / 2 = 128 rows)
+template <class Seg>
+hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *out,
+                    const typename Seg::Params &prm, hipStream_t st) {
+  constexpr int RG = Seg::kRG, NPF = Seg::kNPF, W = 128;
+  if (pl.h > RG * NPF / 2) return hipErrorInvalidValue;
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  const int TX = W - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = (size_t)pl.h * W * sizeof(float);
+  auto fn = k_lane_tb<Seg, RG, NPF>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  // persistent grid: the resident workgroups, a multiple of 8 (XCDs)
+  const int ntiles = tx * ty;
+  int grid = lane_slots((const void *)fn, 64 * RG, lds);
+  if (grid <= 0) return hipErrorInvalidValue;
+  grid = grid < ntiles ? grid : ntiles;
+  if (grid >= 8) grid &= ~7;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st, cur, out, nx, ny, pl.h, pl.tb, tx,
+                     ntiles, prm);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur, float *out,
+                   hipStream_t st) {
+  const KC<float> k = make_kc<float>(c);
+  if (c.eq == kLCDE) {
+    LinC lc{};
+    for (int p = 0; p < P; ++p) {
+      lc.ap[p] = k.Ap[p];
+      lc.nam[p] = -k.Am[p];
+    }
+    lc.a0 = k.A0t;
+    return lane_cfg<LinSeg<P>>(g, pl, cur, out, lc, st);
+  }
+  if (!burgers_weights_symmetric(k, c.lattice)) return hipErrorInvalidValue;
+  BurgC bc{};
+  bc.wa = k.w[1];
+  bc.wd = P == 4 ? k.w[5] : 0.0f;
+  bc.w1a = k.w1[1];
+  bc.w1d = P == 4 ? k.w1[5] : 0.0f;
+  bc.bh = k.bh;
+  bc.cpl = k.ap;
+  bc.cmi = k.am;
+  bc.a0 = k.A0t;
+  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, bc, st);
+}
+}  // namespace
+
+hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
+                          float *out, hipStream_t st) {
+  if (!lane_tb_applies(c, 4) || pl.w != 128) return hipErrorInvalidValue;
+  if (c.lattice == 3) return lane_eq<4>(c, g, pl, cur, out, st);
+  return lane_eq<2>(c, g, pl, cur, out, st);
+}
+
+}  // namespace mfd

@@ -289,8 +289,8 @@ hipError_t btb_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, i
 
 size_t tb_lds_bytes(const Consts &c, const TbPlan &pl, int elem) {
   if (c.eq == kNSE) return (size_t)2 * c.npair * pl.h * pl.w * elem;  // pair parts only
-  const int pitch = pl.w == 126 ? 128 : pl.w;  // lane-shared LCDE window
-  return (size_t)(c.three ? 3 : 2) * pl.h * pitch * elem;
+  if (pl.w == 128 && lane_tb_applies(c, elem)) return (size_t)pl.h * 128 * elem;  // in place
+  return (size_t)(c.three ? 3 : 2) * pl.h * pl.w * elem;
 }
 
 bool tb_plan_valid(const TbPlan &pl, int levels, int elem) {
@@ -310,15 +310,10 @@ bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
   if (!tb_equation_supported(c)) return false;
   if (c.eq == kNSE) {
     if (!nse_tb_plan_valid(pl, c.npair, elem)) return false;
-  } else if (pl.w == 126) {
-    // 126 columns: the lane-shared binary32 LCDE window (LDS pitch 128)
-    TbPlan q = pl;
-    q.w = 128;
-    if (!lcde_tb_applies(c, elem) || !tb_plan_valid(q, 2, elem) || !lcde_tb_window_fits(pl))
-      return false;
+  } else if (pl.w == 128 && lane_tb_applies(c, elem)) {
+    // the in-place binary32 LCDE window: one LDS level
+    if (!tb_plan_valid(pl, 1, elem) || !lane_tb_window_fits(pl)) return false;
   } else if (!tb_plan_valid(pl, c.three ? 3 : 2, elem)) {
-    return false;
-  } else if (pl.w == 64 && lcde_tb_applies(c, elem) && !lcde_tb_window_fits(pl)) {
     return false;
   }
   // one conditional wrap per coordinate covers the window
@@ -329,10 +324,8 @@ template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
-    if (lcde_tb_applies(c, 4) && (pl.w == 64 || pl.w == 126))
-      return launch_lcde_tb(c, g, pl, cur, out_cur, st);
+    if (lane_tb_applies(c, 4) && pl.w == 128) return launch_lane_tb(c, g, pl, cur, out_cur, st);
   }
-  if (pl.w == 126) return hipErrorInvalidValue;
   if (c.lattice == 3) return tb_eq<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
   if (c.lattice == 2) return tb_eq<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
   return hipErrorInvalidValue;

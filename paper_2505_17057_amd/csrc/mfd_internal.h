@@ -117,8 +117,7 @@ bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
 struct TbPlan {
   int tb;       // steps per launch
   int h;        // window rows
-  int w = 64;   // window columns: 64 or 128 (one thread per column); 126 for
-                // the lane-shared binary32 LCDE kernel
+  int w = 64;   // window columns: 64 or 128
 };
 size_t tb_lds_bytes(const Consts &c, const TbPlan &pl, int elem);
 // plan limits (depth, window height, LDS) for `levels` LDS levels
@@ -128,11 +127,12 @@ bool tb_equation_supported(const Consts &c);
 // the single-grid blocked kernel can run this plan on this grid
 bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 int tb_window_cols();
-// lane-shared binary32 two-level LCDE step (kernels_lcde_tb.hip): windows of
-// 64 or 126 columns; level t in, level t + tb out
-bool lcde_tb_applies(const Consts &c, int elem);
-bool lcde_tb_window_fits(const TbPlan &pl);
-hipError_t launch_lcde_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
+// lane-shared binary32 two-level steps of the linear CDE and Burgers' equation
+// with beta = 1 (kernels_lane_tb.hip): 128-column windows updated in place;
+// level t in, level t + tb out
+bool lane_tb_applies(const Consts &c, int elem);
+bool lane_tb_window_fits(const TbPlan &pl);
+hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
                           float *out, hipStream_t st);
 // blocked MesoFD step, two-level linear CDE / Burgers (kernels_mesofd_tb.hip):
 // moments of level t in, moments and populations of level t + tb out

@@ -264,17 +264,24 @@ def test_mesofd_autotune_preserves_state(M):
     s.close()
 
 
-@pytest.mark.parametrize("plan", [(4, 40, 126), (8, 48, 126), (2, 20, 126), (16, 40, 126),
-                                  (3, 32, 64), (8, 64, 64), (16, 36, 64)])
+@pytest.mark.parametrize("plan", [(8, 128, 128), (10, 52, 128), (3, 10, 128), (16, 37, 128),
+                                  (6, 99, 128), (12, 112, 128), (2, 20, 128)])
 @pytest.mark.parametrize("lattice", ["D2Q9", "D2Q5"])
-def test_lcde_lane_shared_fp32_equals_unblocked(M, plan, lattice):
-    """The binary32 two-level LCDE window whose lanes share neighbour values
-    (64 or 126 columns) equals the single-step kernel bit for bit, on a grid
-    with ragged tiles in both directions."""
+@pytest.mark.parametrize("eq", ["lcde", "burgers", "burgers-beta"])
+def test_lane_shared_fp32_equals_unblocked(M, plan, lattice, eq):
+    """The binary32 two-level windows whose lanes share neighbour values (128
+    columns updated in place, two per lane: the linear CDE and Burgers with
+    beta = 1; beta != 1 runs the general window) equal the single-step kernel
+    bit for bit, on a grid with ragged tiles in both directions."""
     from parity_util import make_solver
-    K = K2 if lattice == "D2Q9" else [[0.3, 0.0], [0.0, 0.2]]
-    case = dict(BASE, lattice=lattice, K=K, n=(301, 139), a=(1.0, 0.0, 0.0))
-    print("case", lattice, plan, flush=True)
+    if eq == "lcde":
+        K = K2 if lattice == "D2Q9" else [[0.3, 0.0], [0.0, 0.2]]
+        case = dict(BASE, lattice=lattice, K=K, n=(301, 139), a=(1.0, 0.0, 0.0))
+    else:
+        case = dict(lattice=lattice, eq="burgers", n=(301, 139), **_burgers_a(301))
+        if eq == "burgers-beta":
+            case["beta"] = 0.6
+    print("case", eq, lattice, plan, flush=True)
     rng = np.random.default_rng(23)
     cur = rand_state(case, rng).astype(np.float32)
     outs = []
@@ -289,13 +296,16 @@ def test_lcde_lane_shared_fp32_equals_unblocked(M, plan, lattice):
     assert np.array_equal(outs[0], outs[1]), np.abs(outs[0] - outs[1]).max()
 
 
-def test_lane_shared_width_only_for_binary32_lcde(M):
+def test_lane_shared_window_limits(M):
+    """The in-place window holds at most 128 rows; other widths are rejected."""
     from parity_util import make_solver
-    for name, prec in (("2l", "fp64"), ("3l-trt", "fp32"), ("burgers-2l", "fp32")):
-        s = make_solver(M, _case(name, (200, 100)), prec)
+    s = make_solver(M, dict(BASE, n=(300, 200), a=(1.0, 0.0, 0.0)), "fp32")
+    for plan in ((4, 130, 128), (4, 40, 126), (4, 40, 96)):
         with pytest.raises(M.MfdError):
-            s.set_plan(4, 40, 126)
-        s.close()
+            s.set_plan(*plan)
+    s.set_plan(4, 128, 128)
+    assert s.launch_plan() == (4, 128, 128)
+    s.close()
 
 
 def test_autotune_preserves_state(M):
@@ -308,9 +318,9 @@ def test_autotune_preserves_state(M):
     s.step(5)
     before = s.get_state()
     d = s.autotune()
-    assert d in (1, 2, 4, 6, 8, 10, 12)
+    assert d in (1, 2, 4, 6, 8, 10, 12, 14, 16)
     tb, h, w = s.launch_plan()
-    assert tb == d and (h == 0) == (d == 1) and w in ((0,) if d == 1 else (64, 126, 128))
+    assert tb == d and (h == 0) == (d == 1) and w in ((0,) if d == 1 else (64, 128))
     assert np.array_equal(s.get_state(), before)
     s.step(9)
     ref = make_solver(M, case, "fp64")
