@@ -358,7 +358,7 @@ def bench_batched(M, torch, I, stream):
     g32 = lups / (ms32 * 1e-3) / 1e9
     g64 = lups / (ms64 * 1e-3) / 1e9
     return dict(instances=len(insts), lups=lups, graph_launches=st["launches"], tiles=st["tiles"],
-                plan=dict(time_steps_per_launch=plan[0], window_rows=plan[1]),
+                plan=dict(time_steps_per_launch=plan[0], window_rows=plan[1], window_cols=plan[2]),
                 autotune_s=round(tune_s, 3),
                 fp32_graph_ms=round(ms32, 2), fp32_glups=round(g32, 2),
                 fp32_first_run_incl_capture_s=round(first_s, 3),

@@ -271,14 +271,19 @@ int mfd_batch_wait(mfd_batch *b);
 int mfd_batch_stats(const mfd_batch *b, int64_t *launches, int64_t *lups, int64_t *tiles);
 
 /* Launch plan of the groups that can be temporally blocked (two-level linear
- * CDE and Burgers groups; others always take one launch per step):
- * tb_depth = 1 one launch per step, tb_depth > 1 up to tb_depth steps per
- * launch over windows of 64 x window_rows nodes, 0 automatic (the plan chosen
- * by mfd_batch_autotune, else one launch per step).  Any grid size can be
- * blocked in a batch (the window wraps periodically).  MFD_E_ARG for a plan
- * beyond the kernel's limits: depth <= 16, 64 - 2 depth >= 8,
- * window_rows >= 2 depth + 4, two window levels within 160 KiB of LDS. */
-int mfd_batch_set_plan(mfd_batch *b, int32_t tb_depth, int32_t window_rows);
+ * CDE and Burgers groups, NSE groups without an older-level stencil; others
+ * always take one launch per step): tb_depth = 1 one launch per step,
+ * tb_depth > 1 up to tb_depth steps per launch over windows of window_cols x
+ * window_rows nodes, 0 automatic (the plan chosen by mfd_batch_autotune, else
+ * one launch per step).  window_cols: 64 (0 means 64), or 128 for the
+ * lane-shared kernel of binary32 two-level linear CDE and Burgers (beta = 1)
+ * groups (other groups then take the same plan in 64-column windows).  Any
+ * grid size can be blocked in a batch (the window wraps periodically).
+ * MFD_E_ARG for a plan beyond the kernels' limits: depth <= 16,
+ * window_cols - 2 depth >= 8, window_rows >= 2 depth + 4, two window levels
+ * (64 columns) or one (128 columns, window_rows <= 128) within 160 KiB of
+ * LDS. */
+int mfd_batch_set_plan(mfd_batch *b, int32_t tb_depth, int32_t window_rows, int32_t window_cols);
 
 /* Pick the plan of every blockable group by timing each candidate's first
  * launch over all the group's instances (their current states; the spare
@@ -287,8 +292,10 @@ int mfd_batch_set_plan(mfd_batch *b, int32_t tb_depth, int32_t window_rows);
 int mfd_batch_autotune(mfd_batch *b);
 
 /* Plan of group `group` (groups in a fixed order of kind) after the last
- * run or autotune. */
-int mfd_batch_plan(const mfd_batch *b, int32_t group, int32_t *tb_depth, int32_t *window_rows);
+ * run or autotune (window sizes 0 when tb_depth is 1).  Any pointer may be
+ * NULL. */
+int mfd_batch_plan(const mfd_batch *b, int32_t group, int32_t *tb_depth, int32_t *window_rows,
+                   int32_t *window_cols);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -46,6 +46,7 @@ void Batch::free_groups() {
   for (auto &g : groups) {
     if (g.d_inst) (void)hipFree(g.d_inst);
     if (g.d_tile_inst) (void)hipFree(g.d_tile_inst);
+    if (g.d_lane) (void)hipFree(g.d_lane);
   }
   groups.clear();
 }
@@ -63,8 +64,12 @@ bool batch_blockable(const BatchKey &k) {
 
 static int elem_of(const BatchKey &k) { return k.precision == MFD_FP64 ? 8 : 4; }
 
-// a blocked plan the group's kernel can run
+// a blocked plan the group's kernel can run: 64-column windows (the general
+// batched kernels), or 128-column ones (the lane-shared kernel)
 static bool group_plan_valid(const BatchKey &k, const TbPlan &p) {
+  if (p.w == 128)
+    return lane_batch_applies(k) && tb_plan_valid(p, 1, 4) && lane_tb_window_fits(p);
+  if (p.w != 64) return false;
   if (k.eq == kNSE) return nse_tb_plan_valid(p, k.lattice == MFD_D2Q9 ? 4 : 2, elem_of(k));
   return tb_plan_valid(p, 2, elem_of(k));
 }
@@ -74,7 +79,7 @@ static int tile_ty(int eq) { return eq == kNSE ? kBatchTYNse : kBatchTY; }
 // tile shape of a group under its plan
 static void tile_shape(const Group &g, int *tx, int *ty) {
   if (g.plan.tb > 1) {
-    *tx = tb_window_cols() - 2 * g.plan.tb;
+    *tx = g.plan.w - 2 * g.plan.tb;
     *ty = g.plan.h - 2 * g.plan.tb;
   } else {
     *tx = kBatchTX;
@@ -139,6 +144,13 @@ int Batch::build() {
       auto it = tuned.find(g.key);
       if (req.tb > 0) g.plan = req;
       else if (it != tuned.end()) g.plan = it->second;
+      if (g.plan.tb > 1 && g.plan.w == 128) {
+        // the lane-shared kernel needs every instance's constants to suit it;
+        // else the same plan in 64-column windows
+        bool ok = group_plan_valid(g.key, g.plan);
+        for (int i : g.order) ok = ok && lane_tb_applies(entries[i].s->consts, 4);
+        if (!ok) g.plan.w = 64;
+      }
       if (g.plan.tb > 1 && !group_plan_valid(g.key, g.plan)) g.plan = TbPlan{1, 0};
     }
     for (int slot = 0; slot < (int)g.order.size(); ++slot) {
@@ -150,6 +162,11 @@ int Batch::build() {
     const size_t isz = g.key.precision == MFD_FP64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
     g.inst_bytes = isz * g.order.size();
     int rc = hip(hipMalloc(&g.d_inst, g.inst_bytes), "hipMalloc (instances)");
+    if (!rc && lane_batch_applies(g.key)) {
+      g.lane_bytes = lane_inst_bytes(g.key) * g.order.size();
+      rc = hip(hipMalloc(&g.d_lane, g.lane_bytes), "hipMalloc (lane instances)");
+      g.h_lane.resize(g.lane_bytes);
+    }
     if (!rc) rc = make_tables(g);
     if (rc) return rc;
     g.h_inst.resize(g.inst_bytes);
@@ -169,6 +186,7 @@ static int active_tiles(const Group &g, int64_t s) {
 // one blocked launch of a group (its `l`-th) over the first nt tiles
 static hipError_t launch_group_tb_impl(const Group &g, int nt, int64_t l, const TbPlan &p,
                                        hipStream_t stream) {
+  if (p.w == 128) return launch_batch_lane_tb(g.key, g.d_lane, g.d_tile_inst, nt, l, p, stream);
   if (g.key.precision == MFD_FP64) {
     const BatchInst<double> *in = (const BatchInst<double> *)g.d_inst;
     return g.key.eq == kNSE ? launch_batch_nse_tb<double>(g.key, in, g.d_tile_inst, nt, l, p, stream)
@@ -258,6 +276,19 @@ int Batch::upload_instances() {
     int rc = hip(hipMemcpyAsync(g.d_inst, g.h_inst.data(), g.inst_bytes, hipMemcpyHostToDevice, stream),
                  "hipMemcpyAsync (instances)");
     if (rc) return rc;
+    if (g.plan.tb > 1 && g.plan.w == 128) {
+      const size_t isz = lane_inst_bytes(g.key);
+      for (int slot = 0; slot < (int)g.order.size(); ++slot) {
+        Solver *s = entries[g.order[slot]].s;
+        if (!lane_inst_fill(g.key, s->consts, (float *)s->buf[s->ic], (float *)s->buf[s->ip],
+                            (int)s->G.n[0], (int)s->G.n[1], g.tiles_x[slot], g.tile0[slot],
+                            g.steps[slot], g.h_lane.data() + isz * slot))
+          return fail(MFD_E_UNSUPPORTED, "a batched solver does not suit 128-column windows");
+      }
+      rc = hip(hipMemcpyAsync(g.d_lane, g.h_lane.data(), g.lane_bytes, hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync (lane instances)");
+      if (rc) return rc;
+    }
   }
   return MFD_OK;
 }
@@ -390,9 +421,15 @@ int Batch::autotune() {
       off += (int64_t)b;
     }
     std::vector<TbPlan> cands{TbPlan{1, 0}};
+    bool lane_ok = lane_batch_applies(g.key);
+    for (int i : g.order) lane_ok = lane_ok && lane_tb_applies(entries[i].s->consts, 4);
     for (int d : {2, 3, 4, 6, 8})
       for (int h : {32, 48, 64, 96, 128})
         if (group_plan_valid(g.key, TbPlan{d, h})) cands.push_back(TbPlan{d, h});
+    if (lane_ok)
+      for (int d : {4, 6, 8, 10, 12})
+        for (int h : {48, 64, 80, 96, 112, 128})
+          if (group_plan_valid(g.key, TbPlan{d, h, 128})) cands.push_back(TbPlan{d, h, 128});
     float best = 1e30f;
     TbPlan best_p{1, 0};
     for (const TbPlan &p : cands) {
@@ -532,15 +569,21 @@ extern "C" int mfd_batch_wait(mfd_batch *h) {
   return b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
 }
 
-extern "C" int mfd_batch_set_plan(mfd_batch *h, int32_t tb_depth, int32_t window_rows) {
+extern "C" int mfd_batch_set_plan(mfd_batch *h, int32_t tb_depth, int32_t window_rows,
+                                  int32_t window_cols) {
   if (!h) return MFD_E_ARG;
   Batch *b = reinterpret_cast<Batch *>(h);
   if (tb_depth < 0) return b->fail(MFD_E_ARG, "negative depth");
-  if (tb_depth > 1 && !tb_plan_valid(TbPlan{tb_depth, window_rows}, 2, 8) &&
-      !tb_plan_valid(TbPlan{tb_depth, window_rows}, 2, 4))
-    return b->fail(MFD_E_ARG, "plan (%d, %d) exceeds the blocked kernel's limits", tb_depth,
-                   window_rows);
-  b->req = TbPlan{tb_depth, tb_depth > 1 ? window_rows : 0};
+  if (window_cols == 0) window_cols = 64;
+  if (window_cols != 64 && window_cols != 128)
+    return b->fail(MFD_E_ARG, "window columns must be 64 or 128");
+  const TbPlan p{tb_depth, window_rows, window_cols};
+  if (tb_depth > 1 &&
+      (window_cols == 128 ? !(tb_plan_valid(p, 1, 4) && lane_tb_window_fits(p))
+                          : !tb_plan_valid(p, 2, 8) && !tb_plan_valid(p, 2, 4)))
+    return b->fail(MFD_E_ARG, "plan (%d, %d, %d) exceeds the blocked kernels' limits", tb_depth,
+                   window_rows, window_cols);
+  b->req = tb_depth > 1 ? p : TbPlan{tb_depth, 0};
   b->dirty = true;
   return MFD_OK;
 }
@@ -551,12 +594,14 @@ extern "C" int mfd_batch_autotune(mfd_batch *h) {
 }
 
 extern "C" int mfd_batch_plan(const mfd_batch *h, int32_t group, int32_t *tb_depth,
-                              int32_t *window_rows) {
+                              int32_t *window_rows, int32_t *window_cols) {
   if (!h) return MFD_E_ARG;
   const Batch *b = reinterpret_cast<const Batch *>(h);
   if (group < 0 || group >= (int32_t)b->groups.size()) return MFD_E_ARG;
-  if (tb_depth) *tb_depth = b->groups[group].plan.tb;
-  if (window_rows) *window_rows = b->groups[group].plan.h;
+  const TbPlan &p = b->groups[group].plan;
+  if (tb_depth) *tb_depth = p.tb;
+  if (window_rows) *window_rows = p.tb > 1 ? p.h : 0;
+  if (window_cols) *window_cols = p.tb > 1 ? p.w : 0;
   return MFD_OK;
 }
 

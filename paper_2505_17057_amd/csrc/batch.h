@@ -31,6 +31,9 @@ struct Group {
   int *d_tile_inst = nullptr;   // instance slot of every tile (capacity tile_cap)
   size_t inst_bytes = 0;
   std::vector<unsigned char> h_inst;
+  void *d_lane = nullptr;       // instance table of the lane-shared kernel (128-column plans)
+  size_t lane_bytes = 0;
+  std::vector<unsigned char> h_lane;
 };
 
 // group kind of a solver, and whether such groups can be temporally blocked

@@ -48,4 +48,15 @@ template <typename T>
 hipError_t launch_batch_nse_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                                int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
 
+// lane-shared batched launch (kernels_lane_tb.hip): binary32 two-level LCDE and
+// Burgers (beta = 1) groups under 128-column plans, with an instance table of
+// their own (lane_inst_bytes per instance, filled by lane_inst_fill; false:
+// this solver's constants do not suit the kernel)
+bool lane_batch_applies(const BatchKey &k);
+size_t lane_inst_bytes(const BatchKey &k);
+bool lane_inst_fill(const BatchKey &k, const Consts &c, float *cur, float *other, int nx, int ny,
+                    int tiles_x, int tile0, int64_t nsteps, void *dst);
+hipError_t launch_batch_lane_tb(const BatchKey &k, const void *inst, const int *tile_inst,
+                                int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
+
 }  // namespace mfd

@@ -17,11 +17,14 @@
 //
 // Burgers' equation (Eq. (2-2-1) with the EDF of Eq. (3-4)): each node forms
 // its pair parts F+-_p once and shares them the same way (see BurgSeg).
+#include <cstring>
 #include <map>
 #include <type_traits>
 #include <mutex>
 #include <tuple>
 
+#include "../../include/mfd.h"
+#include "batch_kernels.h"
 #include "mfd_internal.h"
 
 namespace mfd {
@@ -262,34 +265,123 @@ struct BurgSeg {
   template <class Emit>
   __device__ __forceinline__ void operator()(const float2 *lds, int lane, int ya, int yb,
                                              float2 top, float2 bot, const Emit &emit) const {
+    // three rows per pass: the pair parts of rows y - 1, y (pa, pb) and the
+    // incoming row rotate through three register sets, so that none is copied
     float2 rc = lds[ya * 64 + lane];
-    PP pp = parts(top), pc = parts(rc);
+    PP pa = parts(top), pb = parts(rc);
     int y = ya;
-    for (; y + 2 < yb; y += 2) {
+    for (; y + 3 < yb; y += 3) {
       const float2 r1 = lds[(y + 1) * 64 + lane];
       const float2 r2 = lds[(y + 2) * 64 + lane];
+      const float2 r3 = lds[(y + 3) * 64 + lane];
       const PP p1 = parts(r1);
-      const float2 o1 = node(rc, pc, p1, pp);
+      const float2 o1 = node(rc, pb, p1, pa);
       const PP p2 = parts(r2);
-      const float2 o2 = node(r1, p1, p2, pc);
+      const float2 o2 = node(r1, p1, p2, pb);
+      const PP p3 = parts(r3);
+      const float2 o3 = node(r2, p2, p3, p1);
       emit(y, o1);
       emit(y + 1, o2);
-      rc = r2;
-      pp = p1;
-      pc = p2;
+      emit(y + 2, o3);
+      rc = r3;
+      pa = p2;
+      pb = p3;
     }
-    if (y + 1 < yb) {
-      const float2 r1 = lds[(y + 1) * 64 + lane];
-      const PP p1 = parts(r1);
-      const float2 o1 = node(rc, pc, p1, pp);
-      const float2 o2 = node(r1, p1, parts(bot), pc);
-      emit(y, o1);
-      emit(y + 1, o2);
-    } else {
-      emit(y, node(rc, pc, parts(bot), pp));
+    // the last one to three rows; the row below the segment is `bot`
+    const int left = yb - y;
+    const float2 r1 = left > 1 ? lds[(y + 1) * 64 + lane] : bot;
+    const PP p1 = parts(r1);
+    emit(y, node(rc, pb, p1, pa));
+    if (left > 1) {
+      const float2 r2 = left > 2 ? lds[(y + 2) * 64 + lane] : bot;
+      const PP p2 = parts(r2);
+      emit(y + 1, node(r1, p1, p2, pb));
+      if (left > 2) emit(y + 2, node(r2, p2, parts(bot), p1));
     }
   }
 };
+
+// The steps of one window: TBS steps (TBS <= TBW) of the window in LDS whose
+// origin is (x0, y0); the last one writes the tile, the interior that starts
+// TBW nodes in, to `out` (an nx x ny grid).  Every wavefront of the
+// workgroup calls it; it ends with a barrier.
+template <class Seg, int RG>
+__device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int H, int TBS,
+                                             int TBW, int x0, int y0, int nx, int ny,
+                                             float *__restrict__ out, const Seg &seg_run) {
+  constexpr int W = 128;
+  // this lane's columns inside the tile (last step's stores)
+  const int c0 = 2 * lane;
+  const bool se = c0 >= TBW && c0 < W - TBW && x0 + c0 < nx;
+  const bool so = c0 + 1 >= TBW && c0 + 1 < W - TBW && x0 + c0 + 1 < nx;
+#pragma unroll 1
+  for (int t = 1; t <= TBS; ++t) {
+    const int Hr = H - 2 * t;
+    const int seg = (Hr + RG - 1) / RG;
+    const int ya = t + rg * seg, yb = min(ya + seg, H - t);
+    const bool act = ya < yb;  // uniform across the wavefront
+    float2 top = make_float2(0.f, 0.f), bot = top;
+    if (act) {
+      top = lds[(ya - 1) * 64 + lane];
+      bot = lds[yb * 64 + lane];
+    }
+    lds_barrier();
+    if (act) {
+      if (t < TBS) {
+        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) { lds[y * 64 + lane] = o; });
+      } else {
+        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) {
+          const int gy = y0 + y;
+          if (y >= TBW && y < H - TBW && gy < ny) {
+            float *row = out + (int64_t)gy * nx + x0 + c0;
+            if (se) row[0] = o.x;
+            if (so) row[1] = o.y;
+          }
+        });
+      }
+    }
+    lds_barrier();
+  }
+}
+
+// The W x H window of an nx x ny grid whose origin is (x0, y0): rows rg,
+// rg + RG, ... (NPF / 2 of them) of this lane's two columns, into registers.
+// ANY: modular wrap (grids smaller than the window); else one conditional
+// wrap (nx >= W, ny >= H).
+template <int RG, int NPF, bool ANY>
+__device__ __forceinline__ void window_fetch(const float *__restrict__ cur, int nx, int ny, int H,
+                                             int x0, int y0, int lane, int rg, float (&pf)[NPF]) {
+  auto wrap = [&](int i, int n) {
+    if constexpr (ANY) {
+      i %= n;
+      return i < 0 ? i + n : i;
+    } else {
+      return i < 0 ? i + n : (i >= n ? i - n : i);
+    }
+  };
+  const int ge = wrap(x0 + 2 * lane, nx), go = wrap(x0 + 2 * lane + 1, nx);
+  // byte offsets within a row (a row is far below 4 GiB): each load is a row
+  // base in scalar registers plus one of these two offsets
+  const uint32_t be = (uint32_t)ge * 4u, bo = (uint32_t)go * 4u;
+#pragma unroll
+  for (int j = 0; j < NPF / 2; ++j) {
+    const int r = min(rg + RG * j, H - 1);
+    const int y = wrap(y0 + r, ny);
+    const char *row = reinterpret_cast<const char *>(cur + (int64_t)y * nx);
+    pf[2 * j] = *reinterpret_cast<const float *>(row + be);
+    pf[2 * j + 1] = *reinterpret_cast<const float *>(row + bo);
+  }
+}
+
+template <int RG, int NPF>
+__device__ __forceinline__ void window_put(float2 *lds, int H, int lane, int rg,
+                                           const float (&pf)[NPF]) {
+#pragma unroll
+  for (int j = 0; j < NPF / 2; ++j) {
+    const int r = rg + RG * j;
+    if (r < H) lds[r * 64 + lane] = make_float2(pf[2 * j], pf[2 * j + 1]);
+  }
+}
 
 // One kernel for every lane-shared segment type Seg; RG wavefronts of row
 // segments; NPF prefetch values per thread (NPF / 2 rows of the next window).
@@ -298,7 +390,7 @@ __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ c
                                                     float *__restrict__ out, int nx, int ny, int H,
                                                     int TB, int tiles_x, int ntiles,
                                                     typename Seg::Params kc) {
-  constexpr int W = 128, ROWS = NPF / 2;
+  constexpr int W = 128;
   extern __shared__ unsigned char smem_lane[];
   float2 *lds = reinterpret_cast<float2 *>(smem_lane);  // [H][64]
   const int TX = W - 2 * TB, TY = H - 2 * TB;
@@ -308,40 +400,15 @@ __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ c
   const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Seg seg_run(kc);
 
-  // window rows rg, rg + RG, ... of the tile whose origin is (x0, y0)
   float pf[NPF];
-  auto fetch = [&](int x0, int y0) {
-    int ge = x0 + 2 * lane, go = ge + 1;
-    ge = ge < 0 ? ge + nx : (ge >= nx ? ge - nx : ge);
-    go = go < 0 ? go + nx : (go >= nx ? go - nx : go);
-    // byte offsets within a row (a row is far below 4 GiB): each load is a
-    // row base in scalar registers plus one of these two offsets
-    const uint32_t be = (uint32_t)ge * 4u, bo = (uint32_t)go * 4u;
-#pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-      const int r = min(rg + RG * j, H - 1);
-      int y = y0 + r;
-      y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-      const char *row = reinterpret_cast<const char *>(cur + (int64_t)y * nx);
-      pf[2 * j] = *reinterpret_cast<const float *>(row + be);
-      pf[2 * j + 1] = *reinterpret_cast<const float *>(row + bo);
-    }
-  };
-  auto put = [&]() {
-#pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-      const int r = rg + RG * j;
-      if (r < H) lds[r * 64 + lane] = make_float2(pf[2 * j], pf[2 * j + 1]);
-    }
-  };
-
   int v = blockIdx.x;
   int tile = xcd_remap_l(v, ntiles);
   int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
-  fetch(x0, y0);
-  put();
+  window_fetch<RG, NPF, false>(cur, nx, ny, H, x0, y0, lane, rg, pf);
+  window_put<RG, NPF>(lds, H, lane, rg, pf);
   lds_barrier();
   while (true) {
+    // the next tile of this workgroup, its window in flight during the steps
     const int vn = v + G;
     const bool more = vn < ntiles;
     int xn = 0, yn = 0;
@@ -349,46 +416,87 @@ __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ c
       const int tn = xcd_remap_l(vn, ntiles);
       xn = (tn % tiles_x) * TX - TB;
       yn = (tn / tiles_x) * TY - TB;
-      fetch(xn, yn);
+      window_fetch<RG, NPF, false>(cur, nx, ny, H, xn, yn, lane, rg, pf);
     }
-    // this lane's columns inside the tile's interior (last step's stores)
-    const int c0 = 2 * lane;
-    const bool se = c0 >= TB && c0 < W - TB && x0 + c0 < nx;
-    const bool so = c0 + 1 >= TB && c0 + 1 < W - TB && x0 + c0 + 1 < nx;
-#pragma unroll 1
-    for (int t = 1; t <= TB; ++t) {
-      const int Hr = H - 2 * t;
-      const int seg = (Hr + RG - 1) / RG;
-      const int ya = t + rg * seg, yb = min(ya + seg, H - t);
-      const bool act = ya < yb;  // uniform across the wavefront
-      float2 top = make_float2(0.f, 0.f), bot = top;
-      if (act) {
-        top = lds[(ya - 1) * 64 + lane];
-        bot = lds[yb * 64 + lane];
-      }
-      lds_barrier();
-      if (act) {
-        if (t < TB) {
-          seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) { lds[y * 64 + lane] = o; });
-        } else {
-          seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) {
-            const int gy = y0 + y;
-            if (gy < ny) {
-              float *row = out + (int64_t)gy * nx + x0 + c0;
-              if (se) row[0] = o.x;
-              if (so) row[1] = o.y;
-            }
-          });
-        }
-      }
-      lds_barrier();
-    }
+    window_steps<Seg, RG>(lds, lane, rg, H, TB, TB, x0, y0, nx, ny, out, seg_run);
     if (!more) break;
-    put();
+    window_put<RG, NPF>(lds, H, lane, rg, pf);
     lds_barrier();
     v = vn;
     x0 = xn;
     y0 = yn;
+  }
+}
+
+// One instance of a batch group run by the lane-shared window: its two
+// level buffers (launch l reads ring[(c0 + l) & 1]), size, tiles and steps.
+template <class Prm>
+struct LaneInst {
+  float *ring[2];
+  int nx, ny, tiles_x, tile0;
+  int64_t nsteps, c0;
+  Prm prm;
+};
+
+// Batched launch `launch` of a run whose launches advance up to TB steps: the
+// tiles of the instances with steps left are the prefix [0, ntiles) of the
+// table; each advances min(TB, its remaining steps) in a window sized for
+// TB.  Persistent workgroups as in k_lane_tb; grids of any size (modular
+// wrap).
+template <class Seg, int RG, int NPF>
+__global__ __launch_bounds__(64 * RG) void k_batch_lane_tb(
+    const LaneInst<typename Seg::Params> *__restrict__ inst, const int *__restrict__ tile_inst,
+    int ntiles, int64_t launch, int H, int TB) {
+  constexpr int W = 128;
+  extern __shared__ unsigned char smem_blane[];
+  float2 *lds = reinterpret_cast<float2 *>(smem_blane);  // [H][64]
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int G = gridDim.x;
+  if ((int)blockIdx.x >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+  struct Where {
+    int i, x0, y0;
+  };
+  auto locate = [&](int v) {
+    const int t = xcd_remap_l(v, ntiles);
+    Where w;
+    w.i = tile_inst[t];
+    const int lt = t - inst[w.i].tile0, tx = inst[w.i].tiles_x;
+    w.x0 = (lt % tx) * TX - TB;
+    w.y0 = (lt / tx) * TY - TB;
+    return w;
+  };
+  auto cur_of = [&](int i) { return inst[i].ring[(inst[i].c0 + launch) & 1]; };
+
+  float pf[NPF];
+  int v = blockIdx.x;
+  Where w = locate(v);
+  window_fetch<RG, NPF, true>(cur_of(w.i), inst[w.i].nx, inst[w.i].ny, H, w.x0, w.y0, lane, rg,
+                              pf);
+  window_put<RG, NPF>(lds, H, lane, rg, pf);
+  lds_barrier();
+  while (true) {
+    const int vn = v + G;
+    const bool more = vn < ntiles;
+    Where wn{0, 0, 0};
+    if (more) {
+      wn = locate(vn);
+      window_fetch<RG, NPF, true>(cur_of(wn.i), inst[wn.i].nx, inst[wn.i].ny, H, wn.x0, wn.y0,
+                                  lane, rg, pf);
+    }
+    const LaneInst<typename Seg::Params> &I = inst[w.i];
+    const int64_t left = I.nsteps - launch * TB;
+    const int TBS = left < TB ? (int)left : TB;
+    const Seg seg_run(I.prm);
+    window_steps<Seg, RG>(lds, lane, rg, H, TBS, TB, w.x0, w.y0, I.nx, I.ny,
+                          I.ring[(I.c0 + launch + 1) & 1], seg_run);
+    if (!more) break;
+    window_put<RG, NPF>(lds, H, lane, rg, pf);
+    lds_barrier();
+    v = vn;
+    w = wn;
   }
 }
 
@@ -461,32 +569,93 @@ hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *ou
   return hipGetLastError();
 }
 
-template <int P>
-hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur, float *out,
-                   hipStream_t st) {
-  const KC<float> k = make_kc<float>(c);
-  if (c.eq == kLCDE) {
-    LinC lc{};
-    for (int p = 0; p < P; ++p) {
-      lc.ap[p] = k.Ap[p];
-      lc.nam[p] = -k.Am[p];
-    }
-    lc.a0 = k.A0t;
-    return lane_cfg<LinSeg<P>>(g, pl, cur, out, lc, st);
+LinC lin_params(const KC<float> &k, int npair) {
+  LinC lc{};
+  for (int p = 0; p < npair; ++p) {
+    lc.ap[p] = k.Ap[p];
+    lc.nam[p] = -k.Am[p];
   }
-  if (!burgers_weights_symmetric(k, c.lattice)) return hipErrorInvalidValue;
+  lc.a0 = k.A0t;
+  return lc;
+}
+
+BurgC burg_params(const KC<float> &k, int npair) {
   BurgC bc{};
   bc.wa = k.w[1];
-  bc.wd = P == 4 ? k.w[5] : 0.0f;
+  bc.wd = npair == 4 ? k.w[5] : 0.0f;
   bc.w1a = k.w1[1];
-  bc.w1d = P == 4 ? k.w1[5] : 0.0f;
+  bc.w1d = npair == 4 ? k.w1[5] : 0.0f;
   bc.bh = k.bh;
   bc.cpl = k.ap;
   bc.cmi = k.am;
   bc.a0 = k.A0t;
-  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, bc, st);
+  return bc;
+}
+
+template <int P>
+hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur, float *out,
+                   hipStream_t st) {
+  const KC<float> k = make_kc<float>(c);
+  if (c.eq == kLCDE) return lane_cfg<LinSeg<P>>(g, pl, cur, out, lin_params(k, P), st);
+  if (!burgers_weights_symmetric(k, c.lattice)) return hipErrorInvalidValue;
+  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, burg_params(k, P), st);
+}
+
+template <class Seg>
+hipError_t batch_lane_cfg(const void *inst, const int *tile_inst, int ntiles, int64_t launch,
+                          const TbPlan &pl, hipStream_t st) {
+  constexpr int RG = Seg::kRG, NPF = Seg::kNPF, W = 128;
+  if (pl.h > RG * NPF / 2) return hipErrorInvalidValue;
+  const size_t lds = (size_t)pl.h * W * sizeof(float);
+  auto fn = k_batch_lane_tb<Seg, RG, NPF>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  int grid = lane_slots((const void *)fn, 64 * RG, lds);
+  if (grid <= 0) return hipErrorInvalidValue;
+  grid = grid < ntiles ? grid : ntiles;
+  if (grid >= 8) grid &= ~7;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st,
+                     (const LaneInst<typename Seg::Params> *)inst, tile_inst, ntiles, launch, pl.h,
+                     pl.tb);
+  return hipGetLastError();
 }
 }  // namespace
+
+bool lane_batch_applies(const BatchKey &k) {
+  return k.precision == MFD_FP32 && !k.three && (k.lattice == MFD_D2Q5 || k.lattice == MFD_D2Q9) &&
+         (k.eq == kLCDE || (k.eq == kBurgers && k.b1));
+}
+
+size_t lane_inst_bytes(const BatchKey &k) {
+  return k.eq == kLCDE ? sizeof(LaneInst<LinC>) : sizeof(LaneInst<BurgC>);
+}
+
+bool lane_inst_fill(const BatchKey &k, const Consts &c, float *cur, float *other, int nx, int ny,
+                    int tiles_x, int tile0, int64_t nsteps, void *dst) {
+  if (!lane_tb_applies(c, 4)) return false;
+  const KC<float> kc = make_kc<float>(c);
+  const int np = c.npair;
+  if (k.eq == kLCDE) {
+    LaneInst<LinC> li{{cur, other}, nx, ny, tiles_x, tile0, nsteps, 0, lin_params(kc, np)};
+    std::memcpy(dst, &li, sizeof(li));
+  } else {
+    LaneInst<BurgC> li{{cur, other}, nx, ny, tiles_x, tile0, nsteps, 0, burg_params(kc, np)};
+    std::memcpy(dst, &li, sizeof(li));
+  }
+  return true;
+}
+
+hipError_t launch_batch_lane_tb(const BatchKey &k, const void *inst, const int *tile_inst,
+                                int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st) {
+  if (!lane_batch_applies(k) || pl.w != 128) return hipErrorInvalidValue;
+  if (k.lattice == MFD_D2Q9) {
+    if (k.eq == kLCDE) return batch_lane_cfg<LinSeg<4>>(inst, tile_inst, ntiles, launch, pl, st);
+    return batch_lane_cfg<BurgSeg<4>>(inst, tile_inst, ntiles, launch, pl, st);
+  }
+  if (k.eq == kLCDE) return batch_lane_cfg<LinSeg<2>>(inst, tile_inst, ntiles, launch, pl, st);
+  return batch_lane_cfg<BurgSeg<2>>(inst, tile_inst, ntiles, launch, pl, st);
+}
 
 hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
                           float *out, hipStream_t st) {

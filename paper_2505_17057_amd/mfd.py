@@ -115,9 +115,10 @@ _SIGS = {
     "mfd_batch_run": ([_H], C.c_int),
     "mfd_batch_wait": ([_H], C.c_int),
     "mfd_batch_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
-    "mfd_batch_set_plan": ([_H, C.c_int32, C.c_int32], C.c_int),
+    "mfd_batch_set_plan": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "mfd_batch_autotune": ([_H], C.c_int),
-    "mfd_batch_plan": ([_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "mfd_batch_plan": ([_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                        C.POINTER(C.c_int32)], C.c_int),
     "mfd_server_create": ([C.POINTER(_H), C.c_int64, C.c_int32, C.c_int64], C.c_int),
     "mfd_server_submit": ([_H, C.POINTER(mfd_request), C.POINTER(C.c_int64)], C.c_int),
     "mfd_server_poll": ([_H, C.c_int64, C.POINTER(C.c_int32), _PD], C.c_int),
@@ -369,16 +370,18 @@ class Batch:
         self.check(lib.mfd_batch_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "mfd_batch_stats")
         return dict(launches=a.value, lups=b.value, tiles=c.value)
 
-    def set_plan(self, tb_depth, window_rows=0):
-        return self.check(lib.mfd_batch_set_plan(self.h, int(tb_depth), int(window_rows)), "mfd_batch_set_plan")
+    def set_plan(self, tb_depth, window_rows=0, window_cols=0):
+        return self.check(lib.mfd_batch_set_plan(self.h, int(tb_depth), int(window_rows), int(window_cols)),
+                          "mfd_batch_set_plan")
 
     def autotune(self):
         return self.check(lib.mfd_batch_autotune(self.h), "mfd_batch_autotune")
 
     def plan(self, group=0):
-        tb, h = C.c_int32(), C.c_int32()
-        self.check(lib.mfd_batch_plan(self.h, int(group), C.byref(tb), C.byref(h)), "mfd_batch_plan")
-        return tb.value, h.value
+        tb, h, w = C.c_int32(), C.c_int32(), C.c_int32()
+        self.check(lib.mfd_batch_plan(self.h, int(group), C.byref(tb), C.byref(h), C.byref(w)),
+                   "mfd_batch_plan")
+        return tb.value, h.value, w.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -210,6 +210,88 @@ def test_batch_blocked_fp64_matches_oracle(M, plan):
         s.close()
 
 
+def _lane_cases():
+    """Burgers (beta = 1) and LCDE grids from smaller than the 128-column
+    window to several windows wide, ragged step counts."""
+    cases = batch_cases()[:10]
+    rng = np.random.default_rng(46)
+    for i, n in enumerate([(300, 140), (129, 200), (64, 64), (257, 33)]):
+        dx = 1.0 / n[0]
+        nu = float(rng.uniform(1e-3, 1e-2))
+        dt = 0.5 * min(0.3 * dx * dx / nu, nu / 0.01)
+        sp = 2 * nu * dt / ((1.0 / 3.0) * dx * dx)
+        cases.append(dict(name="burgers-w%d" % i, lattice="D2Q9", eq="burgers", n=n, dx=dx, dt=dt,
+                          a=((sp + 1) / 2, 1 - sp, (sp - 1) / 2), steps=int(rng.integers(20, 41))))
+    cases.append(dict(name="lcde-w", lattice="D2Q9", eq="lcde", n=(260, 150), u=(0.1, -0.07),
+                      K=[[0.3, 0.04], [0.04, 0.2]], lambda_bar=1, a=(1.0, 0.0, 0.0), steps=29))
+    cases.append(dict(name="lcde-d2q5", lattice="D2Q5", eq="lcde", n=(150, 99), u=(0.1, -0.07),
+                      K=[[0.3, 0.0], [0.0, 0.2]], lambda_bar=1, a=(1.0, 0.0, 0.0), steps=17))
+    return cases
+
+
+@pytest.mark.parametrize("plan", [(4, 48, 128), (8, 64, 128), (12, 112, 128), (2, 16, 128),
+                                  (16, 128, 128)])
+def test_batch_lane_fp32_equals_solo(M, plan):
+    """Batched 128-column lane-shared windows (persistent workgroups over the
+    tile table, modular wrap for grids narrower than the window) give every
+    Burgers and LCDE instance the result of stepping it alone, bit for bit,
+    across two runs (graph replay)."""
+    print("plan", plan, flush=True)
+    cases = _lane_cases()
+    states = _states(cases, seed=13)
+    solo = []
+    for c, (cur, _) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_blocking(1)
+        s.set_state(cur.astype(np.float32))
+        s.step(2 * c["steps"])
+        solo.append(s.get_state())
+        s.close()
+    b = M.Batch(use_graph=True)
+    b.set_plan(*plan)
+    solvers = []
+    for c, (cur, _) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_state(cur.astype(np.float32))
+        b.add(s, c["steps"])
+        solvers.append(s)
+    for _ in range(2):
+        b.run()
+        b.wait()
+    for g in range(2):  # the Burgers and the D2Q9 LCDE groups use the lane kernel
+        assert b.plan(g) == plan, (g, b.plan(g))
+    for c, s, want in zip(cases, solvers, solo):
+        assert np.array_equal(s.get_state(), want), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_lane_plan_falls_back_for_fp64(M):
+    """A 128-column plan asked of binary64 groups runs them in 64-column
+    windows; results equal the oracle."""
+    cases = _lane_cases()[:3]
+    states = _states(cases, seed=14)
+    b = M.Batch()
+    b.set_plan(4, 48, 128)
+    solvers = []
+    for c, (cur, _) in zip(cases, states):
+        s = make_solver(M, c, "fp64")
+        s.set_state(cur)
+        b.add(s, c["steps"])
+        solvers.append(s)
+    b.run()
+    b.wait()
+    assert b.plan(0) == (4, 48, 64)
+    for c, (cur, prev), s in zip(cases, states, solvers):
+        assert np.array_equal(s.get_state(), run_oracle(c, cur, prev, c["steps"])), c["name"]
+    b.close()
+    for s in solvers:
+        s.close()
+    with pytest.raises(M.MfdError):
+        M.Batch().set_plan(4, 48, 96)
+
+
 def test_batch_autotune_fp32_equals_solo(M):
     """The batch autotuner leaves every state as it was, and the run under the
     plan it picks equals each instance stepped alone, bit for bit."""
