@@ -251,6 +251,8 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty), dim3(256),
                        0, st, cur, prev, out, nx, ny, tx, tx * ty, kc);
+  } else if constexpr (L::D == 3 && EQ == kNSE && !THREE_ST) {
+    return launch_nse3d_pp<T>(c, g, cur, prev, out, st);
   } else {
     constexpr int TX = 32, TY = (THREE_ST && sizeof(T) == 8) ? 4 : 8;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;

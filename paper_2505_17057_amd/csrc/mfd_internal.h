@@ -101,6 +101,12 @@ template <typename T>
 hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
                             int tb_depth, hipStream_t st);
 
+// one NSE step on D3Q19 without an older-level stencil, pair parts staged
+// once per node (kernels_nse3d.hip)
+template <typename T>
+hipError_t launch_nse3d_pp(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                           hipStream_t st);
+
 // LDS-resident 1D run: nsteps steps inside one workgroup; ring buffers
 // a (level t) / b (level t - dt) are updated in place; returns the index of
 // the buffer holding the final level among {a, b, c}.
