@@ -110,11 +110,13 @@ def stored_traffic(kernel_src, tb, h, w):
         return None, None
     info = json.load(open(path))
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if (info.get("kernel_source_sha256") != sha or info.get("time_steps_per_launch") != tb
-            or info.get("window_cols") != w):
+    if info.get("kernel_source_sha256") != sha:
         return None, None
-    plan = [info.get("time_steps_per_launch"), info.get("window_rows"), info.get("window_cols")]
-    return info.get("hbm_bytes_per_launch"), plan
+    for r in [info] + info.get("alternates", []):
+        if r.get("time_steps_per_launch") == tb and r.get("window_cols") == w:
+            plan = [r.get("time_steps_per_launch"), r.get("window_rows"), r.get("window_cols")]
+            return r.get("hbm_bytes_per_launch"), plan
+    return None, None
 
 
 def cpu_baseline(cfg, budget_s=15.0):

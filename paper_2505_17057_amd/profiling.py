@@ -126,6 +126,8 @@ def main(argv=None):
     p.add_argument("--out-md", required=True)
     p.add_argument("--out-json", required=True)
     p.add_argument("--command", action="append", default=[], help="command that produced an input")
+    p.add_argument("--alt", action="append", default=[],
+                   help="TB,H,W:FETCH_DB:WRITE_DB, counter runs of another launch plan of the kernel")
     a = p.parse_args(argv)
     here = os.getcwd() + os.sep
     a.command = a.command + ["python -m paper_2505_17057_amd.profiling " +
@@ -153,6 +155,20 @@ def main(argv=None):
                hbm_bytes_per_launch=round(traffic), algorithmic_bytes_per_launch=a.algorithmic_bytes,
                one_pass_bytes=a.pass_bytes,
                commands=a.command)
+    # other plans the autotuner may pick: their counters, scaled the same way
+    alts = []
+    for spec in a.alt:
+        plan, fdb, wdb = spec.split(":")
+        atb, ah, aw = (int(v) for v in plan.split(","))
+        fg = counter_by_grid(fdb, "FETCH_SIZE", a.kernel)
+        wg = counter_by_grid(wdb, "WRITE_SIZE", a.kernel)
+        g = max(fg, key=lambda k: len(fg[k]))
+        afk, awk = fg[g], wg[g]
+        ab = statistics.fmean(afk) * 1024.0 * ff + statistics.fmean(awk) * 1024.0 * wf
+        alts.append(dict(time_steps_per_launch=atb, window_rows=ah, window_cols=aw,
+                         hbm_bytes_per_launch=round(ab), fetch_kib_raw=statistics.fmean(afk),
+                         write_kib_raw=statistics.fmean(awk), dispatches=len(afk)))
+    rec["alternates"] = alts
     with open(a.out_json, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -189,6 +205,16 @@ def main(argv=None):
              "over the stored fields (%.0f B) and %.3f x the algorithmic bytes of the launch's time steps "
              "(%.0f B)." % (fetch_b, write_b, traffic, traffic / a.pass_bytes, a.pass_bytes,
                             traffic / a.algorithmic_bytes, a.algorithmic_bytes))
+    if alts:
+        L.append("")
+        L.append("Other launch plans of the same kernel (the same counters and factors):\n")
+        L.append("| plan (TB, rows, cols) | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch | x one pass |")
+        L.append("|---|---|---|---|---|")
+        for r in alts:
+            L.append("| %d, %d, %d | %.1f | %.1f | %d | %.3f |" % (
+                r["time_steps_per_launch"], r["window_rows"], r["window_cols"], r["fetch_kib_raw"],
+                r["write_kib_raw"], r["hbm_bytes_per_launch"], r["hbm_bytes_per_launch"] / a.pass_bytes))
+        L.append("")
     L.append("Kernel source SHA-256: `%s` (%s)." % (sha, a.kernel_source))
     with open(a.out_md, "w") as f:
         f.write("\n".join(L) + "\n")
