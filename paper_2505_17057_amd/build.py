@@ -30,6 +30,7 @@ SOURCES = [
     "kernels_nse_tb.hip",
     "kernels_lane_tb.hip",
     "kernels_nse3d.hip",
+    "kernels_1d_wave.hip",
     "kernels_mesofd_tb.hip",
     "kernels_mesofd.hip",
     "kernels_misc.hip",

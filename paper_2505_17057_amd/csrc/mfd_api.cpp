@@ -104,6 +104,16 @@ template <typename T>
 int Solver::step_t(int64_t nsteps) {
   T *B[kNumBuf];
   for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  if (cfg.kind != MFD_THETA && wave1d_applies(consts, G) && nsteps > 1) {
+    // the whole run in one wavefront's registers; levels stay in place
+    const bool meso = grid.form == MFD_MESOFD;
+    hipError_t e = launch_1d_wave<T>(consts, G, meso, B[ic], B[ip], meso ? B[pc] : nullptr,
+                                     nsteps, stream);
+    if (e != hipSuccess) return hip(e, "1d wavefront launch");
+    steps_done += nsteps;
+    prev_gap = 1;
+    return MFD_OK;
+  }
   if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && mmfd_1d_resident_fits(consts, G, sizeof(T)) &&
       nsteps > 1) {
     // ga = level t, gb = level t - dt; afterwards the same roles

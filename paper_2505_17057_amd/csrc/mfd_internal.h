@@ -114,6 +114,14 @@ template <typename T>
 hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T *cbuf,
                                    int64_t nsteps, hipStream_t st);
 bool mmfd_1d_resident_fits(const Consts &c, const Grid &g, int elem_bytes);
+// whole run of a small periodic 1D two-level LCDE grid (64, 128, 256, 512 or
+// 1024 nodes) in the registers of one workgroup (kernels_1d_wave.hip); levels
+// stay in place (ga: last level, gb: the one before), MesoFD populations to
+// pop
+bool wave1d_applies(const Consts &c, const Grid &g);
+template <typename T>
+hipError_t launch_1d_wave(const Consts &c, const Grid &g, bool mesofd, T *ga, T *gb, T *pop,
+                          int64_t nsteps, hipStream_t st);
 
 // Temporally blocked MMFD step (linear CDE, Burgers) on D2Q5 / D2Q9: one
 // launch advances tb steps

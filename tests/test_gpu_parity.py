@@ -25,6 +25,10 @@ CASES = [
          a=(1.25, -0.5, 0.25)),
     dict(name="d1q3-lcde-2l-resident", lattice="D1Q3", n=(1024,), eq="lcde", u=(0.2,), K=[[0.25]],
          a=(1.25, -0.5, 0.25)),
+    dict(name="d1q3-lcde-2l-wave64", lattice="D1Q3", n=(64,), eq="lcde", u=(0.2,), K=[[0.25]],
+         a=(1.25, -0.5, 0.25)),
+    dict(name="d1q3-lcde-mesofd-wave", lattice="D1Q3", n=(512,), eq="lcde", u=(0.2,), K=[[0.25]],
+         a=(1.25, -0.5, 0.25), form="mesofd"),
     dict(name="d1q3-burgers-3l", lattice="D1Q3", n=(999,), eq="burgers", dx=0.1, dt=0.02,
          kind="three_level", a=EX13[0], ah=EX13[1]),
     dict(name="d1q3-lcde-mesofd", lattice="D1Q3", n=(1030,), eq="lcde", u=(0.2,), K=[[0.25]],
@@ -127,3 +131,33 @@ def test_fp32_tolerance(M, case):
     err = rel_l2(got, want)
     print("fp32 rel-L2 %s: %.3e" % (case["name"], err))
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("form", ["mmfd", "mesofd"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_1d_register_run_equals_single_steps(M, n, form, precision):
+    """A run of small periodic 1D two-level LCDE grids held in the registers
+    of one workgroup (wavefronts joined by DPP shifts and their end nodes)
+    equals the same steps taken one launch at a time, bit for bit: the last
+    level and, for MesoFD, the populations."""
+    from parity_util import make_solver
+    case = dict(lattice="D1Q3", n=(n,), eq="lcde", u=(0.2,), K=[[0.25]], a=(1.25, -0.5, 0.25),
+                form=form)
+    rng = np.random.default_rng(n)
+    dt = np.float64 if precision == "fp64" else np.float32
+    cur = rand_state(case, rng).astype(dt)
+    outs = []
+    for chunks in ([23], [1] * 23):
+        s = make_solver(M, case, precision)
+        s.set_state(cur)
+        for k in chunks:
+            s.step(k)
+        got = [s.get_state()]
+        if form == "mesofd":
+            got.append(s.get_state(populations=True))
+        outs.append(got)
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
