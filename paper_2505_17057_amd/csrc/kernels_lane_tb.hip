@@ -25,6 +25,7 @@
 
 #include "../../include/mfd.h"
 #include "batch_kernels.h"
+#include "edf.h"
 #include "mfd_internal.h"
 
 namespace mfd {
@@ -146,6 +147,7 @@ template <int P>
 struct LinSeg {
   using Params = LinC;
   static constexpr int kRG = 8, kNPF = 32;  // 8 wavefronts, 16 rows each
+  static constexpr int kQ = 0;              // no populations
   PairNode<P> node;
   __device__ __forceinline__ explicit LinSeg(const LinC &kc) {
     node.a0 = kc.a0;
@@ -211,6 +213,7 @@ template <int P>
 struct BurgSeg {
   using Params = BurgC;
   static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
+  static constexpr int kQ = 0;               // no populations
   BurgC k;
   __device__ __forceinline__ explicit BurgSeg(const BurgC &kc) : k(kc) {}
   __device__ __forceinline__ PP parts(float2 r) const {
@@ -301,6 +304,136 @@ struct BurgSeg {
   }
 };
 
+// MesoFD form of the two-level linear CDE (Eq. (2-1), the moments by
+// Eq. (2-1-1)), binary32: the node function of the single-step kernel
+// (mesofd_pops, moments_of), whose EDF values are g_J(y) = ubar_J phi(y) for
+// the moving directions and, at rest, g_0(x) = phi(x) - sum_J g_J(x).  Each
+// node forms its products ubar_J phi once, when its row enters, and the
+// populations f_J(x) = sum_k a_k g_J(x + k e_J) take their neighbours' from
+// the lanes beside (DPP) or the rows' registers.  The populations of the
+// launch's last step go to memory with the moment.
+struct MesoC {
+  float ub[9];  // ubar_J, J = 1 .. Q-1 (index J - 1)
+  float a[3];   // a_k, k = -1, 0, +1
+};
+
+// AM: bit k + 1 set when a_k is not zero (the terms the scheme has)
+template <class L, int AM>
+struct MesoSeg {
+  using Params = MesoC;
+  static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
+  static constexpr int kQ = L::Q;
+  static constexpr int QM = L::Q - 1;  // moving directions
+  static constexpr bool ak[3] = {(AM & 1) != 0, (AM & 2) != 0, (AM & 4) != 0};
+  float ub[QM], a[3];
+  __device__ __forceinline__ explicit MesoSeg(const MesoC &kc) {
+#pragma unroll
+    for (int j = 0; j < QM; ++j) ub[j] = kc.ub[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] = kc.a[k];
+      asm("" : "+v"(a[k]));  // a VGPR operand of the lane-shifted multiply-adds
+    }
+  }
+  struct Row {  // a row's two columns: the products ubar_J phi and g_0
+    float ue[QM], uo[QM], g0e, g0o;
+  };
+  __device__ __forceinline__ Row parts(float2 r) const {
+    Row q;
+    float se = 0.0f, so = 0.0f;
+#pragma unroll
+    for (int j = 0; j < QM; ++j) {
+      q.ue[j] = ub[j] * r.x;
+      q.uo[j] = ub[j] * r.y;
+      se = se + q.ue[j];
+      so = so + q.uo[j];
+    }
+    q.g0e = r.x - se;
+    q.g0o = r.y - so;
+    return q;
+  }
+  // f += a_k g, with g the product of direction J at column offset dx (-1,
+  // 0, +1) from column 2l (ODD = 0) or 2l + 1 (ODD = 1) in row R
+  template <int J, bool ODD>
+  __device__ __forceinline__ float term(float f, int k, int dx, const Row &R) const {
+    const int j = J - 1;
+    if constexpr (!ODD) {
+      if (dx < 0) return fmac_from_left(f, R.uo[j], a[k]);
+      return __builtin_fmaf(a[k], dx == 0 ? R.ue[j] : R.uo[j], f);
+    } else {
+      if (dx > 0) return fmac_from_right(f, R.ue[j], a[k]);
+      return __builtin_fmaf(a[k], dx == 0 ? R.uo[j] : R.ue[j], f);
+    }
+  }
+  // the populations and the moment of row y (rows y - 1, y, y + 1: p, c, n)
+  template <bool ODD>
+  __device__ __forceinline__ float node(const Row &p, const Row &c, const Row &n,
+                                        float (&fo)[L::Q]) const {
+    // rest direction: g_0 at x for every k
+    {
+      float f = 0.0f;
+      const float g = ODD ? c.g0o : c.g0e;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (ak[k]) f = __builtin_fmaf(a[k], g, f);
+      fo[0] = f;
+    }
+    static_for<L::Q - 1>([&](auto JI) {
+      constexpr int J = decltype(JI)::value + 1;
+      constexpr int ex = L::E[J][0], ey = L::E[J][1];
+      float f = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (ak[k]) {
+          const int dy = (k - 1) * ey, dx = (k - 1) * ex;
+          const Row &R = dy < 0 ? p : (dy > 0 ? n : c);
+          f = term<J, ODD>(f, k, dx, R);
+        }
+      }
+      fo[J] = f;
+    });
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < L::Q; ++j) m = m + fo[j];
+    return m;
+  }
+  template <class Emit>
+  __device__ __forceinline__ void operator()(const float2 *lds, int lane, int ya, int yb,
+                                             float2 top, float2 bot, const Emit &emit) const {
+    auto row = [&](int y, const Row &p, const Row &c, const Row &n) {
+      float fe[L::Q], fo[L::Q];
+      const float me = node<false>(p, c, n, fe);
+      const float mo = node<true>(p, c, n, fo);
+      emit(y, make_float2(me, mo), fe, fo);
+    };
+    Row pa = parts(top), pb = parts(lds[ya * 64 + lane]);
+    int y = ya;
+    // three rows per pass; each row's parts are formed just before the row
+    // that needs them, so that at most four rows' are live
+    for (; y + 3 < yb; y += 3) {
+      const float2 r1 = lds[(y + 1) * 64 + lane];
+      const float2 r2 = lds[(y + 2) * 64 + lane];
+      const float2 r3 = lds[(y + 3) * 64 + lane];
+      const Row p1 = parts(r1);
+      row(y, pa, pb, p1);
+      const Row p2 = parts(r2);
+      row(y + 1, pb, p1, p2);
+      const Row p3 = parts(r3);
+      row(y + 2, p1, p2, p3);
+      pa = p2;
+      pb = p3;
+    }
+    const int left = yb - y;
+    const Row p1 = parts(left > 1 ? lds[(y + 1) * 64 + lane] : bot);
+    row(y, pa, pb, p1);
+    if (left > 1) {
+      const Row p2 = parts(left > 2 ? lds[(y + 2) * 64 + lane] : bot);
+      row(y + 1, pb, p1, p2);
+      if (left > 2) row(y + 2, p1, p2, parts(bot));
+    }
+  }
+};
+
 // The steps of one window: TBS steps (TBS <= TBW) of the window in LDS whose
 // origin is (x0, y0); the last one writes the tile, the interior that starts
 // TBW nodes in, to `out` (an nx x ny grid).  Every wavefront of the
@@ -308,7 +441,8 @@ struct BurgSeg {
 template <class Seg, int RG>
 __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int H, int TBS,
                                              int TBW, int x0, int y0, int nx, int ny,
-                                             float *__restrict__ out, const Seg &seg_run) {
+                                             float *__restrict__ out, float *__restrict__ pop,
+                                             const Seg &seg_run) {
   constexpr int W = 128;
   // this lane's columns inside the tile (last step's stores)
   const int c0 = 2 * lane;
@@ -328,14 +462,27 @@ __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int 
     lds_barrier();
     if (act) {
       if (t < TBS) {
-        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) { lds[y * 64 + lane] = o; });
+        seg_run(lds, lane, ya, yb, top, bot,
+                [&](int y, float2 o, const auto &...) { lds[y * 64 + lane] = o; });
       } else {
-        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o) {
+        // the tile: moments, and the populations of segments that form them
+        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o, const auto &...pops) {
           const int gy = y0 + y;
           if (y >= TBW && y < H - TBW && gy < ny) {
-            float *row = out + (int64_t)gy * nx + x0 + c0;
-            if (se) row[0] = o.x;
-            if (so) row[1] = o.y;
+            const int64_t gi = (int64_t)gy * nx + x0 + c0;
+            if (se) out[gi] = o.x;
+            if (so) out[gi + 1] = o.y;
+            if constexpr (sizeof...(pops) == 2) {
+              const int64_t N = (int64_t)nx * ny;
+              auto store = [&](const float *fe, const float *fo) {
+#pragma unroll
+                for (int j = 0; j < Seg::kQ; ++j) {
+                  if (se) pop[j * N + gi] = fe[j];
+                  if (so) pop[j * N + gi + 1] = fo[j];
+                }
+              };
+              store(pops...);
+            }
           }
         });
       }
@@ -387,8 +534,9 @@ __device__ __forceinline__ void window_put(float2 *lds, int H, int lane, int rg,
 // segments; NPF prefetch values per thread (NPF / 2 rows of the next window).
 template <class Seg, int RG, int NPF>
 __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ cur,
-                                                    float *__restrict__ out, int nx, int ny, int H,
-                                                    int TB, int tiles_x, int ntiles,
+                                                    float *__restrict__ out,
+                                                    float *__restrict__ pop, int nx, int ny,
+                                                    int H, int TB, int tiles_x, int ntiles,
                                                     typename Seg::Params kc) {
   constexpr int W = 128;
   extern __shared__ unsigned char smem_lane[];
@@ -418,7 +566,7 @@ __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ c
       yn = (tn / tiles_x) * TY - TB;
       window_fetch<RG, NPF, false>(cur, nx, ny, H, xn, yn, lane, rg, pf);
     }
-    window_steps<Seg, RG>(lds, lane, rg, H, TB, TB, x0, y0, nx, ny, out, seg_run);
+    window_steps<Seg, RG>(lds, lane, rg, H, TB, TB, x0, y0, nx, ny, out, pop, seg_run);
     if (!more) break;
     window_put<RG, NPF>(lds, H, lane, rg, pf);
     lds_barrier();
@@ -491,7 +639,7 @@ __global__ __launch_bounds__(64 * RG) void k_batch_lane_tb(
     const int TBS = left < TB ? (int)left : TB;
     const Seg seg_run(I.prm);
     window_steps<Seg, RG>(lds, lane, rg, H, TBS, TB, w.x0, w.y0, I.nx, I.ny,
-                          I.ring[(I.c0 + launch + 1) & 1], seg_run);
+                          I.ring[(I.c0 + launch + 1) & 1], nullptr, seg_run);
     if (!more) break;
     window_put<RG, NPF>(lds, H, lane, rg, pf);
     lds_barrier();
@@ -546,7 +694,7 @@ int lane_slots(const void *fn, int threads, size_t lds) {
 // 128-column window in place: RG wavefronts, NPF / 2 rows of the next
 // window each (RG NPF / 2 = 128 rows)
 template <class Seg>
-hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *out,
+hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *out, float *pop,
                     const typename Seg::Params &prm, hipStream_t st) {
   constexpr int RG = Seg::kRG, NPF = Seg::kNPF, W = 128;
   if (pl.h > RG * NPF / 2) return hipErrorInvalidValue;
@@ -564,8 +712,8 @@ hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *ou
   if (grid <= 0) return hipErrorInvalidValue;
   grid = grid < ntiles ? grid : ntiles;
   if (grid >= 8) grid &= ~7;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st, cur, out, nx, ny, pl.h, pl.tb, tx,
-                     ntiles, prm);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st, cur, out, pop, nx, ny, pl.h, pl.tb,
+                     tx, ntiles, prm);
   return hipGetLastError();
 }
 
@@ -596,9 +744,32 @@ template <int P>
 hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur, float *out,
                    hipStream_t st) {
   const KC<float> k = make_kc<float>(c);
-  if (c.eq == kLCDE) return lane_cfg<LinSeg<P>>(g, pl, cur, out, lin_params(k, P), st);
+  if (c.eq == kLCDE) return lane_cfg<LinSeg<P>>(g, pl, cur, out, nullptr, lin_params(k, P), st);
   if (!burgers_weights_symmetric(k, c.lattice)) return hipErrorInvalidValue;
-  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, burg_params(k, P), st);
+  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, nullptr, burg_params(k, P), st);
+}
+
+template <class L>
+hipError_t meso_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
+                   float *mom_out, float *pop_out, hipStream_t st) {
+  const KC<float> k = make_kc<float>(c);
+  MesoC mc{};
+  for (int j = 1; j < L::Q; ++j) mc.ub[j - 1] = k.ubar[j];
+  int am = 0;
+  for (int q = 0; q < 3; ++q) {
+    mc.a[q] = k.a[q];
+    if (k.a[q] != 0.0f) am |= 1 << q;
+  }
+  switch (am) {
+    case 0: return lane_cfg<MesoSeg<L, 0>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 1: return lane_cfg<MesoSeg<L, 1>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 2: return lane_cfg<MesoSeg<L, 2>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 3: return lane_cfg<MesoSeg<L, 3>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 4: return lane_cfg<MesoSeg<L, 4>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 5: return lane_cfg<MesoSeg<L, 5>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 6: return lane_cfg<MesoSeg<L, 6>>(g, pl, cur, mom_out, pop_out, mc, st);
+    default: return lane_cfg<MesoSeg<L, 7>>(g, pl, cur, mom_out, pop_out, mc, st);
+  }
 }
 
 template <class Seg>
@@ -655,6 +826,18 @@ hipError_t launch_batch_lane_tb(const BatchKey &k, const void *inst, const int *
   }
   if (k.eq == kLCDE) return batch_lane_cfg<LinSeg<2>>(inst, tile_inst, ntiles, launch, pl, st);
   return batch_lane_cfg<BurgSeg<2>>(inst, tile_inst, ntiles, launch, pl, st);
+}
+
+bool lane_meso_applies(const Consts &c, int elem) {
+  return elem == 4 && c.eq == kLCDE && !c.three && c.dim == 2 && (c.lattice == 2 || c.lattice == 3);
+}
+
+hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl,
+                                 const float *cur, float *mom_out, float *pop_out,
+                                 hipStream_t st) {
+  if (!lane_meso_applies(c, 4) || pl.w != 128) return hipErrorInvalidValue;
+  if (c.lattice == 3) return meso_eq<LatD2Q9>(c, g, pl, cur, mom_out, pop_out, st);
+  return meso_eq<LatD2Q5>(c, g, pl, cur, mom_out, pop_out, st);
 }
 
 hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,

@@ -132,7 +132,12 @@ __global__ __launch_bounds__(W *RG) void k_mesofd_tb(const T *__restrict__ cur,
 bool mesofd_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
   if (c.dim != 2 || (c.lattice != 2 && c.lattice != 3)) return false;
   if ((c.eq != kLCDE && c.eq != kBurgers) || c.three) return false;
-  if (!tb_plan_valid(pl, 2, elem)) return false;
+  if (pl.w == 128 && lane_meso_applies(c, elem)) {
+    // the in-place lane-shared window (one LDS level)
+    if (!tb_plan_valid(pl, 1, elem) || !lane_tb_window_fits(pl)) return false;
+  } else if (!tb_plan_valid(pl, 2, elem)) {
+    return false;
+  }
   return g.n[0] >= pl.w && g.n[1] >= pl.h;
 }
 
@@ -174,6 +179,10 @@ hipError_t mtb_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur
 template <typename T>
 hipError_t launch_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                             T *mom_out, T *pop_out, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (pl.w == 128 && lane_meso_applies(c, 4))
+      return launch_lane_mesofd_tb(c, g, pl, cur, mom_out, pop_out, st);
+  }
   if (c.lattice == 3) return mtb_eq<LatD2Q9, T>(c, g, pl, cur, mom_out, pop_out, st);
   if (c.lattice == 2) return mtb_eq<LatD2Q5, T>(c, g, pl, cur, mom_out, pop_out, st);
   return hipErrorInvalidValue;

@@ -146,6 +146,11 @@ int tb_window_cols();
 // level t in, level t + tb out
 bool lane_tb_applies(const Consts &c, int elem);
 bool lane_tb_window_fits(const TbPlan &pl);
+// the same window for the two-level MesoFD form of the binary32 linear CDE:
+// moments of level t in; moments and populations of level t + tb out
+bool lane_meso_applies(const Consts &c, int elem);
+hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl,
+                                 const float *cur, float *mom_out, float *pop_out, hipStream_t st);
 hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
                           float *out, hipStream_t st);
 // blocked MesoFD step, two-level linear CDE / Burgers (kernels_mesofd_tb.hip):

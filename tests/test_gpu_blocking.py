@@ -234,7 +234,7 @@ def test_mesofd_blocked_fp32_equals_unblocked(M, name):
     rng = np.random.default_rng(20)
     cur = rand_state(case, rng).astype(np.float32)
     outs = []
-    for plan in ((1,), (4, 32, 64), (6, 64, 128)):
+    for plan in ((1,), (4, 32, 64), (6, 64, 128), (12, 112, 128), (3, 10, 128), (16, 37, 128)):
         s = make_solver(M, case, "fp32")
         s.set_plan(*plan)
         s.set_state(cur)
