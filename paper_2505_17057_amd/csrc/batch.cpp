@@ -148,7 +148,7 @@ int Batch::build() {
         // the lane-shared kernel needs every instance's constants to suit it;
         // else the same plan in 64-column windows
         bool ok = group_plan_valid(g.key, g.plan);
-        for (int i : g.order) ok = ok && lane_tb_applies(entries[i].s->consts, 4);
+        for (int i : g.order) ok = ok && lane_shared_fp32(entries[i].s->consts);
         if (!ok) g.plan.w = 64;
       }
       if (g.plan.tb > 1 && !group_plan_valid(g.key, g.plan)) g.plan = TbPlan{1, 0};
@@ -422,7 +422,7 @@ int Batch::autotune() {
     }
     std::vector<TbPlan> cands{TbPlan{1, 0}};
     bool lane_ok = lane_batch_applies(g.key);
-    for (int i : g.order) lane_ok = lane_ok && lane_tb_applies(entries[i].s->consts, 4);
+    for (int i : g.order) lane_ok = lane_ok && lane_shared_fp32(entries[i].s->consts);
     for (int d : {2, 3, 4, 6, 8})
       for (int h : {32, 48, 64, 96, 128})
         if (group_plan_valid(g.key, TbPlan{d, h})) cands.push_back(TbPlan{d, h});

@@ -26,7 +26,9 @@
 #include "../../include/mfd.h"
 #include "batch_kernels.h"
 #include "edf.h"
+#include "mesofd_node.h"
 #include "mfd_internal.h"
+#include "mmfd_node.h"
 
 namespace mfd {
 
@@ -75,6 +77,39 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
+
+// the two-column value of a lane's row, in the precision T
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+template <typename T>
+using V2 = typename Pair2<T>::type;
+template <typename T>
+__device__ __forceinline__ V2<T> mk2(T a, T b) {
+  V2<T> v;
+  v.x = a;
+  v.y = b;
+  return v;
+}
+
+// binary64 lane shifts: the two halves moved by DPP (lanes without a
+// source read 0)
+template <int CTRL>
+__device__ __forceinline__ double shift64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v) { return shift64<0x130>(v); }
+__device__ __forceinline__ double from_left(double v) { return shift64<0x138>(v); }
 
 }  // namespace
 
@@ -146,6 +181,7 @@ struct PairNode {
 template <int P>
 struct LinSeg {
   using Params = LinC;
+  using T = float;
   static constexpr int kRG = 8, kNPF = 32;  // 8 wavefronts, 16 rows each
   static constexpr int kQ = 0;              // no populations
   PairNode<P> node;
@@ -212,6 +248,7 @@ struct PP {  // pair parts of a lane's two columns
 template <int P>
 struct BurgSeg {
   using Params = BurgC;
+  using T = float;
   static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
   static constexpr int kQ = 0;               // no populations
   BurgC k;
@@ -321,6 +358,7 @@ struct MesoC {
 template <class L, int AM>
 struct MesoSeg {
   using Params = MesoC;
+  using T = float;
   static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
   static constexpr int kQ = L::Q;
   static constexpr int QM = L::Q - 1;  // moving directions
@@ -434,15 +472,104 @@ struct MesoSeg {
   }
 };
 
+// Any two-level linear CDE or Burgers step, MMFD or MesoFD form, binary32
+// or binary64, through the single-step kernels' node functions (mmfd_node;
+// mesofd_pops and moments_of), which read the nine values around a node from
+// an accessor: here the lane's two columns and their neighbours in the lanes
+// beside (DPP, taken once per row) for the rows y - 1, y, y + 1 held in
+// registers (Burgers' second record field, phi^2 dt / (2 dx), is formed from
+// them where read).  The segment for the cases without a specialized one.
+template <class L, int EQ, bool B1, bool MESO, typename TT>
+struct AccSeg {
+  using T = TT;
+  using Params = KC<TT>;
+  // binary32: 16 wavefronts, 8 prefetch rows each; binary64 (twice the
+  // registers a value): 8 wavefronts, 16 rows each
+  static constexpr int kRG = sizeof(TT) == 8 ? 8 : 16, kNPF = 256 / kRG;
+  static constexpr int kQ = MESO ? L::Q : 0;
+  const KC<TT> &kc;
+  __device__ __forceinline__ explicit AccSeg(const KC<TT> &k) : kc(k) {}
+  struct Row {  // this lane's columns 2l, 2l + 1 and the columns 2l - 1, 2l + 2
+    T e, o, l, r;
+  };
+  __device__ __forceinline__ Row row(V2<T> v) const {
+    Row q;
+    q.e = v.x;
+    q.o = v.y;
+    q.l = from_left(v.y);
+    q.r = from_right(v.x);
+    return q;
+  }
+  // the new moment (and, MesoFD, populations) of column 2l (ODD = 0) or 2l + 1
+  template <bool ODD>
+  __device__ __forceinline__ T node(const Row &p, const Row &c, const Row &n,
+                                    T (&fo)[MESO ? L::Q : 1]) const {
+    auto val = [&](int dy, int dx) {
+      const Row &R = dy < 0 ? p : (dy > 0 ? n : c);
+      if constexpr (ODD) return dx < 0 ? R.e : (dx == 0 ? R.o : R.r);
+      else return dx < 0 ? R.l : (dx == 0 ? R.e : R.o);
+    };
+    auto at = [&](int q, int, int dy, int dx) {
+      const T v = val(dy, dx);
+      if constexpr (EQ == kBurgers) return q == 0 ? v : (v * v) * kc.bh;
+      else return v;
+    };
+    auto ath = [&](int, int, int, int) { return T(0); };
+    if constexpr (MESO) {
+      T m[1];
+      mesofd_pops<L, EQ, false, B1>(at, ath, (const T *)nullptr, false, fo, kc);
+      moments_of<L, EQ>(fo, m);
+      return m[0];
+    } else {
+      T cc[1] = {ODD ? c.o : c.e}, pc[1] = {T(0)}, oc[1];
+      mmfd_node<L, EQ, false, false, T, B1>(at, ath, cc, pc, oc, kc);
+      return oc[0];
+    }
+  }
+  template <class Emit>
+  __device__ __forceinline__ void operator()(const V2<T> *lds, int lane, int ya, int yb,
+                                             V2<T> top, V2<T> bot, const Emit &emit) const {
+    auto one = [&](int y, const Row &p, const Row &c, const Row &n) {
+      T fe[MESO ? L::Q : 1], fo[MESO ? L::Q : 1];
+      const T me = node<false>(p, c, n, fe);
+      const T mo = node<true>(p, c, n, fo);
+      if constexpr (MESO) emit(y, mk2<T>(me, mo), fe, fo);
+      else emit(y, mk2<T>(me, mo));
+    };
+    Row pa = row(top), pb = row(lds[ya * 64 + lane]);
+    int y = ya;
+    for (; y + 3 < yb; y += 3) {
+      const Row p1 = row(lds[(y + 1) * 64 + lane]);
+      const Row p2 = row(lds[(y + 2) * 64 + lane]);
+      const Row p3 = row(lds[(y + 3) * 64 + lane]);
+      one(y, pa, pb, p1);
+      one(y + 1, pb, p1, p2);
+      one(y + 2, p1, p2, p3);
+      pa = p2;
+      pb = p3;
+    }
+    const int left = yb - y;
+    const Row p1 = row(left > 1 ? lds[(y + 1) * 64 + lane] : bot);
+    one(y, pa, pb, p1);
+    if (left > 1) {
+      const Row p2 = row(left > 2 ? lds[(y + 2) * 64 + lane] : bot);
+      one(y + 1, pb, p1, p2);
+      if (left > 2) one(y + 2, p1, p2, row(bot));
+    }
+  }
+};
+
 // The steps of one window: TBS steps (TBS <= TBW) of the window in LDS whose
 // origin is (x0, y0); the last one writes the tile, the interior that starts
 // TBW nodes in, to `out` (an nx x ny grid).  Every wavefront of the
 // workgroup calls it; it ends with a barrier.
 template <class Seg, int RG>
-__device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int H, int TBS,
-                                             int TBW, int x0, int y0, int nx, int ny,
-                                             float *__restrict__ out, float *__restrict__ pop,
+__device__ __forceinline__ void window_steps(V2<typename Seg::T> *lds, int lane, int rg, int H,
+                                             int TBS, int TBW, int x0, int y0, int nx, int ny,
+                                             typename Seg::T *__restrict__ out,
+                                             typename Seg::T *__restrict__ pop,
                                              const Seg &seg_run) {
+  using T = typename Seg::T;
   constexpr int W = 128;
   // this lane's columns inside the tile (last step's stores)
   const int c0 = 2 * lane;
@@ -454,7 +581,7 @@ __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int 
     const int seg = (Hr + RG - 1) / RG;
     const int ya = t + rg * seg, yb = min(ya + seg, H - t);
     const bool act = ya < yb;  // uniform across the wavefront
-    float2 top = make_float2(0.f, 0.f), bot = top;
+    V2<T> top = mk2<T>(T(0), T(0)), bot = top;
     if (act) {
       top = lds[(ya - 1) * 64 + lane];
       bot = lds[yb * 64 + lane];
@@ -463,10 +590,10 @@ __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int 
     if (act) {
       if (t < TBS) {
         seg_run(lds, lane, ya, yb, top, bot,
-                [&](int y, float2 o, const auto &...) { lds[y * 64 + lane] = o; });
+                [&](int y, V2<T> o, const auto &...) { lds[y * 64 + lane] = o; });
       } else {
         // the tile: moments, and the populations of segments that form them
-        seg_run(lds, lane, ya, yb, top, bot, [&](int y, float2 o, const auto &...pops) {
+        seg_run(lds, lane, ya, yb, top, bot, [&](int y, V2<T> o, const auto &...pops) {
           const int gy = y0 + y;
           if (y >= TBW && y < H - TBW && gy < ny) {
             const int64_t gi = (int64_t)gy * nx + x0 + c0;
@@ -474,7 +601,7 @@ __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int 
             if (so) out[gi + 1] = o.y;
             if constexpr (sizeof...(pops) == 2) {
               const int64_t N = (int64_t)nx * ny;
-              auto store = [&](const float *fe, const float *fo) {
+              auto store = [&](const T *fe, const T *fo) {
 #pragma unroll
                 for (int j = 0; j < Seg::kQ; ++j) {
                   if (se) pop[j * N + gi] = fe[j];
@@ -495,9 +622,9 @@ __device__ __forceinline__ void window_steps(float2 *lds, int lane, int rg, int 
 // rg + RG, ... (NPF / 2 of them) of this lane's two columns, into registers.
 // ANY: modular wrap (grids smaller than the window); else one conditional
 // wrap (nx >= W, ny >= H).
-template <int RG, int NPF, bool ANY>
-__device__ __forceinline__ void window_fetch(const float *__restrict__ cur, int nx, int ny, int H,
-                                             int x0, int y0, int lane, int rg, float (&pf)[NPF]) {
+template <int RG, int NPF, bool ANY, typename T>
+__device__ __forceinline__ void window_fetch(const T *__restrict__ cur, int nx, int ny, int H,
+                                             int x0, int y0, int lane, int rg, T (&pf)[NPF]) {
   auto wrap = [&](int i, int n) {
     if constexpr (ANY) {
       i %= n;
@@ -509,38 +636,37 @@ __device__ __forceinline__ void window_fetch(const float *__restrict__ cur, int 
   const int ge = wrap(x0 + 2 * lane, nx), go = wrap(x0 + 2 * lane + 1, nx);
   // byte offsets within a row (a row is far below 4 GiB): each load is a row
   // base in scalar registers plus one of these two offsets
-  const uint32_t be = (uint32_t)ge * 4u, bo = (uint32_t)go * 4u;
+  const uint32_t be = (uint32_t)ge * (uint32_t)sizeof(T), bo = (uint32_t)go * (uint32_t)sizeof(T);
 #pragma unroll
   for (int j = 0; j < NPF / 2; ++j) {
     const int r = min(rg + RG * j, H - 1);
     const int y = wrap(y0 + r, ny);
     const char *row = reinterpret_cast<const char *>(cur + (int64_t)y * nx);
-    pf[2 * j] = *reinterpret_cast<const float *>(row + be);
-    pf[2 * j + 1] = *reinterpret_cast<const float *>(row + bo);
+    pf[2 * j] = *reinterpret_cast<const T *>(row + be);
+    pf[2 * j + 1] = *reinterpret_cast<const T *>(row + bo);
   }
 }
 
-template <int RG, int NPF>
-__device__ __forceinline__ void window_put(float2 *lds, int H, int lane, int rg,
-                                           const float (&pf)[NPF]) {
+template <int RG, int NPF, typename T>
+__device__ __forceinline__ void window_put(V2<T> *lds, int H, int lane, int rg,
+                                           const T (&pf)[NPF]) {
 #pragma unroll
   for (int j = 0; j < NPF / 2; ++j) {
     const int r = rg + RG * j;
-    if (r < H) lds[r * 64 + lane] = make_float2(pf[2 * j], pf[2 * j + 1]);
+    if (r < H) lds[r * 64 + lane] = mk2<T>(pf[2 * j], pf[2 * j + 1]);
   }
 }
 
 // One kernel for every lane-shared segment type Seg; RG wavefronts of row
 // segments; NPF prefetch values per thread (NPF / 2 rows of the next window).
-template <class Seg, int RG, int NPF>
-__global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ cur,
-                                                    float *__restrict__ out,
-                                                    float *__restrict__ pop, int nx, int ny,
-                                                    int H, int TB, int tiles_x, int ntiles,
-                                                    typename Seg::Params kc) {
+template <class Seg, int RG, int NPF, typename T = typename Seg::T>
+__global__ __launch_bounds__(64 * RG) void k_lane_tb(const T *__restrict__ cur,
+                                                    T *__restrict__ out, T *__restrict__ pop,
+                                                    int nx, int ny, int H, int TB, int tiles_x,
+                                                    int ntiles, typename Seg::Params kc) {
   constexpr int W = 128;
   extern __shared__ unsigned char smem_lane[];
-  float2 *lds = reinterpret_cast<float2 *>(smem_lane);  // [H][64]
+  V2<T> *lds = reinterpret_cast<V2<T> *>(smem_lane);  // [H][64]
   const int TX = W - 2 * TB, TY = H - 2 * TB;
   const int G = gridDim.x;
   if ((int)blockIdx.x >= ntiles) return;
@@ -548,7 +674,7 @@ __global__ __launch_bounds__(64 * RG) void k_lane_tb(const float *__restrict__ c
   const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Seg seg_run(kc);
 
-  float pf[NPF];
+  T pf[NPF];
   int v = blockIdx.x;
   int tile = xcd_remap_l(v, ntiles);
   int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
@@ -659,10 +785,14 @@ bool burgers_weights_symmetric(const KC<float> &k, int lattice) {
 }  // namespace
 
 bool lane_tb_applies(const Consts &c, int elem) {
-  if (elem != 4 || c.three || c.dim != 2 || (c.lattice != 2 && c.lattice != 3)) return false;
+  if ((elem != 4 && elem != 8) || c.three || c.dim != 2) return false;
+  return (c.lattice == 2 || c.lattice == 3) && (c.eq == kLCDE || c.eq == kBurgers);
+}
+
+bool lane_shared_fp32(const Consts &c) {
+  if (!lane_tb_applies(c, 4)) return false;
   if (c.eq == kLCDE) return true;
-  if (c.eq != kBurgers || !c.beta_one) return false;
-  return burgers_weights_symmetric(make_kc<float>(c), c.lattice);
+  return c.beta_one && burgers_weights_symmetric(make_kc<float>(c), c.lattice);
 }
 
 bool lane_tb_window_fits(const TbPlan &pl) {
@@ -694,14 +824,16 @@ int lane_slots(const void *fn, int threads, size_t lds) {
 // 128-column window in place: RG wavefronts, NPF / 2 rows of the next
 // window each (RG NPF / 2 = 128 rows)
 template <class Seg>
-hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const float *cur, float *out, float *pop,
-                    const typename Seg::Params &prm, hipStream_t st) {
+hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const typename Seg::T *cur,
+                    typename Seg::T *out, typename Seg::T *pop, const typename Seg::Params &prm,
+                    hipStream_t st) {
+  using T = typename Seg::T;
   constexpr int RG = Seg::kRG, NPF = Seg::kNPF, W = 128;
   if (pl.h > RG * NPF / 2) return hipErrorInvalidValue;
   const int nx = (int)g.n[0], ny = (int)g.n[1];
   const int TX = W - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
   const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
-  const size_t lds = (size_t)pl.h * W * sizeof(float);
+  const size_t lds = (size_t)pl.h * W * sizeof(T);
   auto fn = k_lane_tb<Seg, RG, NPF>;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -740,36 +872,59 @@ BurgC burg_params(const KC<float> &k, int npair) {
   return bc;
 }
 
-template <int P>
-hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur, float *out,
-                   hipStream_t st) {
-  const KC<float> k = make_kc<float>(c);
-  if (c.eq == kLCDE) return lane_cfg<LinSeg<P>>(g, pl, cur, out, nullptr, lin_params(k, P), st);
-  if (!burgers_weights_symmetric(k, c.lattice)) return hipErrorInvalidValue;
-  return lane_cfg<BurgSeg<P>>(g, pl, cur, out, nullptr, burg_params(k, P), st);
+// the node-function segment for every case without a specialized one
+template <class L, int EQ, bool MESO, typename T>
+hipError_t acc_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *out, T *pop,
+                  hipStream_t st) {
+  const KC<T> k = make_kc<T>(c);
+  if constexpr (EQ == kBurgers) {
+    if (c.beta_one) return lane_cfg<AccSeg<L, EQ, true, MESO, T>>(g, pl, cur, out, pop, k, st);
+  }
+  return lane_cfg<AccSeg<L, EQ, false, MESO, T>>(g, pl, cur, out, pop, k, st);
 }
 
-template <class L>
-hipError_t meso_eq(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
-                   float *mom_out, float *pop_out, hipStream_t st) {
-  const KC<float> k = make_kc<float>(c);
-  MesoC mc{};
-  for (int j = 1; j < L::Q; ++j) mc.ub[j - 1] = k.ubar[j];
-  int am = 0;
-  for (int q = 0; q < 3; ++q) {
-    mc.a[q] = k.a[q];
-    if (k.a[q] != 0.0f) am |= 1 << q;
+template <class L, typename T>
+hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *out,
+                   hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (lane_shared_fp32(c)) {
+      const KC<float> k = make_kc<float>(c);
+      if (c.eq == kLCDE)
+        return lane_cfg<LinSeg<L::P>>(g, pl, cur, out, nullptr, lin_params(k, L::P), st);
+      return lane_cfg<BurgSeg<L::P>>(g, pl, cur, out, nullptr, burg_params(k, L::P), st);
+    }
   }
-  switch (am) {
-    case 0: return lane_cfg<MesoSeg<L, 0>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 1: return lane_cfg<MesoSeg<L, 1>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 2: return lane_cfg<MesoSeg<L, 2>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 3: return lane_cfg<MesoSeg<L, 3>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 4: return lane_cfg<MesoSeg<L, 4>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 5: return lane_cfg<MesoSeg<L, 5>>(g, pl, cur, mom_out, pop_out, mc, st);
-    case 6: return lane_cfg<MesoSeg<L, 6>>(g, pl, cur, mom_out, pop_out, mc, st);
-    default: return lane_cfg<MesoSeg<L, 7>>(g, pl, cur, mom_out, pop_out, mc, st);
+  if (c.eq == kLCDE) return acc_eq<L, kLCDE, false, T>(c, g, pl, cur, out, nullptr, st);
+  return acc_eq<L, kBurgers, false, T>(c, g, pl, cur, out, nullptr, st);
+}
+
+template <class L, typename T>
+hipError_t meso_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *mom_out,
+                   T *pop_out, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (c.eq == kLCDE) {
+      const KC<float> k = make_kc<float>(c);
+      MesoC mc{};
+      for (int j = 1; j < L::Q; ++j) mc.ub[j - 1] = k.ubar[j];
+      int am = 0;
+      for (int q = 0; q < 3; ++q) {
+        mc.a[q] = k.a[q];
+        if (k.a[q] != 0.0f) am |= 1 << q;
+      }
+      switch (am) {
+        case 0: return lane_cfg<MesoSeg<L, 0>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 1: return lane_cfg<MesoSeg<L, 1>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 2: return lane_cfg<MesoSeg<L, 2>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 3: return lane_cfg<MesoSeg<L, 3>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 4: return lane_cfg<MesoSeg<L, 4>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 5: return lane_cfg<MesoSeg<L, 5>>(g, pl, cur, mom_out, pop_out, mc, st);
+        case 6: return lane_cfg<MesoSeg<L, 6>>(g, pl, cur, mom_out, pop_out, mc, st);
+        default: return lane_cfg<MesoSeg<L, 7>>(g, pl, cur, mom_out, pop_out, mc, st);
+      }
+    }
   }
+  if (c.eq == kLCDE) return acc_eq<L, kLCDE, true, T>(c, g, pl, cur, mom_out, pop_out, st);
+  return acc_eq<L, kBurgers, true, T>(c, g, pl, cur, mom_out, pop_out, st);
 }
 
 template <class Seg>
@@ -804,7 +959,7 @@ size_t lane_inst_bytes(const BatchKey &k) {
 
 bool lane_inst_fill(const BatchKey &k, const Consts &c, float *cur, float *other, int nx, int ny,
                     int tiles_x, int tile0, int64_t nsteps, void *dst) {
-  if (!lane_tb_applies(c, 4)) return false;
+  if (!lane_shared_fp32(c)) return false;
   const KC<float> kc = make_kc<float>(c);
   const int np = c.npair;
   if (k.eq == kLCDE) {
@@ -828,23 +983,31 @@ hipError_t launch_batch_lane_tb(const BatchKey &k, const void *inst, const int *
   return batch_lane_cfg<BurgSeg<2>>(inst, tile_inst, ntiles, launch, pl, st);
 }
 
-bool lane_meso_applies(const Consts &c, int elem) {
-  return elem == 4 && c.eq == kLCDE && !c.three && c.dim == 2 && (c.lattice == 2 || c.lattice == 3);
+bool lane_meso_applies(const Consts &c, int elem) { return lane_tb_applies(c, elem); }
+
+template <typename T>
+hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                                 T *mom_out, T *pop_out, hipStream_t st) {
+  if (!lane_meso_applies(c, sizeof(T)) || pl.w != 128) return hipErrorInvalidValue;
+  if (c.lattice == 3) return meso_eq<LatD2Q9, T>(c, g, pl, cur, mom_out, pop_out, st);
+  return meso_eq<LatD2Q5, T>(c, g, pl, cur, mom_out, pop_out, st);
 }
 
-hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl,
-                                 const float *cur, float *mom_out, float *pop_out,
-                                 hipStream_t st) {
-  if (!lane_meso_applies(c, 4) || pl.w != 128) return hipErrorInvalidValue;
-  if (c.lattice == 3) return meso_eq<LatD2Q9>(c, g, pl, cur, mom_out, pop_out, st);
-  return meso_eq<LatD2Q5>(c, g, pl, cur, mom_out, pop_out, st);
+template <typename T>
+hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *out,
+                          hipStream_t st) {
+  if (!lane_tb_applies(c, sizeof(T)) || pl.w != 128) return hipErrorInvalidValue;
+  if (c.lattice == 3) return lane_eq<LatD2Q9, T>(c, g, pl, cur, out, st);
+  return lane_eq<LatD2Q5, T>(c, g, pl, cur, out, st);
 }
 
-hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
-                          float *out, hipStream_t st) {
-  if (!lane_tb_applies(c, 4) || pl.w != 128) return hipErrorInvalidValue;
-  if (c.lattice == 3) return lane_eq<4>(c, g, pl, cur, out, st);
-  return lane_eq<2>(c, g, pl, cur, out, st);
-}
+#define MFD_LANE_INST(T)                                                                     \
+  template hipError_t launch_lane_mesofd_tb<T>(const Consts &, const Grid &, const TbPlan &, \
+                                               const T *, T *, T *, hipStream_t);            \
+  template hipError_t launch_lane_tb<T>(const Consts &, const Grid &, const TbPlan &,        \
+                                        const T *, T *, hipStream_t);
+MFD_LANE_INST(float)
+MFD_LANE_INST(double)
+#undef MFD_LANE_INST
 
 }  // namespace mfd

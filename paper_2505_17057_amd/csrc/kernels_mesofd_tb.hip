@@ -179,10 +179,8 @@ hipError_t mtb_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur
 template <typename T>
 hipError_t launch_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                             T *mom_out, T *pop_out, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (pl.w == 128 && lane_meso_applies(c, 4))
-      return launch_lane_mesofd_tb(c, g, pl, cur, mom_out, pop_out, st);
-  }
+  if (pl.w == 128 && lane_meso_applies(c, sizeof(T)))
+    return launch_lane_mesofd_tb<T>(c, g, pl, cur, mom_out, pop_out, st);
   if (c.lattice == 3) return mtb_eq<LatD2Q9, T>(c, g, pl, cur, mom_out, pop_out, st);
   if (c.lattice == 2) return mtb_eq<LatD2Q5, T>(c, g, pl, cur, mom_out, pop_out, st);
   return hipErrorInvalidValue;

@@ -323,9 +323,8 @@ bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
 template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (lane_tb_applies(c, 4) && pl.w == 128) return launch_lane_tb(c, g, pl, cur, out_cur, st);
-  }
+  if (pl.w == 128 && lane_tb_applies(c, sizeof(T)))
+    return launch_lane_tb<T>(c, g, pl, cur, out_cur, st);
   if (c.lattice == 3) return tb_eq<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
   if (c.lattice == 2) return tb_eq<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
   return hipErrorInvalidValue;

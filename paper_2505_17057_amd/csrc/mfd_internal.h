@@ -141,18 +141,23 @@ bool tb_equation_supported(const Consts &c);
 // the single-grid blocked kernel can run this plan on this grid
 bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 int tb_window_cols();
-// lane-shared binary32 two-level steps of the linear CDE and Burgers' equation
-// with beta = 1 (kernels_lane_tb.hip): 128-column windows updated in place;
-// level t in, level t + tb out
+// lane-shared two-level steps of the linear CDE and Burgers' equation
+// (kernels_lane_tb.hip): 128-column windows updated in place; level t in,
+// level t + tb out; binary32 and binary64
 bool lane_tb_applies(const Consts &c, int elem);
+// the binary32 constants suit the specialized linear CDE / Burgers segments
+// (also the batched lane kernel's condition)
+bool lane_shared_fp32(const Consts &c);
 bool lane_tb_window_fits(const TbPlan &pl);
-// the same window for the two-level MesoFD form of the binary32 linear CDE:
-// moments of level t in; moments and populations of level t + tb out
+// the same window for the two-level MesoFD form: moments of level t in;
+// moments and populations of level t + tb out
 bool lane_meso_applies(const Consts &c, int elem);
-hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl,
-                                 const float *cur, float *mom_out, float *pop_out, hipStream_t st);
-hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
-                          float *out, hipStream_t st);
+template <typename T>
+hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
+                                 T *mom_out, T *pop_out, hipStream_t st);
+template <typename T>
+hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *out,
+                          hipStream_t st);
 // blocked MesoFD step, two-level linear CDE / Burgers (kernels_mesofd_tb.hip):
 // moments of level t in, moments and populations of level t + tb out
 bool mesofd_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);

@@ -296,6 +296,47 @@ def test_lane_shared_fp32_equals_unblocked(M, plan, lattice, eq):
     assert np.array_equal(outs[0], outs[1]), np.abs(outs[0] - outs[1]).max()
 
 
+@pytest.mark.parametrize("plan", [(8, 128, 128), (10, 52, 128), (3, 10, 128), (16, 37, 128),
+                                  (12, 112, 128)])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q5"])
+@pytest.mark.parametrize("eq", ["lcde", "burgers", "burgers-beta"])
+@pytest.mark.parametrize("form", ["mmfd", "mesofd"])
+def test_lane_shared_fp64_bitwise(M, plan, lattice, eq, form):
+    """The binary64 lane-shared windows (the node functions of the single-step
+    kernels on values shared across lanes) equal the oracle value for value,
+    moments and (MesoFD) populations, on a grid with ragged tiles in both
+    directions and a ragged remainder of steps."""
+    from parity_util import make_solver
+    if eq == "lcde":
+        K = K2 if lattice == "D2Q9" else [[0.3, 0.0], [0.0, 0.2]]
+        case = dict(BASE, lattice=lattice, K=K, n=(301, 139), a=(1.0, 0.0, 0.0))
+    else:
+        case = dict(lattice=lattice, eq="burgers", n=(301, 139), **_burgers_a(301))
+        if eq == "burgers-beta":
+            case["beta"] = 0.6
+    if form == "mesofd":
+        case["form"] = "mesofd"
+    print("case", form, eq, lattice, plan, flush=True)
+    rng = np.random.default_rng(29)
+    cur = rand_state(case, rng)
+    steps = 2 * plan[0] + 3
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    assert s.launch_plan() == plan
+    s.set_state(cur)
+    s.step(steps)
+    got = s.get_state()
+    if form == "mesofd":
+        pop, want = _meso_oracle(case, cur, steps)
+        gpop = s.get_state(populations=True)
+        s.close()
+        assert np.array_equal(gpop, pop), np.abs(gpop - pop).max()
+    else:
+        want = run_oracle(case, cur, None, steps)
+        s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
 def test_lane_shared_window_limits(M):
     """The in-place window holds at most 128 rows; other widths are rejected."""
     from parity_util import make_solver
