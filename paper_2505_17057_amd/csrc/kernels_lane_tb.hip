@@ -342,31 +342,38 @@ struct BurgSeg {
 };
 
 // MesoFD form of the two-level linear CDE (Eq. (2-1), the moments by
-// Eq. (2-1-1)), binary32: the node function of the single-step kernel
-// (mesofd_pops, moments_of), whose EDF values are g_J(y) = ubar_J phi(y) for
-// the moving directions and, at rest, g_0(x) = phi(x) - sum_J g_J(x).  Each
-// node forms its products ubar_J phi once, when its row enters, and the
-// populations f_J(x) = sum_k a_k g_J(x + k e_J) take their neighbours' from
-// the lanes beside (DPP) or the rows' registers.  The populations of the
-// launch's last step go to memory with the moment.
+// Eq. (2-1-1)): the node function of the single-step kernel (mesofd_pops,
+// moments_of), whose EDF values are g_J(y) = ubar_J phi(y) for the moving
+// directions and, at rest, g_0 = ubar_0 phi (binary64) or phi - sum_J g_J
+// (binary32, so that a node's populations sum to phi).  Each node forms its
+// products ubar_J phi once, when its row enters, and the populations
+// f_J(x) = sum_k a_k g_J(x + k e_J) take their neighbours' from the lanes
+// beside (DPP) or the rows' registers.  The populations of the launch's last
+// step go to memory with the moment.  binary32 accumulates with fused
+// multiply-adds, binary64 with a rounded product and sum, as the single-step
+// kernel does.
+template <typename T>
 struct MesoC {
-  float ub[9];  // ubar_J, J = 1 .. Q-1 (index J - 1)
-  float a[3];   // a_k, k = -1, 0, +1
+  T ub[9];  // ubar_J, J = 0 .. Q-1
+  T a[3];   // a_k, k = -1, 0, +1
 };
 
 // AM: bit k + 1 set when a_k is not zero (the terms the scheme has)
-template <class L, int AM>
+template <class L, int AM, typename TT>
 struct MesoSeg {
-  using Params = MesoC;
-  using T = float;
-  static constexpr int kRG = 16, kNPF = 16;  // 16 wavefronts, 8 rows each
+  using T = TT;
+  using Params = MesoC<TT>;
+  static constexpr bool F32 = std::is_same<TT, float>::value;
+  // binary64 values take two registers: 8 wavefronts, 16 prefetch rows each
+  static constexpr int kRG = F32 ? 16 : 8, kNPF = 256 / kRG;
   static constexpr int kQ = L::Q;
   static constexpr int QM = L::Q - 1;  // moving directions
   static constexpr bool ak[3] = {(AM & 1) != 0, (AM & 2) != 0, (AM & 4) != 0};
-  float ub[QM], a[3];
-  __device__ __forceinline__ explicit MesoSeg(const MesoC &kc) {
+  T ub0, ub[QM], a[3];
+  __device__ __forceinline__ explicit MesoSeg(const MesoC<TT> &kc) {
+    ub0 = kc.ub[0];
 #pragma unroll
-    for (int j = 0; j < QM; ++j) ub[j] = kc.ub[j];
+    for (int j = 0; j < QM; ++j) ub[j] = kc.ub[j + 1];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       a[k] = kc.a[k];
@@ -374,11 +381,11 @@ struct MesoSeg {
     }
   }
   struct Row {  // a row's two columns: the products ubar_J phi and g_0
-    float ue[QM], uo[QM], g0e, g0o;
+    T ue[QM], uo[QM], g0e, g0o;
   };
-  __device__ __forceinline__ Row parts(float2 r) const {
+  __device__ __forceinline__ Row parts(V2<T> r) const {
     Row q;
-    float se = 0.0f, so = 0.0f;
+    T se = T(0), so = T(0);
 #pragma unroll
     for (int j = 0; j < QM; ++j) {
       q.ue[j] = ub[j] * r.x;
@@ -386,40 +393,56 @@ struct MesoSeg {
       se = se + q.ue[j];
       so = so + q.uo[j];
     }
-    q.g0e = r.x - se;
-    q.g0o = r.y - so;
+    if constexpr (F32) {
+      q.g0e = r.x - se;
+      q.g0o = r.y - so;
+    } else {
+      q.g0e = ub0 * r.x;
+      q.g0o = ub0 * r.y;
+    }
     return q;
+  }
+  // f + c g in the single-step kernel's rounding
+  __device__ __forceinline__ static T mac(T c, T g, T f) {
+    if constexpr (F32) return __builtin_fmaf(c, g, f);
+    else return c * g + f;
   }
   // f += a_k g, with g the product of direction J at column offset dx (-1,
   // 0, +1) from column 2l (ODD = 0) or 2l + 1 (ODD = 1) in row R
   template <int J, bool ODD>
-  __device__ __forceinline__ float term(float f, int k, int dx, const Row &R) const {
+  __device__ __forceinline__ T term(T f, int k, int dx, const Row &R) const {
     const int j = J - 1;
     if constexpr (!ODD) {
-      if (dx < 0) return fmac_from_left(f, R.uo[j], a[k]);
-      return __builtin_fmaf(a[k], dx == 0 ? R.ue[j] : R.uo[j], f);
+      if (dx < 0) {
+        if constexpr (F32) return fmac_from_left(f, R.uo[j], a[k]);
+        else return mac(a[k], from_left(R.uo[j]), f);
+      }
+      return mac(a[k], dx == 0 ? R.ue[j] : R.uo[j], f);
     } else {
-      if (dx > 0) return fmac_from_right(f, R.ue[j], a[k]);
-      return __builtin_fmaf(a[k], dx == 0 ? R.uo[j] : R.ue[j], f);
+      if (dx > 0) {
+        if constexpr (F32) return fmac_from_right(f, R.ue[j], a[k]);
+        else return mac(a[k], from_right(R.ue[j]), f);
+      }
+      return mac(a[k], dx == 0 ? R.uo[j] : R.ue[j], f);
     }
   }
   // the populations and the moment of row y (rows y - 1, y, y + 1: p, c, n)
   template <bool ODD>
-  __device__ __forceinline__ float node(const Row &p, const Row &c, const Row &n,
-                                        float (&fo)[L::Q]) const {
+  __device__ __forceinline__ T node(const Row &p, const Row &c, const Row &n,
+                                    T (&fo)[L::Q]) const {
     // rest direction: g_0 at x for every k
     {
-      float f = 0.0f;
-      const float g = ODD ? c.g0o : c.g0e;
+      T f = T(0);
+      const T g = ODD ? c.g0o : c.g0e;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        if (ak[k]) f = __builtin_fmaf(a[k], g, f);
+        if (ak[k]) f = mac(a[k], g, f);
       fo[0] = f;
     }
     static_for<L::Q - 1>([&](auto JI) {
       constexpr int J = decltype(JI)::value + 1;
       constexpr int ex = L::E[J][0], ey = L::E[J][1];
-      float f = 0.0f;
+      T f = T(0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (ak[k]) {
@@ -430,28 +453,28 @@ struct MesoSeg {
       }
       fo[J] = f;
     });
-    float m = 0.0f;
+    T m = T(0);
 #pragma unroll
     for (int j = 0; j < L::Q; ++j) m = m + fo[j];
     return m;
   }
   template <class Emit>
-  __device__ __forceinline__ void operator()(const float2 *lds, int lane, int ya, int yb,
-                                             float2 top, float2 bot, const Emit &emit) const {
+  __device__ __forceinline__ void operator()(const V2<T> *lds, int lane, int ya, int yb,
+                                             V2<T> top, V2<T> bot, const Emit &emit) const {
     auto row = [&](int y, const Row &p, const Row &c, const Row &n) {
-      float fe[L::Q], fo[L::Q];
-      const float me = node<false>(p, c, n, fe);
-      const float mo = node<true>(p, c, n, fo);
-      emit(y, make_float2(me, mo), fe, fo);
+      T fe[L::Q], fo[L::Q];
+      const T me = node<false>(p, c, n, fe);
+      const T mo = node<true>(p, c, n, fo);
+      emit(y, mk2<T>(me, mo), fe, fo);
     };
     Row pa = parts(top), pb = parts(lds[ya * 64 + lane]);
     int y = ya;
     // three rows per pass; each row's parts are formed just before the row
     // that needs them, so that at most four rows' are live
     for (; y + 3 < yb; y += 3) {
-      const float2 r1 = lds[(y + 1) * 64 + lane];
-      const float2 r2 = lds[(y + 2) * 64 + lane];
-      const float2 r3 = lds[(y + 3) * 64 + lane];
+      const V2<T> r1 = lds[(y + 1) * 64 + lane];
+      const V2<T> r2 = lds[(y + 2) * 64 + lane];
+      const V2<T> r3 = lds[(y + 3) * 64 + lane];
       const Row p1 = parts(r1);
       row(y, pa, pb, p1);
       const Row p2 = parts(r2);
@@ -901,30 +924,25 @@ hipError_t lane_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cu
 template <class L, typename T>
 hipError_t meso_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *mom_out,
                    T *pop_out, hipStream_t st) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (c.eq == kLCDE) {
-      const KC<float> k = make_kc<float>(c);
-      MesoC mc{};
-      for (int j = 1; j < L::Q; ++j) mc.ub[j - 1] = k.ubar[j];
-      int am = 0;
-      for (int q = 0; q < 3; ++q) {
-        mc.a[q] = k.a[q];
-        if (k.a[q] != 0.0f) am |= 1 << q;
-      }
-      switch (am) {
-        case 0: return lane_cfg<MesoSeg<L, 0>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 1: return lane_cfg<MesoSeg<L, 1>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 2: return lane_cfg<MesoSeg<L, 2>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 3: return lane_cfg<MesoSeg<L, 3>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 4: return lane_cfg<MesoSeg<L, 4>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 5: return lane_cfg<MesoSeg<L, 5>>(g, pl, cur, mom_out, pop_out, mc, st);
-        case 6: return lane_cfg<MesoSeg<L, 6>>(g, pl, cur, mom_out, pop_out, mc, st);
-        default: return lane_cfg<MesoSeg<L, 7>>(g, pl, cur, mom_out, pop_out, mc, st);
-      }
-    }
+  if (c.eq != kLCDE) return acc_eq<L, kBurgers, true, T>(c, g, pl, cur, mom_out, pop_out, st);
+  const KC<T> k = make_kc<T>(c);
+  MesoC<T> mc{};
+  for (int j = 0; j < L::Q; ++j) mc.ub[j] = k.ubar[j];
+  int am = 0;
+  for (int q = 0; q < 3; ++q) {
+    mc.a[q] = k.a[q];
+    if (k.a[q] != T(0)) am |= 1 << q;
   }
-  if (c.eq == kLCDE) return acc_eq<L, kLCDE, true, T>(c, g, pl, cur, mom_out, pop_out, st);
-  return acc_eq<L, kBurgers, true, T>(c, g, pl, cur, mom_out, pop_out, st);
+  switch (am) {
+    case 0: return lane_cfg<MesoSeg<L, 0, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 1: return lane_cfg<MesoSeg<L, 1, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 2: return lane_cfg<MesoSeg<L, 2, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 3: return lane_cfg<MesoSeg<L, 3, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 4: return lane_cfg<MesoSeg<L, 4, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 5: return lane_cfg<MesoSeg<L, 5, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    case 6: return lane_cfg<MesoSeg<L, 6, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+    default: return lane_cfg<MesoSeg<L, 7, T>>(g, pl, cur, mom_out, pop_out, mc, st);
+  }
 }
 
 template <class Seg>
