@@ -35,8 +35,9 @@
  * Parity status: every function below is pinned by a CPU test (Fourier
  * symbol, FTCS identity, textbook LBGK equilibrium, EDF moment identities,
  * exact rational brute force, conservation, convergence to analytic
- * solutions).  The paper's Table 2/3 error values are NOT reproduced and are
- * not used as pins.
+ * solutions; the source term by its Fourier symbol, the literal form,
+ * conservation and second-order convergence on Example 1).  The paper's
+ * Table 1/2/3 error values are NOT reproduced and are not used as pins.
  */
 #include <math.h>
 #include <stdint.h>
@@ -699,6 +700,120 @@ int orc_theta_step(const orc_params *P, const double *cur, double *out, double *
     }
     if (P->theta_iters == 0) memcpy(out, cur, sizeof(double) * N);
     free(rhs);
+    return 0;
+}
+
+/* ------------------------------------------------------------ source term */
+
+/*
+ * Source of the scheme, the b terms of Eq. (2-1) / (3layerMMFD-1):
+ *   Delta t sum_j sum_k [ b_k F_j(x + k e_j, t) + bh_k F_j(x + k e_j, t - dt) ]
+ * with F_j of Eq. (SourceF) for the NCDE: F_j = w_j (S + c_j.M_1F / c_s^2),
+ * M_1F = v S for a constant vector v, i.e. in lattice units
+ *   F_j(y) = w_j (S(y) + (e_j.vh / d0) S(y)),   vh = v dt / dx.
+ * S is given at both time levels (the caller evaluates it); its time levels
+ * are independent of the scheme's levels of phi.
+ */
+typedef struct {
+    double b[3], bh[3];   /* k = -1, 0, +1 at level t and t - dt            */
+    double v[3];          /* M_1F = v S (physical velocity)                 */
+} orc_source;
+
+/* MMFD form: Eq. (2-2-1) with its b terms,
+ *   dt [ B0 S(t) + Bh0 S(t-dt) ]
+ *   + dt sum_p [ b+ D2_p F+(t) + b- D1_p F-(t) + bh+ D2_p F+(t-dt) + bh- D1_p F-(t-dt) ]
+ * with B0 = sum_k b_k, b+- = b_1 +- b_-1, the pair parts F+_p = w_p S and
+ * F-_p = (w_p / d0)(e_p.vh) S (the even / odd split of Eq. (2-5)), every pair
+ * counted once for both of its directions. */
+static void source_mmfd(const orc_params *P, const orc_ctx *c, const orc_source *Q,
+                        const double *St, const double *Sm, double *out)
+{
+    double vh[3];
+    for (int a = 0; a < 3; ++a) vh[a] = Q->v[a] * P->dt / P->dx;
+    const int np = c->L.npair;
+    double wp[ORC_MAXP], wm[ORC_MAXP];
+    for (int p = 0; p < np; ++p) {
+        int j = c->L.pair[p];
+        wp[p] = c->L.w[j];
+        wm[p] = c->w1[j] * edot(c, j, vh);
+    }
+    const double B0 = Q->b[0] + Q->b[1] + Q->b[2];
+    const double Bh0 = Q->bh[0] + Q->bh[1] + Q->bh[2];
+    const double bp = Q->b[2] + Q->b[0], bm = Q->b[2] - Q->b[0];
+    const double bhp = Q->bh[2] + Q->bh[0], bhm = Q->bh[2] - Q->bh[0];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c->n[2]; ++z)
+        for (int64_t y = 0; y < c->n[1]; ++y)
+            for (int64_t x = 0; x < c->n[0]; ++x) {
+                int64_t i = (z * c->n[1] + y) * c->n[0] + x;
+                double sv = B0 * St[i] + Bh0 * Sm[i];
+                double sa = 0.0;
+                for (int lev = 0; lev < 2; ++lev) {
+                    const double *S = lev == 0 ? St : Sm;
+                    const double cp = lev == 0 ? bp : bhp, cm = lev == 0 ? bm : bhm;
+                    for (int p = 0; p < np; ++p) {
+                        int j = c->L.pair[p];
+                        int64_t ip = nb(c, x, y, z, j, 1), im = nb(c, x, y, z, j, -1);
+                        double d2v = (wp[p] * S[ip] - 2.0 * (wp[p] * S[i])) + wp[p] * S[im];
+                        double d1v = wm[p] * S[ip] - wm[p] * S[im];
+                        sa = sa + cp * d2v;
+                        sa = sa + cm * d1v;
+                    }
+                }
+                out[i] = out[i] + P->dt * (sv + sa);
+            }
+}
+
+/* one MMFD step of the linear CDE with the source: the step of
+ * orc_mmfd_step, then its source term added */
+int orc_mmfd_source_step(const orc_params *P, const orc_source *Q, const double *cur,
+                         const double *prev, const double *St, const double *Sm, double *out)
+{
+    if (P->eq != ORC_LCDE) return -5;
+    int rc = orc_mmfd_step(P, cur, prev, out);
+    if (rc) return rc;
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+    source_mmfd(P, &c, Q, St, Sm, out);
+    return 0;
+}
+
+/* the literal form: orc_literal_step, then
+ *   dt sum_j sum_k [ b_k F_j(x + k e_j, t) + bh_k F_j(x + k e_j, t - dt) ]
+ * with F_j evaluated direction by direction */
+int orc_literal_source_step(const orc_params *P, const orc_source *Q, const double *cur,
+                            const double *prev, const double *St, const double *Sm, double *out)
+{
+    if (P->eq != ORC_LCDE) return -5;
+    int rc = orc_literal_step(P, cur, prev, out);
+    if (rc) return rc;
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+    double vh[3];
+    for (int a = 0; a < 3; ++a) vh[a] = Q->v[a] * P->dt / P->dx;
+    const int b = c.L.b;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                double s = 0.0;
+                for (int j = 0; j < b; ++j) {
+                    double ev = edot(&c, j, vh) * c.inv_d0;
+                    double fj = 0.0;
+                    for (int lev = 0; lev < 2; ++lev) {
+                        const double *S = lev == 0 ? St : Sm;
+                        const double *bk = lev == 0 ? Q->b : Q->bh;
+                        for (int k = -1; k <= 1; ++k) {
+                            if (bk[k + 1] == 0.0) continue;
+                            double Sy = S[nb(&c, x, y, z, j, k)];
+                            fj = fj + bk[k + 1] * (c.L.w[j] * (Sy + ev * Sy));
+                        }
+                    }
+                    s = s + fj;
+                }
+                out[i] = out[i] + P->dt * s;
+            }
     return 0;
 }
 

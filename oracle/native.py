@@ -50,6 +50,10 @@ class Params(C.Structure):
     ]
 
 
+class Source(C.Structure):
+    _fields_ = [("b", C.c_double * 3), ("bh", C.c_double * 3), ("v", C.c_double * 3)]
+
+
 _lib = None
 
 
@@ -69,6 +73,8 @@ def lib():
             ("orc_mesofd_step", [P, D, D, D, D]),
             ("orc_theta_step", [P, D, D, D]),
             ("orc_tables", [P, D, D, D]),
+            ("orc_mmfd_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
+            ("orc_literal_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -147,7 +153,32 @@ def _check(rc, name):
         raise RuntimeError("%s failed (%d)" % (name, rc))
 
 
-def mmfd_step(spec, cur, prev=None):
+def make_source(src: dict) -> Source:
+    """src keys: b, bh (k = -1, 0, 1 at levels t and t - dt), v (M_1F = v S)."""
+    Q = Source()
+    Q.b = _triple([float(x) for x in src.get("b", (0.0, 0.0, 0.0))])
+    Q.bh = _triple([float(x) for x in src.get("bh", (0.0, 0.0, 0.0))])
+    Q.v = _triple([float(x) for x in src.get("v", ())])
+    return Q
+
+
+def _source_step(fn, name, spec, cur, prev, src):
+    P = make_params(spec)
+    Q = make_source(src)
+    out = np.empty_like(cur)
+    prev = cur if prev is None else prev
+    St = np.ascontiguousarray(src["S_t"], dtype=np.float64)
+    Sm = np.ascontiguousarray(src["S_m"], dtype=np.float64)
+    assert St.size == cur.size and Sm.size == cur.size
+    _check(fn(C.byref(P), C.byref(Q), _ptr(cur), _ptr(prev), _ptr(St), _ptr(Sm), _ptr(out)), name)
+    return out
+
+
+def mmfd_step(spec, cur, prev=None, src=None):
+    """One MMFD step; src (linear CDE only): dict(b, bh, v, S_t, S_m) adds the
+    scheme's source term with S given at levels t and t - dt."""
+    if src is not None:
+        return _source_step(lib().orc_mmfd_source_step, "mmfd_source_step", spec, cur, prev, src)
     P = make_params(spec)
     out = np.empty_like(cur)
     prev = cur if prev is None else prev
@@ -155,7 +186,10 @@ def mmfd_step(spec, cur, prev=None):
     return out
 
 
-def literal_step(spec, cur, prev=None):
+def literal_step(spec, cur, prev=None, src=None):
+    if src is not None:
+        return _source_step(lib().orc_literal_source_step, "literal_source_step", spec, cur, prev,
+                            src)
     P = make_params(spec)
     out = np.empty_like(cur)
     prev = cur if prev is None else prev
