@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    p.add_argument("--sections", default="variants,theta,big,c1,nse,burgers,batched,serving",
+    p.add_argument("--sections", default="variants,theta,big,c1,nse,source,burgers,batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
@@ -238,6 +238,42 @@ def bench_c1(M, torch, I, stream):
         res[form + "_fp64_us_per_1000_steps"] = round(ms * 1e3, 1)
         s.close()
     return res
+
+
+def bench_source(M, torch, I, stream, steps=500):
+    """Example 1 (linear CDE with the source R, three-level Case 2 with the
+    source coefficients b_-1 = 3/2, bh_-1 = -1/2) on a 2048^2 grid, FP64 and
+    FP32: GLUPS of step + source launches, the FP32 error against FP64 and
+    the FP64 run's GRE against the exact solution."""
+    ex = I.example1_source_2d(n=N_SIDE)
+    a, ah = (7 / 8, 1 / 4, -1 / 8), (1 / 8, -1 / 4, 1 / 8)
+    out, finals = {}, {}
+    for prec in ("fp64", "fp32"):
+        s = M.Solver("D2Q9", ex["n"], ex["dx"], prec, "mmfd")
+        s.set_equation("lcde", u=ex["u"], K=ex["K"], lambda_bar=1)
+        s.set_scheme("three_level", a, ah, dt=ex["dt"])
+        s.set_stream(stream.cuda_stream)
+
+        def start():
+            s.set_state(ex["phi0"].astype(s.dtype))
+            s.set_state(ex["phim"].astype(s.dtype), level=1)
+            s.set_source(ex["G"], ex["lam"], (1.5, 0.0, 0.0), (-0.5, 0.0, 0.0), ex["u"])
+        start()
+        s.step(20)
+        start()
+        ms = timed(torch, lambda: s.step(steps))
+        finals[prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = ex["n"][0] * ex["n"][1] * steps / (ms * 1e-3) / 1e9
+        bpl = 4 * (8 if prec == "fp64" else 4)  # read t, t - dt and G; write t + dt
+        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                         frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl)
+    exact = ex["exact"](steps * ex["dt"])
+    out.update(steps=steps, scheme="three-level (7/8, 1/4, -1/8 | 1/8, -1/4, 1/8), b_-1 = 3/2, bh_-1 = -1/2",
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
+                                         / np.linalg.norm(finals["fp64"])),
+               fp64_gre_vs_exact=float(np.abs(finals["fp64"] - exact).sum() / np.abs(exact).sum()))
+    return out
 
 
 def _nse_solver(M, lat, c, precision, stream):
@@ -512,6 +548,9 @@ def main():
     if "nse" in sections:
         log("NSE")
         extra["nse"] = bench_nse(M, torch, I, stream)
+    if "source" in sections:
+        log("source")
+        extra["source_example1_2048"] = bench_source(M, torch, I, stream)
     if "burgers" in sections:
         log("burgers 2048^2")
         extra["burgers_2048_mmfd_fp32"] = bench_burgers_single(M, torch, I, stream)

@@ -180,6 +180,30 @@ int mfd_get_state(mfd_solver *s, int level, void *dst, int64_t bytes, int on_dev
 /* Enqueue nsteps >= 0 time steps; asynchronous with respect to the host. */
 int mfd_step(mfd_solver *s, int64_t nsteps);
 
+/* Source term of the linear CDE (MMFD form, explicit two- or three-level
+ * scheme): the b terms of Eq. (2-1) / (3layerMMFD-1) with the source
+ * distribution F_j of Eq. (SourceF) for the NCDE, F_j = w_j (S + c_j.M_1F /
+ * c_s^2), taken in the central-difference form of Eq. (2-2-1):
+ *   S(x, t)  = exp(lambda t) G(x), t = n dt with n the steps taken since the
+ *              last level-0 mfd_set_state (the step from t to t + dt reads S
+ *              at t and at t - dt, whatever the scheme's levels of phi);
+ *   M_1F     = v S, v[0..dim-1] a constant vector in physical units;
+ *   b[3]     = b_k at level t, bh[3] = b_k at level t - dt, k = -1, 0, +1
+ *              (Example 1 of the paper: b = (3/2, 0, 0), bh = (-1/2, 0, 0)).
+ * G holds count = nx ny nz binary64 values, x fastest (host memory, or
+ * device memory when on_device); it is copied (converted to the solver's
+ * precision) into a device buffer the solver owns until mfd_clear_source or
+ * mfd_destroy.  Each step is then a single-step launch followed by the source
+ * launch: temporal blocking and the resident 1D paths are not used while a
+ * source is set.  Returns MFD_E_ORDER before the scheme is set,
+ * MFD_E_UNSUPPORTED for the MesoFD form, another equation or the theta scheme,
+ * MFD_E_ARG for a null G, a wrong count or non-finite values, MFD_E_OOM. */
+int mfd_set_source(mfd_solver *s, const double *G, int64_t count, int on_device, double lambda,
+                   const double b[3], const double bh[3], const double v[3]);
+
+/* Remove the source term (frees its buffer). */
+int mfd_clear_source(mfd_solver *s);
+
 /* Wait for all work the solver has enqueued. */
 int mfd_synchronize(mfd_solver *s);
 
@@ -254,7 +278,7 @@ int mfd_batch_set_graph(mfd_batch *b, int use_graph);
 
 /* Add a configured solver with its state set, to be advanced nsteps >= 0 per
  * run.  *slot receives its index.  MFD_E_UNSUPPORTED for solvers that are not
- * 2D explicit MMFD. */
+ * 2D explicit MMFD or that have a source term. */
 int mfd_batch_add(mfd_batch *b, mfd_solver *s, int64_t nsteps, int32_t *slot);
 
 /* Remove every solver. */

@@ -76,6 +76,24 @@ def gaussian_hill_exact(n, t, sigma=0.05, K=C2_K, u=C2_U, images=1):
     return out * sigma * sigma / math.sqrt(np.linalg.det(S))
 
 
+def example1_source_2d(n=2048, kappa=0.01, u=(0.1, 0.1)):
+    """Example 1 of the paper (isotropic CDE with a source), D2Q9, periodic
+    [0,2)^2 with n nodes a side: dx = 2/n, the example's diffusive scaling
+    N_t = 0.06 N_x^2 (N_x = 1/dx) read as dt = dx^2 / 0.06, u = (0.1, 0.1),
+    kappa = 0.01.  The source is R = exp(lam t) G(x, y) with
+    lam = 1 - 2 pi^2 kappa, G = sin(pi (x + y)) + pi (u_x + u_y) cos(pi (x + y));
+    the exact solution is exp(lam t) sin(pi (x + y)).  Returns the grid, the
+    physical parameters, G and the exact fields at t = 0 and t = -dt."""
+    x, dx = _grid(n, 2.0)
+    dt = dx * dx / 0.06
+    X, Y = np.meshgrid(x, x)
+    lam = 1.0 - 2.0 * math.pi ** 2 * kappa
+    G = (np.sin(math.pi * (X + Y)) + math.pi * (u[0] + u[1]) * np.cos(math.pi * (X + Y))).ravel()
+    exact = lambda t: math.exp(lam * t) * np.sin(math.pi * (X + Y)).ravel()
+    return dict(n=(n, n), dx=dx, dt=dt, u=tuple(u), K=[[kappa, 0.0], [0.0, kappa]], lam=lam,
+                G=G, phi0=exact(0.0), phim=exact(-dt), exact=exact)
+
+
 def random_linear_case(dim, seed, n=None):
     """Random anisotropic linear CDE on a small periodic grid (for pins)."""
     rng = np.random.default_rng(seed)

@@ -35,6 +35,7 @@ SOURCES = [
     "kernels_mesofd.hip",
     "kernels_misc.hip",
     "kernels_batch.hip",
+    "kernels_source.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

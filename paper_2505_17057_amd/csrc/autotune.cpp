@@ -51,13 +51,13 @@ int default_h(const Solver &s, int tb) {
 }  // namespace
 
 bool Solver::plan_supported(const TbPlan &p) const {
-  if (cfg.kind == MFD_THETA) return false;
+  if (cfg.kind == MFD_THETA || src_on) return false;
   if (grid.form == MFD_MESOFD) return mesofd_tb_supported(consts, G, p, (int)elem());
   return tb_supported(consts, G, p, (int)elem());
 }
 
 TbPlan Solver::effective_plan() const {
-  if (!tunable(*this)) return TbPlan{1, 0};
+  if (!tunable(*this) || src_on) return TbPlan{1, 0};
   if (tb == 1) return TbPlan{1, 0};
   if (tb > 1) {
     if (tuned.tb == tb) return tuned;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -104,6 +105,31 @@ template <typename T>
 int Solver::step_t(int64_t nsteps) {
   T *B[kNumBuf];
   for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  if (src_on) {
+    // with a source term: one launch per step (3D: the step, then the source)
+    if (!source_supported())
+      return fail(MFD_E_UNSUPPORTED, "the source term needs the MMFD form of the linear CDE "
+                                     "with an explicit scheme");
+    src.dt = cfg.dt;
+    src.dx = grid.dx;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      T *out = consts.three ? B[io] : B[ip];
+      hipError_t e = launch_mmfd_source_step<T>(consts, G, src, steps_done, B[ic], B[ip], out,
+                                                (const T *)d_src, stream);
+      if (e != hipSuccess) return hip(e, "source step launch");
+      if (!consts.three) {
+        std::swap(ic, ip);
+      } else {
+        const int t = ip;
+        ip = ic;
+        ic = io;
+        io = t;
+      }
+      ++steps_done;
+    }
+    prev_gap = 1;
+    return MFD_OK;
+  }
   if (cfg.kind != MFD_THETA && wave1d_applies(consts, G) && nsteps > 1) {
     // the whole run in one wavefront's registers; levels stay in place
     const bool meso = grid.form == MFD_MESOFD;
@@ -226,6 +252,10 @@ int Solver::step_t(int64_t nsteps) {
   return MFD_OK;
 }
 
+bool Solver::source_supported() const {
+  return grid.form == MFD_MMFD && cfg.kind != MFD_THETA && consts.eq == kLCDE;
+}
+
 int Solver::step(int64_t nsteps) {
   if (sticky) return fail(MFD_E_HIP, "solver is in a failed HIP state: %s", err.c_str());
   if (nsteps < 0) return fail(MFD_E_ARG, "nsteps < 0");
@@ -267,8 +297,9 @@ extern "C" int mfd_create(mfd_solver **out, const mfd_grid *g) {
 extern "C" int mfd_destroy(mfd_solver *h) {
   if (!h) return MFD_OK;
   Solver *s = reinterpret_cast<Solver *>(h);
-  if (s->buf[0]) (void)hipStreamSynchronize(s->stream);
+  if (s->buf[0] || s->d_src) (void)hipStreamSynchronize(s->stream);
   s->release();
+  if (s->d_src) (void)hipFree(s->d_src);
   delete s;
   return MFD_OK;
 }
@@ -603,6 +634,80 @@ extern "C" int mfd_launch_plan(const mfd_solver *h, int32_t *tb_depth, int32_t *
   if (tb_depth) *tb_depth = p.tb;
   if (window_rows) *window_rows = p.tb > 1 ? p.h : 0;
   if (window_cols) *window_cols = p.tb > 1 ? p.w : 0;
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_source(mfd_solver *h, const double *G, int64_t count, int on_device,
+                              double lambda, const double b[3], const double bh[3],
+                              const double v[3]) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->configured) return s->fail(MFD_E_ORDER, "set the scheme first");
+  if (!s->source_supported())
+    return s->fail(MFD_E_UNSUPPORTED, "the source term needs the MMFD form of the linear CDE "
+                                      "with an explicit scheme");
+  if (!G || !b || !bh || !v) return s->fail(MFD_E_ARG, "null argument");
+  if (count != s->G.N)
+    return s->fail(MFD_E_ARG, "expected %lld source values, got %lld", (long long)s->G.N,
+                   (long long)count);
+  if (!std::isfinite(lambda)) return s->fail(MFD_E_ARG, "lambda is not finite");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(b[k]) || !std::isfinite(bh[k]) || !std::isfinite(v[k]))
+      return s->fail(MFD_E_ARG, "non-finite coefficient");
+  const int64_t N = s->G.N;
+  std::vector<double> host;
+  const double *hg = G;
+  if (on_device) {
+    host.resize((size_t)N);
+    int rc = s->hip(hipMemcpy(host.data(), G, (size_t)N * 8, hipMemcpyDeviceToHost),
+                    "hipMemcpy (source)");
+    if (rc) return rc;
+    hg = host.data();
+  }
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(hg[i])) return s->fail(MFD_E_ARG, "source value %lld is not finite", (long long)i);
+  const int64_t es = s->elem();
+  if (s->d_src) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->d_src);
+    s->d_src = nullptr;
+    s->src_on = false;
+  }
+  if (hipMalloc(&s->d_src, (size_t)(N * es)) != hipSuccess) {
+    (void)hipGetLastError();
+    s->d_src = nullptr;
+    return s->fail(MFD_E_OOM, "no device memory for the source field");
+  }
+  int rc;
+  if (es == 8) {
+    rc = s->hip(hipMemcpy(s->d_src, hg, (size_t)N * 8, hipMemcpyHostToDevice), "hipMemcpy (source)");
+  } else {
+    std::vector<float> f((size_t)N);
+    for (int64_t i = 0; i < N; ++i) f[(size_t)i] = (float)hg[i];
+    rc = s->hip(hipMemcpy(s->d_src, f.data(), (size_t)N * 4, hipMemcpyHostToDevice),
+                "hipMemcpy (source)");
+  }
+  if (rc) return rc;
+  for (int k = 0; k < 3; ++k) {
+    s->src.b[k] = b[k];
+    s->src.bh[k] = bh[k];
+    s->src.v[k] = k < s->grid.dim ? v[k] : 0.0;
+  }
+  s->src.lambda = lambda;
+  s->src_on = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_clear_source(mfd_solver *h) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->d_src) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->d_src);
+  }
+  s->d_src = nullptr;
+  s->src_on = false;
   return MFD_OK;
 }
 

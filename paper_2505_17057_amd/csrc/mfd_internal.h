@@ -101,6 +101,19 @@ template <typename T>
 hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
                             int tb_depth, hipStream_t st);
 
+// source term of the linear CDE (kernels_source.hip): S(x, t) = exp(lambda t)
+// G(x), M_1F = v S, coefficients b (level t) and bh (level t - dt)
+struct SourceSpec {
+  double b[3], bh[3], v[3];
+  double lambda, dt, dx;
+};
+// one MMFD step from t = n dt with the source term: level t (cur), t - dt
+// (prev, three-level) in, t + dt out; G the source field
+template <typename T>
+hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n,
+                                   const T *cur, const T *prev, T *out, const T *G,
+                                   hipStream_t st);
+
 // one NSE step on D3Q19 without an older-level stencil, pair parts staged
 // once per node (kernels_nse3d.hip)
 template <typename T>

@@ -44,6 +44,10 @@ struct Solver {
   int prev_gap = 1;  // steps between the current and the held previous level
   int tb = 0;           // temporal-blocking depth requested (0 = automatic)
   TbPlan tuned{0, 0};   // plan chosen by the autotuner (tb = 0: not tuned)
+  // source term (linear CDE): G in the solver's precision, on the device
+  bool src_on = false;
+  SourceSpec src{};
+  void *d_src = nullptr;
   std::string err;
 
   int fail(int code, const char *fmt, ...);
@@ -59,6 +63,7 @@ struct Solver {
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
   int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
   int step(int64_t nsteps);
+  bool source_supported() const;
   TbPlan effective_plan() const;
   bool plan_supported(const TbPlan &p) const;  // the blocked kernel of this form can run p
   int autotune(int32_t *chosen);

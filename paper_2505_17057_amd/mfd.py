@@ -99,6 +99,8 @@ _SIGS = {
     "mfd_autotune": ([_H, C.POINTER(C.c_int32)], C.c_int),
     "mfd_set_blocking": ([_H, C.c_int32], C.c_int),
     "mfd_set_plan": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "mfd_set_source": ([_H, _PD, C.c_int64, C.c_int, C.c_double, _PD, _PD, _PD], C.c_int),
+    "mfd_clear_source": ([_H], C.c_int),
     "mfd_launch_plan": ([_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "mfd_coeff_moments": ([_PD, _PD, _PD], C.c_int),
     "mfd_coeffs_from_constraints": ([C.c_double] * 5 + [_PD, _PD], C.c_int),
@@ -299,6 +301,19 @@ class Solver:
     def set_plan(self, tb_depth, window_rows=0, window_cols=64):
         return self.check(lib.mfd_set_plan(self.h, int(tb_depth), int(window_rows), int(window_cols)),
                           "mfd_set_plan")
+
+    def set_source(self, G, lam=0.0, b=(0.0, 1.0, 0.0), bh=(0.0, 0.0, 0.0), v=()):
+        """Source term of the linear CDE: S(x, t) = exp(lam t) G(x) (t counted
+        from the last set_state), coefficients b (level t) and bh (level
+        t - dt) for k = -1, 0, 1, source flux M_1F = v S.  G: float64 array of
+        the grid's node count (host)."""
+        g = np.ascontiguousarray(np.asarray(G, dtype=np.float64).ravel())
+        vv = list(v) + [0.0] * (3 - len(v))
+        return self.check(lib.mfd_set_source(self.h, g.ctypes.data_as(_PD), g.size, 0, float(lam),
+                                             _d3(b), _d3(bh), _d3(vv)), "mfd_set_source")
+
+    def clear_source(self):
+        return self.check(lib.mfd_clear_source(self.h), "mfd_clear_source")
 
     def launch_plan(self):
         """(time steps per launch, LDS window rows, LDS window columns)."""

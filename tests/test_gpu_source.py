@@ -1,0 +1,148 @@
+"""GPU: the source term of the linear CDE step (the b terms of Eq. (2-1) /
+(3layerMMFD-1), F_j of Eq. (SourceF) with M_1F = v S, S = exp(lambda t) G).
+
+* binary64 equals the oracle value for value on every lattice, for the
+  two-level and three-level schemes of Example 1 and random coefficients, on
+  ragged grids, with the steps split over several calls (the time of a step
+  counts from the last set_state);
+* binary32 stays within 1e-5 (relative L2) of the binary64 oracle;
+* a launch plan set before the source is not used while it is set;
+* the MesoFD form, other equations, the theta scheme and batches refuse it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import native as O
+from parity_util import make_solver, oracle_spec, rand_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+K2 = [[0.02, 0.005], [0.005, 0.01]]
+SCHEMES = {
+    "srt": dict(a=(1.0, 0.0, 0.0)),
+    "ex1-case2": dict(kind="three_level", a=(7 / 8, 1 / 4, -1 / 8), ah=(1 / 8, -1 / 4, 1 / 8)),
+    "ex1-case3": dict(kind="three_level", a=(7 / 8, 0.0, 1 / 8), ah=(1 / 8, 0.0, -1 / 8)),
+}
+GRIDS = {
+    "D1Q3": dict(n=(301,), u=(0.3,), K=[[0.02]], lambda_bar=1),
+    "D2Q5": dict(n=(150, 77), u=(0.3, -0.2), K=[[0.02, 0.0], [0.0, 0.02]], lambda_bar=0),
+    "D2Q9": dict(n=(150, 77), u=(0.3, -0.2), K=K2, lambda_bar=1),
+    "D3Q19": dict(n=(20, 12, 9), u=(0.3, -0.2, 0.1), K=[[0.02, 0.0, 0.0], [0.0, 0.02, 0.0], [0.0, 0.0, 0.02]],
+                  lambda_bar=1),
+}
+COEFS = {
+    "example1": dict(b=(1.5, 0.0, 0.0), bh=(-0.5, 0.0, 0.0)),
+    "random": dict(b=(0.3, 0.5, 0.2), bh=(0.1, -0.2, 0.05)),
+}
+
+
+def _case(lat, scheme):
+    return dict(lattice=lat, eq="lcde", dx=0.05, dt=0.01, **GRIDS[lat], **SCHEMES[scheme])
+
+
+def _oracle(case, cur, prev, steps, G, lam, coef, v):
+    spec = oracle_spec(case)
+    three = spec["levels"] == 3
+    dt = case["dt"]
+    for s in range(steps):
+        src = dict(coef, v=v, S_t=math.exp(lam * (s * dt)) * G,
+                   S_m=math.exp(lam * ((s - 1) * dt)) * G)
+        nxt = O.mmfd_step(spec, cur, prev if three else None, src)
+        prev, cur = cur, nxt
+    return cur
+
+
+def _gpu(M, case, cur, prev, chunks, G, lam, coef, v, precision="fp64", plan=None):
+    s = make_solver(M, case, precision)
+    dt = np.float64 if precision == "fp64" else np.float32
+    if plan:
+        s.set_plan(*plan)
+    s.set_state(cur.astype(dt))
+    if case.get("kind") == "three_level":
+        s.set_state(prev.astype(dt), level=1)
+    s.set_source(G, lam, coef["b"], coef["bh"], v)
+    plan_seen = s.launch_plan()
+    for k in chunks:
+        s.step(k)
+    out = s.get_state().astype(np.float64)
+    s.close()
+    return out, plan_seen
+
+
+@pytest.mark.parametrize("lat", list(GRIDS))
+@pytest.mark.parametrize("scheme", list(SCHEMES))
+@pytest.mark.parametrize("coef", list(COEFS))
+def test_source_fp64_bitwise(M, lat, scheme, coef):
+    case = _case(lat, scheme)
+    print("case", lat, scheme, coef, flush=True)
+    rng = np.random.default_rng(41)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    v = tuple(rng.uniform(-0.5, 0.5, len(case["n"])))
+    want = _oracle(case, cur, prev, 7, G, -0.7, COEFS[coef], v)
+    got, _ = _gpu(M, case, cur, prev, (3, 4), G, -0.7, COEFS[coef], v)
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+@pytest.mark.parametrize("scheme", list(SCHEMES))
+def test_source_fp32_tolerance(M, scheme):
+    case = _case("D2Q9", scheme)
+    rng = np.random.default_rng(42)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    want = _oracle(case, cur, prev, 40, G, 0.4, COEFS["example1"], (0.2, 0.1))
+    got, _ = _gpu(M, case, cur, prev, (40,), G, 0.4, COEFS["example1"], (0.2, 0.1), "fp32")
+    err = rel_l2(got, want)
+    print("fp32 rel L2", scheme, err)
+    assert err < 1e-5
+
+
+def test_source_overrides_plan(M):
+    case = _case("D2Q9", "srt")
+    rng = np.random.default_rng(43)
+    cur = rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    want = _oracle(case, cur, cur, 9, G, -0.2, COEFS["example1"], (0.1, 0.3))
+    got, plan = _gpu(M, case, cur, cur, (9,), G, -0.2, COEFS["example1"], (0.1, 0.3),
+                     plan=(4, 40, 128))
+    assert plan == (1, 0, 0)
+    assert np.array_equal(got, want)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(4, 40, 128)
+    s.set_state(cur)
+    s.set_source(G)
+    assert s.launch_plan() == (1, 0, 0)
+    with pytest.raises(M.MfdError):
+        s.set_plan(4, 40, 128)
+    s.clear_source()
+    assert s.launch_plan() == (4, 40, 128)
+    s.close()
+
+
+def test_source_rejections(M):
+    rng = np.random.default_rng(44)
+    base = _case("D2Q9", "srt")
+    G = rng.standard_normal(int(np.prod(base["n"])))
+    for case in (dict(base, form="mesofd"),
+                 dict(lattice="D2Q9", eq="burgers", n=base["n"], dx=0.05, dt=0.001, a=(1.0, 0.0, 0.0)),
+                 dict(base, kind="theta", theta=0.5, theta_iters=2)):
+        s = make_solver(M, case, "fp64")
+        with pytest.raises(M.MfdError):
+            s.set_source(G)
+        s.close()
+    s = make_solver(M, base, "fp64")
+    with pytest.raises(M.MfdError):
+        s.set_source(G[:-1])
+    bad = G.copy()
+    bad[5] = np.nan
+    with pytest.raises(M.MfdError):
+        s.set_source(bad)
+    s.set_state(rand_state(base, rng))
+    s.set_source(G)
+    b = M.Batch()
+    with pytest.raises(M.MfdError):
+        b.add(s, 10)
+    b.close()
+    s.close()
