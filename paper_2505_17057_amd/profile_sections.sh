@@ -9,7 +9,7 @@ R=$(pwd)
 O=$R/gpurun_out
 mkdir -p "$O"
 export TMPDIR=/tmp
-for sec in ${@:-variants nse burgers batched serving}; do
+for sec in ${@:-variants theta big c1 nse source burgers batched serving}; do
   echo "profile: $sec"
   CMD="rocprofv3 --kernel-trace --stats -d /tmp/prof_$sec -o p -- python3 bench.py --steps 1 --warmup 0 --no-cpu --sections $sec"
   (cd /tmp && timeout -k 10 600 rocprofv3 --kernel-trace --stats -d /tmp/prof_$sec -o p -- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --sections $sec > "$O/prof_$sec.txt" 2>&1) || exit 2
