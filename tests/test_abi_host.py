@@ -141,6 +141,39 @@ def test_argument_validation(M):
     s.close()
 
 
+def test_source_argument_validation(M):
+    """mfd_set_source checks order, form, equation, scheme kind, count and
+    finiteness before it touches the device."""
+    G = np.zeros(64)
+    s = M.Solver("D2Q9", (8, 8), 1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(G)  # not configured
+    assert e.value.code == M.MFD_E_ORDER
+    s.set_equation("lcde", u=(0.01, 0.0), K=[[0.1, 0.0], [0.0, 0.1]])
+    s.set_scheme("two_level", (1, 0, 0), dt=1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(G[:-1])
+    assert e.value.code == M.MFD_E_ARG
+    bad = G.copy()
+    bad[3] = np.inf
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(bad)
+    assert e.value.code == M.MFD_E_ARG
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(G, lam=float("nan"))
+    assert e.value.code == M.MFD_E_ARG
+    s.close()
+    for form, eq, kind in (("mesofd", "lcde", "two_level"), ("mmfd", "burgers", "two_level"),
+                           ("mmfd", "lcde", "theta")):
+        s = M.Solver("D2Q9", (8, 8), 1.0, "fp64", form)
+        s.set_equation(eq, u=(0.01, 0.0), K=[[0.1, 0.0], [0.0, 0.1]])
+        s.set_scheme(kind, (1, 0, 0), theta=0.5, theta_iters=2, dt=1.0)
+        with pytest.raises(M.MfdError) as e:
+            s.set_source(G)
+        assert e.value.code == M.MFD_E_UNSUPPORTED
+        s.close()
+
+
 def test_stability_warning(M):
     """Theorem 1 for C1-like D1Q3 schemes: r = 0.25 proven, r = 0.55 not."""
     for r, want in ((0.25, 0), (0.55, M.MFD_W_STABILITY_UNPROVEN)):
