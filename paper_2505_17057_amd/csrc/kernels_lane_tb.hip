@@ -126,8 +126,9 @@ __device__ __forceinline__ double from_left(double v) { return shift64<0x138>(v)
 // interior straight to global memory.
 //
 // Workgroups are persistent: workgroup b takes the tiles of the virtual
-// blocks b, b + G, b + 2G, ... (G = gridDim.x, a multiple of 8, so that every
-// virtual block of a workgroup maps to tiles of its own XCD).  While a tile's
+// blocks b, b + G, b + 2G, ... (G = gridDim.x; a multiple of 8 when there are
+// more tiles than workgroups, so that every virtual block of a workgroup maps
+// to tiles of its own XCD, else one workgroup per tile).  While a tile's
 // steps run, the next tile's window is loaded into registers, and it goes to
 // the buffer after the last step.
 template <int P>
@@ -861,12 +862,13 @@ hipError_t lane_cfg(const Grid &g, const TbPlan &pl, const typename Seg::T *cur,
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  // persistent grid: the resident workgroups, a multiple of 8 (XCDs)
+  // persistent grid: the resident workgroups (a multiple of 8, the XCDs),
+  // or one workgroup per tile when the tiles fit in one round
   const int ntiles = tx * ty;
   int grid = lane_slots((const void *)fn, 64 * RG, lds);
   if (grid <= 0) return hipErrorInvalidValue;
-  grid = grid < ntiles ? grid : ntiles;
-  if (grid >= 8) grid &= ~7;
+  if (ntiles <= grid) grid = ntiles;  // one tile per workgroup: no walk
+  else if (grid >= 8) grid &= ~7;     // the walk v, v + G, ... stays on one XCD
   hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st, cur, out, pop, nx, ny, pl.h, pl.tb,
                      tx, ntiles, prm);
   return hipGetLastError();
@@ -957,8 +959,8 @@ hipError_t batch_lane_cfg(const void *inst, const int *tile_inst, int ntiles, in
   if (e != hipSuccess) return e;
   int grid = lane_slots((const void *)fn, 64 * RG, lds);
   if (grid <= 0) return hipErrorInvalidValue;
-  grid = grid < ntiles ? grid : ntiles;
-  if (grid >= 8) grid &= ~7;
+  if (ntiles <= grid) grid = ntiles;  // one tile per workgroup: no walk
+  else if (grid >= 8) grid &= ~7;     // the walk v, v + G, ... stays on one XCD
   hipLaunchKernelGGL(fn, dim3(grid), dim3(64 * RG), lds, st,
                      (const LaneInst<typename Seg::Params> *)inst, tile_inst, ntiles, launch, pl.h,
                      pl.tb);
