@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <algorithm>
 #include <mutex>
+#include <vector>
 #include <tuple>
 
 #include "../../include/mfd.h"
@@ -118,11 +120,26 @@ int Solver::autotune(int32_t *chosen) {
   int64_t trial0 = ((int64_t)1 << 29) / G.N;
   trial0 = trial0 < 96 ? 96 : (trial0 > 480 ? 480 : trial0);
   const int depths[] = {1, 2, 4, 6, 8, 10, 12, 14, 16};
-  int heights[25];
-  for (int i = 0; i < 25; ++i) heights[i] = 32 + 4 * i;  // 32 .. 128
+  int heights[49];
+  for (int i = 0; i < 49; ++i) heights[i] = 32 + 2 * i;  // 32 .. 128
   const int widths[] = {64, 128};
-  float best_ms = 1e30f;
-  TbPlan best{1, 0};
+  // time per step of plan p over about `steps` steps (whole blocks of its depth)
+  auto time_plan = [&](const TbPlan &p, int64_t steps, float *ms) {
+    tb = p.tb;
+    tuned = p;
+    const int64_t trial = p.tb * ((steps + p.tb - 1) / p.tb);
+    int r = step(trial);  // warm-up
+    if (!r) r = hip(hipEventRecord(e0, stream), "hipEventRecord");
+    if (!r) r = step(trial);
+    if (!r) r = hip(hipEventRecord(e1, stream), "hipEventRecord");
+    if (!r) r = hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    if (!r) r = hip(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime");
+    *ms /= (float)trial;
+    return r;
+  };
+  // scan every plan, then time the four fastest again over four times the
+  // steps (the scan's short trials rank close plans by noise)
+  std::vector<std::pair<float, TbPlan>> timed;
   for (int d : depths) {
     for (int w : widths)
     for (int h : heights) {
@@ -130,22 +147,23 @@ int Solver::autotune(int32_t *chosen) {
       TbPlan p{d, d == 1 ? 0 : h, w};
       if (d == 1 && (h != heights[0] || w != widths[0])) continue;
       if (d > 1 && !plan_supported(p)) continue;
-      tb = d;
-      tuned = p;
-      const int64_t trial = d * ((trial0 + d - 1) / d);
-      rc = step(trial);  // warm-up
-      if (rc) break;
-      rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
-      if (!rc) rc = step(trial);
-      if (!rc) rc = hip(hipEventRecord(e1, stream), "hipEventRecord");
-      if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
       float ms = 0.f;
-      if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-      ms /= (float)trial;
-      if (!rc && ms < best_ms) {
-        best_ms = ms;
-        best = p;
-      }
+      rc = time_plan(p, trial0, &ms);
+      if (!rc) timed.emplace_back(ms, p);
+    }
+  }
+  std::stable_sort(timed.begin(), timed.end(),
+                   [](const std::pair<float, TbPlan> &a, const std::pair<float, TbPlan> &b) {
+                     return a.first < b.first;
+                   });
+  float best_ms = 1e30f;
+  TbPlan best{1, 0};
+  for (size_t i = 0; i < timed.size() && i < 4 && !rc; ++i) {
+    float ms = 0.f;
+    rc = time_plan(timed[i].second, 4 * trial0, &ms);
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = timed[i].second;
     }
   }
   tb = saved_tb;
