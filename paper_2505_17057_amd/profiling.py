@@ -137,10 +137,16 @@ def main(argv=None):
     grids = kernel_grids(a.trace, a.kernel)
     tb, h, w, ev_ms = bench_plan(a.bench_log)
     a.algorithmic_bytes = a.algorithmic_bytes_per_step * tb
-    main_grid = max(grids, key=lambda g: grids[g][0])  # the timed plan launches most often
     ff, fvals = copy_factor(a.fetch, "FETCH_SIZE", a.copy_bytes)
     wf, wvals = copy_factor(a.write, "WRITE_SIZE", a.copy_bytes)
-    fk = counter_by_grid(a.fetch, "FETCH_SIZE", a.kernel)[main_grid]
+    # the counter runs launch the timed plan only (no autotuning), so its grid
+    # is the one they launch most; the trace's autotuning scan launches other
+    # grids, some of them more often than the timed plan's
+    fgrids = counter_by_grid(a.fetch, "FETCH_SIZE", a.kernel)
+    main_grid = max(fgrids, key=lambda g: len(fgrids[g]))
+    if main_grid not in grids:
+        raise SystemExit("the trace has no launch of the counter runs' grid %d" % main_grid)
+    fk = fgrids[main_grid]
     wk = counter_by_grid(a.write, "WRITE_SIZE", a.kernel)[main_grid]
     fetch_b = statistics.fmean(fk) * 1024.0 * ff
     write_b = statistics.fmean(wk) * 1024.0 * wf
