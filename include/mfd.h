@@ -228,9 +228,10 @@ int mfd_autotune(mfd_solver *s, int32_t *chosen_tb);
  * (depth <= 16, window LDS <= 160 KiB) for the MMFD form of the linear CDE,
  * Burgers' equation (two- and three-level) and the NSE (without an older-level
  * stencil), and for the two-level MesoFD form of the linear CDE and Burgers'
- * equation (the populations are then written at the last step of each launch
- * only: every step depends on the one before through its moments alone, and
- * the populations read back after mfd_step are those of the final step);
+ * equation (the populations are then written at the last step of each
+ * mfd_step call only: every step depends on the one before through its
+ * moments alone, and the populations read back after mfd_step are those of
+ * the final step);
  * MFD_E_UNSUPPORTED for other configured solvers. */
 int mfd_set_blocking(mfd_solver *s, int32_t tb_depth);
 

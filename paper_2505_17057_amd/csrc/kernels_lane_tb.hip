@@ -350,7 +350,8 @@ struct BurgSeg {
 // products ubar_J phi once, when its row enters, and the populations
 // f_J(x) = sum_k a_k g_J(x + k e_J) take their neighbours' from the lanes
 // beside (DPP) or the rows' registers.  The populations of the launch's last
-// step go to memory with the moment.  binary32 accumulates with fused
+// step go to memory with the moment (when the launch is given a population
+// buffer).  binary32 accumulates with fused
 // multiply-adds, binary64 with a rounded product and sum, as the single-step
 // kernel does.
 template <typename T>
@@ -624,6 +625,7 @@ __device__ __forceinline__ void window_steps(V2<typename Seg::T> *lds, int lane,
             if (se) out[gi] = o.x;
             if (so) out[gi + 1] = o.y;
             if constexpr (sizeof...(pops) == 2) {
+              if (pop == nullptr) return;  // moments only
               const int64_t N = (int64_t)nx * ny;
               auto store = [&](const T *fe, const T *fo) {
 #pragma unroll

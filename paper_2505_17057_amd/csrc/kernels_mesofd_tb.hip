@@ -6,7 +6,8 @@
 // new populations (Eq. (2-1), the node function of the single-step kernel)
 // in registers and sums them into its moment of the new level (Eq. (2-1-1)),
 // which goes to LDS for the next step.  The populations of the launch's last
-// step and their moments are stored for the window's interior.  The
+// step (unless pop_out is null) and their moments are stored for the window's
+// interior.  The
 // populations of the intermediate steps are formed like every other and
 // summed, but not written to memory (no later step reads populations: each
 // step depends on the previous one only through its moments).  Results
@@ -107,8 +108,10 @@ __global__ __launch_bounds__(W *RG) void k_mesofd_tb(const T *__restrict__ cur,
           const int gx = x0 + xx, gy = y0 + y;
           if (xx >= TB && xx < W - TB && y >= TB && y < H - TB && gx < nx && gy < ny) {
             const int64_t gi = (int64_t)gy * nx + gx;
+            if (pop_out) {  // null: moments only
 #pragma unroll
-            for (int j = 0; j < L::Q; ++j) pop_out[j * N + gi] = fo[j];
+              for (int j = 0; j < L::Q; ++j) pop_out[j * N + gi] = fo[j];
+            }
             mom_out[gi] = m[0];
           }
         }

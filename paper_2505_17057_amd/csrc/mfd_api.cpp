@@ -224,11 +224,15 @@ int Solver::step_t(int64_t nsteps) {
         io = t;
       }
     } else if (d > 1 && plan_supported(pl) && s + d <= nsteps) {
-      // blocked MesoFD: d steps; moments of t + d into B[io], populations of
-      // t + d into pop[pn]; the held previous level is d steps old
-      e = launch_mesofd_tb<T>(consts, G, pl, B[ic], B[io], B[pn], stream);
+      // blocked MesoFD: d steps; moments of t + d into B[io]; the held
+      // previous level is d steps old.  The populations of t + d go to
+      // pop[pn] only when no step follows in this call: a step reads the one
+      // before through its moments alone, so only the call's last
+      // populations are ever read.
+      const bool final_launch = s + d == nsteps;
+      e = launch_mesofd_tb<T>(consts, G, pl, B[ic], B[io], final_launch ? B[pn] : nullptr, stream);
       if (e != hipSuccess) return hip(e, "blocked mesofd launch");
-      std::swap(pc, pn);
+      if (final_launch) std::swap(pc, pn);
       const int t = ip;
       ip = ic;
       ic = io;

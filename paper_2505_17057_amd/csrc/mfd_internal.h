@@ -163,7 +163,7 @@ bool lane_tb_applies(const Consts &c, int elem);
 bool lane_shared_fp32(const Consts &c);
 bool lane_tb_window_fits(const TbPlan &pl);
 // the same window for the two-level MesoFD form: moments of level t in;
-// moments and populations of level t + tb out
+// moments and (pop_out not null) populations of level t + tb out
 bool lane_meso_applies(const Consts &c, int elem);
 template <typename T>
 hipError_t launch_lane_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
@@ -172,7 +172,8 @@ template <typename T>
 hipError_t launch_lane_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, T *out,
                           hipStream_t st);
 // blocked MesoFD step, two-level linear CDE / Burgers (kernels_mesofd_tb.hip):
-// moments of level t in, moments and populations of level t + tb out
+// moments of level t in, moments and (pop_out not null) populations of level
+// t + tb out
 bool mesofd_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
 template <typename T>
 hipError_t launch_mesofd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
