@@ -104,8 +104,8 @@ __device__ __forceinline__ void mesofd_pops(const At &at, const AtH &ath, const 
   });
 }
 
-// evaluate the b new populations of one node, store them and the moments of
-// the new level
+// evaluate the b new populations of one node, store them (unless pout is
+// null) and the moments of the new level
 template <class L, int EQ, bool THREE_ST, typename T, class At, class AtH>
 __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const T *hcentre,
                                             bool three, T *pout, T *mout, int64_t N, int64_t gi,
@@ -113,8 +113,10 @@ __device__ __forceinline__ void mesofd_node(const At &at, const AtH &ath, const 
   constexpr int NF = Rec<L, EQ>::NF;
   T fo[L::Q];
   mesofd_pops<L, EQ, THREE_ST>(at, ath, hcentre, three, fo, kc);
+  if (pout) {  // null: the moments only
 #pragma unroll
-  for (int j = 0; j < L::Q; ++j) pout[j * N + gi] = fo[j];
+    for (int j = 0; j < L::Q; ++j) pout[j * N + gi] = fo[j];
+  }
   T m[NF];
   moments_of<L, EQ>(fo, m);
 #pragma unroll

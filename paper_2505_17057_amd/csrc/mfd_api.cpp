@@ -240,11 +240,14 @@ int Solver::step_t(int64_t nsteps) {
       s += d - 1;
       prev_gap = d;
     } else {
-      // MesoFD: moments of t in B[ic] (those of pop[pc]) and of t-dt in
-      // B[ip]; writes pop[pn] and its moments into B[io]; then rotate.
-      e = launch_mesofd_step<T>(consts, G, B[ic], B[ip], B[pn], B[io], stream);
+      // MesoFD: moments of t in B[ic] and of t-dt in B[ip]; writes the new
+      // moments into B[io] and, at the call's last step, the populations
+      // they sum into pop[pn] (no step reads populations); then rotate.
+      const bool final_step = s + 1 == nsteps;
+      e = launch_mesofd_step<T>(consts, G, B[ic], B[ip], final_step ? B[pn] : nullptr, B[io],
+                                stream);
       if (e != hipSuccess) return hip(e, "mesofd step launch");
-      std::swap(pc, pn);
+      if (final_step) std::swap(pc, pn);
       const int t = ip;
       ip = ic;
       ic = io;

@@ -187,8 +187,8 @@ template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                           const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 
-// MesoFD step: moments of level t (mom) and t-dt (prev_mom) in; populations
-// and moments of level t+1 out.
+// MesoFD step: moments of level t (mom) and t-dt (prev_mom) in; moments and
+// (pop_out not null) populations of level t+1 out.
 template <typename T>
 hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, const T *prev_mom,
                               T *pop_out, T *mom_out, hipStream_t st);
