@@ -555,6 +555,47 @@ int orc_literal_step(const orc_params *P, const double *cur, const double *prev,
     return 0;
 }
 
+/* ------------------------------------------------------------ source term */
+
+/*
+ * Source of the scheme, the b terms of Eq. (2-1) / (3layerMMFD-1):
+ *   Delta t sum_j sum_k [ b_k F_j(x + k e_j, t) + bh_k F_j(x + k e_j, t - dt) ]
+ * with F_j of Eq. (SourceF) for the NCDE: F_j = w_j (S + c_j.M_1F / c_s^2),
+ * M_1F = v S for a constant vector v, i.e. in lattice units
+ *   F_j(y) = w_j (S(y) + (e_j.vh / d0) S(y)),   vh = v dt / dx.
+ * S is given at both time levels (the caller evaluates it); its time levels
+ * are independent of the scheme's levels of phi.
+ */
+typedef struct {
+    double b[3], bh[3];   /* k = -1, 0, +1 at level t and t - dt            */
+    double v[3];          /* M_1F = v S (physical velocity)                 */
+} orc_source;
+
+/* the source term of direction j at node (x, y, z), before the factor dt:
+ *   sum_k b_k F_j(x + k e_j, t) + sum_k bh_k F_j(x + k e_j, t - dt),
+ * zero coefficients skipped, level t first */
+static double source_dir(const orc_params *P, const orc_ctx *c, const orc_source *Q,
+                         const double *St, const double *Sm, int j, int64_t x, int64_t y,
+                         int64_t z)
+{
+    double vh[3];
+    for (int a = 0; a < 3; ++a) vh[a] = Q->v[a] * P->dt / P->dx;
+    double ev = edot(c, j, vh) * c->inv_d0;
+    double sj = 0.0;
+    for (int lev = 0; lev < 2; ++lev) {
+        const double *S = lev == 0 ? St : Sm;
+        const double *bk = lev == 0 ? Q->b : Q->bh;
+        for (int k = -1; k <= 1; ++k) {
+            if (bk[k + 1] == 0.0) continue;
+            double Sy = S[nb(c, x, y, z, j, k)];
+            sj = sj + bk[k + 1] * (c->L.w[j] * (Sy + ev * Sy));
+        }
+    }
+    return sj;
+}
+
+
+
 /* ------------------------------------------------------------------ MesoFD */
 
 /* populations of the EDF of a moment state: pop[j*N + i] = f_j^eq(i) */
@@ -602,8 +643,21 @@ int orc_moments(const orc_params *P, const double *pop, double *mom)
  * Writes the new populations and, for three-level schemes, the moments of
  * level t (the t-dt level of the next step) into `mom_out`.
  */
+static int mesofd_step(const orc_params *P, const orc_source *Q, const double *pop,
+                       const double *prev_mom, const double *St, const double *Sm,
+                       double *pop_out, double *mom_out);
+
 int orc_mesofd_step(const orc_params *P, const double *pop, const double *prev_mom,
                     double *pop_out, double *mom_out)
+{
+    return mesofd_step(P, NULL, pop, prev_mom, NULL, NULL, pop_out, mom_out);
+}
+
+/* the populations of one step, Eq. (2-1) / (3layer-1), with the source
+ * term of each direction added when Q is given */
+static int mesofd_step(const orc_params *P, const orc_source *Q, const double *pop,
+                       const double *prev_mom, const double *St, const double *Sm,
+                       double *pop_out, double *mom_out)
 {
     orc_ctx c;
     if (make_ctx(P, &c)) return -1;
@@ -633,6 +687,7 @@ int orc_mesofd_step(const orc_params *P, const double *pop, const double *prev_m
                     if (three)
                         for (int k = -1; k <= 1; ++k)
                             if (P->ah[k + 1] != 0.0) fj = fj + P->ah[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                    if (Q) fj = fj + P->dt * source_dir(P, &c, Q, St, Sm, j, x, y, z);
                     pop_out[j * N + i] = fj;
                 }
             }
@@ -702,22 +757,6 @@ int orc_theta_step(const orc_params *P, const double *cur, double *out, double *
     free(rhs);
     return 0;
 }
-
-/* ------------------------------------------------------------ source term */
-
-/*
- * Source of the scheme, the b terms of Eq. (2-1) / (3layerMMFD-1):
- *   Delta t sum_j sum_k [ b_k F_j(x + k e_j, t) + bh_k F_j(x + k e_j, t - dt) ]
- * with F_j of Eq. (SourceF) for the NCDE: F_j = w_j (S + c_j.M_1F / c_s^2),
- * M_1F = v S for a constant vector v, i.e. in lattice units
- *   F_j(y) = w_j (S(y) + (e_j.vh / d0) S(y)),   vh = v dt / dx.
- * S is given at both time levels (the caller evaluates it); its time levels
- * are independent of the scheme's levels of phi.
- */
-typedef struct {
-    double b[3], bh[3];   /* k = -1, 0, +1 at level t and t - dt            */
-    double v[3];          /* M_1F = v S (physical velocity)                 */
-} orc_source;
 
 /* MMFD form: Eq. (2-2-1) with its b terms,
  *   dt [ B0 S(t) + Bh0 S(t-dt) ]
@@ -789,8 +828,6 @@ int orc_literal_source_step(const orc_params *P, const orc_source *Q, const doub
     if (rc) return rc;
     orc_ctx c;
     if (make_ctx(P, &c)) return -1;
-    double vh[3];
-    for (int a = 0; a < 3; ++a) vh[a] = Q->v[a] * P->dt / P->dx;
     const int b = c.L.b;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t z = 0; z < c.n[2]; ++z)
@@ -798,23 +835,20 @@ int orc_literal_source_step(const orc_params *P, const orc_source *Q, const doub
             for (int64_t x = 0; x < c.n[0]; ++x) {
                 int64_t i = (z * c.n[1] + y) * c.n[0] + x;
                 double s = 0.0;
-                for (int j = 0; j < b; ++j) {
-                    double ev = edot(&c, j, vh) * c.inv_d0;
-                    double fj = 0.0;
-                    for (int lev = 0; lev < 2; ++lev) {
-                        const double *S = lev == 0 ? St : Sm;
-                        const double *bk = lev == 0 ? Q->b : Q->bh;
-                        for (int k = -1; k <= 1; ++k) {
-                            if (bk[k + 1] == 0.0) continue;
-                            double Sy = S[nb(&c, x, y, z, j, k)];
-                            fj = fj + bk[k + 1] * (c.L.w[j] * (Sy + ev * Sy));
-                        }
-                    }
-                    s = s + fj;
-                }
+                for (int j = 0; j < b; ++j) s = s + source_dir(P, &c, Q, St, Sm, j, x, y, z);
                 out[i] = out[i] + P->dt * s;
             }
     return 0;
+}
+
+/* one MesoFD step of the linear CDE with the source: every population gets
+ * dt times its direction's source term (source_dir) after its a terms */
+int orc_mesofd_source_step(const orc_params *P, const orc_source *Q, const double *pop,
+                           const double *prev_mom, const double *St, const double *Sm,
+                           double *pop_out, double *mom_out)
+{
+    if (P->eq != ORC_LCDE) return -5;
+    return mesofd_step(P, Q, pop, prev_mom, St, Sm, pop_out, mom_out);
 }
 
 /* ---------------------------------------------------------- tables / sums */

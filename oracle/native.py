@@ -75,6 +75,7 @@ def lib():
             ("orc_tables", [P, D, D, D]),
             ("orc_mmfd_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
             ("orc_literal_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
+            ("orc_mesofd_source_step", [P, C.POINTER(Source), D, D, D, D, D, D]),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -211,13 +212,23 @@ def moments(spec, pop):
     return mom
 
 
-def mesofd_step(spec, pop, prev_mom=None):
-    """Returns (new populations, moments of the input level)."""
+def mesofd_step(spec, pop, prev_mom=None, src=None):
+    """Returns (new populations, moments of the input level); src (linear
+    CDE): dict(b, bh, v, S_t, S_m) adds each direction's source term."""
     P = make_params(spec)
     out = np.empty_like(pop)
     mom_out = np.empty((nfields(spec) * npoints(spec),))
     if prev_mom is None:
         prev_mom = np.zeros_like(mom_out)  # read only by three-level schemes
+    if src is not None:
+        Q = make_source(src)
+        St = np.ascontiguousarray(src["S_t"], dtype=np.float64)
+        Sm = np.ascontiguousarray(src["S_m"], dtype=np.float64)
+        assert St.size == npoints(spec) and Sm.size == npoints(spec)
+        _check(lib().orc_mesofd_source_step(C.byref(P), C.byref(Q), _ptr(pop), _ptr(prev_mom),
+                                            _ptr(St), _ptr(Sm), _ptr(out), _ptr(mom_out)),
+               "mesofd_source_step")
+        return out, mom_out
     _check(lib().orc_mesofd_step(C.byref(P), _ptr(pop), _ptr(prev_mom), _ptr(out), _ptr(mom_out)),
            "mesofd_step")
     return out, mom_out

@@ -2,7 +2,9 @@
 (3layerMMFD-1) with F_j of Eq. (SourceF), M_1F = v S), linear CDE.
 
 * the MMFD form (pair parts of F, Eq. (2-2-1) with its b terms) equals the
-  literal sum over directions and k to round-off, on every lattice;
+  literal sum over directions and k to round-off, on every lattice, and the
+  moments of the MesoFD step with the source (each population with its own
+  direction's b terms) equal it too;
 * its Fourier symbol: the source part of a step multiplies each mode of S
   by dt sum_j w_j (1 + e_j.vh/d0) sum_k b_k exp(i k xi.e_j);
 * conservation on a periodic grid: the source adds dt (B0 sum S(t) +
@@ -60,6 +62,30 @@ def test_source_forms_agree(lat, name):
     scale = np.abs(cur).max() + np.abs(prev).max() + spec["dt"] * (
         np.abs(src["S_t"]).max() + np.abs(src["S_m"]).max())
     assert np.abs(mm - lit).max() < 1e-13 * scale
+
+
+@pytest.mark.parametrize("lat", LATS)
+@pytest.mark.parametrize("name", list(SCHEMES))
+def test_source_mesofd_moments_equal_mmfd(lat, name):
+    """MesoFD with the source (each population gets dt times its direction's
+    b terms): the moments of the new populations equal the MMFD step with the
+    source to round-off, and the populations sum to them."""
+    spec, case = _spec(lat, name, seed=39)
+    rng = np.random.default_rng(40)
+    src = _source(spec, rng)
+    cur, prev = case["phi0"], case["phim"]
+    pop = O.init_populations(spec, cur)
+    newpop, mom_cur = O.mesofd_step(spec, pop, prev, src)
+    meso = O.moments(spec, newpop)
+    mm = O.mmfd_step(spec, cur, prev, src)
+    scale = np.abs(cur).max() + np.abs(prev).max() + spec["dt"] * (
+        np.abs(src["S_t"]).max() + np.abs(src["S_m"]).max())
+    assert np.abs(meso - mm).max() < 1e-13 * scale
+    assert np.abs(mom_cur - cur).max() < 1e-14 * scale
+    # without the source the same call is the plain MesoFD step
+    plain, _ = O.mesofd_step(spec, pop, prev)
+    zero = dict(src, b=(0.0, 0.0, 0.0), bh=(0.0, 0.0, 0.0))
+    assert np.array_equal(O.mesofd_step(spec, pop, prev, zero)[0], plain)
 
 
 @pytest.mark.parametrize("lat", LATS)
