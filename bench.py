@@ -248,8 +248,8 @@ def bench_source(M, torch, I, stream, steps=500):
     ex = I.example1_source_2d(n=N_SIDE)
     a, ah = (7 / 8, 1 / 4, -1 / 8), (1 / 8, -1 / 4, 1 / 8)
     out, finals = {}, {}
-    for prec in ("fp64", "fp32"):
-        s = M.Solver("D2Q9", ex["n"], ex["dx"], prec, "mmfd")
+    for prec, form in (("fp64", "mmfd"), ("fp32", "mmfd"), ("fp64", "mesofd"), ("fp32", "mesofd")):
+        s = M.Solver("D2Q9", ex["n"], ex["dx"], prec, form)
         s.set_equation("lcde", u=ex["u"], K=ex["K"], lambda_bar=1)
         s.set_scheme("three_level", a, ah, dt=ex["dt"])
         s.set_stream(stream.cuda_stream)
@@ -262,17 +262,26 @@ def bench_source(M, torch, I, stream, steps=500):
         s.step(20)
         start()
         ms = timed(torch, lambda: s.step(steps))
-        finals[prec] = s.get_state().astype(np.float64)
+        finals[prec, form] = s.get_state().astype(np.float64)
         s.close()
         g = ex["n"][0] * ex["n"][1] * steps / (ms * 1e-3) / 1e9
-        bpl = 4 * (8 if prec == "fp64" else 4)  # read t, t - dt and G; write t + dt
-        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
-                         frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl)
+        es = 8 if prec == "fp64" else 4
+        key = prec if form == "mmfd" else "mesofd_" + prec
+        if form == "mmfd":
+            bpl = 4 * es  # read t, t - dt and G; write t + dt
+            out[key] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                            frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl)
+        else:
+            # the population form's own bytes: read and write the 9 populations, read G
+            bpl = (2 * 9 + 1) * es
+            out[key] = dict(glups=round(g, 2), pop_form_bytes_per_lup=bpl,
+                            pop_form_equiv_gbs=round(g * bpl, 1))
     exact = ex["exact"](steps * ex["dt"])
+    f64 = finals["fp64", "mmfd"]
     out.update(steps=steps, scheme="three-level (7/8, 1/4, -1/8 | 1/8, -1/4, 1/8), b_-1 = 3/2, bh_-1 = -1/2",
-               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
-                                         / np.linalg.norm(finals["fp64"])),
-               fp64_gre_vs_exact=float(np.abs(finals["fp64"] - exact).sum() / np.abs(exact).sum()))
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32", "mmfd"] - f64) / np.linalg.norm(f64)),
+               mesofd_vs_mmfd_fp64_max_abs=float(np.abs(finals["fp64", "mesofd"] - f64).max()),
+               fp64_gre_vs_exact=float(np.abs(f64 - exact).sum() / np.abs(exact).sum()))
     return out
 
 

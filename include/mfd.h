@@ -180,10 +180,12 @@ int mfd_get_state(mfd_solver *s, int level, void *dst, int64_t bytes, int on_dev
 /* Enqueue nsteps >= 0 time steps; asynchronous with respect to the host. */
 int mfd_step(mfd_solver *s, int64_t nsteps);
 
-/* Source term of the linear CDE (MMFD form, explicit two- or three-level
- * scheme): the b terms of Eq. (2-1) / (3layerMMFD-1) with the source
- * distribution F_j of Eq. (SourceF) for the NCDE, F_j = w_j (S + c_j.M_1F /
- * c_s^2), taken in the central-difference form of Eq. (2-2-1):
+/* Source term of the linear CDE (explicit two- or three-level scheme; MMFD
+ * form on every lattice, MesoFD form on 1D / 2D lattices): the b terms of
+ * Eq. (2-1) / (3layerMMFD-1) with the source distribution F_j of
+ * Eq. (SourceF) for the NCDE, F_j = w_j (S + c_j.M_1F / c_s^2), added to each
+ * population (MesoFD) or taken in the central-difference form of
+ * Eq. (2-2-1) (MMFD):
  *   S(x, t)  = exp(lambda t) G(x), t = n dt with n the steps taken since the
  *              last level-0 mfd_set_state (the step from t to t + dt reads S
  *              at t and at t - dt, whatever the scheme's levels of phi);
@@ -196,7 +198,7 @@ int mfd_step(mfd_solver *s, int64_t nsteps);
  * mfd_destroy.  Each step is then a single-step launch followed by the source
  * launch: temporal blocking and the resident 1D paths are not used while a
  * source is set.  Returns MFD_E_ORDER before the scheme is set,
- * MFD_E_UNSUPPORTED for the MesoFD form, another equation or the theta scheme,
+ * MFD_E_UNSUPPORTED for another equation, the theta scheme or a 3D MesoFD grid,
  * MFD_E_ARG for a null G, a wrong count or non-finite values, MFD_E_OOM. */
 int mfd_set_source(mfd_solver *s, const double *G, int64_t count, int on_device, double lambda,
                    const double b[3], const double bh[3], const double v[3]);

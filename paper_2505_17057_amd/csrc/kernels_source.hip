@@ -20,6 +20,7 @@
 // that adds the source term to the level it wrote.
 #include <cmath>
 
+#include "mesofd_node.h"
 #include "mfd_internal.h"
 #include "mmfd_node.h"
 
@@ -32,6 +33,9 @@ struct SrcC {
   T wp[kMaxP], wm[kMaxP];
   T B0, Bh0, bp, bm, bhp, bhm;
   T dt, sig_t, sig_m;
+  // MesoFD: F_j(y) = wj (S(y) + evj S(y)) per direction, b_k and bh_k
+  T wj[kMaxQ], evj[kMaxQ];
+  T b[3], bh[3];
 };
 
 // the source term at one node; g(dz, dy, dx) reads G at the node's neighbour
@@ -101,6 +105,74 @@ __global__ __launch_bounds__(256) void k_lcde_source_plane(const T *__restrict__
   }
 }
 
+// MesoFD form (1D / 2D), one launch per step: the same staging; each node
+// forms its b populations with the single-step node function (mesofd_pops),
+// adds to each dt times its direction's source term
+//   sum_k b_k F_j(x + k e_j, t) + sum_k bh_k F_j(x + k e_j, t - dt)
+// (zero coefficients skipped, level t first), stores them (pop_out not null)
+// and their sum, the new moment (Eq. (2-1-1)).
+template <class L, bool THREE, bool THREE_ST, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_lcde_mesofd_source_plane(
+    const T *__restrict__ cur, const T *__restrict__ prev, const T *__restrict__ G,
+    T *__restrict__ pop_out, T *__restrict__ mom_out, int nx, int ny, int tiles_x, int ntiles,
+    KC<T> kc, SrcC<T> sc) {
+  constexpr int HYL = L::D >= 2 ? 1 : 0;
+  constexpr int HX = TX + 2, HY = TY + 2 * HYL;
+  __shared__ T ph[HY][HX];
+  __shared__ T hp[THREE_ST ? HY : 1][THREE_ST ? HX : 1];
+  __shared__ T gs[HY][HX];
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+  const int64_t N = (int64_t)nx * ny;
+  for (int i = threadIdx.x; i < HX * HY; i += 256) {
+    const int lx = i % HX, ly = i / HX;
+    const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - HYL + ly, ny);
+    const int64_t gi = (int64_t)gy * nx + gx;
+    ph[ly][lx] = cur[gi];
+    if constexpr (THREE_ST) hp[ly][lx] = prev[gi];
+    gs[ly][lx] = G[gi];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TX * TY; i += 256) {
+    const int lx = i % TX, ly = i / TX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int cx = lx + 1, cy = ly + HYL;
+    const int64_t gi = (int64_t)gy * nx + gx;
+    auto at = [&](int, int, int dy, int dx) { return ph[cy + dy][cx + dx]; };
+    auto ath = [&](int, int, int dy, int dx) {
+      if constexpr (THREE_ST) return hp[cy + dy][cx + dx];
+      else return T(0);
+    };
+    T hc[1] = {THREE && !THREE_ST ? prev[gi] : T(0)};
+    T fo[L::Q], m[1];
+    mesofd_pops<L, kLCDE, THREE_ST>(at, ath, hc, THREE, fo, kc);
+#pragma unroll
+    for (int j = 0; j < L::Q; ++j) {
+      T sj = T(0);
+#pragma unroll
+      for (int lev = 0; lev < 2; ++lev) {
+        const T sig = lev == 0 ? sc.sig_t : sc.sig_m;
+#pragma unroll
+        for (int k = -1; k <= 1; ++k) {
+          const T bk = lev == 0 ? sc.b[k + 1] : sc.bh[k + 1];
+          if (bk != T(0)) {
+            const T sy = sig * gs[cy + k * L::E[j][1]][cx + k * L::E[j][0]];
+            sj = sj + bk * (sc.wj[j] * (sy + sc.evj[j] * sy));
+          }
+        }
+      }
+      fo[j] = fo[j] + sc.dt * sj;
+    }
+    if (pop_out) {
+#pragma unroll
+      for (int j = 0; j < L::Q; ++j) pop_out[j * N + gi] = fo[j];
+    }
+    moments_of<L, kLCDE>(fo, m);
+    mom_out[gi] = m[0];
+  }
+}
+
 // 3D: adds the source term to the level the step kernel wrote; blocks of
 // 256 nodes along x, grid (x blocks, y, z)
 template <class L, typename T>
@@ -148,13 +220,9 @@ hipError_t step_l(const Consts &c, const Grid &g, const T *cur, const T *prev, c
 
 }  // namespace
 
+namespace {
 template <typename T>
-hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n,
-                                   const T *cur, const T *prev, T *out, const T *G,
-                                   hipStream_t st) {
-  if (c.eq != kLCDE) return hipErrorInvalidValue;
-  // the 3D source launch is a (x blocks, y, z) grid
-  if (c.dim == 3 && (g.n[1] > 65535 || g.n[2] > 65535)) return hipErrorInvalidValue;
+SrcC<T> src_consts(const Consts &c, const SourceSpec &s, int64_t n) {
   SrcC<T> sc{};
   double vh[3];
   for (int a = 0; a < 3; ++a) vh[a] = s.v[a] * s.dt / s.dx;
@@ -178,6 +246,52 @@ hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceS
   // S at the step's two levels, t = n dt and t - dt
   sc.sig_t = (T)std::exp(s.lambda * ((double)n * s.dt));
   sc.sig_m = (T)std::exp(s.lambda * ((double)(n - 1) * s.dt));
+  for (int j = 0; j < c.q; ++j) {
+    double ev = 0.0;
+    for (int a = 0; a < c.dim; ++a) {
+      if (c.e[j][a] == 1) ev = ev + vh[a];
+      else if (c.e[j][a] == -1) ev = ev - vh[a];
+    }
+    sc.wj[j] = (T)c.w[j];
+    sc.evj[j] = (T)(ev * c.inv_d0);
+  }
+  for (int k = 0; k < 3; ++k) {
+    sc.b[k] = (T)s.b[k];
+    sc.bh[k] = (T)s.bh[k];
+  }
+  return sc;
+}
+
+template <class L, bool THREE, bool THREE_ST, typename T>
+hipError_t meso_cfg(const Consts &c, const Grid &g, const T *cur, const T *prev, const T *G,
+                    T *pop_out, T *mom_out, const SrcC<T> &sc, hipStream_t st) {
+  constexpr int TX = L::D >= 2 ? 64 : 256, TY = L::D >= 2 ? 16 : 1;
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  hipLaunchKernelGGL((k_lcde_mesofd_source_plane<L, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty),
+                     dim3(256), 0, st, cur, prev, G, pop_out, mom_out, nx, ny, tx, tx * ty,
+                     make_kc<T>(c), sc);
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t meso_l(const Consts &c, const Grid &g, const T *cur, const T *prev, const T *G,
+                  T *pop_out, T *mom_out, const SrcC<T> &sc, hipStream_t st) {
+  if (!c.three) return meso_cfg<L, false, false, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+  if (!c.three_stencil)
+    return meso_cfg<L, true, false, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+  return meso_cfg<L, true, true, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n,
+                                   const T *cur, const T *prev, T *out, const T *G,
+                                   hipStream_t st) {
+  if (c.eq != kLCDE) return hipErrorInvalidValue;
+  // the 3D source launch is a (x blocks, y, z) grid
+  if (c.dim == 3 && (g.n[1] > 65535 || g.n[2] > 65535)) return hipErrorInvalidValue;
+  const SrcC<T> sc = src_consts<T>(c, s, n);
   switch (c.lattice) {
     case 1: return step_l<LatD1Q3, T>(c, g, cur, prev, G, out, sc, st);
     case 2: return step_l<LatD2Q5, T>(c, g, cur, prev, G, out, sc, st);
@@ -187,6 +301,28 @@ hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceS
   }
 }
 
+template <typename T>
+hipError_t launch_mesofd_source_step(const Consts &c, const Grid &g, const SourceSpec &s,
+                                     int64_t n, const T *cur, const T *prev, T *pop_out,
+                                     T *mom_out, const T *G, hipStream_t st) {
+  if (c.eq != kLCDE || c.dim == 3) return hipErrorInvalidValue;
+  const SrcC<T> sc = src_consts<T>(c, s, n);
+  switch (c.lattice) {
+    case 1: return meso_l<LatD1Q3, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+    case 2: return meso_l<LatD2Q5, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+    case 3: return meso_l<LatD2Q9, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_mesofd_source_step<float>(const Consts &, const Grid &,
+                                                     const SourceSpec &, int64_t, const float *,
+                                                     const float *, float *, float *,
+                                                     const float *, hipStream_t);
+template hipError_t launch_mesofd_source_step<double>(const Consts &, const Grid &,
+                                                      const SourceSpec &, int64_t, const double *,
+                                                      const double *, double *, double *,
+                                                      const double *, hipStream_t);
 template hipError_t launch_mmfd_source_step<float>(const Consts &, const Grid &,
                                                    const SourceSpec &, int64_t, const float *,
                                                    const float *, float *, const float *,

@@ -108,10 +108,27 @@ int Solver::step_t(int64_t nsteps) {
   if (src_on) {
     // with a source term: one launch per step (3D: the step, then the source)
     if (!source_supported())
-      return fail(MFD_E_UNSUPPORTED, "the source term needs the MMFD form of the linear CDE "
-                                     "with an explicit scheme");
+      return fail(MFD_E_UNSUPPORTED, "the source term needs the linear CDE with an explicit "
+                                     "scheme (MesoFD form: 1D / 2D)");
     src.dt = cfg.dt;
     src.dx = grid.dx;
+    if (grid.form == MFD_MESOFD) {
+      for (int64_t s = 0; s < nsteps; ++s) {
+        const bool final_step = s + 1 == nsteps;
+        hipError_t e = launch_mesofd_source_step<T>(consts, G, src, steps_done, B[ic], B[ip],
+                                                    final_step ? B[pn] : nullptr, B[io],
+                                                    (const T *)d_src, stream);
+        if (e != hipSuccess) return hip(e, "mesofd source step launch");
+        if (final_step) std::swap(pc, pn);
+        const int t = ip;
+        ip = ic;
+        ic = io;
+        io = t;
+        ++steps_done;
+      }
+      prev_gap = 1;
+      return MFD_OK;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
       T *out = consts.three ? B[io] : B[ip];
       hipError_t e = launch_mmfd_source_step<T>(consts, G, src, steps_done, B[ic], B[ip], out,
@@ -260,7 +277,8 @@ int Solver::step_t(int64_t nsteps) {
 }
 
 bool Solver::source_supported() const {
-  return grid.form == MFD_MMFD && cfg.kind != MFD_THETA && consts.eq == kLCDE;
+  if (cfg.kind == MFD_THETA || consts.eq != kLCDE) return false;
+  return grid.form == MFD_MMFD || grid.dim <= 2;  // MesoFD: 1D / 2D
 }
 
 int Solver::step(int64_t nsteps) {
@@ -652,8 +670,8 @@ extern "C" int mfd_set_source(mfd_solver *h, const double *G, int64_t count, int
   if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
   if (!s->configured) return s->fail(MFD_E_ORDER, "set the scheme first");
   if (!s->source_supported())
-    return s->fail(MFD_E_UNSUPPORTED, "the source term needs the MMFD form of the linear CDE "
-                                      "with an explicit scheme");
+    return s->fail(MFD_E_UNSUPPORTED, "the source term needs the linear CDE with an explicit "
+                                      "scheme (MesoFD form: 1D / 2D)");
   if (!G || !b || !bh || !v) return s->fail(MFD_E_ARG, "null argument");
   if (count != s->G.N)
     return s->fail(MFD_E_ARG, "expected %lld source values, got %lld", (long long)s->G.N,

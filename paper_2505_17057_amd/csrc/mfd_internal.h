@@ -113,6 +113,13 @@ template <typename T>
 hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n,
                                    const T *cur, const T *prev, T *out, const T *G,
                                    hipStream_t st);
+// the same for the MesoFD form (1D / 2D): moments of t (cur) and t - dt (prev)
+// in; the populations of t + dt (pop_out, unless null) and their moments
+// (mom_out) out
+template <typename T>
+hipError_t launch_mesofd_source_step(const Consts &c, const Grid &g, const SourceSpec &s,
+                                     int64_t n, const T *cur, const T *prev, T *pop_out,
+                                     T *mom_out, const T *G, hipStream_t st);
 
 // one NSE step on D3Q19 without an older-level stencil, pair parts staged
 // once per node (kernels_nse3d.hip)

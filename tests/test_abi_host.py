@@ -163,8 +163,7 @@ def test_source_argument_validation(M):
         s.set_source(G, lam=float("nan"))
     assert e.value.code == M.MFD_E_ARG
     s.close()
-    for form, eq, kind in (("mesofd", "lcde", "two_level"), ("mmfd", "burgers", "two_level"),
-                           ("mmfd", "lcde", "theta")):
+    for form, eq, kind in (("mmfd", "burgers", "two_level"), ("mmfd", "lcde", "theta")):
         s = M.Solver("D2Q9", (8, 8), 1.0, "fp64", form)
         s.set_equation(eq, u=(0.01, 0.0), K=[[0.1, 0.0], [0.0, 0.1]])
         s.set_scheme(kind, (1, 0, 0), theta=0.5, theta_iters=2, dt=1.0)
@@ -172,6 +171,13 @@ def test_source_argument_validation(M):
             s.set_source(G)
         assert e.value.code == M.MFD_E_UNSUPPORTED
         s.close()
+    s = M.Solver("D3Q19", (4, 4, 4), 1.0, "fp64", "mesofd")  # MesoFD with a source: 1D / 2D
+    s.set_equation("lcde", u=(0.01, 0.0, 0.0), K=np.eye(3).tolist())
+    s.set_scheme("two_level", (1, 0, 0), dt=1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(np.zeros(64))
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    s.close()
 
 
 def test_stability_warning(M):

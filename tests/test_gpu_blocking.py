@@ -337,6 +337,30 @@ def test_lane_shared_fp64_bitwise(M, plan, lattice, eq, form):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
+@pytest.mark.parametrize("plan", [(4, 40, 128), (3, 32, 64)])
+@pytest.mark.parametrize("chunks", [(8,), (3, 8), (1, 1, 4)])
+def test_mesofd_populations_of_the_last_step(M, plan, chunks):
+    """Only the last step of each mfd_step call stores the populations (a
+    blocked launch with steps after it in the call stores moments only): after
+    calls that end in a blocked launch, in single steps, or in both, the
+    populations read back equal the oracle's of the final step."""
+    from parity_util import make_solver
+    case = dict(MESO["lcde-d2q9"], n=(150, 77), name="lcde-d2q9", form="mesofd")
+    rng = np.random.default_rng(47)
+    cur = rand_state(case, rng)
+    steps = sum(chunks)
+    pop, want = _meso_oracle(case, cur, steps)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    s.set_state(cur)
+    for k in chunks:
+        s.step(k)
+    got, gpop = s.get_state(), s.get_state(populations=True)
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    assert np.array_equal(gpop, pop), np.abs(gpop - pop).max()
+
+
 def test_lane_shared_window_limits(M):
     """The in-place window holds at most 128 rows; other widths are rejected."""
     from parity_util import make_solver

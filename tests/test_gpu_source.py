@@ -6,8 +6,10 @@
   ragged grids, with the steps split over several calls (the time of a step
   counts from the last set_state);
 * binary32 stays within 1e-5 (relative L2) of the binary64 oracle;
+* the MesoFD form (1D / 2D): moments and populations equal the oracle value
+  for value;
 * a launch plan set before the source is not used while it is set;
-* the MesoFD form, other equations, the theta scheme and batches refuse it.
+* 3D MesoFD, other equations, the theta scheme and batches refuse it.
 """
 import math
 
@@ -86,6 +88,45 @@ def test_source_fp64_bitwise(M, lat, scheme, coef):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
+def _oracle_meso(case, cur, prev, steps, G, lam, coef, v):
+    spec = oracle_spec(case)
+    three = spec["levels"] == 3
+    dt = case["dt"]
+    pop = O.init_populations(spec, cur)
+    pm = prev if three else None
+    for s in range(steps):
+        src = dict(coef, v=v, S_t=math.exp(lam * (s * dt)) * G,
+                   S_m=math.exp(lam * ((s - 1) * dt)) * G)
+        pop, pm = O.mesofd_step(spec, pop, pm, src)
+    return pop, O.moments(spec, pop)
+
+
+@pytest.mark.parametrize("lat", ["D1Q3", "D2Q5", "D2Q9"])
+@pytest.mark.parametrize("scheme", list(SCHEMES))
+@pytest.mark.parametrize("coef", list(COEFS))
+def test_source_mesofd_fp64_bitwise(M, lat, scheme, coef):
+    """MesoFD with the source: moments and populations equal the oracle value
+    for value, with the steps split over calls."""
+    case = dict(_case(lat, scheme), form="mesofd")
+    print("case mesofd", lat, scheme, coef, flush=True)
+    rng = np.random.default_rng(45)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    v = tuple(rng.uniform(-0.5, 0.5, len(case["n"])))
+    pop, want = _oracle_meso(case, cur, prev, 7, G, -0.7, COEFS[coef], v)
+    s = make_solver(M, case, "fp64")
+    s.set_state(cur)
+    if case.get("kind") == "three_level":
+        s.set_state(prev, level=1)
+    s.set_source(G, -0.7, COEFS[coef]["b"], COEFS[coef]["bh"], v)
+    s.step(3)
+    s.step(4)
+    got, gpop = s.get_state(), s.get_state(populations=True)
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    assert np.array_equal(gpop, pop), np.abs(gpop - pop).max()
+
+
 @pytest.mark.parametrize("scheme", list(SCHEMES))
 def test_source_fp32_tolerance(M, scheme):
     case = _case("D2Q9", scheme)
@@ -125,12 +166,14 @@ def test_source_rejections(M):
     rng = np.random.default_rng(44)
     base = _case("D2Q9", "srt")
     G = rng.standard_normal(int(np.prod(base["n"])))
-    for case in (dict(base, form="mesofd"),
-                 dict(lattice="D2Q9", eq="burgers", n=base["n"], dx=0.05, dt=0.001, a=(1.0, 0.0, 0.0)),
-                 dict(base, kind="theta", theta=0.5, theta_iters=2)):
+    G3 = rng.standard_normal(int(np.prod(GRIDS["D3Q19"]["n"])))
+    for case, g in ((dict(_case("D3Q19", "srt"), form="mesofd"), G3),
+                    (dict(lattice="D2Q9", eq="burgers", n=base["n"], dx=0.05, dt=0.001,
+                          a=(1.0, 0.0, 0.0)), G),
+                    (dict(base, kind="theta", theta=0.5, theta_iters=2), G)):
         s = make_solver(M, case, "fp64")
         with pytest.raises(M.MfdError):
-            s.set_source(G)
+            s.set_source(g)
         s.close()
     s = make_solver(M, base, "fp64")
     with pytest.raises(M.MfdError):
