@@ -427,24 +427,24 @@ int Batch::autotune() {
       for (int h : {32, 48, 64, 96, 128})
         if (group_plan_valid(g.key, TbPlan{d, h})) cands.push_back(TbPlan{d, h});
     if (lane_ok)
-      for (int d : {4, 6, 8, 10, 12, 14, 16})
-        for (int h = 48; h <= 128; h += 8)
+      for (int d : {4, 6, 8, 10, 12})
+        for (int h : {48, 64, 80, 96, 112, 128})
           if (group_plan_valid(g.key, TbPlan{d, h, 128})) cands.push_back(TbPlan{d, h, 128});
-    // time per lattice update of the group's first launch under plan p, over
-    // `reps` launches
-    auto time_plan = [&](const TbPlan &p, int reps, float *per) -> int {
-      *per = 1e30f;
+    float best = 1e30f;
+    TbPlan best_p{1, 0};
+    for (const TbPlan &p : cands) {
+      if (rc) break;
       g.plan = p;
-      int r = make_tables(g);
-      if (!r) r = upload_instances();
-      if (r) return r;
+      rc = make_tables(g);
+      if (!rc) rc = upload_instances();
+      if (rc) break;
       double lups = 0;
       for (int slot = 0; slot < (int)g.order.size(); ++slot) {
         const int64_t n = std::min<int64_t>(g.steps[slot], p.tb);
         lups += (double)entries[g.order[slot]].s->G.N * (double)n;
       }
       const int nt = active_tiles(g, 0);
-      if (nt == 0 || lups == 0) return 0;
+      if (nt == 0 || lups == 0) continue;
       auto launch = [&]() -> hipError_t {
         if (p.tb > 1) return launch_group_tb(g, nt, 0);
         return g.key.precision == MFD_FP64
@@ -453,36 +453,17 @@ int Batch::autotune() {
                    : launch_batch_step<float>(g.key, (const BatchInst<float> *)g.d_inst,
                                               g.d_tile_inst, nt, 0, stream);
       };
-      r = hip(launch(), "autotune launch");
-      if (!r) r = hip(hipEventRecord(e0, stream), "hipEventRecord");
-      for (int k = 0; k < reps && !r; ++k) r = hip(launch(), "autotune launch");
-      if (!r) r = hip(hipEventRecord(e1, stream), "hipEventRecord");
-      if (!r) r = hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      rc = hip(launch(), "autotune launch");
+      if (!rc) rc = hip(hipEventRecord(e0, stream), "hipEventRecord");
+      for (int k = 0; k < 3 && !rc; ++k) rc = hip(launch(), "autotune launch");
+      if (!rc) rc = hip(hipEventRecord(e1, stream), "hipEventRecord");
+      if (!rc) rc = hip(hipEventSynchronize(e1), "hipEventSynchronize");
       float ms = 0.f;
-      if (!r) r = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-      if (!r) *per = (float)(ms / (reps * lups));
-      return r;
-    };
-    // scan, then the four fastest again over four times the launches
-    std::vector<std::pair<float, TbPlan>> scanned;
-    for (const TbPlan &p : cands) {
-      if (rc) break;
-      float per = 0.f;
-      rc = time_plan(p, 3, &per);
-      if (!rc && per < 1e30f) scanned.emplace_back(per, p);
-    }
-    std::stable_sort(scanned.begin(), scanned.end(),
-                     [](const std::pair<float, TbPlan> &a, const std::pair<float, TbPlan> &b) {
-                       return a.first < b.first;
-                     });
-    float best = 1e30f;
-    TbPlan best_p{1, 0};
-    for (size_t i = 0; i < scanned.size() && i < 4 && !rc; ++i) {
-      float per = 0.f;
-      rc = time_plan(scanned[i].second, 12, &per);
+      if (!rc) rc = hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      const float per = (float)(ms / (3.0 * lups));
       if (!rc && per < best) {
         best = per;
-        best_p = scanned[i].second;
+        best_p = p;
       }
     }
     // restore the spare levels
