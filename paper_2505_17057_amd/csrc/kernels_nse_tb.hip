@@ -21,7 +21,7 @@ namespace mfd {
 
 namespace {
 constexpr int kNseW = 64;  // window columns (one per thread)
-constexpr int kNseR = 4;   // window rows per thread; H = 4 RG
+constexpr int kNseR = 4;   // window rows per thread for 64-row windows (32-row: 2)
 
 __device__ __forceinline__ int xcd_remap_nse(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(W *RG) void k_batch_nse_tb(const BatchInst<T> *__re
 
 // ------------------------------------------------------------ host side
 bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem) {
-  // 64 x 32 or 64 x 64 windows (4 rows per thread)
+  // 64 x 32 (2 rows per thread) or 64 x 64 windows (4 rows per thread)
   if (pl.w != kNseW || (pl.h != 32 && pl.h != 64)) return false;
   if (pl.tb < 1 || pl.h - 2 * pl.tb < 8 || pl.w - 2 * pl.tb < 8) return false;
   return (size_t)2 * npair * pl.h * pl.w * elem <= 160 * 1024;
@@ -181,16 +181,16 @@ bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem) {
 
 namespace {
 
-template <class L, bool THREE, int RG, typename T>
+template <class L, bool THREE, int RG, typename T, int R = kNseR>
 hipError_t nse_tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
                       const T *prev, T *oc, T *op, hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
   const int nx = (int)g.n[0], ny = (int)g.n[1];
-  constexpr int H = kNseR * RG;
+  constexpr int H = R * RG;
   const int TX = kNseW - 2 * pl.tb, TY = H - 2 * pl.tb;
   const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
   const size_t lds = (size_t)2 * L::P * H * kNseW * sizeof(T);  // the pair parts
-  auto fn = k_nse_tb<L, THREE, kNseW, RG, kNseR, T>;
+  auto fn = k_nse_tb<L, THREE, kNseW, RG, R, T>;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -203,19 +203,19 @@ template <class L, typename T>
 hipError_t nse_tb_l(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
                     T *oc, T *op, hipStream_t st) {
   if (pl.h == 32) {
-    if (c.three) return nse_tb_cfg<L, true, 8, T>(c, g, pl, cur, prev, oc, op, st);
-    return nse_tb_cfg<L, false, 8, T>(c, g, pl, cur, prev, oc, op, st);
+    if (c.three) return nse_tb_cfg<L, true, 16, T, 2>(c, g, pl, cur, prev, oc, op, st);
+    return nse_tb_cfg<L, false, 16, T, 2>(c, g, pl, cur, prev, oc, op, st);
   }
   if (c.three) return nse_tb_cfg<L, true, 16, T>(c, g, pl, cur, prev, oc, op, st);
   return nse_tb_cfg<L, false, 16, T>(c, g, pl, cur, prev, oc, op, st);
 }
 
-template <class L, bool THREE, int RG, typename T>
+template <class L, bool THREE, int RG, typename T, int R = kNseR>
 hipError_t bnse_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, int64_t launch,
                     const TbPlan &pl, hipStream_t st) {
-  constexpr int H = kNseR * RG;
+  constexpr int H = R * RG;
   const size_t lds = (size_t)2 * L::P * H * kNseW * sizeof(T);
-  auto fn = k_batch_nse_tb<L, THREE, kNseW, RG, kNseR, T>;
+  auto fn = k_batch_nse_tb<L, THREE, kNseW, RG, R, T>;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -228,8 +228,8 @@ template <class L, typename T>
 hipError_t bnse_l(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst, int ntiles,
                   int64_t launch, const TbPlan &pl, hipStream_t st) {
   if (pl.h == 32) {
-    if (k.three) return bnse_cfg<L, true, 8, T>(inst, tile_inst, ntiles, launch, pl, st);
-    return bnse_cfg<L, false, 8, T>(inst, tile_inst, ntiles, launch, pl, st);
+    if (k.three) return bnse_cfg<L, true, 16, T, 2>(inst, tile_inst, ntiles, launch, pl, st);
+    return bnse_cfg<L, false, 16, T, 2>(inst, tile_inst, ntiles, launch, pl, st);
   }
   if (k.three) return bnse_cfg<L, true, 16, T>(inst, tile_inst, ntiles, launch, pl, st);
   return bnse_cfg<L, false, 16, T>(inst, tile_inst, ntiles, launch, pl, st);
