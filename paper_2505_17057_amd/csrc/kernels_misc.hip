@@ -345,7 +345,7 @@ hipError_t launch_reduce(const T *cur, const T *prev, int nf, int64_t N, double 
   return hipGetLastError();
 }
 
-constexpr int kThetaW = 64, kThetaRG = 4;
+constexpr int kThetaW = 64, kThetaRG = 8;
 
 // window rows of the fused theta step for K sweeps, or 0 when it cannot run
 int theta_fused_rows(const Consts &c, const Grid &g, int K, int elem) {
