@@ -223,9 +223,9 @@ __global__ __launch_bounds__(W *RG) void k_batch_tb(const BatchInst<T> *__restri
 namespace {
 
 // Window: W = 64 or 128 columns (one per thread; a wavefront reads 64
-// consecutive LDS words of a row), H rows in RG = 4 row groups; the tile
+// consecutive LDS words of a row), H rows in RG = 8 row groups; the tile
 // advanced is (W - 2 TB) x (H - 2 TB).  The batched kernel uses W = 64.
-constexpr int kTbW = 64, kTbRG = 4;
+constexpr int kTbW = 64, kTbRG = 8;
 
 template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, int W, typename T>
 hipError_t tb_cfg_w(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
