@@ -13,11 +13,15 @@
 // in the order written, so binary64 results equal the step followed by this
 // sum value for value.
 //
+// The MesoFD form adds to each population f_j dt times its direction's b
+// terms, sum_k b_k F_j(x + k e_j, t) + sum_k bh_k F_j(x + k e_j, t - dt); the
+// moments of the new populations equal the MMFD value to round-off.
+//
 // 1D / 2D: one fused launch per step.  A workgroup stages phi at t (and at
 // t - dt when that level has a stencil) and G for a TX x TY tile and a
 // one-node halo into LDS, then each node forms its step value and its source
-// term from LDS and stores once.  3D: the plain step launch, then a launch
-// that adds the source term to the level it wrote.
+// term from LDS and stores once.  3D (MMFD only): the plain step launch, then
+// a launch that adds the source term to the level it wrote.
 #include <cmath>
 
 #include "mesofd_node.h"
