@@ -182,6 +182,26 @@ def bench_variants(M, torch, cfg, stream, N):
                mesofd=float(np.linalg.norm(finals[("fp32", "mesofd")] - finals[("fp64", "mesofd")])
                             / np.linalg.norm(finals[("fp64", "mesofd")])))
     meso_vs_mmfd = float(np.abs(finals[("fp64", "mesofd")] - f64).max())
+    # the three-level scheme of Example 1 Case 3 (a = 7/8, 0, 1/8; ah = 1/8,
+    # 0, -1/8) on the same workload, both levels starting from phi0
+    f3 = {}
+    for prec in ("fp32", "fp64"):
+        sv = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
+        sv.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
+        sv.set_scheme("three_level", (7 / 8, 0.0, 1 / 8), (1 / 8, 0.0, -1 / 8), dt=cfg["dt"])
+        sv.set_stream(stream.cuda_stream)
+        sv.set_state(cfg["phi0"].astype(sv.dtype))
+        sv.autotune()
+        ms = timed(torch, lambda: sv.step(TIME_STEPS))
+        g = N * TIME_STEPS / (ms * 1e-3) / 1e9
+        bpl = 3 * (8 if prec == "fp64" else 4)  # read t and t - dt, write t + dt
+        out["mmfd_three_level_" + prec] = dict(glups=round(g, 2), ms_per_solve=round(ms, 3),
+                                               plan=list(sv.launch_plan()), alg_gbs=round(g * bpl, 1),
+                                               frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
+                                               bytes_per_lup=bpl)
+        f3[prec] = sv.get_state().astype(np.float64)
+        sv.close()
+    err["mmfd_three_level"] = float(np.linalg.norm(f3["fp32"] - f3["fp64"]) / np.linalg.norm(f3["fp64"]))
     return out, err, meso_vs_mmfd
 
 
