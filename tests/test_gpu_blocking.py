@@ -337,6 +337,95 @@ def test_lane_shared_fp64_bitwise(M, plan, lattice, eq, form):
     assert np.array_equal(got, want), np.abs(got - want).max()
 
 
+def _three_level_case(lattice, eq, hat):
+    ah = {"trt": (0.0, -0.4, 0.0), "stencil": (0.125, 0.0, -0.125)}[hat]
+    a = (1.0, 0.0, 0.4) if hat == "trt" else (0.875, 0.0, 0.125)
+    if eq == "lcde":
+        K = K2 if lattice == "D2Q9" else [[0.3, 0.0], [0.0, 0.2]]
+        return dict(BASE, lattice=lattice, K=K, n=(301, 139), kind="three_level", a=a, ah=ah)
+    case = dict(lattice=lattice, eq="burgers", n=(301, 139), **_burgers_a(301))
+    case.update(kind="three_level", a=a, ah=ah)
+    if eq == "burgers-beta":
+        case["beta"] = 0.6
+    return case
+
+
+@pytest.mark.parametrize("plan", [(8, 48, 128), (10, 52, 128), (3, 10, 128), (16, 37, 128),
+                                  (2, 20, 128)])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q5"])
+@pytest.mark.parametrize("eq", ["lcde", "burgers", "burgers-beta"])
+@pytest.mark.parametrize("hat", ["trt", "stencil"])
+def test_three_level_wide_fp64_bitwise(M, plan, lattice, eq, hat):
+    """Three-level steps in 128-column windows (levels t, t - dt and the new
+    one in LDS) equal the oracle value for value, both levels of the result,
+    on a grid with ragged tiles in both directions and a ragged remainder of
+    steps; the level t - dt enters through its centre value (trt) or through
+    central differences (stencil)."""
+    from parity_util import make_solver
+    case = _three_level_case(lattice, eq, hat)
+    print("case", hat, eq, lattice, plan, flush=True)
+    rng = np.random.default_rng(31)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    steps = 2 * plan[0] + 3
+    want = run_oracle(case, cur, prev, steps)
+    want_prev = run_oracle(case, cur, prev, steps - 1)
+    s = make_solver(M, case, "fp64")
+    s.set_plan(*plan)
+    assert s.launch_plan() == plan
+    s.set_state(cur)
+    s.set_state(prev, level=1)
+    s.step(steps)
+    got, got_prev = s.get_state(), s.get_state(level=1)
+    s.close()
+    assert np.array_equal(got, want), np.abs(got - want).max()
+    assert np.array_equal(got_prev, want_prev), np.abs(got_prev - want_prev).max()
+
+
+@pytest.mark.parametrize("plan", [(8, 104, 128), (12, 96, 128), (3, 10, 128), (16, 37, 128)])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q5"])
+@pytest.mark.parametrize("eq", ["lcde", "burgers-beta"])
+@pytest.mark.parametrize("hat", ["trt", "stencil"])
+def test_three_level_wide_fp32_equals_unblocked(M, plan, lattice, eq, hat):
+    """The binary32 three-level windows equal the single-step kernel bit for
+    bit (the same node function), both levels."""
+    from parity_util import make_solver
+    case = _three_level_case(lattice, eq, hat)
+    print("case", hat, eq, lattice, plan, flush=True)
+    rng = np.random.default_rng(37)
+    cur = rand_state(case, rng).astype(np.float32)
+    prev = rand_state(case, rng).astype(np.float32)
+    outs = []
+    for p in ((1,), plan):
+        s = make_solver(M, case, "fp32")
+        s.set_plan(*p)
+        s.set_state(cur)
+        s.set_state(prev, level=1)
+        s.step(3 * plan[0] + 1)
+        outs.append((s.get_state(), s.get_state(level=1)))
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b), np.abs(a - b).max()
+
+
+def test_three_level_window_limits(M):
+    """Three levels of 128 columns in 160 KiB of LDS: up to 106 rows in
+    binary32, 53 in binary64."""
+    from parity_util import make_solver
+    case = _three_level_case("D2Q9", "lcde", "stencil")
+    s = make_solver(M, dict(case, n=(300, 200)), "fp32")
+    s.set_plan(4, 106, 128)
+    assert s.launch_plan() == (4, 106, 128)
+    with pytest.raises(M.MfdError):
+        s.set_plan(4, 108, 128)
+    s.close()
+    s = make_solver(M, dict(case, n=(300, 200)), "fp64")
+    s.set_plan(4, 53, 128)
+    assert s.launch_plan() == (4, 53, 128)
+    with pytest.raises(M.MfdError):
+        s.set_plan(4, 54, 128)
+    s.close()
+
+
 @pytest.mark.parametrize("plan", [(4, 40, 128), (3, 32, 64)])
 @pytest.mark.parametrize("chunks", [(8,), (3, 8), (1, 1, 4)])
 def test_mesofd_populations_of_the_last_step(M, plan, chunks):
