@@ -11,6 +11,9 @@ afford, and properties that hold at any size where it cannot.
   periodic sum of the central-difference form), FP32 within 1e-6 of FP64.
 * 256 Burgers grids: the autotuned blocked batch equals every grid stepped
   alone (FP32, bit for bit), and the smallest grids equal the oracle (FP64).
+* 2048^2 three-level Example 1 Case 3 scheme (autotuned): FP64 bit-exact,
+  both levels; FP32 within 1e-5.
+* 2048^2 Example 1 with its source: FP64 bit-exact, FP32 within 1e-5.
 """
 import numpy as np
 import pytest
@@ -212,3 +215,69 @@ def test_batched_256_burgers(M):
         assert np.array_equal(s.get_state(), want), i
         s.close()
     b.close()
+
+
+def _three_level_c2(M, c, precision):
+    s = M.Solver("D2Q9", c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("lcde", u=c["u"], K=c["K"], lambda_bar=1)
+    s.set_scheme("three_level", (7 / 8, 0.0, 1 / 8), (1 / 8, 0.0, -1 / 8), dt=c["dt"])
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_level_case3(M, c2, precision):
+    """The three-level scheme of Example 1 Case 3 on the 2048^2 workload, both
+    levels starting from phi0, autotuned plan: FP64 bit-exact with the oracle,
+    FP32 within 1e-5 (rel. L2)."""
+    steps = 13
+    x0 = c2["phi0"].astype(np.float32 if precision == "fp32" else np.float64)
+    spec = dict(_c2_spec(c2), a=(7 / 8, 0.0, 1 / 8), ah=(1 / 8, 0.0, -1 / 8), levels=3)
+    cur, prev = x0.astype(np.float64), x0.astype(np.float64)
+    for _ in range(steps):
+        cur, prev = O.mmfd_step(spec, cur, prev), cur
+    s = _three_level_c2(M, c2, precision)
+    s.set_state(x0)
+    s.set_state(x0, level=1)
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got, got_prev = s.get_state().astype(np.float64), s.get_state(level=1).astype(np.float64)
+    s.close()
+    if precision == "fp64":
+        assert np.array_equal(got, cur) and np.array_equal(got_prev, prev)
+    else:
+        assert _rel(got, cur) <= 1e-5 and _rel(got_prev, prev) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_source_example1_2048(M, precision):
+    """Example 1 with its source (three-level Case 2, b_-1 = 3/2, bh_-1 = -1/2)
+    on the 2048^2 grid the benchmark times: FP64 bit-exact with the oracle
+    over 6 steps in two calls, FP32 within 1e-5."""
+    import math
+    ex = I.example1_source_2d(n=2048)
+    a, ah = (7 / 8, 1 / 4, -1 / 8), (1 / 8, -1 / 4, 1 / 8)
+    coef = dict(b=(1.5, 0.0, 0.0), bh=(-0.5, 0.0, 0.0))
+    spec = dict(lattice="D2Q9", eq="lcde", n=ex["n"], dx=ex["dx"], dt=ex["dt"], u=ex["u"], K=ex["K"],
+                lambda_bar=1, a=a, ah=ah, levels=3)
+    dt, lam, G = ex["dt"], ex["lam"], ex["G"]
+    ftype = np.float32 if precision == "fp32" else np.float64
+    cur, prev = ex["phi0"].astype(ftype).astype(np.float64), ex["phim"].astype(ftype).astype(np.float64)
+    for k in range(6):
+        src = dict(coef, v=ex["u"], S_t=math.exp(lam * (k * dt)) * G,
+                   S_m=math.exp(lam * ((k - 1) * dt)) * G)
+        cur, prev = O.mmfd_step(spec, cur, prev, src), cur
+    s = M.Solver("D2Q9", ex["n"], ex["dx"], precision, "mmfd")
+    s.set_equation("lcde", u=ex["u"], K=ex["K"], lambda_bar=1)
+    s.set_scheme("three_level", a, ah, dt=dt)
+    s.set_state(ex["phi0"].astype(ftype))
+    s.set_state(ex["phim"].astype(ftype), level=1)
+    s.set_source(G, lam, coef["b"], coef["bh"], ex["u"])
+    s.step(4)
+    s.step(2)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    if precision == "fp64":
+        assert np.array_equal(got, cur)
+    else:
+        assert _rel(got, cur) <= 1e-5
