@@ -14,6 +14,8 @@ afford, and properties that hold at any size where it cannot.
 * 2048^2 three-level Example 1 Case 3 scheme (autotuned): FP64 bit-exact,
   both levels; FP32 within 1e-5.
 * 2048^2 Example 1 with its source: FP64 bit-exact, FP32 within 1e-5.
+* 2048^2 theta = 0.5 (4 Jacobi sweeps) and one 2048^2 Burgers grid
+  (autotuned): FP64 bit-exact, FP32 within 1e-5.
 """
 import numpy as np
 import pytest
@@ -281,3 +283,55 @@ def test_source_example1_2048(M, precision):
         assert np.array_equal(got, cur)
     else:
         assert _rel(got, cur) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_theta_2048(M, c2, precision):
+    """The theta = 0.5 scheme with 4 Jacobi sweeps per step on the 2048^2
+    workload: FP64 bit-exact with the oracle over 5 steps, FP32 within 1e-5."""
+    steps = 5
+    spec = dict(_c2_spec(c2), theta=0.5, theta_iters=4)
+    x0 = c2["phi0"].astype(np.float32 if precision == "fp32" else np.float64)
+    want = x0.astype(np.float64)
+    for _ in range(steps):
+        want = O.theta_step(spec, want)
+    s = M.Solver("D2Q9", c2["n"], c2["dx"], precision, "mmfd")
+    s.set_equation("lcde", u=c2["u"], K=c2["K"], lambda_bar=1)
+    s.set_scheme("theta", M.mfd_preset("srt")[0], theta=0.5, theta_iters=4, dt=c2["dt"])
+    s.set_state(x0)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    if precision == "fp64":
+        assert np.array_equal(got, want)
+    else:
+        assert _rel(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_burgers_2048(M, precision):
+    """One 2048^2 Burgers grid of the batched workload's recipe, autotuned plan:
+    FP64 bit-exact with the oracle over 25 steps, FP32 within 1e-5."""
+    rng = np.random.default_rng(6)
+    c = I.burgers_instance(rng, side_lo=2048, side_hi=2048, steps_lo=1000, steps_hi=1000)
+    a = M.mfd_preset("two_level", 2.0 * c["nu"] * c["dt"] / (D0 * c["dx"] ** 2))[0]
+    spec = dict(lattice="D2Q9", eq="burgers", n=c["n"], dx=c["dx"], dt=c["dt"], a=a, levels=2,
+                ah=(0.0, 0.0, 0.0))
+    steps = 25
+    x0 = c["phi0"].astype(np.float32 if precision == "fp32" else np.float64)
+    want = x0.astype(np.float64)
+    for _ in range(steps):
+        want = O.mmfd_step(spec, want)
+    s = M.Solver("D2Q9", c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("burgers")
+    s.set_scheme("two_level", a, dt=c["dt"])
+    s.set_state(x0)
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    if precision == "fp64":
+        assert np.array_equal(got, want)
+    else:
+        assert _rel(got, want) <= 1e-5
