@@ -5,7 +5,8 @@ afford, and properties that hold at any size where it cannot.
 * 2048^2 linear CDE (the headline workload): FP64 bit-exact with the oracle
   after two blocked launches' worth of steps plus a ragged remainder; FP32
   within 1e-5 (rel. L2) of the oracle.
-* 2048^2 MesoFD FP64: populations-carried moments bit-exact with the oracle.
+* 2048^2 MesoFD FP64: populations-carried moments bit-exact with the oracle,
+  also under the autotuned blocked plan (FP32 within 1e-5 there).
 * 4096^2 NSE three-level TRT: FP64 bit-exact, FP32 within 1e-5.
 * 512^3 NSE (D3Q19): mass and momentum conserved by the FP64 step (the
   periodic sum of the central-difference form), FP32 within 1e-6 of FP64.
@@ -335,3 +336,30 @@ def test_burgers_2048(M, precision):
         assert np.array_equal(got, want)
     else:
         assert _rel(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mesofd_autotuned_2048(M, c2, precision):
+    """MesoFD on the 2048^2 workload under the autotuned blocked plan the
+    benchmark times, 23 steps (two blocked launches and a ragged remainder at
+    the usual depths): FP64 moments and populations bit-exact with the
+    oracle, FP32 moments within 1e-5."""
+    steps = 23
+    spec = _c2_spec(c2)
+    x0 = c2["phi0"].astype(np.float32 if precision == "fp32" else np.float64)
+    pop = O.init_populations(spec, x0.astype(np.float64))
+    for _ in range(steps):
+        pop, _ = O.mesofd_step(spec, pop, None)
+    want = O.moments(spec, pop)
+    s = _c2_solver(M, c2, precision, "mesofd")
+    s.set_state(x0)
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    if precision == "fp64":
+        assert np.array_equal(got, want)
+        assert np.array_equal(s.get_state(populations=True), pop)
+    else:
+        assert _rel(got, want) <= 1e-5
+    s.close()
