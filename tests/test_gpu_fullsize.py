@@ -4,7 +4,7 @@ afford, and properties that hold at any size where it cannot.
 
 * 2048^2 linear CDE (the headline workload): FP64 bit-exact with the oracle
   after two blocked launches' worth of steps plus a ragged remainder; FP32
-  within 1e-5 (rel. L2) of the oracle.
+  within 1e-5 (rel. L2) of the oracle; the same at 8192^2.
 * 2048^2 MesoFD FP64: populations-carried moments bit-exact with the oracle,
   also under the autotuned blocked plan (FP32 within 1e-5 there).
 * 4096^2 NSE three-level TRT: FP64 bit-exact, FP32 within 1e-5.
@@ -363,3 +363,28 @@ def test_mesofd_autotuned_2048(M, c2, precision):
     else:
         assert _rel(got, want) <= 1e-5
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_headline_8192(M, precision):
+    """The 8192^2 grid of the same workload under its autotuned plan, 27 steps
+    (two blocked launches at depth 12 and a ragged remainder): FP32 within
+    1e-5 of the oracle, FP64 bit-exact."""
+    big = I.c2_hill_2d(n=8192)
+    steps = 27
+    x0 = big["phi0"].astype(np.float32 if precision == "fp32" else np.float64)
+    want = x0.astype(np.float64)
+    spec = _c2_spec(big)
+    for _ in range(steps):
+        want = O.mmfd_step(spec, want)
+    s = _c2_solver(M, big, precision)
+    s.set_state(x0)
+    s.autotune()
+    print("plan", s.launch_plan(), flush=True)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    if precision == "fp64":
+        assert np.array_equal(got, want)
+    else:
+        assert _rel(got, want) <= 1e-5
