@@ -14,7 +14,8 @@ afford, and properties that hold at any size where it cannot.
   alone (FP32, bit for bit), and the smallest grids equal the oracle (FP64).
 * 2048^2 three-level Example 1 Case 3 scheme (autotuned): FP64 bit-exact,
   both levels; FP32 within 1e-5.
-* 2048^2 Example 1 with its source: FP64 bit-exact, FP32 within 1e-5.
+* 2048^2 Example 1 with its source: FP64 bit-exact, FP32 within 1e-5; the
+  MesoFD form FP64 bit-exact (moments and populations).
 * 2048^2 theta = 0.5 (4 Jacobi sweeps) and one 2048^2 Burgers grid
   (autotuned): FP64 bit-exact, FP32 within 1e-5.
 """
@@ -388,3 +389,33 @@ def test_headline_8192(M, precision):
         assert np.array_equal(got, want)
     else:
         assert _rel(got, want) <= 1e-5
+
+
+def test_source_example1_mesofd_2048(M):
+    """The MesoFD form of the Example 1 step with its source on the 2048^2
+    grid the benchmark times: FP64 moments and populations bit-exact with the
+    oracle over 4 steps in two calls."""
+    import math
+    ex = I.example1_source_2d(n=2048)
+    a, ah = (7 / 8, 1 / 4, -1 / 8), (1 / 8, -1 / 4, 1 / 8)
+    coef = dict(b=(1.5, 0.0, 0.0), bh=(-0.5, 0.0, 0.0))
+    spec = dict(lattice="D2Q9", eq="lcde", n=ex["n"], dx=ex["dx"], dt=ex["dt"], u=ex["u"], K=ex["K"],
+                lambda_bar=1, a=a, ah=ah, levels=3)
+    pop, pm = O.init_populations(spec, ex["phi0"]), ex["phim"]
+    for k in range(4):
+        src = dict(coef, v=ex["u"], S_t=math.exp(ex["lam"] * (k * ex["dt"])) * ex["G"],
+                   S_m=math.exp(ex["lam"] * ((k - 1) * ex["dt"])) * ex["G"])
+        pop, pm = O.mesofd_step(spec, pop, pm, src)
+    want = O.moments(spec, pop)
+    s = M.Solver("D2Q9", ex["n"], ex["dx"], "fp64", "mesofd")
+    s.set_equation("lcde", u=ex["u"], K=ex["K"], lambda_bar=1)
+    s.set_scheme("three_level", a, ah, dt=ex["dt"])
+    s.set_state(ex["phi0"])
+    s.set_state(ex["phim"], level=1)
+    s.set_source(ex["G"], ex["lam"], coef["b"], coef["bh"], ex["u"])
+    s.step(1)
+    s.step(3)
+    got, gpop = s.get_state(), s.get_state(populations=True)
+    s.close()
+    assert np.array_equal(got, want)
+    assert np.array_equal(gpop, pop)
