@@ -59,6 +59,8 @@ extern "C" {
 #define MFD_E_HIP (-5)              /* HIP runtime failure (sticky)          */
 #define MFD_E_UNSTABLE (-6)         /* NaN / Inf found by a reduction        */
 #define MFD_E_BUDGET (-7)           /* request exceeds a memory budget       */
+#define MFD_E_CANCELLED (-8)        /* served request cancelled              */
+#define MFD_E_TIMEOUT (-9)          /* served request exceeded its timeout   */
 
 /* --------------------------------------------------------------- enums     */
 #define MFD_D1Q3 1   /* rD1Q3: e = 0, +1, -1;  w = 1-d0, d0/2, d0/2           */
@@ -355,16 +357,40 @@ typedef struct {
     int64_t result_bytes;
     int32_t exclude_from_stats; /* 1: not counted in the latency percentiles  */
     int32_t reserved;
+    double timeout_s;         /* > 0: fail with MFD_E_TIMEOUT once this long   */
+                              /* has passed since submission (checked at       */
+                              /* quantum boundaries); 0: no timeout            */
 } mfd_request;
 
-/* Create a server with a device-memory budget (bytes of solver state held at
- * once), a slot limit and a quantum.  Starts the scheduler thread. */
+/* Create a server with a device-memory budget, a slot limit and a quantum.
+ * Starts the scheduler thread.  A request holds, from admission to
+ * retirement, the device bytes of its solver (mfd_state_size: level ring,
+ * fourth level of blocked three-level steps, reduction scratch) plus one
+ * state level for the batch autotuner's copy and its batch tables; the sum
+ * over admitted requests never exceeds hbm_budget_bytes. */
 int mfd_server_create(mfd_server **out, int64_t hbm_budget_bytes, int32_t max_slots,
                       int64_t quantum_steps);
 
-/* Queue a request (thread-safe, non-blocking); *ticket identifies it.  A
- * request whose state can never fit the budget fails with MFD_E_BUDGET. */
+/* Queue a request (thread-safe, non-blocking); *ticket identifies it.  The
+ * request's configuration is checked here (host only): errors of
+ * mfd_create / mfd_set_lattice / mfd_set_equation / mfd_set_scheme are
+ * returned, MFD_E_UNSUPPORTED for a kind other than MFD_TWO_LEVEL /
+ * MFD_THREE_LEVEL or a lattice other than D2Q5 / D2Q9, MFD_E_ARG for a
+ * result buffer of the wrong size.  A request whose bytes can never fit the
+ * budget fails with MFD_E_BUDGET; one whose final level is not finite fails
+ * with MFD_E_UNSTABLE; a failed batch run fails the requests it held with its
+ * error.  A failed request frees its slot and budget without touching the
+ * others. */
 int mfd_server_submit(mfd_server *srv, const mfd_request *req, int64_t *ticket);
+
+/* Device bytes a request holds while admitted (the figure the budget is
+ * checked against); host only.  Errors as mfd_server_submit. */
+int mfd_server_request_bytes(const mfd_request *req, int64_t *bytes);
+
+/* Cancel a ticket: a queued request fails at once with MFD_E_CANCELLED, a
+ * running one at the next quantum boundary (its slot and budget are freed).
+ * MFD_E_ORDER if the request has already finished. */
+int mfd_server_cancel(mfd_server *srv, int64_t ticket);
 
 /* State of a ticket: 0 queued, 1 running, 2 done (result written), -1 failed
  * (the return value is then the error).  *latency_s: submission to result,
@@ -383,6 +409,11 @@ int mfd_server_stats(mfd_server *srv, double *p50_s, double *p99_s, double *req_
 
 /* Stop accepting work, finish the running requests, free everything. */
 int mfd_server_destroy(mfd_server *srv);
+
+/* Device bytes held now by every object of the library in this process, and
+ * the peak since the last reset (reset_peak = 1 sets the peak to the current
+ * figure after reading it).  Thread-safe. */
+int mfd_memory_stats(int64_t *in_use, int64_t *peak, int reset_peak);
 
 /* ------------------------------------------------------ host-side algebra */
 
@@ -408,6 +439,32 @@ int mfd_transport_coefficient(const double a[3], const double ah[3], double dx, 
  * (roots of lambda^2 - p1 lambda - p0 for three-level schemes, the theta
  * factor of Eq. (Tcond1-1) for MFD_THETA). */
 int mfd_max_amplification(mfd_solver *s, double *out);
+
+/* Largest stable time step of the two-level m = 1 MMFD scheme for the linear
+ * CDE with the linear EDF (D0 = I, beta = 1, lambda_bar = 0; Eq. (LMMFD-1))
+ * whose coefficients follow Eq. (LMMFD-2-2) for each dt (a_0 = 1 - s,
+ * a_{+-1} = (s -+ 1)/2, s = 2 alpha dt / (d0 dx^2)), isotropic diffusivity
+ * alpha > 0 and velocity u[3] (physical units; unused axes 0) on `lattice`
+ * with d0 (<= 0: 1/3):
+ *   *dt_sufficient = the bound of Eq. (LMMFD-2-3),
+ *                    min(d0 dx^2 / (2 alpha (1 - w0)), 2 alpha / |u|^2);
+ *   *dt_exact      = (when n and dt_exact are non-NULL) the largest dt with
+ *                    |lambda| <= 1 for every Fourier mode of the periodic
+ *                    grid n[0..dim-1] (Eq. (TforMMFD-3)), in closed form per
+ *                    mode; n may hold at most 2^24 nodes.
+ * Host only.  MFD_E_ARG for a bad lattice, d0, dx, alpha, u or n. */
+int mfd_max_stable_dt(int lattice, double d0, double dx, const double u[3], double alpha,
+                      const int64_t n[3], double *dt_sufficient, double *dt_exact);
+
+/* Device address of the current storage of a time level: level 0 = t^n,
+ * level 1 = t^(n-1) (three-level schemes), moment field `field` (0..nf-1),
+ * or with populations = 1 (MesoFD, level 0) population j = field.  The
+ * address is owned by the solver and stays valid until the next call that
+ * steps or sets the state (mfd_step rotates the level roles among the
+ * solver's buffers); it is device memory holding G.N elements of the
+ * solver's precision, x fastest.  MFD_E_ORDER before the state is set,
+ * MFD_E_ARG for a level, field or population request that does not exist. */
+int mfd_level_ptr(mfd_solver *s, int level, int field, int populations, void **ptr);
 
 /* Per-pair linear EDF constants of the configured LCDE (for checks):
  * ubar[b] (full EDF per unit phi), and per opposite pair p:

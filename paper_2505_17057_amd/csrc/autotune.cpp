@@ -97,10 +97,10 @@ int Solver::autotune(int32_t *chosen) {
   const size_t pbytes = meso ? (size_t)(pop_elems() * elem()) : 0;
   void *save[3] = {nullptr, nullptr, nullptr};
   for (int k = 0; k < (meso ? 3 : 2); ++k) {
-    hipError_t e = hipMalloc(&save[k], k == 2 ? pbytes : bytes);
+    hipError_t e = dev_malloc(&save[k], k == 2 ? pbytes : bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      for (int j = 0; j < k; ++j) (void)hipFree(save[j]);
+      for (int j = 0; j < k; ++j) dev_free(save[j]);
       return fail(MFD_E_OOM, "autotune: no memory for the state copy");
     }
   }
@@ -180,7 +180,7 @@ int Solver::autotune(int32_t *chosen) {
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   for (void *p : save)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   if (rc) return rc;
   tuned = best;
   {

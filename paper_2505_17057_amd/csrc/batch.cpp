@@ -44,9 +44,9 @@ void Batch::free_graph() {
 
 void Batch::free_groups() {
   for (auto &g : groups) {
-    if (g.d_inst) (void)hipFree(g.d_inst);
-    if (g.d_tile_inst) (void)hipFree(g.d_tile_inst);
-    if (g.d_lane) (void)hipFree(g.d_lane);
+    if (g.d_inst) dev_free(g.d_inst);
+    if (g.d_tile_inst) dev_free(g.d_tile_inst);
+    if (g.d_lane) dev_free(g.d_lane);
   }
   groups.clear();
 }
@@ -104,10 +104,10 @@ int Batch::make_tables(Group &g) {
   }
   g.ntiles = (int)tile_inst.size();
   if (g.ntiles > g.tile_cap) {
-    if (g.d_tile_inst) (void)hipFree(g.d_tile_inst);
+    if (g.d_tile_inst) dev_free(g.d_tile_inst);
     g.d_tile_inst = nullptr;
     g.tile_cap = 0;
-    int rc = hip(hipMalloc((void **)&g.d_tile_inst, sizeof(int) * (size_t)g.ntiles), "hipMalloc (tiles)");
+    int rc = hip(dev_malloc((void **)&g.d_tile_inst, sizeof(int) * (size_t)g.ntiles), "hipMalloc (tiles)");
     if (rc) return rc;
     g.tile_cap = g.ntiles;
   }
@@ -161,10 +161,10 @@ int Batch::build() {
     }
     const size_t isz = g.key.precision == MFD_FP64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
     g.inst_bytes = isz * g.order.size();
-    int rc = hip(hipMalloc(&g.d_inst, g.inst_bytes), "hipMalloc (instances)");
+    int rc = hip(dev_malloc(&g.d_inst, g.inst_bytes), "hipMalloc (instances)");
     if (!rc && lane_batch_applies(g.key)) {
       g.lane_bytes = lane_inst_bytes(g.key) * g.order.size();
-      rc = hip(hipMalloc(&g.d_lane, g.lane_bytes), "hipMalloc (lane instances)");
+      rc = hip(dev_malloc(&g.d_lane, g.lane_bytes), "hipMalloc (lane instances)");
       g.h_lane.resize(g.lane_bytes);
     }
     if (!rc) rc = make_tables(g);
@@ -410,7 +410,7 @@ int Batch::autotune() {
     int64_t total = 0;
     for (int i : g.order) total += entries[i].s->mom_elems();
     void *save = nullptr;
-    rc = hip(hipMalloc(&save, (size_t)total * es), "hipMalloc (autotune copy)");
+    rc = hip(dev_malloc(&save, (size_t)total * es), "hipMalloc (autotune copy)");
     if (rc) break;
     int64_t off = 0;
     for (int i : g.order) {
@@ -476,7 +476,7 @@ int Batch::autotune() {
       off += (int64_t)b;
     }
     if (!rc) rc = hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    (void)hipFree(save);
+    dev_free(save);
     if (!rc) tuned[g.key] = best_p;
   }
   if (e0) (void)hipEventDestroy(e0);

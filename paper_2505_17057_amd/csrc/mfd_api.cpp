@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <vector>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "../../include/mfd.h"
 #include "mfd_internal.h"
@@ -18,6 +20,32 @@
 using namespace mfd;
 
 namespace mfd {
+
+namespace {
+std::mutex g_alloc_mu;
+std::unordered_map<void *, size_t> g_alloc;
+int64_t g_alloc_now = 0, g_alloc_peak = 0;
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc[*p] = bytes;
+  g_alloc_now += (int64_t)bytes;
+  if (g_alloc_now > g_alloc_peak) g_alloc_peak = g_alloc_now;
+  return e;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  auto it = g_alloc.find(p);
+  if (it == g_alloc.end()) return;
+  g_alloc_now -= (int64_t)it->second;
+  g_alloc.erase(it);
+}
 
 int Solver::fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -55,7 +83,7 @@ int64_t Solver::device_bytes_needed() const {
 
 void Solver::release() {
   for (auto &p : buf) {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
   }
   allocated_bytes = 0;
@@ -72,7 +100,7 @@ int Solver::ensure_buffers() {
   if (!(grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))) sizes[8] = 0;
   for (int i = 0; i < kNumBuf; ++i) {
     if (sizes[i] == 0) continue;
-    hipError_t e = hipMalloc(&buf[i], (size_t)sizes[i]);
+    hipError_t e = dev_malloc(&buf[i], (size_t)sizes[i]);
     if (e != hipSuccess) {
       release();
       (void)hipGetLastError();
@@ -324,8 +352,16 @@ extern "C" int mfd_destroy(mfd_solver *h) {
   Solver *s = reinterpret_cast<Solver *>(h);
   if (s->buf[0] || s->d_src) (void)hipStreamSynchronize(s->stream);
   s->release();
-  if (s->d_src) (void)hipFree(s->d_src);
+  if (s->d_src) dev_free(s->d_src);
   delete s;
+  return MFD_OK;
+}
+
+extern "C" int mfd_memory_stats(int64_t *in_use, int64_t *peak, int reset_peak) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (in_use) *in_use = g_alloc_now;
+  if (peak) *peak = g_alloc_peak;
+  if (reset_peak) g_alloc_peak = g_alloc_now;
   return MFD_OK;
 }
 
@@ -435,6 +471,19 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
     const double v[4] = {a[k], ah ? ah[k] : 0.0, ab ? ab[k] : a[k], abh ? abh[k] : (ah ? ah[k] : 0.0)};
     for (double x : v)
       if (!std::isfinite(x)) return s->fail(MFD_E_ARG, "non-finite coefficient");
+  }
+  if (kind == MFD_THREE_LEVEL && s->grid.precision == MFD_FP32) {
+    // the binary32 kernels form the base as phi - Ah0 (phi - phi^(n-1)) in
+    // binary64, which is A0 phi + Ah0 phi^(n-1) only when A0 + Ah0 = 1
+    // (A00 = 1 of Eq. (4-2-00a)); the momentum set likewise
+    const double *sets[2][2] = {{a, ah}, {ab ? ab : a, abh ? abh : ah}};
+    for (auto &st : sets) {
+      const double A0 = st[0][0] + st[0][1] + st[0][2];
+      const double Ah0 = st[1][0] + st[1][1] + st[1][2];
+      if (std::fabs(A0 + Ah0 - 1.0) > 1e-12)
+        return s->fail(MFD_E_UNSUPPORTED,
+                       "binary32 three-level schemes need A0 + Ah0 = 1 (got %.17g)", A0 + Ah0);
+    }
   }
   if (s->grid.form == MFD_MESOFD && (ab || abh)) {
     for (int k = 0; k < 3; ++k)
@@ -695,11 +744,11 @@ extern "C" int mfd_set_source(mfd_solver *h, const double *G, int64_t count, int
   const int64_t es = s->elem();
   if (s->d_src) {
     (void)hipStreamSynchronize(s->stream);
-    (void)hipFree(s->d_src);
+    dev_free(s->d_src);
     s->d_src = nullptr;
     s->src_on = false;
   }
-  if (hipMalloc(&s->d_src, (size_t)(N * es)) != hipSuccess) {
+  if (dev_malloc(&s->d_src, (size_t)(N * es)) != hipSuccess) {
     (void)hipGetLastError();
     s->d_src = nullptr;
     return s->fail(MFD_E_OOM, "no device memory for the source field");
@@ -729,7 +778,7 @@ extern "C" int mfd_clear_source(mfd_solver *h) {
   Solver *s = reinterpret_cast<Solver *>(h);
   if (s->d_src) {
     (void)hipStreamSynchronize(s->stream);
-    (void)hipFree(s->d_src);
+    dev_free(s->d_src);
   }
   s->d_src = nullptr;
   s->src_on = false;
@@ -771,4 +820,51 @@ extern "C" int mfd_linear_tables(mfd_solver *h, double *w, double *ubar, double 
       out6[5 * kMaxP + p] = c.Chm[p];
     }
   return c.q;
+}
+
+extern "C" int mfd_max_stable_dt(int lattice, double d0, double dx, const double u[3],
+                                 double alpha, const int64_t n[3], double *dt_sufficient,
+                                 double *dt_exact) {
+  if (!u || !dt_sufficient || !(dx > 0.0) || !(alpha > 0.0) || !std::isfinite(dx) ||
+      !std::isfinite(alpha))
+    return MFD_E_ARG;
+  if (d0 <= 0.0) d0 = 1.0 / 3.0;
+  if (!(d0 < 1.0)) return MFD_E_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(u[a])) return MFD_E_ARG;
+  int64_t N = 1;
+  if (n && dt_exact) {
+    Consts c;
+    std::memset(&c, 0, sizeof(c));
+    if (lattice_weights(lattice, d0, c) != MFD_OK) return MFD_E_ARG;
+    for (int a = 0; a < c.dim; ++a) {
+      if (n[a] < 1) return MFD_E_ARG;
+      N *= n[a];
+    }
+    if (N > ((int64_t)1 << 24)) return MFD_E_ARG;
+  }
+  double s = 0.0, e = 0.0;
+  if (max_stable_dt(lattice, d0, dx, u, alpha, dt_exact ? n : nullptr, &s, &e) != 0)
+    return MFD_E_ARG;
+  *dt_sufficient = s;
+  if (n && dt_exact) *dt_exact = e;
+  return MFD_OK;
+}
+
+extern "C" int mfd_level_ptr(mfd_solver *h, int level, int field, int populations, void **ptr) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!ptr) return s->fail(MFD_E_ARG, "null output");
+  if (!s->state_set) return s->fail(MFD_E_ORDER, "state not set");
+  if (level != 0 && level != 1) return s->fail(MFD_E_ARG, "level must be 0 or 1");
+  if (level == 1 && !s->consts.three)
+    return s->fail(MFD_E_ARG, "level 1 exists only for three-level schemes");
+  const bool meso = s->grid.form == MFD_MESOFD;
+  if (populations && (!meso || level != 0))
+    return s->fail(MFD_E_ARG, "populations exist only for MesoFD level 0");
+  const int64_t nfld = populations ? s->q() : s->nf();
+  if (field < 0 || field >= nfld) return s->fail(MFD_E_ARG, "field %d out of range", field);
+  char *base = (char *)s->buf[populations ? s->pc : (level == 0 ? s->ic : s->ip)];
+  *ptr = base + (int64_t)field * s->G.N * s->elem();
+  return MFD_OK;
 }

@@ -88,6 +88,12 @@ struct KC {
 template <typename T>
 KC<T> make_kc(const Consts &c);
 
+// ------------------------------------------------------ device allocations
+// Every device allocation of the library goes through these two calls, which
+// count the bytes held (now and at peak) for mfd_memory_stats.
+hipError_t dev_malloc(void **p, size_t bytes);
+void dev_free(void *p);
+
 // ------------------------------------------------------ kernel launchers
 // Each returns a hipError_t of the launch.  `cur`/`prev`/`out` are moment
 // levels (field-major); n = (nx, ny, nz).

@@ -8,6 +8,7 @@
 // Every constant is formed in binary64 in a fixed expression order (left to
 // right as written); the FP64 kernels consume them unchanged.
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -296,6 +297,53 @@ double max_amplification(const Consts &c, const int64_t n[3]) {
         best = std::max(best, r);
       }
   return best;
+}
+
+// Largest stable time step of the two-level m = 1 family with the linear EDF
+// (D0 = I, beta = 1, lambda_bar = 0) and the coefficients of Eq. (LMMFD-2-2):
+// a_0 = 1 - s, a_{+-1} = (s -+ 1)/2 with s = 2 alpha dt / (d0 dx^2), so
+// ubar+_j = w_j and ubar-_j = w_j e_j.u dt / (d0 dx).
+//  * sufficient: Eq. (LMMFD-2-3), |u|^2 <= 2 alpha / dt <= c_s^2 / (1 - w0)
+//    with c_s^2 = d0 dx^2 / dt^2;
+//  * exact: for a grid mode xi the factor of Eq. (TforMMFD-3) is
+//    lambda = 1 - kappa dt X - i dt Y, X = sum_j w_j (1 - cos xi_j) >= 0,
+//    Y = sum_j w_j (e_j.u / (d0 dx)) sin xi_j, kappa = 2 alpha / (d0 dx^2);
+//    |lambda| <= 1 holds exactly for dt <= 2 kappa X / (kappa^2 X^2 + Y^2),
+//    so the bound over the periodic grid's modes is the smallest such dt
+//    (modes with X = 0 have lambda = 1).
+int max_stable_dt(int lattice, double d0, double dx, const double u[3], double alpha,
+                  const int64_t *n, double *dt_suff, double *dt_exact) {
+  Consts c;
+  std::memset(&c, 0, sizeof(c));
+  if (lattice_weights(lattice, d0, c) != 0) return -1;
+  double u2 = 0.0;
+  for (int a = 0; a < c.dim; ++a) u2 += u[a] * u[a];
+  const double t1 = d0 * dx * dx / (2.0 * alpha * (1.0 - c.w[0]));
+  *dt_suff = u2 == 0.0 ? t1 : std::min(t1, 2.0 * alpha / u2);
+  if (!n || !dt_exact) return 0;
+  const int64_t nx = n[0], ny = c.dim > 1 ? n[1] : 1, nz = c.dim > 2 ? n[2] : 1;
+  const double kappa = 2.0 * alpha / (d0 * dx * dx);
+  const double tp = 2.0 * M_PI;
+  double best = HUGE_VAL;
+  for (int64_t mz = 0; mz < nz; ++mz)
+    for (int64_t my = 0; my < ny; ++my)
+      for (int64_t mx = 0; mx < nx; ++mx) {
+        const double xi[3] = {tp * mx / nx, tp * my / ny, tp * mz / nz};
+        double X = 0.0, Y = 0.0;
+        for (int j = 1; j < c.q; ++j) {
+          double ph = 0.0, eu = 0.0;
+          for (int a = 0; a < c.dim; ++a) {
+            ph += c.e[j][a] * xi[a];
+            eu += c.e[j][a] * u[a];
+          }
+          X += c.w[j] * (1.0 - std::cos(ph));
+          Y += c.w[j] * eu / (d0 * dx) * std::sin(ph);
+        }
+        if (X <= 1e-300) continue;
+        best = std::min(best, 2.0 * kappa * X / (kappa * kappa * X * X + Y * Y));
+      }
+  *dt_exact = best;
+  return 0;
 }
 
 }  // namespace mfd

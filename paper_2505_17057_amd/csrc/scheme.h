@@ -25,5 +25,7 @@ int lattice_weights(int lattice, double d0, Consts &c);
 int build_consts(const SchemeInput &in, Consts &c);
 bool stability_proven(const Consts &c);
 double max_amplification(const Consts &c, const int64_t n[3]);
+int max_stable_dt(int lattice, double d0, double dx, const double u[3], double alpha,
+                  const int64_t *n, double *dt_suff, double *dt_exact);
 
 }  // namespace mfd

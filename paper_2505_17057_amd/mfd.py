@@ -36,6 +36,8 @@ MFD_E_OOM = -4
 MFD_E_HIP = -5
 MFD_E_UNSTABLE = -6
 MFD_E_BUDGET = -7
+MFD_E_CANCELLED = -8
+MFD_E_TIMEOUT = -9
 
 LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
 DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
@@ -69,7 +71,8 @@ class mfd_request(C.Structure):
                 ("dt", C.c_double), ("ep", mfd_eq_params), ("a", C.c_double * 3),
                 ("ah", C.c_double * 3), ("nsteps", C.c_int64), ("state0", C.c_void_p),
                 ("prev0", C.c_void_p), ("result_out", C.c_void_p), ("result_bytes", C.c_int64),
-                ("exclude_from_stats", C.c_int32), ("reserved", C.c_int32)]
+                ("exclude_from_stats", C.c_int32), ("reserved", C.c_int32),
+                ("timeout_s", C.c_double)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -107,6 +110,10 @@ _SIGS = {
     "mfd_preset": ([C.c_int, C.c_double, _PD, _PD], C.c_int),
     "mfd_transport_coefficient": ([_PD, _PD, C.c_double, C.c_double, C.c_double, C.c_double, _PD], C.c_int),
     "mfd_max_amplification": ([_H, _PD], C.c_int),
+    "mfd_max_stable_dt": ([C.c_int, C.c_double, C.c_double, _PD, C.c_double, C.POINTER(C.c_int64),
+                           _PD, _PD], C.c_int),
+    "mfd_level_ptr": ([_H, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "mfd_memory_stats": ([C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int], C.c_int),
     "mfd_batch_create": ([C.POINTER(_H)], C.c_int),
     "mfd_batch_destroy": ([_H], C.c_int),
     "mfd_batch_last_error": ([_H], C.c_char_p),
@@ -124,6 +131,8 @@ _SIGS = {
     "mfd_server_create": ([C.POINTER(_H), C.c_int64, C.c_int32, C.c_int64], C.c_int),
     "mfd_server_submit": ([_H, C.POINTER(mfd_request), C.POINTER(C.c_int64)], C.c_int),
     "mfd_server_poll": ([_H, C.c_int64, C.POINTER(C.c_int32), _PD], C.c_int),
+    "mfd_server_cancel": ([_H, C.c_int64], C.c_int),
+    "mfd_server_request_bytes": ([C.POINTER(mfd_request), C.POINTER(C.c_int64)], C.c_int),
     "mfd_server_drain": ([_H, C.c_double], C.c_int),
     "mfd_server_stats": ([_H, _PD, _PD, _PD, C.POINTER(C.c_int64), _PD], C.c_int),
     "mfd_server_destroy": ([_H], C.c_int),
@@ -171,6 +180,21 @@ def mfd_transport_coefficient(a, ah, dx, dt, d0=1.0 / 3.0, beta=1.0):
     if rc:
         raise MfdError(rc, "mfd_transport_coefficient")
     return out.value
+
+
+def mfd_max_stable_dt(lattice, dx, u, alpha, n=None, d0=1.0 / 3.0):
+    """(dt_sufficient, dt_exact or None) of mfd_max_stable_dt."""
+    uu = list(u) + [0.0] * (3 - len(u))
+    s, e = C.c_double(), C.c_double()
+    nn = None
+    if n is not None:
+        n3 = list(n) + [1] * (3 - len(n))
+        nn = (C.c_int64 * 3)(*[int(v) for v in n3])
+    rc = lib.mfd_max_stable_dt(LATTICES[lattice], float(d0), float(dx), _d3(uu), float(alpha), nn,
+                               C.byref(s), C.byref(e) if n is not None else None)
+    if rc:
+        raise MfdError(rc, "mfd_max_stable_dt")
+    return s.value, (e.value if n is not None else None)
 
 
 def _ptr_of(x):
@@ -326,6 +350,12 @@ class Solver:
         self.check(lib.mfd_autotune(self.h, C.byref(d)), "mfd_autotune")
         return d.value
 
+    def level_ptr(self, level=0, field=0, populations=False):
+        p = C.c_void_p()
+        self.check(lib.mfd_level_ptr(self.h, int(level), int(field), 1 if populations else 0,
+                                     C.byref(p)), "mfd_level_ptr")
+        return p.value
+
     def max_amplification(self):
         out = C.c_double()
         self.check(lib.mfd_max_amplification(self.h, C.byref(out)), "mfd_max_amplification")
@@ -412,7 +442,7 @@ class Batch:
 
 def make_request(lattice, eq, n, dx, dt, a, nsteps, state0, ah=None, kind="two_level",
                  precision="fp32", u=(), K=None, lambda_bar=0, beta=1.0, rho0=0.0, he_luo=0,
-                 result_out=None, prev0=None, exclude=False, d0=1.0 / 3.0):
+                 result_out=None, prev0=None, exclude=False, d0=1.0 / 3.0, timeout_s=0.0):
     """Fill an mfd_request; the arrays must stay alive until the request is done."""
     r = mfd_request()
     r.lattice = LATTICES[lattice]
@@ -444,7 +474,24 @@ def make_request(lattice, eq, n, dx, dt, a, nsteps, state0, ah=None, kind="two_l
     r.result_out = result_out.ctypes.data if result_out is not None else None
     r.result_bytes = result_out.nbytes if result_out is not None else 0
     r.exclude_from_stats = 1 if exclude else 0
+    r.timeout_s = float(timeout_s)
     return r
+
+
+def server_request_bytes(req):
+    """Device bytes a request holds while admitted (mfd_server_request_bytes)."""
+    b = C.c_int64()
+    rc = lib.mfd_server_request_bytes(C.byref(req), C.byref(b))
+    if rc:
+        raise MfdError(rc, "mfd_server_request_bytes")
+    return b.value
+
+
+def memory_stats(reset_peak=False):
+    """Device bytes the library holds now and at peak (mfd_memory_stats)."""
+    a, b = C.c_int64(), C.c_int64()
+    lib.mfd_memory_stats(C.byref(a), C.byref(b), 1 if reset_peak else 0)
+    return a.value, b.value
 
 
 class Server:
@@ -471,6 +518,9 @@ class Server:
         lat = C.c_double()
         rc = lib.mfd_server_poll(self.h, int(ticket), C.byref(st), C.byref(lat))
         return st.value, lat.value, rc
+
+    def cancel(self, ticket):
+        return lib.mfd_server_cancel(self.h, int(ticket))
 
     def drain(self, timeout_s=600.0):
         rc = lib.mfd_server_drain(self.h, float(timeout_s))

@@ -203,3 +203,61 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError, match="libmfd.so is not built"):
         spec.loader.exec_module(mod)
+
+
+@pytest.mark.parametrize("lat,n,u,alpha,dx", [
+    ("D1Q3", (1024,), (0.1,), 0.01, 1.0 / 1024),
+    ("D1Q3", (64,), (2.0,), 0.05, 1.0 / 64),
+    ("D2Q9", (24, 20), (0.9, 0.7), 0.02, 0.05),
+    ("D2Q5", (16, 18), (0.3, -0.2), 0.01, 0.1),
+    ("D3Q19", (6, 5, 4), (0.2, 0.1, -0.3), 0.01, 0.1),
+])
+def test_max_stable_dt_matches_oracle(M, lat, n, u, alpha, dx):
+    """mfd_max_stable_dt: the sufficient bound equals Eq. (LMMFD-2-3) of the
+    oracle's algebra; the exact bound sits where the oracle's Fourier symbol
+    of the m = 1 two-level family (Eq. (LMMFD-2-2) coefficients, linear EDF)
+    crosses |lambda| = 1 on the same periodic grid."""
+    _, w, pairs = O.lattice_info(lat)
+    E, _, _ = O.lattice_info(lat)
+    d0 = 1.0 / 3.0
+    suff, exact = M.mfd_max_stable_dt(lat, dx, u, alpha, n=n)
+    want = S.linear_edf_bound_dt(alpha, np.array(u, dtype=float), dx, (d0, w[0]))
+    assert suff == pytest.approx(want, rel=1e-15)
+    assert exact >= suff * (1 - 1e-12)  # Eq. (LMMFD-2-3) is sufficient
+
+    def amp(dt):
+        s = 2 * alpha * dt / (d0 * dx * dx)
+        a = ((s + 1) / 2, 1 - s, (s - 1) / 2)  # a_{-1}, a_0, a_1
+        uh = np.array(list(u) + [0.0] * (3 - len(u))) * dt / dx
+        ubp = [w[j] for j in pairs]
+        ubm = [w[j] * float(np.dot(E[j], uh)) / d0 for j in pairs]
+        return S.max_amplification(E, pairs, ubp, ubm, n, a, (0.0, 0.0, 0.0))
+
+    assert amp(exact * (1 - 1e-9)) <= 1 + 1e-12
+    assert amp(exact * (1 + 1e-6)) > 1 + 1e-13
+    assert amp(suff) <= 1 + 1e-12
+
+
+def test_c1_time_step_is_half_the_library_bound(M):
+    """The 1D workload's dt = 25 * 2^-20 is half the Eq. (LMMFD-2-3) bound the
+    library reports for D1Q3, N = 1024, u = 0.1, D = 0.01."""
+    from mfd_inputs import c1_linear_1d
+
+    c1 = c1_linear_1d()
+    suff, _ = M.mfd_max_stable_dt("D1Q3", c1["dx"], c1["u"], c1["D"])
+    assert 0.5 * suff == pytest.approx(c1["dt"], rel=1e-14)
+
+
+def test_max_stable_dt_argument_checks(M):
+    import ctypes as C
+
+    d = C.c_double()
+    u = (C.c_double * 3)(0.1, 0.0, 0.0)
+    assert M.lib.mfd_max_stable_dt(1, 0.0, 0.0, u, 0.01, None, C.byref(d), None) == M.MFD_E_ARG
+    assert M.lib.mfd_max_stable_dt(1, 0.0, 0.1, u, -1.0, None, C.byref(d), None) == M.MFD_E_ARG
+    assert M.lib.mfd_max_stable_dt(9, 0.0, 0.1, u, 0.01, None, C.byref(d), None) == M.MFD_E_ARG
+    assert M.lib.mfd_max_stable_dt(1, 0.0, 0.1, None, 0.01, None, C.byref(d), None) == M.MFD_E_ARG
+    big = (C.c_int64 * 3)(1 << 13, 1 << 13, 1)
+    e = C.c_double()
+    assert M.lib.mfd_max_stable_dt(3, 0.0, 0.1, u, 0.01, big, C.byref(d), C.byref(e)) == M.MFD_E_ARG
+

@@ -108,12 +108,12 @@ def test_batch_fp32_equals_solo(M):
         s.close()
 
 
-def _request(M, c, state, out, exclude=False):
+def _request(M, c, state, out, exclude=False, precision="fp32", prev=None, timeout_s=0.0):
     return M.make_request(c["lattice"], c["eq"], c["n"], c.get("dx", 1.0), c.get("dt", 1.0), c["a"],
                           c["steps"], state, ah=c.get("ah"), kind=c.get("kind", "two_level"),
-                          precision="fp32", u=c.get("u", ()), K=c.get("K"),
+                          precision=precision, u=c.get("u", ()), K=c.get("K"),
                           lambda_bar=c.get("lambda_bar", 0), rho0=c.get("rho0", 0.0),
-                          result_out=out, exclude=exclude)
+                          result_out=out, exclude=exclude, prev0=prev, timeout_s=timeout_s)
 
 
 def test_server_alone_equals_mixed(M):
@@ -151,7 +151,9 @@ def test_server_alone_equals_mixed(M):
 def test_server_budget(M):
     c = batch_cases()[0]
     st = np.random.default_rng(1).uniform(-0.5, 0.5, c["n"][0] * c["n"][1]).astype(np.float32)
-    one = 3 * st.nbytes + (64 << 10)
+    out0 = np.empty_like(st)
+    one = M.server_request_bytes(_request(M, c, st, out0))
+    assert one > 3 * st.nbytes
     srv = M.Server(hbm_budget_bytes=2 * one, max_slots=16, quantum_steps=2)
     outs = [np.empty_like(st) for _ in range(6)]
     ts = [srv.submit(_request(M, c, st, o), keep=(st, o)) for o in outs]
