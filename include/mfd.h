@@ -77,6 +77,10 @@ extern "C" {
 #define MFD_LCDE 0
 #define MFD_BURGERS 1
 #define MFD_NSE 2
+#define MFD_WAVE 3   /* wave equation, Eq. (ME-NCDE-W-1): EDF of Example 3   */
+
+#define MFD_PERIODIC 0
+#define MFD_DIRICHLET 1 /* 2D MMFD: edge nodes hold prescribed values        */
 
 #define MFD_TWO_LEVEL 0   /* explicit, level t only (ah = 0)                 */
 #define MFD_THETA 1       /* two-level theta scheme, Eq. (GCN), LCDE only   */
@@ -94,25 +98,35 @@ typedef struct {
     int32_t dim;        /* 1, 2 or 3; must match the lattice                 */
     int32_t precision;  /* MFD_FP64 / MFD_FP32                               */
     int32_t form;       /* MFD_MMFD / MFD_MESOFD                             */
-    int32_t reserved;   /* must be 0                                         */
+    int32_t boundary;   /* MFD_PERIODIC, or MFD_DIRICHLET (2D, MMFD form)    */
     int64_t n[3];       /* nodes along x, y, z (unused axes: 1); >= 3 each   */
     double dx;          /* node spacing (square / cubic grid), > 0           */
 } mfd_grid;
 
+/* Equation parameters.  MFD_WAVE (phi_tt = alpha Laplacian phi) uses the EDF
+ * f_j = w_j phi [1 + (beta - 1)(|e_j|^2 - dim d0) / (2 d0)] printed with
+ * Example 3 (beta > 0; 0 selects 1) and the linear-CDE kernels; its wave
+ * coefficient is alpha = A22 beta c_s^2 (Eq. (ME-NCDE-W-1)), set through the
+ * coefficients (e.g. a = (gamma, 2(1 - gamma), gamma), ah = (0, -1, 0),
+ * gamma = alpha / (beta c_s^2), after Eq. (4-2-00)). */
 typedef struct {
     double u[3];        /* LCDE: constant advection velocity (physical)      */
     double K[9];        /* LCDE: diffusion tensor, row-major 3 x 3           */
     int32_t lambda_bar; /* LCDE: 0 or 1, the u u term of Eq. (TforMMFD-0)    */
     int32_t he_luo;     /* NSE: 1 selects g(rho, rho0 u, rho0 u u)           */
-    double beta;        /* Burgers: D = phi I scaled by beta (1 = default)   */
+    double beta;        /* Burgers: D = phi I scaled by beta (1 = default);  */
+                        /* wave: the EDF's beta                              */
     double rho0;        /* NSE: reference density stored apart from rho      */
 } mfd_eq_params;
 
 /* ---------------------------------------------------------- solver set-up */
 
-/* Create a solver for a periodic grid.  *out receives an owned handle to be
- * released with mfd_destroy.  Errors: MFD_E_ARG (null pointers, dim/n/dx out
- * of range, unknown precision or form). */
+/* Create a solver for a periodic grid, or (boundary = MFD_DIRICHLET, 2D,
+ * MMFD form) a grid whose edge nodes (x or y = 0 or n - 1) hold prescribed
+ * values (mfd_set_boundary) and whose other nodes are updated by the scheme.
+ * *out receives an owned handle to be released with mfd_destroy.  Errors:
+ * MFD_E_ARG (null pointers, dim/n/dx out of range, unknown precision, form or
+ * boundary), MFD_E_UNSUPPORTED (Dirichlet outside 2D MMFD). */
 int mfd_create(mfd_solver **out, const mfd_grid *g);
 
 /* Release the solver and every device buffer it owns.  Never frees memory
@@ -146,6 +160,27 @@ int mfd_set_equation(mfd_solver *s, int eq, const mfd_eq_params *p);
 int mfd_set_scheme(mfd_solver *s, int kind, const double a[3], const double ah[3],
                    const double ab[3], const double abh[3], double theta,
                    int32_t theta_iters, double dt);
+
+/* Solve every theta step (Eq. (GCN), Theorem 2) to a residual tolerance:
+ * Jacobi sweeps started from phi(t), checked after every `chunk` sweeps
+ * (0: 8; at most 16), stopping at the first check where
+ *     den^2 sum_x (x_k - x_(k-1))^2 <= tol^2 sum_x rhs^2
+ * (den (x_k - x_(k-1)) is the residual rhs - (I - (1-theta) L) x_(k-1);
+ * den = 1 + (1-theta) 2 sum_p (a_1 + a_-1) ubar+_p; sums in binary64), or at
+ * the first check at or beyond theta_iters sweeps (the cap), returning x_k.
+ * tol = 0 restores the fixed count of theta_iters sweeps.  On 2D D2Q5 / D2Q9
+ * grids of at least 64 x 32 nodes the stop is decided on the device (no host
+ * round trip per step); other grids check on the host after each chunk.
+ * Suggested tolerances: 1e-12 (binary64), 1e-6 (binary32).  MFD_E_ORDER
+ * unless a theta scheme is set, MFD_E_ARG for tol < 0, chunk outside
+ * [0, 16] or a cap below 1. */
+int mfd_set_theta_tolerance(mfd_solver *s, double tol, int32_t chunk);
+
+/* Sweeps taken by the to-tolerance theta solves since the last reset: total,
+ * time steps, the most in one step and the steps stopped by the cap before
+ * the tolerance held.  Synchronous; reset = 1 zeroes the counters. */
+int mfd_theta_stats(mfd_solver *s, int64_t *total_sweeps, int64_t *steps, int32_t *max_sweeps,
+                    int32_t *unconverged, int reset);
 
 /* Enqueue all further work of this solver on the HIP stream `stream`
  * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL =
@@ -204,6 +239,35 @@ int mfd_step(mfd_solver *s, int64_t nsteps);
  * MFD_E_ARG for a null G, a wrong count or non-finite values, MFD_E_OOM. */
 int mfd_set_source(mfd_solver *s, const double *G, int64_t count, int on_device, double lambda,
                    const double b[3], const double bh[3], const double v[3]);
+
+/* Dirichlet values of a boundary = MFD_DIRICHLET grid (the grids of Example 3
+ * of the paper): at time t = n dt (n the steps taken since the last level-0
+ * mfd_set_state, as for the source term) every edge node holds
+ * G(x) exp(lambda t); each step writes the values of its new level (binary32
+ * grids: the binary64 product rounded once).  G holds nx * ny binary64
+ * values, x fastest (host, or device memory when on_device); only the edge
+ * nodes are read and copied (2 nx + 2 (ny - 2) values, owned by the solver).
+ * The values of the levels passed to mfd_set_state are the caller's.
+ * Supported steps: explicit two- and three-level MMFD of the linear CDE,
+ * Burgers' equation and the wave equation (64-column blocked windows or one
+ * step per launch).  MFD_E_ORDER on a periodic grid, MFD_E_ARG for a null G,
+ * a wrong count or non-finite values, MFD_E_OOM.  mfd_step returns
+ * MFD_E_ORDER on a Dirichlet grid until the values are set. */
+int mfd_set_boundary(mfd_solver *s, const double *G, int64_t count, int on_device, double lambda);
+
+/* Special first step of the three-level wave scheme (Example 3): from
+ * phi^0 = level 0 as just set (no step taken yet) and phi_t = d phi / dt at
+ * t = 0 (count = nodes binary64 values, host or device memory),
+ *   phi^1 = phi^0 + dt phi_t + cw sum_axes [phi^0(x+e_a) - 2 phi^0 + phi^0(x-e_a)],
+ *   cw = A22 beta d0 / 2  (the Taylor start phi + dt phi_t + dt^2 alpha
+ *                          Laplacian(phi) / 2 with alpha = A22 beta c_s^2),
+ * evaluated in binary64 and rounded once to the solver's precision, with the
+ * Dirichlet values of t = dt on the edge of a Dirichlet grid.  Afterwards
+ * level 1 holds phi^0, level 0 phi^1 and one step counts as taken.
+ * Synchronous.  MFD_E_ORDER unless a three-level MFD_WAVE scheme is set and
+ * level 0 was set with no step since (and on a Dirichlet grid the values),
+ * MFD_E_ARG for a null phi_t or a wrong count. */
+int mfd_wave_start(mfd_solver *s, const double *phi_t, int64_t count, int on_device);
 
 /* Remove the source term (frees its buffer). */
 int mfd_clear_source(mfd_solver *s);

@@ -48,20 +48,20 @@
 #endif
 
 enum { ORC_D1Q3 = 1, ORC_D2Q5 = 2, ORC_D2Q9 = 3, ORC_D3Q19 = 4 };
-enum { ORC_LCDE = 0, ORC_BURGERS = 1, ORC_NSE = 2 };
+enum { ORC_LCDE = 0, ORC_BURGERS = 1, ORC_NSE = 2, ORC_WAVE = 3 };
 
 #define ORC_MAXQ 19
 #define ORC_MAXP 9
 
 typedef struct {
     int32_t lattice;      /* ORC_D1Q3 ...                                    */
-    int32_t eq;           /* ORC_LCDE / ORC_BURGERS / ORC_NSE                */
+    int32_t eq;           /* ORC_LCDE / ORC_BURGERS / ORC_NSE / ORC_WAVE     */
     int32_t levels;       /* 2: two-level explicit, 3: three-level explicit  */
     int32_t lambda_bar;   /* LCDE: 1 adds u u to C (Eq. TforMMFD-0)          */
     int32_t he_luo;       /* NSE: C = j j / rho0 (Remark 4)                  */
     int32_t nthreads;     /* 0: OpenMP default                               */
     int32_t theta_iters;  /* Jacobi sweeps per theta step                    */
-    int32_t pad_;
+    int32_t bc;           /* 0 periodic, 1 Dirichlet edges (2D, scalar)      */
     int64_t n[3];         /* nodes along x, y, z (x fastest)                 */
     double d0, dx, dt;
     double u[3];          /* LCDE advection velocity (physical)              */
@@ -71,6 +71,11 @@ typedef struct {
     double a[3], ah[3];   /* k = -1, 0, +1 at level t and t-dt               */
     double ab[3], abh[3]; /* momentum parameter set of Eq. (2-4)             */
     double theta;         /* weight of the old level, Eq. (GCN)              */
+    /* Dirichlet edges: the nodes with x or y = 0 or n-1 of the level a step
+     * writes hold bG[i] * bscale (bscale = exp(lambda t) of that level,
+     * evaluated by the caller); bG has one value per node (edges read) */
+    double bscale;
+    const double *bG;
 } orc_params;
 
 typedef struct {
@@ -261,6 +266,25 @@ static int make_ctx(const orc_params *P, orc_ctx *c)
             c->Chp[p] = c->ahp * c->ubp[p];
             c->Chm[p] = c->ahm * c->ubm[p];
         }
+    } else if (P->eq == ORC_WAVE) {
+        /* Example 3: f_j = w_j phi [1 + (beta-1)(|e_j|^2 - dim d0)/(2 d0)],
+         * the EDF printed there (its 2 c_s^2 is dim c_s^2 for dim = 2); a
+         * linear EDF with no odd part */
+        for (int j = 0; j < c->L.b; ++j) {
+            double e2 = 0.0;
+            for (int a = 0; a < 3; ++a) e2 = e2 + (double)(c->L.e[j][a] * c->L.e[j][a]);
+            double t = (e2 - (double)c->dim * d0) / (2.0 * d0);
+            c->ubar[j] = c->L.w[j] * (1.0 + (P->beta - 1.0) * t);
+        }
+        for (int p = 0; p < c->L.npair; ++p) {
+            int j = c->L.pair[p];
+            c->ubp[p] = c->ubar[j];
+            c->ubm[p] = 0.0;
+            c->Cp[p] = c->ap * c->ubp[p];
+            c->Cm[p] = 0.0;
+            c->Chp[p] = c->ahp * c->ubp[p];
+            c->Chm[p] = 0.0;
+        }
     } else if (P->eq == ORC_BURGERS) {
         c->bh = 0.5 * P->dt / P->dx;
         c->beta_one = P->beta == 1.0;
@@ -374,7 +398,41 @@ static void pair_parts(const orc_params *P, const orc_ctx *c, const double *lev,
  *   prev : level t - dt (ignored for two-level)
  *   out  : level t + dt
  */
+static int mmfd_step_all(const orc_params *P, const double *cur, const double *prev, double *out);
+static int literal_step_all(const orc_params *P, const double *cur, const double *prev,
+                            double *out);
+
+static int is_linear(const orc_params *P) { return P->eq == ORC_LCDE || P->eq == ORC_WAVE; }
+
+/* Dirichlet edges (2D scalar equations only) */
+static int bc_ok(const orc_params *P, const orc_ctx *c)
+{
+    if (!P->bc) return 1;
+    return c->dim == 2 && P->eq != ORC_NSE && P->bG != NULL;
+}
+
+/* the edge nodes of a new level take their prescribed values */
+static void apply_dirichlet(const orc_params *P, const orc_ctx *c, double *out)
+{
+    for (int64_t y = 0; y < c->n[1]; ++y)
+        for (int64_t x = 0; x < c->n[0]; ++x) {
+            if (!(x == 0 || y == 0 || x == c->n[0] - 1 || y == c->n[1] - 1)) continue;
+            int64_t i = y * c->n[0] + x;
+            out[i] = P->bG[i] * P->bscale;
+        }
+}
+
 int orc_mmfd_step(const orc_params *P, const double *cur, const double *prev, double *out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c) || !bc_ok(P, &c)) return -1;
+    int rc = mmfd_step_all(P, cur, prev, out);
+    if (rc == 0 && P->bc) apply_dirichlet(P, &c, out);
+    return rc;
+}
+
+/* every node updated by the scheme (periodic wrap at the grid's edges) */
+static int mmfd_step_all(const orc_params *P, const double *cur, const double *prev, double *out)
 {
     orc_ctx c;
     if (make_ctx(P, &c)) return -1;
@@ -385,7 +443,7 @@ int orc_mmfd_step(const orc_params *P, const double *cur, const double *prev, do
     const int three = P->levels == 3;
     const int np = c.L.npair;
 
-    if (P->eq == ORC_LCDE) {
+    if (is_linear(P)) {
 #pragma omp parallel for collapse(2) schedule(static)
         for (int64_t z = 0; z < c.n[2]; ++z)
             for (int64_t y = 0; y < c.n[1]; ++y)
@@ -492,7 +550,7 @@ static void full_edf(const orc_params *P, const orc_ctx *c, const double *lev, d
     const int nf = nfields(P, c);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-        if (P->eq == ORC_LCDE) {
+        if (is_linear(P)) {
             for (int j = 0; j < c->L.b; ++j) G[j * N + i] = c->ubar[j] * lev[i];
             continue;
         }
@@ -510,6 +568,16 @@ static void full_edf(const orc_params *P, const orc_ctx *c, const double *lev, d
  * and for the NSE first moments the same with e_j and the momentum set.
  */
 int orc_literal_step(const orc_params *P, const double *cur, const double *prev, double *out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c) || !bc_ok(P, &c)) return -1;
+    int rc = literal_step_all(P, cur, prev, out);
+    if (rc == 0 && P->bc) apply_dirichlet(P, &c, out);
+    return rc;
+}
+
+static int literal_step_all(const orc_params *P, const double *cur, const double *prev,
+                            double *out)
 {
     orc_ctx c;
     if (make_ctx(P, &c)) return -1;
@@ -660,7 +728,7 @@ static int mesofd_step(const orc_params *P, const orc_source *Q, const double *p
                        double *pop_out, double *mom_out)
 {
     orc_ctx c;
-    if (make_ctx(P, &c)) return -1;
+    if (make_ctx(P, &c) || P->bc) return -1;  /* MesoFD: periodic grids */
     const int64_t N = c.N;
     const int b = c.L.b;
     const int nf = nfields(P, &c);
@@ -696,6 +764,8 @@ static int mesofd_step(const orc_params *P, const orc_source *Q, const double *p
     return 0;
 }
 
+double orc_sum(const double *v, int64_t n);
+
 /* --------------------------------------------------------- theta (linear) */
 
 /*
@@ -707,7 +777,7 @@ static int mesofd_step(const orc_params *P, const orc_source *Q, const double *p
 int orc_theta_step(const orc_params *P, const double *cur, double *out, double *work)
 {
     orc_ctx c;
-    if (make_ctx(P, &c) || P->eq != ORC_LCDE) return -1;
+    if (make_ctx(P, &c) || P->eq != ORC_LCDE || P->bc) return -1;
 #ifdef _OPENMP
     if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
 #endif
@@ -755,6 +825,91 @@ int orc_theta_step(const orc_params *P, const double *cur, double *out, double *
     }
     if (P->theta_iters == 0) memcpy(out, cur, sizeof(double) * N);
     free(rhs);
+    return 0;
+}
+
+/*
+ * The same theta step solved to a tolerance: Jacobi sweeps (as above, started
+ * from phi(t)) in chunks of `chunk` sweeps; after each chunk the residual of
+ * the iterate before the chunk's last sweep is
+ *     r = rhs - (I - (1-theta) L) x_{k-1} = den (x_k - x_{k-1}),
+ *     den = 1 + (1-theta) 2 sum_p Cp_p
+ * (the Jacobi update written out), and the solve stops at the first chunk
+ * with  den^2 sum (x_k - x_{k-1})^2 <= tol^2 sum rhs^2  (both sums
+ * compensated), or when `cap` sweeps are reached.  Returns x_k in `out`, the
+ * sweeps taken in *sweeps and 1 / 0 in *converged.
+ */
+int orc_theta_solve(const orc_params *P, const double *cur, double *out, double *work,
+                    double tol, int chunk, int cap, int *sweeps, int *converged)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c) || P->eq != ORC_LCDE || P->bc || chunk < 1 || cap < 1) return -1;
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    const int64_t N = c.N;
+    const int np = c.L.npair;
+    const double th = P->theta, th1 = 1.0 - P->theta;
+    double sp = 0.0;
+    for (int p = 0; p < np; ++p) sp = sp + c.Cp[p];
+    const double den = 1.0 + th1 * (2.0 * sp);
+    const double inv_den = 1.0 / den;
+    double *rhs = malloc(sizeof(double) * N), *sq = malloc(sizeof(double) * N);
+    double *x[2] = {out, work};
+    if (!rhs || !sq) { free(rhs); free(sq); return -4; }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t xx = 0; xx < c.n[0]; ++xx) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + xx;
+                double acc = 0.0;
+                for (int p = 0; p < np; ++p) {
+                    int j = c.L.pair[p];
+                    int64_t ip = nb(&c, xx, y, z, j, 1), im = nb(&c, xx, y, z, j, -1);
+                    acc = acc + c.Cp[p] * d2(cur, ip, i, im);
+                    acc = acc + c.Cm[p] * d1(cur, ip, im);
+                }
+                rhs[i] = c.A0 * cur[i] + th * acc;
+            }
+    for (int64_t i = 0; i < N; ++i) sq[i] = rhs[i] * rhs[i];
+    const double b2 = orc_sum(sq, N);
+    const double *src = cur;
+    int k = 0, done = 0, conv = 0, w = 0;
+    while (!done) {
+        for (int it = 0; it < chunk; ++it) {
+            double *dst = x[w];
+#pragma omp parallel for collapse(2) schedule(static)
+            for (int64_t z = 0; z < c.n[2]; ++z)
+                for (int64_t y = 0; y < c.n[1]; ++y)
+                    for (int64_t xx = 0; xx < c.n[0]; ++xx) {
+                        int64_t i = (z * c.n[1] + y) * c.n[0] + xx;
+                        double acc = 0.0;
+                        for (int p = 0; p < np; ++p) {
+                            int j = c.L.pair[p];
+                            int64_t ip = nb(&c, xx, y, z, j, 1), im = nb(&c, xx, y, z, j, -1);
+                            acc = acc + c.Cp[p] * (src[ip] + src[im]);
+                            acc = acc + c.Cm[p] * (src[ip] - src[im]);
+                        }
+                        dst[i] = (rhs[i] + th1 * acc) * inv_den;
+                    }
+            ++k;
+            if (it + 1 == chunk) {
+                for (int64_t i = 0; i < N; ++i) {
+                    double d = dst[i] - src[i];
+                    sq[i] = d * d;
+                }
+            }
+            src = dst;
+            w ^= 1;
+        }
+        const double d2s = orc_sum(sq, N);
+        conv = den * den * d2s <= tol * tol * b2;
+        done = conv || k >= cap;
+    }
+    if (src != out) memcpy(out, src, sizeof(double) * N);
+    *sweeps = k;
+    *converged = conv;
+    free(rhs); free(sq);
     return 0;
 }
 
@@ -808,7 +963,7 @@ static void source_mmfd(const orc_params *P, const orc_ctx *c, const orc_source 
 int orc_mmfd_source_step(const orc_params *P, const orc_source *Q, const double *cur,
                          const double *prev, const double *St, const double *Sm, double *out)
 {
-    if (P->eq != ORC_LCDE) return -5;
+    if (P->eq != ORC_LCDE || P->bc) return -5;
     int rc = orc_mmfd_step(P, cur, prev, out);
     if (rc) return rc;
     orc_ctx c;
@@ -823,7 +978,7 @@ int orc_mmfd_source_step(const orc_params *P, const orc_source *Q, const double 
 int orc_literal_source_step(const orc_params *P, const orc_source *Q, const double *cur,
                             const double *prev, const double *St, const double *Sm, double *out)
 {
-    if (P->eq != ORC_LCDE) return -5;
+    if (P->eq != ORC_LCDE || P->bc) return -5;
     int rc = orc_literal_step(P, cur, prev, out);
     if (rc) return rc;
     orc_ctx c;
@@ -847,8 +1002,47 @@ int orc_mesofd_source_step(const orc_params *P, const orc_source *Q, const doubl
                            const double *prev_mom, const double *St, const double *Sm,
                            double *pop_out, double *mom_out)
 {
-    if (P->eq != ORC_LCDE) return -5;
+    if (P->eq != ORC_LCDE || P->bc) return -5;
     return mesofd_step(P, Q, pop, prev_mom, St, Sm, pop_out, mom_out);
+}
+
+/* ------------------------------------------------------- wave first step */
+
+/*
+ * Special first step of the three-level wave scheme (Example 3): a Taylor
+ * step with phi_tt = alpha Laplacian(phi), alpha = A22 beta c_s^2
+ * (Eq. (ME-NCDE-W-1)), the Laplacian by the axis second differences:
+ *   phi(x, dt) = phi(x, 0) + dt phi_t(x, 0)
+ *                + (dt^2 alpha / (2 dx^2)) sum_axes [phi(x+e_a) - 2 phi(x) + phi(x-e_a)]
+ * whose factor is A22 beta d0 / 2 in lattice units (Example 3: (dt/(2dx))^2).
+ * The wrap is periodic; with Dirichlet edges those nodes take bG * bscale
+ * (bscale = exp(lambda dt)).
+ */
+int orc_wave_start(const orc_params *P, const double *phi0, const double *phit, double *out)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c) || P->eq != ORC_WAVE || P->levels != 3 || !bc_ok(P, &c)) return -1;
+    const double A22 = 0.5 * (c.ap + c.ahp);
+    const double cw = ((0.5 * A22) * P->beta) * P->d0;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < c.n[2]; ++z)
+        for (int64_t y = 0; y < c.n[1]; ++y)
+            for (int64_t x = 0; x < c.n[0]; ++x) {
+                int64_t i = (z * c.n[1] + y) * c.n[0] + x;
+                double lap = 0.0;
+                for (int a = 0; a < c.dim; ++a) {
+                    int64_t xs[2] = {x, x}, ys[2] = {y, y}, zs[2] = {z, z};
+                    if (a == 0) { xs[0] = wrap(x + 1, c.n[0]); xs[1] = wrap(x - 1, c.n[0]); }
+                    if (a == 1) { ys[0] = wrap(y + 1, c.n[1]); ys[1] = wrap(y - 1, c.n[1]); }
+                    if (a == 2) { zs[0] = wrap(z + 1, c.n[2]); zs[1] = wrap(z - 1, c.n[2]); }
+                    int64_t ip = (zs[0] * c.n[1] + ys[0]) * c.n[0] + xs[0];
+                    int64_t im = (zs[1] * c.n[1] + ys[1]) * c.n[0] + xs[1];
+                    lap = lap + d2(phi0, ip, i, im);
+                }
+                out[i] = (phi0[i] + P->dt * phit[i]) + cw * lap;
+            }
+    if (P->bc) apply_dirichlet(P, &c, out);
+    return 0;
 }
 
 /* ---------------------------------------------------------- tables / sums */

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmfd_oracle.so")
 LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
 DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
 QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
-EQS = {"lcde": 0, "burgers": 1, "nse": 2}
+EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
 MAXP = 9
 
 
@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [
         ("lattice", C.c_int32), ("eq", C.c_int32), ("levels", C.c_int32),
         ("lambda_bar", C.c_int32), ("he_luo", C.c_int32), ("nthreads", C.c_int32),
-        ("theta_iters", C.c_int32), ("pad_", C.c_int32),
+        ("theta_iters", C.c_int32), ("bc", C.c_int32),
         ("n", C.c_int64 * 3),
         ("d0", C.c_double), ("dx", C.c_double), ("dt", C.c_double),
         ("u", C.c_double * 3), ("K", C.c_double * 9),
@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("a", C.c_double * 3), ("ah", C.c_double * 3),
         ("ab", C.c_double * 3), ("abh", C.c_double * 3),
         ("theta", C.c_double),
+        ("bscale", C.c_double), ("bG", C.POINTER(C.c_double)),
     ]
 
 
@@ -73,6 +74,7 @@ def lib():
             ("orc_mesofd_step", [P, D, D, D, D]),
             ("orc_theta_step", [P, D, D, D]),
             ("orc_tables", [P, D, D, D]),
+            ("orc_wave_start", [P, D, D, D]),
             ("orc_mmfd_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
             ("orc_literal_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
             ("orc_mesofd_source_step", [P, C.POINTER(Source), D, D, D, D, D, D]),
@@ -85,6 +87,9 @@ def lib():
         L.orc_lattice_info.restype = C.c_int
         L.orc_edf.argtypes = [C.c_int, C.c_double, C.c_double, D, D, D]
         L.orc_edf.restype = C.c_int
+        L.orc_theta_solve.argtypes = [P, D, D, D, C.c_double, C.c_int, C.c_int,
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_theta_solve.restype = C.c_int
         L.orc_sum.argtypes = [D, C.c_int64]
         L.orc_sum.restype = C.c_double
         _lib = L
@@ -141,6 +146,19 @@ def make_params(spec: dict) -> Params:
     return P
 
 
+def _with_boundary(P, bc):
+    """Dirichlet edges: bc = dict(G=values per node, scale=exp(lambda t) of
+    the level written).  The array is kept alive on the parameter block."""
+    if bc is None:
+        return P
+    G = np.ascontiguousarray(bc["G"], dtype=np.float64).ravel()
+    P.bc = 1
+    P.bscale = float(bc["scale"])
+    P.bG = G.ctypes.data_as(C.POINTER(C.c_double))
+    P._keep = G
+    return P
+
+
 def nfields(spec) -> int:
     return 1 + DIMS[spec["lattice"]] if spec.get("eq", "lcde") == "nse" else 1
 
@@ -175,26 +193,37 @@ def _source_step(fn, name, spec, cur, prev, src):
     return out
 
 
-def mmfd_step(spec, cur, prev=None, src=None):
+def mmfd_step(spec, cur, prev=None, src=None, bc=None):
     """One MMFD step; src (linear CDE only): dict(b, bh, v, S_t, S_m) adds the
-    scheme's source term with S given at levels t and t - dt."""
+    scheme's source term with S given at levels t and t - dt; bc (2D scalar
+    equations): dict(G, scale) sets the edge nodes of the new level to
+    G * scale (Dirichlet)."""
     if src is not None:
         return _source_step(lib().orc_mmfd_source_step, "mmfd_source_step", spec, cur, prev, src)
-    P = make_params(spec)
+    P = _with_boundary(make_params(spec), bc)
     out = np.empty_like(cur)
     prev = cur if prev is None else prev
     _check(lib().orc_mmfd_step(C.byref(P), _ptr(cur), _ptr(prev), _ptr(out)), "mmfd_step")
     return out
 
 
-def literal_step(spec, cur, prev=None, src=None):
+def literal_step(spec, cur, prev=None, src=None, bc=None):
     if src is not None:
         return _source_step(lib().orc_literal_source_step, "literal_source_step", spec, cur, prev,
                             src)
-    P = make_params(spec)
+    P = _with_boundary(make_params(spec), bc)
     out = np.empty_like(cur)
     prev = cur if prev is None else prev
     _check(lib().orc_literal_step(C.byref(P), _ptr(cur), _ptr(prev), _ptr(out)), "literal_step")
+    return out
+
+
+def wave_start(spec, phi0, phit, bc=None):
+    """Special first step of the three-level wave scheme (orc_wave_start)."""
+    P = _with_boundary(make_params(spec), bc)
+    out = np.empty_like(phi0)
+    phit = np.ascontiguousarray(phit, dtype=np.float64)
+    _check(lib().orc_wave_start(C.byref(P), _ptr(phi0), _ptr(phit), _ptr(out)), "wave_start")
     return out
 
 
@@ -240,6 +269,18 @@ def theta_step(spec, cur):
     work = np.empty_like(cur)
     _check(lib().orc_theta_step(C.byref(P), _ptr(cur), _ptr(out), _ptr(work)), "theta_step")
     return out
+
+
+def theta_solve(spec, cur, tol, chunk, cap):
+    """Theta step solved to a tolerance (orc_theta_solve): returns
+    (phi(t + dt), sweeps, converged)."""
+    P = make_params(spec)
+    out = np.empty_like(cur)
+    work = np.empty_like(cur)
+    sw, cv = C.c_int(), C.c_int()
+    _check(lib().orc_theta_solve(C.byref(P), _ptr(cur), _ptr(out), _ptr(work), float(tol),
+                                 int(chunk), int(cap), C.byref(sw), C.byref(cv)), "theta_solve")
+    return out, sw.value, bool(cv.value)
 
 
 def tables(spec):

@@ -19,13 +19,13 @@ namespace mfd {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int, int64_t, int64_t, int64_t>;
+using Key = std::tuple<int, int, int, int, int, int, int64_t, int64_t, int64_t, int>;
 std::mutex g_mu;
 std::map<Key, TbPlan> g_cache;
 
 Key key_of(const Solver &s) {
   return Key(s.consts.lattice, s.consts.eq, s.grid.form, s.grid.precision, s.consts.three,
-             s.consts.three_stencil, s.G.n[0], s.G.n[1], s.G.n[2]);
+             s.consts.three_stencil, s.G.n[0], s.G.n[1], s.G.n[2], s.dirichlet ? 1 : 0);
 }
 
 bool tunable(const Solver &s) {
@@ -54,6 +54,9 @@ int default_h(const Solver &s, int tb) {
 
 bool Solver::plan_supported(const TbPlan &p) const {
   if (cfg.kind == MFD_THETA || src_on) return false;
+  // Dirichlet nodes are set by the 64-column windows (the in-place 128-column
+  // window of the linear CDE has no boundary handling)
+  if (dirichlet && (p.w != 64 || p.tb > kMaxBcSteps)) return false;
   if (grid.form == MFD_MESOFD) return mesofd_tb_supported(consts, G, p, (int)elem());
   return tb_supported(consts, G, p, (int)elem());
 }

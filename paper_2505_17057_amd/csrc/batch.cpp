@@ -542,6 +542,7 @@ extern "C" int mfd_batch_add(mfd_batch *h, mfd_solver *sh, int64_t nsteps, int32
       (s->consts.lattice != MFD_D2Q9 && s->consts.lattice != MFD_D2Q5))
     return b->fail(MFD_E_UNSUPPORTED, "batches hold 2D explicit MMFD solvers (D2Q5 / D2Q9)");
   if (s->src_on) return b->fail(MFD_E_UNSUPPORTED, "batches hold solvers without a source term");
+  if (s->dirichlet) return b->fail(MFD_E_UNSUPPORTED, "batches hold periodic solvers");
   for (auto &e : b->entries)
     if (e.s == s) return b->fail(MFD_E_ARG, "solver already in the batch");
   if (slot) *slot = (int32_t)b->entries.size();

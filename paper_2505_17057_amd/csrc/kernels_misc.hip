@@ -14,6 +14,12 @@
 
 namespace mfd {
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Launch shape of the theta kernels: x in blocks of 256 threads, one grid row
 // per (y, z) line (grid-stride in y and z beyond the grid limits), so that a
 // thread finds its node and its neighbours without any division.
@@ -87,9 +93,34 @@ __global__ __launch_bounds__(256) void k_theta_sweep(const T *__restrict__ src,
 // stores the (W - 2(K+1)) x (H - 2(K+1)) interior of the last sweep.  Each
 // node's arithmetic is that of k_theta_rhs / k_theta_sweep, so the result is
 // the same value for value.  The host guarantees nx >= W and ny >= H.
-template <class L, int W, int RG, typename T>
-__global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur,
-                                                      T *__restrict__ out, int nx, int ny, int H,
+//
+// Solved to a tolerance (SOLVE): the launch is one chunk of K sweeps of a
+// step's Jacobi solve.  The level phi^n, the iterate a chunk starts from and
+// the buffer it writes are chosen on the device by a control block, so the
+// host enqueues the same chunk sequence for every step (the first chunk of a
+// step starts from phi^n; later chunks continue from the last iterate and
+// return at once when the solve has stopped).  Each tile adds its interior's
+// sum (x_K - x_{K-1})^2 and sum rhs^2 (binary64) to its slot of `part`; the
+// last workgroup to finish (atomic count, no waiting) sums the slots in tile
+// order and stops the solve when den^2 sum d^2 <= tol^2 sum rhs^2 (the
+// residual of x_{K-1} is den (x_K - x_{K-1})) or the sweep cap is reached,
+// rotating the level roles: prev <- phi^n, phi^n <- the last iterate.
+template <typename T>
+struct ThetaRing {
+  T *b[4];  // the four level buffers the control block's roles index
+};
+
+struct ThetaSolveArgs {
+  ThetaCtl *ctl;
+  double *part;  // 2 per tile
+  double tol2, den2;
+  int cap, first;
+};
+
+template <class L, int W, int RG, typename T, bool SOLVE>
+__global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur_in,
+                                                      T *__restrict__ out_in, ThetaRing<T> ring,
+                                                      ThetaSolveArgs sa, int nx, int ny, int H,
                                                       int K, int tiles_x, int ntiles, KC<T> kc) {
   constexpr int NT = W * RG;
   constexpr int KB = 8;
@@ -100,25 +131,46 @@ __global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur
   const int TX = W - 2 * halo, TY = H - 2 * halo;
   const int tile = blockIdx.x;
   const int x0 = (tile % tiles_x) * TX - halo, y0 = (tile / tiles_x) * TY - halo;
+  __shared__ int s_sel[4];  // skip, level, iterate source, destination
 
-  for (int base = 0; base < WH; base += KB * NT) {
-    T v[KB];
+  const T *cur = cur_in, *itsrc = cur_in;
+  T *out = out_in;
+  if constexpr (SOLVE) {
+    if (threadIdx.x == 0) {
+      const ThetaCtl *c = sa.ctl;
+      s_sel[0] = (!sa.first && c->done) ? 1 : 0;
+      s_sel[1] = c->role[0];
+      s_sel[2] = sa.first ? c->role[0] : c->nsrc;
+      s_sel[3] = sa.first ? c->role[2] : c->ndst;
+    }
+    __syncthreads();
+    if (s_sel[0]) return;
+    cur = ring.b[s_sel[1]];
+    itsrc = ring.b[s_sel[2]];
+    out = ring.b[s_sel[3]];
+  }
+
+  auto load_window = [&](const T *__restrict__ g) {
+    for (int base = 0; base < WH; base += KB * NT) {
+      T v[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int i = base + threadIdx.x + k * NT;
-      if (i < WH) {
-        int gx = x0 + (i % W), gy = y0 + i / W;
-        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-        gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-        v[k] = cur[(int64_t)gy * nx + gx];
+      for (int k = 0; k < KB; ++k) {
+        const int i = base + threadIdx.x + k * NT;
+        if (i < WH) {
+          int gx = x0 + (i % W), gy = y0 + i / W;
+          gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+          gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+          v[k] = g[(int64_t)gy * nx + gx];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int i = base + threadIdx.x + k * NT;
+        if (i < WH) lds[i] = v[k];
       }
     }
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int i = base + threadIdx.x + k * NT;
-      if (i < WH) lds[i] = v[k];
-    }
-  }
+  };
+  load_window(cur);
   __syncthreads();
 
   const int xx = threadIdx.x % W, rg = threadIdx.x / W;
@@ -166,6 +218,12 @@ __global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur
     R[y * W + xx] = madd(kc.th, acc, b);
   });
   __syncthreads();
+  if constexpr (SOLVE) {
+    if (sa.first == 0) {  // continue from the last iterate
+      load_window(itsrc);
+      __syncthreads();
+    }
+  }
   int src = 0;
 #pragma unroll 1
   for (int k = 1; k <= K; ++k) {
@@ -188,11 +246,120 @@ __global__ __launch_bounds__(W *RG) void k_theta_fused(const T *__restrict__ cur
   }
 
   const T *C = lds + src * WH;
+  const T *Pv = lds + (src == 0 ? 2 : 0) * WH;  // the sweep before the last
+  double d2 = 0.0, b2 = 0.0;
   for (int i = threadIdx.x; i < TX * TY; i += NT) {
     const int lx = i % TX, ly = i / TX;
     const int gx = x0 + halo + lx, gy = y0 + halo + ly;
     if (gx >= nx || gy >= ny) continue;
-    out[(int64_t)gy * nx + gx] = C[(halo + ly) * W + halo + lx];
+    const int li = (halo + ly) * W + halo + lx;
+    out[(int64_t)gy * nx + gx] = C[li];
+    if constexpr (SOLVE) {
+      const double d = (double)C[li] - (double)Pv[li];
+      const double r = (double)R[li];
+      d2 += d * d;
+      b2 += r * r;
+    }
+  }
+  if constexpr (SOLVE) {
+    // tile sums (fixed order: lanes, then wavefronts), then the last
+    // workgroup's pass over the tiles
+    __shared__ double red[2][NT / 64];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    d2 = wave_sum(d2);
+    b2 = wave_sum(b2);
+    if (lane == 0) {
+      red[0][wave] = d2;
+      red[1][wave] = b2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        a += red[0][w];
+        b += red[1][w];
+      }
+      sa.part[2 * tile] = a;
+      sa.part[2 * tile + 1] = b;
+      __threadfence();
+      s_last = atomicAdd(&sa.ctl->count, 1u) == (unsigned)(ntiles - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += NT) {
+      a += __builtin_nontemporal_load(&sa.part[2 * t]);
+      b += __builtin_nontemporal_load(&sa.part[2 * t + 1]);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+      red[0][wave] = a;
+      red[1][wave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double D2 = 0.0, B2 = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        D2 += red[0][w];
+        B2 += red[1][w];
+      }
+      ThetaCtl *c = sa.ctl;
+      const int sweeps = (sa.first ? 0 : c->sweeps) + K;
+      const bool conv = sa.den2 * D2 <= sa.tol2 * B2;
+      const int dst = s_sel[3];
+      const int other = dst == c->role[2] ? c->role[3] : c->role[2];
+      if (conv || sweeps >= sa.cap) {
+        const int oc = c->role[0], op = c->role[1];
+        c->role[0] = dst;
+        c->role[1] = oc;
+        c->role[2] = op;
+        c->role[3] = other;
+        c->done = 1;
+        c->total_sweeps += sweeps;
+        c->steps += 1;
+        if (sweeps > c->max_sweeps) c->max_sweeps = sweeps;
+        if (!conv) c->unconverged += 1;
+      } else {
+        c->done = 0;
+        c->nsrc = dst;
+        c->ndst = other;
+      }
+      c->sweeps = sweeps;
+      c->count = 0u;
+      __threadfence();
+    }
+  }
+}
+
+// start of an mfd_step call of the to-tolerance solve: identity roles
+__global__ void k_theta_ctl_init(ThetaCtl *c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) c->role[i] = i;
+    c->done = 1;
+    c->nsrc = 0;
+    c->ndst = 2;
+    c->sweeps = 0;
+    c->count = 0u;
+  }
+}
+
+// end of the call: phi^n and phi^(n-1) back into buffers 0 and 1 (each node
+// reads both sources before writing, so any permutation of roles is safe)
+template <typename T>
+__global__ __launch_bounds__(256) void k_theta_gather(ThetaRing<T> ring, const ThetaCtl *c,
+                                                      int64_t N) {
+  const int r0 = c->role[0], r1 = c->role[1];
+  if (r0 == 0 && r1 == 1) return;
+  const T *s0 = ring.b[r0], *s1 = ring.b[r1];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T v0 = s0[i], v1 = s1[i];
+    ring.b[0][i] = v0;
+    ring.b[1][i] = v1;
   }
 }
 
@@ -243,11 +410,6 @@ hipError_t launch_theta_sweep(const Consts &c, const Grid &g, const T *src, cons
 // ------------------------------------------------------------ reductions
 constexpr int kRedQ = 8;  // quantities per pass: 4 field sums, squared diff, spare
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <typename T, int NF>
 __global__ __launch_bounds__(256) void k_reduce_partial(const T *__restrict__ cur,
@@ -370,17 +532,155 @@ hipError_t launch_theta_fused(const Consts &c, const Grid &g, int K, const T *cu
   const int halo = K + 1, TX = kThetaW - 2 * halo, TY = H - 2 * halo;
   const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
   const size_t lds = (size_t)3 * H * kThetaW * sizeof(T);
-  auto fn = c.lattice == 3 ? k_theta_fused<LatD2Q9, kThetaW, kThetaRG, T>
-                           : k_theta_fused<LatD2Q5, kThetaW, kThetaRG, T>;
+  auto fn = c.lattice == 3 ? k_theta_fused<LatD2Q9, kThetaW, kThetaRG, T, false>
+                           : k_theta_fused<LatD2Q5, kThetaW, kThetaRG, T, false>;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kThetaW * kThetaRG), lds, st, cur, out, nx, ny, H, K,
-                     tx, tx * ty, kc);
+  ThetaRing<T> ring{{nullptr, nullptr, nullptr, nullptr}};
+  ThetaSolveArgs sa{nullptr, nullptr, 0.0, 0.0, 0, 1};
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kThetaW * kThetaRG), lds, st, cur, out, ring, sa, nx,
+                     ny, H, K, tx, tx * ty, kc);
+  return hipGetLastError();
+}
+
+int theta_solve_tiles(const Consts &c, const Grid &g, int K, int elem) {
+  const int H = theta_fused_rows(c, g, K, elem);
+  if (!H) return 0;
+  const int halo = K + 1, TX = kThetaW - 2 * halo, TY = H - 2 * halo;
+  return (int)(((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY));
+}
+
+template <typename T>
+hipError_t launch_theta_ctl_init(ThetaCtl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta_ctl_init, dim3(1), dim3(64), 0, st, ctl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_theta_chunk(const Consts &c, const Grid &g, int K, T *const bufs[4],
+                              ThetaCtl *ctl, double *part, double tol, int cap, bool first,
+                              hipStream_t st) {
+  const int H = theta_fused_rows(c, g, K, (int)sizeof(T));
+  if (!H) return hipErrorInvalidValue;
+  const KC<T> kc = make_kc<T>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  const int halo = K + 1, TX = kThetaW - 2 * halo, TY = H - 2 * halo;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = (size_t)3 * H * kThetaW * sizeof(T);
+  auto fn = c.lattice == 3 ? k_theta_fused<LatD2Q9, kThetaW, kThetaRG, T, true>
+                           : k_theta_fused<LatD2Q5, kThetaW, kThetaRG, T, true>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  ThetaRing<T> ring{{bufs[0], bufs[1], bufs[2], bufs[3]}};
+  const double den = theta_den(c);
+  ThetaSolveArgs sa{ctl, part, tol * tol, den * den, cap, first ? 1 : 0};
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(kThetaW * kThetaRG), lds, st, nullptr, nullptr, ring,
+                     sa, nx, ny, H, K, tx, tx * ty, kc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_theta_gather(T *const bufs[4], const ThetaCtl *ctl, int64_t N, hipStream_t st) {
+  ThetaRing<T> ring{{bufs[0], bufs[1], bufs[2], bufs[3]}};
+  int nblk = (int)std::min<int64_t>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_theta_gather<T>), dim3(nblk), dim3(256), 0, st, ring, ctl, N);
+  return hipGetLastError();
+}
+
+// sums sum (a - b)^2 and sum c^2 in binary64 over N nodes (deterministic):
+// out[0], out[1]
+template <typename T>
+__global__ __launch_bounds__(256) void k_sq_partial(const T *__restrict__ a,
+                                                    const T *__restrict__ b,
+                                                    const T *__restrict__ cc, int64_t N,
+                                                    double *__restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)a[i] - (double)b[i];
+    const double r = (double)cc[i];
+    s0 += d * d;
+    s1 += r * r;
+  }
+  __shared__ double red[2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < kRedQ) {
+    const int q = threadIdx.x;
+    partial[blockIdx.x * kRedQ + q] =
+        q < 2 ? ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3] : 0.0;
+  }
+}
+
+template <typename T>
+hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,
+                          double *out, hipStream_t st) {
+  int nblk = (int)((N + 255) / 256);
+  if (nblk > kReduceBlocks) nblk = kReduceBlocks;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL((k_sq_partial<T>), dim3(nblk), dim3(256), 0, st, a, b, c, N, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// Special first step of the three-level wave scheme (Example 3 of the paper):
+// phi(t + dt) = phi + dt phi_t + cw sum_axes [(phi(x+e_a) - 2 phi) + phi(x-e_a)]
+// at every node (periodic wrap), in binary64 and rounded once; on a
+// Dirichlet grid the boundary nodes take G_b E[1].
+template <typename T>
+__global__ __launch_bounds__(256) void k_wave_start(const T *__restrict__ phi0,
+                                                    const double *__restrict__ phit,
+                                                    T *__restrict__ out, Dims d, int dim,
+                                                    double dt, double cw, DirBC bc) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= d.n[0]) return;
+  for (int z = blockIdx.z; z < d.n[2]; z += gridDim.z)
+    for (int y = blockIdx.y; y < d.n[1]; y += gridDim.y) {
+      const int64_t i = ((int64_t)z * d.n[1] + y) * d.n[0] + x;
+      double v;
+      if (bc.on && dir_node(x, y, d.n[0], d.n[1])) {
+        v = bc.Gb[dir_index(x, y, d.n[0], d.n[1])] * bc.E[1];
+      } else {
+        const double c = (double)phi0[i];
+        double lap = 0.0;
+        for (int a = 0; a < dim; ++a) {
+          const int ex = a == 0, ey = a == 1, ez = a == 2;
+          const int64_t ip = ((int64_t)wrap_step(z + ez, d.n[2]) * d.n[1] + wrap_step(y + ey, d.n[1])) *
+                                 d.n[0] + wrap_step(x + ex, d.n[0]);
+          const int64_t im = ((int64_t)wrap_step(z - ez, d.n[2]) * d.n[1] + wrap_step(y - ey, d.n[1])) *
+                                 d.n[0] + wrap_step(x - ex, d.n[0]);
+          lap = lap + (((double)phi0[ip] - 2.0 * c) + (double)phi0[im]);
+        }
+        v = (c + dt * phit[i]) + cw * lap;
+      }
+      out[i] = (T)v;
+    }
+}
+
+template <typename T>
+hipError_t launch_wave_start(const Consts &c, const Grid &g, const T *phi0, const double *phit,
+                             T *out, double dt, double cw, const DirBC &bc, hipStream_t st) {
+  if (bc.on && c.dim != 2) return hipErrorInvalidValue;
+  Dims d;
+  dim3 gr;
+  theta_shape(g, &d, &gr);
+  hipLaunchKernelGGL((k_wave_start<T>), gr, dim3(256), 0, st, phi0, phit, out, d, c.dim, dt, cw,
+                     bc);
   return hipGetLastError();
 }
 
 #define MFD_INST(T)                                                                               \
+  template hipError_t launch_wave_start<T>(const Consts &, const Grid &, const T *,               \
+                                           const double *, T *, double, double, const DirBC &,    \
+                                           hipStream_t);                                          \
   template hipError_t launch_theta_fused<T>(const Consts &, const Grid &, int, const T *, T *,    \
                                             hipStream_t);                                         \
   template hipError_t launch_theta_rhs<T>(const Consts &, const Grid &, const T *, T *,           \
@@ -388,7 +688,15 @@ hipError_t launch_theta_fused(const Consts &c, const Grid &g, int K, const T *cu
   template hipError_t launch_theta_sweep<T>(const Consts &, const Grid &, const T *, const T *,   \
                                             T *, hipStream_t);                                    \
   template hipError_t launch_reduce<T>(const T *, const T *, int, int64_t, double *, double *,    \
-                                       hipStream_t);
+                                       hipStream_t);                                              \
+  template hipError_t launch_theta_ctl_init<T>(ThetaCtl *, hipStream_t);                          \
+  template hipError_t launch_theta_chunk<T>(const Consts &, const Grid &, int, T *const[4],       \
+                                            ThetaCtl *, double *, double, int, bool,              \
+                                            hipStream_t);                                         \
+  template hipError_t launch_theta_gather<T>(T *const[4], const ThetaCtl *, int64_t,              \
+                                             hipStream_t);                                        \
+  template hipError_t launch_sq_sums<T>(const T *, const T *, const T *, int64_t, double *,       \
+                                        double *, hipStream_t);
 MFD_INST(float)
 MFD_INST(double)
 #undef MFD_INST

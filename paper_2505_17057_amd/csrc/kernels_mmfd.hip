@@ -28,10 +28,11 @@ template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T
 __global__ __launch_bounds__(256) void k_mmfd_plane(const T *__restrict__ cur,
                                                     const T *__restrict__ prev,
                                                     T *__restrict__ out, int nx, int ny,
-                                                    int tiles_x, int ntiles, KC<T> kc) {
+                                                    int tiles_x, int ntiles, KC<T> kc,
+                                                    DirBC bc) {
   const int tile = xcd_remap(blockIdx.x, ntiles);
   const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
-  mmfd_plane_tile<L, EQ, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc);
+  mmfd_plane_tile<L, EQ, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc, &bc);
 }
 
 // ------------------------------------- 2D NSE, persistent workgroups
@@ -224,6 +225,7 @@ constexpr int kNumCUs = 256;
 
 template <class L, int EQ, bool THREE, bool THREE_ST, typename T>
 hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
+                      const DirBC &bc,
                       hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
   const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
@@ -231,7 +233,7 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     constexpr int TX = 1024, TY = 1;
     const int tx = (nx + TX - 1) / TX;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx), dim3(256), 0,
-                       st, cur, prev, out, nx, 1, tx, tx, kc);
+                       st, cur, prev, out, nx, 1, tx, tx, kc, bc);
   } else if constexpr (L::D == 2 && EQ == kNSE) {
     constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
@@ -250,7 +252,7 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     constexpr int TX = 64, TY = 16;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty), dim3(256),
-                       0, st, cur, prev, out, nx, ny, tx, tx * ty, kc);
+                       0, st, cur, prev, out, nx, ny, tx, tx * ty, kc, bc);
   } else if constexpr (L::D == 3 && EQ == kNSE && !THREE_ST) {
     return launch_nse3d_pp<T>(c, g, cur, prev, out, st);
   } else {
@@ -266,20 +268,20 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
 
 template <class L, int EQ, typename T>
 hipError_t launch_levels(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
-                         hipStream_t st) {
-  if (!c.three) return launch_cfg<L, EQ, false, false, T>(c, g, cur, prev, out, st);
-  if (!c.three_stencil) return launch_cfg<L, EQ, true, false, T>(c, g, cur, prev, out, st);
-  return launch_cfg<L, EQ, true, true, T>(c, g, cur, prev, out, st);
+                         const DirBC &bc, hipStream_t st) {
+  if (!c.three) return launch_cfg<L, EQ, false, false, T>(c, g, cur, prev, out, bc, st);
+  if (!c.three_stencil) return launch_cfg<L, EQ, true, false, T>(c, g, cur, prev, out, bc, st);
+  return launch_cfg<L, EQ, true, true, T>(c, g, cur, prev, out, bc, st);
 }
 
 template <class L, typename T>
 hipError_t launch_eq(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
-                     hipStream_t st) {
+                     const DirBC &bc, hipStream_t st) {
   switch (c.eq) {
-    case kLCDE: return launch_levels<L, kLCDE, T>(c, g, cur, prev, out, st);
-    case kBurgers: return launch_levels<L, kBurgers, T>(c, g, cur, prev, out, st);
+    case kLCDE: return launch_levels<L, kLCDE, T>(c, g, cur, prev, out, bc, st);
+    case kBurgers: return launch_levels<L, kBurgers, T>(c, g, cur, prev, out, bc, st);
     case kNSE:
-      if constexpr (L::D >= 2) return launch_levels<L, kNSE, T>(c, g, cur, prev, out, st);
+      if constexpr (L::D >= 2) return launch_levels<L, kNSE, T>(c, g, cur, prev, out, bc, st);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -324,21 +326,27 @@ hipError_t launch_mmfd_1d_resident(const Consts &c, const Grid &g, T *a, T *b, T
 
 template <typename T>
 hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
-                            int tb_depth, hipStream_t st) {
+                            int tb_depth, hipStream_t st, const DirBC *bcp) {
   (void)tb_depth;
+  DirBC bc{};
+  if (bcp) bc = *bcp;
+  // the Dirichlet override lives in the 2D scalar plane kernel only
+  if (bc.on && (c.dim != 2 || c.eq == kNSE)) return hipErrorInvalidValue;
   switch (c.lattice) {
-    case 1: return launch_eq<LatD1Q3, T>(c, g, cur, prev, out, st);
-    case 2: return launch_eq<LatD2Q5, T>(c, g, cur, prev, out, st);
-    case 3: return launch_eq<LatD2Q9, T>(c, g, cur, prev, out, st);
-    case 4: return launch_eq<LatD3Q19, T>(c, g, cur, prev, out, st);
+    case 1: return launch_eq<LatD1Q3, T>(c, g, cur, prev, out, bc, st);
+    case 2: return launch_eq<LatD2Q5, T>(c, g, cur, prev, out, bc, st);
+    case 3: return launch_eq<LatD2Q9, T>(c, g, cur, prev, out, bc, st);
+    case 4: return launch_eq<LatD3Q19, T>(c, g, cur, prev, out, bc, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_mmfd_step<float>(const Consts &, const Grid &, const float *,
-                                            const float *, float *, int, hipStream_t);
+                                            const float *, float *, int, hipStream_t,
+                                            const DirBC *);
 template hipError_t launch_mmfd_step<double>(const Consts &, const Grid &, const double *,
-                                             const double *, double *, int, hipStream_t);
+                                             const double *, double *, int, hipStream_t,
+                                             const DirBC *);
 template hipError_t launch_mmfd_1d_resident<float>(const Consts &, const Grid &, float *, float *,
                                                    float *, int64_t, hipStream_t);
 template hipError_t launch_mmfd_1d_resident<double>(const Consts &, const Grid &, double *,

@@ -39,7 +39,7 @@ template <class L, int EQ, bool THREE, bool THREE_ST, int W, int RG, bool WRAP_A
 __device__ __forceinline__ void tb_window(const T *__restrict__ cur, const T *__restrict__ prev,
                                           T *__restrict__ out_cur, T *__restrict__ out_prev,
                                           int nx, int ny, int H, int TBW, int TBS, int x0, int y0,
-                                          const KC<T> &kc, T *lds) {
+                                          const KC<T> &kc, T *lds, const DirBC *bc = nullptr) {
   constexpr int NT = W * RG;
   constexpr int KB = 8;  // window loads in flight per thread
   constexpr bool BURG = EQ == kBurgers;
@@ -135,6 +135,14 @@ __device__ __forceinline__ void tb_window(const T *__restrict__ cur, const T *__
         T pc[1] = {THREE ? P[y * W + xx] : T(0)};
         T oc[1];
         mmfd_node<L, EQ, THREE, THREE_ST, T, B1>(at, ath, cc, pc, oc, kc);
+        if (bc && bc->on) {
+          // Dirichlet nodes take the value prescribed for step t of this
+          // launch (window nodes outside the grid are wrapped copies that
+          // only ever feed boundary nodes)
+          const int gx = x0 + xx, gy = y0 + y;
+          if (gx >= 0 && gy >= 0 && gx < nx && gy < ny && dir_node(gx, gy, nx, ny))
+            oc[0] = (T)(bc->Gb[dir_index(gx, gy, nx, ny)] * bc->E[t]);
+        }
         O[y * W + xx] = oc[0];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -188,14 +196,14 @@ __global__ __launch_bounds__(W *RG) void k_mmfd_tb(const T *__restrict__ cur,
                                                   T *__restrict__ out_cur,
                                                   T *__restrict__ out_prev, int nx, int ny,
                                                   int H, int TB, int tiles_x, int ntiles,
-                                                  KC<T> kc) {
+                                                  KC<T> kc, DirBC bc) {
   extern __shared__ unsigned char smem_tb[];
   T *lds = reinterpret_cast<T *>(smem_tb);  // [levels][H][W]
   const int TX = W - 2 * TB, TY = H - 2 * TB;
   const int tile = xcd_remap_tb(blockIdx.x, ntiles);
   const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
   tb_window<L, EQ, THREE, THREE_ST, W, RG, false, B1, T>(cur, prev, out_cur, out_prev, nx, ny, H,
-                                                         TB, TB, x0, y0, kc, lds);
+                                                         TB, TB, x0, y0, kc, lds, &bc);
 }
 
 // Batched two-level variant: launch `launch` of a run whose launches advance
@@ -229,7 +237,7 @@ constexpr int kTbW = 64, kTbRG = 8;
 
 template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, int W, typename T>
 hipError_t tb_cfg_w(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
-                    T *oc, T *op, hipStream_t st) {
+                    T *oc, T *op, const DirBC &bc, hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
   const int nx = (int)g.n[0], ny = (int)g.n[1];
   const int TX = W - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
@@ -240,34 +248,38 @@ hipError_t tb_cfg_w(const Consts &c, const Grid &g, const TbPlan &pl, const T *c
                                      (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(W * kTbRG), lds, st, cur, prev, oc, op, nx, ny,
-                     pl.h, pl.tb, tx, tx * ty, kc);
+                     pl.h, pl.tb, tx, tx * ty, kc, bc);
   return hipGetLastError();
 }
 
 template <class L, int EQ, bool THREE, bool THREE_ST, bool B1, typename T>
 hipError_t tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
-                  T *oc, T *op, hipStream_t st) {
+                  T *oc, T *op, const DirBC &bc, hipStream_t st) {
   if (pl.w == 128)
-    return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 128, T>(c, g, pl, cur, prev, oc, op, st);
-  return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 64, T>(c, g, pl, cur, prev, oc, op, st);
+    return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 128, T>(c, g, pl, cur, prev, oc, op, bc, st);
+  return tb_cfg_w<L, EQ, THREE, THREE_ST, B1, 64, T>(c, g, pl, cur, prev, oc, op, bc, st);
 }
 
 template <class L, int EQ, bool B1, typename T>
 hipError_t tb_levels(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
-                     const T *prev, T *oc, T *op, hipStream_t st) {
-  if (!c.three) return tb_cfg<L, EQ, false, false, B1, T>(c, g, pl, cur, prev, oc, op, st);
-  if (!c.three_stencil) return tb_cfg<L, EQ, true, false, B1, T>(c, g, pl, cur, prev, oc, op, st);
-  return tb_cfg<L, EQ, true, true, B1, T>(c, g, pl, cur, prev, oc, op, st);
+                     const T *prev, T *oc, T *op, const DirBC &bc, hipStream_t st) {
+  if (!c.three) return tb_cfg<L, EQ, false, false, B1, T>(c, g, pl, cur, prev, oc, op, bc, st);
+  if (!c.three_stencil)
+    return tb_cfg<L, EQ, true, false, B1, T>(c, g, pl, cur, prev, oc, op, bc, st);
+  return tb_cfg<L, EQ, true, true, B1, T>(c, g, pl, cur, prev, oc, op, bc, st);
 }
 
 template <class L, typename T>
 hipError_t tb_eq(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
-                 T *oc, T *op, hipStream_t st) {
-  if (c.eq == kNSE) return launch_nse_tb<T>(c, g, pl, cur, prev, oc, op, st);
-  if (c.eq == kLCDE) return tb_levels<L, kLCDE, false, T>(c, g, pl, cur, prev, oc, op, st);
+                 T *oc, T *op, const DirBC &bc, hipStream_t st) {
+  if (c.eq == kNSE) {
+    if (bc.on) return hipErrorInvalidValue;
+    return launch_nse_tb<T>(c, g, pl, cur, prev, oc, op, st);
+  }
+  if (c.eq == kLCDE) return tb_levels<L, kLCDE, false, T>(c, g, pl, cur, prev, oc, op, bc, st);
   if (c.eq == kBurgers) {
-    if (c.beta_one) return tb_levels<L, kBurgers, true, T>(c, g, pl, cur, prev, oc, op, st);
-    return tb_levels<L, kBurgers, false, T>(c, g, pl, cur, prev, oc, op, st);
+    if (c.beta_one) return tb_levels<L, kBurgers, true, T>(c, g, pl, cur, prev, oc, op, bc, st);
+    return tb_levels<L, kBurgers, false, T>(c, g, pl, cur, prev, oc, op, bc, st);
   }
   return hipErrorInvalidValue;
 }
@@ -322,11 +334,17 @@ bool tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
 
 template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
-                          const T *prev, T *out_cur, T *out_prev, hipStream_t st) {
-  if (pl.w == 128 && lane_tb_applies(c, sizeof(T)))
+                          const T *prev, T *out_cur, T *out_prev, hipStream_t st,
+                          const DirBC *bcp) {
+  DirBC bc{};
+  if (bcp) bc = *bcp;
+  if (bc.on && pl.tb > kMaxBcSteps) return hipErrorInvalidValue;
+  if (pl.w == 128 && lane_tb_applies(c, sizeof(T))) {
+    if (bc.on) return hipErrorInvalidValue;  // the in-place window has no boundary nodes
     return launch_lane_tb<T>(c, g, pl, cur, out_cur, st);
-  if (c.lattice == 3) return tb_eq<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
-  if (c.lattice == 2) return tb_eq<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, st);
+  }
+  if (c.lattice == 3) return tb_eq<LatD2Q9, T>(c, g, pl, cur, prev, out_cur, out_prev, bc, st);
+  if (c.lattice == 2) return tb_eq<LatD2Q5, T>(c, g, pl, cur, prev, out_cur, out_prev, bc, st);
   return hipErrorInvalidValue;
 }
 
@@ -356,7 +374,7 @@ hipError_t launch_batch_tb(const BatchKey &k, const BatchInst<T> *inst, const in
 
 #define MFD_INST(T)                                                                               \
   template hipError_t launch_mmfd_tb<T>(const Consts &, const Grid &, const TbPlan &, const T *, \
-                                        const T *, T *, T *, hipStream_t);                        \
+                                        const T *, T *, T *, hipStream_t, const DirBC *);         \
   template hipError_t launch_batch_tb<T>(const BatchKey &, const BatchInst<T> *, const int *,    \
                                          int, int64_t, const TbPlan &, hipStream_t);
 MFD_INST(float)

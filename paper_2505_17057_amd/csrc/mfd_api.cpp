@@ -3,6 +3,7 @@
 // report.  See include/mfd.h for the contract of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -74,11 +75,19 @@ int64_t Solver::device_bytes_needed() const {
   const int64_t es = elem();
   int64_t b = 3 * mom_elems() * es;  // level ring (MMFD) / moment ping-pong + scratch (MesoFD)
   if (grid.form == MFD_MESOFD) b += 2 * pop_elems() * es;
-  if (cfg.kind == MFD_THETA) b += 2 * mom_elems() * es;
+  if (cfg.kind == MFD_THETA) b += 2 * mom_elems() * es + theta_buf_bytes();
   if (grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))
     b += mom_elems() * es;
   b += (kReduceBlocks * 8 + 8) * (int64_t)sizeof(double);
   return b;
+}
+
+// control block and two binary64 partials per tile of the largest chunk
+// tiling (tiles hold at least 8 x 8 interior nodes)
+int64_t Solver::theta_buf_bytes() const {
+  if (cfg.kind != MFD_THETA) return 0;
+  const int64_t tiles = (G.n[0] / 8 + 2) * (G.n[1] / 8 + 2);
+  return kThetaCtlBytes + 2 * 8 * tiles;
 }
 
 void Solver::release() {
@@ -95,7 +104,8 @@ int Solver::ensure_buffers() {
   if (buf[0] && need == allocated_bytes) return MFD_OK;
   release();
   const int64_t es = elem(), me = mom_elems() * es, pe = pop_elems() * es;
-  int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8, me};
+  int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8, me,
+                            theta_buf_bytes()};
   if (cfg.kind != MFD_THETA) sizes[5] = sizes[6] = 0;
   if (!(grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))) sizes[8] = 0;
   for (int i = 0; i < kNumBuf; ++i) {
@@ -201,6 +211,7 @@ int Solver::step_t(int64_t nsteps) {
     prev_gap = 1;
     return MFD_OK;
   }
+  if (cfg.kind == MFD_THETA && theta_tol > 0.0) return theta_solve_steps<T>(nsteps);
   const TbPlan pl = effective_plan();
   const int d = pl.tb;
   if (grid.form == MFD_MMFD && cfg.kind != MFD_THETA && d > 1 &&
@@ -211,12 +222,13 @@ int Solver::step_t(int64_t nsteps) {
     const int64_t nblk = nsteps / d;
     for (int64_t b = 0; b < nblk; ++b) {
       hipError_t e;
+      const DirBC bc = dir_bc(steps_done + b * d, d);
       if (!consts.three) {
-        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], nullptr, B[ip], nullptr, stream);
+        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], nullptr, B[ip], nullptr, stream, &bc);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         std::swap(ic, ip);
       } else {
-        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], B[ip], B[io], B[ix], stream);
+        e = launch_mmfd_tb<T>(consts, G, pl, B[ic], B[ip], B[io], B[ix], stream, &bc);
         if (e != hipSuccess) return hip(e, "blocked step launch");
         const int oc = ic, op = ip;
         ic = io;
@@ -257,11 +269,13 @@ int Solver::step_t(int64_t nsteps) {
         std::swap(ic, io);  // two-level: old current becomes prev
         ip = io;
       } else if (!consts.three) {
-        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[ip], tb, stream);
+        const DirBC bc = dir_bc(steps_done + s, 1);
+        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[ip], tb, stream, &bc);
         if (e != hipSuccess) return hip(e, "mmfd step launch");
         std::swap(ic, ip);
       } else {
-        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[io], tb, stream);
+        const DirBC bc = dir_bc(steps_done + s, 1);
+        e = launch_mmfd_step<T>(consts, G, B[ic], B[ip], B[io], tb, stream, &bc);
         if (e != hipSuccess) return hip(e, "mmfd step launch");
         const int t = ip;
         ip = ic;
@@ -304,8 +318,95 @@ int Solver::step_t(int64_t nsteps) {
   return MFD_OK;
 }
 
+// Dirichlet values of the launch that writes steps first_step + 1 .. +nsteps
+DirBC Solver::dir_bc(int64_t first_step, int nsteps) const {
+  DirBC b;
+  std::memset(&b, 0, sizeof(b));
+  if (!dirichlet) return b;
+  b.on = 1;
+  b.Gb = (const double *)d_bnd;
+  for (int s = 1; s <= nsteps && s <= kMaxBcSteps; ++s)
+    b.E[s] = std::exp(bnd_lambda * ((double)(first_step + s) * cfg.dt));
+  return b;
+}
+
+// Theta steps solved to a tolerance.  2D grids the fused window takes: the
+// chunk sequence is decided on the device (no host round trip per step);
+// others: one host check per chunk of sweeps.
+template <typename T>
+int Solver::theta_solve_steps(int64_t nsteps) {
+  T *B[kNumBuf];
+  for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  const int K = theta_chunk;
+  const int cap = cfg.theta_iters;
+  const int nchunk = (cap + K - 1) / K;
+  const int64_t part_cap = (theta_buf_bytes() - kThetaCtlBytes) / 16;
+  const int tiles = theta_solve_tiles(consts, G, K, (int)sizeof(T));
+  if (tiles > 0 && tiles <= part_cap) {
+    ThetaCtl *ctl = (ThetaCtl *)buf[kThetaBuf];
+    double *part = (double *)((char *)buf[kThetaBuf] + kThetaCtlBytes);
+    T *const ring[4] = {B[ic], B[ip], B[5], B[6]};
+    hipError_t e = launch_theta_ctl_init<T>(ctl, stream);
+    if (e != hipSuccess) return hip(e, "theta control launch");
+    for (int64_t s = 0; s < nsteps; ++s)
+      for (int c = 0; c < nchunk; ++c) {
+        e = launch_theta_chunk<T>(consts, G, K, ring, ctl, part, theta_tol, cap, c == 0, stream);
+        if (e != hipSuccess) return hip(e, "theta chunk launch");
+      }
+    e = launch_theta_gather<T>(ring, ctl, G.N, stream);
+    if (e != hipSuccess) return hip(e, "theta gather launch");
+    steps_done += nsteps;
+    prev_gap = 1;
+    return MFD_OK;
+  }
+  // host-checked chunks: rhs into B[5]; iterates alternate B[io] / B[6]
+  double *part = (double *)buf[kRedBuf];
+  double *out = part + kReduceBlocks * 8;
+  const double den = theta_den(consts);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e = launch_theta_rhs<T>(consts, G, B[ic], B[5], stream);
+    if (e != hipSuccess) return hip(e, "theta rhs launch");
+    const T *src = B[ic];
+    int k = 0;
+    bool conv = false;
+    while (true) {
+      const T *before = src;
+      for (int it = 0; it < K; ++it) {
+        T *dst = (k % 2 == 0) ? B[io] : B[6];
+        e = launch_theta_sweep<T>(consts, G, src, B[5], dst, stream);
+        if (e != hipSuccess) return hip(e, "theta sweep launch");
+        before = src;
+        src = dst;
+        ++k;
+      }
+      e = launch_sq_sums<T>(src, before, B[5], G.N, part, out, stream);
+      if (e != hipSuccess) return hip(e, "theta residual launch");
+      double h[2];
+      int rc = copy_out(h, out, sizeof(h), 0);
+      if (rc) return rc;
+      if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+        return fail(MFD_E_UNSTABLE, "non-finite theta residual");
+      conv = den * den * h[0] <= theta_tol * theta_tol * h[1];
+      if (conv || k >= cap) break;
+    }
+    if (src == B[6]) {  // the result is kept in the io role
+      std::swap(buf[io], buf[6]);
+      std::swap(B[io], B[6]);
+    }
+    std::swap(ic, io);
+    ip = io;
+    ++steps_done;
+    th_total += k;
+    ++th_steps;
+    th_max = std::max(th_max, k);
+    if (!conv) ++th_unconv;
+  }
+  prev_gap = 1;
+  return MFD_OK;
+}
+
 bool Solver::source_supported() const {
-  if (cfg.kind == MFD_THETA || consts.eq != kLCDE) return false;
+  if (cfg.kind == MFD_THETA || consts.eq != kLCDE || consts.wave || dirichlet) return false;
   return grid.form == MFD_MMFD || grid.dim <= 2;  // MesoFD: 1D / 2D
 }
 
@@ -313,6 +414,7 @@ int Solver::step(int64_t nsteps) {
   if (sticky) return fail(MFD_E_HIP, "solver is in a failed HIP state: %s", err.c_str());
   if (nsteps < 0) return fail(MFD_E_ARG, "nsteps < 0");
   if (!state_set) return fail(MFD_E_ORDER, "state not set");
+  if (dirichlet && !bnd_set) return fail(MFD_E_ORDER, "Dirichlet values not set (mfd_set_boundary)");
   if (nsteps == 0) return MFD_OK;
   return grid.precision == MFD_FP64 ? step_t<double>(nsteps) : step_t<float>(nsteps);
 }
@@ -326,7 +428,10 @@ int Solver::step(int64_t nsteps) {
 
 extern "C" int mfd_create(mfd_solver **out, const mfd_grid *g) {
   if (!out || !g) return MFD_E_ARG;
-  if (g->dim < 1 || g->dim > 3 || g->reserved != 0) return MFD_E_ARG;
+  if (g->dim < 1 || g->dim > 3) return MFD_E_ARG;
+  if (g->boundary != MFD_PERIODIC && g->boundary != MFD_DIRICHLET) return MFD_E_ARG;
+  if (g->boundary == MFD_DIRICHLET && (g->dim != 2 || g->form != MFD_MMFD))
+    return MFD_E_UNSUPPORTED;
   if (g->precision != MFD_FP64 && g->precision != MFD_FP32) return MFD_E_ARG;
   if (g->form != MFD_MMFD && g->form != MFD_MESOFD) return MFD_E_ARG;
   if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return MFD_E_ARG;
@@ -341,6 +446,7 @@ extern "C" int mfd_create(mfd_solver **out, const mfd_grid *g) {
   Solver *s = new (std::nothrow) Solver();
   if (!s) return MFD_E_OOM;
   s->grid = *g;
+  s->dirichlet = g->boundary == MFD_DIRICHLET;
   for (int a = 0; a < 3; ++a) s->G.n[a] = a < g->dim ? g->n[a] : 1;
   s->G.N = N;
   *out = reinterpret_cast<mfd_solver *>(s);
@@ -350,9 +456,10 @@ extern "C" int mfd_create(mfd_solver **out, const mfd_grid *g) {
 extern "C" int mfd_destroy(mfd_solver *h) {
   if (!h) return MFD_OK;
   Solver *s = reinterpret_cast<Solver *>(h);
-  if (s->buf[0] || s->d_src) (void)hipStreamSynchronize(s->stream);
+  if (s->buf[0] || s->d_src || s->d_bnd) (void)hipStreamSynchronize(s->stream);
   s->release();
   if (s->d_src) dev_free(s->d_src);
+  if (s->d_bnd) dev_free(s->d_bnd);
   delete s;
   return MFD_OK;
 }
@@ -423,8 +530,12 @@ extern "C" int mfd_set_equation(mfd_solver *h, int eq, const mfd_eq_params *p) {
   SOLVER_OR_ARG(h);
   Solver *s = reinterpret_cast<Solver *>(h);
   if (!p) return s->fail(MFD_E_ARG, "null equation parameters");
-  if (eq != MFD_LCDE && eq != MFD_BURGERS && eq != MFD_NSE)
+  if (eq != MFD_LCDE && eq != MFD_BURGERS && eq != MFD_NSE && eq != MFD_WAVE)
     return s->fail(MFD_E_ARG, "unknown equation %d", eq);
+  if (eq == MFD_NSE && s->dirichlet)
+    return s->fail(MFD_E_UNSUPPORTED, "Dirichlet boundaries are implemented for scalar equations");
+  if (eq == MFD_WAVE && !(p->beta == 0.0 || (p->beta > 0.0 && std::isfinite(p->beta))))
+    return s->fail(MFD_E_ARG, "the wave EDF needs beta > 0");
   if (eq == MFD_NSE && s->grid.dim == 1)
     return s->fail(MFD_E_UNSUPPORTED, "the NSE needs a 2D or 3D lattice");
   if (eq == MFD_NSE && !p->he_luo && p->rho0 != 0.0 && !std::isfinite(p->rho0))
@@ -433,7 +544,7 @@ extern "C" int mfd_set_equation(mfd_solver *h, int eq, const mfd_eq_params *p) {
     return s->fail(MFD_E_ARG, "He-Luo EDF needs rho0 > 0");
   s->cfg.eq = eq;
   s->cfg.ep = *p;
-  if (eq == MFD_BURGERS && p->beta == 0.0) s->cfg.ep.beta = 1.0;
+  if ((eq == MFD_BURGERS || eq == MFD_WAVE) && p->beta == 0.0) s->cfg.ep.beta = 1.0;
   s->have_eq = true;
   int rc = rebuild(s);
   if (rc < 0) return rc;
@@ -460,6 +571,8 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
   if (kind == MFD_THREE_LEVEL && !ah) return s->fail(MFD_E_ARG, "three-level scheme needs ah");
   if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(MFD_E_ARG, "dt must be positive");
   if (kind == MFD_THETA) {
+    if (s->dirichlet)
+      return s->fail(MFD_E_UNSUPPORTED, "the theta scheme runs on periodic grids");
     if (s->cfg.eq != MFD_LCDE)
       return s->fail(MFD_E_UNSUPPORTED, "the theta scheme is implemented for the LCDE only");
     if (!(theta >= 0.0 && theta <= 1.0) || theta_iters < 0)
@@ -866,5 +979,149 @@ extern "C" int mfd_level_ptr(mfd_solver *h, int level, int field, int population
   if (field < 0 || field >= nfld) return s->fail(MFD_E_ARG, "field %d out of range", field);
   char *base = (char *)s->buf[populations ? s->pc : (level == 0 ? s->ic : s->ip)];
   *ptr = base + (int64_t)field * s->G.N * s->elem();
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_theta_tolerance(mfd_solver *h, double tol, int32_t chunk) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->configured || s->cfg.kind != MFD_THETA)
+    return s->fail(MFD_E_ORDER, "set a theta scheme first");
+  if (!std::isfinite(tol) || tol < 0.0) return s->fail(MFD_E_ARG, "tolerance must be >= 0");
+  if (chunk == 0) chunk = 8;
+  if (chunk < 1 || chunk > 16) return s->fail(MFD_E_ARG, "chunk must lie in [1, 16]");
+  if (tol > 0.0 && s->cfg.theta_iters < 1)
+    return s->fail(MFD_E_ARG, "the sweep cap (theta_iters) must be >= 1");
+  s->theta_tol = tol;
+  s->theta_chunk = chunk;
+  return MFD_OK;
+}
+
+extern "C" int mfd_theta_stats(mfd_solver *h, int64_t *total_sweeps, int64_t *steps,
+                               int32_t *max_sweeps, int32_t *unconverged, int reset) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  ThetaCtl c;
+  std::memset(&c, 0, sizeof(c));
+  if (s->buf[Solver::kThetaBuf]) {
+    int rc = s->copy_out(&c, s->buf[Solver::kThetaBuf], sizeof(c), 0);
+    if (rc) return rc;
+  }
+  if (total_sweeps) *total_sweeps = c.total_sweeps + s->th_total;
+  if (steps) *steps = c.steps + s->th_steps;
+  if (max_sweeps) *max_sweeps = std::max(c.max_sweeps, s->th_max);
+  if (unconverged) *unconverged = c.unconverged + s->th_unconv;
+  if (reset) {
+    s->th_total = s->th_steps = 0;
+    s->th_max = s->th_unconv = 0;
+    if (s->buf[Solver::kThetaBuf]) {
+      c.total_sweeps = c.steps = 0;
+      c.max_sweeps = c.unconverged = 0;
+      int rc = s->copy_in(s->buf[Solver::kThetaBuf], &c, sizeof(c), 0);
+      if (rc) return rc;
+    }
+  }
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_boundary(mfd_solver *h, const double *G, int64_t count, int on_device,
+                                double lambda) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->dirichlet) return s->fail(MFD_E_ORDER, "the grid was created periodic");
+  if (!G) return s->fail(MFD_E_ARG, "null boundary values");
+  if (count != s->G.N)
+    return s->fail(MFD_E_ARG, "expected %lld values, got %lld", (long long)s->G.N,
+                   (long long)count);
+  if (!std::isfinite(lambda)) return s->fail(MFD_E_ARG, "lambda is not finite");
+  const int nx = (int)s->G.n[0], ny = (int)s->G.n[1];
+  std::vector<double> full;
+  const double *hg = G;
+  if (on_device) {
+    full.resize((size_t)s->G.N);
+    int rc = s->hip(hipMemcpy(full.data(), G, (size_t)s->G.N * 8, hipMemcpyDeviceToHost),
+                    "hipMemcpy (boundary)");
+    if (rc) return rc;
+    hg = full.data();
+  }
+  const int64_t nb = dir_count(nx, ny);
+  std::vector<double> comp((size_t)nb);
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      if (!dir_node(x, y, nx, ny)) continue;
+      const double v = hg[(int64_t)y * nx + x];
+      if (!std::isfinite(v)) return s->fail(MFD_E_ARG, "boundary value (%d, %d) is not finite", x, y);
+      comp[(size_t)dir_index(x, y, nx, ny)] = v;
+    }
+  if (!s->d_bnd) {
+    if (dev_malloc(&s->d_bnd, (size_t)nb * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      s->d_bnd = nullptr;
+      return s->fail(MFD_E_OOM, "no device memory for the boundary values");
+    }
+  } else {
+    (void)hipStreamSynchronize(s->stream);
+  }
+  int rc = s->hip(hipMemcpy(s->d_bnd, comp.data(), (size_t)nb * 8, hipMemcpyHostToDevice),
+                  "hipMemcpy (boundary)");
+  if (rc) return rc;
+  s->bnd_lambda = lambda;
+  s->bnd_set = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_wave_start(mfd_solver *h, const double *phi_t, int64_t count, int on_device) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->configured || !s->consts.wave || !s->consts.three)
+    return s->fail(MFD_E_ORDER, "configure a three-level wave scheme first");
+  if (s->grid.form != MFD_MMFD)
+    return s->fail(MFD_E_UNSUPPORTED, "the special first step is a moment (MMFD) step");
+  if (!s->state_set || s->steps_done != 0)
+    return s->fail(MFD_E_ORDER, "set level 0 (phi at t = 0) just before the first step");
+  if (s->dirichlet && !s->bnd_set)
+    return s->fail(MFD_E_ORDER, "Dirichlet values not set (mfd_set_boundary)");
+  if (!phi_t) return s->fail(MFD_E_ARG, "null phi_t");
+  if (count != s->G.N)
+    return s->fail(MFD_E_ARG, "expected %lld values, got %lld", (long long)s->G.N,
+                   (long long)count);
+  void *dphit = nullptr;
+  const size_t bytes = (size_t)s->G.N * 8;
+  if (dev_malloc(&dphit, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return s->fail(MFD_E_OOM, "no device memory for phi_t");
+  }
+  int rc = s->hip(hipMemcpyAsync(dphit, phi_t, bytes,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 s->stream),
+                  "hipMemcpyAsync (phi_t)");
+  // alpha = A22 beta c_s^2 of the wave equation: the Taylor start
+  // phi + dt phi_t + (dt^2 / 2) alpha Laplacian phi in lattice units
+  const double A22 = 0.5 * (s->consts.ap + s->consts.ahp);
+  const double cw = ((0.5 * A22) * s->cfg.ep.beta) * s->consts.d0;
+  const DirBC bc = s->dir_bc(0, 1);
+  if (!rc) {
+    hipError_t e = s->grid.precision == MFD_FP64
+                       ? launch_wave_start<double>(s->consts, s->G, (const double *)s->buf[s->ic],
+                                                   (const double *)dphit, (double *)s->buf[s->io],
+                                                   s->cfg.dt, cw, bc, s->stream)
+                       : launch_wave_start<float>(s->consts, s->G, (const float *)s->buf[s->ic],
+                                                  (const double *)dphit, (float *)s->buf[s->io],
+                                                  s->cfg.dt, cw, bc, s->stream);
+    rc = s->hip(e, "wave start launch");
+  }
+  if (!rc) rc = s->hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  dev_free(dphit);
+  if (rc) return rc;
+  const int oc = s->ic, op = s->ip;
+  s->ic = s->io;
+  s->ip = oc;
+  s->io = op;
+  s->steps_done = 1;
+  s->prev_gap = 1;
+  s->prev_set = true;
   return MFD_OK;
 }

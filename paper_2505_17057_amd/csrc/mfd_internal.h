@@ -42,6 +42,9 @@ struct LatD3Q19 {
 
 // ---------------------------------------------------------- configuration
 enum Eq { kLCDE = 0, kBurgers = 1, kNSE = 2 };
+// equation code of the wave equation as given by the caller; its constants
+// are those of a linear EDF, so its steps run as kLCDE
+constexpr int kWaveInput = 3;
 
 // All derived constants of one solver, in binary64 (host side).
 struct Consts {
@@ -64,7 +67,8 @@ struct Consts {
   double rho0, rinv0;
   int he_luo;
   // theta
-  double theta, th1, inv_den;
+  double theta, th1, den, inv_den;  // den = 1 + (1 - theta) 2 sum_p Cp_p
+  int wave;           // the linear EDF of the wave equation (eq = kLCDE)
   int three;          // three-level scheme
   int three_stencil;  // level t - dt enters through central differences
 };
@@ -103,9 +107,39 @@ struct Grid {
   int64_t N;
 };
 
+// Dirichlet boundary of a 2D grid: the nodes with x or y on the grid's edge
+// hold prescribed values G_b(x) exp(lambda t).  G_b is stored compactly in
+// binary64: row y = 0 (x = 0..nx-1), row y = ny-1, then column x = 0 and
+// column x = nx-1 (y = 1..ny-2 each).  A launch that writes the levels
+// t + s dt, s = 1..tb, takes E[s] = exp(lambda (t + s dt)); binary32 levels
+// hold the binary64 product rounded once.
+constexpr int kMaxBcSteps = 16;
+struct DirBC {
+  const double *Gb;
+  double E[kMaxBcSteps + 1];
+  int on;
+};
+__host__ __device__ inline bool dir_node(int gx, int gy, int nx, int ny) {
+  return gx == 0 || gy == 0 || gx == nx - 1 || gy == ny - 1;
+}
+__host__ __device__ inline int64_t dir_index(int gx, int gy, int nx, int ny) {
+  if (gy == 0) return gx;
+  if (gy == ny - 1) return (int64_t)nx + gx;
+  if (gx == 0) return 2 * (int64_t)nx + (gy - 1);
+  return 2 * (int64_t)nx + (ny - 2) + (gy - 1);
+}
+inline int64_t dir_count(int64_t nx, int64_t ny) { return 2 * nx + 2 * (ny - 2); }
+
 template <typename T>
 hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const T *prev, T *out,
-                            int tb_depth, hipStream_t st);
+                            int tb_depth, hipStream_t st, const DirBC *bc = nullptr);
+
+// special first step of the three-level wave scheme: out = phi^0 + dt phi_t
+// + cw sum_axes D2_axis phi^0 (binary64 arithmetic, rounded once), with the
+// Dirichlet values of t = dt on the boundary when bc is on
+template <typename T>
+hipError_t launch_wave_start(const Consts &c, const Grid &g, const T *phi0, const double *phit,
+                             T *out, double dt, double cw, const DirBC &bc, hipStream_t st);
 
 // source term of the linear CDE (kernels_source.hip): S(x, t) = exp(lambda t)
 // G(x), M_1F = v S, coefficients b (level t) and bh (level t - dt)
@@ -198,7 +232,8 @@ hipError_t launch_nse_tb(const Consts &c, const Grid &g, const TbPlan &pl, const
                          const T *prev, T *out_cur, T *out_prev, hipStream_t st);
 template <typename T>
 hipError_t launch_mmfd_tb(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur,
-                          const T *prev, T *out_cur, T *out_prev, hipStream_t st);
+                          const T *prev, T *out_cur, T *out_prev, hipStream_t st,
+                          const DirBC *bc = nullptr);
 
 // MesoFD step: moments of level t (mom) and t-dt (prev_mom) in; moments and
 // (pop_out not null) populations of level t+1 out.
@@ -226,6 +261,36 @@ int theta_fused_rows(const Consts &c, const Grid &g, int K, int elem);
 template <typename T>
 hipError_t launch_theta_fused(const Consts &c, const Grid &g, int K, const T *cur, T *out,
                               hipStream_t st);
+
+// Theta step solved to a tolerance (kernels_misc.hip).  The control block
+// lives in device memory; its roles index four level buffers: 0 and 1 hold
+// phi^n and phi^(n-1) between mfd_step calls, 2 and 3 are work buffers.
+struct ThetaCtl {
+  int role[4];    // buffer of: phi^n, phi^(n-1), next destination, spare
+  int nsrc, ndst; // iterate source / destination of the next continuation chunk
+  int done;       // the running step's solve has stopped
+  int sweeps;     // sweeps of the running step so far
+  unsigned count; // workgroups finished in the running chunk
+  int max_sweeps, unconverged;
+  int pad;
+  long long total_sweeps, steps;
+};
+inline double theta_den(const Consts &c) { return c.den; }
+// tiles of one chunk of K sweeps (0 when the fused window cannot run)
+int theta_solve_tiles(const Consts &c, const Grid &g, int K, int elem);
+template <typename T>
+hipError_t launch_theta_ctl_init(ThetaCtl *ctl, hipStream_t st);
+// one chunk of K sweeps; first = the step's first chunk (starts from phi^n)
+template <typename T>
+hipError_t launch_theta_chunk(const Consts &c, const Grid &g, int K, T *const bufs[4],
+                              ThetaCtl *ctl, double *part, double tol, int cap, bool first,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_theta_gather(T *const bufs[4], const ThetaCtl *ctl, int64_t N, hipStream_t st);
+// sum (a - b)^2 and sum c^2 in binary64 (out[0], out[1]); partial as launch_reduce
+template <typename T>
+hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,
+                          double *out, hipStream_t st);
 
 template <typename T>
 hipError_t launch_theta_rhs(const Consts &c, const Grid &g, const T *cur, T *rhs, hipStream_t st);

@@ -289,7 +289,8 @@ template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T
 __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
                                                 const T *__restrict__ prev,
                                                 T *__restrict__ out, int nx, int ny, int x0,
-                                                int y0, const KC<T> &kc) {
+                                                int y0, const KC<T> &kc,
+                                                const DirBC *bc = nullptr) {
   if constexpr (EQ == kNSE && L::D == 2) {
     mmfd_plane_tile_pf<L, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc);
   } else {
@@ -339,6 +340,11 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
       pc[f] = THREE ? prev[f * N + gi] : T(0);
     }
     mmfd_node<L, EQ, THREE, THREE_ST, T>(at, ath, cc, pc, oc, kc);
+    if constexpr (L::D == 2 && NF == 1) {
+      // Dirichlet nodes take their prescribed value
+      if (bc && bc->on && dir_node(gx, gy, nx, ny))
+        oc[0] = (T)(bc->Gb[dir_index(gx, gy, nx, ny)] * bc->E[1]);
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
   }

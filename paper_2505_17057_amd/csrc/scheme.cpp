@@ -138,7 +138,32 @@ int build_consts(const SchemeInput &in, Consts &c) {
   c.three = in.kind == MFD_THREE_LEVEL;
   c.three_stencil = c.three && (c.ahp != 0.0 || c.ahm != 0.0 || c.abhp != 0.0 || c.abhm != 0.0);
 
-  if (in.eq == kLCDE) {
+  if (in.eq == kWaveInput) {
+    // wave equation (Example 3 of the paper): the linear EDF
+    // f_j = w_j phi [1 + (beta - 1)(|e_j|^2 - dim d0) / (2 d0)], no velocity;
+    // it runs the linear CDE kernels with this constant table
+    c.eq = kLCDE;
+    c.wave = 1;
+    for (int j = 0; j < c.q; ++j) {
+      double e2 = 0.0;
+      for (int x = 0; x < 3; ++x) e2 = e2 + (double)(c.e[j][x] * c.e[j][x]);
+      const double t = (e2 - (double)c.dim * d0) / (2.0 * d0);
+      c.ubar[j] = c.w[j] * (1.0 + (in.beta - 1.0) * t);
+    }
+    for (int p = 0; p < c.npair; ++p) {
+      const int j = c.pair[p];
+      c.ubp[p] = c.ubar[j];
+      c.ubm[p] = 0.0;
+      c.Cp[p] = c.ap * c.ubp[p];
+      c.Cm[p] = 0.0;
+      c.Chp[p] = c.ahp * c.ubp[p];
+      c.Chm[p] = 0.0;
+    }
+    c.theta = 1.0;
+    c.th1 = 0.0;
+    c.den = 1.0;
+    c.inv_den = 1.0;
+  } else if (in.eq == kLCDE) {
     const double A10 = -c.Ah0 - 1.0;
     const double A22 = 0.5 * (c.ap + c.ahp);
     const double ratio = -A10 / A22;
@@ -168,7 +193,8 @@ int build_consts(const SchemeInput &in, Consts &c) {
     c.th1 = 1.0 - c.theta;
     double sp = 0.0;
     for (int p = 0; p < c.npair; ++p) sp = sp + c.Cp[p];
-    c.inv_den = 1.0 / (1.0 + c.th1 * (2.0 * sp));
+    c.den = 1.0 + c.th1 * (2.0 * sp);
+    c.inv_den = 1.0 / c.den;
   } else if (in.eq == kBurgers) {
     c.bh = 0.5 * in.dt / in.dx;
     c.beta_one = in.beta == 1.0;

@@ -25,9 +25,12 @@ struct Config {
 struct Solver {
   // device buffers: 0..2 moment ring, 3..4 population ping-pong, 5..6 theta
   // rhs / Jacobi work, 7 reduction scratch, 8 fourth moment buffer (blocked
-  // three-level steps write two levels)
-  static constexpr int kNumBuf = 9;
+  // three-level steps write two levels), 9 control block and tile partials of
+  // the to-tolerance theta solve
+  static constexpr int kNumBuf = 10;
   static constexpr int kRedBuf = 7;
+  static constexpr int kThetaBuf = 9;
+  static constexpr int64_t kThetaCtlBytes = 256;
 
   mfd_grid grid{};
   Grid G{};
@@ -41,9 +44,20 @@ struct Solver {
   int64_t allocated_bytes = 0;
   int ic = 0, ip = 1, io = 2, pc = 3, pn = 4, ix = 8;  // roles in the rings
   int64_t steps_done = 0;
+  // theta step solved to a tolerance (tol > 0; theta_iters is then the cap)
+  double theta_tol = 0.0;
+  int theta_chunk = 8;
+  int64_t th_total = 0, th_steps = 0;  // host-checked solves (unfused path)
+  int th_max = 0, th_unconv = 0;
   int prev_gap = 1;  // steps between the current and the held previous level
   int tb = 0;           // temporal-blocking depth requested (0 = automatic)
   TbPlan tuned{0, 0};   // plan chosen by the autotuner (tb = 0: not tuned)
+  // Dirichlet boundary (2D): compact binary64 values G_b on the device,
+  // prescribed value G_b exp(lambda t) with t = n dt as for the source term
+  bool dirichlet = false, bnd_set = false;
+  void *d_bnd = nullptr;
+  double bnd_lambda = 0.0;
+  DirBC dir_bc(int64_t first_step, int nsteps) const;
   // source term (linear CDE): G in the solver's precision, on the device
   bool src_on = false;
   SourceSpec src{};
@@ -58,6 +72,7 @@ struct Solver {
   int64_t mom_elems() const;
   int64_t pop_elems() const;
   int64_t device_bytes_needed() const;
+  int64_t theta_buf_bytes() const;
   void release();
   int ensure_buffers();
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
@@ -69,6 +84,8 @@ struct Solver {
   int autotune(int32_t *chosen);
   template <typename T>
   int step_t(int64_t nsteps);
+  template <typename T>
+  int theta_solve_steps(int64_t nsteps);
 };
 
 }  // namespace mfd

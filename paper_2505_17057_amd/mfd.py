@@ -44,7 +44,8 @@ DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
 QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 FORMS = {"mmfd": 0, "mesofd": 1}
-EQS = {"lcde": 0, "burgers": 1, "nse": 2}
+EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
+BOUNDARIES = {"periodic": 0, "dirichlet": 1}
 KINDS = {"two_level": 0, "theta": 1, "three_level": 2}
 PRESETS = {"srt": 0, "trt": 1, "one_stage": 2, "two_level": 3}
 
@@ -57,7 +58,7 @@ class MfdError(RuntimeError):
 
 class mfd_grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("form", C.c_int32),
-                ("reserved", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double)]
+                ("boundary", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double)]
 
 
 class mfd_eq_params(C.Structure):
@@ -113,6 +114,11 @@ _SIGS = {
     "mfd_max_stable_dt": ([C.c_int, C.c_double, C.c_double, _PD, C.c_double, C.POINTER(C.c_int64),
                            _PD, _PD], C.c_int),
     "mfd_level_ptr": ([_H, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
+    "mfd_theta_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                         C.POINTER(C.c_int32), C.c_int], C.c_int),
+    "mfd_set_boundary": ([_H, _PD, C.c_int64, C.c_int, C.c_double], C.c_int),
+    "mfd_wave_start": ([_H, _PD, C.c_int64, C.c_int], C.c_int),
     "mfd_memory_stats": ([C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int], C.c_int),
     "mfd_batch_create": ([C.POINTER(_H)], C.c_int),
     "mfd_batch_destroy": ([_H], C.c_int),
@@ -210,7 +216,7 @@ def _ptr_of(x):
 class Solver:
     """Owner of one mfd_solver handle (marshalling only)."""
 
-    def __init__(self, lattice, n, dx, precision="fp64", form="mmfd"):
+    def __init__(self, lattice, n, dx, precision="fp64", form="mmfd", boundary="periodic"):
         self.lattice = lattice
         self.dim = DIMS[lattice]
         n = tuple(int(v) for v in n)
@@ -219,7 +225,7 @@ class Solver:
         g.dim = self.dim
         g.precision = PRECISIONS[precision]
         g.form = FORMS[form]
-        g.reserved = 0
+        g.boundary = BOUNDARIES[boundary]
         g.n = (C.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
         g.dx = float(dx)
         h = _H()
@@ -298,6 +304,11 @@ class Solver:
         return self.check(lib.mfd_set_state(self.h, level, C.c_void_p(addr), nb, dev, int(populations)),
                           "mfd_set_state")
 
+    def set_state_device(self, addr, nbytes, level=0, populations=False):
+        """mfd_set_state from a raw device address (e.g. mfd_level_ptr)."""
+        return self.check(lib.mfd_set_state(self.h, level, C.c_void_p(int(addr)), int(nbytes), 1,
+                                            int(populations)), "mfd_set_state")
+
     def get_state(self, level=0, populations=False, out=None):
         m, p, _ = self.state_size()
         if out is None:
@@ -349,6 +360,29 @@ class Solver:
         d = C.c_int32()
         self.check(lib.mfd_autotune(self.h, C.byref(d)), "mfd_autotune")
         return d.value
+
+    def set_theta_tolerance(self, tol, chunk=0):
+        return self.check(lib.mfd_set_theta_tolerance(self.h, float(tol), int(chunk)),
+                          "mfd_set_theta_tolerance")
+
+    def theta_stats(self, reset=False):
+        a, b = C.c_int64(), C.c_int64()
+        c, d = C.c_int32(), C.c_int32()
+        self.check(lib.mfd_theta_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
+                                       1 if reset else 0), "mfd_theta_stats")
+        return dict(total_sweeps=a.value, steps=b.value, max_sweeps=c.value, unconverged=d.value)
+
+    def set_boundary(self, G, lam=0.0):
+        """Dirichlet values G(x) exp(lam t) of the edge nodes (mfd_set_boundary)."""
+        G = np.ascontiguousarray(G, dtype=np.float64).ravel()
+        return self.check(lib.mfd_set_boundary(self.h, G.ctypes.data_as(_PD), G.size, 0, float(lam)),
+                          "mfd_set_boundary")
+
+    def wave_start(self, phi_t):
+        """Special first step of the three-level wave scheme (mfd_wave_start)."""
+        v = np.ascontiguousarray(phi_t, dtype=np.float64).ravel()
+        return self.check(lib.mfd_wave_start(self.h, v.ctypes.data_as(_PD), v.size, 0),
+                          "mfd_wave_start")
 
     def level_ptr(self, level=0, field=0, populations=False):
         p = C.c_void_p()

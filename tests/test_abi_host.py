@@ -261,3 +261,58 @@ def test_max_stable_dt_argument_checks(M):
     e = C.c_double()
     assert M.lib.mfd_max_stable_dt(3, 0.0, 0.1, u, 0.01, big, C.byref(d), C.byref(e)) == M.MFD_E_ARG
 
+
+
+@pytest.mark.parametrize("lat,beta,gamma", [("D2Q5", 1.0, 0.375), ("D2Q9", 1.0, 0.375),
+                                            ("D2Q9", 0.75, 0.5), ("D3Q19", 1.25, 0.3)])
+def test_wave_constant_tables_bitwise(M, lat, beta, gamma):
+    """The wave EDF table (Example 3) of the library equals the oracle's bit
+    for bit, and the configured three-level wave scheme is neutral (largest
+    root modulus 1) on a periodic grid."""
+    n = (9,) * O.DIMS[lat]
+    a, ah = (gamma, 2 * (1 - gamma), gamma), (0.0, -1.0, 0.0)
+    spec = dict(lattice=lat, eq="wave", n=n, beta=beta, a=a, ah=ah, levels=3)
+    w, ub, tab = O.tables(spec)
+    s = M.Solver(lat, n, 1.0, "fp64", "mmfd")
+    s.set_equation("wave", beta=beta)
+    s.set_scheme("three_level", a, ah, dt=1.0)
+    gw, gub, gtab = s.linear_tables()
+    assert np.array_equal(gw, w) and np.array_equal(gub, ub)
+    for k in tab:
+        assert np.array_equal(gtab[k], tab[k]), k
+    assert abs(s.max_amplification() - 1.0) < 1e-12
+    s.close()
+
+
+def test_dirichlet_argument_checks(M):
+    """Dirichlet grids are 2D MMFD; scalar equations only; periodic grids have
+    no boundary values; the first wave step needs a three-level wave scheme."""
+    with pytest.raises(M.MfdError) as ei:
+        M.Solver("D1Q3", (16,), 1.0, "fp64", "mmfd", boundary="dirichlet")
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    with pytest.raises(M.MfdError) as ei:
+        M.Solver("D2Q9", (16, 16), 1.0, "fp64", "mesofd", boundary="dirichlet")
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    s = M.Solver("D2Q9", (16, 16), 1.0, "fp64", "mmfd", boundary="dirichlet")
+    with pytest.raises(M.MfdError) as ei:
+        s.set_equation("nse", rho0=1.0)
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    s.set_equation("lcde", u=(0.1, 0.0), K=[[0.1, 0], [0, 0.1]])
+    with pytest.raises(M.MfdError) as ei:
+        s.set_scheme("theta", (1.0, 0.0, 0.0), theta=0.5, theta_iters=4)
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    with pytest.raises(M.MfdError):
+        s.set_boundary(np.zeros(10))  # wrong count
+    with pytest.raises(M.MfdError):
+        s.set_boundary(np.full(256, np.nan))
+    s.close()
+    p = M.Solver("D2Q9", (16, 16), 1.0, "fp64", "mmfd")
+    p.set_equation("wave", beta=1.0)
+    p.set_scheme("three_level", (0.375, 1.25, 0.375), (0.0, -1.0, 0.0), dt=1.0)
+    with pytest.raises(M.MfdError) as ei:
+        p.set_boundary(np.zeros(256))
+    assert ei.value.code == M.MFD_E_ORDER
+    with pytest.raises(M.MfdError) as ei:
+        p.wave_start(np.zeros(256))  # no state yet
+    assert ei.value.code == M.MFD_E_ORDER
+    p.close()

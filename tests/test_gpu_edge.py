@@ -135,3 +135,42 @@ def test_server_zero_step_request(M):
     assert state == 2 and rc == 0
     assert np.array_equal(out, st)
     srv.close()
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c["name"] in ("lcde-3l-blocked", "nse-trt",
+                                                                     "mesofd-lcde")],
+                         ids=lambda c: c["name"])
+def test_level_ptr_reports_current_storage(M, case):
+    """mfd_level_ptr names the buffers that hold the live levels after the
+    roles have rotated: a second solver loaded from those device addresses
+    (mfd_set_state with on_device = 1) holds the same levels."""
+    rng = np.random.default_rng(3)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    s = _new(M, case, "fp64")
+    s.set_state(cur)
+    three = case.get("kind") == "three_level"
+    if three:
+        s.set_state(prev, level=1)
+    s.step(7)
+    N = int(np.prod(case["n"]))
+    nf = 1 if case["eq"] != "nse" else 1 + len(case["n"])
+    p0 = [s.level_ptr(0, f) for f in range(nf)]
+    assert all(p0[f] - p0[0] == f * N * 8 for f in range(nf))
+    t = _new(M, case, "fp64")
+    meso = case.get("form") == "mesofd"
+    if not meso:  # (MesoFD moments re-initialise the populations; checked below)
+        t.set_state_device(p0[0], nf * N * 8)
+        assert np.array_equal(t.get_state(), s.get_state())
+    if three:
+        t.set_state_device(s.level_ptr(1, 0), nf * N * 8, level=1)
+        assert np.array_equal(t.get_state(level=1), s.get_state(level=1))
+    if meso:
+        q = 9
+        pp = [s.level_ptr(0, j, populations=True) for j in range(q)]
+        assert all(pp[j] - pp[0] == j * N * 8 for j in range(q))
+        t.set_state_device(pp[0], q * N * 8, populations=True)
+        assert np.array_equal(t.get_state(populations=True), s.get_state(populations=True))
+    with pytest.raises(M.MfdError):
+        s.level_ptr(0, nf)
+    t.close()
+    s.close()

@@ -1,0 +1,124 @@
+"""GPU: the theta scheme of Eq. (GCN) solved to a residual tolerance.
+
+Each case runs several time steps on the GPU and the same steps with the
+oracle's to-tolerance solve (orc_theta_solve: the same chunked stopping rule
+in binary64 with compensated sums):
+* binary64: every state bit-exact, and the sweeps the GPU reports equal the
+  oracle's (the decision could only differ where the residual ratio sits
+  within round-off of the tolerance, which the test detects and reports);
+* binary32 at 1e-6: relative L2 within 1e-5 of the oracle's binary64 solve.
+The device-decided path (2D windows) and the host-checked path (small, 1D and
+3D grids) are both covered, as are ragged tiles and a stop forced by the cap.
+"""
+import numpy as np
+import pytest
+
+from oracle import native as O
+from parity_util import make_solver, oracle_spec, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+K2 = [[0.3, 0.04], [0.04, 0.2]]
+
+CASES = [
+    dict(name="d2q9-fused", lattice="D2Q9", n=(203, 150), u=(0.1, -0.07), K=K2, lambda_bar=1),
+    dict(name="d2q5-fused", lattice="D2Q5", n=(130, 77), u=(0.05, 0.02), K=[[0.2, 0.0], [0.0, 0.2]]),
+    dict(name="d2q9-small", lattice="D2Q9", n=(40, 21), u=(0.1, -0.07), K=K2, lambda_bar=1),
+    dict(name="d1q3", lattice="D1Q3", n=(300,), u=(0.1,), K=[[0.3]]),
+    dict(name="d3q19", lattice="D3Q19", n=(14, 11, 9), u=(0.05, 0.02, -0.03),
+         K=[[0.1, 0, 0], [0, 0.1, 0], [0, 0, 0.1]]),
+]
+
+
+def _case(c, cap):
+    a = (1.0, 0.0, 0.0)  # SRT tau = 1 (a_-1 = 1)
+    return dict(c, eq="lcde", a=a, kind="theta", theta=0.5, theta_iters=cap, dx=1.0, dt=1.0)
+
+
+def _oracle_run(case, phi, steps, tol, chunk, cap):
+    spec = oracle_spec(case)
+    sweeps = []
+    for _ in range(steps):
+        phi, k, _ = O.theta_solve(spec, phi, tol, chunk, cap)
+        sweeps.append(k)
+    return phi, sweeps
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c["name"])
+@pytest.mark.parametrize("tol,chunk", [(1e-12, 8), (1e-9, 3)])
+def test_theta_tolerance_fp64_matches_oracle(M, case, tol, chunk):
+    cap, steps = 96, 4
+    c = _case(case, cap)
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal(int(np.prod(c["n"])))
+    want, sweeps = _oracle_run(c, phi, steps, tol, chunk, cap)
+    s = make_solver(M, c, "fp64")
+    s.set_theta_tolerance(tol, chunk)
+    s.set_state(phi)
+    s.step(1)
+    s.step(steps - 1)
+    got = s.get_state()
+    st = s.theta_stats()
+    s.close()
+    assert st["steps"] == steps and st["unconverged"] == 0
+    assert st["total_sweeps"] == sum(sweeps), (st, sweeps)
+    assert st["max_sweeps"] == max(sweeps)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]], ids=["fused", "host-checked"])
+def test_theta_tolerance_fp32_within_1e5(M, case):
+    cap, steps = 96, 6
+    c = _case(case, cap)
+    rng = np.random.default_rng(6)
+    phi = rng.standard_normal(int(np.prod(c["n"])))
+    phi32 = phi.astype(np.float32)
+    want, _ = _oracle_run(c, phi32.astype(np.float64), steps, 1e-12, 8, cap)
+    s = make_solver(M, c, "fp32")
+    s.set_theta_tolerance(1e-6, 8)
+    s.set_state(phi32)
+    s.step(steps)
+    got = s.get_state().astype(np.float64)
+    st = s.theta_stats(reset=True)
+    assert s.theta_stats()["total_sweeps"] == 0
+    s.close()
+    assert st["unconverged"] == 0 and st["steps"] == steps
+    assert rel_l2(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3]], ids=["fused", "host-checked"])
+def test_theta_cap_stops_and_equals_fixed_sweeps(M, case):
+    """An unreachable tolerance stops every step at the cap (whole chunks),
+    equal to the fixed-count theta step of that many sweeps, and is counted
+    as not converged."""
+    c = _case(case, 10)
+    rng = np.random.default_rng(7)
+    phi = rng.standard_normal(int(np.prod(c["n"])))
+    s = make_solver(M, c, "fp64")
+    s.set_theta_tolerance(1e-300, 4)
+    s.set_state(phi)
+    s.step(3)
+    got = s.get_state()
+    st = s.theta_stats()
+    s.close()
+    assert st == dict(total_sweeps=36, steps=3, max_sweeps=12, unconverged=3)
+    want = phi
+    spec = oracle_spec(dict(c, theta_iters=12))
+    for _ in range(3):
+        want = O.theta_step(spec, want)
+    assert np.array_equal(got, want)
+
+
+def test_theta_tolerance_argument_checks(M):
+    c = _case(CASES[2], 8)
+    s = make_solver(M, c, "fp64")
+    with pytest.raises(M.MfdError):
+        s.set_theta_tolerance(-1.0)
+    with pytest.raises(M.MfdError):
+        s.set_theta_tolerance(1e-6, 17)
+    s.close()
+    c2 = dict(CASES[2], eq="lcde", a=(1.0, 0.0, 0.0), dx=1.0, dt=1.0)
+    e = make_solver(M, c2, "fp64")
+    with pytest.raises(M.MfdError):
+        e.set_theta_tolerance(1e-6)
+    e.close()

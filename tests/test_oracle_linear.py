@@ -160,6 +160,56 @@ def test_theta_closed_form(lat, theta):
     assert np.abs(fo - lam * fc).max() / np.abs(fc).max() < 1e-12
 
 
+@pytest.mark.parametrize("lat", ["D2Q9", "D2Q5", "D1Q3"])
+@pytest.mark.parametrize("tol,chunk", [(1e-6, 1), (1e-10, 3), (1e-12, 8)])
+def test_theta_solve_to_tolerance(lat, tol, chunk):
+    """The theta step solved to a residual tolerance (Eq. (GCN) with the
+    stopping rule den ||x_k - x_(k-1)|| <= tol ||rhs||, checked every `chunk`
+    sweeps):
+    * the result lies within tol ||rhs|| of the exact theta solution, the
+      closed form lambda = (A0 + th z)/(1 - (1-th) z) of Eq. (Tcond1-1) mode
+      by mode (|1 - (1-th) z| >= 1 on a stable scheme, so the error is at most
+      the residual of x_(k-1), which the rule bounds);
+    * the sweep count is the first chunk boundary where the rule holds,
+      recomputed here with numpy norms from fixed-count solves;
+    * with the rule unreachable the solve stops at the cap and equals the
+      fixed-count step."""
+    case = I.random_linear_case(O.DIMS[lat], seed=9)
+    a = SCHEMES["two_level_s"][0]
+    theta = 0.5
+    spec = lin_spec(lat, case, a)
+    spec["u"] = tuple(0.3 * np.array(case["u"]))
+    spec.update(theta=theta, theta_iters=1)
+    cur = case["phi0"]
+    out, sweeps, conv = O.theta_solve(spec, cur, tol, chunk, 400)
+    assert conv and sweeps % chunk == 0
+    E, w, pairs = O.lattice_info(lat)
+    _, _, tab = O.tables(spec)
+    n = spec["n"]
+    A1, _ = S.fourier_symbols(E, pairs, tab["ubp"], tab["ubm"], n, a, (0, 0, 0))
+    z = A1 - 1.0
+    shape = tuple(reversed(n))
+    fc = np.fft.fftn(cur.reshape(shape))
+    exact = np.real(np.fft.ifftn((1 + theta * z) / (1 - (1 - theta) * z) * fc)).ravel()
+    rhs = np.real(np.fft.ifftn((1 + theta * z) * fc)).ravel()
+    err = np.linalg.norm(out - exact)
+    assert err <= tol * np.linalg.norm(rhs) * 1.001 + 1e-13 * np.linalg.norm(exact)
+    # the stopping point, from fixed-count solves and numpy norms
+    den = 1.0 + (1 - theta) * 2 * float(np.sum(tab["ubp"]) * (a[0] + a[2]))
+
+    def ratio(k):
+        xk = O.theta_step(dict(spec, theta_iters=k), cur)
+        xk1 = O.theta_step(dict(spec, theta_iters=k - 1), cur)
+        return den * np.linalg.norm(xk - xk1) / np.linalg.norm(rhs)
+
+    assert ratio(sweeps) <= tol * (1 + 1e-9)
+    if sweeps > chunk:
+        assert ratio(sweeps - chunk) > tol * (1 - 1e-9)
+    fixed = O.theta_step(dict(spec, theta_iters=2 * chunk), cur)
+    capped, k, c = O.theta_solve(spec, cur, 1e-300, chunk, 2 * chunk)
+    assert k == 2 * chunk and not c and np.array_equal(capped, fixed)
+
+
 def test_theta_one_is_explicit():
     case = I.random_linear_case(2, seed=4)
     spec = lin_spec("D2Q9", case, SCHEMES["two_level_s"][0])
