@@ -217,6 +217,25 @@ int mfd_get_state(mfd_solver *s, int level, void *dst, int64_t bytes, int on_dev
 /* Enqueue nsteps >= 0 time steps; asynchronous with respect to the host. */
 int mfd_step(mfd_solver *s, int64_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mfd_step on
+ * caller-owned levels, allocating nothing.  `level0` (phi^n) and, for
+ * three-level schemes only, `level1` (phi^(n-1)) are device buffers of the
+ * solver's precision and layout (mfd_state_size moment elements each), read
+ * and overwritten in place with phi^(n+nsteps) and phi^(n+nsteps-1)
+ * (level1 must be NULL for two-level schemes).  The solver needs its
+ * lattice, equation and scheme (explicit MMFD, no source term) but no state:
+ * its own buffers and level roles are not touched.  The work levels live in
+ * a fixed 64 MiB device array per GPU, held until the process ends, so a
+ * level may hold at most 32 MiB (e.g. 2048^2 binary64 scalar fields or
+ * 1448^2 binary32 NSE fields).  Every call on a GPU shares that array:
+ * calls that overlap on one GPU (other streams or host threads) race and must
+ * be serialised by the caller.  Asynchronous on the solver's stream, like
+ * mfd_step.  MFD_E_ORDER before the scheme is set, MFD_E_UNSUPPORTED for
+ * MesoFD, theta or source-term solvers, MFD_E_ARG for missing / extra level
+ * pointers, nsteps < 0 or a state larger than the limit. */
+int mfd_step_noalloc(mfd_solver *s, void *level0, void *level1, int64_t nsteps);
+
 /* Source term of the linear CDE (explicit two- or three-level scheme; MMFD
  * form on every lattice, MesoFD form on 1D / 2D lattices): the b terms of
  * Eq. (2-1) / (3layerMMFD-1) with the source distribution F_j of

@@ -22,6 +22,37 @@ using namespace mfd;
 
 namespace mfd {
 
+// Work levels of mfd_step_noalloc: a fixed device array per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a host-side stand-in); it uses the device address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// device address of `scratch` on the current device (looked up once per
+// device, with that device current)
+hipError_t noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 namespace {
 std::mutex g_alloc_mu;
 std::unordered_map<void *, size_t> g_alloc;
@@ -1023,6 +1054,92 @@ extern "C" int mfd_theta_stats(mfd_solver *h, int64_t *total_sweeps, int64_t *st
     }
   }
   return MFD_OK;
+}
+
+extern "C" int mfd_step_noalloc(mfd_solver *h, void *level0, void *level1, int64_t nsteps) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!s->configured) return s->fail(MFD_E_ORDER, "configure the solver first");
+  if (s->grid.form != MFD_MMFD || s->cfg.kind == MFD_THETA || s->src_on)
+    return s->fail(MFD_E_UNSUPPORTED,
+                   "mfd_step_noalloc takes explicit MMFD schemes without a source term");
+  const bool three = s->consts.three != 0;
+  if (!level0 || (three && !level1) || (!three && level1))
+    return s->fail(MFD_E_ARG, "level0 (and for three-level schemes only, level1) must be given");
+  if (nsteps < 0) return s->fail(MFD_E_ARG, "nsteps < 0");
+  if (nsteps == 0) return MFD_OK;
+  const int64_t me = s->mom_elems() * s->elem();
+  if (2 * me > (int64_t)kNoAllocScratchBytes)
+    return s->fail(MFD_E_ARG, "state of %lld bytes per level exceeds the %lld-byte limit "
+                              "(two work levels in %lld bytes of scratch)",
+                   (long long)me, (long long)(kNoAllocScratchBytes / 2),
+                   (long long)kNoAllocScratchBytes);
+  void *scr = nullptr;
+  int rc = s->hip(noalloc_scratch(&scr), "hipGetSymbolAddress (scratch)");
+  if (rc) return rc;
+  char *w0 = (char *)scr, *w1 = (char *)scr + me;
+  // run the ordinary step loop on the caller's levels and the scratch
+  void *saved_buf[Solver::kNumBuf];
+  for (int i = 0; i < Solver::kNumBuf; ++i) saved_buf[i] = s->buf[i];
+  const int sic = s->ic, sip = s->ip, sio = s->io, spc = s->pc, spn = s->pn, six = s->ix;
+  const int64_t ssteps = s->steps_done;
+  const int sgap = s->prev_gap;
+  const bool sset = s->state_set;
+  for (int i = 0; i < Solver::kNumBuf; ++i) s->buf[i] = nullptr;
+  s->buf[0] = level0;
+  if (three) {
+    s->buf[1] = level1;
+    s->buf[2] = w0;
+    s->buf[8] = w1;
+  } else {
+    s->buf[1] = w0;
+    s->buf[2] = w1;
+  }
+  s->ic = 0;
+  s->ip = 1;
+  s->io = 2;
+  s->ix = 8;
+  s->steps_done = 0;
+  s->prev_gap = 1;
+  s->state_set = true;
+  rc = s->step(nsteps);
+  // the final levels back into the caller's buffers (plain device copies)
+  const int ic = s->ic, ip = s->ip;
+  void *B[Solver::kNumBuf];
+  for (int i = 0; i < Solver::kNumBuf; ++i) B[i] = s->buf[i];
+  auto cp = [&](int dst, int src) {
+    if (rc == MFD_OK)
+      rc = s->hip(hipMemcpyAsync(B[dst], B[src], (size_t)me, hipMemcpyDeviceToDevice, s->stream),
+                  "hipMemcpyAsync (noalloc level)");
+  };
+  if (rc == MFD_OK) {
+    if (!three) {
+      if (ic != 0) cp(0, ic);
+    } else if (ic == 1 && ip == 0) {
+      const int free_buf = 2;  // both work levels are free here
+      cp(free_buf, 1);
+      cp(1, 0);
+      cp(0, free_buf);
+    } else if (ic == 1) {
+      cp(0, 1);
+      cp(1, ip);
+    } else {
+      if (ip != 1) cp(1, ip);
+      if (ic != 0) cp(0, ic);
+    }
+  }
+  for (int i = 0; i < Solver::kNumBuf; ++i) s->buf[i] = saved_buf[i];
+  s->ic = sic;
+  s->ip = sip;
+  s->io = sio;
+  s->pc = spc;
+  s->pn = spn;
+  s->ix = six;
+  s->steps_done = ssteps;
+  s->prev_gap = sgap;
+  s->state_set = sset;
+  return rc;
 }
 
 extern "C" int mfd_set_boundary(mfd_solver *h, const double *G, int64_t count, int on_device,

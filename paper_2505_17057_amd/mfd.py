@@ -117,6 +117,7 @@ _SIGS = {
     "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
     "mfd_theta_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.c_int], C.c_int),
+    "mfd_step_noalloc": ([_H, _VP, _VP, C.c_int64], C.c_int),
     "mfd_set_boundary": ([_H, _PD, C.c_int64, C.c_int, C.c_double], C.c_int),
     "mfd_wave_start": ([_H, _PD, C.c_int64, C.c_int], C.c_int),
     "mfd_memory_stats": ([C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int], C.c_int),
@@ -371,6 +372,12 @@ class Solver:
         self.check(lib.mfd_theta_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d),
                                        1 if reset else 0), "mfd_theta_stats")
         return dict(total_sweeps=a.value, steps=b.value, max_sweeps=c.value, unconverged=d.value)
+
+    def step_noalloc(self, level0_ptr, level1_ptr=None, nsteps=1):
+        """mfd_step_noalloc on caller-owned device levels (raw addresses)."""
+        return self.check(lib.mfd_step_noalloc(self.h, C.c_void_p(int(level0_ptr)),
+                                               C.c_void_p(int(level1_ptr)) if level1_ptr else None,
+                                               int(nsteps)), "mfd_step_noalloc")
 
     def set_boundary(self, G, lam=0.0):
         """Dirichlet values G(x) exp(lam t) of the edge nodes (mfd_set_boundary)."""
