@@ -1,21 +1,27 @@
 """Benchmark of the MesoFD / MMFD time step on one MI355X.
 
-Headline workload (the one the metric is quoted on): 2D anisotropic linear
-CDE, D2Q9, periodic 2048 x 2048, K = [[0.02,0.005],[0.005,0.01]],
-u = (0.05, 0.03), dt = 2^-18, SRT coefficients, Gaussian hill + seeded noise,
-10 000 time steps per solve.  One benchmark "step" is one full solve
-(10 000 time steps of the MMFD form in FP32, then an FP64 mass reduction).
+Headline workload (the one the metric is quoted on): the largest single-GPU
+configuration, the 2D incompressible NSE, three-level TRT MMFD, D2Q9,
+periodic 4096 x 4096 Taylor-Green vortex (Re = 100) with seeded velocity noise,
+FP32 state and arithmetic with FP64 reductions, 20 000 time steps per solve.
+One benchmark "step" is one full solve: 20 000 time steps, then the FP64
+mass / momentum / residual reduction.
 
 Beside it the same JSON line reports
-* the other forms / precisions of that workload and an HBM-resident 8192^2 point,
-* the FP32 error of the full run against the FP64 run,
-* the 1D D1Q3 workload (1024 nodes, 1000 steps, LDS-resident),
-* the NSE three-level MMFD workloads (4096^2 D2Q9, 512^3 D3Q19),
+* the FP32 error of the full 20 000-step run against the FP64 run,
+* the 2D linear CDE workload (2048^2, 10 000 steps) in every form and
+  precision, with its own roofline figures, and an HBM-resident 8192^2 point,
+* the theta scheme solved to a residual tolerance,
+* the 1D D1Q3 workload (1024 nodes, 1000 steps, dt from the library's
+  stability bound),
+* the 3D D3Q19 NSE at 512^3 (1000 steps, FP32 error against FP64),
+* the source-term workload (Example 1) and the wave equation with Dirichlet
+  edges (Example 3 scaled up),
 * the batched workload: 256 Burgers grids, one graph launch in FP32, against
   plain per-instance FP64 stepping,
-* the serving workload: Poisson arrivals of mixed Burgers / NSE solves,
-  p50 / p99 latency and throughput,
-* the oracle on the host cores (CPU baseline).
+* the serving workload: Poisson arrivals of mixed Burgers / NSE solves under
+  a 200 GB and a 2 GB budget, p50 / p99 latency and throughput,
+* the oracle on the host cores, all threads and one (CPU baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu]
 Prints one JSON line.
@@ -36,7 +42,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TIME_STEPS = 10000
+# FP32 vector peak, published: 256 CUs x 128 FP32 lanes x 2 flops (fused
+# multiply-add) x 2.4 GHz.  (The headline kernel's counters show more than one
+# wavefront VALU instruction per CU per clock, so half this figure is no
+# ceiling for it.)
+VALU_FP32_TFLOPS = 157.3
+HEAD_STEPS = 20000  # NSE TGV time steps per solve (headline)
+HEAD_SIDE = 4096
+NSE_D2Q9_FLOPS_PER_LUP = 230.0  # three-level TRT MMFD, pair form
+LCDE_D2Q9_FLOPS_PER_LUP = 30.0  # two-level linear pair form
+TIME_STEPS = 10000  # linear CDE workload
 N_SIDE = 2048
 D0 = 1.0 / 3.0
 
@@ -48,11 +63,14 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    p.add_argument("--sections", default="variants,theta,big,c1,nse,source,burgers,batched,serving",
+    p.add_argument("--no-headline", action="store_true",
+                   help="skip the headline (profiling of the other sections; value is then null)")
+    p.add_argument("--sections",
+                   default="c3err,c2,variants,theta,big,c1,nse3d,source,wave,burgers,batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
-    p.add_argument("--serve-requests", type=int, default=300)
+    p.add_argument("--serve-requests", type=int, default=2200)
     p.add_argument("--plan", default="",
                    help="tb,rows,cols: run the headline with this launch plan instead of autotuning "
                         "(used to profile counters on the plan an earlier run chose)")
@@ -100,47 +118,74 @@ def launch_durations(torch, s, tb, n=1000):
     return a.elapsed_time(b) / n
 
 
-def stored_traffic(kernel_src, tb, h, w):
-    """(HBM bytes per launch, profiled plan) from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source with the
-    same steps per launch and window width (the window height changes only
-    halo re-reads, which the profiled plan states); else (None, None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_mmfd_lcde_d2q9_2048_fp32.json")
+def stored_counters(json_name, kernel_src, tb, w):
+    """The committed rocprofv3 counter record of a step kernel
+    (profiles/<json_name>), if it was taken on the current kernel source with
+    the same steps per launch and window width (the window height changes
+    only halo re-reads, which the record states); else None.  Returns a dict
+    with hbm_bytes_per_launch, valu_insts_per_launch (or None) and the plan."""
+    path = os.path.join(ROOT, "profiles", json_name)
     if not os.path.exists(path):
-        return None, None
+        return None
     info = json.load(open(path))
     sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     if info.get("kernel_source_sha256") != sha:
-        return None, None
+        return None
     for r in [info] + info.get("alternates", []):
         if r.get("time_steps_per_launch") == tb and r.get("window_cols") == w:
-            plan = [r.get("time_steps_per_launch"), r.get("window_rows"), r.get("window_cols")]
-            return r.get("hbm_bytes_per_launch"), plan
-    return None, None
+            return dict(hbm_bytes_per_launch=r.get("hbm_bytes_per_launch"),
+                        valu_insts_per_launch=r.get("valu_insts_per_launch"),
+                        plan=[r.get("time_steps_per_launch"), r.get("window_rows"),
+                              r.get("window_cols")])
+    return None
 
 
-def cpu_baseline(cfg, budget_s=15.0):
-    """The FP64 oracle (MMFD form) on the host cores, bounded sample."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(c3, budget_s=12.0, one_core_s=8.0):
+    """The FP64 oracle (MMFD form) on the host cores, bounded samples of the
+    headline workload: all threads, then one thread."""
     from oracle import native as O
     from oracle import scheme as S
 
-    spec = dict(lattice="D2Q9", n=cfg["n"], dx=cfg["dx"], dt=cfg["dt"], u=cfg["u"], K=cfg["K"],
-                lambda_bar=1, a=S.preset_srt()[0])
+    nu, dx, dt = c3["nu"], c3["dx"], c3["dt"]
+    s = S.trt_s_for(nu, dx, dt, D0)
+    a, ah = S.preset_trt(s)
+    spec = dict(lattice="D2Q9", eq="nse", n=c3["n"], dx=dx, dt=dt, rho0=c3["rho0"],
+                a=[float(v) for v in a], ah=[float(v) for v in ah], levels=3)
+    N = int(np.prod(c3["n"]))
+
+    def run(threads, budget):
+        spec["nthreads"] = threads
+        cur = c3["state0"].copy()
+        prev = cur
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            cur, prev = O.mmfd_step(spec, cur, prev), cur
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget or steps >= 200:
+                break
+        return N * steps / el / 1e9, steps, el
+
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    spec["nthreads"] = threads
-    phi = cfg["phi0"].copy()
-    N = phi.size
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        phi = O.mmfd_step(spec, phi)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or steps >= 2000:
-            break
-    return dict(value=round(N * steps / el / 1e9, 4), unit="GLUPS", cores=threads, kind="oracle",
-                sample="%d MMFD FP64 time steps of the 2048^2 D2Q9 linear-CDE workload (%.1f s)"
-                       % (steps, el))
+    g, st, el = run(threads, budget_s)
+    g1, st1, el1 = run(1, one_core_s)
+    return dict(value=round(g, 4), unit="GLUPS", cores=threads, kind="oracle",
+                cpu_model=cpu_model(), logical_cpus=os.cpu_count(),
+                sample="%d three-level TRT NSE MMFD FP64 time steps of the 4096^2 D2Q9 TGV workload "
+                       "(%.1f s, %d threads)" % (st, el, threads),
+                one_core=dict(value=round(g1, 4), unit="GLUPS", cores=1,
+                              sample="%d time steps (%.1f s)" % (st1, el1)))
 
 
 def two_level_a(M, nu, dx, dt):
@@ -205,28 +250,33 @@ def bench_variants(M, torch, cfg, stream, N):
     return out, err, meso_vs_mmfd
 
 
-def bench_theta(M, torch, cfg, stream, N, theta=0.5, sweeps=4, steps=1000):
-    """theta scheme (linear CDE) on the headline grid: right-hand side plus
-    `sweeps` Jacobi sweeps per time step, FP32, and its error against the
-    FP64 run of the same steps."""
+def bench_theta(M, torch, cfg, stream, N, theta=0.5, steps=1000, chunk=8, cap=64):
+    """theta scheme (linear CDE, SRT coefficients) on the 2048^2 workload,
+    each step solved to a residual tolerance (binary64 1e-12, binary32 1e-6;
+    Jacobi sweeps checked every `chunk`, at most `cap`): GLUPS at convergence,
+    sweeps per step, the FP32 error against the FP64 run of the same steps."""
     out = {}
     finals = {}
-    for prec in ("fp32", "fp64"):
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-12)):
         s = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
         s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
-        s.set_scheme("theta", M.mfd_preset("srt")[0], theta=theta, theta_iters=sweeps, dt=cfg["dt"])
+        s.set_scheme("theta", M.mfd_preset("srt")[0], theta=theta, theta_iters=cap, dt=cfg["dt"])
+        s.set_theta_tolerance(tol, chunk)
         s.set_stream(stream.cuda_stream)
         s.set_state(cfg["phi0"].astype(s.dtype))
         s.step(10)
         s.set_state(cfg["phi0"].astype(s.dtype))
+        s.theta_stats(reset=True)
         ms = timed(torch, lambda: s.step(steps))
+        st = s.theta_stats()
         finals[prec] = s.get_state().astype(np.float64)
         s.close()
         g = N * steps / (ms * 1e-3) / 1e9
-        bpl = (2 + 3 * sweeps) * (4 if prec == "fp32" else 8)  # rhs: read + write; sweep: 2 reads + write
-        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1), frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4),
-                         bytes_per_lup=bpl)
-    out.update(theta=theta, jacobi_sweeps=sweeps, steps=steps,
+        sw = st["total_sweeps"] / max(st["steps"], 1)
+        out[prec] = dict(glups=round(g, 2), tolerance=tol, sweeps_per_step=round(sw, 2),
+                         max_sweeps=st["max_sweeps"], steps_stopped_by_cap=st["unconverged"],
+                         sweep_glups=round(g * sw, 2))
+    out.update(theta=theta, chunk_sweeps=chunk, sweep_cap=cap, steps=steps,
                fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
                                          / np.linalg.norm(finals["fp64"])))
     return out
@@ -244,7 +294,10 @@ def bench_big(M, torch, I, stream):
 
 def bench_c1(M, torch, I, stream):
     c1 = I.c1_linear_1d()
-    res = {}
+    # dt = half the library's Eq. (LMMFD-2-3) bound (the recipe's 25 * 2^-20)
+    bound, exact = M.mfd_max_stable_dt("D1Q3", c1["dx"], c1["u"], c1["D"], n=c1["n"])
+    c1["dt"] = 0.5 * bound
+    res = dict(dt=c1["dt"], dt_bound_sufficient=bound, dt_bound_exact_modes=exact)
     for form in ("mmfd", "mesofd"):
         s = M.Solver("D1Q3", c1["n"], c1["dx"], "fp64", form)
         s.set_equation("lcde", u=c1["u"], K=c1["K"])
@@ -320,41 +373,115 @@ def _rel_l2_dev(torch, a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def bench_nse(M, torch, I, stream):
-    """Three-level TRT NSE: FP32 timing, and the FP32 error against the FP64
-    run of the same steps from the same (binary32-rounded) start."""
-    res = {}
-    for lat, c, warm, steps, bpl, key in (
-            ("D2Q9", I.tgv_2d(n=4096), 20, 200, 36, "d2q9_4096_three_level_fp32"),
-            ("D3Q19", I.tgv_3d(n=512, dtype=np.float32), 2, 20, 48, "d3q19_512_three_level_fp32")):
-        x0 = torch.from_numpy(np.ascontiguousarray(c["state0"], dtype=np.float32)).to("cuda")
-        del c["state0"]
-        nodes = int(np.prod(c["n"]))
-        s = _nse_solver(M, lat, c, "fp32", stream)
-        s.set_state(x0)
-        s.autotune()
-        plan = s.launch_plan()
-        s.step(warm)
-        ms = timed(torch, lambda: s.step(steps))
-        g = nodes * steps / (ms * 1e-3) / 1e9
-        y32 = torch.empty_like(x0)
-        s.get_state(out=y32)
-        s.close()
-        s64 = _nse_solver(M, lat, c, "fp64", stream)
-        x64 = x0.double()
-        s64.set_state(x64)
-        s64.step(warm + steps)
-        y64 = torch.empty_like(x64)
-        s64.get_state(out=y64)
-        s64.close()
-        torch.cuda.synchronize()
-        res[key] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
-                        frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl,
-                        steps=warm + steps, plan=list(plan),
-                        fp32_rel_l2_vs_fp64=_rel_l2_dev(torch, y32, y64))
-        del x0, x64, y32, y64
-        torch.cuda.empty_cache()
+def bench_nse3d(M, torch, I, stream, steps=1000):
+    """Three-level TRT NSE on D3Q19 at 512^3, 1000 time steps in FP32 (after
+    the autotuner), and the FP32 error against the FP64 run of the same steps
+    from the same (binary32-rounded) start."""
+    c = I.tgv_3d(n=512, dtype=np.float32)
+    x0 = torch.from_numpy(np.ascontiguousarray(c["state0"], dtype=np.float32)).to("cuda")
+    del c["state0"]
+    nodes = int(np.prod(c["n"]))
+    s = _nse_solver(M, "D3Q19", c, "fp32", stream)
+    s.set_state(x0)
+    s.autotune()
+    plan = s.launch_plan()
+    s.step(2)
+    s.set_state(x0)
+    ms = timed(torch, lambda: s.step(steps))
+    g = nodes * steps / (ms * 1e-3) / 1e9
+    y32 = torch.empty_like(x0)
+    s.get_state(out=y32)
+    s.close()
+    s64 = _nse_solver(M, "D3Q19", c, "fp64", stream)
+    x64 = x0.double()
+    del x0
+    s64.set_state(x64)
+    ms64 = timed(torch, lambda: s64.step(steps))
+    y64 = torch.empty_like(x64)
+    s64.get_state(out=y64)
+    s64.close()
+    torch.cuda.synchronize()
+    bpl = 48
+    res = dict(glups=round(g, 2), fp64_glups=round(nodes * steps / (ms64 * 1e-3) / 1e9, 2),
+               alg_gbs=round(g * bpl, 1), frac_hbm_algorithmic=round(g * bpl / HBM_PEAK_GBS, 4),
+               bytes_per_lup=bpl, steps=steps, plan=list(plan),
+               fp32_rel_l2_vs_fp64=_rel_l2_dev(torch, y32, y64))
+    del x64, y32, y64
+    torch.cuda.empty_cache()
     return res
+
+
+def bench_c3_error(M, torch, c3, x0, stream, steps=HEAD_STEPS):
+    """FP32 error of the headline workload after its full run: the FP32 solve
+    of `steps` time steps against the FP64 solve from the same
+    (binary32-rounded) start, relative L2 over all fields."""
+    out = {}
+    ys = {}
+    for prec in ("fp32", "fp64"):
+        s = _nse_solver(M, "D2Q9", c3, prec, stream)
+        x = x0 if prec == "fp32" else x0.double()
+        s.set_state(x)
+        ms = timed(torch, lambda: s.step(steps))
+        y = torch.empty_like(x)
+        s.get_state(out=y)
+        sums = s.reduce()
+        s.close()
+        ys[prec] = y
+        out[prec + "_glups"] = round(int(np.prod(c3["n"])) * steps / (ms * 1e-3) / 1e9, 2)
+        out[prec + "_mass_momentum"] = [float(v) for v in sums[0][:3]]
+    out["fp32_rel_l2_vs_fp64"] = _rel_l2_dev(torch, ys["fp32"], ys["fp64"])
+    out["steps"] = steps
+    del ys
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_wave(M, torch, stream, nx=4095):
+    """The wave equation of Example 3 scaled up: phi = exp(x + y + t) on
+    [0,1]^2 with (nx + 1)^2 nodes, dt = dx / 2 (N_t = 2 N_x), Dirichlet edges
+    from the exact solution, the special first step, D2Q9, beta = 3/4,
+    gamma = 1/2 (Case 3), T = 1.  FP32 and FP64: GLUPS of the three-level
+    steps (64-column blocked windows), the GRE against the exact solution and
+    the FP32 error against FP64."""
+    import math
+    n = (nx + 1, nx + 1)
+    dx = 1.0 / nx
+    dt = dx / 2.0
+    steps = 2 * nx
+    x = np.arange(nx + 1) * dx
+    G = np.exp(x[None, :] + x[:, None]).ravel()
+    gamma, beta = 0.5, 0.75
+    a, ah = (gamma, 2 * (1 - gamma), gamma), (0.0, -1.0, 0.0)
+    out, fin = {}, {}
+    N = n[0] * n[1]
+    for prec in ("fp32", "fp64"):
+        s = M.Solver("D2Q9", n, dx, prec, "mmfd", boundary="dirichlet")
+        s.set_equation("wave", beta=beta)
+        s.set_scheme("three_level", a, ah, dt=dt)
+        s.set_stream(stream.cuda_stream)
+        s.set_boundary(G, 1.0)
+
+        def start():
+            s.set_state(G.astype(s.dtype))
+            s.wave_start(G)
+        start()
+        s.autotune()
+        start()
+        ms = timed(torch, lambda: s.step(steps - 1))
+        plan = s.launch_plan()
+        fin[prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = N * (steps - 1) / (ms * 1e-3) / 1e9
+        bpl = 3 * (4 if prec == "fp32" else 8)
+        ex = (G * math.e).reshape(n)[1:-1, 1:-1]
+        gre = float(np.abs(fin[prec].reshape(n)[1:-1, 1:-1] - ex).sum() / np.abs(ex).sum())
+        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                         frac_hbm_algorithmic=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl,
+                         plan=list(plan), gre_vs_exact=gre)
+    out.update(nodes=N, steps=steps, scheme="a = (1/2, 1, 1/2), ah = (0, -1, 0), beta = 3/4",
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(fin["fp32"] - fin["fp64"])
+                                         / np.linalg.norm(fin["fp64"])))
+    return out
 
 
 def bench_burgers_single(M, torch, I, stream):
@@ -437,12 +564,17 @@ def bench_batched(M, torch, I, stream):
                                     final_over_initial_norm=decay[worst]))
 
 
-def bench_serving(M, I, n_total, rate=200.0, warm=50, quantum=50):
+def serving_requests(M, I, n_total, rate=200.0, warm=200):
+    """The serving trace's requests with their initial states (built once,
+    shared by the runs under different budgets)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     trace = I.serving_trace(count=n_total - warm, warmup=warm, rate=rate)
     reqs = []
     t0 = time.perf_counter()
-    for r in trace:
-        inst = I.serving_request_state(r)
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        states = list(ex.map(I.serving_request_state, trace))
+    for r, inst in zip(trace, states):
         dx, dt = inst["dx"], inst["dt"]
         if r["kind"] == "burgers":
             st = inst["phi0"].astype(np.float32)
@@ -451,12 +583,22 @@ def bench_serving(M, I, n_total, rate=200.0, warm=50, quantum=50):
             st = inst["state0"].astype(np.float32)
             a, ah = trt_coeffs(M, inst["nu"], dx, dt)
             kind, eq, rho0 = "three_level", "nse", inst["rho0"]
-        out = np.empty_like(st)
-        req = M.make_request("D2Q9", eq, inst["n"], dx, dt, a, r["steps"], st, ah=ah, kind=kind,
-                             precision="fp32", rho0=rho0, result_out=out, exclude=r["warmup"])
-        reqs.append((r, req, st, out))
-    gen_s = time.perf_counter() - t0
-    srv = M.Server(hbm_budget_bytes=200 * 10 ** 9, max_slots=1024, quantum_steps=quantum)
+        reqs.append(dict(r=r, st=st, a=a, ah=ah, kind=kind, eq=eq, rho0=rho0, n=inst["n"], dx=dx,
+                         dt=dt))
+    return reqs, time.perf_counter() - t0, trace
+
+
+def bench_serving(M, reqs_all, gen_s, n_warm, rate=200.0, quantum=50, budget=200 * 10 ** 9):
+    reqs = []
+    for q in reqs_all:
+        out = np.empty_like(q["st"])
+        req = M.make_request("D2Q9", q["eq"], q["n"], q["dx"], q["dt"], q["a"], q["r"]["steps"], q["st"],
+                             ah=q["ah"], kind=q["kind"], precision="fp32", rho0=q["rho0"],
+                             result_out=out, exclude=q["r"]["warmup"])
+        reqs.append((q["r"], req, q["st"], out))
+    srv = M.Server(hbm_budget_bytes=budget, max_slots=1024, quantum_steps=quantum)
+    M.memory_stats(reset_peak=True)
+    base, _ = M.memory_stats()
     tickets = []
 
     def submitter():
@@ -471,15 +613,119 @@ def bench_serving(M, I, n_total, rate=200.0, warm=50, quantum=50):
     th.start()
     th.join()
     srv.drain(600)
+    _, peak = M.memory_stats()
     stats = srv.stats()
     fails = sum(1 for t in tickets if srv.poll(t)[0] != 2)
     srv.close()
     lups = sum(r["side"] * r["side"] * r["steps"] for r, _, _, _ in reqs)
-    return dict(requests=len(reqs), warmup_excluded=warm, rate_per_s=rate, quantum_steps=quantum,
-                hbm_budget_bytes=200 * 10 ** 9, p50_s=round(stats["p50_s"], 4),
-                p99_s=round(stats["p99_s"], 4), completed_per_s=round(stats["req_per_s"], 2),
-                glups=round(stats["glups"], 2), failed=fails, offered_glup=round(lups / 1e9, 1),
-                input_generation_s=round(gen_s, 1), precision="fp32")
+    span = reqs[-1][0]["arrival"] if reqs else 0.0
+    return dict(requests=len(reqs), warmup_excluded=n_warm, rate_per_s=rate, quantum_steps=quantum,
+                hbm_budget_bytes=budget, peak_device_bytes=peak - base,
+                p50_s=round(stats["p50_s"], 4), p99_s=round(stats["p99_s"], 4),
+                completed_per_s=round(stats["req_per_s"], 2), glups=round(stats["glups"], 2),
+                offered_glups=round(lups / max(span, 1e-9) / 1e9, 1), failed=fails,
+                offered_glup=round(lups / 1e9, 1), input_generation_s=round(gen_s, 1),
+                precision="fp32")
+
+
+def bench_c2(M, torch, cfg, stream, N):
+    """The 2D linear CDE workload (2048^2, MMFD FP32, 10 000 steps) after the
+    autotuner, with its step kernel's figures: algorithmic flops against the
+    FP32 vector peak, and the committed HBM counters when they match."""
+    s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
+    s32.autotune()
+    tb, h, w = s32.launch_plan()
+    timed(torch, lambda: s32.step(TIME_STEPS))
+    ms = timed(torch, lambda: s32.step(TIME_STEPS))
+    g = N * TIME_STEPS / (ms * 1e-3) / 1e9
+    mean_ms = launch_durations(torch, s32, tb, n=max(1, 4000 // tb)) if tb > 1 else None
+    s32.close()
+    kname, ksrc = (("k_lane_tb", "kernels_lane_tb.hip") if tb > 1 and w == 128 else
+                   ("k_mmfd_tb", "kernels_tb.hip") if tb > 1 else ("k_mmfd_plane", "kernels_mmfd.hip"))
+    rec = stored_counters("traffic_mmfd_lcde_d2q9_2048_fp32.json",
+                          os.path.join(ROOT, "paper_2505_17057_amd", "csrc", ksrc), tb, w)
+    tfl = g * 1e9 * LCDE_D2Q9_FLOPS_PER_LUP / 1e12
+    out = dict(glups=round(g, 2), plan=[tb, h, w], kernel=kname, ms_per_solve=round(ms, 3),
+               alg_tflops=round(tfl, 2), frac_valu_fp32=round(tfl / VALU_FP32_TFLOPS, 4),
+               alg_gbs_depth1=round(g * 8, 1))
+    if rec and mean_ms:
+        gbs = rec["hbm_bytes_per_launch"] / (mean_ms * 1e-3) / 1e9
+        out.update(launch_ms_mean=round(mean_ms, 5), measured_hbm_bytes_per_launch=rec["hbm_bytes_per_launch"],
+                   measured_hbm_gbs=round(gbs, 1), measured_hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                   counters_plan=rec["plan"])
+    return out
+
+
+def headline(M, torch, c3, x0, stream, args):
+    """The headline: K full solves of the 4096^2 NSE workload, timed, and the
+    roofline figures of its step kernel."""
+    log("headline: 4096^2 NSE three-level FP32")
+    NH = HEAD_SIDE * HEAD_SIDE
+    s32 = _nse_solver(M, "D2Q9", c3, "fp32", stream)
+    s32.set_state(x0)
+    if args.plan:
+        s32.set_plan(*[int(v) for v in args.plan.split(",")])
+    else:
+        s32.autotune()
+    tb, h, w = s32.launch_plan()
+    for _ in range(args.warmup):
+        timed(torch, lambda: s32.step(HEAD_STEPS))
+        s32.reduce()
+    # Timed region: K solves, each HEAD_STEPS time steps then the FP64 mass /
+    # momentum / residual reduction (each continues from the state the last
+    # left); events on the solver's stream split off the step kernels' share
+    # to give the mean launch duration.
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for e0, e1, e2 in ev:
+        e0.record()
+        s32.step(HEAD_STEPS)
+        e1.record()
+        s32.reduce()  # synchronous
+        e2.record()
+    torch.cuda.synchronize()
+    ms_per_step = sum(e0.elapsed_time(e2) for e0, _, e2 in ev) / args.steps
+    kernel_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
+    glups = NH * HEAD_STEPS / (ms_per_step * 1e-3) / 1e9
+    if HEAD_STEPS % tb == 0:
+        launches = HEAD_STEPS // tb
+        mean_ms = kernel_ms / launches
+        how = "HIP events on the solver's stream over the timed region: %d launches per solve" % launches
+    else:
+        mean_ms = launch_durations(torch, s32, tb)
+        how = "HIP events on the solver's stream around 1000 back-to-back launches"
+    # the step kernel of this plan: the blocked NSE window, or one step a launch
+    kname, ksrc = (("k_nse_tb", "kernels_nse_tb.hip") if tb > 1 else
+                   ("k_nse_plane_pp", "kernels_mmfd.hip"))
+    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc", ksrc)
+    rec = stored_counters("counters_nse_tb_d2q9_4096_fp32.json", kernel_src, tb, w)
+    lups_launch = NH * tb
+    alg_flops = NSE_D2Q9_FLOPS_PER_LUP * lups_launch
+    achieved = alg_flops / (mean_ms * 1e-3) / 1e12
+    traffic = rec["hbm_bytes_per_launch"] if rec else None
+    valu = rec["valu_insts_per_launch"] if rec else None
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=round(VALU_FP32_TFLOPS, 2),
+                    unit="TFLOP/s", frac=round(achieved / VALU_FP32_TFLOPS, 4), traffic=traffic,
+                    kernel=kname + " D2Q9 NSE three-level TRT FP32",
+                    kernel_source="paper_2505_17057_amd/csrc/" + ksrc,
+                    launch_ms_mean=round(mean_ms, 5), launch_timing=how,
+                    time_steps_per_launch=tb, window_rows=h, window_cols=w,
+                    algorithmic_flops_per_lup=NSE_D2Q9_FLOPS_PER_LUP,
+                    algorithmic_flops_per_launch=alg_flops,
+                    peak_derivation="published FP32 vector peak: 256 CUs x 128 lanes x 2 (fused "
+                                    "multiply-add) x 2.4 GHz",
+                    hbm_algorithmic_bytes_per_lup=36,
+                    hbm_algorithmic_gbs_depth1=round(glups * 36, 1),
+                    measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None),
+                    measured_hbm_frac=(round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                       if traffic else None),
+                    valu_insts_per_launch=valu,
+                    valu_insts_per_s=(round(valu / (mean_ms * 1e-3), -6) if valu else None),
+                    valu_lane_insts_per_lup=(round(valu * 64 / lups_launch, 1) if valu else None),
+                    counters_plan=(rec["plan"] if rec else None))
+    s32.close()
+    return glups, ms_per_step, tb, roofline
+
 
 
 def main():
@@ -496,61 +742,15 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    cfg = I.c2_hill_2d(n=N_SIDE)
-    N = N_SIDE * N_SIDE
 
     # ---------------------------------------------------------- headline
-    log("headline: 2048^2 MMFD FP32")
-    s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
-    if args.plan:
-        s32.set_plan(*[int(v) for v in args.plan.split(",")])
+    c3 = I.tgv_2d(n=HEAD_SIDE)
+    NH = HEAD_SIDE * HEAD_SIDE
+    x0 = torch.from_numpy(np.ascontiguousarray(c3["state0"], dtype=np.float32)).to("cuda")
+    if args.no_headline:
+        glups, ms_per_step, tb, roofline = None, None, None, None
     else:
-        s32.autotune()
-    tb, h, w = s32.launch_plan()
-    for _ in range(args.warmup):
-        timed(torch, lambda: s32.step(TIME_STEPS))
-        s32.reduce()
-    # Timed region: K solves, each TIME_STEPS time steps then the FP64 mass /
-    # residual reduction; events on the solver's stream split off the step
-    # kernels' share to give the mean launch duration.
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for e0, e1, e2 in ev:
-        e0.record()
-        s32.step(TIME_STEPS)
-        e1.record()
-        s32.reduce()  # synchronous
-        e2.record()
-    torch.cuda.synchronize()
-    ms_per_step = sum(e0.elapsed_time(e2) for e0, _, e2 in ev) / args.steps
-    kernel_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in ev) / args.steps
-    glups = N * TIME_STEPS / (ms_per_step * 1e-3) / 1e9
-    if TIME_STEPS % tb == 0:
-        launches = TIME_STEPS // tb
-        mean_ms = kernel_ms / launches
-        how = "HIP events over the timed region: %d launches per solve" % launches
-    else:
-        mean_ms = launch_durations(torch, s32, tb)
-        how = "HIP events around 1000 back-to-back launches"
-    alg_bytes = 8.0 * N * tb  # read phi^n, write phi^(n+1): 8 B per LUP in FP32
-    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
-    # the step kernel of this plan: the in-place lane-shared LCDE window (128
-    # columns), the general blocked window (64 columns), or one step a launch
-    kname, ksrc = (("k_lane_tb", "kernels_lane_tb.hip") if tb > 1 and w == 128 else
-                   ("k_mmfd_tb", "kernels_tb.hip") if tb > 1 else
-                   ("k_mmfd_plane", "kernels_mmfd.hip"))
-    kernel_src = os.path.join(ROOT, "paper_2505_17057_amd", "csrc", ksrc)
-    traffic, traffic_plan = stored_traffic(kernel_src, tb, h, w)
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=kname + " D2Q9 LCDE FP32",
-                    kernel_source="paper_2505_17057_amd/csrc/" + ksrc,
-                    launch_ms_mean=round(mean_ms, 5), launch_timing=how,
-                    time_steps_per_launch=tb, window_rows=h, window_cols=w,
-                    algorithmic_bytes_per_launch=alg_bytes,
-                    measured_hbm_gbs=(round(traffic / (mean_ms * 1e-3) / 1e9, 1) if traffic else None),
-                    traffic_plan=traffic_plan)
-    s32.close()
+        glups, ms_per_step, tb, roofline = headline(M, torch, c3, x0, stream, args)
 
     extra = {}
     if args.copy_calibration:
@@ -560,7 +760,18 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         extra["copy_calibration_bytes"] = x.numel() * 4  # read once and written once
+        del x, y
     sections = set() if args.quick else set(x for x in args.sections.split(",") if x)
+    if "c3err" in sections:
+        log("headline FP32 error after the full run")
+        extra["headline_error"] = bench_c3_error(M, torch, c3, x0, stream)
+    del x0
+    torch.cuda.empty_cache()
+    cfg = I.c2_hill_2d(n=N_SIDE)
+    N = N_SIDE * N_SIDE
+    if "c2" in sections:
+        log("2048^2 linear CDE")
+        extra["lcde_d2q9_2048_mmfd_fp32"] = bench_c2(M, torch, cfg, stream, N)
     if "variants" in sections:
         log("variants")
         extra["variants"], extra["fp32_rel_l2_vs_fp64_after_10000"], extra["mesofd_vs_mmfd_fp64_max_abs"] = \
@@ -574,12 +785,15 @@ def main():
     if "c1" in sections:
         log("1D")
         extra["c1_d1q3_1024"] = bench_c1(M, torch, I, stream)
-    if "nse" in sections:
-        log("NSE")
-        extra["nse"] = bench_nse(M, torch, I, stream)
+    if "nse3d" in sections:
+        log("NSE 3D")
+        extra["nse_d3q19_512_three_level"] = bench_nse3d(M, torch, I, stream)
     if "source" in sections:
         log("source")
         extra["source_example1_2048"] = bench_source(M, torch, I, stream)
+    if "wave" in sections:
+        log("wave")
+        extra["wave_example3_4096"] = bench_wave(M, torch, stream)
     if "burgers" in sections:
         log("burgers 2048^2")
         extra["burgers_2048_mmfd_fp32"] = bench_burgers_single(M, torch, I, stream)
@@ -587,28 +801,35 @@ def main():
         log("batched")
         extra["batched_256_burgers"] = bench_batched(M, torch, I, stream)
     if "serving" in sections:
-        log("serving")
-        extra["serving"] = bench_serving(M, I, args.serve_requests)
+        log("serving: requests")
+        warm = min(200, args.serve_requests // 10)
+        reqs, gen_s, _ = serving_requests(M, I, args.serve_requests, warm=warm)
+        log("serving, 200 GB budget")
+        extra["serving"] = bench_serving(M, reqs, gen_s, warm)
+        log("serving, 2 GB budget")
+        extra["serving_2gb_budget"] = bench_serving(M, reqs, gen_s, warm, budget=2 * 10 ** 9)
+        del reqs
 
-    cpu = None if args.no_cpu else cpu_baseline(cfg)
+    cpu = None if args.no_cpu else cpu_baseline(c3)
 
     line = {
         "metric": "GLUPS + achieved HBM GB/s (% of peak); batched p50/p99 solve latency",
-        "value": round(glups, 2),
+        "value": round(glups, 2) if glups is not None else None,
         "unit": "GLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(ms_per_step, 4) if ms_per_step is not None else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D anisotropic linear CDE, D2Q9, MMFD two-level SRT, periodic "
-                               "2048x2048, 10000 time steps per step, Gaussian hill + noise",
-                   "form": "MMFD", "precision": "fp32", "time_steps_per_step": TIME_STEPS,
-                   "nodes": N, "tb_depth": tb},
+        "config": {"workload": "2D incompressible NSE, three-level TRT MMFD, D2Q9, periodic "
+                               "4096x4096 Taylor-Green vortex Re = 100 + seeded velocity noise, "
+                               "FP32 state with FP64 reductions, 20000 time steps per step",
+                   "form": "MMFD", "precision": "fp32 (fp64 reductions)",
+                   "time_steps_per_step": HEAD_STEPS, "nodes": NH, "tb_depth": tb},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,9 +1,11 @@
 #!/bin/bash
-# rocprofv3 evidence for the headline step kernel (run from the repository
-# root on a machine with the GPU; writes raw results under gpurun_out/):
-#   1. kernel trace + stats of the headline benchmark,
-#   2. FETCH_SIZE and 3. WRITE_SIZE counters, each in a run of its own, with a
-#      256 MiB device copy as the counter calibration,
+# rocprofv3 evidence for the headline step kernel (2D NSE, three-level TRT,
+# D2Q9, 4096^2, FP32; run from the repository root on a machine with the GPU;
+# raw results under gpurun_out/):
+#   1. kernel trace + stats of the headline benchmark (autotuned plan),
+#   2. FETCH_SIZE, 3. WRITE_SIZE and 4. SQ_INSTS_VALU + SQ_WAVES counters, each
+#      in a run of its own on the plan of run 1, with a 256 MiB device copy as
+#      the HBM counter calibration,
 # then summarises them with paper_2505_17057_amd.profiling into gpurun_out/
 # (copy the .md and .json into profiles/).
 set -u
@@ -11,10 +13,9 @@ R=$(pwd)
 O=$R/gpurun_out
 mkdir -p "$O"
 export TMPDIR=/tmp
+B="python3 $R/bench.py --quick --no-cpu --copy-calibration"
 echo "profile: kernel trace"
-(cd /tmp && timeout -k 10 240 rocprofv3 --kernel-trace --stats -d "$O/prof_kt" -o kt -- python3 $R/bench.py --quick --steps 5 --warmup 1 --no-cpu --copy-calibration > "$O/prof_kt.txt" 2>&1) || exit 2
-# the counter runs use the plan the autotuner chose in the traced run, and
-# the summary takes the kernel that plan runs
+(cd /tmp && timeout -k 10 300 rocprofv3 --kernel-trace --stats -d "$O/prof_kt" -o kt -- $B --steps 2 --warmup 0 > "$O/prof_kt.txt" 2>&1) || exit 2
 read PLAN KNAME KSRC < <(python3 -c "import json,sys
 for l in open(sys.argv[1]):
     if l.startswith('{'):
@@ -23,31 +24,22 @@ for l in open(sys.argv[1]):
               r['kernel'].split()[0], r['kernel_source'])" "$O/prof_kt.txt")
 echo "plan $PLAN kernel $KNAME ($KSRC)"
 echo "profile: FETCH_SIZE"
-(cd /tmp && timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --kernel-trace -d "$O/prof_fetch" -o f -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration --plan $PLAN > "$O/prof_fetch.txt" 2>&1) || exit 3
+(cd /tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --kernel-trace -d "$O/prof_fetch" -o f -- $B --steps 1 --warmup 0 --plan $PLAN > "$O/prof_fetch.txt" 2>&1) || exit 3
 echo "profile: WRITE_SIZE"
-(cd /tmp && timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --kernel-trace -d "$O/prof_write" -o w -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration --plan $PLAN > "$O/prof_write.txt" 2>&1) || exit 4
-# the same two counters for the other plans the autotuner picks between runs
-ALTS=()
-for ALT in 10,106,128 12,112,128 14,116,128 16,120,128; do
-  [ "${ALT%%,*}" = "${PLAN%%,*}" ] && continue
-  T=${ALT//,/_}
-  echo "profile: FETCH_SIZE / WRITE_SIZE at $ALT"
-  # (result databases in /tmp: only the summaries come back)
-  (cd /tmp && timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --kernel-trace -d "/tmp/prof_fetch_$T" -o f -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --plan $ALT > "$O/prof_fetch_$T.txt" 2>&1) || exit 5
-  (cd /tmp && timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --kernel-trace -d "/tmp/prof_write_$T" -o w -- python3 $R/bench.py --quick --steps 1 --warmup 0 --no-cpu --plan $ALT > "$O/prof_write_$T.txt" 2>&1) || exit 5
-  ALTS+=(--alt "$ALT:/tmp/prof_fetch_$T/f_results.db:/tmp/prof_write_$T/w_results.db")
-  ALTS+=(--command "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d /tmp/prof_fetch_$T -o f -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --plan $ALT")
-  ALTS+=(--command "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d /tmp/prof_write_$T -o w -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --plan $ALT")
-done
-N=4194304
+(cd /tmp && timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --kernel-trace -d "$O/prof_write" -o w -- $B --steps 1 --warmup 0 --plan $PLAN > "$O/prof_write.txt" 2>&1) || exit 4
+echo "profile: SQ_INSTS_VALU SQ_WAVES"
+(cd /tmp && timeout -s KILL 300 rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --kernel-trace -d "$O/prof_valu" -o v -- $B --steps 1 --warmup 0 --plan $PLAN > "$O/prof_valu.txt" 2>&1) || exit 5
+N=16777216
+C="bench.py --quick --no-cpu --copy-calibration"
 python3 -m paper_2505_17057_amd.profiling --trace "$O/prof_kt/kt_results.db" \
   --fetch "$O/prof_fetch/f_results.db" --write "$O/prof_write/w_results.db" \
+  --valu "$O/prof_valu/v_results.db" --flops-per-lup 230 --lups-per-step $N \
   --kernel "$KNAME" --copy-bytes 268435456 \
   --kernel-source "$KSRC" --bench-log "$O/prof_kt.txt" \
-  --algorithmic-bytes-per-step $((8 * N)) --pass-bytes $((8 * N)) \
-  --workload "2D linear CDE, D2Q9, 2048x2048, MMFD FP32 (bench.py headline)" \
-  --out-md "$O/mmfd_lcde_d2q9_2048_fp32.md" --out-json "$O/traffic_mmfd_lcde_d2q9_2048_fp32.json" \
-  --command "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_kt -o kt -- python3 bench.py --quick --steps 5 --warmup 1 --no-cpu --copy-calibration" \
-  --command "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d gpurun_out/prof_fetch -o f -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration --plan $PLAN" \
-  --command "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d gpurun_out/prof_write -o w -- python3 bench.py --quick --steps 1 --warmup 0 --no-cpu --copy-calibration --plan $PLAN" \
-  "${ALTS[@]}"
+  --algorithmic-bytes-per-step $((36 * N)) --pass-bytes $((48 * N)) \
+  --workload "2D NSE, three-level TRT, D2Q9, 4096x4096, MMFD FP32 (bench.py headline)" \
+  --out-md "$O/nse_tb_d2q9_4096_fp32.md" --out-json "$O/counters_nse_tb_d2q9_4096_fp32.json" \
+  --command "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_kt -o kt -- python3 $C --steps 2 --warmup 0" \
+  --command "rocprofv3 --pmc FETCH_SIZE --kernel-trace -d gpurun_out/prof_fetch -o f -- python3 $C --steps 1 --warmup 0 --plan $PLAN" \
+  --command "rocprofv3 --pmc WRITE_SIZE --kernel-trace -d gpurun_out/prof_write -o w -- python3 $C --steps 1 --warmup 0 --plan $PLAN" \
+  --command "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --kernel-trace -d gpurun_out/prof_valu -o v -- python3 $C --steps 1 --warmup 0 --plan $PLAN"

@@ -87,9 +87,22 @@ def bench_plan(log_path):
     raise SystemExit("no bench JSON line in " + log_path)
 
 
-def stats_table(db_path, top=15):
-    """Markdown table of the `top` kernels by total time."""
-    stats = kernel_stats(db_path)
+def kernel_stats_by_grid(db_path):
+    """[(name [grid], calls, total_ns, mean_ns, min_ns, max_ns)] per kernel and
+    launch grid (a launch plan), sorted by total time."""
+    db = sqlite3.connect(db_path)
+    rows = defaultdict(list)
+    for name, grid, dur in db.execute("select name, grid_x, duration from kernels"):
+        rows["%s [grid %d]" % (name.split("(")[0], int(grid))].append(int(dur))
+    out = [(n, len(d), sum(d), sum(d) / len(d), min(d), max(d)) for n, d in rows.items()]
+    out.sort(key=lambda r: -r[2])
+    return out
+
+
+def stats_table(db_path, top=15, by_grid=False):
+    """Markdown table of the `top` kernels by total time (per launch grid, i.e.
+    per launch plan, when by_grid)."""
+    stats = kernel_stats_by_grid(db_path) if by_grid else kernel_stats(db_path)
     total = sum(r[2] for r in stats) or 1
     L = ["| kernel | calls | total ms | mean us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
     for n, c, t, m, lo, hi in stats[:top]:
@@ -108,7 +121,7 @@ def main(argv=None):
         if len(argv) > 4:
             print("Command (from the repository root; `cd /tmp && export TMPDIR=/tmp` first):\n")
             print("    " + argv[4] + "\n")
-        print(stats_table(argv[1], top))
+        print(stats_table(argv[1], top, by_grid=True))
         return
     p = argparse.ArgumentParser()
     p.add_argument("--trace", required=True)
@@ -128,6 +141,12 @@ def main(argv=None):
     p.add_argument("--command", action="append", default=[], help="command that produced an input")
     p.add_argument("--alt", action="append", default=[],
                    help="TB,H,W:FETCH_DB:WRITE_DB, counter runs of another launch plan of the kernel")
+    p.add_argument("--valu", default="",
+                   help="result database of a run with --pmc SQ_INSTS_VALU SQ_WAVES (optional)")
+    p.add_argument("--flops-per-lup", type=float, default=0.0,
+                   help="algorithmic flops per lattice update (for the VALU summary)")
+    p.add_argument("--lups-per-step", type=float, default=0.0,
+                   help="lattice updates of one time step over the grid")
     a = p.parse_args(argv)
     here = os.getcwd() + os.sep
     a.command = a.command + ["python -m paper_2505_17057_amd.profiling " +
@@ -175,6 +194,16 @@ def main(argv=None):
                          hbm_bytes_per_launch=round(ab), fetch_kib_raw=statistics.fmean(afk),
                          write_kib_raw=statistics.fmean(awk), dispatches=len(afk)))
     rec["alternates"] = alts
+    valu = None
+    if a.valu:
+        vg = counter_by_grid(a.valu, "SQ_INSTS_VALU", a.kernel)
+        wg = counter_by_grid(a.valu, "SQ_WAVES", a.kernel)
+        if main_grid in vg:
+            vi = statistics.fmean(vg[main_grid])
+            wv = statistics.fmean(wg[main_grid]) if main_grid in wg else None
+            valu = dict(insts=vi, waves=wv, dispatches=len(vg[main_grid]))
+            rec["valu_insts_per_launch"] = round(vi)
+            rec["waves_per_launch"] = round(wv) if wv else None
     with open(a.out_json, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -220,6 +249,29 @@ def main(argv=None):
             L.append("| %d, %d, %d | %.1f | %.1f | %d | %.3f |" % (
                 r["time_steps_per_launch"], r["window_rows"], r["window_cols"], r["fetch_kib_raw"],
                 r["write_kib_raw"], r["hbm_bytes_per_launch"], r["hbm_bytes_per_launch"] / a.pass_bytes))
+        L.append("")
+    if valu:
+        dur_s = mean_ns * 1e-9
+        issue = valu["insts"] / (dur_s * 256 * 2.4e9)
+        L.append("## VALU issue (`--pmc SQ_INSTS_VALU SQ_WAVES`)\n")
+        L.append("| quantity | per launch |")
+        L.append("|---|---|")
+        L.append("| SQ_INSTS_VALU (wavefront instructions, mean of %d) | %.0f |" % (valu["dispatches"],
+                                                                                 valu["insts"]))
+        if valu["waves"]:
+            L.append("| SQ_WAVES | %.0f |" % valu["waves"])
+            L.append("| VALU instructions per wavefront | %.1f |" % (valu["insts"] / valu["waves"]))
+        if a.lups_per_step:
+            L.append("| VALU instructions per lattice update (x 64 lanes) | %.1f |"
+                     % (valu["insts"] * 64 / (a.lups_per_step * tb)))
+        L.append("")
+        L.append("VALU issue rate over the trace's mean launch: %.3e wavefront instructions/s, "
+                 "%.3f wavefront instructions per CU per clock (256 CUs, 2.4 GHz)." %
+                 (valu["insts"] / dur_s, issue))
+        if a.flops_per_lup and a.lups_per_step:
+            tf = a.flops_per_lup * a.lups_per_step * tb / dur_s / 1e12
+            L.append("Algorithmic flops (%.0f per update): %.2f TFLOP/s = %.3f of the published FP32 "
+                     "vector peak (157.3 TFLOP/s)." % (a.flops_per_lup, tf, tf / 157.3))
         L.append("")
     L.append("Kernel source SHA-256: `%s` (%s)." % (sha, a.kernel_source))
     with open(a.out_md, "w") as f:
