@@ -66,7 +66,8 @@ def parse():
     p.add_argument("--no-headline", action="store_true",
                    help="skip the headline (profiling of the other sections; value is then null)")
     p.add_argument("--sections",
-                   default="c3err,c2,variants,theta,big,c1,nse3d,source,wave,burgers,batched,serving",
+                   default="c3err,c2,variants,multiset,theta,big,c1,nse3d,source,wave,burgers,burgers_theta,"
+                           "batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
@@ -504,6 +505,77 @@ def bench_burgers_single(M, torch, I, stream):
                 bytes_per_lup=8, time_steps_per_launch=tb, window_rows=h, window_cols=w)
 
 
+def bench_burgers_theta(M, torch, I, stream, theta=0.5, steps=200, chunk=4, cap=64):
+    """theta scheme for Burgers' equation (Picard iteration with the Jacobi
+    splitting of the linear even part) on one 2048^2 grid of the batched
+    workload's recipe, dt four times its explicit step, each step solved to a
+    tolerance (binary64 1e-12, binary32 1e-6): GLUPS at convergence, sweeps
+    per step, FP32 error against the FP64 run of the same steps."""
+    rng = np.random.default_rng(6)
+    c = I.burgers_instance(rng, side_lo=2048, side_hi=2048, steps_lo=steps, steps_hi=steps)
+    dt = 4.0 * c["dt"]
+    sp = 2 * c["nu"] * dt / ((1.0 / 3.0) * c["dx"] ** 2)
+    a = M.mfd_preset("two_level", sp)[0]
+    out, finals = {}, {}
+    N = 2048 * 2048
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-12)):
+        s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        s.set_equation("burgers")
+        s.set_scheme("theta", a, theta=theta, theta_iters=cap, dt=dt)
+        s.set_theta_tolerance(tol, chunk)
+        s.set_stream(stream.cuda_stream)
+        s.set_state(c["phi0"].astype(s.dtype))
+        s.step(5)
+        s.set_state(c["phi0"].astype(s.dtype))
+        s.theta_stats(reset=True)
+        ms = timed(torch, lambda: s.step(steps))
+        st = s.theta_stats()
+        finals[prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = N * steps / (ms * 1e-3) / 1e9
+        sw = st["total_sweeps"] / max(st["steps"], 1)
+        out[prec] = dict(glups=round(g, 2), tolerance=tol, sweeps_per_step=round(sw, 2),
+                         max_sweeps=st["max_sweeps"], steps_stopped_by_cap=st["unconverged"],
+                         sweep_glups=round(g * sw, 2))
+    out.update(theta=theta, dt_over_explicit=4.0, chunk_sweeps=chunk, sweep_cap=cap, steps=steps,
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
+                                         / np.linalg.norm(finals["fp64"])))
+    return out
+
+
+def bench_multiset(M, torch, cfg, stream, N, steps=1000):
+    """Multiple-set (TRT-type) two-level linear CDE, Eq. (2-2-1b), on the
+    2048^2 workload: base set SRT (a_-1 = 1), even set (1/2, 0, 1/2) and odd
+    set (3/4, 0, -1/4), which keep SRT's a_1 + a_-1 and a_1 - a_-1 (the
+    transport coefficients unchanged, so the run is stable at the same dt).
+    GLUPS (autotuned plan), FP32 error against FP64 after the run."""
+    a = M.mfd_preset("srt")[0]
+    ae = (0.5, 0.0, 0.5)
+    ao = (0.75, 0.0, -0.25)
+    out, finals = {}, {}
+    for prec in ("fp32", "fp64"):
+        s = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
+        s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
+        s.set_scheme_sets("two_level", a, ae, ao, dt=cfg["dt"])
+        s.set_stream(stream.cuda_stream)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        s.autotune()
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        ms = timed(torch, lambda: s.step(steps))
+        plan = s.launch_plan()
+        finals[prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = N * steps / (ms * 1e-3) / 1e9
+        bpl = 2 * (4 if prec == "fp32" else 8)
+        out[prec] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
+                         frac_hbm_algorithmic=round(g * bpl / HBM_PEAK_GBS, 4),
+                         time_steps_per_launch=plan[0], window_rows=plan[1], window_cols=plan[2])
+    out.update(steps=steps, base=a, even=ae, odd=ao,
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
+                                         / np.linalg.norm(finals["fp64"])))
+    return out
+
+
 def bench_batched(M, torch, I, stream):
     insts = I.c4_batch(256, seed=4)
     lups = sum(int(np.prod(c["n"])) * c["steps"] for c in insts)
@@ -776,6 +848,9 @@ def main():
         log("variants")
         extra["variants"], extra["fp32_rel_l2_vs_fp64_after_10000"], extra["mesofd_vs_mmfd_fp64_max_abs"] = \
             bench_variants(M, torch, cfg, stream, N)
+    if "multiset" in sections:
+        log("multiset")
+        extra["multiset_d2q9_2048"] = bench_multiset(M, torch, cfg, stream, N)
     if "theta" in sections:
         log("theta")
         extra["theta_d2q9_2048"] = bench_theta(M, torch, cfg, stream, N)
@@ -797,6 +872,9 @@ def main():
     if "burgers" in sections:
         log("burgers 2048^2")
         extra["burgers_2048_mmfd_fp32"] = bench_burgers_single(M, torch, I, stream)
+    if "burgers_theta" in sections:
+        log("burgers theta")
+        extra["burgers_theta_2048"] = bench_burgers_theta(M, torch, I, stream)
     if "batched" in sections:
         log("batched")
         extra["batched_256_burgers"] = bench_batched(M, torch, I, stream)

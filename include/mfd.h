@@ -161,6 +161,22 @@ int mfd_set_scheme(mfd_solver *s, int kind, const double a[3], const double ah[3
                    const double ab[3], const double abh[3], double theta,
                    int32_t theta_iters, double dt);
 
+/* Multiple-set (TRT-type) explicit scheme of Eq. (2-2-1b) for a scalar
+ * equation (linear CDE, Burgers, wave) in the MMFD form: the base terms
+ * sum_k a_k phi (+ sum_k ah_k phi^(n-1)) take the set a / ah, the second
+ * differences of the even EDF parts take the even set ae / aeh (through
+ * ae_1 + ae_-1), the first differences of the odd parts the odd set ao / aoh
+ * (through ao_1 - ao_-1); index k + 1 for k = -1, 0, +1, level t and t - dt
+ * (ah, aeh, aoh only for MFD_THREE_LEVEL).  With ae = ao = a it is the scheme
+ * of mfd_set_scheme; with a = ae its moments are those of the populations of
+ * Eq. (2-1b).  The linear CDE maps K with A10 of the base set and A22 of the
+ * even set.  Checks and warnings as mfd_set_scheme on the base set;
+ * MFD_E_UNSUPPORTED for the NSE, the MesoFD form or kinds other than two-
+ * and three-level. */
+int mfd_set_scheme_sets(mfd_solver *s, int kind, const double a[3], const double ah[3],
+                        const double ae[3], const double aeh[3], const double ao[3],
+                        const double aoh[3], double dt);
+
 /* Solve every theta step (Eq. (GCN), Theorem 2) to a residual tolerance:
  * Jacobi sweeps started from phi(t), checked after every `chunk` sweeps
  * (0: 8; at most 16), stopping at the first check where

@@ -76,6 +76,12 @@ typedef struct {
      * evaluated by the caller); bG has one value per node (edges read) */
     double bscale;
     const double *bG;
+    /* multiple-set parameters, Eq. (2-2-1b) / (2-1b) (scalar equations):
+     * multiset = 1 takes the Delta^2 (even) terms from ae/aeh and the
+     * Delta^1 (odd) terms from ao/aoh; a/ah keep the base terms */
+    int32_t multiset;
+    int32_t pad2_;
+    double ae[3], aeh[3], ao[3], aoh[3];
 } orc_params;
 
 typedef struct {
@@ -235,6 +241,13 @@ static int make_ctx(const orc_params *P, orc_ctx *c)
     c->Abh0 = P->abh[0] + P->abh[1] + P->abh[2];
     c->ap = P->a[2] + P->a[0];    c->am = P->a[2] - P->a[0];
     c->ahp = P->ah[2] + P->ah[0]; c->ahm = P->ah[2] - P->ah[0];
+    if (P->multiset) {
+        /* Eq. (2-2-1b): the even parts' second differences take the even
+         * set, the odd parts' first differences the odd set */
+        if (P->eq == ORC_NSE) return -4;
+        c->ap = P->ae[2] + P->ae[0];    c->am = P->ao[2] - P->ao[0];
+        c->ahp = P->aeh[2] + P->aeh[0]; c->ahm = P->aoh[2] - P->aoh[0];
+    }
     c->abp = P->ab[2] + P->ab[0]; c->abm = P->ab[2] - P->ab[0];
     c->abhp = P->abh[2] + P->abh[0]; c->abhm = P->abh[2] - P->abh[0];
 
@@ -567,6 +580,33 @@ static void full_edf(const orc_params *P, const orc_ctx *c, const double *lev, d
  *   phi(x, t+dt) = sum_j sum_(k,level) a_k f_j^eq(x + k e_j, level)
  * and for the NSE first moments the same with e_j and the momentum set.
  */
+/*
+ * Population j at node (x,y,z) of the multiple-set scheme, Eq. (2-1b):
+ *   f_j = sum_k [ ae_k g+_j(x + k e_j) + ao_k g-_j(x + k e_j) ]   (level t)
+ *       + sum_k [ aeh_k g+_j(...) + aoh_k g-_j(...) ]              (level t - dt)
+ * with g+-_j = (g_j +- g_jbar)/2 the even / odd parts of the EDF at the same
+ * node (Eq. (2-5)); zero coefficients skipped, k = -1, 0, +1, level t first.
+ */
+static double multiset_pop(const orc_params *P, const orc_ctx *c, const double *G,
+                           const double *H, int j, int64_t x, int64_t y, int64_t z)
+{
+    const int64_t N = c->N;
+    const int jb = c->L.opp[j];
+    double fj = 0.0;
+    for (int lev = 0; lev < (H ? 2 : 1); ++lev) {
+        const double *L = lev == 0 ? G : H;
+        const double *ae = lev == 0 ? P->ae : P->aeh, *ao = lev == 0 ? P->ao : P->aoh;
+        for (int k = -1; k <= 1; ++k) {
+            int64_t y0 = nb(c, x, y, z, j, k);
+            double gp = 0.5 * (L[j * N + y0] + L[jb * N + y0]);
+            double gm = 0.5 * (L[j * N + y0] - L[jb * N + y0]);
+            if (ae[k + 1] != 0.0) fj = fj + ae[k + 1] * gp;
+            if (ao[k + 1] != 0.0) fj = fj + ao[k + 1] * gm;
+        }
+    }
+    return fj;
+}
+
 int orc_literal_step(const orc_params *P, const double *cur, const double *prev, double *out)
 {
     orc_ctx c;
@@ -609,11 +649,15 @@ static int literal_step_all(const orc_params *P, const double *cur, const double
                         int e = f == 0 ? 1 : c.L.e[j][f - 1];
                         if (e == 0) continue;
                         double fj = 0.0;
-                        for (int k = -1; k <= 1; ++k)
-                            if (ak[k + 1] != 0.0) fj = fj + ak[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
-                        if (three)
+                        if (P->multiset) {
+                            fj = multiset_pop(P, &c, G, three ? H : NULL, j, x, y, z);
+                        } else {
                             for (int k = -1; k <= 1; ++k)
-                                if (ahk[k + 1] != 0.0) fj = fj + ahk[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                                if (ak[k + 1] != 0.0) fj = fj + ak[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
+                            if (three)
+                                for (int k = -1; k <= 1; ++k)
+                                    if (ahk[k + 1] != 0.0) fj = fj + ahk[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                        }
                         s = e == 1 ? s + fj : s - fj;
                     }
                     out[f * N + i] = s;
@@ -750,11 +794,15 @@ static int mesofd_step(const orc_params *P, const orc_source *Q, const double *p
                 int64_t i = (z * c.n[1] + y) * c.n[0] + x;
                 for (int j = 0; j < b; ++j) {
                     double fj = 0.0;
-                    for (int k = -1; k <= 1; ++k)
-                        if (P->a[k + 1] != 0.0) fj = fj + P->a[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
-                    if (three)
+                    if (P->multiset) {
+                        fj = multiset_pop(P, &c, G, three ? H : NULL, j, x, y, z);
+                    } else {
                         for (int k = -1; k <= 1; ++k)
-                            if (P->ah[k + 1] != 0.0) fj = fj + P->ah[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                            if (P->a[k + 1] != 0.0) fj = fj + P->a[k + 1] * G[j * N + nb(&c, x, y, z, j, k)];
+                        if (three)
+                            for (int k = -1; k <= 1; ++k)
+                                if (P->ah[k + 1] != 0.0) fj = fj + P->ah[k + 1] * H[j * N + nb(&c, x, y, z, j, k)];
+                    }
                     if (Q) fj = fj + P->dt * source_dir(P, &c, Q, St, Sm, j, x, y, z);
                     pop_out[j * N + i] = fj;
                 }

@@ -48,6 +48,9 @@ class Params(C.Structure):
         ("ab", C.c_double * 3), ("abh", C.c_double * 3),
         ("theta", C.c_double),
         ("bscale", C.c_double), ("bG", C.POINTER(C.c_double)),
+        ("multiset", C.c_int32), ("pad2_", C.c_int32),
+        ("ae", C.c_double * 3), ("aeh", C.c_double * 3),
+        ("ao", C.c_double * 3), ("aoh", C.c_double * 3),
     ]
 
 
@@ -143,6 +146,13 @@ def make_params(spec: dict) -> Params:
     P.ab = _triple([float(x) for x in spec.get("ab", a)])
     P.abh = _triple([float(x) for x in spec.get("abh", ah)])
     P.theta = float(spec.get("theta", 1.0))
+    if "ae" in spec or "ao" in spec:
+        # multiple-set scheme, Eq. (2-2-1b): even set ae/aeh, odd set ao/aoh
+        P.multiset = 1
+        P.ae = _triple([float(x) for x in spec.get("ae", a)])
+        P.aeh = _triple([float(x) for x in spec.get("aeh", ah)])
+        P.ao = _triple([float(x) for x in spec.get("ao", a)])
+        P.aoh = _triple([float(x) for x in spec.get("aoh", ah)])
     return P
 
 

@@ -631,6 +631,56 @@ hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double 
   return hipGetLastError();
 }
 
+// Picard-Jacobi theta step of Burgers' equation (Eq. (GCN)): the elementwise
+// parts around the explicit step kernel S,
+//   R       = theta S(phi^n) + (1 - theta) (A0 phi^n),
+//   x_{k+1} = (R + (1 - theta) ((S(x_k) - A0 x_k) + dd x_k)) / den,
+// one rounding per operation in the order written.
+template <typename T>
+__global__ __launch_bounds__(256) void k_picard_rhs(const T *__restrict__ S0,
+                                                    const T *__restrict__ phi, T *__restrict__ R,
+                                                    T th, T th1, T A0, int64_t N) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T a = th * S0[i];
+    const T b = A0 * phi[i];
+    R[i] = a + th1 * b;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_picard_update(const T *__restrict__ Sx,
+                                                       const T *__restrict__ x,
+                                                       const T *__restrict__ R,
+                                                       T *__restrict__ out, T A0, T dd, T th1,
+                                                       T inv_den, int64_t N) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T xi = x[i];
+    const T t = (Sx[i] - A0 * xi) + dd * xi;
+    const T c = th1 * t;
+    out[i] = (R[i] + c) * inv_den;
+  }
+}
+
+template <typename T>
+hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, double A0,
+                             int64_t N, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_picard_rhs<T>), dim3(nblk), dim3(256), 0, st, S0, phi, R, (T)th, (T)th1,
+                     (T)A0, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, double A0, double dd,
+                                double th1, double inv_den, int64_t N, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_picard_update<T>), dim3(nblk), dim3(256), 0, st, Sx, x, R, out, (T)A0,
+                     (T)dd, (T)th1, (T)inv_den, N);
+  return hipGetLastError();
+}
+
 // Special first step of the three-level wave scheme (Example 3 of the paper):
 // phi(t + dt) = phi + dt phi_t + cw sum_axes [(phi(x+e_a) - 2 phi) + phi(x-e_a)]
 // at every node (periodic wrap), in binary64 and rounded once; on a
@@ -678,6 +728,10 @@ hipError_t launch_wave_start(const Consts &c, const Grid &g, const T *phi0, cons
 }
 
 #define MFD_INST(T)                                                                               \
+  template hipError_t launch_picard_rhs<T>(const T *, const T *, T *, double, double, double,     \
+                                           int64_t, hipStream_t);                                 \
+  template hipError_t launch_picard_update<T>(const T *, const T *, const T *, T *, double,       \
+                                              double, double, double, int64_t, hipStream_t);      \
   template hipError_t launch_wave_start<T>(const Consts &, const Grid &, const T *,               \
                                            const double *, T *, double, double, const DirBC &,    \
                                            hipStream_t);                                          \

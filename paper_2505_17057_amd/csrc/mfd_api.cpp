@@ -242,6 +242,7 @@ int Solver::step_t(int64_t nsteps) {
     prev_gap = 1;
     return MFD_OK;
   }
+  if (cfg.kind == MFD_THETA && consts.eq == kBurgers) return theta_picard_steps<T>(nsteps);
   if (cfg.kind == MFD_THETA && theta_tol > 0.0) return theta_solve_steps<T>(nsteps);
   const TbPlan pl = effective_plan();
   const int d = pl.tb;
@@ -436,6 +437,75 @@ int Solver::theta_solve_steps(int64_t nsteps) {
   return MFD_OK;
 }
 
+// Theta steps of Burgers' equation (beta = 1): Picard iteration with the
+// Jacobi splitting of the linear even part (chunks of theta_chunk sweeps
+// checked on the host when a tolerance is set, else theta_iters sweeps).
+template <typename T>
+int Solver::theta_picard_steps(int64_t nsteps) {
+  T *B[kNumBuf];
+  for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  const bool tol_on = theta_tol > 0.0;
+  const int cap = cfg.theta_iters;
+  const int K = tol_on ? theta_chunk : cap;
+  const int third = 3 - ic - io;  // the ring level neither phi^n nor the io role holds
+  const double th = consts.theta, th1 = consts.th1;
+  const double A0 = consts.A0;
+  double sp = 0.0;
+  for (int p = 0; p < consts.npair; ++p) sp = sp + consts.ap * consts.w[consts.pair[p]];
+  const double dd = 2.0 * sp;
+  const double den = 1.0 + th1 * dd;
+  const double inv_den = 1.0 / den;
+  double *part = (double *)buf[kRedBuf];
+  double *out = part + kReduceBlocks * 8;
+  const int64_t N = G.N;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e = launch_mmfd_step<T>(consts, G, B[ic], nullptr, B[6], 1, stream);
+    if (e == hipSuccess) e = launch_picard_rhs<T>(B[6], B[ic], B[5], th, th1, A0, N, stream);
+    if (e != hipSuccess) return hip(e, "picard rhs launch");
+    const T *src = B[ic];
+    int k = 0;
+    bool conv = false;
+    while (true) {
+      const T *before = src;
+      for (int it = 0; it < K; ++it) {
+        T *dst = (k % 2 == 0) ? B[io] : B[third];
+        e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
+        if (e == hipSuccess)
+          e = launch_picard_update<T>(B[6], src, B[5], dst, A0, dd, th1, inv_den, N, stream);
+        if (e != hipSuccess) return hip(e, "picard sweep launch");
+        before = src;
+        src = dst;
+        ++k;
+      }
+      if (!tol_on) break;
+      e = launch_sq_sums<T>(src, before, B[5], N, part, out, stream);
+      if (e != hipSuccess) return hip(e, "picard residual launch");
+      double hsum[2];
+      int rc = copy_out(hsum, out, sizeof(hsum), 0);
+      if (rc) return rc;
+      if (!std::isfinite(hsum[0]) || !std::isfinite(hsum[1]))
+        return fail(MFD_E_UNSTABLE, "non-finite theta residual");
+      conv = den * den * hsum[0] <= theta_tol * theta_tol * hsum[1];
+      if (conv || k >= cap) break;
+    }
+    if (src == B[third]) {  // the result is kept in the io role
+      std::swap(buf[io], buf[third]);
+      std::swap(B[io], B[third]);
+    }
+    std::swap(ic, io);
+    ip = io;
+    ++steps_done;
+    if (tol_on) {
+      th_total += k;
+      ++th_steps;
+      th_max = std::max(th_max, k);
+      if (!conv) ++th_unconv;
+    }
+  }
+  prev_gap = 1;
+  return MFD_OK;
+}
+
 bool Solver::source_supported() const {
   if (cfg.kind == MFD_THETA || consts.eq != kLCDE || consts.wave || dirichlet) return false;
   return grid.form == MFD_MMFD || grid.dim <= 2;  // MesoFD: 1D / 2D
@@ -532,6 +602,13 @@ static int rebuild(Solver *s) {
   in.beta = s->cfg.ep.beta;
   in.rho0 = s->cfg.ep.rho0;
   in.he_luo = s->cfg.ep.he_luo;
+  in.multiset = s->cfg.multiset;
+  for (int k = 0; k < 3; ++k) {
+    in.ae[k] = s->cfg.ae[k];
+    in.ao[k] = s->cfg.ao[k];
+    in.aeh[k] = s->cfg.kind == MFD_THREE_LEVEL ? s->cfg.aeh[k] : 0.0;
+    in.aoh[k] = s->cfg.kind == MFD_THREE_LEVEL ? s->cfg.aoh[k] : 0.0;
+  }
   int rc = build_consts(in, s->consts);
   if (rc) return s->fail(rc, "scheme constants could not be formed");
   s->configured = true;
@@ -604,8 +681,10 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
   if (kind == MFD_THETA) {
     if (s->dirichlet)
       return s->fail(MFD_E_UNSUPPORTED, "the theta scheme runs on periodic grids");
-    if (s->cfg.eq != MFD_LCDE)
-      return s->fail(MFD_E_UNSUPPORTED, "the theta scheme is implemented for the LCDE only");
+    if (s->cfg.eq != MFD_LCDE &&
+        !(s->cfg.eq == MFD_BURGERS && (s->cfg.ep.beta == 1.0 || s->cfg.ep.beta == 0.0)))
+      return s->fail(MFD_E_UNSUPPORTED,
+                     "the theta scheme is implemented for the LCDE and Burgers' equation (beta = 1)");
     if (!(theta >= 0.0 && theta <= 1.0) || theta_iters < 0)
       return s->fail(MFD_E_ARG, "theta must lie in [0,1] and theta_iters >= 0");
     if (s->grid.form != MFD_MMFD)
@@ -644,6 +723,7 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
   s->cfg.theta = kind == MFD_THETA ? theta : 1.0;
   s->cfg.theta_iters = kind == MFD_THETA ? theta_iters : 0;
   s->cfg.dt = dt;
+  s->cfg.multiset = 0;
   s->have_scheme = true;
   int rc = rebuild(s);
   if (rc < 0) return rc;
@@ -1241,4 +1321,39 @@ extern "C" int mfd_wave_start(mfd_solver *h, const double *phi_t, int64_t count,
   s->prev_gap = 1;
   s->prev_set = true;
   return MFD_OK;
+}
+
+extern "C" int mfd_set_scheme_sets(mfd_solver *h, int kind, const double a[3], const double ah[3],
+                                   const double ae[3], const double aeh[3], const double ao[3],
+                                   const double aoh[3], double dt) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->have_lattice || !s->have_eq)
+    return s->fail(MFD_E_ORDER, "mfd_set_lattice and mfd_set_equation must precede the scheme");
+  if (kind != MFD_TWO_LEVEL && kind != MFD_THREE_LEVEL)
+    return s->fail(MFD_E_UNSUPPORTED, "multiple-set schemes are explicit two- or three-level");
+  if (s->cfg.eq == MFD_NSE || s->grid.form != MFD_MMFD)
+    return s->fail(MFD_E_UNSUPPORTED, "multiple-set schemes: scalar equations, MMFD form");
+  const bool three = kind == MFD_THREE_LEVEL;
+  if (!a || !ae || !ao || (three && (!ah || !aeh || !aoh)))
+    return s->fail(MFD_E_ARG, "null coefficient set");
+  for (int k = 0; k < 3; ++k) {
+    const double v[6] = {a[k], ae[k], ao[k], three ? ah[k] : 0.0, three ? aeh[k] : 0.0,
+                         three ? aoh[k] : 0.0};
+    for (double x : v)
+      if (!std::isfinite(x)) return s->fail(MFD_E_ARG, "non-finite coefficient");
+  }
+  // the base set through the single-set call (checks, A00, stability report)
+  int rc = mfd_set_scheme(h, kind, a, three ? ah : nullptr, nullptr, nullptr, 1.0, 0, dt);
+  if (rc < 0) return rc;
+  s->cfg.multiset = 1;
+  for (int k = 0; k < 3; ++k) {
+    s->cfg.ae[k] = ae[k];
+    s->cfg.ao[k] = ao[k];
+    s->cfg.aeh[k] = three ? aeh[k] : 0.0;
+    s->cfg.aoh[k] = three ? aoh[k] : 0.0;
+  }
+  int rc2 = rebuild(s);
+  if (rc2 < 0) return rc2;
+  return rc;
 }

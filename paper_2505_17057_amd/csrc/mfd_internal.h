@@ -69,6 +69,7 @@ struct Consts {
   // theta
   double theta, th1, den, inv_den;  // den = 1 + (1 - theta) 2 sum_p Cp_p
   int wave;           // the linear EDF of the wave equation (eq = kLCDE)
+  int multiset;       // a+-/ah+- from the even / odd sets of Eq. (2-2-1b)
   int three;          // three-level scheme
   int three_stencil;  // level t - dt enters through central differences
 };
@@ -79,6 +80,7 @@ struct KC {
   T w[kMaxQ], w1[kMaxQ], qd[kMaxQ][3], qo[kMaxQ][3], inv_d0;
   T ubar[kMaxQ];
   T ap, am, ahp, ahm, abp, abm, abhp, abhm;
+  T nw[kMaxP][4];  // binary32 NSE pair form: a+ w_p, a- w_p / d0, abar+ w_p / d0, abar- w_p
   T a[3], ah[3];              // k = -1, 0, +1 (MesoFD)
   T Cp[kMaxP], Cm[kMaxP], Chp[kMaxP], Chm[kMaxP];
   T Ap[kMaxP], Am[kMaxP], Ahp[kMaxP], Ahm[kMaxP];  // Cp +- Cm, Chp +- Chm (binary32 form)
@@ -287,6 +289,13 @@ hipError_t launch_theta_chunk(const Consts &c, const Grid &g, int K, T *const bu
                               hipStream_t st);
 template <typename T>
 hipError_t launch_theta_gather(T *const bufs[4], const ThetaCtl *ctl, int64_t N, hipStream_t st);
+// Picard-Jacobi theta step of Burgers' equation: the elementwise parts
+template <typename T>
+hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, double A0,
+                             int64_t N, hipStream_t st);
+template <typename T>
+hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, double A0, double dd,
+                                double th1, double inv_den, int64_t N, hipStream_t st);
 // sum (a - b)^2 and sum c^2 in binary64 (out[0], out[1]); partial as launch_reduce
 template <typename T>
 hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,

@@ -131,6 +131,13 @@ int build_consts(const SchemeInput &in, Consts &c) {
   c.abm = ab[2] - ab[0];
   c.abhp = abh[2] + abh[0];
   c.abhm = abh[2] - abh[0];
+  if (in.multiset) {
+    c.ap = in.ae[2] + in.ae[0];
+    c.am = in.ao[2] - in.ao[0];
+    c.ahp = in.aeh[2] + in.aeh[0];
+    c.ahm = in.aoh[2] - in.aoh[0];
+    c.multiset = 1;
+  }
   for (int k = 0; k < 3; ++k) {
     c.a[k] = a[k];
     c.ah[k] = in.kind == MFD_THREE_LEVEL ? ah[k] : 0.0;
@@ -196,6 +203,8 @@ int build_consts(const SchemeInput &in, Consts &c) {
     c.den = 1.0 + c.th1 * (2.0 * sp);
     c.inv_den = 1.0 / c.den;
   } else if (in.eq == kBurgers) {
+    c.theta = in.kind == MFD_THETA ? in.theta : 1.0;
+    c.th1 = 1.0 - c.theta;
     c.bh = 0.5 * in.dt / in.dx;
     c.beta_one = in.beta == 1.0;
     c.cbeta = (in.beta - 1.0) * d0;
@@ -238,6 +247,13 @@ KC<T> make_kc(const Consts &c) {
     k.Am[p] = (T)(c.Cp[p] - c.Cm[p]);
     k.Ahp[p] = (T)(c.Chp[p] + c.Chm[p]);
     k.Ahm[p] = (T)(c.Chp[p] - c.Chm[p]);
+  }
+  for (int p = 0; p < c.npair; ++p) {
+    const int j = c.pair[p];
+    k.nw[p][0] = (T)(c.ap * c.w[j]);
+    k.nw[p][1] = (T)(c.am * c.w1[j]);
+    k.nw[p][2] = (T)(c.abp * c.w1[j]);
+    k.nw[p][3] = (T)(c.abm * c.w[j]);
   }
   k.bh = (T)c.bh;
   k.cbeta = (T)c.cbeta;

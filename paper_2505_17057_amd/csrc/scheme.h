@@ -19,6 +19,10 @@ struct SchemeInput {
   int lambda_bar;
   double beta, rho0;
   int he_luo;
+  // multiple-set scheme, Eq. (2-2-1b): even set ae/aeh (second differences of
+  // the even EDF parts), odd set ao/aoh (first differences of the odd parts)
+  int multiset;
+  double ae[3], aeh[3], ao[3], aoh[3];
 };
 
 int lattice_weights(int lattice, double d0, Consts &c);

@@ -20,6 +20,8 @@ struct Config {
   double theta = 1.0;
   int theta_iters = 0;
   double dt = 0.0;
+  int multiset = 0;
+  double ae[3] = {0, 0, 0}, aeh[3] = {0, 0, 0}, ao[3] = {0, 0, 0}, aoh[3] = {0, 0, 0};
 };
 
 struct Solver {
@@ -86,6 +88,8 @@ struct Solver {
   int step_t(int64_t nsteps);
   template <typename T>
   int theta_solve_steps(int64_t nsteps);
+  template <typename T>
+  int theta_picard_steps(int64_t nsteps);
 };
 
 }  // namespace mfd

@@ -114,6 +114,7 @@ _SIGS = {
     "mfd_max_stable_dt": ([C.c_int, C.c_double, C.c_double, _PD, C.c_double, C.POINTER(C.c_int64),
                            _PD, _PD], C.c_int),
     "mfd_level_ptr": ([_H, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "mfd_set_scheme_sets": ([_H, C.c_int, _PD, _PD, _PD, _PD, _PD, _PD, C.c_double], C.c_int),
     "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
     "mfd_theta_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.c_int], C.c_int),
@@ -361,6 +362,14 @@ class Solver:
         d = C.c_int32()
         self.check(lib.mfd_autotune(self.h, C.byref(d)), "mfd_autotune")
         return d.value
+
+    def set_scheme_sets(self, kind, a, ae, ao, ah=None, aeh=None, aoh=None, dt=1.0):
+        """Multiple-set scheme of Eq. (2-2-1b) (mfd_set_scheme_sets)."""
+        self.kind = kind
+        three = kind == "three_level"
+        f = (lambda v: _d3(v) if three else None)
+        return self.check(lib.mfd_set_scheme_sets(self.h, KINDS[kind], _d3(a), f(ah), _d3(ae), f(aeh),
+                                                  _d3(ao), f(aoh), float(dt)), "mfd_set_scheme_sets")
 
     def set_theta_tolerance(self, tol, chunk=0):
         return self.check(lib.mfd_set_theta_tolerance(self.h, float(tol), int(chunk)),

@@ -93,7 +93,8 @@ def kernel_stats_by_grid(db_path):
     db = sqlite3.connect(db_path)
     rows = defaultdict(list)
     for name, grid, dur in db.execute("select name, grid_x, duration from kernels"):
-        rows["%s [grid %d]" % (name.split("(")[0], int(grid))].append(int(dur))
+        base = name.replace("(anonymous namespace)::", "").split("(")[0]
+        rows["%s [grid %d]" % (base, int(grid))].append(int(dur))
     out = [(n, len(d), sum(d), sum(d) / len(d), min(d), max(d)) for n, d in rows.items()]
     out.sort(key=lambda r: -r[2])
     return out

@@ -316,3 +316,28 @@ def test_dirichlet_argument_checks(M):
         p.wave_start(np.zeros(256))  # no state yet
     assert ei.value.code == M.MFD_E_ORDER
     p.close()
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_multiset_constant_tables_bitwise(M, three):
+    """The multiple-set constants (Eq. (2-2-1b)) of the library equal the
+    oracle's bit for bit."""
+    kw = dict(n=(8, 8), u=(0.3, -0.2), K=[[0.3, 0.05], [0.05, 0.2]], lambda_bar=1)
+    a, ah = ((0.875, 0.0, 0.125), (0.125, 0.0, -0.125)) if three else ((0.6, 0.2, 0.2), None)
+    ae, aeh = (0.8, 0.1, 0.1), (0.1, -0.1, 0.1)
+    ao, aoh = (0.95, 0.0, 0.05), (0.05, 0.0, -0.05)
+    spec = dict(lattice="D2Q9", eq="lcde", a=a, ae=ae, ao=ao, levels=3 if three else 2, **kw)
+    if three:
+        spec.update(ah=ah, aeh=aeh, aoh=aoh)
+    w, ub, tab = O.tables(spec)
+    s = M.Solver("D2Q9", kw["n"], 1.0, "fp64", "mmfd")
+    s.set_equation("lcde", u=kw["u"], K=kw["K"], lambda_bar=1)
+    if three:
+        s.set_scheme_sets("three_level", a, ae, ao, ah, aeh, aoh, dt=1.0)
+    else:
+        s.set_scheme_sets("two_level", a, ae, ao, dt=1.0)
+    gw, gub, gtab = s.linear_tables()
+    assert np.array_equal(gub, ub)
+    for k in tab:
+        assert np.array_equal(gtab[k], tab[k]), k
+    s.close()

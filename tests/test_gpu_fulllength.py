@@ -1,0 +1,234 @@
+"""GPU: parity over the full lengths and in the launch plans the benchmark
+times.
+
+* 1D linear CDE (1024 nodes, D1Q3, dt = half the library's Eq. (LMMFD-2-3)
+  bound): all 1000 steps, MMFD and MesoFD, binary64 bit-exact with the
+  oracle.
+* 2048^2 linear CDE: all 10 000 steps under the autotuned plan, binary64
+  bit-exact with the oracle; binary32 within 1e-5 (relative L2) of it.
+* 4096^2 NSE three-level TRT: the autotuned plan and the (4, 32, 64) plan,
+  two launches and a ragged remainder, both levels binary64 bit-exact.
+* 3D NSE D3Q19: all 1000 steps at 96^3 bit-exact; a two-step prefix at
+  512^3 when the host has the memory for the oracle (about 60 GB).
+* 256 Burgers grids (the batched workload): binary32 batch against the
+  per-instance binary64 runs after the full run of every grid, each error
+  measured against the grid's initial norm (the fields decay by up to six
+  orders of magnitude, so their final norm is no scale for round-off), and
+  the three smallest grids' binary64 runs bit-exact with the oracle over
+  their full length.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import mfd_inputs as I
+from oracle import native as O
+from oracle import scheme as S
+
+pytestmark = pytest.mark.gpu
+
+D0 = 1.0 / 3.0
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("form", ["mmfd", "mesofd"])
+def test_c1_full_run(M, form):
+    c = I.c1_linear_1d()
+    bound, _ = M.mfd_max_stable_dt("D1Q3", c["dx"], c["u"], c["D"])
+    dt = 0.5 * bound
+    sp = 2 * c["D"] * dt / (D0 * c["dx"] ** 2)
+    a = M.mfd_preset("two_level", sp)[0]
+    spec = dict(lattice="D1Q3", n=c["n"], dx=c["dx"], dt=dt, u=c["u"], K=c["K"], a=a)
+    s = M.Solver("D1Q3", c["n"], c["dx"], "fp64", form)
+    s.set_equation("lcde", u=c["u"], K=c["K"])
+    s.set_scheme("two_level", a, dt=dt)
+    s.set_state(c["phi0"])
+    s.step(c["steps"])
+    got = s.get_state()
+    if form == "mmfd":
+        want = c["phi0"]
+        for _ in range(c["steps"]):
+            want = O.mmfd_step(spec, want)
+        assert np.array_equal(got, want)
+    else:
+        pop = O.init_populations(spec, c["phi0"])
+        for _ in range(c["steps"]):
+            pop, _ = O.mesofd_step(spec, pop)
+        assert np.array_equal(s.get_state(populations=True), pop)
+        assert np.array_equal(got, O.moments(spec, pop))
+    s.close()
+
+
+@pytest.mark.timeout(900)
+def test_c2_full_10000_steps(M):
+    c = I.c2_hill_2d(n=2048)
+    spec = dict(lattice="D2Q9", n=c["n"], dx=c["dx"], dt=c["dt"], u=c["u"], K=c["K"],
+                lambda_bar=1, a=S.preset_srt()[0])
+    steps = c["steps"]
+    _say("C2: oracle, %d steps of 2048^2" % steps)
+    want = c["phi0"]
+    for k in range(steps):
+        want = O.mmfd_step(spec, want)
+        if k % 2000 == 1999:
+            _say("  oracle step", k + 1)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        s.set_equation("lcde", u=c["u"], K=c["K"], lambda_bar=1)
+        s.set_scheme("two_level", M.mfd_preset("srt")[0], dt=c["dt"])
+        s.set_state(c["phi0"].astype(s.dtype))
+        s.autotune()
+        res[prec + "_plan"] = s.launch_plan()
+        s.set_state(c["phi0"].astype(s.dtype))
+        s.step(steps)
+        res[prec] = s.get_state().astype(np.float64)
+        s.close()
+    _say("C2 plans", res["fp64_plan"], res["fp32_plan"])
+    assert res["fp64_plan"][0] > 1 and res["fp32_plan"][0] > 1  # blocked plans
+    assert np.array_equal(res["fp64"], want)
+    assert _rel(res["fp32"], want) <= 1e-5
+
+
+@pytest.mark.parametrize("plan", ["autotuned", (4, 32, 64)], ids=["autotuned", "tb4-32x64"])
+def test_c3_2d_benched_plan(M, plan):
+    c = I.tgv_2d(n=4096)
+    x = c["state0"].astype(np.float32).astype(np.float64)
+    s = M.Solver("D2Q9", c["n"], c["dx"], "fp64", "mmfd")
+    s.set_equation("nse", rho0=c["rho0"])
+    nu = c["nu"]
+    sl = 1.0 / (nu / (c["dt"] * D0 * (c["dx"] / c["dt"]) ** 2) + 0.5)
+    a, ah = M.mfd_preset("trt", sl)
+    s.set_scheme("three_level", a, ah, dt=c["dt"])
+    s.set_state(x)
+    if plan == "autotuned":
+        s.autotune()
+        s.set_state(x)
+    else:
+        s.set_plan(*plan)
+    tb = s.launch_plan()[0]
+    steps = 2 * tb + 1  # two launches and a remainder step
+    spec = dict(lattice="D2Q9", eq="nse", n=c["n"], dx=c["dx"], dt=c["dt"], rho0=c["rho0"],
+                a=a, ah=ah, levels=3)
+    cur, prev = x, x
+    for _ in range(steps):
+        cur, prev = O.mmfd_step(spec, cur, prev), cur
+    s.step(steps)
+    _say("C3-2D plan", s.launch_plan(), "steps", steps)
+    assert np.array_equal(s.get_state(), cur)
+    assert np.array_equal(s.get_state(level=1), prev)
+    s.close()
+
+
+def _nse3(M, c, precision):
+    s = M.Solver("D3Q19", c["n"], c["dx"], precision, "mmfd")
+    s.set_equation("nse", rho0=c["rho0"])
+    sl = 1.0 / (c["nu"] / (c["dt"] * D0 * (c["dx"] / c["dt"]) ** 2) + 0.5)
+    a, ah = M.mfd_preset("trt", sl)
+    s.set_scheme("three_level", a, ah, dt=c["dt"])
+    spec = dict(lattice="D3Q19", eq="nse", n=c["n"], dx=c["dx"], dt=c["dt"], rho0=c["rho0"],
+                a=a, ah=ah, levels=3)
+    return s, spec
+
+
+@pytest.mark.timeout(900)
+def test_c3_3d_96_full_1000_steps(M):
+    c = I.tgv_3d(n=96)
+    x = c["state0"]
+    s, spec = _nse3(M, c, "fp64")
+    s.set_state(x)
+    s.step(1000)
+    got, gotp = s.get_state(), s.get_state(level=1)
+    s.close()
+    cur, prev = x, x
+    for k in range(1000):
+        cur, prev = O.mmfd_step(spec, cur, prev), cur
+        if k % 250 == 249:
+            _say("  oracle 96^3 step", k + 1)
+    assert np.array_equal(got, cur)
+    assert np.array_equal(gotp, prev)
+    s32, _ = _nse3(M, c, "fp32")
+    s32.set_state(x.astype(np.float32))
+    s32.step(1000)
+    err = _rel(s32.get_state().astype(np.float64), cur)
+    s32.close()
+    assert err <= 1e-5, err
+
+
+@pytest.mark.timeout(900)
+def test_c3_3d_512_prefix(M):
+    try:
+        import psutil
+        avail = psutil.virtual_memory().available
+    except ImportError:
+        avail = 0
+    if avail < 90 * 2 ** 30:
+        pytest.skip("the 512^3 oracle prefix needs about 60 GB of free host memory (%.0f GB free)"
+                    % (avail / 2 ** 30))
+    c = I.tgv_3d(n=512, dtype=np.float32)
+    x = c["state0"].astype(np.float64)
+    del c["state0"]
+    s, spec = _nse3(M, c, "fp64")
+    s.set_state(x)
+    s.step(2)
+    got = s.get_state()
+    s.close()
+    _say("512^3: oracle two steps")
+    cur, prev = x, x
+    for _ in range(2):
+        cur, prev = O.mmfd_step(spec, cur, prev), cur
+    assert np.array_equal(got, cur)
+
+
+@pytest.mark.timeout(600)
+def test_c4_full_runs_fp32_and_oracle(M):
+    insts = I.c4_batch(256, seed=4)
+
+    def make(c, prec):
+        s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        s.set_equation("burgers")
+        sp = 2 * c["nu"] * c["dt"] / (D0 * c["dx"] ** 2)
+        a = M.mfd_preset("two_level", sp)[0]
+        s.set_scheme("two_level", a, dt=c["dt"])
+        s.set_state(c["phi0"].astype(s.dtype))
+        return s, a
+
+    s32 = [make(c, "fp32")[0] for c in insts]
+    b = M.Batch()
+    for s, c in zip(s32, insts):
+        b.add(s, c["steps"])
+    b.autotune()
+    for s, c in zip(s32, insts):
+        s.set_state(c["phi0"].astype(np.float32))
+    b.run()
+    b.wait()
+    worst = 0.0
+    small = sorted(range(len(insts)), key=lambda i: insts[i]["n"][0])[:3]
+    for i, (s, c) in enumerate(zip(s32, insts)):
+        f64, a = make(c, "fp64")
+        f64.set_blocking(1)
+        f64.step(c["steps"])
+        y = f64.get_state()
+        f64.close()
+        x = s.get_state().astype(np.float64)
+        e0 = float(np.linalg.norm(x - y) / np.linalg.norm(c["phi0"]))
+        worst = max(worst, e0)
+        assert e0 <= 1e-5, (i, c["n"], c["steps"], e0)
+        if i in small:
+            spec = dict(lattice="D2Q9", eq="burgers", n=c["n"], dx=c["dx"], dt=c["dt"], a=a)
+            want = c["phi0"]
+            for _ in range(c["steps"]):
+                want = O.mmfd_step(spec, want)
+            assert np.array_equal(y, want), (i, c["n"], c["steps"])
+    _say("C4 worst FP32 error over the initial norm", worst)
+    b.close()
+    for s in s32:
+        s.close()

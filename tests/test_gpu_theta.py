@@ -122,3 +122,68 @@ def test_theta_tolerance_argument_checks(M):
     with pytest.raises(M.MfdError):
         e.set_theta_tolerance(1e-6)
     e.close()
+
+
+BURG = [
+    dict(name="burgers-d2q9", lattice="D2Q9", n=(203, 150)),
+    dict(name="burgers-d1q3", lattice="D1Q3", n=(500,)),
+    dict(name="burgers-d3q19", lattice="D3Q19", n=(14, 11, 9)),
+]
+
+
+def _burgers_theta(c, dt_factor=4.0, nu=5e-3, theta=0.5, cap=64):
+    dx = 1.0 / c["n"][0]
+    dt = dt_factor * 0.3 * dx * dx / nu
+    s = 2 * nu * dt / ((1.0 / 3.0) * dx * dx)
+    a = ((s + 1) / 2, 1 - s, (s - 1) / 2)
+    return dict(c, eq="burgers", a=a, kind="theta", theta=theta, theta_iters=cap, dx=dx, dt=dt)
+
+
+@pytest.mark.parametrize("case", BURG, ids=lambda c: c["name"])
+@pytest.mark.parametrize("tol,chunk", [(1e-12, 4), (0.0, 6)], ids=["tol", "fixed"])
+def test_theta_burgers_fp64_matches_oracle(M, case, tol, chunk):
+    """Burgers' equation with the theta scheme (Picard iteration with the
+    Jacobi splitting of the linear even part): every state bit-exact with the
+    oracle's iteration, sweep counts equal; tol = 0 runs theta_iters sweeps."""
+    from oracle import implicit as IM
+
+    cap = 64 if tol > 0 else chunk
+    c = _burgers_theta(case, cap=cap)
+    spec = oracle_spec(c)
+    rng = np.random.default_rng(12)
+    phi = 0.1 * rng.uniform(-1, 1, int(np.prod(c["n"])))
+    want, sweeps = phi, []
+    for _ in range(3):
+        want, k, _ = IM.theta_picard_solve(spec, want, tol if tol > 0 else 1e-300,
+                                           chunk if tol > 0 else cap, cap)
+        sweeps.append(k)
+    s = make_solver(M, c, "fp64")
+    if tol > 0:
+        s.set_theta_tolerance(tol, chunk)
+    s.set_state(phi)
+    s.step(3)
+    got = s.get_state()
+    st = s.theta_stats()
+    s.close()
+    assert np.array_equal(got, want)
+    if tol > 0:
+        assert st["total_sweeps"] == sum(sweeps) and st["unconverged"] == 0
+
+
+def test_theta_burgers_fp32_within_1e5(M):
+    from oracle import implicit as IM
+
+    c = _burgers_theta(BURG[0])
+    spec = oracle_spec(c)
+    rng = np.random.default_rng(13)
+    phi = (0.1 * rng.uniform(-1, 1, int(np.prod(c["n"])))).astype(np.float32)
+    want = phi.astype(np.float64)
+    for _ in range(4):
+        want, _, _ = IM.theta_picard_solve(spec, want, 1e-12, 4, 64)
+    s = make_solver(M, c, "fp32")
+    s.set_theta_tolerance(1e-6, 4)
+    s.set_state(phi)
+    s.step(4)
+    got = s.get_state().astype(np.float64)
+    s.close()
+    assert rel_l2(got, want) < 1e-5
