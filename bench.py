@@ -219,6 +219,24 @@ def bench_variants(M, torch, cfg, stream, N):
         out["%s_%s" % (form, prec)] = r
         finals[(prec, form)] = sv.get_state().astype(np.float64)
         sv.close()
+    # MesoFD with its populations written at every step (one step per call,
+    # so every call stores the b = 9 populations the caller can read back):
+    # the cost of streaming the population layout through HBM
+    for prec, sz in (("fp32", 4), ("fp64", 8)):
+        sv = c2_solver(M, cfg, prec, "mesofd", stream)
+        sv.set_blocking(1)
+        nstep = 300
+
+        def run():
+            for _ in range(nstep):
+                sv.step(1)
+        run()
+        ms = timed(torch, run)
+        g = N * nstep / (ms * 1e-3) / 1e9
+        out["mesofd_populations_every_step_" + prec] = dict(
+            glups=round(g, 2), steps=nstep, populations_written_gbs=round(g * 9 * sz, 1),
+            pop_form_bytes_per_lup=2 * 9 * sz, frac_hbm_pop_form=round(g * 18 * sz / HBM_PEAK_GBS, 4))
+        sv.close()
     s32 = c2_solver(M, cfg, "fp32", "mmfd", stream)
     s32.step(TIME_STEPS)
     f32 = s32.get_state().astype(np.float64)

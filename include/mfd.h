@@ -320,6 +320,17 @@ int mfd_synchronize(mfd_solver *s);
  * Returns MFD_E_UNSTABLE if a sum or the residual is not finite. */
 int mfd_reduce(mfd_solver *s, double sums[4], double *residual);
 
+/* Growth check of a solve (the moment sums of the reductions above are the
+ * conserved quantities of Sec. 2; a blow-up of an unstable scheme makes them
+ * overflow to Inf or NaN): with every > 0, mfd_step runs its steps in runs of
+ * `every` and after each run performs the reductions of mfd_reduce, returning
+ * MFD_E_UNSTABLE at the first non-finite sum or residual (the state then
+ * holds the level that failed the check; the steps after it are not taken).
+ * Each check synchronises the solver's stream.  The results of the steps are
+ * those without the check, bit for bit.  every = 0 (the default) turns it
+ * off; every < 0 is MFD_E_ARG. */
+int mfd_set_check_interval(mfd_solver *s, int64_t every);
+
 /* Autotune the launch plan (tile shape, temporal-blocking depth) of this
  * solver's configuration by timing candidates on its own state (restored
  * afterwards); the choice is cached per (lattice, equation, form, precision,

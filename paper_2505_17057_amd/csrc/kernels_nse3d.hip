@@ -12,8 +12,9 @@
 // first 2 (TX + TY) + 4 threads, one halo node) and updates that same
 // interior node, so the moments of its node at t (and t - dt) stay in its
 // registers.  The moments of the plane after next are loaded into registers
-// while a plane is updated.  The node update is the single-step kernel's
-// (mmfd_node on pair parts), so results equal it value for value.
+// while a plane is updated.  The node update is mmfd_node on pair parts in
+// binary64 (results equal the oracle's value for value) and the binary32 pair
+// form of nse32_parts / nse32_node in binary32.
 #include "mmfd_node.h"
 
 namespace mfd {
@@ -50,6 +51,8 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
   constexpr int HX = TX + 2, HY = TY + 2, NT = TX * TY;
   constexpr int NHALO = 2 * HX + 2 * TY;
   static_assert(NHALO <= NT, "one halo node per thread at most");
+  // binary32: the unweighted pair form of nse32_parts / nse32_node
+  constexpr bool kF32 = std::is_same<T, float>::value;
   extern __shared__ unsigned char smem_nse3d[];
   // zb[3][2 kZP][HY][HX] then ib[2 kIP][HY][HX]
   T *const zb = reinterpret_cast<T *>(smem_nse3d);
@@ -111,23 +114,42 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (s == 0 || has_halo) {
-        T rec[NR];
-        make_record<L3, kNSE>(m[s], rec, kc);
-        static_for<L3::P>([&](auto PI) {
-          constexpr int P = decltype(PI)::value;
-          constexpr int J = L3::PR[P];
-          if constexpr (zpair(P)) {
-            if (zpairs) {
-              zat(slot, 2 * zslot(P), hy[s], hx[s]) = fplus<L3, kNSE, J>(rec, kc);
-              zat(slot, 2 * zslot(P) + 1, hy[s], hx[s]) = fminus<L3, kNSE, J>(rec, kc);
+        if constexpr (kF32) {
+          T g[2 * L3::P];
+          nse32_parts<L3>(m[s], g, kc);
+          static_for<L3::P>([&](auto PI) {
+            constexpr int P = decltype(PI)::value;
+            if constexpr (zpair(P)) {
+              if (zpairs) {
+                zat(slot, 2 * zslot(P), hy[s], hx[s]) = g[2 * P];
+                zat(slot, 2 * zslot(P) + 1, hy[s], hx[s]) = g[2 * P + 1];
+              }
+            } else {
+              if (!zpairs) {
+                iat(2 * islot(P), hy[s], hx[s]) = g[2 * P];
+                iat(2 * islot(P) + 1, hy[s], hx[s]) = g[2 * P + 1];
+              }
             }
-          } else {
-            if (!zpairs) {
-              iat(2 * islot(P), hy[s], hx[s]) = fplus<L3, kNSE, J>(rec, kc);
-              iat(2 * islot(P) + 1, hy[s], hx[s]) = fminus<L3, kNSE, J>(rec, kc);
+          });
+        } else {
+          T rec[NR];
+          make_record<L3, kNSE>(m[s], rec, kc);
+          static_for<L3::P>([&](auto PI) {
+            constexpr int P = decltype(PI)::value;
+            constexpr int J = L3::PR[P];
+            if constexpr (zpair(P)) {
+              if (zpairs) {
+                zat(slot, 2 * zslot(P), hy[s], hx[s]) = fplus<L3, kNSE, J>(rec, kc);
+                zat(slot, 2 * zslot(P) + 1, hy[s], hx[s]) = fminus<L3, kNSE, J>(rec, kc);
+              }
+            } else {
+              if (!zpairs) {
+                iat(2 * islot(P), hy[s], hx[s]) = fplus<L3, kNSE, J>(rec, kc);
+                iat(2 * islot(P) + 1, hy[s], hx[s]) = fminus<L3, kNSE, J>(rec, kc);
+              }
             }
-          }
-        });
+          });
+        }
       }
     }
   };
@@ -159,15 +181,32 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
     if (z + 1 < z1) load(z + 2, mn, pn);
     __syncthreads();
     if (upd) {
-      auto slot = [&](int dz) { return dz == 0 ? s0 : (dz > 0 ? sp : sm); };
+      // the node's place in each ring slot and in the in-plane parts; every
+      // access below is one of these plus a compile-time offset
+      const int ctr = hy[0] * HX + hx[0];
+      const T *const zpm = zb + sm * 2 * kZP * HY * HX + ctr;
+      const T *const zp0 = zb + s0 * 2 * kZP * HY * HX + ctr;
+      const T *const zpp = zb + sp * 2 * kZP * HY * HX + ctr;
+      const T *const ipc = ib + ctr;
       auto at = [&](int q, int dz, int dy, int dx) {
         const int p = q >> 1, h = q & 1;
-        const int y = hy[0] + dy, x = hx[0] + dx;
-        return zpair(p) ? zat(slot(dz), 2 * zslot(p) + h, y, x) : iat(2 * islot(p) + h, y, x);
+        const int off = dy * HX + dx;
+        if (zpair(p)) {
+          const T *b = dz == 0 ? zp0 : (dz > 0 ? zpp : zpm);
+          return b[(2 * zslot(p) + h) * HY * HX + off];
+        }
+        return ipc[(2 * islot(p) + h) * HY * HX + off];
       };
       auto ath = [&](int, int, int, int) { return T(0); };
       T oc[NF];
-      mmfd_node<L3, kNSE, THREE, false, T, false, true>(at, ath, cc, pcc, oc, kc);
+      if constexpr (kF32) {
+        T g0[2 * L3::P];
+#pragma unroll
+        for (int q = 0; q < 2 * L3::P; ++q) g0[q] = at(q, 0, 0, 0);
+        nse32_node<L3, THREE>(at, g0, cc, pcc, oc, kc);
+      } else {
+        mmfd_node<L3, kNSE, THREE, false, T, false, true>(at, ath, cc, pcc, oc, kc);
+      }
       const int64_t gi = (int64_t)z * plane + (int64_t)gyi * nx + gxi;
 #pragma unroll
       for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];

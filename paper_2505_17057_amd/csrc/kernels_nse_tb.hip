@@ -49,7 +49,11 @@ __device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *_
     else return i < 0 ? i + n : (i >= n ? i - n : i);
   };
 
+  // binary32: the unweighted pair form of nse32_parts / nse32_node; each
+  // thread keeps its own nodes' parts of the step in registers
+  constexpr bool F32 = std::is_same<T, float>::value;
   T cm[R][NF], pm[R][NF];
+  T own[F32 ? R : 1][NPF];
   {
     const int gx = wrap(x0 + xx, nx);
 #pragma unroll
@@ -71,9 +75,16 @@ __device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *_
       for (int r = 0; r < R; ++r) {
         const int y = yr + r;
         if (y >= t - 1 && y < H - t + 1) {
-          T rec[NR], f[NPF];
-          make_record<L, kNSE>(cm[r], rec, kc);
-          pair_parts<L, kNSE>(rec, f, kc);
+          T f[NPF];
+          if constexpr (F32) {
+            nse32_parts<L>(cm[r], f, kc);
+#pragma unroll
+            for (int q = 0; q < NPF; ++q) own[r][q] = f[q];
+          } else {
+            T rec[NR];
+            make_record<L, kNSE>(cm[r], rec, kc);
+            pair_parts<L, kNSE>(rec, f, kc);
+          }
 #pragma unroll
           for (int q = 0; q < NPF; ++q) pf[(q * H + y) * W + xx] = f[q];
         }
@@ -86,10 +97,15 @@ __device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *_
       for (int r = 0; r < R; ++r) {
         const int y = yr + r;
         if (y >= t && y < H - t) {
-          auto at = [&](int q, int, int dy, int dx) { return pf[(q * H + y + dy) * W + xx + dx]; };
-          auto ath = [&](int, int, int, int) { return T(0); };
           T oc[NF];
-          mmfd_node<L, kNSE, THREE, false, T, false, true>(at, ath, cm[r], pm[r], oc, kc);
+          if constexpr (F32) {
+            auto at = [&](int q, int, int dy, int dx) { return pf[(q * H + y + dy) * W + xx + dx]; };
+            nse32_node<L, THREE>(at, own[r], cm[r], pm[r], oc, kc);
+          } else {
+            auto at = [&](int q, int, int dy, int dx) { return pf[(q * H + y + dy) * W + xx + dx]; };
+            auto ath = [&](int, int, int, int) { return T(0); };
+            mmfd_node<L, kNSE, THREE, false, T, false, true>(at, ath, cm[r], pm[r], oc, kc);
+          }
 #pragma unroll
           for (int q = 0; q < NF; ++q) {
             pm[r][q] = cm[r][q];

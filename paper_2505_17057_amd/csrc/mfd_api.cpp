@@ -517,7 +517,49 @@ int Solver::step(int64_t nsteps) {
   if (!state_set) return fail(MFD_E_ORDER, "state not set");
   if (dirichlet && !bnd_set) return fail(MFD_E_ORDER, "Dirichlet values not set (mfd_set_boundary)");
   if (nsteps == 0) return MFD_OK;
-  return grid.precision == MFD_FP64 ? step_t<double>(nsteps) : step_t<float>(nsteps);
+  if (check_every <= 0)
+    return grid.precision == MFD_FP64 ? step_t<double>(nsteps) : step_t<float>(nsteps);
+  // the steps in runs of check_every, each followed by the FP64 reduction;
+  // a run ends as it would inside one call (the blocked kernels give the
+  // single-step values), so the check changes no result
+  for (int64_t done = 0; done < nsteps;) {
+    const int64_t k = std::min(check_every, nsteps - done);
+    int rc = grid.precision == MFD_FP64 ? step_t<double>(k) : step_t<float>(k);
+    if (rc) return rc;
+    done += k;
+    rc = reduce(nullptr, nullptr);
+    if (rc) return rc;
+  }
+  return MFD_OK;
+}
+
+int Solver::reduce(double sums[4], double *residual) {
+  if (sticky) return fail(MFD_E_HIP, "solver is in a failed HIP state");
+  if (!state_set) return fail(MFD_E_ORDER, "state not set");
+  double *part = (double *)buf[kRedBuf];
+  double *out = part + kReduceBlocks * 8;
+  const bool have_prev = steps_done > 0;
+  hipError_t e;
+  if (grid.precision == MFD_FP64) {
+    const double *cur = (const double *)buf[ic];
+    const double *prev = have_prev ? (const double *)buf[ip] : nullptr;
+    e = launch_reduce<double>(cur, prev, (int)nf(), G.N, part, out, stream);
+  } else {
+    const float *cur = (const float *)buf[ic];
+    const float *prev = have_prev ? (const float *)buf[ip] : nullptr;
+    e = launch_reduce<float>(cur, prev, (int)nf(), G.N, part, out, stream);
+  }
+  if (e != hipSuccess) return hip(e, "reduce launch");
+  double host[8];
+  int rc = copy_out(host, out, sizeof(host), 0);
+  if (rc) return rc;
+  bool finite = std::isfinite(host[4]);
+  for (int f = 0; f < nf(); ++f) finite = finite && std::isfinite(host[f]);
+  if (!finite) return fail(MFD_E_UNSTABLE, "non-finite moment sum or residual");
+  if (sums)
+    for (int f = 0; f < 4; ++f) sums[f] = f < nf() ? host[f] : 0.0;
+  if (residual) *residual = std::sqrt(host[4]) / (double)prev_gap;
+  return MFD_OK;
 }
 
 }  // namespace mfd
@@ -696,8 +738,9 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
       if (!std::isfinite(x)) return s->fail(MFD_E_ARG, "non-finite coefficient");
   }
   if (kind == MFD_THREE_LEVEL && s->grid.precision == MFD_FP32) {
-    // the binary32 kernels form the base as phi - Ah0 (phi - phi^(n-1)) in
-    // binary64, which is A0 phi + Ah0 phi^(n-1) only when A0 + Ah0 = 1
+    // the binary32 kernels form the base as phi - Ah0 (phi - phi^(n-1))
+    // (in binary64, or with one fused multiply-add in the binary32 NSE pair
+    // form), which is A0 phi + Ah0 phi^(n-1) only when A0 + Ah0 = 1
     // (A00 = 1 of Eq. (4-2-00a)); the momentum set likewise
     const double *sets[2][2] = {{a, ah}, {ab ? ab : a, abh ? abh : ah}};
     for (auto &st : sets) {
@@ -863,32 +906,14 @@ extern "C" int mfd_synchronize(mfd_solver *h) {
 
 extern "C" int mfd_reduce(mfd_solver *h, double sums[4], double *residual) {
   SOLVER_OR_ARG(h);
+  return reinterpret_cast<Solver *>(h)->reduce(sums, residual);
+}
+
+extern "C" int mfd_set_check_interval(mfd_solver *h, int64_t every) {
+  SOLVER_OR_ARG(h);
   Solver *s = reinterpret_cast<Solver *>(h);
-  if (s->sticky) return s->fail(MFD_E_HIP, "solver is in a failed HIP state");
-  if (!s->state_set) return s->fail(MFD_E_ORDER, "state not set");
-  double *part = (double *)s->buf[Solver::kRedBuf];
-  double *out = part + kReduceBlocks * 8;
-  const bool have_prev = s->steps_done > 0;
-  hipError_t e;
-  if (s->grid.precision == MFD_FP64) {
-    const double *cur = (const double *)s->buf[s->ic];
-    const double *prev = have_prev ? (const double *)s->buf[s->ip] : nullptr;
-    e = launch_reduce<double>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
-  } else {
-    const float *cur = (const float *)s->buf[s->ic];
-    const float *prev = have_prev ? (const float *)s->buf[s->ip] : nullptr;
-    e = launch_reduce<float>(cur, prev, (int)s->nf(), s->G.N, part, out, s->stream);
-  }
-  if (e != hipSuccess) return s->hip(e, "reduce launch");
-  double host[8];
-  int rc = s->copy_out(host, out, sizeof(host), 0);
-  if (rc) return rc;
-  bool finite = std::isfinite(host[4]);
-  for (int f = 0; f < s->nf(); ++f) finite = finite && std::isfinite(host[f]);
-  if (!finite) return s->fail(MFD_E_UNSTABLE, "non-finite moment sum or residual");
-  if (sums)
-    for (int f = 0; f < 4; ++f) sums[f] = f < s->nf() ? host[f] : 0.0;
-  if (residual) *residual = std::sqrt(host[4]) / (double)s->prev_gap;
+  if (every < 0) return s->fail(MFD_E_ARG, "check interval < 0");
+  s->check_every = every;
   return MFD_OK;
 }
 

@@ -147,6 +147,141 @@ __device__ __forceinline__ void pair_parts(const T *r, T *out, const KC<T> &kc) 
   });
 }
 
+// ------------------------------------------------ binary32 NSE pair form
+// The binary32 NSE steps (2D, no older-level stencil) use unweighted pair
+// parts, G+_p = (rho - rho0) + Q~_p : C and G-_p = e_p . j, so that
+// F+_p = w_p G+_p and F-_p = (w_p / d0) G-_p; the weights are folded into
+// the per-pair constants kc.nw[p] = {a+ w, a- w / d0, abar+ w / d0, abar- w}.
+// Each difference of Eq. (2-2-1) is formed from the differences to the
+// node's own part, dP = G(x + e_p) - G(x) and dM = G(x - e_p) - G(x)
+// (second difference dP + dM, first difference dP - dM): neighbouring values
+// differ in their low bits only, so these subtractions are exact or nearly
+// so.  The time-level base A0 phi + Ah0 phi_hat is formed as
+// phi + (acc - Ah0 (phi - phi_hat)) (A0 + Ah0 = 1), rounded once at the
+// scale of phi.
+// Every kernel that takes such a step uses these two functions, so the
+// single-step, blocked and batched launches agree bit for bit.
+template <class L>
+__device__ __forceinline__ void nse32_parts(const float *m, float *g, const KC<float> &kc) {
+  constexpr int D = L::D;
+  static_assert(D >= 2, "2D and 3D lattices");
+  const float rinv = kc.he_luo ? kc.rinv0 : __builtin_amdgcn_rcpf(kc.rho0 + m[0]);
+  float u[D], cd[D], co[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) u[a] = m[1 + a] * rinv;
+#pragma unroll
+  for (int a = 0; a < D; ++a) cd[a] = m[1 + a] * u[a];
+  co[0] = m[1] * u[1];
+  co[1] = D == 3 ? m[1] * u[D - 1] : 0.f;
+  co[2] = D == 3 ? m[2] * u[D - 1] : 0.f;
+  static_for<L::P>([&](auto PI) {
+    constexpr int P = decltype(PI)::value;
+    constexpr int J = L::PR[P];
+    float gp = __builtin_fmaf(kc.qd[J][0], cd[0], m[0]);
+#pragma unroll
+    for (int a = 1; a < D; ++a) gp = __builtin_fmaf(kc.qd[J][a], cd[a], gp);
+    if constexpr (L::E[J][0] * L::E[J][1] != 0) gp = __builtin_fmaf(kc.qo[J][0], co[0], gp);
+    if constexpr (D == 3) {
+      if constexpr (L::E[J][0] * L::E[J][2] != 0) gp = __builtin_fmaf(kc.qo[J][1], co[1], gp);
+      if constexpr (L::E[J][1] * L::E[J][2] != 0) gp = __builtin_fmaf(kc.qo[J][2], co[2], gp);
+    }
+    // e_J . j, from the first nonzero component on (no addition to zero)
+    float gm = 0.f;
+    bool started = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (L::E[J][a] == 0) continue;
+      const float v = L::E[J][a] > 0 ? m[1 + a] : -m[1 + a];
+      gm = started ? gm + v : v;
+      started = true;
+    }
+    g[2 * P] = gp;
+    g[2 * P + 1] = gm;
+  });
+}
+
+// first pair (lattice pair order) whose direction has a nonzero component a
+template <class L>
+__device__ __host__ constexpr int nse32_first_pair(int a) {
+  for (int p = 0; p < L::P; ++p)
+    if (L::E[L::PR[p]][a] != 0) return p;
+  return L::P;
+}
+template <class L, int P>
+__device__ __host__ constexpr int nse32_ncomp() {
+  int k = 0;
+  for (int a = 0; a < L::D; ++a) k += L::E[L::PR[P]][a] != 0 ? 1 : 0;
+  return k;
+}
+
+// `at(q, dz, dy, dx)` returns part q (2p: G+_p, 2p + 1: G-_p) of the node
+// at that offset; g0 the node's own parts; cur_c / prev_c its moments at t
+// and t - dt.
+template <class L, bool THREE, class At>
+__device__ __forceinline__ void nse32_node(const At &at, const float *g0, const float *cur_c,
+                                           const float *prev_c, float *out_c,
+                                           const KC<float> &kc) {
+  constexpr int D = L::D;
+  float acc = 0.f, mo[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mo[a] = 0.f;
+  static_for<L::P>([&](auto PI) {
+    constexpr int P = decltype(PI)::value;
+    constexpr int J = L::PR[P];
+    constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+    const float cP = kc.nw[P][0], cM = kc.nw[P][1], bP = kc.nw[P][2], bM = kc.nw[P][3];
+    const float pP = at(2 * P, ez, ey, ex) - g0[2 * P];  // G+ differences
+    const float pM = at(2 * P, -ez, -ey, -ex) - g0[2 * P];
+    const float mP = at(2 * P + 1, ez, ey, ex) - g0[2 * P + 1];  // G- differences
+    const float mM = at(2 * P + 1, -ez, -ey, -ex) - g0[2 * P + 1];
+    // rho: a+ D2 F+ + a- D1 F-
+    if constexpr (P == 0) acc = cP * pP;
+    else acc = __builtin_fmaf(cP, pP, acc);
+    acc = __builtin_fmaf(cP, pM, acc);
+    acc = __builtin_fmaf(cM, mP, acc);
+    acc = __builtin_fmaf(-cM, mM, acc);
+    // j: e_p (abar+ D2 F- + abar- D1 F+)
+    if constexpr (nse32_ncomp<L, P>() == 1) {
+      constexpr int a = ex != 0 ? 0 : (ey != 0 ? 1 : 2);
+      constexpr int sg = L::E[J][a];
+      const float sP = sg > 0 ? bP : -bP, sM = sg > 0 ? bM : -bM;
+      if constexpr (nse32_first_pair<L>(a) == P) mo[a] = sM * pP;
+      else mo[a] = __builtin_fmaf(sM, pP, mo[a]);
+      mo[a] = __builtin_fmaf(-sM, pM, mo[a]);
+      mo[a] = __builtin_fmaf(sP, mP, mo[a]);
+      mo[a] = __builtin_fmaf(sP, mM, mo[a]);
+    } else {
+      float b = bM * pP;
+      b = __builtin_fmaf(-bM, pM, b);
+      b = __builtin_fmaf(bP, mP, b);
+      b = __builtin_fmaf(bP, mM, b);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (L::E[J][a] == 0) continue;
+        const bool pos = L::E[J][a] > 0;
+        if (nse32_first_pair<L>(a) == P) mo[a] = pos ? b : -b;
+        else mo[a] = pos ? mo[a] + b : mo[a] - b;
+      }
+    }
+  });
+#pragma unroll
+  for (int f = 0; f <= D; ++f) {
+    const float c = cur_c[f], d = f == 0 ? acc : mo[f - 1];
+    if constexpr (THREE) {
+      // c + (d - Ah0 (c - c_hat)): the bracket is of the size of one step's
+      // change, so its rounding is far below an ulp of c, and the new value
+      // is rounded once at the scale of c (as A0 c + Ah0 c_hat + d in
+      // binary64 would be).  Rounding c - Ah0 (c - c_hat) first would add a
+      // second rounding at that scale whose sign follows the slowly varying
+      // change, i.e. a drift that grows linearly over a long run.
+      const float t = __builtin_fmaf(f == 0 ? -kc.Ah0t : -kc.Abh0t, c - prev_c[f], d);
+      out_c[f] = c + t;
+    } else {
+      out_c[f] = __builtin_fmaf(f == 0 ? kc.A0t : kc.Ab0t, c, d);
+    }
+  }
+}
+
 // One TX x TY tile of a 2D grid for the NSE, in three parts so that a
 // persistent kernel can overlap the next tile's loads with this tile's work:
 //   load   the moments of the tile and a one-node halo (both levels when the
@@ -170,6 +305,8 @@ struct PfTile {
   static constexpr int HX = TX + 2, HY = TY + 2;
   static constexpr int KH = (HX * HY + 255) / 256;  // halo-tile nodes per thread
   static constexpr int KI = (TX * TY + 255) / 256;  // interior nodes per thread
+  // binary32 without an older-level stencil: the binary32 pair form above
+  static constexpr bool kNse32 = std::is_same<T, float>::value && !THREE_ST;
   struct Lds {
     T pf[NPF][HY][HX];
     T hpf[THREE_ST ? NPF : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
@@ -224,8 +361,12 @@ struct PfTile {
 #pragma unroll
           for (int q = 0; q < NF; ++q) s.mc[q][ly - 1][lx - 1] = g.mv[k][q];
         }
-        make_record<L, kNSE>(g.mv[k], r, kc);
-        pair_parts<L, kNSE>(r, f, kc);
+        if constexpr (kNse32) {
+          nse32_parts<L>(g.mv[k], f, kc);
+        } else {
+          make_record<L, kNSE>(g.mv[k], r, kc);
+          pair_parts<L, kNSE>(r, f, kc);
+        }
 #pragma unroll
         for (int q = 0; q < NPF; ++q) s.pf[q][ly][lx] = f[q];
         if constexpr (THREE_ST) {
@@ -262,7 +403,15 @@ struct PfTile {
         cc[q] = s.mc[q][ly][lx];
         pc[q] = THREE ? pcv[k][q] : T(0);
       }
-      mmfd_node<L, kNSE, THREE, THREE_ST, T, false, true>(at, ath, cc, pc, oc, kc);
+      if constexpr (kNse32) {
+        T g0[NPF];
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) g0[q] = s.pf[q][cy][cx];
+        auto at2 = [&](int q, int, int dy, int dx) { return s.pf[q][cy + dy][cx + dx]; };
+        nse32_node<L, THREE>(at2, g0, cc, pc, oc, kc);
+      } else {
+        mmfd_node<L, kNSE, THREE, THREE_ST, T, false, true>(at, ath, cc, pc, oc, kc);
+      }
 #pragma unroll
       for (int q = 0; q < NF; ++q) out[q * N + gi] = oc[q];
     }

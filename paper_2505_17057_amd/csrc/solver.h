@@ -52,6 +52,7 @@ struct Solver {
   int64_t th_total = 0, th_steps = 0;  // host-checked solves (unfused path)
   int th_max = 0, th_unconv = 0;
   int prev_gap = 1;  // steps between the current and the held previous level
+  int64_t check_every = 0;  // finiteness check every this many steps (0: off)
   int tb = 0;           // temporal-blocking depth requested (0 = automatic)
   TbPlan tuned{0, 0};   // plan chosen by the autotuner (tb = 0: not tuned)
   // Dirichlet boundary (2D): compact binary64 values G_b on the device,
@@ -80,6 +81,7 @@ struct Solver {
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
   int copy_out(void *dst, const void *src, int64_t bytes, int on_device);
   int step(int64_t nsteps);
+  int reduce(double sums[4], double *residual);
   bool source_supported() const;
   TbPlan effective_plan() const;
   bool plan_supported(const TbPlan &p) const;  // the blocked kernel of this form can run p

@@ -100,6 +100,7 @@ _SIGS = {
     "mfd_step": ([_H, C.c_int64], C.c_int),
     "mfd_synchronize": ([_H], C.c_int),
     "mfd_reduce": ([_H, _PD, _PD], C.c_int),
+    "mfd_set_check_interval": ([_H, C.c_int64], C.c_int),
     "mfd_autotune": ([_H, C.POINTER(C.c_int32)], C.c_int),
     "mfd_set_blocking": ([_H, C.c_int32], C.c_int),
     "mfd_set_plan": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
@@ -331,6 +332,9 @@ class Solver:
         res = C.c_double()
         self.check(lib.mfd_reduce(self.h, sums, C.byref(res)), "mfd_reduce")
         return list(sums), res.value
+
+    def set_check_interval(self, every):
+        return self.check(lib.mfd_set_check_interval(self.h, int(every)), "mfd_set_check_interval")
 
     def set_blocking(self, depth):
         return self.check(lib.mfd_set_blocking(self.h, int(depth)), "mfd_set_blocking")

@@ -6,6 +6,8 @@
 * Zero steps change nothing; empty batches and zero-step batch members run;
   a zero-step request comes back unchanged from the server.
 * Calls out of order fail with MFD_E_ORDER, bad sizes with MFD_E_ARG.
+* The growth check (mfd_set_check_interval) changes no result and stops a
+  solve whose sums are not finite with MFD_E_UNSTABLE.
 """
 import numpy as np
 import pytest
@@ -174,3 +176,51 @@ def test_level_ptr_reports_current_storage(M, case):
         s.level_ptr(0, nf)
     t.close()
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [c for c in CASES if c["name"] in ("lcde-2l-blocked", "nse-trt",
+                                                                      "mesofd-lcde")],
+                         ids=lambda c: c["name"])
+def test_check_interval_changes_nothing(M, case, precision):
+    """Steps taken in runs with the growth check between them equal the same
+    steps in one call, bit for bit."""
+    print("case", case["name"], precision, flush=True)
+    rng = np.random.default_rng(23)
+    dt = np.float64 if precision == "fp64" else np.float32
+    cur, prev = rand_state(case, rng).astype(dt), rand_state(case, rng).astype(dt)
+    three = case.get("kind") == "three_level"
+    outs = []
+    for every in (0, 7):
+        s = _new(M, case, precision)
+        s.set_check_interval(every)
+        s.set_state(cur)
+        if three:
+            s.set_state(prev, level=1)
+        s.step(30)
+        outs.append((s.get_state(), s.get_state(level=1)))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_check_interval_stops_a_blow_up(M):
+    """A NaN in the state (the stand-in for an overflowing unstable run)
+    stops the solve at the first check with MFD_E_UNSTABLE; without the
+    check the same call returns success."""
+    case = CASES[0]
+    rng = np.random.default_rng(24)
+    st = rand_state(case, rng)
+    st[st.size // 2] = np.nan
+    s = _new(M, case, "fp64")
+    s.set_state(st)
+    s.step(5)  # no check: enqueued and done
+    s.set_check_interval(4)
+    with pytest.raises(M.MfdError) as e:
+        s.step(40)
+    assert e.value.code == M.MFD_E_UNSTABLE
+    s.close()
+    t = _new(M, case, "fp64")
+    with pytest.raises(M.MfdError) as e:
+        t.set_check_interval(-1)
+    assert e.value.code == M.MFD_E_ARG
+    t.close()

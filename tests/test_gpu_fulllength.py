@@ -7,7 +7,8 @@ times.
 * 2048^2 linear CDE: all 10 000 steps under the autotuned plan, binary64
   bit-exact with the oracle; binary32 within 1e-5 (relative L2) of it.
 * 4096^2 NSE three-level TRT: the autotuned plan and the (4, 32, 64) plan,
-  two launches and a ragged remainder, both levels binary64 bit-exact.
+  two launches and a ragged remainder, both levels binary64 bit-exact; the
+  full 20 000-step run in binary32 within 1e-5 (relative L2) of binary64.
 * 3D NSE D3Q19: all 1000 steps at 96^3 bit-exact; a two-step prefix at
   512^3 when the host has the memory for the oracle (about 60 GB).
 * 256 Burgers grids (the batched workload): binary32 batch against the
@@ -126,6 +127,39 @@ def test_c3_2d_benched_plan(M, plan):
     assert np.array_equal(s.get_state(), cur)
     assert np.array_equal(s.get_state(level=1), prev)
     s.close()
+
+
+@pytest.mark.timeout(600)
+def test_c3_2d_fp32_full_run_within_1e5(M):
+    """The headline run in binary32 (20 000 steps, the benched plan) against
+    the binary64 run of the same steps (itself bit-exact with the oracle in
+    the plans above): relative L2 of the state after the full run <= 1e-5,
+    and the mass sum within binary32 round-off of the binary64 one."""
+    c = I.tgv_2d(n=4096)
+    x = c["state0"].astype(np.float32).astype(np.float64)
+    nu = c["nu"]
+    sl = 1.0 / (nu / (c["dt"] * D0 * (c["dx"] / c["dt"]) ** 2) + 0.5)
+    a, ah = M.mfd_preset("trt", sl)
+    res, sums = {}, {}
+    for prec in ("fp64", "fp32"):
+        s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        s.set_equation("nse", rho0=c["rho0"])
+        s.set_scheme("three_level", a, ah, dt=c["dt"])
+        s.set_state(x.astype(s.dtype))
+        s.set_plan(4, 32, 64)
+        s.step(20000)
+        res[prec] = s.get_state().astype(np.float64)
+        sums[prec] = s.reduce()[0]
+        s.close()
+    N = c["n"][0] * c["n"][1]
+    for f in range(3):
+        a64, a32 = res["fp64"][f * N:(f + 1) * N], res["fp32"][f * N:(f + 1) * N]
+        _say("C3-2D FP32 field", f, "rel L2 after 20000 steps", _rel(a32, a64))
+    err = _rel(res["fp32"], res["fp64"])
+    _say("C3-2D FP32 state rel L2", err, "sums", sums)
+    assert err <= 1e-5, err
+    # mass: binary32 round-off of 16.7 M nodes over the run, not a drift
+    assert abs(sums["fp32"][0] - sums["fp64"][0]) <= 1e-3, sums
 
 
 def _nse3(M, c, precision):
