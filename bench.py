@@ -72,6 +72,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
     p.add_argument("--serve-requests", type=int, default=2200)
+    p.add_argument("--nse3d-steps", type=int, default=1000,
+                   help="time steps of the 512^3 NSE section (fewer for profiling runs)")
     p.add_argument("--plan", default="",
                    help="tb,rows,cols: run the headline with this launch plan instead of autotuning "
                         "(used to profile counters on the plan an earlier run chose)")
@@ -880,7 +882,7 @@ def main():
         extra["c1_d1q3_1024"] = bench_c1(M, torch, I, stream)
     if "nse3d" in sections:
         log("NSE 3D")
-        extra["nse_d3q19_512_three_level"] = bench_nse3d(M, torch, I, stream)
+        extra["nse_d3q19_512_three_level"] = bench_nse3d(M, torch, I, stream, steps=args.nse3d_steps)
     if "source" in sections:
         log("source")
         extra["source_example1_2048"] = bench_source(M, torch, I, stream)

@@ -67,10 +67,12 @@ def counter_by_grid(db_path, counter, kernel):
 
 def copy_factor(db_path, counter, copy_bytes):
     """Scale factor bytes / (counter KiB * 1024) from the copy dispatches of
-    `copy_bytes` bytes (those whose counter reads at least a quarter of it)."""
+    `copy_bytes` bytes: a copy moves its bytes once each way, and the counters
+    read between a quarter of them and all of them (gfx950's FETCH_SIZE reads
+    half), so larger copies of the same run (state copies) are left out."""
     vals = []
     for vs in counter_by_grid(db_path, counter, "copyBuffer").values():
-        vals += [v for v in vs if v * 1024.0 >= copy_bytes / 4]
+        vals += [v for v in vs if copy_bytes / 4 <= v * 1024.0 <= 1.25 * copy_bytes]
     if not vals:
         raise SystemExit("no copy dispatch of %d bytes found for %s" % (copy_bytes, counter))
     return copy_bytes / (statistics.fmean(vals) * 1024.0), vals
@@ -131,7 +133,13 @@ def main(argv=None):
     p.add_argument("--kernel", required=True)
     p.add_argument("--copy-bytes", type=int, required=True, help="bytes copied by one calibration copy")
     p.add_argument("--kernel-source", required=True)
-    p.add_argument("--bench-log", required=True)
+    p.add_argument("--bench-log", default="",
+                   help="log of the traced bench run (its roofline names the timed plan)")
+    p.add_argument("--plan", default="",
+                   help="TB,H,W of the timed plan, for runs whose log carries no roofline")
+    p.add_argument("--more", action="append", default=[],
+                   help="result database of a further counter run (every counter it holds for the "
+                        "kernel's timed grid is listed)")
     p.add_argument("--algorithmic-bytes-per-step", type=float, required=True,
                    help="algorithmic bytes of one time step over the grid (x time steps per launch)")
     p.add_argument("--pass-bytes", type=float, required=True,
@@ -155,7 +163,11 @@ def main(argv=None):
 
     stats = kernel_stats(a.trace)
     grids = kernel_grids(a.trace, a.kernel)
-    tb, h, w, ev_ms = bench_plan(a.bench_log)
+    if a.plan:
+        tb, h, w = (int(v) for v in a.plan.split(","))
+        ev_ms = None
+    else:
+        tb, h, w, ev_ms = bench_plan(a.bench_log)
     a.algorithmic_bytes = a.algorithmic_bytes_per_step * tb
     ff, fvals = copy_factor(a.fetch, "FETCH_SIZE", a.copy_bytes)
     wf, wvals = copy_factor(a.write, "WRITE_SIZE", a.copy_bytes)
@@ -205,6 +217,16 @@ def main(argv=None):
             valu = dict(insts=vi, waves=wv, dispatches=len(vg[main_grid]))
             rec["valu_insts_per_launch"] = round(vi)
             rec["waves_per_launch"] = round(wv) if wv else None
+    more = []
+    for db in a.more:
+        con = sqlite3.connect(db)
+        q = "select distinct counter_name from counters_collection"
+        for (cn,) in con.execute(q):
+            g = counter_by_grid(db, cn, a.kernel)
+            if main_grid in g:
+                more.append((cn, statistics.fmean(g[main_grid]), len(g[main_grid])))
+    if more:
+        rec["counters"] = {cn: v for cn, v, _ in more}
     with open(a.out_json, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -273,6 +295,13 @@ def main(argv=None):
             tf = a.flops_per_lup * a.lups_per_step * tb / dur_s / 1e12
             L.append("Algorithmic flops (%.0f per update): %.2f TFLOP/s = %.3f of the published FP32 "
                      "vector peak (157.3 TFLOP/s)." % (a.flops_per_lup, tf, tf / 157.3))
+        L.append("")
+    if more:
+        L.append("## Further counters (per dispatch of the timed plan)\n")
+        L.append("| counter | mean per dispatch | dispatches |")
+        L.append("|---|---|---|")
+        for cn, v, n in more:
+            L.append("| %s | %.1f | %d |" % (cn, v, n))
         L.append("")
     L.append("Kernel source SHA-256: `%s` (%s)." % (sha, a.kernel_source))
     with open(a.out_md, "w") as f:
