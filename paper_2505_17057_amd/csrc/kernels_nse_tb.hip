@@ -12,6 +12,11 @@
 // The store writes the interior of the last two levels (the next three-level
 // launch needs both).  Results equal the single-step kernel's value for value.
 //
+// Binary32 64 x 64 and 64 x 128 windows take a register window instead
+// (nse_window_reg): the parts stay in registers, the lanes beside share them
+// by DPP and only the first and last rows of each wavefront's run pass
+// through LDS.
+//
 // The batched kernel runs the same window for every tile of a batch group's
 // table; each instance advances min(TB, its remaining steps).
 #include "batch_kernels.h"
@@ -22,6 +27,16 @@ namespace mfd {
 namespace {
 constexpr int kNseW = 64;  // window columns (one per thread)
 constexpr int kNseR = 4;   // window rows per thread for 64-row windows (32-row: 2)
+constexpr int kNseRR = 8;  // rows per thread of the binary32 register window
+
+// value of the lane one above (lane + 1) / one below (lane - 1) in the
+// wavefront; lanes without a source read 0
+__device__ __forceinline__ float nse_from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float nse_from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
 
 __device__ __forceinline__ int xcd_remap_nse(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
@@ -137,6 +152,174 @@ __device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *_
   }
 }
 
+// ---------------------------------------------------------------- binary32
+// The binary32 window with the parts kept in registers: a thread owns one
+// column (its lane) and kNseRR consecutive rows, whose moments at t and
+// t - dt stay in its registers across the launch's steps.  A step forms the
+// pair parts (nse32_parts) of each of the thread's rows as the update slides
+// down them; the node update (nse32_node) reads the parts of the columns
+// beside from the lanes beside (DPP) and those of the rows above and below
+// from the thread's own registers, except for the row above its first row
+// and the row below its last, which the neighbouring wavefronts own: the
+// parts of every wavefront's first and last rows pass through LDS (two slots
+// by step parity, so one barrier a step suffices).  Lanes at the wavefront's
+// edges read 0 for their missing neighbour; like every node outside the
+// step's region their values are not used by any node of the region.
+template <class L, bool THREE, int RG, bool WRAP_ANY>
+__device__ __forceinline__ void nse_window_reg(const float *__restrict__ cur,
+                                               const float *__restrict__ prev,
+                                               float *__restrict__ out_cur,
+                                               float *__restrict__ out_prev, int nx, int ny,
+                                               int TBW, int TBS, int x0, int y0,
+                                               const KC<float> &kc, float *bnd) {
+  constexpr int NF = 1 + L::D, NPF = 2 * L::P, R = kNseRR, W = 64;
+  constexpr int H = R * RG;
+  constexpr int SLOT = RG * 2 * NPF * W;  // one parity's slots
+  const int64_t N = (int64_t)nx * ny;
+  const int lane = threadIdx.x & 63;
+  const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int yr = rg * R;
+  auto wrap = [&](int i, int n) {
+    if constexpr (WRAP_ANY) return wrapi(i, n);
+    else return i < 0 ? i + n : (i >= n ? i - n : i);
+  };
+  float cm[R][NF], pm[R][NF];
+  {
+    const int gx = wrap(x0 + lane, nx);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int gy = wrap(y0 + yr + r, ny);
+      const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        cm[r][q] = cur[q * N + gi];
+        pm[r][q] = THREE ? prev[q * N + gi] : 0.f;
+      }
+    }
+  }
+  // slot (parity, wavefront, 0 = first row / 1 = last row, part, lane)
+  auto sl = [&](int par, int g, int end, int q) -> float & {
+    return bnd[par * SLOT + ((g * 2 + end) * NPF + q) * W + lane];
+  };
+  const int ga = rg > 0 ? rg - 1 : rg, gb = rg < RG - 1 ? rg + 1 : rg;
+#pragma unroll 1
+  for (int t = 1; t <= TBS; ++t) {
+    const int par = t & 1;
+    {
+      float f[NPF];
+      nse32_parts<L>(cm[0], f, kc);
+#pragma unroll
+      for (int q = 0; q < NPF; ++q) sl(par, rg, 0, q) = f[q];
+      nse32_parts<L>(cm[R - 1], f, kc);
+#pragma unroll
+      for (int q = 0; q < NPF; ++q) sl(par, rg, 1, q) = f[q];
+    }
+    __syncthreads();
+    // parts of the rows r - 1, r, r + 1 of the slide
+    float pa[NPF], pb[NPF], pc[NPF];
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      pa[q] = sl(par, ga, 1, q);  // the last row of the wavefront above
+      pb[q] = sl(par, rg, 0, q);  // this thread's first row
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r + 1 < R - 1) {
+        nse32_parts<L>(cm[r + 1], pc, kc);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) pc[q] = r + 1 == R - 1 ? sl(par, rg, 1, q) : sl(par, gb, 0, q);
+      }
+      const int y = yr + r;
+      if (y >= t && y < H - t) {
+        auto at = [&](int q, int, int dy, int dx) {
+          const float v = dy < 0 ? pa[q] : (dy > 0 ? pc[q] : pb[q]);
+          return dx < 0 ? nse_from_left(v) : (dx > 0 ? nse_from_right(v) : v);
+        };
+        float oc[NF];
+        nse32_node<L, THREE>(at, pb, cm[r], pm[r], oc, kc);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+          pm[r][q] = cm[r][q];
+          cm[r][q] = oc[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NPF; ++q) {
+        pa[q] = pb[q];
+        pb[q] = pc[q];
+      }
+    }
+  }
+  // store the interior of the last level (and the one before it)
+  if (lane >= TBW && lane < W - TBW) {
+    const int gx = x0 + lane;
+    if (gx < nx) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int y = yr + r;
+        const int gy = y0 + y;
+        if (y >= TBW && y < H - TBW && gy < ny) {
+          const int64_t gi = (int64_t)gy * nx + gx;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            out_cur[q * N + gi] = cm[r][q];
+            if constexpr (THREE) out_prev[q * N + gi] = pm[r][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class L, bool THREE, int RG>
+__global__ __launch_bounds__(64 * RG) void k_nse_tb_reg(const float *__restrict__ cur,
+                                                       const float *__restrict__ prev,
+                                                       float *__restrict__ out_cur,
+                                                       float *__restrict__ out_prev, int nx, int ny,
+                                                       int TB, int tiles_x, int ntiles,
+                                                       KC<float> kc) {
+  extern __shared__ float smem_nse_reg[];
+  constexpr int H = kNseRR * RG;
+  const int TX = 64 - 2 * TB, TY = H - 2 * TB;
+  const int tile = xcd_remap_nse(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
+  nse_window_reg<L, THREE, RG, false>(cur, prev, out_cur, out_prev, nx, ny, TB, TB, x0, y0, kc,
+                                      smem_nse_reg);
+}
+
+template <class L, bool THREE, int RG>
+__global__ __launch_bounds__(64 * RG) void k_batch_nse_tb_reg(const BatchInst<float> *__restrict__ inst,
+                                                             const int *__restrict__ tile_inst,
+                                                             int ntiles, int64_t launch, int TB) {
+  extern __shared__ float smem_bnse_reg[];
+  constexpr int H = kNseRR * RG;
+  const int t = xcd_remap_nse(blockIdx.x, ntiles);
+  const BatchInst<float> &I = inst[tile_inst[t]];
+  const int64_t left = I.nsteps - launch * TB;
+  const int TBS = left < TB ? (int)left : TB;
+  const int TX = 64 - 2 * TB, TY = H - 2 * TB;
+  const int lt = t - I.tile0;
+  const int x0 = (lt % I.tiles_x) * TX - TB, y0 = (lt / I.tiles_x) * TY - TB;
+  const int64_t r = I.c0 + launch;
+  const float *cur, *prev;
+  float *oc, *op;
+  if constexpr (THREE) {
+    const int a = (int)(r & 1) * 2, b = 2 - a;
+    cur = I.ring[a];
+    prev = I.ring[a + 1];
+    oc = I.ring[b];
+    op = I.ring[b + 1];
+  } else {
+    cur = I.ring[r & 1];
+    prev = nullptr;
+    oc = I.ring[(r + 1) & 1];
+    op = nullptr;
+  }
+  nse_window_reg<L, THREE, RG, true>(cur, prev, oc, op, I.nx, I.ny, TB, TBS, x0, y0, I.kc,
+                                     smem_bnse_reg);
+}
+
 template <class L, bool THREE, int W, int RG, int R, typename T>
 __global__ __launch_bounds__(W *RG) void k_nse_tb(const T *__restrict__ cur,
                                                  const T *__restrict__ prev,
@@ -188,10 +371,22 @@ __global__ __launch_bounds__(W *RG) void k_batch_nse_tb(const BatchInst<T> *__re
 }
 
 // ------------------------------------------------------------ host side
+// binary32 64 x 64 and 64 x 128 windows run the register window
+// (kNseRR rows per thread); the others the LDS window
+static bool nse_reg_plan(const TbPlan &pl, int elem) {
+  return elem == 4 && (pl.h == 64 || pl.h == 128);
+}
+static size_t nse_reg_lds(int h, int npair) {
+  return (size_t)2 * (h / kNseRR) * 2 * (2 * npair) * kNseW * sizeof(float);
+}
+
 bool nse_tb_plan_valid(const TbPlan &pl, int npair, int elem) {
-  // 64 x 32 (2 rows per thread) or 64 x 64 windows (4 rows per thread)
-  if (pl.w != kNseW || (pl.h != 32 && pl.h != 64)) return false;
+  // 64 x 32 (2 rows per thread) or 64 x 64 windows (4 rows per thread);
+  // binary32: 64 x 64 or 64 x 128 (8 rows per thread, register window)
+  if (pl.w != kNseW) return false;
+  if (pl.h != 32 && pl.h != 64 && !nse_reg_plan(pl, elem)) return false;
   if (pl.tb < 1 || pl.h - 2 * pl.tb < 8 || pl.w - 2 * pl.tb < 8) return false;
+  if (nse_reg_plan(pl, elem)) return nse_reg_lds(pl.h, npair) <= 160 * 1024;
   return (size_t)2 * npair * pl.h * pl.w * elem <= 160 * 1024;
 }
 
@@ -215,9 +410,37 @@ hipError_t nse_tb_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const T 
   return hipGetLastError();
 }
 
+template <class L, bool THREE, int RG>
+hipError_t nse_reg_cfg(const Consts &c, const Grid &g, const TbPlan &pl, const float *cur,
+                       const float *prev, float *oc, float *op, hipStream_t st) {
+  const KC<float> kc = make_kc<float>(c);
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  constexpr int H = kNseRR * RG;
+  const int TX = kNseW - 2 * pl.tb, TY = H - 2 * pl.tb;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = nse_reg_lds(H, L::P);
+  auto fn = k_nse_tb_reg<L, THREE, RG>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(64 * RG), lds, st, cur, prev, oc, op, nx, ny, pl.tb,
+                     tx, tx * ty, kc);
+  return hipGetLastError();
+}
+
 template <class L, typename T>
 hipError_t nse_tb_l(const Consts &c, const Grid &g, const TbPlan &pl, const T *cur, const T *prev,
                     T *oc, T *op, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (nse_reg_plan(pl, 4)) {
+      if (pl.h == 64) {
+        if (c.three) return nse_reg_cfg<L, true, 8>(c, g, pl, cur, prev, oc, op, st);
+        return nse_reg_cfg<L, false, 8>(c, g, pl, cur, prev, oc, op, st);
+      }
+      if (c.three) return nse_reg_cfg<L, true, 16>(c, g, pl, cur, prev, oc, op, st);
+      return nse_reg_cfg<L, false, 16>(c, g, pl, cur, prev, oc, op, st);
+    }
+  }
   if (pl.h == 32) {
     if (c.three) return nse_tb_cfg<L, true, 16, T, 2>(c, g, pl, cur, prev, oc, op, st);
     return nse_tb_cfg<L, false, 16, T, 2>(c, g, pl, cur, prev, oc, op, st);
@@ -240,9 +463,32 @@ hipError_t bnse_cfg(const BatchInst<T> *inst, const int *tile_inst, int ntiles, 
   return hipGetLastError();
 }
 
+template <class L, bool THREE, int RG>
+hipError_t bnse_reg_cfg(const BatchInst<float> *inst, const int *tile_inst, int ntiles,
+                        int64_t launch, const TbPlan &pl, hipStream_t st) {
+  const size_t lds = nse_reg_lds(kNseRR * RG, L::P);
+  auto fn = k_batch_nse_tb_reg<L, THREE, RG>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(64 * RG), lds, st, inst, tile_inst, ntiles, launch,
+                     pl.tb);
+  return hipGetLastError();
+}
+
 template <class L, typename T>
 hipError_t bnse_l(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst, int ntiles,
                   int64_t launch, const TbPlan &pl, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (nse_reg_plan(pl, 4)) {
+      if (pl.h == 64) {
+        if (k.three) return bnse_reg_cfg<L, true, 8>(inst, tile_inst, ntiles, launch, pl, st);
+        return bnse_reg_cfg<L, false, 8>(inst, tile_inst, ntiles, launch, pl, st);
+      }
+      if (k.three) return bnse_reg_cfg<L, true, 16>(inst, tile_inst, ntiles, launch, pl, st);
+      return bnse_reg_cfg<L, false, 16>(inst, tile_inst, ntiles, launch, pl, st);
+    }
+  }
   if (pl.h == 32) {
     if (k.three) return bnse_cfg<L, true, 16, T, 2>(inst, tile_inst, ntiles, launch, pl, st);
     return bnse_cfg<L, false, 16, T, 2>(inst, tile_inst, ntiles, launch, pl, st);
