@@ -89,6 +89,11 @@ CASES = [
     dict(name="d3q19-nse-2l-srt", lattice="D3Q19", n=(9, 7, 5), eq="nse", rho0=1.0, a=(1.0, 0.0, 0.0)),
     dict(name="d3q19-nse-trt-wide", lattice="D3Q19", n=(70, 33, 6), eq="nse", rho0=1.0,
          kind="three_level", a=TRT[0], ah=TRT[1]),
+    # the binary32 register march (x >= 64, y >= 16): ragged strips, rows and z chunks
+    dict(name="d3q19-nse-trt-strips", lattice="D3Q19", n=(131, 47, 9), eq="nse", rho0=1.0,
+         kind="three_level", a=TRT[0], ah=TRT[1]),
+    dict(name="d3q19-nse-2l-strips", lattice="D3Q19", n=(66, 16, 3), eq="nse", rho0=1.0,
+         a=(1.0, 0.0, 0.0)),
     dict(name="d3q19-nse-3l-stencil", lattice="D3Q19", n=(35, 19, 13), eq="nse", rho0=1.0,
          kind="three_level", a=EX13[0], ah=EX13[1]),
     dict(name="d3q19-nse-mesofd", lattice="D3Q19", n=(35, 19, 13), eq="nse", rho0=1.0,
