@@ -529,8 +529,9 @@ def bench_burgers_theta(M, torch, I, stream, theta=0.5, steps=200, chunk=4, cap=
     """theta scheme for Burgers' equation (Picard iteration with the Jacobi
     splitting of the linear even part) on one 2048^2 grid of the batched
     workload's recipe, dt four times its explicit step, each step solved to a
-    tolerance (binary64 1e-12, binary32 1e-6): GLUPS at convergence, sweeps
-    per step, FP32 error against the FP64 run of the same steps."""
+    tolerance (binary64 1e-12, binary32 2e-7: a stopping error of 1e-6 per
+    step accumulates to ~1e-4 over the run): GLUPS at convergence, sweeps per
+    step, FP32 error against the FP64 run of the same steps."""
     rng = np.random.default_rng(6)
     c = I.burgers_instance(rng, side_lo=2048, side_hi=2048, steps_lo=steps, steps_hi=steps)
     dt = 4.0 * c["dt"]
@@ -538,7 +539,7 @@ def bench_burgers_theta(M, torch, I, stream, theta=0.5, steps=200, chunk=4, cap=
     a = M.mfd_preset("two_level", sp)[0]
     out, finals = {}, {}
     N = 2048 * 2048
-    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-12)):
+    for prec, tol in (("fp32", 2e-7), ("fp64", 1e-12)):
         s = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
         s.set_equation("burgers")
         s.set_scheme("theta", a, theta=theta, theta_iters=cap, dt=dt)
@@ -654,6 +655,47 @@ def bench_batched(M, torch, I, stream):
                 fp32_err_over_initial_norm_max=max(errs0),
                 worst_instance=dict(side=insts[worst]["n"][0], steps=insts[worst]["steps"],
                                     final_over_initial_norm=decay[worst]))
+
+
+def bench_tiny_batch(M, torch, I, stream, count=512):
+    """Many small grids: 512 Burgers grids of the batched recipe with sides
+    log-uniform in [16, 64] and 200 .. 2000 steps, FP32, one graph per run:
+    the LDS-resident path (every grid within 4096 nodes: all steps in one
+    workgroup) against the windowed launches (resident path off, autotuned
+    plan).  Both give the solo results bit for bit."""
+    insts = I.c4_batch(count, seed=7, side_lo=16, side_hi=64, steps_lo=200, steps_hi=2000)
+    lups = sum(int(np.prod(c["n"])) * c["steps"] for c in insts)
+    out = {}
+    finals = {}
+    for name, res in (("resident", 4096), ("windowed", 0)):
+        ss = []
+        b = M.Batch(stream.cuda_stream, use_graph=True)
+        b.set_resident(res)
+        for c in insts:
+            s = M.Solver("D2Q9", c["n"], c["dx"], "fp32", "mmfd")
+            s.set_equation("burgers")
+            s.set_scheme("two_level", two_level_a(M, c["nu"], c["dx"], c["dt"]), dt=c["dt"])
+            s.set_stream(stream.cuda_stream)
+            s.set_state(c["phi0"].astype(np.float32))
+            b.add(s, c["steps"])
+            ss.append(s)
+        if not res:
+            b.autotune()
+        b.run()
+        b.wait()  # capture and first run
+        for s, c in zip(ss, insts):
+            s.set_state(c["phi0"].astype(np.float32))
+        ms = timed(torch, lambda: b.run())
+        st = b.stats()
+        finals[name] = [s.get_state() for s in ss]
+        out[name] = dict(glups=round(lups / (ms * 1e-3) / 1e9, 2), ms=round(ms, 2),
+                         launches=st["launches"], resident_instances=b.resident())
+        b.close()
+        for s in ss:
+            s.close()
+    out["identical"] = all(np.array_equal(a, b) for a, b in zip(finals["resident"], finals["windowed"]))
+    out.update(instances=count, lups=lups)
+    return out
 
 
 def serving_requests(M, I, n_total, rate=200.0, warm=200):
@@ -898,6 +940,8 @@ def main():
     if "batched" in sections:
         log("batched")
         extra["batched_256_burgers"] = bench_batched(M, torch, I, stream)
+        log("batched: small grids")
+        extra["batched_512_small_burgers"] = bench_tiny_batch(M, torch, I, stream)
     if "serving" in sections:
         log("serving: requests")
         warm = min(200, args.serve_requests // 10)

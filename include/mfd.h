@@ -409,6 +409,22 @@ int mfd_batch_wait(mfd_batch *b);
 /* Kernel launches per run, lattice-node updates per run, tiles. */
 int mfd_batch_stats(const mfd_batch *b, int64_t *launches, int64_t *lups, int64_t *tiles);
 
+/* LDS-resident instances: binary32 two-level linear CDE and Burgers
+ * instances of at most max_nodes nodes (nx ny; capped at 20480, where their
+ * two levels fill the 160 KiB of LDS) run all of their steps in one
+ * workgroup each, in one launch per kind on a branch of the run beside the
+ * windowed launches (the run's graph forks and joins it), with the
+ * single-step node function: results are those of the windowed path value
+ * for value.  max_nodes = 0 sends every instance to the windowed launches;
+ * the default is 4096 (grids up to 64 x 64, which a blocked window would
+ * mostly spend on wrapped copies of the grid; larger resident grids hold a
+ * CU's whole LDS for all of their steps).  MFD_E_ARG for max_nodes < 0.
+ * Takes effect at the next run. */
+int mfd_batch_set_resident(mfd_batch *b, int32_t max_nodes);
+
+/* Number of instances the last build sent to the LDS-resident kernel. */
+int mfd_batch_resident(const mfd_batch *b, int32_t *count);
+
 /* Launch plan of the groups that can be temporally blocked (two-level linear
  * CDE and Burgers groups, NSE groups without an older-level stencil; others
  * always take one launch per step): tb_depth = 1 one launch per step,

@@ -49,6 +49,9 @@ void Batch::free_groups() {
     if (g.d_lane) dev_free(g.d_lane);
   }
   groups.clear();
+  for (auto &r : res)
+    if (r.d) dev_free(r.d);
+  res.clear();
 }
 
 BatchKey batch_key_of(const Solver *s) {
@@ -126,12 +129,38 @@ int Batch::build() {
     if (rc) return rc;
     stream = own_stream;
   }
-  std::map<BatchKey, std::vector<int>> by_key;
+  std::map<BatchKey, std::vector<int>> by_key, res_key;
   for (int i = 0; i < (int)entries.size(); ++i) {
-    by_key[batch_key_of(entries[i].s)].push_back(i);
+    const Solver *s = entries[i].s;
+    const BatchKey k = batch_key_of(s);
+    if (entries[i].nsteps > 0 && s->G.N <= resident_max && resident_applies(k, s->G.n[0], s->G.n[1]))
+      res_key[k].push_back(i);
+    else
+      by_key[k].push_back(i);
   }
   max_steps = 0;
   lups_per_run = 0;
+  for (auto &kv : res_key) {
+    res.emplace_back();
+    ResGroup &r = res.back();
+    r.key = kv.first;
+    r.order = kv.second;
+    r.h.resize(r.order.size());
+    for (int i : r.order) {
+      max_steps = std::max(max_steps, entries[i].nsteps);
+      lups_per_run += entries[i].s->G.N * entries[i].nsteps;
+    }
+    int rc = hip(dev_malloc((void **)&r.d, sizeof(ResInst) * r.order.size()),
+                 "hipMalloc (resident instances)");
+    if (rc) return rc;
+  }
+  if (!res.empty() && !side) {
+    // default-priority stream and events of the resident branch
+    int rc = hip(hipStreamCreateWithFlags(&side, hipStreamNonBlocking), "hipStreamCreate (side)");
+    if (!rc) rc = hip(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "hipEventCreate");
+    if (!rc) rc = hip(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "hipEventCreate");
+    if (rc) return rc;
+  }
   for (auto &kv : by_key) {
     groups.emplace_back();
     Group &g = groups.back();
@@ -203,6 +232,30 @@ hipError_t Batch::launch_group_tb(const Group &g, int nt, int64_t l) {
 
 int Batch::enqueue_steps() {
   launches_per_run = 0;
+  // the LDS-resident instances on a branch of their own, joined at the end
+  if (!res.empty()) {
+    int rc = hip(hipEventRecord(ev_fork, stream), "hipEventRecord (fork)");
+    if (!rc) rc = hip(hipStreamWaitEvent(side, ev_fork, 0), "hipStreamWaitEvent (fork)");
+    for (auto &r : res) {
+      if (rc) break;
+      int64_t nmax = 0;
+      for (int i : r.order) nmax = std::max(nmax, entries[i].s->G.N);
+      rc = hip(launch_batch_resident(r.key, r.d, (int)r.order.size(), (int)nmax, side),
+               "resident batch launch");
+      ++launches_per_run;
+    }
+    if (!rc) rc = hip(hipEventRecord(ev_join, side), "hipEventRecord (join)");
+    if (rc) return rc;
+  }
+  int rc = enqueue_group_steps();
+  if (!res.empty()) {
+    const int rj = hip(hipStreamWaitEvent(stream, ev_join, 0), "hipStreamWaitEvent (join)");
+    if (!rc) rc = rj;
+  }
+  return rc;
+}
+
+int Batch::enqueue_group_steps() {
   for (auto &g : groups) {
     const int64_t gmax = g.steps.empty() ? 0 : g.steps[0];
     if (g.plan.tb > 1) {
@@ -270,6 +323,25 @@ static void fill_inst(const Group &g, const std::vector<BatchEntry> &entries,
 }
 
 int Batch::upload_instances() {
+  for (auto &r : res) {
+    for (int k = 0; k < (int)r.order.size(); ++k) {
+      const BatchEntry &e = entries[r.order[k]];
+      const Solver *s = e.s;
+      ResInst ri;
+      std::memset(&ri, 0, sizeof(ri));
+      ri.lv[0] = (float *)s->buf[s->ic];
+      ri.lv[1] = (float *)s->buf[s->ip];
+      ri.nx = (int)s->G.n[0];
+      ri.ny = (int)s->G.n[1];
+      ri.nsteps = e.nsteps;
+      ri.kc = make_kc<float>(s->consts);
+      r.h[k] = ri;
+    }
+    int rc = hip(hipMemcpyAsync(r.d, r.h.data(), sizeof(ResInst) * r.h.size(), hipMemcpyHostToDevice,
+                                stream),
+                 "hipMemcpyAsync (resident instances)");
+    if (rc) return rc;
+  }
   for (auto &g : groups) {
     if (g.key.precision == MFD_FP64) fill_inst<double>(g, entries, g.h_inst);
     else fill_inst<float>(g, entries, g.h_inst);
@@ -341,6 +413,8 @@ int Batch::run() {
   dirty = false;
   for (auto &g : groups)
     for (int i : g.order) entries[i].tb = g.plan.tb;
+  for (auto &r : res)
+    for (int i : r.order) entries[i].tb = 1;  // the roles of a run of single steps
   // hand the rotated level roles back to the solvers
   for (auto &e : entries) {
     Solver *s = e.s;
@@ -502,8 +576,12 @@ extern "C" int mfd_batch_destroy(mfd_batch *h) {
   if (!h) return MFD_OK;
   Batch *b = reinterpret_cast<Batch *>(h);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);
   b->free_graph();
   b->free_groups();
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
   delete b;
   return MFD_OK;
@@ -604,6 +682,24 @@ extern "C" int mfd_batch_plan(const mfd_batch *h, int32_t group, int32_t *tb_dep
   if (tb_depth) *tb_depth = p.tb;
   if (window_rows) *window_rows = p.tb > 1 ? p.h : 0;
   if (window_cols) *window_cols = p.tb > 1 ? p.w : 0;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_set_resident(mfd_batch *h, int32_t max_nodes) {
+  if (!h) return MFD_E_ARG;
+  Batch *b = reinterpret_cast<Batch *>(h);
+  if (max_nodes < 0) return b->fail(MFD_E_ARG, "max_nodes < 0");
+  b->resident_max = max_nodes;
+  b->dirty = true;
+  return MFD_OK;
+}
+
+extern "C" int mfd_batch_resident(const mfd_batch *h, int32_t *count) {
+  if (!h || !count) return MFD_E_ARG;
+  const Batch *b = reinterpret_cast<const Batch *>(h);
+  int32_t c = 0;
+  for (auto &r : b->res) c += (int32_t)r.order.size();
+  *count = c;
   return MFD_OK;
 }
 

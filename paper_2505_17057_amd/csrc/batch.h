@@ -36,6 +36,14 @@ struct Group {
   std::vector<unsigned char> h_lane;
 };
 
+// instances run by the LDS-resident kernel (one launch per kind)
+struct ResGroup {
+  BatchKey key{};
+  std::vector<int> order;  // entry indices
+  ResInst *d = nullptr;
+  std::vector<ResInst> h;
+};
+
 // group kind of a solver, and whether such groups can be temporally blocked
 BatchKey batch_key_of(const Solver *s);
 bool batch_blockable(const BatchKey &k);
@@ -43,7 +51,11 @@ bool batch_blockable(const BatchKey &k);
 struct Batch {
   std::vector<BatchEntry> entries;
   std::vector<Group> groups;
+  std::vector<ResGroup> res;            // LDS-resident instances
+  int resident_max = 4096;              // binary32 instances of at most this many nodes run LDS-resident
   hipStream_t stream = nullptr, own_stream = nullptr;
+  hipStream_t side = nullptr;           // the resident launches' branch of a run
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = true, dirty = true, sticky = false;
@@ -60,6 +72,7 @@ struct Batch {
   int make_tables(Group &g);
   int upload_instances();
   int enqueue_steps();
+  int enqueue_group_steps();
   hipError_t launch_group_tb(const Group &g, int nt, int64_t l);
   int run();
   int autotune();

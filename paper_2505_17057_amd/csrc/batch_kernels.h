@@ -48,6 +48,23 @@ template <typename T>
 hipError_t launch_batch_nse_tb(const BatchKey &k, const BatchInst<T> *inst, const int *tile_inst,
                                int ntiles, int64_t launch, const TbPlan &pl, hipStream_t st);
 
+// LDS-resident batched run (kernels_batch.hip): binary32 two-level linear CDE
+// and Burgers MMFD instances whose two levels fit in LDS; one workgroup per
+// instance runs all of its steps.  lv[0] holds level t at the start; after
+// nsteps steps level t + nsteps is in lv[nsteps % 2] and the level before it
+// in the other (the roles a run of single steps leaves).
+struct ResInst {
+  float *lv[2];
+  int nx, ny;
+  int64_t nsteps;
+  KC<float> kc;
+};
+constexpr int kResMaxNodes = 20480;  // two binary32 levels in 160 KiB of LDS
+bool resident_applies(const BatchKey &k, int64_t nx, int64_t ny);
+// nmax: the largest instance's node count (sizes the LDS and the workgroup)
+hipError_t launch_batch_resident(const BatchKey &k, const ResInst *inst, int count, int nmax,
+                                 hipStream_t st);
+
 // lane-shared batched launch (kernels_lane_tb.hip): binary32 two-level LCDE and
 // Burgers (beta = 1) groups under 128-column plans, with an instance table of
 // their own (lane_inst_bytes per instance, filled by lane_inst_fill; false:

@@ -35,6 +35,20 @@ __global__ __launch_bounds__(256) void k_mmfd_plane(const T *__restrict__ cur,
   mmfd_plane_tile<L, EQ, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc, &bc);
 }
 
+// one sweep of Burgers' theta step (1D / 2D): the explicit step of the
+// iterate x and the Picard-Jacobi update in one pass
+template <class L, bool B1, int TX, int TY, typename T>
+__global__ __launch_bounds__(256) void k_picard_plane(const T *__restrict__ x,
+                                                      T *__restrict__ out, int nx, int ny,
+                                                      int tiles_x, int ntiles, KC<T> kc,
+                                                      PicardEp<T> pe) {
+  const int tile = xcd_remap(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+  mmfd_plane_tile<L, kBurgers, false, false, TX, TY, T>(x, nullptr, out, nx, ny, x0, y0, kc,
+                                                        nullptr, &pe);
+  (void)B1;
+}
+
 // ------------------------------------- 2D NSE, persistent workgroups
 // Each workgroup walks a contiguous run of tiles (XCD-aware: the runs of one
 // XCD are adjacent, so halo rows are shared in its L2) and loads the next
@@ -340,6 +354,47 @@ hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const 
     default: return hipErrorInvalidValue;
   }
 }
+
+namespace {
+template <class L, typename T>
+hipError_t picard_l(const Consts &c, const Grid &g, const T *x, const T *R, T *out, double A0,
+                    double dd, double th1, double inv_den, hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  const PicardEp<T> pe{R, (T)A0, (T)dd, (T)th1, (T)inv_den};
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  if constexpr (L::D == 1) {
+    constexpr int TX = 1024, TY = 1;
+    const int tx = (nx + TX - 1) / TX;
+    hipLaunchKernelGGL((k_picard_plane<L, true, TX, TY, T>), dim3(tx), dim3(256), 0, st, x, out,
+                       nx, 1, tx, tx, kc, pe);
+  } else {
+    constexpr int TX = 64, TY = 16;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_picard_plane<L, true, TX, TY, T>), dim3(tx * ty), dim3(256), 0, st, x,
+                       out, nx, ny, tx, tx * ty, kc, pe);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
+                               double A0, double dd, double th1, double inv_den, hipStream_t st) {
+  if (c.eq != kBurgers || c.three) return hipErrorInvalidValue;
+  switch (c.lattice) {
+    case 1: return picard_l<LatD1Q3, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+    case 2: return picard_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+    case 3: return picard_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_picard_sweep<float>(const Consts &, const Grid &, const float *,
+                                               const float *, float *, double, double, double,
+                                               double, hipStream_t);
+template hipError_t launch_picard_sweep<double>(const Consts &, const Grid &, const double *,
+                                                const double *, double *, double, double, double,
+                                                double, hipStream_t);
 
 template hipError_t launch_mmfd_step<float>(const Consts &, const Grid &, const float *,
                                             const float *, float *, int, hipStream_t,

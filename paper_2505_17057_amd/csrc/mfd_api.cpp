@@ -469,9 +469,13 @@ int Solver::theta_picard_steps(int64_t nsteps) {
       const T *before = src;
       for (int it = 0; it < K; ++it) {
         T *dst = (k % 2 == 0) ? B[io] : B[third];
-        e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
-        if (e == hipSuccess)
-          e = launch_picard_update<T>(B[6], src, B[5], dst, A0, dd, th1, inv_den, N, stream);
+        if (consts.dim <= 2) {
+          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0, dd, th1, inv_den, stream);
+        } else {
+          e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
+          if (e == hipSuccess)
+            e = launch_picard_update<T>(B[6], src, B[5], dst, A0, dd, th1, inv_den, N, stream);
+        }
         if (e != hipSuccess) return hip(e, "picard sweep launch");
         before = src;
         src = dst;

@@ -296,6 +296,11 @@ hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double 
 template <typename T>
 hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, double A0, double dd,
                                 double th1, double inv_den, int64_t N, hipStream_t st);
+// one Picard-Jacobi sweep of Burgers' theta step fused with the explicit
+// step of the iterate (1D / 2D; hipErrorInvalidValue otherwise)
+template <typename T>
+hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
+                               double A0, double dd, double th1, double inv_den, hipStream_t st);
 // sum (a - b)^2 and sum c^2 in binary64 (out[0], out[1]); partial as launch_reduce
 template <typename T>
 hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,

@@ -434,12 +434,22 @@ __device__ __forceinline__ void mmfd_plane_tile_pf(const T *__restrict__ cur,
 
 // One TX x TY tile (origin x0, y0) of a 1D / 2D grid: EDF records of the tile
 // and a one-node halo into LDS (periodic wrap), then the node updates.
+// Sweep of the Picard-Jacobi iteration of Burgers' theta step, applied to
+// the explicit step value S(x) of a node: out = (R + th1 ((S - A0 x) +
+// dd x)) inv_den (the operations and roundings of the separate update).
+template <typename T>
+struct PicardEp {
+  const T *R;
+  T A0, dd, th1, inv_den;
+};
+
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
 __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
                                                 const T *__restrict__ prev,
                                                 T *__restrict__ out, int nx, int ny, int x0,
                                                 int y0, const KC<T> &kc,
-                                                const DirBC *bc = nullptr) {
+                                                const DirBC *bc = nullptr,
+                                                const PicardEp<T> *pe = nullptr) {
   if constexpr (EQ == kNSE && L::D == 2) {
     mmfd_plane_tile_pf<L, THREE, THREE_ST, TX, TY, T>(cur, prev, out, nx, ny, x0, y0, kc);
   } else {
@@ -493,6 +503,14 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
       // Dirichlet nodes take their prescribed value
       if (bc && bc->on && dir_node(gx, gy, nx, ny))
         oc[0] = (T)(bc->Gb[dir_index(gx, gy, nx, ny)] * bc->E[1]);
+    }
+    if constexpr (NF == 1) {
+      if (pe) {
+        const T xi = cc[0];
+        const T t = (oc[0] - pe->A0 * xi) + pe->dd * xi;
+        const T c = pe->th1 * t;
+        oc[0] = (pe->R[gi] + c) * pe->inv_den;
+      }
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];

@@ -134,6 +134,8 @@ _SIGS = {
     "mfd_batch_wait": ([_H], C.c_int),
     "mfd_batch_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "mfd_batch_set_plan": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "mfd_batch_set_resident": ([_H, C.c_int32], C.c_int),
+    "mfd_batch_resident": ([_H, C.POINTER(C.c_int32)], C.c_int),
     "mfd_batch_autotune": ([_H], C.c_int),
     "mfd_batch_plan": ([_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                         C.POINTER(C.c_int32)], C.c_int),
@@ -468,6 +470,14 @@ class Batch:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         self.check(lib.mfd_batch_stats(self.h, C.byref(a), C.byref(b), C.byref(c)), "mfd_batch_stats")
         return dict(launches=a.value, lups=b.value, tiles=c.value)
+
+    def set_resident(self, max_nodes):
+        return self.check(lib.mfd_batch_set_resident(self.h, int(max_nodes)), "mfd_batch_set_resident")
+
+    def resident(self):
+        c = C.c_int32()
+        self.check(lib.mfd_batch_resident(self.h, C.byref(c)), "mfd_batch_resident")
+        return c.value
 
     def set_plan(self, tb_depth, window_rows=0, window_cols=0):
         return self.check(lib.mfd_batch_set_plan(self.h, int(tb_depth), int(window_rows), int(window_cols)),

@@ -4,6 +4,8 @@
   every instance exactly its solo result: FP64 equal to the oracle value for
   value, FP32 bit-identical to the solo FP32 run; graph replay and plain
   launches agree.
+* Small binary32 instances run LDS-resident (all steps in one workgroup)
+  with the same results as the windowed path and the solo run.
 * The server returns, for each request of a mixed stream, exactly the result
   of the same request solved alone; admission respects the memory budget and
   a request larger than the budget fails cleanly.
@@ -106,6 +108,69 @@ def test_batch_fp32_equals_solo(M):
     b.close()
     for s in solvers:
         s.close()
+
+
+def _resident_cases():
+    rng = np.random.default_rng(45)
+    cases = []
+    for i, n in enumerate([(64, 64), (143, 143), (100, 37), (3, 5), (150, 140), (200, 160)]):
+        dx = 1.0 / n[0]
+        nu = float(rng.uniform(1e-3, 1e-2))
+        dt = 0.5 * min(0.3 * dx * dx / nu, nu / 0.01)
+        sp = 2 * nu * dt / ((1.0 / 3.0) * dx * dx)
+        a = ((sp + 1) / 2, 1 - sp, (sp - 1) / 2)
+        cases.append(dict(name="burgers-%dx%d" % n, lattice="D2Q9", eq="burgers", n=n, dx=dx, dt=dt,
+                          a=a, steps=int(rng.integers(5, 40))))
+    cases.append(dict(name="lcde-d2q5", lattice="D2Q5", eq="lcde", n=(90, 61), u=(0.1, -0.07),
+                      K=[[0.25, 0.0], [0.0, 0.25]], lambda_bar=1, a=(1.0, 0.0, 0.0), steps=17))
+    cases.append(dict(name="lcde-d2q9-zero", lattice="D2Q9", eq="lcde", n=(40, 30), u=(0.1, -0.07),
+                      K=[[0.3, 0.04], [0.04, 0.2]], lambda_bar=1, a=(1.0, 0.0, 0.0), steps=0))
+    return cases
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_resident_equals_solo(M, use_graph):
+    """Small binary32 instances (two levels within LDS) run LDS-resident, all
+    steps in one workgroup, beside the windowed launches of the large ones:
+    every instance's state equals the solo run's bit for bit, with the
+    resident path on and off; a resident instance also holds the level one
+    step before it, as a run of single steps does (a blocked run holds the
+    level its last launch started from)."""
+    cases = _resident_cases()
+    states = _states(cases, seed=6)
+    solo = []
+    for c, (cur, _) in zip(cases, states):
+        s = make_solver(M, c, "fp32")
+        s.set_blocking(1)
+        s.set_state(cur.astype(np.float32))
+        s.step(c["steps"])
+        solo.append((s.get_state(), s.get_state(level=1)))
+        s.close()
+    for resident in (True, False):
+        b = M.Batch(use_graph=use_graph)
+        b.set_resident(20480 if resident else 0)
+        solvers = []
+        for c, (cur, _) in zip(cases, states):
+            s = make_solver(M, c, "fp32")
+            s.set_state(cur.astype(np.float32))
+            b.add(s, c["steps"])
+            solvers.append(s)
+        b.run()
+        b.wait()
+        # every instance of at most 20480 nodes with steps to take
+        want_res = sum(1 for c in cases if c["steps"] > 0 and c["n"][0] * c["n"][1] <= 20480
+                       and min(c["n"]) >= 3)
+        assert b.resident() == (want_res if resident else 0)
+        for c, s, (w0, w1) in zip(cases, solvers, solo):
+            assert np.array_equal(s.get_state(), w0), (c["name"], resident)
+            if resident and c["steps"] > 0 and c["n"][0] * c["n"][1] <= 20480:
+                assert np.array_equal(s.get_state(level=1), w1), c["name"]
+        # a second run continues from the levels the first left
+        b.run()
+        b.wait()
+        b.close()
+        for s in solvers:
+            s.close()
 
 
 def _request(M, c, state, out, exclude=False, precision="fp32", prev=None, timeout_s=0.0):
