@@ -47,7 +47,8 @@
 #include <omp.h>
 #endif
 
-enum { ORC_D1Q3 = 1, ORC_D2Q5 = 2, ORC_D2Q9 = 3, ORC_D3Q19 = 4 };
+enum { ORC_D1Q3 = 1, ORC_D2Q5 = 2, ORC_D2Q9 = 3, ORC_D3Q19 = 4, ORC_D2Q5II = 5, ORC_D3Q7 = 6,
+       ORC_D3Q9 = 7 };
 enum { ORC_LCDE = 0, ORC_BURGERS = 1, ORC_NSE = 2, ORC_WAVE = 3 };
 
 #define ORC_MAXQ 19
@@ -141,6 +142,30 @@ static int build_lattice(int lattice, double d0, orc_lattice *L)
         double we = d0 * d0 / 4.0;
         for (int j = 1; j <= 6; ++j) L->w[j] = w1;
         for (int j = 7; j <= 18; ++j) L->w[j] = we;
+    } else if (lattice == ORC_D2Q5II) {
+        /* the rest velocity and the four diagonals, weights d0 / 4 */
+        L->dim = 2; L->b = 5;
+        set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 1, 0); set_e(L, 2, -1, 1, 0);
+        set_e(L, 3, -1, -1, 0); set_e(L, 4, 1, -1, 0);
+        L->w[0] = 1.0 - d0;
+        for (int j = 1; j <= 4; ++j) L->w[j] = d0 / 4.0;
+    } else if (lattice == ORC_D3Q7) {
+        /* the rest velocity and the six axis directions, weights d0 / 2 */
+        L->dim = 3; L->b = 7;
+        set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
+        set_e(L, 3, 0, 0, 1); set_e(L, 4, -1, 0, 0); set_e(L, 5, 0, -1, 0);
+        set_e(L, 6, 0, 0, -1);
+        L->w[0] = 1.0 - d0 - d0 - d0;
+        for (int j = 1; j <= 6; ++j) L->w[j] = d0 / 2.0;
+    } else if (lattice == ORC_D3Q9) {
+        /* the rest velocity and the eight cube corners, weights d0 / 8 */
+        static const int E[9][3] = {
+            {0,0,0}, {1,1,1}, {1,1,-1}, {1,-1,1}, {-1,1,1},
+            {-1,-1,-1}, {-1,-1,1}, {-1,1,-1}, {1,-1,-1}};
+        L->dim = 3; L->b = 9;
+        for (int j = 0; j < 9; ++j) set_e(L, j, E[j][0], E[j][1], E[j][2]);
+        L->w[0] = 1.0 - d0;
+        for (int j = 1; j <= 8; ++j) L->w[j] = d0 / 8.0;
     } else {
         return -1;
     }

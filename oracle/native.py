@@ -17,9 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mfd_oracle.c")
 LIB = os.path.join(HERE, "libmfd_oracle.so")
 
-LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
-DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
-QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9}
 EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
 MAXP = 9
 

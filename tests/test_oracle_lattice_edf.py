@@ -11,7 +11,10 @@ import pytest
 from oracle import native as O
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "printed_values.json")))
-LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19"]
+LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19", "D2Q5II", "D3Q7", "D3Q9"]
+# Appendix A's ranges of d0 with every weight positive
+D0_MAX = {"D1Q3": 1.0, "D2Q5": 0.5, "D2Q9": 1.0, "D3Q19": 0.5, "D2Q5II": 1.0, "D3Q7": 1.0 / 3.0,
+          "D3Q9": 1.0}
 
 
 def test_d2q9_weights_printed():
@@ -29,6 +32,8 @@ def test_d3q19_weights_d0_third():
 @pytest.mark.parametrize("lat", LATS)
 @pytest.mark.parametrize("d0", [1.0 / 3.0, 0.25, 0.4])
 def test_lattice_moments(lat, d0):
+    if d0 >= D0_MAX[lat]:
+        pytest.skip("d0 outside the lattice's range in Appendix A")
     E, w, pairs = O.lattice_info(lat, d0)
     dim = O.DIMS[lat]
     b = len(w)
@@ -53,8 +58,9 @@ def _rand_args(lat, rng):
     Cm = 0.5 * (Cm + Cm.T)
     if lat == "D1Q3":
         Cm = np.diag(np.diag(Cm))
-    if lat == "D2Q5":
-        # rD2Q5I has no e_x^2 e_y^2 moment, so the quadratic part of Eq. (3-3)
+    if lat in ("D2Q5", "D3Q7", "D2Q5II", "D3Q9"):
+        # rD2Q5I and rD3Q7 have no e_a^2 e_b^2 moment, rD2Q5II and rD3Q9 only
+        # the value d0 for it (not d0^2): the quadratic part of Eq. (3-3)
         # meets the second-moment identity of Eq. (3-5) only for C = 0
         Cm = np.zeros((dim, dim))
     return A, B, Cm
@@ -86,6 +92,38 @@ def test_d2q5_quadratic_term_cross_talk():
     M2 = np.einsum("j,ja,jb->ab", g, E[:, :2], E[:, :2])
     assert abs(M2[0, 0] - (-d0 / (1 - d0) * 0.1)) < 1e-15
     assert abs(M2[1, 1] - 0.1) < 1e-15
+
+
+def test_corner_lattice_quadratic_term():
+    """On rD2Q5II (and rD3Q9) every moving velocity has e_a^2 = 1, so a
+    diagonal C reaches each diagonal second moment through its trace, and an
+    off-diagonal C_xy comes back divided by d0: the reading recorded for
+    these lattices (they serve equations with C = 0)."""
+    d0 = 0.25
+    for lat, dim in (("D2Q5II", 2), ("D3Q9", 3)):
+        E, w, _ = O.lattice_info(lat, d0)
+        Ed = E[:, :dim]
+        Cd = np.diag(np.arange(1, dim + 1) * 0.01)
+        g = O.edf(lat, d0, 0.0, np.zeros(dim), Cd)
+        M2 = np.einsum("j,ja,jb->ab", g, Ed, Ed)
+        assert np.allclose(np.diag(M2), np.trace(Cd), atol=1e-15)
+        Co = np.zeros((dim, dim))
+        Co[0, 1] = Co[1, 0] = 0.02
+        g = O.edf(lat, d0, 0.0, np.zeros(dim), Co)
+        M2 = np.einsum("j,ja,jb->ab", g, Ed, Ed)
+        assert abs(M2[0, 1] - 0.02 / d0) < 1e-15
+
+
+def test_d3q7_weights_and_pairs():
+    """rD3Q7: w0 = 1 - 3 d0, w_axis = d0 / 2; three opposite pairs along the
+    axes.  rD3Q9: w0 = 1 - d0, w_corner = d0 / 8; four corner pairs."""
+    d0 = 0.25
+    E, w, pairs = O.lattice_info("D3Q7", d0)
+    assert np.allclose(w, [1 - 3 * d0] + [d0 / 2] * 6, rtol=0, atol=1e-16)
+    assert sorted(tuple(E[j]) for j in pairs) == [(0, 0, 1), (0, 1, 0), (1, 0, 0)]
+    E, w, pairs = O.lattice_info("D3Q9", d0)
+    assert np.allclose(w, [1 - d0] + [d0 / 8] * 8, rtol=0, atol=1e-16)
+    assert len(pairs) == 4 and all(np.abs(E[j]).sum() == 3 for j in pairs)
 
 
 @pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])

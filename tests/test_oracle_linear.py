@@ -19,17 +19,19 @@ import mfd_inputs as I
 from oracle import native as O
 from oracle import scheme as S
 
-LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19"]
+LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19", "D2Q5II", "D3Q7", "D3Q9"]
+# lattices whose EDF meets the second-moment identity only for C = 0
+C0_LATS = ("D2Q5", "D2Q5II", "D3Q7", "D3Q9")
 
 
 def lin_spec(lat, case, a, ah=(0, 0, 0), lam=1, levels=None):
     dim = O.DIMS[lat]
     K = case["K"]
-    if lat == "D2Q5":  # keep C = 0 on rD2Q5I (see the EDF pins)
+    if lat in C0_LATS:  # keep C = 0 there (see the EDF pins)
         lam = 0
     spec = dict(lattice=lat, n=case["n"], dx=case["dx"], dt=case["dt"], u=case["u"], K=K,
                 lambda_bar=lam, a=a, ah=ah, levels=levels or (3 if any(ah) else 2))
-    if lat == "D2Q5":
+    if lat in C0_LATS:
         m = S.coeff_moments(a, ah)
         ratio = -m[(1, 0)] / m[(2, 2)]
         # isotropic K that makes C = ratio*kh - d0 I vanish
