@@ -67,6 +67,16 @@ extern "C" {
 #define MFD_D2Q5 2   /* rD2Q5I of Appendix A                                  */
 #define MFD_D2Q9 3   /* rD2Q9 of Appendix A                                   */
 #define MFD_D3Q19 4  /* rD3Q19 of Appendix A                                  */
+/* The lattices below carry the single-step kernels only (no temporally
+ * blocked plans, batches or fused theta windows).  Their EDF meets the
+ * second-moment identity of Eq. (3-5) only for C = 0 (isotropic diffusion
+ * with lambda_bar = 0, or the wave equation at beta = 1). */
+#define MFD_D2Q5II 5 /* rD2Q5II: the rest velocity and the four diagonals,
+                        w = 1-d0, d0/4 (x4)                                  */
+#define MFD_D3Q7 6   /* rD3Q7: rest and the six axis velocities,
+                        w = 1-3d0, d0/2 (x6); 0 < d0 < 1/3                   */
+#define MFD_D3Q9 7   /* rD3Q9: rest and the eight cube corners,
+                        w = 1-d0, d0/8 (x8)                                  */
 
 #define MFD_FP64 0
 #define MFD_FP32 1

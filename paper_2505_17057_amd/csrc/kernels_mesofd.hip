@@ -386,6 +386,9 @@ hipError_t launch_mesofd_step(const Consts &c, const Grid &g, const T *mom, cons
     case 2: return meso_eq<LatD2Q5, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
     case 3: return meso_eq<LatD2Q9, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
     case 4: return meso_eq<LatD3Q19, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 5: return meso_eq<LatD2Q5II, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 6: return meso_eq<LatD3Q7, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
+    case 7: return meso_eq<LatD3Q9, T>(c, g, mom, prev_mom, pop_out, mom_out, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -436,6 +439,9 @@ hipError_t launch_init_populations(const Consts &c, const Grid &g, const T *mom,
     case 2: return init_eq<LatD2Q5, T>(c, g, mom, pop, st);
     case 3: return init_eq<LatD2Q9, T>(c, g, mom, pop, st);
     case 4: return init_eq<LatD3Q19, T>(c, g, mom, pop, st);
+    case 5: return init_eq<LatD2Q5II, T>(c, g, mom, pop, st);
+    case 6: return init_eq<LatD3Q7, T>(c, g, mom, pop, st);
+    case 7: return init_eq<LatD3Q9, T>(c, g, mom, pop, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -447,6 +453,9 @@ hipError_t launch_moments(const Consts &c, const Grid &g, const T *pop, T *mom, 
     case 2: return mom_eq<LatD2Q5, T>(c, g, pop, mom, st);
     case 3: return mom_eq<LatD2Q9, T>(c, g, pop, mom, st);
     case 4: return mom_eq<LatD3Q19, T>(c, g, pop, mom, st);
+    case 5: return mom_eq<LatD2Q5II, T>(c, g, pop, mom, st);
+    case 6: return mom_eq<LatD3Q7, T>(c, g, pop, mom, st);
+    case 7: return mom_eq<LatD3Q9, T>(c, g, pop, mom, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -384,6 +384,9 @@ hipError_t launch_theta_rhs(const Consts &c, const Grid &g, const T *cur, T *rhs
     case 2: hipLaunchKernelGGL((k_theta_rhs<LatD2Q5, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
     case 3: hipLaunchKernelGGL((k_theta_rhs<LatD2Q9, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
     case 4: hipLaunchKernelGGL((k_theta_rhs<LatD3Q19, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
+    case 5: hipLaunchKernelGGL((k_theta_rhs<LatD2Q5II, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
+    case 6: hipLaunchKernelGGL((k_theta_rhs<LatD3Q7, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
+    case 7: hipLaunchKernelGGL((k_theta_rhs<LatD3Q9, T>), gr, bl, 0, st, cur, rhs, d, kc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -402,6 +405,9 @@ hipError_t launch_theta_sweep(const Consts &c, const Grid &g, const T *src, cons
     case 2: hipLaunchKernelGGL((k_theta_sweep<LatD2Q5, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
     case 3: hipLaunchKernelGGL((k_theta_sweep<LatD2Q9, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
     case 4: hipLaunchKernelGGL((k_theta_sweep<LatD3Q19, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
+    case 5: hipLaunchKernelGGL((k_theta_sweep<LatD2Q5II, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
+    case 6: hipLaunchKernelGGL((k_theta_sweep<LatD3Q7, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
+    case 7: hipLaunchKernelGGL((k_theta_sweep<LatD3Q9, T>), gr, bl, 0, st, src, rhs, dst, d, kc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -267,7 +267,7 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx * ty), dim3(256),
                        0, st, cur, prev, out, nx, ny, tx, tx * ty, kc, bc);
-  } else if constexpr (L::D == 3 && EQ == kNSE && !THREE_ST) {
+  } else if constexpr (L::D == 3 && EQ == kNSE && !THREE_ST && L::id == 4) {
     return launch_nse3d_pp<T>(c, g, cur, prev, out, st);
   } else {
     constexpr int TX = 32, TY = (THREE_ST && sizeof(T) == 8) ? 4 : 8;
@@ -351,6 +351,9 @@ hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const 
     case 2: return launch_eq<LatD2Q5, T>(c, g, cur, prev, out, bc, st);
     case 3: return launch_eq<LatD2Q9, T>(c, g, cur, prev, out, bc, st);
     case 4: return launch_eq<LatD3Q19, T>(c, g, cur, prev, out, bc, st);
+    case 5: return launch_eq<LatD2Q5II, T>(c, g, cur, prev, out, bc, st);
+    case 6: return launch_eq<LatD3Q7, T>(c, g, cur, prev, out, bc, st);
+    case 7: return launch_eq<LatD3Q9, T>(c, g, cur, prev, out, bc, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -385,6 +388,7 @@ hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const
     case 1: return picard_l<LatD1Q3, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
     case 2: return picard_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
     case 3: return picard_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+    case 5: return picard_l<LatD2Q5II, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
     default: return hipErrorInvalidValue;
   }
 }

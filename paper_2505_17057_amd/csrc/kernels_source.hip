@@ -301,6 +301,9 @@ hipError_t launch_mmfd_source_step(const Consts &c, const Grid &g, const SourceS
     case 2: return step_l<LatD2Q5, T>(c, g, cur, prev, G, out, sc, st);
     case 3: return step_l<LatD2Q9, T>(c, g, cur, prev, G, out, sc, st);
     case 4: return step_l<LatD3Q19, T>(c, g, cur, prev, G, out, sc, st);
+    case 5: return step_l<LatD2Q5II, T>(c, g, cur, prev, G, out, sc, st);
+    case 6: return step_l<LatD3Q7, T>(c, g, cur, prev, G, out, sc, st);
+    case 7: return step_l<LatD3Q9, T>(c, g, cur, prev, G, out, sc, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -315,6 +318,7 @@ hipError_t launch_mesofd_source_step(const Consts &c, const Grid &g, const Sourc
     case 1: return meso_l<LatD1Q3, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
     case 2: return meso_l<LatD2Q5, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
     case 3: return meso_l<LatD2Q9, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
+    case 5: return meso_l<LatD2Q5II, T>(c, g, cur, prev, G, pop_out, mom_out, sc, st);
     default: return hipErrorInvalidValue;
   }
 }

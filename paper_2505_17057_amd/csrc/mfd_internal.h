@@ -40,6 +40,24 @@ struct LatD3Q19 {
   static constexpr int PR[P] = {1, 2, 3, 7, 8, 11, 12, 15, 16};
 };
 
+struct LatD2Q5II {
+  static constexpr int id = 5, D = 2, Q = 5, P = 2;
+  static constexpr int E[Q][3] = {{0, 0, 0}, {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+  static constexpr int PR[P] = {1, 2};
+};
+struct LatD3Q7 {
+  static constexpr int id = 6, D = 3, Q = 7, P = 3;
+  static constexpr int E[Q][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0}, {0, 0, 1},
+                                  {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}};
+  static constexpr int PR[P] = {1, 2, 3};
+};
+struct LatD3Q9 {
+  static constexpr int id = 7, D = 3, Q = 9, P = 4;
+  static constexpr int E[Q][3] = {{0, 0, 0},    {1, 1, 1},   {1, 1, -1},  {1, -1, 1}, {-1, 1, 1},
+                                  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+  static constexpr int PR[P] = {1, 2, 3, 4};
+};
+
 // ---------------------------------------------------------- configuration
 enum Eq { kLCDE = 0, kBurgers = 1, kNSE = 2 };
 // equation code of the wave equation as given by the caller; its constants

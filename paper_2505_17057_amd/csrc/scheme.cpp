@@ -92,6 +92,21 @@ int lattice_weights(int lattice, double d0, Consts &c) {
       for (int j = 7; j <= 18; ++j) c.w[j] = we;
       break;
     }
+    case MFD_D2Q5II:
+      copy_lattice<LatD2Q5II>(c);
+      c.w[0] = 1.0 - d0;
+      for (int j = 1; j <= 4; ++j) c.w[j] = d0 / 4.0;
+      break;
+    case MFD_D3Q7:
+      copy_lattice<LatD3Q7>(c);
+      c.w[0] = 1.0 - d0 - d0 - d0;
+      for (int j = 1; j <= 6; ++j) c.w[j] = d0 / 2.0;
+      break;
+    case MFD_D3Q9:
+      copy_lattice<LatD3Q9>(c);
+      c.w[0] = 1.0 - d0;
+      for (int j = 1; j <= 8; ++j) c.w[j] = d0 / 8.0;
+      break;
     default:
       return MFD_E_ARG;
   }

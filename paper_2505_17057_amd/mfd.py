@@ -39,9 +39,9 @@ MFD_E_BUDGET = -7
 MFD_E_CANCELLED = -8
 MFD_E_TIMEOUT = -9
 
-LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4}
-DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3}
-QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19}
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 FORMS = {"mmfd": 0, "mesofd": 1}
 EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
@@ -221,7 +221,8 @@ def _ptr_of(x):
 class Solver:
     """Owner of one mfd_solver handle (marshalling only)."""
 
-    def __init__(self, lattice, n, dx, precision="fp64", form="mmfd", boundary="periodic"):
+    def __init__(self, lattice, n, dx, precision="fp64", form="mmfd", boundary="periodic",
+                 d0=1.0 / 3.0):
         self.lattice = lattice
         self.dim = DIMS[lattice]
         n = tuple(int(v) for v in n)
@@ -243,7 +244,7 @@ class Solver:
         self.form = form
         self.dtype = np.float64 if precision == "fp64" else np.float32
         self.warnings = []
-        self.check(lib.mfd_set_lattice(self.h, LATTICES[lattice], 1.0 / 3.0), "mfd_set_lattice")
+        self.check(lib.mfd_set_lattice(self.h, LATTICES[lattice], float(d0)), "mfd_set_lattice")
 
     # -------------------------------------------------------------- plumbing
     def check(self, rc, what):

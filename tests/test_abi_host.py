@@ -76,10 +76,16 @@ LIN = [
      (0.875, 0.0, 0.125), (0.125, 0.0, -0.125)),
     ("D3Q19", dict(n=(5, 5, 5), u=(0.1, 0.2, -0.1), K=[[0.2, 0.01, 0.0], [0.01, 0.3, 0.02], [0.0, 0.02, 0.25]],
                    lambda_bar=1), (1.0, 0.0, 0.4), (0.0, -0.4, 0.0)),
+    ("D2Q5II", dict(n=(8, 6), u=(0.1, -0.2), K=[[0.2, 0.0], [0.0, 0.2]], d0=0.4), (1.0, 0.0, 0.0), None),
+    ("D3Q7", dict(n=(4, 5, 6), u=(0.1, 0.2, -0.1), K=[[0.15, 0.0, 0.0], [0.0, 0.15, 0.0], [0.0, 0.0, 0.15]],
+                  d0=0.25), (1.0, 0.0, 0.4), (0.0, -0.4, 0.0)),
+    ("D3Q9", dict(n=(4, 5, 6), u=(0.1, 0.2, -0.1), K=[[0.2, 0.0, 0.0], [0.0, 0.2, 0.0], [0.0, 0.0, 0.2]]),
+     (1.1, -0.2, 0.1), None),
 ]
 
 
-@pytest.mark.parametrize("lat,kw,a,ah", LIN, ids=["d1q3", "d2q9-c2", "d2q9-3l", "d3q19-trt"])
+@pytest.mark.parametrize("lat,kw,a,ah", LIN, ids=["d1q3", "d2q9-c2", "d2q9-3l", "d3q19-trt", "d2q5ii",
+                                                   "d3q7-trt", "d3q9"])
 def test_linear_constant_tables_bitwise(M, lat, kw, a, ah):
     """The library's and the oracle's EDF constants are formed independently
     from the same formulas; FP64 parity requires them to be identical."""
@@ -87,7 +93,7 @@ def test_linear_constant_tables_bitwise(M, lat, kw, a, ah):
     spec = dict(lattice=lat, eq="lcde", a=a, ah=ah or (0, 0, 0), levels=3 if ah else 2,
                 dx=kw.get("dx", 1.0), dt=kw.get("dt", 1.0), **{k: v for k, v in kw.items() if k not in ("dx", "dt")})
     w, ub, tab = O.tables(spec)
-    s = M.Solver(lat, kw["n"], kw.get("dx", 1.0), "fp64", "mmfd")
+    s = M.Solver(lat, kw["n"], kw.get("dx", 1.0), "fp64", "mmfd", d0=kw.get("d0", 1.0 / 3.0))
     s.set_equation("lcde", u=kw["u"], K=kw["K"], lambda_bar=kw.get("lambda_bar", 0))
     s.set_scheme(kind, a, ah, dt=kw.get("dt", 1.0))
     gw, gub, gtab = s.linear_tables()

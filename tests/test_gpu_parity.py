@@ -81,6 +81,27 @@ CASES = [
          kind="three_level", a=TRT[0], ah=TRT[1]),
     dict(name="d2q9-nse-mesofd-trt", lattice="D2Q9", n=(70, 37), eq="nse", rho0=1.0,
          kind="three_level", a=TRT[0], ah=TRT[1], form="mesofd"),
+    # --- the further lattices of Appendix A (single-step kernels; C = 0)
+    dict(name="d2q5ii-lcde", lattice="D2Q5II", n=(67, 33), eq="lcde", u=(0.1, -0.05),
+         K=[[0.2, 0.0], [0.0, 0.2]], d0=0.4, a=(1.0, 0.0, 0.0)),
+    dict(name="d2q5ii-lcde-3l-mesofd", lattice="D2Q5II", n=(40, 31), eq="lcde", u=(0.1, -0.05),
+         K=[[0.2, 0.0], [0.0, 0.2]], d0=0.4, kind="three_level", a=EX13[0], ah=EX13[1],
+         form="mesofd"),
+    dict(name="d2q5ii-burgers", lattice="D2Q5II", n=(70, 37), eq="burgers", dx=0.05, dt=0.01,
+         a=(0.8, -0.6, -0.2)),
+    dict(name="d2q5ii-nse-trt", lattice="D2Q5II", n=(66, 21), eq="nse", rho0=1.0,
+         kind="three_level", a=TRT[0], ah=TRT[1]),
+    dict(name="d3q7-lcde-trt", lattice="D3Q7", n=(35, 19, 13), eq="lcde", u=(0.05, 0.02, -0.03),
+         K=[[0.1, 0.0, 0.0], [0.0, 0.1, 0.0], [0.0, 0.0, 0.1]], d0=0.25, kind="three_level",
+         a=TRT[0], ah=TRT[1]),
+    dict(name="d3q7-burgers-mesofd", lattice="D3Q7", n=(20, 13, 9), eq="burgers", dx=0.05,
+         dt=0.01, d0=0.25, a=(0.8, -0.6, -0.2), form="mesofd"),
+    dict(name="d3q7-nse-trt", lattice="D3Q7", n=(34, 10, 7), eq="nse", rho0=1.0, d0=0.25,
+         kind="three_level", a=TRT[0], ah=TRT[1]),
+    dict(name="d3q9-lcde", lattice="D3Q9", n=(35, 19, 13), eq="lcde", u=(0.05, 0.02, -0.03),
+         K=[[0.15, 0.0, 0.0], [0.0, 0.15, 0.0], [0.0, 0.0, 0.15]], a=(1.1, -0.2, 0.1)),
+    dict(name="d3q9-nse-trt", lattice="D3Q9", n=(20, 13, 9), eq="nse", rho0=1.0,
+         kind="three_level", a=TRT[0], ah=TRT[1]),
     # --- 3D
     dict(name="d3q19-nse-trt", lattice="D3Q19", n=(35, 19, 13), eq="nse", rho0=1.0,
          kind="three_level", a=TRT[0], ah=TRT[1]),
