@@ -109,8 +109,12 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
 #pragma unroll
     for (int f = 0; f < NF; ++f) p[f] = THREE ? prev[f * N + zo + col[0]] : T(0);
   };
-  // the parts of the z pairs (into ring slot `slot`) or of the in-plane pairs
-  auto stage = [&](const T (&m)[2][NF], int slot, bool zpairs) {
+  // binary32: the parts of the thread's own node at plane z stay in
+  // registers (own), those of its z pairs at plane z + 1 in ownn
+  T own[kF32 ? 2 * L3::P : 1], ownn[kF32 ? 2 * L3::P : 1];
+  // the parts of the z pairs (into ring slot `slot`) or of the in-plane pairs;
+  // binary32: the own node's also into keep (when given)
+  auto stage = [&](const T (&m)[2][NF], int slot, bool zpairs, T *keep) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (s == 0 || has_halo) {
@@ -123,11 +127,19 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
               if (zpairs) {
                 zat(slot, 2 * zslot(P), hy[s], hx[s]) = g[2 * P];
                 zat(slot, 2 * zslot(P) + 1, hy[s], hx[s]) = g[2 * P + 1];
+                if (s == 0 && keep) {
+                  keep[2 * P] = g[2 * P];
+                  keep[2 * P + 1] = g[2 * P + 1];
+                }
               }
             } else {
               if (!zpairs) {
                 iat(2 * islot(P), hy[s], hx[s]) = g[2 * P];
                 iat(2 * islot(P) + 1, hy[s], hx[s]) = g[2 * P + 1];
+                if (s == 0 && keep) {
+                  keep[2 * P] = g[2 * P];
+                  keep[2 * P + 1] = g[2 * P + 1];
+                }
               }
             }
           });
@@ -156,15 +168,15 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
 
   // ring slot of plane z0 - 1 + k is k % 3
   load(z0 - 1, mn, pn);
-  stage(mn, 0, true);
+  stage(mn, 0, true, nullptr);
   load(z0, mc, pc);
-  stage(mc, 1, true);
+  stage(mc, 1, true, kF32 ? own : nullptr);
   load(z0 + 1, mn, pn);
   for (int z = z0; z < z1; ++z) {
     const int rel = z - z0;
     const int sm = rel % 3, s0 = (rel + 1) % 3, sp = (rel + 2) % 3;
-    stage(mc, 0, false);  // in-plane parts of plane z
-    stage(mn, sp, true);  // z parts of plane z + 1
+    stage(mc, 0, false, kF32 ? own : nullptr);  // in-plane parts of plane z
+    stage(mn, sp, true, kF32 ? ownn : nullptr);  // z parts of plane z + 1
     // moments of plane z + 1 for the next pass; plane z + 2 in flight
     T cc[NF], pcc[NF];
 #pragma unroll
@@ -200,10 +212,7 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
       auto ath = [&](int, int, int, int) { return T(0); };
       T oc[NF];
       if constexpr (kF32) {
-        T g0[2 * L3::P];
-#pragma unroll
-        for (int q = 0; q < 2 * L3::P; ++q) g0[q] = at(q, 0, 0, 0);
-        nse32_node<L3, THREE>(at, g0, cc, pcc, oc, kc);
+        nse32_node<L3, THREE>(at, own, cc, pcc, oc, kc);
       } else {
         mmfd_node<L3, kNSE, THREE, false, T, false, true>(at, ath, cc, pcc, oc, kc);
       }
@@ -212,6 +221,16 @@ __global__ __launch_bounds__(TX *TY) void k_nse3d_pp(const T *__restrict__ cur,
       for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
     }
     __syncthreads();
+    if constexpr (kF32) {
+      // the z pairs' parts of plane z + 1 become the current plane's
+      static_for<L3::P>([&](auto PI) {
+        constexpr int P = decltype(PI)::value;
+        if constexpr (zpair(P)) {
+          own[2 * P] = ownn[2 * P];
+          own[2 * P + 1] = ownn[2 * P + 1];
+        }
+      });
+    }
   }
 }
 
