@@ -353,9 +353,13 @@ def bench_source(M, torch, I, stream, steps=500):
             s.set_state(ex["phim"].astype(s.dtype), level=1)
             s.set_source(ex["G"], ex["lam"], (1.5, 0.0, 0.0), (-0.5, 0.0, 0.0), ex["u"])
         start()
+        if form == "mmfd":
+            s.autotune()  # blocked source plans (G staged once per launch) or single steps
+            start()
         s.step(20)
         start()
         ms = timed(torch, lambda: s.step(steps))
+        plan = s.launch_plan()
         finals[prec, form] = s.get_state().astype(np.float64)
         s.close()
         g = ex["n"][0] * ex["n"][1] * steps / (ms * 1e-3) / 1e9
@@ -364,7 +368,9 @@ def bench_source(M, torch, I, stream, steps=500):
         if form == "mmfd":
             bpl = 4 * es  # read t, t - dt and G; write t + dt
             out[key] = dict(glups=round(g, 2), alg_gbs=round(g * bpl, 1),
-                            frac_hbm=round(g * bpl / HBM_PEAK_GBS, 4), bytes_per_lup=bpl)
+                            frac_hbm_algorithmic=round(g * bpl / HBM_PEAK_GBS, 4),
+                            bytes_per_lup=bpl, time_steps_per_launch=plan[0],
+                            window_rows=plan[1], window_cols=plan[2])
         else:
             # the population form's own bytes: read and write the 9 populations, read G
             bpl = (2 * 9 + 1) * es

@@ -19,17 +19,20 @@ namespace mfd {
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int, int64_t, int64_t, int64_t, int>;
+using Key = std::tuple<int, int, int, int, int, int, int64_t, int64_t, int64_t, int, int>;
 std::mutex g_mu;
 std::map<Key, TbPlan> g_cache;
 
 Key key_of(const Solver &s) {
   return Key(s.consts.lattice, s.consts.eq, s.grid.form, s.grid.precision, s.consts.three,
-             s.consts.three_stencil, s.G.n[0], s.G.n[1], s.G.n[2], s.dirichlet ? 1 : 0);
+             s.consts.three_stencil, s.G.n[0], s.G.n[1], s.G.n[2], s.dirichlet ? 1 : 0,
+             s.src_on ? 1 : 0);
 }
 
 bool tunable(const Solver &s) {
   if (s.cfg.kind == MFD_THETA) return false;
+  // with a source term: the blocked MMFD source step (2D linear CDE)
+  if (s.src_on) return s.grid.form == MFD_MMFD && s.consts.dim == 2 && tb_equation_supported(s.consts);
   if (s.grid.form == MFD_MESOFD)
     return s.consts.dim == 2 && !s.consts.three && (s.consts.eq == kLCDE || s.consts.eq == kBurgers);
   return tb_equation_supported(s.consts);
@@ -53,7 +56,8 @@ int default_h(const Solver &s, int tb) {
 }  // namespace
 
 bool Solver::plan_supported(const TbPlan &p) const {
-  if (cfg.kind == MFD_THETA || src_on) return false;
+  if (cfg.kind == MFD_THETA) return false;
+  if (src_on) return grid.form == MFD_MMFD && source_tb_supported(consts, G, p, (int)elem());
   // Dirichlet nodes are set by the 64-column windows (the in-place 128-column
   // window of the linear CDE has no boundary handling)
   if (dirichlet && (p.w != 64 || p.tb > kMaxBcSteps)) return false;
@@ -62,18 +66,20 @@ bool Solver::plan_supported(const TbPlan &p) const {
 }
 
 TbPlan Solver::effective_plan() const {
-  if (!tunable(*this) || src_on) return TbPlan{1, 0};
+  if (!tunable(*this)) return TbPlan{1, 0};
   if (tb == 1) return TbPlan{1, 0};
+  // a plan chosen before a source term was set may not suit the source step
+  // (128-column windows): then the default window of the same depth
   if (tb > 1) {
-    if (tuned.tb == tb) return tuned;
+    if (tuned.tb == tb && plan_supported(tuned)) return tuned;
     const int h = default_h(*this, tb);
     return h ? TbPlan{tb, h} : TbPlan{1, 0};
   }
-  if (tuned.tb > 0) return tuned;
+  if (tuned.tb > 0 && plan_supported(tuned)) return tuned;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key_of(*this));
-    if (it != g_cache.end()) return it->second;
+    if (it != g_cache.end() && plan_supported(it->second)) return it->second;
   }
   const int h = default_h(*this, 4);
   return h ? TbPlan{4, h} : TbPlan{1, 0};

@@ -27,6 +27,7 @@
 #include "mesofd_node.h"
 #include "mfd_internal.h"
 #include "mmfd_node.h"
+#include "tb_window.h"
 
 namespace mfd {
 
@@ -42,15 +43,16 @@ struct SrcC {
   T b[3], bh[3];
 };
 
-// the source term at one node; g(dz, dy, dx) reads G at the node's neighbour
+// the source term at one node; g(dz, dy, dx) reads G at the node's
+// neighbour; sig_t, sig_m the factors exp(lambda t) of the step's two levels
 template <class L, typename T, class Gat>
-__device__ __forceinline__ T source_at(const Gat &g, const SrcC<T> &sc) {
+__device__ __forceinline__ T source_at(const Gat &g, const SrcC<T> &sc, T sig_t, T sig_m) {
   const T g0 = g(0, 0, 0);
-  const T sv = sc.B0 * (sc.sig_t * g0) + sc.Bh0 * (sc.sig_m * g0);
+  const T sv = sc.B0 * (sig_t * g0) + sc.Bh0 * (sig_m * g0);
   T sa = T(0);
 #pragma unroll
   for (int lev = 0; lev < 2; ++lev) {
-    const T sig = lev == 0 ? sc.sig_t : sc.sig_m;
+    const T sig = lev == 0 ? sig_t : sig_m;
     const T cp = lev == 0 ? sc.bp : sc.bhp, cm = lev == 0 ? sc.bm : sc.bhm;
     const T s0 = sig * g0;
 #pragma unroll
@@ -66,6 +68,35 @@ __device__ __forceinline__ T source_at(const Gat &g, const SrcC<T> &sc) {
   }
   return sc.dt * (sv + sa);
 }
+template <class L, typename T, class Gat>
+__device__ __forceinline__ T source_at(const Gat &g, const SrcC<T> &sc) {
+  return source_at<L, T>(g, sc, sc.sig_t, sc.sig_m);
+}
+
+// the source term as a hook of the blocked window (tb_window.h): G staged
+// once per launch beside the levels (a static field), each step's factors
+// from sig[]: step t of the launch reads level n0 + t - 1, so sig_t =
+// sig[t] and sig_m = sig[t - 1] with sig[k] = exp(lambda (n0 + k - 1) dt)
+template <class L, typename T>
+struct SrcTbHook {
+  static constexpr int kExtra = 1;
+  const T *G;
+  SrcC<T> sc;
+  T sig[kMaxBcSteps + 1];
+  __device__ __forceinline__ void load(T *extra, int W, int H, int x0, int y0, int nx, int ny,
+                                       int tid, int nt) const {
+    for (int i = tid; i < W * H; i += nt) {
+      int gx = x0 + (i % W), gy = y0 + i / W;
+      gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+      gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+      extra[i] = G[(int64_t)gy * nx + gx];
+    }
+  }
+  __device__ __forceinline__ T apply(int t, const T *extra, int W, int y, int x, T v) const {
+    auto g = [&](int, int dy, int dx) { return extra[(y + dy) * W + x + dx]; };
+    return v + source_at<L, T>(g, sc, sig[t], sig[t - 1]);
+  }
+};
 
 // 1D / 2D fused step + source over one TX x TY tile per workgroup
 template <class L, bool THREE, bool THREE_ST, int TX, int TY, typename T>
@@ -331,6 +362,86 @@ template hipError_t launch_mesofd_source_step<double>(const Consts &, const Grid
                                                       const SourceSpec &, int64_t, const double *,
                                                       const double *, double *, double *,
                                                       const double *, hipStream_t);
+// ------------------------------------------------------------ blocked
+// Linear CDE with the source on D2Q5 / D2Q9, MMFD, TB steps per launch: the
+// blocked window of tb_window.h with G staged beside the levels; each step's
+// value is the plain step's plus its source term, as in the one-step launch.
+template <class L, bool THREE, bool THREE_ST, int W, int RG, typename T>
+__global__ __launch_bounds__(W *RG) void k_lcde_source_tb(const T *__restrict__ cur,
+                                                         const T *__restrict__ prev,
+                                                         T *__restrict__ out_cur,
+                                                         T *__restrict__ out_prev, int nx, int ny,
+                                                         int H, int TB, int tiles_x, int ntiles,
+                                                         KC<T> kc, SrcTbHook<L, T> hook) {
+  extern __shared__ unsigned char smem_srctb[];
+  T *lds = reinterpret_cast<T *>(smem_srctb);  // [levels + G][H][W]
+  const int TX = W - 2 * TB, TY = H - 2 * TB;
+  const int tile = xcd_remap_tb(blockIdx.x, ntiles);
+  const int x0 = (tile % tiles_x) * TX - TB, y0 = (tile / tiles_x) * TY - TB;
+  tb_window<L, kLCDE, THREE, THREE_ST, W, 8, false, false, T, SrcTbHook<L, T>>(
+      cur, prev, out_cur, out_prev, nx, ny, H, TB, TB, x0, y0, kc, lds, nullptr, hook);
+}
+
+namespace {
+template <class L, bool THREE, bool THREE_ST, typename T>
+hipError_t src_tb_cfg(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n0,
+                      const TbPlan &pl, const T *cur, const T *prev, T *oc, T *op, const T *G,
+                      hipStream_t st) {
+  constexpr int W = 64;
+  SrcTbHook<L, T> hook;
+  hook.G = G;
+  hook.sc = src_consts<T>(c, s, n0);
+  for (int k = 0; k <= pl.tb; ++k)
+    hook.sig[k] = (T)std::exp(s.lambda * ((double)(n0 + k - 1) * s.dt));
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  const int TX = W - 2 * pl.tb, TY = pl.h - 2 * pl.tb;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const size_t lds = (size_t)((THREE ? 3 : 2) + 1) * pl.h * W * sizeof(T);
+  auto fn = k_lcde_source_tb<L, THREE, THREE_ST, W, 8, T>;
+  hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(tx * ty), dim3(W * 8), lds, st, cur, prev, oc, op, nx, ny, pl.h,
+                     pl.tb, tx, tx * ty, make_kc<T>(c), hook);
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t src_tb_l(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n0,
+                    const TbPlan &pl, const T *cur, const T *prev, T *oc, T *op, const T *G,
+                    hipStream_t st) {
+  if (!c.three) return src_tb_cfg<L, false, false, T>(c, g, s, n0, pl, cur, prev, oc, op, G, st);
+  if (!c.three_stencil)
+    return src_tb_cfg<L, true, false, T>(c, g, s, n0, pl, cur, prev, oc, op, G, st);
+  return src_tb_cfg<L, true, true, T>(c, g, s, n0, pl, cur, prev, oc, op, G, st);
+}
+}  // namespace
+
+bool source_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem) {
+  if (c.dim != 2 || (c.lattice != 2 && c.lattice != 3) || c.eq != kLCDE) return false;
+  if (pl.w != 64 || pl.tb < 2 || pl.tb > kMaxBcSteps) return false;
+  if (!tb_plan_valid(pl, (c.three ? 3 : 2) + 1, elem)) return false;
+  return g.n[0] >= pl.w && g.n[1] >= pl.h;
+}
+
+template <typename T>
+hipError_t launch_mmfd_source_tb(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n0,
+                                 const TbPlan &pl, const T *cur, const T *prev, T *out_cur,
+                                 T *out_prev, const T *G, hipStream_t st) {
+  if (!source_tb_supported(c, g, pl, (int)sizeof(T))) return hipErrorInvalidValue;
+  if (c.lattice == 3) return src_tb_l<LatD2Q9, T>(c, g, s, n0, pl, cur, prev, out_cur, out_prev, G, st);
+  return src_tb_l<LatD2Q5, T>(c, g, s, n0, pl, cur, prev, out_cur, out_prev, G, st);
+}
+
+template hipError_t launch_mmfd_source_tb<float>(const Consts &, const Grid &, const SourceSpec &,
+                                                 int64_t, const TbPlan &, const float *,
+                                                 const float *, float *, float *, const float *,
+                                                 hipStream_t);
+template hipError_t launch_mmfd_source_tb<double>(const Consts &, const Grid &, const SourceSpec &,
+                                                  int64_t, const TbPlan &, const double *,
+                                                  const double *, double *, double *,
+                                                  const double *, hipStream_t);
+
 template hipError_t launch_mmfd_source_step<float>(const Consts &, const Grid &,
                                                    const SourceSpec &, int64_t, const float *,
                                                    const float *, float *, const float *,

@@ -198,6 +198,34 @@ int Solver::step_t(int64_t nsteps) {
       prev_gap = 1;
       return MFD_OK;
     }
+    // 2D: blocks of d steps in the blocked window (G staged once per launch),
+    // then single steps for the remainder
+    const TbPlan pl = effective_plan();
+    if (pl.tb > 1 && source_tb_supported(consts, G, pl, (int)sizeof(T))) {
+      const int d = pl.tb;
+      const int64_t nblk = nsteps / d;
+      for (int64_t b = 0; b < nblk; ++b) {
+        hipError_t e;
+        if (!consts.three) {
+          e = launch_mmfd_source_tb<T>(consts, G, src, steps_done, pl, B[ic], nullptr, B[ip],
+                                       nullptr, (const T *)d_src, stream);
+          if (e != hipSuccess) return hip(e, "blocked source launch");
+          std::swap(ic, ip);
+        } else {
+          e = launch_mmfd_source_tb<T>(consts, G, src, steps_done, pl, B[ic], B[ip], B[io], B[ix],
+                                       (const T *)d_src, stream);
+          if (e != hipSuccess) return hip(e, "blocked source launch");
+          const int oc = ic, op = ip;
+          ic = io;
+          ip = ix;
+          io = oc;
+          ix = op;
+        }
+        steps_done += d;
+      }
+      nsteps -= nblk * d;
+      if (nblk > 0) prev_gap = consts.three ? 1 : d;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
       T *out = consts.three ? B[io] : B[ip];
       hipError_t e = launch_mmfd_source_step<T>(consts, G, src, steps_done, B[ic], B[ip], out,
@@ -213,7 +241,7 @@ int Solver::step_t(int64_t nsteps) {
       }
       ++steps_done;
     }
-    prev_gap = 1;
+    if (nsteps > 0) prev_gap = 1;
     return MFD_OK;
   }
   if (cfg.kind != MFD_THETA && wave1d_applies(consts, G) && nsteps > 1) {

@@ -216,6 +216,16 @@ struct TbPlan {
 size_t tb_lds_bytes(const Consts &c, const TbPlan &pl, int elem);
 // plan limits (depth, window height, LDS) for `levels` LDS levels
 bool tb_plan_valid(const TbPlan &pl, int levels, int elem);
+
+// blocked MMFD steps of the linear CDE with the source term (D2Q5 / D2Q9,
+// 64-column windows, 2 .. kMaxBcSteps steps per launch): the launch starts
+// from level n0 (cur; prev = level n0 - 1 for three-level schemes) and
+// writes n0 + tb (out_cur) and, three-level, n0 + tb - 1 (out_prev)
+bool source_tb_supported(const Consts &c, const Grid &g, const TbPlan &pl, int elem);
+template <typename T>
+hipError_t launch_mmfd_source_tb(const Consts &c, const Grid &g, const SourceSpec &s, int64_t n0,
+                                 const TbPlan &pl, const T *cur, const T *prev, T *out_cur,
+                                 T *out_prev, const T *G, hipStream_t st);
 // equations / lattices the blocked kernels implement
 bool tb_equation_supported(const Consts &c);
 // the single-grid blocked kernel can run this plan on this grid

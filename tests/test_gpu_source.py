@@ -8,7 +8,10 @@
 * binary32 stays within 1e-5 (relative L2) of the binary64 oracle;
 * the MesoFD form (1D / 2D): moments and populations equal the oracle value
   for value;
-* a launch plan set before the source is not used while it is set;
+* blocked source steps (several steps per launch, G staged once) equal the
+  oracle value for value under every plan, split over calls;
+* a launch plan the source step cannot take (128-column windows) is not
+  used while the source is set;
 * 3D MesoFD, other equations, the theta scheme and batches refuse it.
 """
 import math
@@ -141,6 +144,9 @@ def test_source_fp32_tolerance(M, scheme):
 
 
 def test_source_overrides_plan(M):
+    """A 128-column plan set before the source is not used while the source
+    is set (the source step takes 64-column windows of the same depth), and
+    comes back when the source is cleared."""
     case = _case("D2Q9", "srt")
     rng = np.random.default_rng(43)
     cur = rand_state(case, rng)
@@ -148,18 +154,54 @@ def test_source_overrides_plan(M):
     want = _oracle(case, cur, cur, 9, G, -0.2, COEFS["example1"], (0.1, 0.3))
     got, plan = _gpu(M, case, cur, cur, (9,), G, -0.2, COEFS["example1"], (0.1, 0.3),
                      plan=(4, 40, 128))
-    assert plan == (1, 0, 0)
+    assert plan[0] == 4 and plan[2] == 64
     assert np.array_equal(got, want)
     s = make_solver(M, case, "fp64")
     s.set_plan(4, 40, 128)
     s.set_state(cur)
     s.set_source(G)
-    assert s.launch_plan() == (1, 0, 0)
+    assert s.launch_plan()[2] == 64
     with pytest.raises(M.MfdError):
         s.set_plan(4, 40, 128)
     s.clear_source()
     assert s.launch_plan() == (4, 40, 128)
     s.close()
+
+
+SRC_PLANS = [(1,), (2, 32), (4, 48), (6, 64), (8, 72), (16, 40)]
+
+
+@pytest.mark.parametrize("plan", SRC_PLANS, ids=lambda p: "tb%d" % p[0])
+@pytest.mark.parametrize("lat,scheme", [("D2Q9", "srt"), ("D2Q9", "ex1-case2"), ("D2Q5", "ex1-case3"),
+                                        ("D2Q9", "ex1-case3")])
+def test_source_blocked_fp64_bitwise(M, lat, scheme, plan):
+    """The blocked source step (G staged once per launch, each step's factors
+    exp(lambda t) from its own level's time): binary64 equal to the oracle
+    for every plan, with blocks and a remainder split over calls."""
+    case = _case(lat, scheme)
+    print("case blocked source", lat, scheme, plan, flush=True)
+    rng = np.random.default_rng(46)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    v = tuple(rng.uniform(-0.5, 0.5, 2))
+    want = _oracle(case, cur, prev, 37, G, 0.7, COEFS["random"], v)
+    got, seen = _gpu(M, case, cur, prev, (5, 32), G, 0.7, COEFS["random"], v,
+                     plan=plan if len(plan) == 1 else (plan[0], plan[1], 64))
+    assert seen[0] == plan[0]
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+@pytest.mark.parametrize("scheme", ["srt", "ex1-case2"])
+def test_source_blocked_fp32_tolerance(M, scheme):
+    case = _case("D2Q9", scheme)
+    rng = np.random.default_rng(47)
+    cur, prev = rand_state(case, rng), rand_state(case, rng)
+    G = rng.standard_normal(cur.size)
+    want = _oracle(case, cur, prev, 40, G, 0.4, COEFS["example1"], (0.2, 0.1))
+    got, seen = _gpu(M, case, cur, prev, (40,), G, 0.4, COEFS["example1"], (0.2, 0.1), "fp32",
+                     plan=(6, 64, 64))
+    assert seen[0] == 6
+    assert rel_l2(got, want) < 1e-5
 
 
 def test_source_rejections(M):
