@@ -38,6 +38,169 @@ __device__ __forceinline__ float nse_from_left(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
+// The eight multiply-adds of one pair p whose direction has an x component,
+// on two accumulators (a: density, m: momentum), with the terms that need
+// the lane beside (dx = -1 / +1) reading it through DPP inside the
+// multiply-add:
+//   a += cP pP;  a += ncP dp[lane + dx];  a += cM mP;  a += cM dm[lane + dx]
+//   m += sM pP;  m += sM dp[lane + dx];   m += sP mP;  m += nsP dm[lane + dx]
+// AF / MF: a / m start here (the first term is a product).  One block, so
+// that one pair of wait states covers every shifted read: dp and dm are
+// written before the block and not inside it.  All operands are in VGPRs.
+#define NSE_DPP_L "wave_shr:1 row_mask:0xf bank_mask:0xf"
+#define NSE_DPP_R "wave_shl:1 row_mask:0xf bank_mask:0xf"
+#define NSE_PAIR_ASM(A1, M1, SH)                                            \
+  "s_nop 1\n\t" A1 "\n\t" M1 "\n\t"                                        \
+  "v_fmac_f32_dpp %0, %4, %7 " SH "\n\t"                                    \
+  "v_fmac_f32_dpp %1, %4, %9 " SH "\n\t"                                    \
+  "v_fmac_f32 %0, %8, %3\n\t"                                               \
+  "v_fmac_f32 %1, %10, %3\n\t"                                              \
+  "v_fmac_f32_dpp %0, %5, %8 " SH "\n\t"                                    \
+  "v_fmac_f32_dpp %1, %5, %11 " SH
+#define NSE_A_MUL "v_mul_f32 %0, %6, %2"
+#define NSE_A_FMA "v_fmac_f32 %0, %6, %2"
+#define NSE_M_MUL "v_mul_f32 %1, %9, %2"
+#define NSE_M_FMA "v_fmac_f32 %1, %9, %2"
+#define NSE_PAIR_IN                                                                    \
+  "v"(pP), "v"(mP), "v"(dp), "v"(dm), "v"(cP), "v"(ncP), "v"(cM), "v"(sM), "v"(sP), \
+      "v"(nsP)
+
+template <int DX, bool AF, bool MF>
+__device__ __forceinline__ void nse_pair_sh(float &a, float &m, float pP, float mP, float dp,
+                                            float dm, float cP, float ncP, float cM, float sM,
+                                            float sP, float nsP) {
+  static_assert(DX == -1 || DX == 1, "lane shift by one");
+  if constexpr (DX < 0) {
+    if constexpr (AF && MF)
+      asm(NSE_PAIR_ASM(NSE_A_MUL, NSE_M_MUL, NSE_DPP_L) : "=&v"(a), "=&v"(m) : NSE_PAIR_IN);
+    else if constexpr (AF)
+      asm(NSE_PAIR_ASM(NSE_A_MUL, NSE_M_FMA, NSE_DPP_L) : "=&v"(a), "+v"(m) : NSE_PAIR_IN);
+    else if constexpr (MF)
+      asm(NSE_PAIR_ASM(NSE_A_FMA, NSE_M_MUL, NSE_DPP_L) : "+v"(a), "=&v"(m) : NSE_PAIR_IN);
+    else
+      asm(NSE_PAIR_ASM(NSE_A_FMA, NSE_M_FMA, NSE_DPP_L) : "+v"(a), "+v"(m) : NSE_PAIR_IN);
+  } else {
+    if constexpr (AF && MF)
+      asm(NSE_PAIR_ASM(NSE_A_MUL, NSE_M_MUL, NSE_DPP_R) : "=&v"(a), "=&v"(m) : NSE_PAIR_IN);
+    else if constexpr (AF)
+      asm(NSE_PAIR_ASM(NSE_A_MUL, NSE_M_FMA, NSE_DPP_R) : "=&v"(a), "+v"(m) : NSE_PAIR_IN);
+    else if constexpr (MF)
+      asm(NSE_PAIR_ASM(NSE_A_FMA, NSE_M_MUL, NSE_DPP_R) : "+v"(a), "=&v"(m) : NSE_PAIR_IN);
+    else
+      asm(NSE_PAIR_ASM(NSE_A_FMA, NSE_M_FMA, NSE_DPP_R) : "+v"(a), "+v"(m) : NSE_PAIR_IN);
+  }
+}
+#undef NSE_PAIR_IN
+#undef NSE_M_FMA
+#undef NSE_M_MUL
+#undef NSE_A_FMA
+#undef NSE_A_MUL
+#undef NSE_PAIR_ASM
+#undef NSE_DPP_R
+#undef NSE_DPP_L
+
+// nse32_node in the register window.  Each node holds the differences to
+// its +e_p neighbours (dc: this row; dp: the row before), and its difference
+// to x - e_p is minus that neighbour's (exactly: d and -d round alike).  The
+// sign goes into the constants, c * (-d) = (-c) * d exactly, so every term
+// keeps its value and its place in the sums of nse32_node, and the results
+// agree with it bit for bit; the terms that read the lane beside take the
+// shift inside their multiply-add (nse_pair_sh).  vc: nse32_node's per-pair
+// constants, with the negated ones, in VGPRs.
+struct NseLaneC {
+  float cP[4], ncP[4], cM[4], sMp[4], sPp[4], nsPp[4];
+};
+
+template <class L>
+__device__ __forceinline__ NseLaneC nse_lane_consts(const KC<float> &kc) {
+  static_assert(L::P <= 4, "2D pair lattices");
+  NseLaneC v;
+  static_for<L::P>([&](auto PI) {
+    constexpr int P = decltype(PI)::value;
+    constexpr int J = L::PR[P];
+    const float cP = kc.nw[P][0], cM = kc.nw[P][1], bP = kc.nw[P][2], bM = kc.nw[P][3];
+    float sP = bP, sM = bM;
+    if constexpr (nse32_ncomp<L, P>() == 1) {
+      constexpr int a = L::E[J][0] != 0 ? 0 : 1;
+      if constexpr (L::E[J][a] < 0) {
+        sP = -bP;
+        sM = -bM;
+      }
+    }
+    v.cP[P] = cP;
+    v.ncP[P] = -cP;
+    v.cM[P] = cM;
+    v.sMp[P] = sM;
+    v.sPp[P] = sP;
+    v.nsPp[P] = -sP;
+  });
+  // keep them in VGPRs: a DPP multiply-add takes no scalar operand
+  float *f = &v.cP[0];
+#pragma unroll
+  for (int i = 0; i < 6 * 4; ++i) asm volatile("" : "+v"(f[i]));
+  return v;
+}
+
+template <class L, bool THREE>
+__device__ __forceinline__ void nse32_node_lane(const float *dc, const float *dp,
+                                                const float *cur_c, const float *prev_c,
+                                                float *out_c, const KC<float> &kc,
+                                                const NseLaneC &vc) {
+  constexpr int D = L::D;
+  float acc = 0.f, mo[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mo[a] = 0.f;
+  static_for<L::P>([&](auto PI) {
+    constexpr int P = decltype(PI)::value;
+    constexpr int J = L::PR[P];
+    constexpr int ex = L::E[J][0], ey = L::E[J][1];
+    constexpr bool single = nse32_ncomp<L, P>() == 1;
+    constexpr int sa = ex != 0 ? 0 : 1;  // the component of a single-component pair
+    const float pP = dc[2 * P], mP = dc[2 * P + 1];
+    // the neighbour x - e_p's differences (negated through the constants)
+    const float *dn = ey == 1 ? dp : dc;
+    const float dpP = dn[2 * P], dmP = dn[2 * P + 1];
+    float b;  // the momentum sum of a pair with two components
+    if constexpr (ex != 0) {
+      constexpr bool mf = !single || nse32_first_pair<L>(sa) == P;
+      nse_pair_sh<-ex, P == 0, mf>(acc, single ? mo[sa] : b, pP, mP, dpP, dmP, vc.cP[P],
+                                   vc.ncP[P], vc.cM[P], vc.sMp[P], vc.sPp[P], vc.nsPp[P]);
+    } else {
+      // rho: cP pP + cP pM + cM mP - cM mM, pM = -dpP, mM = -dmP
+      if constexpr (P == 0) acc = vc.cP[P] * pP;
+      else acc = __builtin_fmaf(vc.cP[P], pP, acc);
+      acc = __builtin_fmaf(vc.ncP[P], dpP, acc);
+      acc = __builtin_fmaf(vc.cM[P], mP, acc);
+      acc = __builtin_fmaf(vc.cM[P], dmP, acc);
+      float &m = single ? mo[sa] : b;
+      if constexpr (!single || nse32_first_pair<L>(sa) == P) m = vc.sMp[P] * pP;
+      else m = __builtin_fmaf(vc.sMp[P], pP, m);
+      m = __builtin_fmaf(vc.sMp[P], dpP, m);
+      m = __builtin_fmaf(vc.sPp[P], mP, m);
+      m = __builtin_fmaf(vc.nsPp[P], dmP, m);
+    }
+    if constexpr (!single) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        if (L::E[J][a] == 0) continue;
+        const bool pos = L::E[J][a] > 0;
+        if (nse32_first_pair<L>(a) == P) mo[a] = pos ? b : -b;
+        else mo[a] = pos ? mo[a] + b : mo[a] - b;
+      }
+    }
+  });
+#pragma unroll
+  for (int f = 0; f <= D; ++f) {
+    const float c = cur_c[f], d = f == 0 ? acc : mo[f - 1];
+    if constexpr (THREE) {
+      const float t = __builtin_fmaf(f == 0 ? -kc.Ah0t : -kc.Abh0t, c - prev_c[f], d);
+      out_c[f] = c + t;
+    } else {
+      out_c[f] = __builtin_fmaf(f == 0 ? kc.A0t : kc.Ab0t, c, d);
+    }
+  }
+}
+
 __device__ __forceinline__ int xcd_remap_nse(int bid, int nblk) {
   const int q = nblk >> 3, r = nblk & 7;
   const int x = bid & 7, k = bid >> 3;
@@ -165,6 +328,11 @@ __device__ __forceinline__ void nse_window(const T *__restrict__ cur, const T *_
 // by step parity, so one barrier a step suffices).  Lanes at the wavefront's
 // edges read 0 for their missing neighbour; like every node outside the
 // step's region their values are not used by any node of the region.
+// Each node forms its differences to its +e_p neighbours once; the node
+// beside (same row, or the next row for pairs with a y component) takes them
+// negated as its differences to x - e_p (nse32_node_lane).  The new level
+// is written over the registers of the oldest one, and two steps per loop
+// turn swap the roles of the two register sets, so nothing is copied.
 template <class L, bool THREE, int RG, bool WRAP_ANY>
 __device__ __forceinline__ void nse_window_reg(const float *__restrict__ cur,
                                                const float *__restrict__ prev,
@@ -202,15 +370,18 @@ __device__ __forceinline__ void nse_window_reg(const float *__restrict__ cur,
     return bnd[par * SLOT + ((g * 2 + end) * NPF + q) * W + lane];
   };
   const int ga = rg > 0 ? rg - 1 : rg, gb = rg < RG - 1 ? rg + 1 : rg;
-#pragma unroll 1
-  for (int t = 1; t <= TBS; ++t) {
+  const NseLaneC vc = nse_lane_consts<L>(kc);
+  // One step: c holds the moments at t - dt, p those at t - 2 dt; the new
+  // level is written over p (the update reads each node's p before), so
+  // the two roles swap from step to step and no register is copied.
+  auto step = [&](int t, float (&c)[R][NF], float (&p)[R][NF]) {
     const int par = t & 1;
     {
       float f[NPF];
-      nse32_parts<L>(cm[0], f, kc);
+      nse32_parts<L>(c[0], f, kc);
 #pragma unroll
       for (int q = 0; q < NPF; ++q) sl(par, rg, 0, q) = f[q];
-      nse32_parts<L>(cm[R - 1], f, kc);
+      nse32_parts<L>(c[R - 1], f, kc);
 #pragma unroll
       for (int q = 0; q < NPF; ++q) sl(par, rg, 1, q) = f[q];
     }
@@ -222,32 +393,75 @@ __device__ __forceinline__ void nse_window_reg(const float *__restrict__ cur,
       pa[q] = sl(par, ga, 1, q);  // the last row of the wavefront above
       pb[q] = sl(par, rg, 0, q);  // this thread's first row
     }
+    // Each node forms the differences to its +e_p neighbour only,
+    // d(x) = G(x + e_p) - G(x); its difference to x - e_p is -d(x - e_p),
+    // exactly, taken from the lane beside (pairs in the row) or from the
+    // previous row's registers (pairs with a y component, which all have
+    // e_y = 1 as representatives).
+    auto shx = [](float v, int dx) {
+      return dx < 0 ? nse_from_left(v) : (dx > 0 ? nse_from_right(v) : v);
+    };
+    float dprev[NPF], dcur[NPF];
+    static_for<L::P>([&](auto PI) {
+      constexpr int P = decltype(PI)::value;
+      constexpr int J = L::PR[P];
+      constexpr int ex = L::E[J][0], ey = L::E[J][1];
+      static_assert(ey == 0 || ey == 1, "pair representatives point up or along x");
+      if constexpr (ey == 1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) dprev[2 * P + h] = shx(pb[2 * P + h], ex) - pa[2 * P + h];
+      }
+    });
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r + 1 < R - 1) {
-        nse32_parts<L>(cm[r + 1], pc, kc);
+        nse32_parts<L>(c[r + 1], pc, kc);
       } else {
 #pragma unroll
         for (int q = 0; q < NPF; ++q) pc[q] = r + 1 == R - 1 ? sl(par, rg, 1, q) : sl(par, gb, 0, q);
       }
+      static_for<L::P>([&](auto PI) {
+        constexpr int P = decltype(PI)::value;
+        constexpr int J = L::PR[P];
+        constexpr int ex = L::E[J][0], ey = L::E[J][1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          dcur[2 * P + h] = shx(ey == 1 ? pc[2 * P + h] : pb[2 * P + h], ex) - pb[2 * P + h];
+          // formed here, before the row's branch, so that the lane shift
+          // stays fused into the subtraction
+          asm("" : "+v"(dcur[2 * P + h]));
+        }
+      });
       const int y = yr + r;
       if (y >= t && y < H - t) {
-        auto at = [&](int q, int, int dy, int dx) {
-          const float v = dy < 0 ? pa[q] : (dy > 0 ? pc[q] : pb[q]);
-          return dx < 0 ? nse_from_left(v) : (dx > 0 ? nse_from_right(v) : v);
-        };
         float oc[NF];
-        nse32_node<L, THREE>(at, pb, cm[r], pm[r], oc, kc);
+        nse32_node_lane<L, THREE>(dcur, dprev, c[r], p[r], oc, kc, vc);
 #pragma unroll
-        for (int q = 0; q < NF; ++q) {
-          pm[r][q] = cm[r][q];
-          cm[r][q] = oc[q];
-        }
+        for (int q = 0; q < NF; ++q) p[r][q] = oc[q];
       }
 #pragma unroll
       for (int q = 0; q < NPF; ++q) {
         pa[q] = pb[q];
         pb[q] = pc[q];
+        dprev[q] = dcur[q];
+      }
+    }
+  };
+  int t = 1;
+#pragma unroll 1
+  for (; t + 1 <= TBS; t += 2) {
+    step(t, cm, pm);
+    step(t + 1, pm, cm);
+  }
+  if (t <= TBS) {
+    step(t, cm, pm);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const float v = pm[r][q];
+        pm[r][q] = cm[r][q];
+        cm[r][q] = v;
       }
     }
   }
