@@ -93,7 +93,7 @@ extern "C" {
 #define MFD_DIRICHLET 1 /* 2D MMFD: edge nodes hold prescribed values        */
 
 #define MFD_TWO_LEVEL 0   /* explicit, level t only (ah = 0)                 */
-#define MFD_THETA 1       /* two-level theta scheme, Eq. (GCN), LCDE only   */
+#define MFD_THETA 1       /* two-level theta scheme, Eq. (GCN): LCDE, Burgers (beta = 1), NSE */
 #define MFD_THREE_LEVEL 2 /* explicit, levels t and t - dt, Eq. (3layer-1)   */
 
 /* presets of the three-level family (after Eq. (4-2-00)) and Eq. (LMMFD-2-2) */
@@ -162,8 +162,14 @@ int mfd_set_equation(mfd_solver *s, int eq, const mfd_eq_params *p);
  * a[k+1] (k = -1, 0, 1) for level t and ah[k+1] for level t - dt
  * (three-level notation of Eq. (3layer-1); ah is ignored unless
  * MFD_THREE_LEVEL), optional momentum set ab / abh of Eq. (2-4) (NULL: equal
- * to a / ah), theta in [0,1] with theta_iters Jacobi sweeps (MFD_THETA) and
- * the time step dt > 0.  Must follow mfd_set_lattice and mfd_set_equation.
+ * to a / ah), theta in [0,1] with theta_iters sweeps (MFD_THETA) and the
+ * time step dt > 0.  The theta step (periodic grids, MMFD form) is solved by
+ * Jacobi sweeps for the linear CDE and by Picard sweeps for Burgers' equation
+ * (beta = 1) and the NSE: each sweep takes the explicit step of the iterate
+ * and moves the own-node coefficient of the linear EDF parts to the left,
+ * per field (density / scalar: 2 sum_p (a_1 + a_-1) w_p; momentum j_a:
+ * 2 sum_{p: e_pa != 0} (ab_1 + ab_-1) w_p / d0); MFD_E_UNSUPPORTED for other
+ * equations.  Must follow mfd_set_lattice and mfd_set_equation.
  * Returns MFD_W_INCONSISTENT if A00 != 1 (Eq. (4-2-00a)) and
  * MFD_W_STABILITY_UNPROVEN if the linear(ised) scheme fails the sufficient
  * conditions (Theorem 1 / Corollary 2); both are warnings. */
@@ -192,8 +198,10 @@ int mfd_set_scheme_sets(mfd_solver *s, int kind, const double a[3], const double
  * (0: 8; at most 16), stopping at the first check where
  *     den^2 sum_x (x_k - x_(k-1))^2 <= tol^2 sum_x rhs^2
  * (den (x_k - x_(k-1)) is the residual rhs - (I - (1-theta) L) x_(k-1);
- * den = 1 + (1-theta) 2 sum_p (a_1 + a_-1) ubar+_p; sums in binary64), or at
- * the first check at or beyond theta_iters sweeps (the cap), returning x_k.
+ * den = 1 + (1-theta) 2 sum_p (a_1 + a_-1) ubar+_p; sums in binary64; for
+ * the NSE the two sums run over all fields, each field's squared differences
+ * weighted by its own den^2), or at the first check at or beyond theta_iters
+ * sweeps (the cap), returning x_k.
  * tol = 0 restores the fixed count of theta_iters sweeps.  On 2D D2Q5 / D2Q9
  * grids of at least 64 x 32 nodes the stop is decided on the device (no host
  * round trip per step); other grids check on the host after each chunk.

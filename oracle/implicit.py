@@ -1,28 +1,38 @@
-"""Two-level theta scheme of Eq. (GCN) for the nonlinear scalar equation
-(Burgers' NCDE, beta = 1), solved by Picard iteration with the Jacobi
-splitting of the scheme's linear even part.
+"""Two-level theta scheme of Eq. (GCN) for the nonlinear equations
+(Burgers' NCDE with beta = 1, and the NSE), solved by Picard iteration with
+the Jacobi splitting of the scheme's linear part.
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 
 With S the explicit two-level step map of Eq. (2-2-1) (``orc_mmfd_step``) and
-L(x) = S(x) - A0 x its increment, Eq. (GCN) reads
+L(x) = S(x) - A0 x its increment (per field: A0 for the density or the
+scalar, Ab0 for the momentum), Eq. (GCN) reads
 
     phi^{n+1} = A0 phi^n + theta L(phi^n) + (1 - theta) L(phi^{n+1}).
 
-The even EDF part of Burgers' equation, w_j phi, is linear in phi, so L has
-the diagonal -2 sum_p Cp_p with Cp_p = (a_1 + a_-1) w_p over the opposite
-pairs p (each pair once).  Moving it to the left side gives the iteration
+The EDF's parts are linear in the conserved moments up to the quadratic
+term: w_p phi (the scalar, or the density in F+_p) and (w_p / d0) e_p . j
+(the momentum in F-_p).  Their second differences give L the own-node
+coefficient -dd per field, taken over the opposite pairs p (each pair once,
+in lattice order):
+
+    scalar / density:  dd = 2 sum_p (a_1 + a_-1) w_p
+    momentum j_a:      dd = 2 sum_{p: e_pa != 0} (ab_1 + ab_-1) (w_p / d0)
+
+(e_pa^2 = 1 for every moving velocity of these lattices).  Moving it to the
+left side gives, field by field,
 
     R       = theta S(phi^n) + (1 - theta) (A0 phi^n)
     x_{k+1} = (R + (1 - theta) ((S(x_k) - A0 x_k) + dd x_k)) / den,
-    dd      = 2 sum_p Cp_p,   den = 1 + (1 - theta) dd,
+    den     = 1 + (1 - theta) dd,
 
 started from x_0 = phi^n: the residual of x_k is den (x_{k+1} - x_k), and the
 solve stops after the first chunk of sweeps with
-den^2 sum (x_k - x_{k-1})^2 <= tol^2 sum R^2 (compensated sums), or at the
-first chunk boundary at or beyond the cap.  For the linear CDE the same
-iteration is the Jacobi iteration of the linear theta step.  Every node's
-arithmetic is written out in the order above (one rounding per operation).
+sum_f den_f^2 sum (x_k - x_{k-1})_f^2 <= tol^2 sum_f sum R_f^2 (compensated
+sums per field, added in field order), or at the first chunk boundary at or
+beyond the cap.  For the linear CDE the same iteration is the Jacobi
+iteration of the linear theta step.  Every node's arithmetic is written out
+in the order above (one rounding per operation).
 """
 from __future__ import annotations
 
@@ -35,19 +45,21 @@ def _explicit_spec(spec):
     s = dict(spec)
     s.pop("theta", None)
     s.pop("theta_iters", None)
+    s.pop("abh", None)
     s["levels"] = 2
     s["ah"] = (0.0, 0.0, 0.0)
     return s
 
 
 def picard_constants(spec):
-    """(A0, dd, den) of the iteration; pair sums in lattice pair order."""
+    """(A0, dd, den) of the scalar iteration (the density's for the NSE);
+    pair sums in lattice pair order."""
     a = [float(v) for v in spec["a"]]
     theta = float(spec["theta"])
     th1 = 1.0 - theta
     A0 = (a[0] + a[1]) + a[2]
     ap = a[2] + a[0]
-    _, w, pairs = O.lattice_info(spec["lattice"])
+    _, w, pairs = O.lattice_info(spec["lattice"], float(spec.get("d0", 1.0 / 3.0)))
     sp = 0.0
     for j in pairs:
         sp = sp + ap * float(w[j])
@@ -56,29 +68,64 @@ def picard_constants(spec):
     return A0, dd, den
 
 
+def picard_field_constants(spec):
+    """[(A0, dd, den)] per field: the scalar's, or the NSE's density and
+    momentum components (see the module docstring)."""
+    first = picard_constants(spec)
+    if spec.get("eq") != "nse":
+        return [first]
+    d0 = float(spec.get("d0", 1.0 / 3.0))
+    ab = [float(v) for v in spec.get("ab", spec["a"])]
+    th1 = 1.0 - float(spec["theta"])
+    Ab0 = (ab[0] + ab[1]) + ab[2]
+    abp = ab[2] + ab[0]
+    E, w, pairs = O.lattice_info(spec["lattice"], d0)
+    out = [first]
+    for a in range(O.DIMS[spec["lattice"]]):
+        sj = 0.0
+        for j in pairs:
+            if E[j][a] != 0:
+                sj = sj + abp * (float(w[j]) / d0)
+        dd = 2.0 * sj
+        out.append((Ab0, dd, 1.0 + th1 * dd))
+    return out
+
+
 def theta_picard_solve(spec, cur, tol, chunk, cap):
-    """One theta step of Burgers' equation (beta = 1) by the Picard-Jacobi
-    iteration above; returns (phi^{n+1}, sweeps, converged)."""
-    if spec.get("eq") != "burgers" or float(spec.get("beta", 1.0)) != 1.0:
-        raise ValueError("the Picard theta step is written for Burgers' equation with beta = 1")
+    """One theta step of Burgers' equation (beta = 1) or of the NSE by the
+    Picard-Jacobi iteration above; returns (phi^{n+1}, sweeps, converged)."""
+    eq = spec.get("eq")
+    if not ((eq == "burgers" and float(spec.get("beta", 1.0)) == 1.0) or eq == "nse"):
+        raise ValueError("the Picard theta step is written for Burgers' equation with beta = 1 "
+                         "and for the NSE")
     es = _explicit_spec(spec)
     theta = float(spec["theta"])
     th1 = 1.0 - theta
-    A0, dd, den = picard_constants(spec)
-    inv_den = 1.0 / den
+    consts = picard_field_constants(spec)
+    F = len(consts)
+    N = cur.size // F
+    fields = [slice(f * N, (f + 1) * N) for f in range(F)]
     S0 = O.mmfd_step(es, cur)
-    R = theta * S0 + th1 * (A0 * cur)
-    b2 = O.csum(R * R)
+    R = np.empty_like(cur)
+    b2 = 0.0
+    for sl, (A0, _, _) in zip(fields, consts):
+        R[sl] = theta * S0[sl] + th1 * (A0 * cur[sl])
+        b2 = b2 + O.csum(R[sl] * R[sl])
     x = cur
     k = 0
     while True:
         for _ in range(chunk):
             Sx = O.mmfd_step(es, x)
-            t = (Sx - A0 * x) + dd * x
-            nxt = (R + th1 * t) * inv_den
+            nxt = np.empty_like(x)
+            for sl, (A0, dd, den) in zip(fields, consts):
+                t = (Sx[sl] - A0 * x[sl]) + dd * x[sl]
+                nxt[sl] = (R[sl] + th1 * t) * (1.0 / den)
             prev, x = x, nxt
             k += 1
-        d = x - prev
-        conv = den * den * O.csum(d * d) <= tol * tol * b2
+        lhs = 0.0
+        for sl, (_, _, den) in zip(fields, consts):
+            d = x[sl] - prev[sl]
+            lhs = lhs + den * den * O.csum(d * d)
+        conv = lhs <= tol * tol * b2
         if conv or k >= cap:
             return x, k, bool(conv)

@@ -270,7 +270,8 @@ int Solver::step_t(int64_t nsteps) {
     prev_gap = 1;
     return MFD_OK;
   }
-  if (cfg.kind == MFD_THETA && consts.eq == kBurgers) return theta_picard_steps<T>(nsteps);
+  if (cfg.kind == MFD_THETA && (consts.eq == kBurgers || consts.eq == kNSE))
+    return theta_picard_steps<T>(nsteps);
   if (cfg.kind == MFD_THETA && theta_tol > 0.0) return theta_solve_steps<T>(nsteps);
   const TbPlan pl = effective_plan();
   const int d = pl.tb;
@@ -465,9 +466,15 @@ int Solver::theta_solve_steps(int64_t nsteps) {
   return MFD_OK;
 }
 
-// Theta steps of Burgers' equation (beta = 1): Picard iteration with the
-// Jacobi splitting of the linear even part (chunks of theta_chunk sweeps
-// checked on the host when a tolerance is set, else theta_iters sweeps).
+// Theta steps of Burgers' equation (beta = 1) and of the NSE: Picard
+// iteration with the Jacobi splitting of the linear part's diagonal, per
+// field (chunks of theta_chunk sweeps checked on the host when a tolerance
+// is set, else theta_iters sweeps).
+//   density (and the scalar):  A0,  dd = 2 sum_p (a_1 + a_-1) w_p
+//   momentum component a:      Ab0, dd = 2 sum_{p: e_pa != 0} (ab_1 + ab_-1) (w_p / d0)
+// (pairs in lattice order): the own-node coefficient of the second
+// differences of the linear parts, w_p rho of F+ and (w_p / d0) e_p . j of
+// F-; the off-diagonal and nonlinear terms stay in S(x) - A0 x.
 template <typename T>
 int Solver::theta_picard_steps(int64_t nsteps) {
   T *B[kNumBuf];
@@ -477,18 +484,38 @@ int Solver::theta_picard_steps(int64_t nsteps) {
   const int K = tol_on ? theta_chunk : cap;
   const int third = 3 - ic - io;  // the ring level neither phi^n nor the io role holds
   const double th = consts.theta, th1 = consts.th1;
-  const double A0 = consts.A0;
-  double sp = 0.0;
-  for (int p = 0; p < consts.npair; ++p) sp = sp + consts.ap * consts.w[consts.pair[p]];
-  const double dd = 2.0 * sp;
-  const double den = 1.0 + th1 * dd;
-  const double inv_den = 1.0 / den;
+  const int F = nf();
+  double A0[4], dd[4], den[4], inv_den[4];
+  {
+    double sp = 0.0;
+    for (int p = 0; p < consts.npair; ++p) sp = sp + consts.ap * consts.w[consts.pair[p]];
+    A0[0] = consts.A0;
+    dd[0] = 2.0 * sp;
+    const double abp = consts.abp;
+    for (int f = 1; f < F; ++f) {
+      double sj = 0.0;
+      for (int p = 0; p < consts.npair; ++p) {
+        const int j = consts.pair[p];
+        if (consts.e[j][f - 1] != 0) sj = sj + abp * (consts.w[j] / consts.d0);
+      }
+      A0[f] = consts.Ab0;
+      dd[f] = 2.0 * sj;
+    }
+    for (int f = 0; f < F; ++f) {
+      den[f] = 1.0 + th1 * dd[f];
+      inv_den[f] = 1.0 / den[f];
+    }
+  }
+  // Burgers on 1D / 2D grids: the sweep fused into the explicit step's tile
+  const bool fused = consts.eq == kBurgers && consts.dim <= 2;
   double *part = (double *)buf[kRedBuf];
   double *out = part + kReduceBlocks * 8;
   const int64_t N = G.N;
   for (int64_t s = 0; s < nsteps; ++s) {
     hipError_t e = launch_mmfd_step<T>(consts, G, B[ic], nullptr, B[6], 1, stream);
-    if (e == hipSuccess) e = launch_picard_rhs<T>(B[6], B[ic], B[5], th, th1, A0, N, stream);
+    for (int f = 0; f < F && e == hipSuccess; ++f)
+      e = launch_picard_rhs<T>(B[6] + f * N, B[ic] + f * N, B[5] + f * N, th, th1, A0[f], N,
+                               stream);
     if (e != hipSuccess) return hip(e, "picard rhs launch");
     const T *src = B[ic];
     int k = 0;
@@ -497,12 +524,14 @@ int Solver::theta_picard_steps(int64_t nsteps) {
       const T *before = src;
       for (int it = 0; it < K; ++it) {
         T *dst = (k % 2 == 0) ? B[io] : B[third];
-        if (consts.dim <= 2) {
-          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0, dd, th1, inv_den, stream);
+        if (fused) {
+          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0[0], dd[0], th1, inv_den[0],
+                                     stream);
         } else {
           e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
-          if (e == hipSuccess)
-            e = launch_picard_update<T>(B[6], src, B[5], dst, A0, dd, th1, inv_den, N, stream);
+          for (int f = 0; f < F && e == hipSuccess; ++f)
+            e = launch_picard_update<T>(B[6] + f * N, src + f * N, B[5] + f * N, dst + f * N,
+                                        A0[f], dd[f], th1, inv_den[f], N, stream);
         }
         if (e != hipSuccess) return hip(e, "picard sweep launch");
         before = src;
@@ -510,14 +539,20 @@ int Solver::theta_picard_steps(int64_t nsteps) {
         ++k;
       }
       if (!tol_on) break;
-      e = launch_sq_sums<T>(src, before, B[5], N, part, out, stream);
-      if (e != hipSuccess) return hip(e, "picard residual launch");
-      double hsum[2];
-      int rc = copy_out(hsum, out, sizeof(hsum), 0);
-      if (rc) return rc;
-      if (!std::isfinite(hsum[0]) || !std::isfinite(hsum[1]))
-        return fail(MFD_E_UNSTABLE, "non-finite theta residual");
-      conv = den * den * hsum[0] <= theta_tol * theta_tol * hsum[1];
+      // sum_f den_f^2 |x_k - x_(k-1)|_f^2 <= tol^2 sum_f |R|_f^2
+      double lhs = 0.0, rhs = 0.0;
+      for (int f = 0; f < F; ++f) {
+        e = launch_sq_sums<T>(src + f * N, before + f * N, B[5] + f * N, N, part, out, stream);
+        if (e != hipSuccess) return hip(e, "picard residual launch");
+        double hsum[2];
+        int rc = copy_out(hsum, out, sizeof(hsum), 0);
+        if (rc) return rc;
+        if (!std::isfinite(hsum[0]) || !std::isfinite(hsum[1]))
+          return fail(MFD_E_UNSTABLE, "non-finite theta residual");
+        lhs = lhs + den[f] * den[f] * hsum[0];
+        rhs = rhs + hsum[1];
+      }
+      conv = lhs <= theta_tol * theta_tol * rhs;
       if (conv || k >= cap) break;
     }
     if (src == B[third]) {  // the result is kept in the io role
@@ -755,10 +790,10 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
   if (kind == MFD_THETA) {
     if (s->dirichlet)
       return s->fail(MFD_E_UNSUPPORTED, "the theta scheme runs on periodic grids");
-    if (s->cfg.eq != MFD_LCDE &&
+    if (s->cfg.eq != MFD_LCDE && s->cfg.eq != MFD_NSE &&
         !(s->cfg.eq == MFD_BURGERS && (s->cfg.ep.beta == 1.0 || s->cfg.ep.beta == 0.0)))
-      return s->fail(MFD_E_UNSUPPORTED,
-                     "the theta scheme is implemented for the LCDE and Burgers' equation (beta = 1)");
+      return s->fail(MFD_E_UNSUPPORTED, "the theta scheme is implemented for the LCDE, "
+                                        "Burgers' equation (beta = 1) and the NSE");
     if (!(theta >= 0.0 && theta <= 1.0) || theta_iters < 0)
       return s->fail(MFD_E_ARG, "theta must lie in [0,1] and theta_iters >= 0");
     if (s->grid.form != MFD_MMFD)

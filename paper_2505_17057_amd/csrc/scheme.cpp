@@ -224,6 +224,8 @@ int build_consts(const SchemeInput &in, Consts &c) {
     c.beta_one = in.beta == 1.0;
     c.cbeta = (in.beta - 1.0) * d0;
   } else if (in.eq == kNSE) {
+    c.theta = in.kind == MFD_THETA ? in.theta : 1.0;
+    c.th1 = 1.0 - c.theta;
     c.rho0 = in.rho0;
     c.he_luo = in.he_luo;
     c.rinv0 = 1.0 / in.rho0;

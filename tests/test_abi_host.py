@@ -129,10 +129,12 @@ def test_argument_validation(M):
     with pytest.raises(M.MfdError) as e:
         s.set_lattice("D3Q19")  # dimension mismatch
     assert e.value.code == M.MFD_E_ARG
-    s.set_equation("nse", rho0=1.0)
-    with pytest.raises(M.MfdError) as e:
+    s.set_equation("burgers", beta=0.5)
+    with pytest.raises(M.MfdError) as e:  # theta: LCDE, Burgers at beta = 1 and the NSE
         s.set_scheme("theta", (1, 0, 0), theta=0.5, theta_iters=3, dt=1.0)
     assert e.value.code == M.MFD_E_UNSUPPORTED
+    s.set_equation("nse", rho0=1.0)
+    s.set_scheme("theta", (1, 0, 0), theta=0.5, theta_iters=3, dt=1.0)
     with pytest.raises(M.MfdError) as e:
         s.step(1)  # no state
     assert e.value.code == M.MFD_E_ORDER

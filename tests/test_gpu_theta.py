@@ -187,3 +187,78 @@ def test_theta_burgers_fp32_within_1e5(M):
     got = s.get_state().astype(np.float64)
     s.close()
     assert rel_l2(got, want) < 1e-5
+
+
+NSE_TH = [
+    dict(name="nse-d2q9", lattice="D2Q9", n=(96, 70)),
+    dict(name="nse-d2q5", lattice="D2Q5", n=(64, 40)),
+    dict(name="nse-d3q19", lattice="D3Q19", n=(14, 11, 9)),
+]
+
+
+def _nse_theta(c, theta=0.5, cap=64, s_rho=1.6, s_j=0.9):
+    def fam(s):
+        return ((s + 1) / 2, 1 - s, (s - 1) / 2)
+
+    return dict(c, eq="nse", rho0=1.0, a=fam(s_rho), ab=fam(s_j), kind="theta", theta=theta,
+                theta_iters=cap, dx=1.0, dt=1.0)
+
+
+def _nse_state(c, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    nf = 1 + len(c["n"])
+    return amp * rng.uniform(-1, 1, nf * int(np.prod(c["n"])))
+
+
+@pytest.mark.parametrize("case", NSE_TH, ids=lambda c: c["name"])
+@pytest.mark.parametrize("theta,tol,chunk", [(0.5, 1e-12, 4), (0.0, 1e-10, 3), (0.5, 0.0, 5)],
+                         ids=["half-tol", "implicit-tol", "fixed"])
+def test_theta_nse_fp64_matches_oracle(M, case, theta, tol, chunk):
+    """The NSE theta step (Picard sweeps, the own-node coefficient of the
+    linear EDF parts split per field): every state bit-exact with the
+    oracle's iteration and the sweep counts equal; tol = 0 runs theta_iters
+    sweeps."""
+    from oracle import implicit as IM
+
+    cap = 64 if tol > 0 else chunk
+    c = _nse_theta(case, theta=theta, cap=cap)
+    spec = oracle_spec(c)
+    phi = _nse_state(c, 21)
+    want, sweeps = phi, []
+    for _ in range(3):
+        want, k, _ = IM.theta_picard_solve(spec, want, tol if tol > 0 else 1e-300,
+                                           chunk if tol > 0 else cap, cap)
+        sweeps.append(k)
+    s = make_solver(M, c, "fp64")
+    if tol > 0:
+        s.set_theta_tolerance(tol, chunk)
+    s.set_state(phi)
+    s.step(1)
+    s.step(2)
+    got = s.get_state()
+    st = s.theta_stats()
+    s.close()
+    assert np.array_equal(got, want)
+    if tol > 0:
+        assert st["total_sweeps"] == sum(sweeps) and st["unconverged"] == 0
+
+
+@pytest.mark.parametrize("case", NSE_TH[:1] + NSE_TH[2:], ids=lambda c: c["name"])
+def test_theta_nse_fp32_within_1e5(M, case):
+    from oracle import implicit as IM
+
+    c = _nse_theta(case)
+    spec = oracle_spec(c)
+    phi = _nse_state(c, 22).astype(np.float32)
+    want = phi.astype(np.float64)
+    for _ in range(4):
+        want, _, _ = IM.theta_picard_solve(spec, want, 1e-12, 4, 64)
+    s = make_solver(M, c, "fp32")
+    s.set_theta_tolerance(1e-6, 4)
+    s.set_state(phi)
+    s.step(4)
+    got = s.get_state().astype(np.float64)
+    st = s.theta_stats()
+    s.close()
+    assert st["unconverged"] == 0
+    assert rel_l2(got, want) < 1e-5

@@ -90,3 +90,111 @@ def test_implicit_step_is_stable_beyond_the_explicit_limit():
     with np.errstate(invalid="ignore"):
         grew = not np.all(np.isfinite(xe)) or np.abs(xe).max() > 10 * np.abs(phi).max()
     assert grew
+
+
+# ------------------------------------------------------------------ NSE
+def nse_case(lat, n, theta, s_rho=1.6, s_j=0.9, dt=1.0):
+    def fam(s):
+        return ((s + 1) / 2, 1 - s, (s - 1) / 2)
+
+    return dict(lattice=lat, eq="nse", n=n, dx=1.0, dt=dt, rho0=1.0, a=fam(s_rho), ab=fam(s_j),
+                theta=theta)
+
+
+def _nse_state(spec, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    return amp * rng.uniform(-1, 1, O.nfields(spec) * O.npoints(spec))
+
+
+NSE_LATS = [("D2Q9", (9, 7)), ("D2Q5", (8, 6)), ("D3Q19", (5, 4, 4))]
+
+
+@pytest.mark.parametrize("lat,n", NSE_LATS)
+def test_nse_theta_one_is_explicit(lat, n):
+    spec = nse_case(lat, n, 1.0)
+    phi = _nse_state(spec, 4)
+    x, k, conv = IM.theta_picard_solve(spec, phi, 1e-12, 2, 10)
+    es = dict(spec)
+    es.pop("theta")
+    assert conv and k == 2
+    assert np.array_equal(x, O.mmfd_step(es, phi))
+
+
+@pytest.mark.parametrize("lat,n", NSE_LATS + [("D3Q7", (4, 4, 3)), ("D2Q5II", (6, 5))])
+def test_nse_split_diagonal_is_the_step_jacobian_diagonal(lat, n):
+    """dd of every field is the own-node coefficient the split moves: at rest
+    (j = 0) the quadratic term has no first-order part, so the diagonal of the
+    explicit step's Jacobian is A0_f - dd_f, measured here by central
+    differences of the step map (exact for the linear parts up to rounding)."""
+    d0 = 0.3 if lat == "D3Q7" else 1.0 / 3.0
+    spec = dict(nse_case(lat, n, 0.5), d0=d0)
+    es = dict(spec)
+    es.pop("theta")
+    consts = IM.picard_field_constants(spec)
+    F = O.nfields(spec)
+    N = O.npoints(spec)
+    assert len(consts) == F
+    base = np.zeros(F * N)
+    h = 1e-4
+    for f in range(F):
+        for i in (0, N // 2, N - 1):
+            e = np.zeros(F * N)
+            e[f * N + i] = h
+            jac = (O.mmfd_step(es, base + e)[f * N + i] - O.mmfd_step(es, base - e)[f * N + i]) / (2 * h)
+            A0, dd, den = consts[f]
+            assert dd > 0 and den == 1.0 + 0.5 * dd
+            assert abs(jac - (A0 - dd)) <= 1e-9 * max(1.0, abs(A0 - dd)), (f, i, jac, A0 - dd)
+
+
+@pytest.mark.parametrize("lat,n", NSE_LATS)
+@pytest.mark.parametrize("theta", [0.5, 0.0])
+def test_nse_converged_step_satisfies_gcn(lat, n, theta):
+    """The converged NSE theta step solves Eq. (GCN) per field, with the
+    increment taken from the literal population sum of Eq. (2-2) (independent
+    of the central pair form the iteration runs), to the tolerance; the
+    stopping point is the first chunk boundary where the rule holds."""
+    spec = nse_case(lat, n, theta)
+    phi = _nse_state(spec, 5)
+    tol = 1e-10
+    x, k, conv = IM.theta_picard_solve(spec, phi, tol, 3, 400)
+    assert conv and k >= 3
+    es = dict(spec)
+    es.pop("theta")
+    F = O.nfields(spec)
+    N = O.npoints(spec)
+    A0v = np.concatenate([np.full(N, c[0]) for c in IM.picard_field_constants(spec)])
+
+    def L(y):
+        return O.literal_step(es, y) - A0v * y
+
+    R = A0v * phi + theta * L(phi)
+    r = x - R - (1 - theta) * L(x)
+    dens = np.concatenate([np.full(N, c[2]) for c in IM.picard_field_constants(spec)])
+    # the stopping rule bounds den (x_k - x_(k-1)), the residual up to O(contraction)
+    assert np.linalg.norm(r) <= 4 * tol * np.linalg.norm(R) + 1e-13 * np.linalg.norm(R)
+
+    def ratio(kk):
+        xk, _, _ = IM.theta_picard_solve(spec, phi, 1e-300, kk, kk)
+        xk1, _, _ = IM.theta_picard_solve(spec, phi, 1e-300, kk - 1, kk - 1)
+        return np.linalg.norm(dens * (xk - xk1)) / np.linalg.norm(R)
+
+    assert ratio(k) <= tol * (1 + 1e-9)
+    if k > 3:
+        assert ratio(k - 3) > tol * (1 - 1e-9)
+    assert F == 1 + O.DIMS[lat]
+
+
+def test_nse_theta_conserves_mass_and_momentum():
+    """On a periodic grid the explicit step keeps each field's total up to
+    the factor A0 (= 1 for these coefficients); R's total is then the total
+    T of phi^n, and a sweep maps an iterate of total T to
+    (T + (1 - theta) dd T) / den = T, so every iterate, and the theta step,
+    keeps the totals of mass and momentum (up to rounding)."""
+    spec = nse_case("D2Q9", (10, 9), 0.5)
+    phi = _nse_state(spec, 6)
+    x, _, conv = IM.theta_picard_solve(spec, phi, 1e-12, 4, 400)
+    assert conv
+    N = O.npoints(spec)
+    for f in range(3):
+        s0, s1 = phi[f * N:(f + 1) * N].sum(), x[f * N:(f + 1) * N].sum()
+        assert abs(s1 - s0) <= 1e-12 * max(1.0, np.abs(phi).sum())
