@@ -303,6 +303,51 @@ def bench_theta(M, torch, cfg, stream, N, theta=0.5, steps=1000, chunk=8, cap=64
     return out
 
 
+def bench_theta_mg(M, torch, cfg, stream, N, theta=0.5, dt_factor=32.0, steps=20):
+    """theta scheme of the 2048^2 linear CDE at dt_factor times the explicit
+    time step, where Jacobi sweeps need hundreds per step: the same steps
+    solved to the same residual tolerance by Jacobi sweeps (device-decided
+    chunks) and by multigrid V(2,2) cycles over every level the grid allows.
+    GLUPS count time steps; FP32 error against the FP64 multigrid run, and
+    the FP64 multigrid result against the FP64 Jacobi one."""
+    out, finals = {}, {}
+    dt = cfg["dt"] * dt_factor
+    for solver, prec, tol, cap, chunk in (("jacobi", "fp64", 1e-10, 4096, 16),
+                                          ("multigrid", "fp64", 1e-10, 40, 0),
+                                          ("jacobi", "fp32", 1e-5, 4096, 16),
+                                          ("multigrid", "fp32", 1e-5, 40, 0)):
+        s = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
+        s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
+        s.set_scheme("theta", M.mfd_preset("srt")[0], theta=theta, theta_iters=cap, dt=dt)
+        s.set_theta_tolerance(tol, chunk)
+        if solver == "multigrid":
+            s.set_theta_multigrid(-1, 2, 2)
+        s.set_stream(stream.cuda_stream)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        s.step(2)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        s.theta_stats(reset=True)
+        ms = timed(torch, lambda: s.step(steps))
+        st = s.theta_stats()
+        finals[solver, prec] = s.get_state().astype(np.float64)
+        s.close()
+        g = N * steps / (ms * 1e-3) / 1e9
+        it = st["total_sweeps"] / max(st["steps"], 1)
+        out["%s_%s" % (solver, prec)] = dict(
+            glups=round(g, 3), ms_per_step=round(ms / steps, 3), tolerance=tol,
+            **{("cycles_per_step" if solver == "multigrid" else "sweeps_per_step"): round(it, 2)},
+            steps_stopped_by_cap=st["unconverged"])
+    ref = finals["multigrid", "fp64"]
+    out.update(theta=theta, dt_over_explicit=dt_factor, steps=steps,
+               multigrid_vs_jacobi_fp64_rel_l2=float(np.linalg.norm(ref - finals["jacobi", "fp64"])
+                                                     / np.linalg.norm(ref)),
+               fp32_multigrid_rel_l2_vs_fp64=float(np.linalg.norm(finals["multigrid", "fp32"] - ref)
+                                                   / np.linalg.norm(ref)),
+               speedup_fp64=round(out["multigrid_fp64"]["glups"] / out["jacobi_fp64"]["glups"], 2),
+               speedup_fp32=round(out["multigrid_fp32"]["glups"] / out["jacobi_fp32"]["glups"], 2))
+    return out
+
+
 def bench_big(M, torch, I, stream):
     big = I.c2_hill_2d(n=8192)
     sb = c2_solver(M, big, "fp32", "mmfd", stream)
@@ -922,6 +967,9 @@ def main():
     if "theta" in sections:
         log("theta")
         extra["theta_d2q9_2048"] = bench_theta(M, torch, cfg, stream, N)
+    if "theta_mg" in sections:
+        log("theta, large steps: Jacobi vs multigrid")
+        extra["theta_large_dt_d2q9_2048"] = bench_theta_mg(M, torch, cfg, stream, N)
     if "big" in sections:
         log("8192^2")
         extra["hbm_resident_8192_mmfd_fp32"] = bench_big(M, torch, I, stream)

@@ -210,6 +210,29 @@ int mfd_set_scheme_sets(mfd_solver *s, int kind, const double a[3], const double
  * [0, 16] or a cap below 1. */
 int mfd_set_theta_tolerance(mfd_solver *s, double tol, int32_t chunk);
 
+/* Solve the theta steps of the linear CDE on a periodic 2D D2Q5 / D2Q9 grid
+ * by geometric multigrid V-cycles instead of Jacobi sweeps (Eq. (GCN): the
+ * same step, (I - (1-theta) L) x = A0 phi + theta L phi).  Level l has
+ * (nx >> l) x (ny >> l) nodes and the operator discretised again on the
+ * coarser spacing (second differences Cp_p / 4^l, first differences
+ * Cm_p / 2^l); weighted Jacobi smoothing (weight 0.8), full-weighting
+ * restriction of the residual, bilinear prolongation; on the coarsest level
+ * as many sweeps (2 .. 64) as cut its error 1000-fold at the weighted Jacobi
+ * bound.  The grid allows levels while both sides stay even and at least 4
+ * when halved.  levels: 0 switches multigrid off (Jacobi sweeps), -1 takes
+ * them down to the first level of at most 4096 nodes (at least 2 levels),
+ * 2 .. the allowed number takes as many; pre in [1, 8] and post in
+ * [0, 8] smoothing sweeps per level and cycle.  Each step starts from
+ * phi(t) and, with a tolerance set (mfd_set_theta_tolerance), stops after the
+ * first cycle with sum (rhs - A x)^2 <= tol^2 sum rhs^2 (binary64 sums), at
+ * most theta_iters cycles; without one it runs theta_iters cycles.
+ * mfd_theta_stats then counts cycles.  Device memory: one more level of
+ * scratch plus three arrays per coarser level (about 2 x one field).  A new
+ * mfd_set_scheme switches it off.  MFD_E_ORDER unless a theta scheme is set,
+ * MFD_E_UNSUPPORTED for other equations or lattices, MFD_E_ARG for levels the
+ * grid does not allow or sweep counts out of range, MFD_E_OOM. */
+int mfd_set_theta_multigrid(mfd_solver *s, int32_t levels, int32_t pre, int32_t post);
+
 /* Sweeps taken by the to-tolerance theta solves since the last reset: total,
  * time steps, the most in one step and the steps stopped by the cap before
  * the tolerance held.  Synchronous; reset = 1 zeroes the counters. */

@@ -129,3 +129,39 @@ def theta_picard_solve(spec, cur, tol, chunk, cap):
         conv = lhs <= tol * tol * b2
         if conv or k >= cap:
             return x, k, bool(conv)
+
+
+def theta_exact_periodic(spec, cur):
+    """The linear CDE's theta step of Eq. (GCN) solved exactly on a periodic
+    grid: (I - (1 - theta) L) x = R with R = theta S(phi) + (1 - theta) A0 phi
+    (S the explicit step, ``orc_mmfd_step``) and L = S - A0 I, whose stencil
+    sum_p [Cp_p (x(+e_p) - 2 x + x(-e_p)) + Cm_p (x(+e_p) - x(-e_p))] is the
+    same at every node, so the discrete Fourier transform diagonalises it:
+    x^(k) = R^(k) / (1 - (1 - theta) sum_p [Cp_p (2 cos(k.e_p) - 2)
+                                            + Cm_p 2 i sin(k.e_p)]).
+    (numpy's transform: a shift by +e multiplies mode k by exp(i k.e).)"""
+    if spec.get("eq", "lcde") != "lcde":
+        raise ValueError("the exact periodic theta step is the linear CDE's")
+    es = _explicit_spec(spec)
+    theta = float(spec["theta"])
+    th1 = 1.0 - theta
+    a = [float(v) for v in spec["a"]]
+    A0 = (a[0] + a[1]) + a[2]
+    S = O.mmfd_step(es, cur)
+    R = theta * S + th1 * (A0 * cur)
+    _, _, t = O.tables(es)
+    E, _, pairs = O.lattice_info(spec["lattice"], float(spec.get("d0", 1.0 / 3.0)))
+    n = list(spec["n"])
+    dims = len(n)
+    shape = tuple(reversed(n))  # x fastest
+    ks = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(m) for m in reversed(n)], indexing="ij")
+    # ks[d] is the angle per node along axis (dims - 1 - d) of the array
+    sym = np.zeros(shape, dtype=np.complex128)
+    for p, j in enumerate(pairs):
+        ang = np.zeros(shape)
+        for ax in range(dims):
+            ang = ang + float(E[j][ax]) * ks[dims - 1 - ax]
+        sym = sym + float(t["Cp"][p]) * (2 * np.cos(ang) - 2) + float(t["Cm"][p]) * (2j * np.sin(ang))
+    Ahat = 1.0 - th1 * sym
+    x = np.fft.ifftn(np.fft.fftn(R.reshape(shape)) / Ahat)
+    return x.real.ravel(), R

@@ -36,6 +36,7 @@ SOURCES = [
     "kernels_misc.hip",
     "kernels_batch.hip",
     "kernels_source.hip",
+    "kernels_mg.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

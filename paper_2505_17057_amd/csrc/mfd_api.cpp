@@ -17,6 +17,7 @@
 #include "mfd_internal.h"
 #include "scheme.h"
 #include "solver.h"
+#include "mg.h"
 
 using namespace mfd;
 
@@ -110,7 +111,22 @@ int64_t Solver::device_bytes_needed() const {
   if (grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))
     b += mom_elems() * es;
   b += (kReduceBlocks * 8 + 8) * (int64_t)sizeof(double);
+  b += mg_bytes();
   return b;
+}
+
+// the fine level's scratch, then three arrays (iterate, right-hand side,
+// scratch) of each coarser level
+int64_t Solver::mg_bytes() const {
+  if (cfg.kind != MFD_THETA || mg_levels < 2) return 0;
+  int64_t e = G.N;
+  int64_t nx = G.n[0], ny = G.n[1];
+  for (int l = 1; l < mg_levels; ++l) {
+    nx /= 2;
+    ny /= 2;
+    e += 3 * nx * ny;
+  }
+  return e * elem();
 }
 
 // control block and two binary64 partials per tile of the largest chunk
@@ -136,7 +152,7 @@ int Solver::ensure_buffers() {
   release();
   const int64_t es = elem(), me = mom_elems() * es, pe = pop_elems() * es;
   int64_t sizes[kNumBuf] = {me, me, me, pe, pe, me, me, (kReduceBlocks * 8 + 8) * 8, me,
-                            theta_buf_bytes()};
+                            theta_buf_bytes(), mg_bytes()};
   if (cfg.kind != MFD_THETA) sizes[5] = sizes[6] = 0;
   if (!(grid.form == MFD_MMFD && consts.three && tb_equation_supported(consts))) sizes[8] = 0;
   for (int i = 0; i < kNumBuf; ++i) {
@@ -270,6 +286,8 @@ int Solver::step_t(int64_t nsteps) {
     prev_gap = 1;
     return MFD_OK;
   }
+  if (cfg.kind == MFD_THETA && mg_levels >= 2 && consts.eq == kLCDE && grid.dim == 2)
+    return theta_mg_steps<T>(nsteps);
   if (cfg.kind == MFD_THETA && (consts.eq == kBurgers || consts.eq == kNSE))
     return theta_picard_steps<T>(nsteps);
   if (cfg.kind == MFD_THETA && theta_tol > 0.0) return theta_solve_steps<T>(nsteps);
@@ -573,6 +591,124 @@ int Solver::theta_picard_steps(int64_t nsteps) {
   return MFD_OK;
 }
 
+// Theta steps of the 2D linear CDE by multigrid V-cycles (kernels_mg.hip):
+// per step the right-hand side R = A0 phi + theta L phi, then V(pre, post)
+// cycles from x = phi, each followed by the binary64 check
+//   sum (R - A x)^2 <= tol^2 sum R^2
+// (tol = 0: exactly theta_iters cycles); theta_iters caps the cycles.
+template <typename T>
+int Solver::theta_mg_steps(int64_t nsteps) {
+  T *B[kNumBuf];
+  for (int i = 0; i < kNumBuf; ++i) B[i] = (T *)buf[i];
+  const int L = mg_levels;
+  const int lat = consts.lattice;
+  const bool tol_on = theta_tol > 0.0;
+  const int cap = cfg.theta_iters;
+  int nxl[kMgMaxLevels], nyl[kMgMaxLevels];
+  MgOp<T> op[kMgMaxLevels];
+  T *xl[kMgMaxLevels], *tl[kMgMaxLevels], *Rl[kMgMaxLevels];
+  {
+    T *m = B[kMgBuf];
+    nxl[0] = (int)G.n[0];
+    nyl[0] = (int)G.n[1];
+    tl[0] = m;
+    m += G.N;
+    Rl[0] = B[5];
+    for (int l = 1; l < L; ++l) {
+      nxl[l] = nxl[l - 1] / 2;
+      nyl[l] = nyl[l - 1] / 2;
+      const int64_t n = (int64_t)nxl[l] * nyl[l];
+      xl[l] = m;
+      Rl[l] = m + n;
+      tl[l] = m + 2 * n;
+      m += 3 * n;
+    }
+    for (int l = 0; l < L; ++l) op[l] = mg_op<T>(consts, l, nxl[l], nyl[l]);
+  }
+  // the coarsest level's sweeps: enough to reduce its error 1000-fold at the
+  // weighted Jacobi bound (1 - w) + w (den - 1) / den (its off-diagonal sum
+  // is at most den - 1 while |Cm| <= Cp), between 2 and kMgCoarseSweeps
+  int coarse_sweeps = kMgCoarseSweeps;
+  {
+    const double den = (double)op[L - 1].den;
+    const double rho = (1.0 - kMgOmega) + kMgOmega * (den - 1.0) / den;
+    if (rho > 0.0 && rho < 1.0)
+      coarse_sweeps = std::max(2, std::min(kMgCoarseSweeps, (int)std::ceil(std::log(1e-3) / std::log(rho))));
+  }
+  double *part = (double *)buf[kRedBuf];
+  double *out = part + kReduceBlocks * 8;
+  const int64_t N = G.N;
+  hipError_t e = hipSuccess;
+  // smoothing sweeps on level l between its iterate and scratch arrays
+  auto smooth = [&](int l, T *&cur, T *&oth, int sweeps, bool from_zero) {
+    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
+      e = launch_mg_smooth<T>(lat, cur, Rl[l], oth, op[l], kMgOmega, from_zero && k == 0, stream);
+      std::swap(cur, oth);
+    }
+  };
+  for (int64_t s = 0; s < nsteps; ++s) {
+    e = launch_theta_rhs<T>(consts, G, B[ic], B[5], stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(B[io], B[ic], (size_t)(N * sizeof(T)), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip(e, "multigrid rhs");
+    T *cur[kMgMaxLevels], *oth[kMgMaxLevels];
+    cur[0] = B[io];
+    oth[0] = tl[0];
+    int k = 0;
+    bool conv = false;
+    while (true) {
+      // down: pre-smooth, restrict the residual; coarse levels start from 0
+      for (int l = 0; l + 1 < L; ++l) {
+        if (l > 0) {
+          cur[l] = xl[l];
+          oth[l] = tl[l];
+        }
+        smooth(l, cur[l], oth[l], mg_pre, l > 0);
+        if (e == hipSuccess) e = launch_mg_restrict<T>(lat, cur[l], Rl[l], Rl[l + 1], op[l], stream);
+      }
+      cur[L - 1] = xl[L - 1];
+      oth[L - 1] = tl[L - 1];
+      smooth(L - 1, cur[L - 1], oth[L - 1], coarse_sweeps, true);
+      // up: add the prolongated correction, post-smooth
+      for (int l = L - 2; l >= 0; --l) {
+        if (e == hipSuccess) e = launch_mg_prolong_add<T>(cur[l + 1], cur[l], nxl[l], nyl[l], stream);
+        smooth(l, cur[l], oth[l], mg_post, false);
+      }
+      if (e != hipSuccess) return hip(e, "multigrid cycle launch");
+      ++k;
+      if (tol_on) {
+        e = launch_mg_apply<T>(lat, cur[0], oth[0], op[0], stream);
+        if (e == hipSuccess) e = launch_sq_sums<T>(B[5], oth[0], B[5], N, part, out, stream);
+        if (e != hipSuccess) return hip(e, "multigrid residual launch");
+        double h[2];
+        int rc = copy_out(h, out, sizeof(h), 0);
+        if (rc) return rc;
+        if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+          return fail(MFD_E_UNSTABLE, "non-finite theta residual");
+        conv = h[0] <= theta_tol * theta_tol * h[1];
+        if (conv || k >= cap) break;
+      } else if (k >= cap) {
+        break;
+      }
+    }
+    if (cur[0] != B[io]) {
+      e = hipMemcpyAsync(B[io], cur[0], (size_t)(N * sizeof(T)), hipMemcpyDeviceToDevice, stream);
+      if (e != hipSuccess) return hip(e, "multigrid result copy");
+    }
+    std::swap(ic, io);
+    ip = io;
+    ++steps_done;
+    if (tol_on) {
+      th_total += k;
+      ++th_steps;
+      th_max = std::max(th_max, k);
+      if (!conv) ++th_unconv;
+    }
+  }
+  prev_gap = 1;
+  return MFD_OK;
+}
+
 bool Solver::source_supported() const {
   if (cfg.kind == MFD_THETA || consts.eq != kLCDE || consts.wave || dirichlet) return false;
   return grid.form == MFD_MMFD || grid.dim <= 2;  // MesoFD: 1D / 2D
@@ -832,6 +968,7 @@ extern "C" int mfd_set_scheme(mfd_solver *h, int kind, const double a[3], const 
   }
   s->cfg.theta = kind == MFD_THETA ? theta : 1.0;
   s->cfg.theta_iters = kind == MFD_THETA ? theta_iters : 0;
+  s->mg_levels = 0;  // a new scheme solves its theta steps by sweeps until set again
   s->cfg.dt = dt;
   s->cfg.multiset = 0;
   s->have_scheme = true;
@@ -1197,6 +1334,62 @@ extern "C" int mfd_set_theta_tolerance(mfd_solver *h, double tol, int32_t chunk)
     return s->fail(MFD_E_ARG, "the sweep cap (theta_iters) must be >= 1");
   s->theta_tol = tol;
   s->theta_chunk = chunk;
+  return MFD_OK;
+}
+
+extern "C" int mfd_set_theta_multigrid(mfd_solver *h, int32_t levels, int32_t pre,
+                                       int32_t post) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!s->configured || s->cfg.kind != MFD_THETA)
+    return s->fail(MFD_E_ORDER, "set a theta scheme first");
+  int L = 0;
+  if (levels != 0) {
+    if (s->consts.eq != kLCDE || s->grid.dim != 2 ||
+        (s->consts.lattice != MFD_D2Q5 && s->consts.lattice != MFD_D2Q9))
+      return s->fail(MFD_E_UNSUPPORTED, "multigrid theta solves: the linear CDE on D2Q5 / D2Q9");
+    if (pre < 1 || pre > 8 || post < 0 || post > 8)
+      return s->fail(MFD_E_ARG, "pre-smoothing sweeps in [1, 8], post-smoothing in [0, 8]");
+    // levels the grid allows: halve while both sides stay even and >= the
+    // minimum; the automatic choice stops at the first level of at most
+    // kMgAutoCoarseNodes nodes (below it a level costs launches, not work)
+    int most = 1, autol = 0;
+    for (int64_t nx = s->G.n[0], ny = s->G.n[1];
+         most < kMgMaxLevels && nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= kMgMinSide &&
+         ny / 2 >= kMgMinSide;
+         nx /= 2, ny /= 2) {
+      if (!autol && nx * ny <= kMgAutoCoarseNodes) autol = most;
+      ++most;
+    }
+    if (!autol) autol = most;
+    L = levels < 0 ? std::max(2, std::min(autol, most)) : levels;
+    if (L < 2 || L > most)
+      return s->fail(MFD_E_ARG, "this grid takes 2 .. %d multigrid levels (got %d)", most, levels);
+  }
+  const int64_t old_bytes = s->mg_bytes();
+  s->mg_levels = L;
+  s->mg_pre = pre;
+  s->mg_post = post;
+  const int64_t new_bytes = s->mg_bytes();
+  // buffers already allocated (state set): replace the multigrid buffer only
+  if (s->buf[0] && new_bytes != old_bytes) {
+    if (s->buf[Solver::kMgBuf]) {
+      hipError_t e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return s->hip(e, "hipStreamSynchronize");
+      dev_free(s->buf[Solver::kMgBuf]);
+      s->buf[Solver::kMgBuf] = nullptr;
+    }
+    if (new_bytes > 0) {
+      hipError_t e = dev_malloc(&s->buf[Solver::kMgBuf], (size_t)new_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s->mg_levels = 0;
+        s->allocated_bytes += -old_bytes;
+        return s->fail(MFD_E_OOM, "hipMalloc of %lld bytes failed", (long long)new_bytes);
+      }
+    }
+    s->allocated_bytes += new_bytes - old_bytes;
+  }
   return MFD_OK;
 }
 

@@ -28,10 +28,12 @@ struct Solver {
   // device buffers: 0..2 moment ring, 3..4 population ping-pong, 5..6 theta
   // rhs / Jacobi work, 7 reduction scratch, 8 fourth moment buffer (blocked
   // three-level steps write two levels), 9 control block and tile partials of
-  // the to-tolerance theta solve
-  static constexpr int kNumBuf = 10;
+  // the to-tolerance theta solve, 10 multigrid levels (fine-level scratch,
+  // then iterate, right-hand side and scratch of every coarser level)
+  static constexpr int kNumBuf = 11;
   static constexpr int kRedBuf = 7;
   static constexpr int kThetaBuf = 9;
+  static constexpr int kMgBuf = 10;
   static constexpr int64_t kThetaCtlBytes = 256;
 
   mfd_grid grid{};
@@ -51,6 +53,8 @@ struct Solver {
   int theta_chunk = 8;
   int64_t th_total = 0, th_steps = 0;  // host-checked solves (unfused path)
   int th_max = 0, th_unconv = 0;
+  // multigrid V-cycles for the theta step (0 levels: Jacobi sweeps)
+  int mg_levels = 0, mg_pre = 2, mg_post = 2;
   int prev_gap = 1;  // steps between the current and the held previous level
   int64_t check_every = 0;  // finiteness check every this many steps (0: off)
   int tb = 0;           // temporal-blocking depth requested (0 = automatic)
@@ -76,6 +80,7 @@ struct Solver {
   int64_t pop_elems() const;
   int64_t device_bytes_needed() const;
   int64_t theta_buf_bytes() const;
+  int64_t mg_bytes() const;
   void release();
   int ensure_buffers();
   int copy_in(void *dst, const void *src, int64_t bytes, int on_device);
@@ -92,6 +97,8 @@ struct Solver {
   int theta_solve_steps(int64_t nsteps);
   template <typename T>
   int theta_picard_steps(int64_t nsteps);
+  template <typename T>
+  int theta_mg_steps(int64_t nsteps);
 };
 
 }  // namespace mfd

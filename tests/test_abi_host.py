@@ -349,3 +349,39 @@ def test_multiset_constant_tables_bitwise(M, three):
     for k in tab:
         assert np.array_equal(gtab[k], tab[k]), k
     s.close()
+
+
+def test_theta_multigrid_argument_checks(M):
+    """mfd_set_theta_multigrid: theta scheme first; the 2D linear CDE on
+    D2Q5 / D2Q9 only; levels the grid allows (halving while both sides stay
+    even and >= 4); pre in [1, 8], post in [0, 8]; 0 switches it off."""
+    s = M.Solver("D2Q9", (96, 64), 1.0, "fp64", "mmfd")
+    s.set_equation("lcde", u=(0.1, 0.0), K=[[1.0, 0], [0, 1.0]])
+    s.set_scheme("two_level", (1.0, 0.0, 0.0), dt=1.0)
+    with pytest.raises(M.MfdError) as ei:
+        s.set_theta_multigrid(-1)
+    assert ei.value.code == M.MFD_E_ORDER
+    s.set_scheme("theta", (1.0, 0.0, 0.0), theta=0.5, theta_iters=20)
+    s.set_theta_multigrid(-1)          # (96,64) (48,32) (24,16) (12,8) (6,4): 5 levels
+    s.set_theta_multigrid(5, 1, 0)
+    for bad in ((6, 2, 2), (1, 2, 2), (3, 0, 2), (3, 9, 2), (3, 2, 9), (3, 2, -1)):
+        with pytest.raises(M.MfdError) as ei:
+            s.set_theta_multigrid(*bad)
+        assert ei.value.code == M.MFD_E_ARG, bad
+    s.set_theta_multigrid(0)
+    s.close()
+    s = M.Solver("D2Q9", (32, 32), 1.0, "fp64", "mmfd")
+    s.set_equation("burgers", beta=1.0)
+    s.set_scheme("theta", (1.0, 0.0, 0.0), theta=0.5, theta_iters=20)
+    with pytest.raises(M.MfdError) as ei:
+        s.set_theta_multigrid(-1)
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    s.set_theta_multigrid(0)  # off is always accepted
+    s.close()
+    s = M.Solver("D1Q3", (64,), 1.0, "fp64", "mmfd")
+    s.set_equation("lcde", u=(0.1,), K=[[1.0]])
+    s.set_scheme("theta", (1.0, 0.0, 0.0), theta=0.5, theta_iters=20)
+    with pytest.raises(M.MfdError) as ei:
+        s.set_theta_multigrid(-1)
+    assert ei.value.code == M.MFD_E_UNSUPPORTED
+    s.close()

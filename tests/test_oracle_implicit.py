@@ -198,3 +198,34 @@ def test_nse_theta_conserves_mass_and_momentum():
     for f in range(3):
         s0, s1 = phi[f * N:(f + 1) * N].sum(), x[f * N:(f + 1) * N].sum()
         assert abs(s1 - s0) <= 1e-12 * max(1.0, np.abs(phi).sum())
+
+
+# ------------------------------------------- linear CDE, exact periodic solve
+def lcde_case(lat, n, theta, diff=2.0):
+    dim = O.DIMS[lat]
+    K = (np.eye(dim) * diff).tolist()
+    u = [0.3, -0.2, 0.1][:dim]
+    return dict(lattice=lat, eq="lcde", n=n, dx=1.0, dt=1.0, a=(1.0, 0.0, 0.0), u=u, K=K,
+                theta=theta)
+
+
+@pytest.mark.parametrize("lat,n", [("D2Q9", (16, 12)), ("D2Q5", (10, 8)), ("D1Q3", (30,)),
+                                   ("D3Q19", (6, 5, 4))])
+@pytest.mark.parametrize("theta", [0.5, 0.0])
+def test_exact_periodic_theta_step(lat, n, theta):
+    """The Fourier solve of the linear theta step satisfies
+    x - (1 - theta)(S(x) - A0 x) = R with S the oracle's explicit step (so
+    its symbol is the step's stencil), and equals the Jacobi solve of
+    orc_theta_solve iterated to 1e-14."""
+    spec = lcde_case(lat, n, theta)
+    rng = np.random.default_rng(8)
+    phi = rng.standard_normal(O.npoints(spec))
+    x, R = IM.theta_exact_periodic(spec, phi)
+    es = dict(spec)
+    es.pop("theta")
+    A0 = sum(spec["a"])
+    r = x - (1 - theta) * (O.mmfd_step(es, x) - A0 * x) - R
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(R)
+    xj, k, conv = O.theta_solve(spec, phi, 1e-14, 8, 20000)
+    assert conv
+    assert np.linalg.norm(xj - x) <= 1e-12 * np.linalg.norm(x)
