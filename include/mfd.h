@@ -113,6 +113,22 @@ typedef struct {
     double dx;          /* node spacing (square / cubic grid), > 0           */
 } mfd_grid;
 
+/* Rectangular lattice of Appendix A for the linear CDE: spacing dx[a] along
+ * axis a and d0[a] = c_s,a^2 / c_a^2 (c_a = dx[a] / dt) per axis (entries
+ * beyond the grid's dimension are ignored).  The weights are Appendix A's
+ * with d0 per axis (e.g. rD2Q9: w0 = (1 - d01)(1 - d02),
+ * w_x = d01 (1 - d02) / 2, w_y = (1 - d01) d02 / 2, w_diag = d01 d02 / 4;
+ * rD2Q5II and rD3Q9 take one d0), the EDF of Eq. (3-3)/(3-4) takes
+ * c~_ja = e_ja / d0_a and Q~ per axis, and the equation's u and K map per
+ * axis (u_a dt / dx_a, K_ab dt / (dx_a dx_b)); the grid's dx is then unused.
+ * The kernels are those of the square lattice (the per-axis values live in
+ * the constant tables).  Call after mfd_set_lattice (which returns to the
+ * square lattice); MFD_E_ORDER before it, MFD_E_UNSUPPORTED for an
+ * equation other than the linear CDE (set before or after), for unequal d0
+ * on rD2Q5II / rD3Q9 and with a source term, MFD_E_ARG for d0 outside
+ * (0, 1), a non-positive spacing or a non-positive weight. */
+int mfd_set_rectangular(mfd_solver *s, const double dx[3], const double d0[3]);
+
 /* Equation parameters.  MFD_WAVE (phi_tt = alpha Laplacian phi) uses the EDF
  * f_j = w_j phi [1 + (beta - 1)(|e_j|^2 - dim d0) / (2 d0)] printed with
  * Example 3 (beta > 0; 0 selects 1) and the linear-CDE kernels; its wave

@@ -48,11 +48,11 @@
 #endif
 
 enum { ORC_D1Q3 = 1, ORC_D2Q5 = 2, ORC_D2Q9 = 3, ORC_D3Q19 = 4, ORC_D2Q5II = 5, ORC_D3Q7 = 6,
-       ORC_D3Q9 = 7 };
+       ORC_D3Q9 = 7, ORC_D3Q27 = 8 };
 enum { ORC_LCDE = 0, ORC_BURGERS = 1, ORC_NSE = 2, ORC_WAVE = 3 };
 
-#define ORC_MAXQ 19
-#define ORC_MAXP 9
+#define ORC_MAXQ 27
+#define ORC_MAXP 13
 
 typedef struct {
     int32_t lattice;      /* ORC_D1Q3 ...                                    */
@@ -83,6 +83,12 @@ typedef struct {
     int32_t multiset;
     int32_t pad2_;
     double ae[3], aeh[3], ao[3], aoh[3];
+    /* rectangular lattice of Appendix A (linear CDE): rect = 1 takes the
+     * spacing dxv[a] and d0v[a] = c_s,a^2 / c_a^2 per axis in place of dx
+     * and d0 (axes beyond the dimension ignored) */
+    int32_t rect;
+    int32_t pad3_;
+    double d0v[3], dxv[3];
 } orc_params;
 
 typedef struct {
@@ -101,64 +107,88 @@ static void set_e(orc_lattice *L, int j, int x, int y, int z)
 }
 
 /* Appendix A with d0_alpha = d0 on every axis (square / cubic grids). */
-static int build_lattice(int lattice, double d0, orc_lattice *L)
+/* Weights of Appendix A with d0_a = dv[a] per axis (equal values: the
+ * square / cubic lattice); rD2Q5II and rD3Q9 take one d0 (dv[0]). */
+static int build_lattice_v(int lattice, const double *dv, orc_lattice *L)
 {
+    const double d0 = dv[0], dx = dv[0], dy = dv[1], dz = dv[2];
     memset(L, 0, sizeof(*L));
     if (lattice == ORC_D1Q3) {
         L->dim = 1; L->b = 3;
         set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, -1, 0, 0);
-        L->w[0] = 1.0 - d0;
-        L->w[1] = d0 / 2.0;
-        L->w[2] = d0 / 2.0;
+        L->w[0] = 1.0 - dx;
+        L->w[1] = dx / 2.0;
+        L->w[2] = dx / 2.0;
     } else if (lattice == ORC_D2Q5) {
         L->dim = 2; L->b = 5;
         set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
         set_e(L, 3, -1, 0, 0); set_e(L, 4, 0, -1, 0);
-        L->w[0] = 1.0 - d0 - d0;
-        L->w[1] = d0 / 2.0; L->w[3] = L->w[1];
-        L->w[2] = d0 / 2.0; L->w[4] = L->w[2];
+        L->w[0] = 1.0 - dx - dy;
+        L->w[1] = dx / 2.0; L->w[3] = L->w[1];
+        L->w[2] = dy / 2.0; L->w[4] = L->w[2];
     } else if (lattice == ORC_D2Q9) {
         L->dim = 2; L->b = 9;
         set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
         set_e(L, 3, -1, 0, 0); set_e(L, 4, 0, -1, 0); set_e(L, 5, 1, 1, 0);
         set_e(L, 6, -1, 1, 0); set_e(L, 7, -1, -1, 0); set_e(L, 8, 1, -1, 0);
-        L->w[0] = (1.0 - d0) * (1.0 - d0);
-        L->w[1] = d0 * (1.0 - d0) / 2.0; L->w[3] = L->w[1];
-        L->w[2] = (1.0 - d0) * d0 / 2.0; L->w[4] = L->w[2];
-        L->w[5] = d0 * d0 / 4.0;
+        L->w[0] = (1.0 - dx) * (1.0 - dy);
+        L->w[1] = dx * (1.0 - dy) / 2.0; L->w[3] = L->w[1];
+        L->w[2] = (1.0 - dx) * dy / 2.0; L->w[4] = L->w[2];
+        L->w[5] = dx * dy / 4.0;
         L->w[6] = L->w[5]; L->w[7] = L->w[5]; L->w[8] = L->w[5];
-    } else if (lattice == ORC_D3Q19) {
-        /* The xz-edge block of the printed table repeats two velocities; the
-         * edge sets here follow the xy pattern (+,+),(-,+),(-,-),(+,-). */
-        static const int E[19][3] = {
+    } else if (lattice == ORC_D3Q19 || lattice == ORC_D3Q27) {
+        /* The xz-edge block of the printed tables repeats two velocities; the
+         * edge sets here follow the xy pattern (+,+),(-,+),(-,-),(+,-).
+         * rD3Q27 adds the eight corners in the printed order. */
+        static const int E[27][3] = {
             {0,0,0}, {1,0,0}, {0,1,0}, {0,0,1}, {-1,0,0}, {0,-1,0}, {0,0,-1},
             {1,1,0}, {-1,1,0}, {-1,-1,0}, {1,-1,0},
             {1,0,1}, {-1,0,1}, {-1,0,-1}, {1,0,-1},
-            {0,1,1}, {0,-1,1}, {0,-1,-1}, {0,1,-1}};
-        L->dim = 3; L->b = 19;
-        for (int j = 0; j < 19; ++j) set_e(L, j, E[j][0], E[j][1], E[j][2]);
-        L->w[0] = 1.0 - d0 - d0 - d0 + d0 * d0 + d0 * d0 + d0 * d0;
-        double w1 = d0 * (1.0 - d0 - d0) / 2.0;
-        double we = d0 * d0 / 4.0;
-        for (int j = 1; j <= 6; ++j) L->w[j] = w1;
-        for (int j = 7; j <= 18; ++j) L->w[j] = we;
+            {0,1,1}, {0,-1,1}, {0,-1,-1}, {0,1,-1},
+            {1,1,1}, {1,1,-1}, {1,-1,1}, {-1,1,1},
+            {-1,-1,-1}, {-1,-1,1}, {-1,1,-1}, {1,-1,-1}};
+        const int b = lattice == ORC_D3Q19 ? 19 : 27;
+        L->dim = 3; L->b = b;
+        for (int j = 0; j < b; ++j) set_e(L, j, E[j][0], E[j][1], E[j][2]);
+        if (lattice == ORC_D3Q19) {
+            L->w[0] = 1.0 - dx - dy - dz + dx * dy + dx * dz + dy * dz;
+            L->w[1] = dx * (1.0 - dy - dz) / 2.0; L->w[4] = L->w[1];
+            L->w[2] = dy * (1.0 - dx - dz) / 2.0; L->w[5] = L->w[2];
+            L->w[3] = dz * (1.0 - dx - dy) / 2.0; L->w[6] = L->w[3];
+            for (int j = 7; j <= 10; ++j) L->w[j] = dx * dy / 4.0;
+            for (int j = 11; j <= 14; ++j) L->w[j] = dx * dz / 4.0;
+            for (int j = 15; j <= 18; ++j) L->w[j] = dy * dz / 4.0;
+        } else {
+            L->w[0] = (1.0 - dx) * (1.0 - dy) * (1.0 - dz);
+            L->w[1] = dx * (1.0 - dy) * (1.0 - dz) / 2.0; L->w[4] = L->w[1];
+            L->w[2] = dy * (1.0 - dx) * (1.0 - dz) / 2.0; L->w[5] = L->w[2];
+            L->w[3] = dz * (1.0 - dx) * (1.0 - dy) / 2.0; L->w[6] = L->w[3];
+            for (int j = 7; j <= 10; ++j) L->w[j] = dx * dy * (1.0 - dz) / 4.0;
+            for (int j = 11; j <= 14; ++j) L->w[j] = dx * dz * (1.0 - dy) / 4.0;
+            for (int j = 15; j <= 18; ++j) L->w[j] = dy * dz * (1.0 - dx) / 4.0;
+            for (int j = 19; j <= 26; ++j) L->w[j] = dx * dy * dz / 8.0;
+        }
     } else if (lattice == ORC_D2Q5II) {
         /* the rest velocity and the four diagonals, weights d0 / 4 */
+        if (dy != d0) return -1;
         L->dim = 2; L->b = 5;
         set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 1, 0); set_e(L, 2, -1, 1, 0);
         set_e(L, 3, -1, -1, 0); set_e(L, 4, 1, -1, 0);
         L->w[0] = 1.0 - d0;
         for (int j = 1; j <= 4; ++j) L->w[j] = d0 / 4.0;
     } else if (lattice == ORC_D3Q7) {
-        /* the rest velocity and the six axis directions, weights d0 / 2 */
+        /* the rest velocity and the six axis directions, weights d0_a / 2 */
         L->dim = 3; L->b = 7;
         set_e(L, 0, 0, 0, 0); set_e(L, 1, 1, 0, 0); set_e(L, 2, 0, 1, 0);
         set_e(L, 3, 0, 0, 1); set_e(L, 4, -1, 0, 0); set_e(L, 5, 0, -1, 0);
         set_e(L, 6, 0, 0, -1);
-        L->w[0] = 1.0 - d0 - d0 - d0;
-        for (int j = 1; j <= 6; ++j) L->w[j] = d0 / 2.0;
+        L->w[0] = 1.0 - dx - dy - dz;
+        L->w[1] = dx / 2.0; L->w[4] = L->w[1];
+        L->w[2] = dy / 2.0; L->w[5] = L->w[2];
+        L->w[3] = dz / 2.0; L->w[6] = L->w[3];
     } else if (lattice == ORC_D3Q9) {
         /* the rest velocity and the eight cube corners, weights d0 / 8 */
+        if (dy != d0 || dz != d0) return -1;
         static const int E[9][3] = {
             {0,0,0}, {1,1,1}, {1,1,-1}, {1,-1,1}, {-1,1,1},
             {-1,-1,-1}, {-1,-1,1}, {-1,1,-1}, {1,-1,-1}};
@@ -182,6 +212,12 @@ static int build_lattice(int lattice, double d0, orc_lattice *L)
     return 0;
 }
 
+static int build_lattice(int lattice, double d0, orc_lattice *L)
+{
+    const double dv[3] = {d0, d0, d0};
+    return build_lattice_v(lattice, dv, L);
+}
+
 /* ------------------------------------------------- derived constant tables */
 
 typedef struct {
@@ -189,6 +225,8 @@ typedef struct {
     int dim;
     int64_t n[3], N;
     double inv_d0;
+    int rect;                 /* per-axis d0 (rectangular lattice)           */
+    double inv_d0v[3];        /* 1 / d0_a                                    */
     double qd[ORC_MAXQ][3];   /* (e_a^2 - d0) / (d0 (1 - d0))                */
     double qo[ORC_MAXQ][3];   /* e_a e_b / d0^2 for (a,b) = (0,1),(0,2),(1,2)*/
     double w1[ORC_MAXQ];      /* w_j / d0                                    */
@@ -240,7 +278,15 @@ static double edot(const orc_ctx *c, int j, const double *B)
 static int make_ctx(const orc_params *P, orc_ctx *c)
 {
     memset(c, 0, sizeof(*c));
-    if (build_lattice(P->lattice, P->d0, &c->L)) return -1;
+    /* per-axis d0 and spacing (rectangular lattice: linear CDE only) */
+    double d0v[3] = {P->d0, P->d0, P->d0}, dxv[3] = {P->dx, P->dx, P->dx};
+    if (P->rect) {
+        if (P->eq != ORC_LCDE) return -1;
+        for (int a = 0; a < 3; ++a) { d0v[a] = P->d0v[a]; dxv[a] = P->dxv[a]; }
+    }
+    if (build_lattice_v(P->lattice, d0v, &c->L)) return -1;
+    c->rect = P->rect;
+    for (int a = 0; a < 3; ++a) c->inv_d0v[a] = 1.0 / d0v[a];
     c->dim = c->L.dim;
     c->N = 1;
     for (int a = 0; a < 3; ++a) {
@@ -250,13 +296,17 @@ static int make_ctx(const orc_params *P, orc_ctx *c)
     }
     const double d0 = P->d0;
     c->inv_d0 = 1.0 / d0;
+    /* Eq. (3-4) in lattice units: c~_ja = e_ja / d0_a,
+     * Q~_jaa = (e_ja^2 - d0_a) / (d0_a (1 - d0_a)), Q~_jab = e_ja e_jb / (2 d0_a d0_b)
+     * (the factor 2 of the off-diagonal pair is taken by summing (a,b) once) */
     for (int j = 0; j < c->L.b; ++j) {
         for (int a = 0; a < 3; ++a) {
             double ea = (double)c->L.e[j][a];
-            c->qd[j][a] = (ea * ea - d0) / (d0 * (1.0 - d0));
+            c->qd[j][a] = (ea * ea - d0v[a]) / (d0v[a] * (1.0 - d0v[a]));
         }
         for (int o = 0; o < 3; ++o)
-            c->qo[j][o] = (double)(c->L.e[j][OFF_A[o]] * c->L.e[j][OFF_B[o]]) / (d0 * d0);
+            c->qo[j][o] = (double)(c->L.e[j][OFF_A[o]] * c->L.e[j][OFF_B[o]]) /
+                          (d0v[OFF_A[o]] * d0v[OFF_B[o]]);
         c->w1[j] = c->L.w[j] * c->inv_d0;
     }
     /* scheme sums, Eq. (2-7-1) */
@@ -282,23 +332,29 @@ static int make_ctx(const orc_params *P, orc_ctx *c)
         double A10 = -c->Ah0 - 1.0;
         double A22 = 0.5 * (c->ap + c->ahp);
         double ratio = -A10 / A22;
-        for (int a = 0; a < 3; ++a) c->uh[a] = P->u[a] * P->dt / P->dx;
-        for (int i = 0; i < 9; ++i) c->kh[i] = P->K[i] * P->dt / (P->dx * P->dx);
+        /* lattice units per axis: u_a dt / dx_a, K_ab dt / (dx_a dx_b) */
+        for (int a = 0; a < 3; ++a) c->uh[a] = P->u[a] * P->dt / dxv[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                c->kh[a * 3 + b] = P->K[a * 3 + b] * P->dt / (dxv[a] * dxv[b]);
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
                 double v = ratio * c->kh[a * 3 + b];
-                if (a == b) v = v - d0;
+                if (a == b) v = v - d0v[a];
                 if (P->lambda_bar) v = v + c->uh[a] * c->uh[b];
                 c->Ch[a * 3 + b] = v;
             }
+        /* c~_j . uh: e_ja uh_a / d0_a summed over the axes (square: one d0) */
+        double ut[3];
+        for (int a = 0; a < 3; ++a) ut[a] = c->uh[a] / d0v[a];
         for (int j = 0; j < c->L.b; ++j) {
-            double eu = edot(c, j, c->uh);
-            c->ubar[j] = c->L.w[j] * ((1.0 + eu * c->inv_d0) + quad_term(c, j, c->Ch));
+            double lin = P->rect ? edot(c, j, ut) : edot(c, j, c->uh) * c->inv_d0;
+            c->ubar[j] = c->L.w[j] * ((1.0 + lin) + quad_term(c, j, c->Ch));
         }
         for (int p = 0; p < c->L.npair; ++p) {
             int j = c->L.pair[p];
             c->ubp[p] = c->L.w[j] * (1.0 + quad_term(c, j, c->Ch));
-            c->ubm[p] = c->w1[j] * edot(c, j, c->uh);
+            c->ubm[p] = P->rect ? c->L.w[j] * edot(c, j, ut) : c->w1[j] * edot(c, j, c->uh);
             c->Cp[p] = c->ap * c->ubp[p];
             c->Cm[p] = c->am * c->ubm[p];
             c->Chp[p] = c->ahp * c->ubp[p];
@@ -388,7 +444,14 @@ static void edf_args(const orc_ctx *c, int eq, const double *m, double *A,
 static double edf_full(const orc_ctx *c, int j, double A, const double *B,
                        const double *C, int hasC)
 {
-    double t = A + edot(c, j, B) * c->inv_d0;
+    double t;
+    if (c->rect) {
+        double Bt[3];
+        for (int a = 0; a < 3; ++a) Bt[a] = B[a] * c->inv_d0v[a];
+        t = A + edot(c, j, Bt);
+    } else {
+        t = A + edot(c, j, B) * c->inv_d0;
+    }
     if (hasC) t = t + quad_term(c, j, C);
     return c->L.w[j] * t;
 }
@@ -1036,6 +1099,7 @@ static void source_mmfd(const orc_params *P, const orc_ctx *c, const orc_source 
 int orc_mmfd_source_step(const orc_params *P, const orc_source *Q, const double *cur,
                          const double *prev, const double *St, const double *Sm, double *out)
 {
+    if (P->rect) return -1;  /* the source term is written for square lattices */
     if (P->eq != ORC_LCDE || P->bc) return -5;
     int rc = orc_mmfd_step(P, cur, prev, out);
     if (rc) return rc;
@@ -1051,6 +1115,7 @@ int orc_mmfd_source_step(const orc_params *P, const orc_source *Q, const double 
 int orc_literal_source_step(const orc_params *P, const orc_source *Q, const double *cur,
                             const double *prev, const double *St, const double *Sm, double *out)
 {
+    if (P->rect) return -1;  /* the source term is written for square lattices */
     if (P->eq != ORC_LCDE || P->bc) return -5;
     int rc = orc_literal_step(P, cur, prev, out);
     if (rc) return rc;
@@ -1075,6 +1140,7 @@ int orc_mesofd_source_step(const orc_params *P, const orc_source *Q, const doubl
                            const double *prev_mom, const double *St, const double *Sm,
                            double *pop_out, double *mom_out)
 {
+    if (P->rect) return -1;  /* the source term is written for square lattices */
     if (P->eq != ORC_LCDE || P->bc) return -5;
     return mesofd_step(P, Q, pop, prev_mom, St, Sm, pop_out, mom_out);
 }
@@ -1155,12 +1221,43 @@ int orc_lattice_info(int lattice, double d0, int *e, double *w, int *npair, int 
     return L.b;
 }
 
+/* the same with d0_a per axis (rectangular lattices of Appendix A) */
+int orc_lattice_info_rect(int lattice, const double *d0v, int *e, double *w, int *npair, int *pairs)
+{
+    orc_lattice L;
+    if (build_lattice_v(lattice, d0v, &L)) return -1;
+    for (int j = 0; j < L.b; ++j) {
+        for (int a = 0; a < 3; ++a) e[j * 3 + a] = L.e[j][a];
+        w[j] = L.w[j];
+    }
+    *npair = L.npair;
+    for (int p = 0; p < L.npair; ++p) pairs[p] = L.pair[p];
+    return L.b;
+}
+
 /* EDF g_j(A,B,C) of Eq. (3-3) for every direction (used by identity pins) */
 int orc_edf(int lattice, double d0, double A, const double *B, const double *C, double *g)
 {
     orc_params P;
     memset(&P, 0, sizeof(P));
     P.lattice = lattice; P.d0 = d0; P.eq = ORC_NSE; P.rho0 = 1.0;
+    P.n[0] = P.n[1] = P.n[2] = 1;
+    orc_ctx c;
+    if (make_ctx(&P, &c)) return -1;
+    for (int j = 0; j < c.L.b; ++j) g[j] = edf_full(&c, j, A, B, C, 1);
+    return c.L.b;
+}
+
+/* the same on a rectangular lattice with d0_a per axis (c~_ja = e_ja / d0_a,
+ * Q~ of Eq. (3-4) per axis) */
+int orc_edf_rect(int lattice, const double *d0v, double A, const double *B, const double *C,
+                 double *g)
+{
+    orc_params P;
+    memset(&P, 0, sizeof(P));
+    P.lattice = lattice; P.d0 = d0v[0]; P.eq = ORC_LCDE; P.rect = 1;
+    P.dx = P.dt = 1.0;
+    for (int a = 0; a < 3; ++a) { P.d0v[a] = d0v[a]; P.dxv[a] = 1.0; }
     P.n[0] = P.n[1] = P.n[2] = 1;
     orc_ctx c;
     if (make_ctx(&P, &c)) return -1;

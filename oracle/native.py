@@ -17,11 +17,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mfd_oracle.c")
 LIB = os.path.join(HERE, "libmfd_oracle.so")
 
-LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7}
-DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3}
-QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9}
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7,
+            "D3Q27": 8}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3,
+        "D3Q27": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9,
+      "D3Q27": 27}
 EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
-MAXP = 9
+MAXP = 13
+MAXQ = 27
 
 
 def build(force: bool = True) -> str:
@@ -51,6 +55,8 @@ class Params(C.Structure):
         ("multiset", C.c_int32), ("pad2_", C.c_int32),
         ("ae", C.c_double * 3), ("aeh", C.c_double * 3),
         ("ao", C.c_double * 3), ("aoh", C.c_double * 3),
+        ("rect", C.c_int32), ("pad3_", C.c_int32),
+        ("d0v", C.c_double * 3), ("dxv", C.c_double * 3),
     ]
 
 
@@ -90,6 +96,11 @@ def lib():
         L.orc_lattice_info.restype = C.c_int
         L.orc_edf.argtypes = [C.c_int, C.c_double, C.c_double, D, D, D]
         L.orc_edf.restype = C.c_int
+        L.orc_lattice_info_rect.argtypes = [C.c_int, D, C.POINTER(C.c_int), D,
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_lattice_info_rect.restype = C.c_int
+        L.orc_edf_rect.argtypes = [C.c_int, D, C.c_double, D, D, D]
+        L.orc_edf_rect.restype = C.c_int
         L.orc_theta_solve.argtypes = [P, D, D, D, C.c_double, C.c_int, C.c_int,
                                       C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_theta_solve.restype = C.c_int
@@ -146,6 +157,15 @@ def make_params(spec: dict) -> Params:
     P.ab = _triple([float(x) for x in spec.get("ab", a)])
     P.abh = _triple([float(x) for x in spec.get("abh", ah)])
     P.theta = float(spec.get("theta", 1.0))
+    if "d0v" in spec or "dxv" in spec:
+        # rectangular lattice (linear CDE): d0 and spacing per axis
+        d0 = float(spec.get("d0", 1.0 / 3.0))
+        dx = float(spec.get("dx", 1.0))
+        d0v = list(spec.get("d0v", [d0] * 3)) + [d0] * 3
+        dxv = list(spec.get("dxv", [dx] * 3)) + [dx] * 3
+        P.rect = 1
+        P.d0v = (C.c_double * 3)(*[float(v) for v in d0v[:3]])
+        P.dxv = (C.c_double * 3)(*[float(v) for v in dxv[:3]])
     if "ae" in spec or "ao" in spec:
         # multiple-set scheme, Eq. (2-2-1b): even set ae/aeh, odd set ao/aoh
         P.multiset = 1
@@ -309,10 +329,10 @@ def tables(spec):
 
 def lattice_info(lattice, d0=1.0 / 3.0):
     """(e[b,3] int, w[b], pair representatives)."""
-    e = (C.c_int * 57)()
-    w = np.zeros(19)
+    e = (C.c_int * (3 * MAXQ))()
+    w = np.zeros(MAXQ)
     npair = C.c_int()
-    pairs = (C.c_int * 9)()
+    pairs = (C.c_int * MAXP)()
     b = lib().orc_lattice_info(LATTICES[lattice], d0, e, _ptr(w), C.byref(npair), pairs)
     _check(b, "lattice_info")
     E = np.array(e[: 3 * b], dtype=np.int64).reshape(b, 3)
@@ -327,9 +347,38 @@ def edf(lattice, d0, A, B, Cm):
     Cm = np.asarray(Cm, dtype=np.float64)
     C9[: Cm.shape[0], : Cm.shape[1]] = Cm
     C9 = np.ascontiguousarray(C9.ravel())
-    g = np.zeros(19)
+    g = np.zeros(MAXQ)
     b = lib().orc_edf(LATTICES[lattice], d0, float(A), _ptr(np.ascontiguousarray(B3)), _ptr(C9), _ptr(g))
     _check(b, "edf")
+    return g[:b].copy()
+
+
+def lattice_info_rect(lattice, d0v):
+    """(e[b,3] int, w[b], pair representatives) with d0 per axis."""
+    e = (C.c_int * (3 * MAXQ))()
+    w = np.zeros(MAXQ)
+    npair = C.c_int()
+    pairs = (C.c_int * MAXP)()
+    dv = np.ascontiguousarray((list(d0v) + [d0v[0]] * 3)[:3], dtype=np.float64)
+    b = lib().orc_lattice_info_rect(LATTICES[lattice], _ptr(dv), e, _ptr(w), C.byref(npair), pairs)
+    _check(b, "lattice_info_rect")
+    E = np.array(e[: 3 * b], dtype=np.int64).reshape(b, 3)
+    return E, w[:b].copy(), [pairs[i] for i in range(npair.value)]
+
+
+def edf_rect(lattice, d0v, A, B, Cm):
+    """g_j(A, B, C) of Eq. (3-3) in lattice units with d0 per axis, all j."""
+    B3 = np.zeros(3)
+    B3[: len(B)] = B
+    C9 = np.zeros((3, 3))
+    Cm = np.asarray(Cm, dtype=np.float64)
+    C9[: Cm.shape[0], : Cm.shape[1]] = Cm
+    C9 = np.ascontiguousarray(C9.ravel())
+    dv = np.ascontiguousarray((list(d0v) + [d0v[0]] * 3)[:3], dtype=np.float64)
+    g = np.zeros(MAXQ)
+    b = lib().orc_edf_rect(LATTICES[lattice], _ptr(dv), float(A), _ptr(np.ascontiguousarray(B3)),
+                           _ptr(C9), _ptr(g))
+    _check(b, "edf_rect")
     return g[:b].copy()
 
 

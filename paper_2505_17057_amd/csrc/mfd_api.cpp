@@ -710,7 +710,8 @@ int Solver::theta_mg_steps(int64_t nsteps) {
 }
 
 bool Solver::source_supported() const {
-  if (cfg.kind == MFD_THETA || consts.eq != kLCDE || consts.wave || dirichlet) return false;
+  if (cfg.kind == MFD_THETA || consts.eq != kLCDE || consts.wave || dirichlet || cfg.rect)
+    return false;
   return grid.form == MFD_MMFD || grid.dim <= 2;  // MesoFD: 1D / 2D
 }
 
@@ -848,6 +849,11 @@ static int rebuild(Solver *s) {
   in.rho0 = s->cfg.ep.rho0;
   in.he_luo = s->cfg.ep.he_luo;
   in.multiset = s->cfg.multiset;
+  in.rect = s->cfg.rect;
+  for (int k = 0; k < 3; ++k) {
+    in.d0v[k] = s->cfg.d0v[k];
+    in.dxv[k] = s->cfg.dxv[k];
+  }
   for (int k = 0; k < 3; ++k) {
     in.ae[k] = s->cfg.ae[k];
     in.ao[k] = s->cfg.ao[k];
@@ -875,7 +881,39 @@ extern "C" int mfd_set_lattice(mfd_solver *h, int lattice, double d0) {
   if (!(d0 < 1.0)) return s->fail(MFD_E_ARG, "d0 must lie in (0, 1)");
   s->cfg.lattice = lattice;
   s->cfg.d0 = d0;
+  s->cfg.rect = 0;  // a new lattice is square until mfd_set_rectangular
   s->have_lattice = true;
+  return rebuild(s);
+}
+
+extern "C" int mfd_set_rectangular(mfd_solver *h, const double dx[3], const double d0[3]) {
+  SOLVER_OR_ARG(h);
+  Solver *s = reinterpret_cast<Solver *>(h);
+  if (!dx || !d0) return s->fail(MFD_E_ARG, "null spacing or d0");
+  if (!s->have_lattice) return s->fail(MFD_E_ORDER, "mfd_set_lattice must precede mfd_set_rectangular");
+  if (s->have_eq && s->cfg.eq != MFD_LCDE)
+    return s->fail(MFD_E_UNSUPPORTED, "rectangular lattices are implemented for the linear CDE");
+  if (s->src_on)
+    return s->fail(MFD_E_UNSUPPORTED, "the source term is implemented for square lattices");
+  const int dim = s->grid.dim;
+  double dv[3], xv[3];
+  for (int a = 0; a < 3; ++a) {
+    dv[a] = a < dim ? d0[a] : d0[0];
+    xv[a] = a < dim ? dx[a] : dx[0];
+    if (!(dv[a] > 0.0 && dv[a] < 1.0) || !(xv[a] > 0.0) || !std::isfinite(xv[a]))
+      return s->fail(MFD_E_ARG, "d0 per axis must lie in (0, 1) and the spacing be positive");
+  }
+  Consts c;
+  std::memset(&c, 0, sizeof(c));
+  const int rc = lattice_weights_v(s->cfg.lattice, dv, c);
+  if (rc == MFD_E_UNSUPPORTED)
+    return s->fail(rc, "rD2Q5II and rD3Q9 take one d0 on every axis");
+  if (rc) return s->fail(MFD_E_ARG, "a weight of the lattice is not positive for these d0");
+  s->cfg.rect = 1;
+  for (int a = 0; a < 3; ++a) {
+    s->cfg.d0v[a] = dv[a];
+    s->cfg.dxv[a] = xv[a];
+  }
   return rebuild(s);
 }
 
@@ -885,6 +923,8 @@ extern "C" int mfd_set_equation(mfd_solver *h, int eq, const mfd_eq_params *p) {
   if (!p) return s->fail(MFD_E_ARG, "null equation parameters");
   if (eq != MFD_LCDE && eq != MFD_BURGERS && eq != MFD_NSE && eq != MFD_WAVE)
     return s->fail(MFD_E_ARG, "unknown equation %d", eq);
+  if (s->cfg.rect && eq != MFD_LCDE)
+    return s->fail(MFD_E_UNSUPPORTED, "rectangular lattices are implemented for the linear CDE");
   if (eq == MFD_NSE && s->dirichlet)
     return s->fail(MFD_E_UNSUPPORTED, "Dirichlet boundaries are implemented for scalar equations");
   if (eq == MFD_WAVE && !(p->beta == 0.0 || (p->beta > 0.0 && std::isfinite(p->beta))))

@@ -57,52 +57,59 @@ double quad(const Consts &c, int j, const double *C) {
 
 }  // namespace
 
-int lattice_weights(int lattice, double d0, Consts &c) {
+int lattice_weights_v(int lattice, const double d0v[3], Consts &c) {
+  const double d0 = d0v[0], dx = d0v[0], dy = d0v[1], dz = d0v[2];
   switch (lattice) {
     case MFD_D1Q3:
       copy_lattice<LatD1Q3>(c);
-      c.w[0] = 1.0 - d0;
-      c.w[1] = d0 / 2.0;
-      c.w[2] = d0 / 2.0;
+      c.w[0] = 1.0 - dx;
+      c.w[1] = dx / 2.0;
+      c.w[2] = dx / 2.0;
       break;
     case MFD_D2Q5:
       copy_lattice<LatD2Q5>(c);
-      c.w[0] = 1.0 - d0 - d0;
-      c.w[1] = d0 / 2.0;
+      c.w[0] = 1.0 - dx - dy;
+      c.w[1] = dx / 2.0;
       c.w[3] = c.w[1];
-      c.w[2] = d0 / 2.0;
+      c.w[2] = dy / 2.0;
       c.w[4] = c.w[2];
       break;
     case MFD_D2Q9:
       copy_lattice<LatD2Q9>(c);
-      c.w[0] = (1.0 - d0) * (1.0 - d0);
-      c.w[1] = d0 * (1.0 - d0) / 2.0;
+      c.w[0] = (1.0 - dx) * (1.0 - dy);
+      c.w[1] = dx * (1.0 - dy) / 2.0;
       c.w[3] = c.w[1];
-      c.w[2] = (1.0 - d0) * d0 / 2.0;
+      c.w[2] = (1.0 - dx) * dy / 2.0;
       c.w[4] = c.w[2];
-      c.w[5] = d0 * d0 / 4.0;
+      c.w[5] = dx * dy / 4.0;
       c.w[6] = c.w[7] = c.w[8] = c.w[5];
       break;
     case MFD_D3Q19: {
       copy_lattice<LatD3Q19>(c);
-      c.w[0] = 1.0 - d0 - d0 - d0 + d0 * d0 + d0 * d0 + d0 * d0;
-      const double w1 = d0 * (1.0 - d0 - d0) / 2.0;
-      const double we = d0 * d0 / 4.0;
-      for (int j = 1; j <= 6; ++j) c.w[j] = w1;
-      for (int j = 7; j <= 18; ++j) c.w[j] = we;
+      c.w[0] = 1.0 - dx - dy - dz + dx * dy + dx * dz + dy * dz;
+      c.w[1] = c.w[4] = dx * (1.0 - dy - dz) / 2.0;
+      c.w[2] = c.w[5] = dy * (1.0 - dx - dz) / 2.0;
+      c.w[3] = c.w[6] = dz * (1.0 - dx - dy) / 2.0;
+      for (int j = 7; j <= 10; ++j) c.w[j] = dx * dy / 4.0;
+      for (int j = 11; j <= 14; ++j) c.w[j] = dx * dz / 4.0;
+      for (int j = 15; j <= 18; ++j) c.w[j] = dy * dz / 4.0;
       break;
     }
     case MFD_D2Q5II:
+      if (dy != d0) return MFD_E_UNSUPPORTED;
       copy_lattice<LatD2Q5II>(c);
       c.w[0] = 1.0 - d0;
       for (int j = 1; j <= 4; ++j) c.w[j] = d0 / 4.0;
       break;
     case MFD_D3Q7:
       copy_lattice<LatD3Q7>(c);
-      c.w[0] = 1.0 - d0 - d0 - d0;
-      for (int j = 1; j <= 6; ++j) c.w[j] = d0 / 2.0;
+      c.w[0] = 1.0 - dx - dy - dz;
+      c.w[1] = c.w[4] = dx / 2.0;
+      c.w[2] = c.w[5] = dy / 2.0;
+      c.w[3] = c.w[6] = dz / 2.0;
       break;
     case MFD_D3Q9:
+      if (dy != d0 || dz != d0) return MFD_E_UNSUPPORTED;
       copy_lattice<LatD3Q9>(c);
       c.w[0] = 1.0 - d0;
       for (int j = 1; j <= 8; ++j) c.w[j] = d0 / 8.0;
@@ -117,20 +124,36 @@ int lattice_weights(int lattice, double d0, Consts &c) {
   return MFD_OK;
 }
 
+int lattice_weights(int lattice, double d0, Consts &c) {
+  const double dv[3] = {d0, d0, d0};
+  return lattice_weights_v(lattice, dv, c);
+}
+
 int build_consts(const SchemeInput &in, Consts &c) {
   std::memset(&c, 0, sizeof(c));
-  int rc = lattice_weights(in.lattice, in.d0, c);
+  // d0 and spacing per axis (rectangular lattice: the linear CDE only)
+  double d0v[3] = {in.d0, in.d0, in.d0}, dxv[3] = {in.dx, in.dx, in.dx};
+  if (in.rect) {
+    if (in.eq != kLCDE) return MFD_E_UNSUPPORTED;
+    for (int x = 0; x < 3; ++x) {
+      d0v[x] = in.d0v[x];
+      dxv[x] = in.dxv[x];
+    }
+  }
+  int rc = lattice_weights_v(in.lattice, d0v, c);
   if (rc) return rc;
   const double d0 = in.d0;
   c.eq = in.eq;
   c.inv_d0 = 1.0 / d0;
+  // Eq. (3-4) in lattice units, per axis
   for (int j = 0; j < c.q; ++j) {
     for (int a = 0; a < 3; ++a) {
       const double ea = (double)c.e[j][a];
-      c.qd[j][a] = (ea * ea - d0) / (d0 * (1.0 - d0));
+      c.qd[j][a] = (ea * ea - d0v[a]) / (d0v[a] * (1.0 - d0v[a]));
     }
     for (int o = 0; o < 3; ++o)
-      c.qo[j][o] = (double)(c.e[j][kOffA[o]] * c.e[j][kOffB[o]]) / (d0 * d0);
+      c.qo[j][o] =
+          (double)(c.e[j][kOffA[o]] * c.e[j][kOffB[o]]) / (d0v[kOffA[o]] * d0v[kOffB[o]]);
     c.w1[j] = c.w[j] * c.inv_d0;
   }
   const double *a = in.a, *ah = in.ah, *ab = in.ab, *abh = in.abh;
@@ -189,23 +212,29 @@ int build_consts(const SchemeInput &in, Consts &c) {
     const double A10 = -c.Ah0 - 1.0;
     const double A22 = 0.5 * (c.ap + c.ahp);
     const double ratio = -A10 / A22;
-    for (int x = 0; x < 3; ++x) c.uh[x] = in.u[x] * in.dt / in.dx;
-    for (int i = 0; i < 9; ++i) c.kh[i] = in.K[i] * in.dt / (in.dx * in.dx);
+    // lattice units per axis: u_a dt / dx_a, K_ab dt / (dx_a dx_b)
+    for (int x = 0; x < 3; ++x) c.uh[x] = in.u[x] * in.dt / dxv[x];
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y) c.kh[x * 3 + y] = in.K[x * 3 + y] * in.dt / (dxv[x] * dxv[y]);
     for (int x = 0; x < 3; ++x)
       for (int y = 0; y < 3; ++y) {
         double v = ratio * c.kh[x * 3 + y];
-        if (x == y) v = v - d0;
+        if (x == y) v = v - d0v[x];
         if (in.lambda_bar) v = v + c.uh[x] * c.uh[y];
         c.Ch[x * 3 + y] = v;
       }
+    // c~_j . uh: the square lattice divides the sum by d0 once, the
+    // rectangular one each axis by its own d0
+    double ut[3];
+    for (int x = 0; x < 3; ++x) ut[x] = c.uh[x] / d0v[x];
     for (int j = 0; j < c.q; ++j) {
-      const double eu = edot(c, j, c.uh);
-      c.ubar[j] = c.w[j] * ((1.0 + eu * c.inv_d0) + quad(c, j, c.Ch));
+      const double lin = in.rect ? edot(c, j, ut) : edot(c, j, c.uh) * c.inv_d0;
+      c.ubar[j] = c.w[j] * ((1.0 + lin) + quad(c, j, c.Ch));
     }
     for (int p = 0; p < c.npair; ++p) {
       const int j = c.pair[p];
       c.ubp[p] = c.w[j] * (1.0 + quad(c, j, c.Ch));
-      c.ubm[p] = c.w1[j] * edot(c, j, c.uh);
+      c.ubm[p] = in.rect ? c.w[j] * edot(c, j, ut) : c.w1[j] * edot(c, j, c.uh);
       c.Cp[p] = c.ap * c.ubp[p];
       c.Cm[p] = c.am * c.ubm[p];
       c.Chp[p] = c.ahp * c.ubp[p];

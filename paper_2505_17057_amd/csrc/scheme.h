@@ -23,9 +23,14 @@ struct SchemeInput {
   // the even EDF parts), odd set ao/aoh (first differences of the odd parts)
   int multiset;
   double ae[3], aeh[3], ao[3], aoh[3];
+  // rectangular lattice (Appendix A; linear CDE): d0 and spacing per axis
+  int rect;
+  double d0v[3], dxv[3];
 };
 
 int lattice_weights(int lattice, double d0, Consts &c);
+// the same with d0_a per axis (rD2Q5II and rD3Q9 take one value)
+int lattice_weights_v(int lattice, const double d0v[3], Consts &c);
 int build_consts(const SchemeInput &in, Consts &c);
 bool stability_proven(const Consts &c);
 double max_amplification(const Consts &c, const int64_t n[3]);

@@ -22,6 +22,8 @@ struct Config {
   double dt = 0.0;
   int multiset = 0;
   double ae[3] = {0, 0, 0}, aeh[3] = {0, 0, 0}, ao[3] = {0, 0, 0}, aoh[3] = {0, 0, 0};
+  int rect = 0;  // rectangular lattice: d0 and spacing per axis
+  double d0v[3] = {0, 0, 0}, dxv[3] = {0, 0, 0};
 };
 
 struct Solver {

@@ -118,6 +118,7 @@ _SIGS = {
     "mfd_set_scheme_sets": ([_H, C.c_int, _PD, _PD, _PD, _PD, _PD, _PD, C.c_double], C.c_int),
     "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
     "mfd_set_theta_multigrid": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "mfd_set_rectangular": ([_H, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "mfd_theta_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.c_int], C.c_int),
     "mfd_step_noalloc": ([_H, _VP, _VP, C.c_int64], C.c_int),
@@ -382,6 +383,12 @@ class Solver:
     def set_theta_tolerance(self, tol, chunk=0):
         return self.check(lib.mfd_set_theta_tolerance(self.h, float(tol), int(chunk)),
                           "mfd_set_theta_tolerance")
+
+    def set_rectangular(self, dx, d0):
+        """Spacing and d0 per axis (rectangular lattice, linear CDE)."""
+        return self.check(lib.mfd_set_rectangular(self.h, _d3((list(dx) + [dx[0]] * 3)[:3]),
+                                                  _d3((list(d0) + [d0[0]] * 3)[:3])),
+                          "mfd_set_rectangular")
 
     def set_theta_multigrid(self, levels=-1, pre=2, post=2):
         return self.check(lib.mfd_set_theta_multigrid(self.h, int(levels), int(pre), int(post)),

@@ -21,7 +21,7 @@ def rand_state(case, rng, scale=1.0):
 
 def oracle_spec(case):
     keys = ("lattice", "n", "d0", "dx", "dt", "eq", "a", "ah", "ab", "abh", "u", "K", "lambda_bar",
-            "beta", "rho0", "he_luo", "theta", "theta_iters")
+            "beta", "rho0", "he_luo", "theta", "theta_iters", "d0v", "dxv")
     spec = {k: case[k] for k in keys if k in case}
     spec["levels"] = 3 if case.get("kind") == "three_level" else 2
     if case.get("kind") != "three_level":
@@ -53,6 +53,9 @@ def run_oracle(case, cur, prev, steps):
 def make_solver(M, case, precision):
     s = M.Solver(case["lattice"], case["n"], case.get("dx", 1.0), precision, case.get("form", "mmfd"),
                  d0=case.get("d0", 1.0 / 3.0))
+    if "dxv" in case or "d0v" in case:
+        s.set_rectangular(case.get("dxv", [case.get("dx", 1.0)] * 3),
+                          case.get("d0v", [case.get("d0", 1.0 / 3.0)] * 3))
     s.set_equation(case.get("eq", "lcde"), u=case.get("u", ()), K=case.get("K"),
                    lambda_bar=case.get("lambda_bar", 0), beta=case.get("beta", 1.0),
                    rho0=case.get("rho0", 0.0), he_luo=case.get("he_luo", 0))

@@ -81,11 +81,22 @@ LIN = [
                   d0=0.25), (1.0, 0.0, 0.4), (0.0, -0.4, 0.0)),
     ("D3Q9", dict(n=(4, 5, 6), u=(0.1, 0.2, -0.1), K=[[0.2, 0.0, 0.0], [0.0, 0.2, 0.0], [0.0, 0.0, 0.2]]),
      (1.1, -0.2, 0.1), None),
+    # rectangular lattices: spacing and d0 per axis
+    ("D2Q9", dict(n=(8, 6), u=(0.3, -0.2), K=[[0.3, 0.05], [0.05, 0.2]], lambda_bar=1,
+                  dxv=(0.5, 2.0), d0v=(0.3, 0.45), dt=0.1), (1.0, 0.0, 0.0), None),
+    ("D2Q5", dict(n=(8, 6), u=(0.3, -0.2), K=[[0.3, 0.0], [0.0, 0.2]], dxv=(1.0, 1.5),
+                  d0v=(0.3, 0.2), dt=0.2), (0.875, 0.0, 0.125), (0.125, 0.0, -0.125)),
+    ("D3Q19", dict(n=(4, 5, 6), u=(0.1, 0.2, -0.1), K=[[0.2, 0.01, 0.0], [0.01, 0.3, 0.02], [0.0, 0.02, 0.25]],
+                   lambda_bar=1, dxv=(1.0, 0.5, 2.0), d0v=(0.3, 0.25, 0.2), dt=0.05), (1.0, 0.0, 0.4),
+     (0.0, -0.4, 0.0)),
+    ("D3Q7", dict(n=(4, 5, 6), u=(0.1, 0.2, -0.1), K=[[0.15, 0.0, 0.0], [0.0, 0.25, 0.0], [0.0, 0.0, 0.1]],
+                  dxv=(1.0, 1.25, 0.75), d0v=(0.3, 0.2, 0.25), dt=0.1), (1.0, 0.0, 0.0), None),
 ]
 
 
 @pytest.mark.parametrize("lat,kw,a,ah", LIN, ids=["d1q3", "d2q9-c2", "d2q9-3l", "d3q19-trt", "d2q5ii",
-                                                   "d3q7-trt", "d3q9"])
+                                                   "d3q7-trt", "d3q9", "rect-d2q9", "rect-d2q5-3l",
+                                                   "rect-d3q19-trt", "rect-d3q7"])
 def test_linear_constant_tables_bitwise(M, lat, kw, a, ah):
     """The library's and the oracle's EDF constants are formed independently
     from the same formulas; FP64 parity requires them to be identical."""
@@ -94,6 +105,8 @@ def test_linear_constant_tables_bitwise(M, lat, kw, a, ah):
                 dx=kw.get("dx", 1.0), dt=kw.get("dt", 1.0), **{k: v for k, v in kw.items() if k not in ("dx", "dt")})
     w, ub, tab = O.tables(spec)
     s = M.Solver(lat, kw["n"], kw.get("dx", 1.0), "fp64", "mmfd", d0=kw.get("d0", 1.0 / 3.0))
+    if "dxv" in kw:
+        s.set_rectangular(kw["dxv"], kw["d0v"])
     s.set_equation("lcde", u=kw["u"], K=kw["K"], lambda_bar=kw.get("lambda_bar", 0))
     s.set_scheme(kind, a, ah, dt=kw.get("dt", 1.0))
     gw, gub, gtab = s.linear_tables()
@@ -384,4 +397,42 @@ def test_theta_multigrid_argument_checks(M):
     with pytest.raises(M.MfdError) as ei:
         s.set_theta_multigrid(-1)
     assert ei.value.code == M.MFD_E_UNSUPPORTED
+    s.close()
+
+
+def test_rectangular_argument_checks(M):
+    """mfd_set_rectangular: after the lattice; the linear CDE only (either
+    order); one d0 on rD2Q5II / rD3Q9; d0 in (0, 1), positive spacing and
+    weights; no source term; a new lattice returns to the square one."""
+    s = M.Solver("D2Q9", (8, 8), 1.0, "fp64", "mmfd")
+    s.set_rectangular((0.5, 2.0), (0.3, 0.4))
+    with pytest.raises(M.MfdError) as e:
+        s.set_equation("burgers", beta=1.0)
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    for bad in (((0.5, 2.0), (0.0, 0.4)), ((0.5, 2.0), (0.3, 1.0)), ((0.0, 2.0), (0.3, 0.4))):
+        with pytest.raises(M.MfdError) as e:
+            s.set_rectangular(*bad)
+        assert e.value.code == M.MFD_E_ARG
+    s.set_equation("lcde", u=(0.1, 0.0), K=[[0.1, 0], [0, 0.1]])
+    s.set_scheme("two_level", (1.0, 0.0, 0.0), dt=0.1)
+    with pytest.raises(M.MfdError) as e:
+        s.set_source(np.zeros(64), 0.0, (0.0, 1.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0))
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    s.close()
+    s = M.Solver("D2Q5", (8, 8), 1.0, "fp64", "mmfd")
+    with pytest.raises(M.MfdError) as e:  # weight 1 - 0.6 - 0.5 < 0
+        s.set_rectangular((1.0, 1.0), (0.6, 0.5))
+    assert e.value.code == M.MFD_E_ARG
+    s.close()
+    s = M.Solver("D2Q5II", (8, 8), 1.0, "fp64", "mmfd")
+    with pytest.raises(M.MfdError) as e:
+        s.set_rectangular((1.0, 2.0), (0.3, 0.4))
+    assert e.value.code == M.MFD_E_UNSUPPORTED
+    s.set_rectangular((1.0, 2.0), (0.3, 0.3))  # one d0, two spacings
+    s.close()
+    s = M.Solver("D2Q9", (8, 8), 1.0, "fp64", "mmfd")
+    s.set_equation("nse", rho0=1.0)
+    with pytest.raises(M.MfdError) as e:
+        s.set_rectangular((0.5, 2.0), (0.3, 0.4))
+    assert e.value.code == M.MFD_E_UNSUPPORTED
     s.close()

@@ -11,16 +11,26 @@ import pytest
 from oracle import native as O
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "printed_values.json")))
-LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19", "D2Q5II", "D3Q7", "D3Q9"]
+LATS = ["D1Q3", "D2Q5", "D2Q9", "D3Q19", "D2Q5II", "D3Q7", "D3Q9", "D3Q27"]
 # Appendix A's ranges of d0 with every weight positive
 D0_MAX = {"D1Q3": 1.0, "D2Q5": 0.5, "D2Q9": 1.0, "D3Q19": 0.5, "D2Q5II": 1.0, "D3Q7": 1.0 / 3.0,
-          "D3Q9": 1.0}
+          "D3Q9": 1.0, "D3Q27": 1.0}
 
 
 def test_d2q9_weights_printed():
     _, w, _ = O.lattice_info("D2Q9", 1.0 / 3.0)
     want = [float(F(x)) for x in GOLD["d2q9_weights_d0_third"]["w"]]
     assert np.allclose(w, want, rtol=1e-15, atol=0)  # d0 = 1/3 is inexact: a few ulp
+
+
+def test_d3q27_weights_d0_third():
+    """rD3Q27 at d0 = 1/3: the product of the 1D weights 2/3, 1/6, 1/6 per
+    axis: 8/27 (rest), 2/27 (axes), 1/54 (edges), 1/216 (corners)."""
+    E, w, pairs = O.lattice_info("D3Q27", 1.0 / 3.0)
+    nz = np.abs(E).sum(1)
+    want = np.choose(nz, [8 / 27, 2 / 27, 1 / 54, 1 / 216])
+    assert np.allclose(w, want, rtol=1e-15, atol=0)
+    assert len(pairs) == 13 and sorted(np.bincount(nz)) == [1, 6, 8, 12]
 
 
 def test_d3q19_weights_d0_third():
@@ -126,7 +136,7 @@ def test_d3q7_weights_and_pairs():
     assert len(pairs) == 4 and all(np.abs(E[j]).sum() == 3 for j in pairs)
 
 
-@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
 def test_edf_third_moment(lat):
     """Eq. (3-7) with delta^(4) = c_s^2 (c^2 - 3 c_s^2) = 0 at d0 = 1/3:
     sum e_a e_b e_c g = d0 (delta_ab B_c + delta_ac B_b + delta_bc B_a)."""
@@ -144,7 +154,7 @@ def test_edf_third_moment(lat):
         assert np.allclose(M3, want, atol=1e-14)
 
 
-@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
 def test_nse_edf_is_textbook_lbgk(lat):
     """Eq. (NSEfeq) at d0 = 1/3 equals w rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u)."""
     rng = np.random.default_rng(2)
