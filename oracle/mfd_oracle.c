@@ -89,6 +89,10 @@ typedef struct {
     int32_t rect;
     int32_t pad3_;
     double d0v[3], dxv[3];
+    /* linear CDE: -A10 / A22 of the scheme when > 0 (schemes beyond the
+     * three-level one, Eq. (4-2-00a) moments of their own coefficients);
+     * 0: from a / ah */
+    double ratio;
 } orc_params;
 
 typedef struct {
@@ -331,7 +335,7 @@ static int make_ctx(const orc_params *P, orc_ctx *c)
          * diffusion tensor follows alpha = -(A22/A10) dt beta c_s^2. */
         double A10 = -c->Ah0 - 1.0;
         double A22 = 0.5 * (c->ap + c->ahp);
-        double ratio = -A10 / A22;
+        double ratio = P->ratio > 0.0 ? P->ratio : -A10 / A22;
         /* lattice units per axis: u_a dt / dx_a, K_ab dt / (dx_a dx_b) */
         for (int a = 0; a < 3; ++a) c->uh[a] = P->u[a] * P->dt / dxv[a];
         for (int a = 0; a < 3; ++a)

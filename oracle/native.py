@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("ao", C.c_double * 3), ("aoh", C.c_double * 3),
         ("rect", C.c_int32), ("pad3_", C.c_int32),
         ("d0v", C.c_double * 3), ("dxv", C.c_double * 3),
+        ("ratio", C.c_double),
     ]
 
 
@@ -157,6 +158,7 @@ def make_params(spec: dict) -> Params:
     P.ab = _triple([float(x) for x in spec.get("ab", a)])
     P.abh = _triple([float(x) for x in spec.get("abh", ah)])
     P.theta = float(spec.get("theta", 1.0))
+    P.ratio = float(spec.get("ratio", 0.0))
     if "d0v" in spec or "dxv" in spec:
         # rectangular lattice (linear CDE): d0 and spacing per axis
         d0 = float(spec.get("d0", 1.0 / 3.0))
