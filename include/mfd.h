@@ -77,6 +77,9 @@ extern "C" {
                         w = 1-3d0, d0/2 (x6); 0 < d0 < 1/3                   */
 #define MFD_D3Q9 7   /* rD3Q9: rest and the eight cube corners,
                         w = 1-d0, d0/8 (x8)                                  */
+#define MFD_D3Q27 8  /* rD3Q27: rest, axes, edges and corners, the product
+                        weights of Appendix A; the general-scheme solver
+                        (mfd_general_*) runs it, mfd_set_lattice does not    */
 
 #define MFD_FP64 0
 #define MFD_FP32 1
@@ -654,6 +657,45 @@ int mfd_level_ptr(mfd_solver *s, int level, int field, int populations, void **p
  * out6[0..5][p] = ubar+_p, ubar-_p, (a_1+a_-1) ubar+_p, (a_1-a_-1) ubar-_p,
  * (ah_1+ah_-1) ubar+_p, (ah_1-ah_-1) ubar-_p; stride 9 per row. */
 int mfd_linear_tables(mfd_solver *s, double *w, double *ubar, double *out6);
+
+/* ------------------------------------------------ general-scheme solver
+ * The MMFD scheme of Eq. (2-2-1) with any stencil reach m and any number n
+ * of time levels (the index ranges -m <= k <= m and the levels t - l dt,
+ * l = 0 .. n - 1, of Eq. (2-1)) for the linear CDE (the linear EDF of
+ * Eq. (TforMMFD-0)), on every lattice of Appendix A including rD3Q27,
+ * square or rectangular, periodic:
+ *   phi(t + dt) = sum_l A_l phi_l + sum_l sum_p sum_{k=1..m}
+ *                 [(a_lk + a_l,-k) ubar+_p D2_{p,k} phi_l + (a_lk - a_l,-k) ubar-_p D1_{p,k} phi_l],
+ * A_l = sum_k a_lk, D2_{p,k} g = g(x + k e_p) - 2 g + g(x - k e_p),
+ * D1_{p,k} g = g(x + k e_p) - g(x - k e_p).  The EDF's diffusion tensor
+ * follows the scheme's own moments of Eq. (4-2-00a) with the new level at
+ * q = 0: C = (-A10 / A22) K dt / dx^2 - diag(d0) + lambda_bar u u (lattice
+ * units), A10 = sum_lk -(l + 1) a_lk, A22 = (1/2) sum_lk k^2 a_lk.
+ * mfd_general_create: grid (MMFD form, periodic, FP64 / FP32), lattice
+ * (MFD_D1Q3 .. MFD_D3Q27), d0 (d0[0] on a square grid, one per axis with
+ * spacing; NULL: 1/3), spacing (NULL: the square grid of grid->dx; else the
+ * spacing per axis of a rectangular lattice), the linear CDE's u, K and
+ * lambda_bar from eq, 1 <= m <= 3, 1 <= n <= 4, a: n rows of 2m + 1
+ * (row l = level t - l dt, entry k + m), dt > 0.  Returns MFD_OK or
+ * MFD_W_INCONSISTENT (A00 != 1 or A11 != A10) with *out set; MFD_E_ARG for
+ * bad sizes or coefficients (A10 < 0 < A22 is required), MFD_E_UNSUPPORTED
+ * for another form or boundary, MFD_E_OOM.  Levels: set_level(0) fills every
+ * level with the data (phi^(-l) = phi^0), set_level(l) then overrides level
+ * t - l dt; get_level(l) reads it (synchronous, host or device pointers, N
+ * values of the grid's precision, x fastest).  step advances nsteps steps
+ * on the solver's stream (the default stream unless set). */
+typedef struct mfd_general mfd_general;
+int mfd_general_create(mfd_general **out, const mfd_grid *grid, int lattice, const double d0[3],
+                       const double spacing[3], const mfd_eq_params *eq, int32_t m, int32_t n,
+                       const double *a, double dt);
+int mfd_general_destroy(mfd_general *g);
+const char *mfd_general_last_error(const mfd_general *g);
+int mfd_general_set_stream(mfd_general *g, void *stream);
+int mfd_general_set_level(mfd_general *g, int32_t level, const void *src, int64_t bytes,
+                          int on_device);
+int mfd_general_get_level(mfd_general *g, int32_t level, void *dst, int64_t bytes, int on_device);
+int mfd_general_step(mfd_general *g, int64_t nsteps);
+int mfd_general_synchronize(mfd_general *g);
 
 #ifdef __cplusplus
 }

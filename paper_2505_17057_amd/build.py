@@ -25,6 +25,7 @@ SOURCES = [
     "autotune.cpp",
     "batch.cpp",
     "server.cpp",
+    "general_api.cpp",
     "kernels_mmfd.hip",
     "kernels_tb.hip",
     "kernels_nse_tb.hip",
@@ -37,6 +38,7 @@ SOURCES = [
     "kernels_batch.hip",
     "kernels_source.hip",
     "kernels_mg.hip",
+    "kernels_general.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,37 @@
+// The general MMFD scheme of Eq. (2-2-1) for linear EDFs: any stencil reach
+// m (<= kGenMaxM) and number of time levels n (<= kGenMaxLevels), any
+// lattice of Appendix A (rD3Q27 included), periodic grids.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mfd_internal.h"
+
+namespace mfd {
+
+constexpr int kGenMaxM = 3;
+constexpr int kGenMaxLevels = 4;
+
+// per level l: A[l] = sum_k a_lk; per level, k = 1..m and pair p:
+// Cp = (a_lk + a_l,-k) ubp_p, Cm = (a_lk - a_l,-k) ubm_p (device memory)
+template <typename T>
+struct GenC {
+  int m, nl;
+  T A[kGenMaxLevels];
+  T Cp[kGenMaxLevels][kGenMaxM][kHostMaxP];
+  T Cm[kGenMaxLevels][kGenMaxM][kHostMaxP];
+};
+
+// the levels t, t - dt, ... of one step, by value
+template <typename T>
+struct GenLevels {
+  const T *p[kGenMaxLevels];
+};
+
+// one step of every node: out = sum_l A_l phi_l + sum_l sum_p sum_k
+// [Cp D2_{p,k} phi_l + Cm D1_{p,k} phi_l]; gc in device memory
+template <typename T>
+hipError_t launch_general_step(int lattice, GenLevels<T> lev, T *out, const int64_t n[3],
+                               const GenC<T> *gc, hipStream_t st);
+
+}  // namespace mfd

@@ -1,0 +1,94 @@
+// The general MMFD step of Eq. (2-2-1) for a linear EDF (the linear CDE):
+// any stencil reach m and number of levels n, any lattice (rD3Q27 included),
+// periodic wrap.  Each thread updates one node:
+//   out = sum_l A_l phi_l + sum_l sum_p sum_{k=1..m} [Cp_lkp D2_{p,k} phi_l
+//                                                  + Cm_lkp D1_{p,k} phi_l],
+//   D2_{p,k} g = (g(x + k e_p) - g(x)) + (g(x - k e_p) - g(x)),
+//   D1_{p,k} g = g(x + k e_p) - g(x - k e_p),
+// accumulated level by level, pairs in lattice order, then k, each product
+// and sum rounded on its own (no fused multiply-add), then the base terms
+// level by level and their sum with the accumulator.  The constants are read
+// from device memory (uniform loads: the rD3Q27 tables exceed what the
+// kernel argument block comfortably holds); the neighbours come through the
+// caches (one load per neighbour and level).
+#include "general.h"
+#include "edf.h"
+
+namespace mfd {
+
+namespace {
+
+__device__ __forceinline__ int gwrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__restrict__ out, int nx,
+                                                      int ny, int nz,
+                                                      const GenC<T> *__restrict__ gc) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int m = gc->m, nl = gc->nl;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t i0 = (int64_t)z * plane + (int64_t)y * nx + x;
+  T acc = 0;
+  for (int l = 0; l < nl; ++l) {
+    const T *__restrict__ g = lev.p[l];
+    const T g0 = g[i0];
+    static_for<L::P>([&](auto PI) {
+      constexpr int P = decltype(PI)::value;
+      constexpr int J = L::PR[P];
+      constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+      for (int k = 1; k <= m; ++k) {
+        const int64_t ip = (int64_t)gwrap(z + k * ez, nz) * plane +
+                           (int64_t)gwrap(y + k * ey, ny) * nx + gwrap(x + k * ex, nx);
+        const int64_t im = (int64_t)gwrap(z - k * ez, nz) * plane +
+                           (int64_t)gwrap(y - k * ey, ny) * nx + gwrap(x - k * ex, nx);
+        const T gp = g[ip], gm = g[im];
+        const T d2 = (gp - g0) + (gm - g0);
+        const T d1 = gp - gm;
+        acc = acc + gc->Cp[l][k - 1][P] * d2;
+        acc = acc + gc->Cm[l][k - 1][P] * d1;
+      }
+    });
+  }
+  T base = gc->A[0] * lev.p[0][i0];
+  for (int l = 1; l < nl; ++l) base = base + gc->A[l] * lev.p[l][i0];
+  out[i0] = base + acc;
+}
+
+template <class L, typename T>
+hipError_t gl(GenLevels<T> lev, T *out, const int64_t n[3], const GenC<T> *gc, hipStream_t st) {
+  const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
+  hipLaunchKernelGGL((k_general_step<L, T>), dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(64, 4), 0,
+                     st, lev, out, nx, ny, nz, gc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_general_step(int lattice, GenLevels<T> lev, T *out, const int64_t n[3],
+                               const GenC<T> *gc, hipStream_t st) {
+  if (n[2] > 65535) return hipErrorInvalidValue;
+  switch (lattice) {
+    case 1: return gl<LatD1Q3, T>(lev, out, n, gc, st);
+    case 2: return gl<LatD2Q5, T>(lev, out, n, gc, st);
+    case 3: return gl<LatD2Q9, T>(lev, out, n, gc, st);
+    case 4: return gl<LatD3Q19, T>(lev, out, n, gc, st);
+    case 5: return gl<LatD2Q5II, T>(lev, out, n, gc, st);
+    case 6: return gl<LatD3Q7, T>(lev, out, n, gc, st);
+    case 7: return gl<LatD3Q9, T>(lev, out, n, gc, st);
+    case 8: return gl<LatD3Q27, T>(lev, out, n, gc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_general_step<float>(int, GenLevels<float>, float *, const int64_t *,
+                                               const GenC<float> *, hipStream_t);
+template hipError_t launch_general_step<double>(int, GenLevels<double>, double *, const int64_t *,
+                                                const GenC<double> *, hipStream_t);
+
+}  // namespace mfd

@@ -879,6 +879,8 @@ extern "C" int mfd_set_lattice(mfd_solver *h, int lattice, double d0) {
     return s->fail(MFD_E_ARG, "lattice dimension %d differs from grid dimension %d", c.dim,
                    s->grid.dim);
   if (!(d0 < 1.0)) return s->fail(MFD_E_ARG, "d0 must lie in (0, 1)");
+  if (lattice == MFD_D3Q27)
+    return s->fail(MFD_E_UNSUPPORTED, "rD3Q27 runs through the general-scheme solver (mfd_general_*)");
   s->cfg.lattice = lattice;
   s->cfg.d0 = d0;
   s->cfg.rect = 0;  // a new lattice is square until mfd_set_rectangular

@@ -7,8 +7,10 @@
 
 namespace mfd {
 
-constexpr int kMaxQ = 19;
+constexpr int kMaxQ = 19;  // the kernels' constant block (KC): up to rD3Q19
 constexpr int kMaxP = 9;
+constexpr int kHostMaxQ = 27;  // host tables (Consts): up to rD3Q27
+constexpr int kHostMaxP = 13;
 
 // --------------------------------------------------------------- lattices
 // Appendix A velocity sets.  D1Q3 is the one-axis member of the family
@@ -57,6 +59,17 @@ struct LatD3Q9 {
                                   {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
   static constexpr int PR[P] = {1, 2, 3, 4};
 };
+// rD3Q27: the rest velocity, the axes, the edges as in D3Q19 and the eight
+// corners in the printed order (run by the general-scheme kernel only)
+struct LatD3Q27 {
+  static constexpr int id = 8, D = 3, Q = 27, P = 13;
+  static constexpr int E[Q][3] = {
+      {0, 0, 0},   {1, 0, 0},   {0, 1, 0},   {0, 0, 1},   {-1, 0, 0},   {0, -1, 0},  {0, 0, -1},
+      {1, 1, 0},   {-1, 1, 0},  {-1, -1, 0}, {1, -1, 0},  {1, 0, 1},    {-1, 0, 1},  {-1, 0, -1},
+      {1, 0, -1},  {0, 1, 1},   {0, -1, 1},  {0, -1, -1}, {0, 1, -1},   {1, 1, 1},   {1, 1, -1},
+      {1, -1, 1},  {-1, 1, 1},  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
+  static constexpr int PR[P] = {1, 2, 3, 7, 8, 11, 12, 15, 16, 19, 20, 21, 22};
+};
 
 // ---------------------------------------------------------- configuration
 enum Eq { kLCDE = 0, kBurgers = 1, kNSE = 2 };
@@ -67,17 +80,18 @@ constexpr int kWaveInput = 3;
 // All derived constants of one solver, in binary64 (host side).
 struct Consts {
   int lattice, dim, q, npair, eq;
-  int e[kMaxQ][3];
-  int pair[kMaxP];
+  int e[kHostMaxQ][3];
+  int pair[kHostMaxP];
   double d0, inv_d0;
-  double w[kMaxQ], w1[kMaxQ];
-  double qd[kMaxQ][3], qo[kMaxQ][3];
+  double w[kHostMaxQ], w1[kHostMaxQ];
+  double qd[kHostMaxQ][3], qo[kHostMaxQ][3];
   double A0, Ah0, Ab0, Abh0;
   double ap, am, ahp, ahm, abp, abm, abhp, abhm;
   double a[3], ah[3];
   // linear CDE
   double uh[3], kh[9], Ch[9];
-  double ubar[kMaxQ], ubp[kMaxP], ubm[kMaxP], Cp[kMaxP], Cm[kMaxP], Chp[kMaxP], Chm[kMaxP];
+  double ubar[kHostMaxQ], ubp[kHostMaxP], ubm[kHostMaxP], Cp[kHostMaxP], Cm[kHostMaxP],
+      Chp[kHostMaxP], Chm[kHostMaxP];
   // Burgers
   double bh, cbeta;
   int beta_one;

@@ -108,6 +108,17 @@ int lattice_weights_v(int lattice, const double d0v[3], Consts &c) {
       c.w[2] = c.w[5] = dy / 2.0;
       c.w[3] = c.w[6] = dz / 2.0;
       break;
+    case MFD_D3Q27:
+      copy_lattice<LatD3Q27>(c);
+      c.w[0] = (1.0 - dx) * (1.0 - dy) * (1.0 - dz);
+      c.w[1] = c.w[4] = dx * (1.0 - dy) * (1.0 - dz) / 2.0;
+      c.w[2] = c.w[5] = dy * (1.0 - dx) * (1.0 - dz) / 2.0;
+      c.w[3] = c.w[6] = dz * (1.0 - dx) * (1.0 - dy) / 2.0;
+      for (int j = 7; j <= 10; ++j) c.w[j] = dx * dy * (1.0 - dz) / 4.0;
+      for (int j = 11; j <= 14; ++j) c.w[j] = dx * dz * (1.0 - dy) / 4.0;
+      for (int j = 15; j <= 18; ++j) c.w[j] = dy * dz * (1.0 - dx) / 4.0;
+      for (int j = 19; j <= 26; ++j) c.w[j] = dx * dy * dz / 8.0;
+      break;
     case MFD_D3Q9:
       if (dy != d0 || dz != d0) return MFD_E_UNSUPPORTED;
       copy_lattice<LatD3Q9>(c);
@@ -211,7 +222,7 @@ int build_consts(const SchemeInput &in, Consts &c) {
   } else if (in.eq == kLCDE) {
     const double A10 = -c.Ah0 - 1.0;
     const double A22 = 0.5 * (c.ap + c.ahp);
-    const double ratio = -A10 / A22;
+    const double ratio = in.ratio > 0.0 ? in.ratio : -A10 / A22;
     // lattice units per axis: u_a dt / dx_a, K_ab dt / (dx_a dx_b)
     for (int x = 0; x < 3; ++x) c.uh[x] = in.u[x] * in.dt / dxv[x];
     for (int x = 0; x < 3; ++x)
@@ -294,7 +305,7 @@ KC<T> make_kc(const Consts &c) {
     k.Ahp[p] = (T)(c.Chp[p] + c.Chm[p]);
     k.Ahm[p] = (T)(c.Chp[p] - c.Chm[p]);
   }
-  for (int p = 0; p < c.npair; ++p) {
+  for (int p = 0; p < c.npair && p < kMaxP; ++p) {
     const int j = c.pair[p];
     k.nw[p][0] = (T)(c.ap * c.w[j]);
     k.nw[p][1] = (T)(c.am * c.w1[j]);

@@ -26,6 +26,8 @@ struct SchemeInput {
   // rectangular lattice (Appendix A; linear CDE): d0 and spacing per axis
   int rect;
   double d0v[3], dxv[3];
+  // linear CDE: -A10 / A22 of a general scheme when > 0 (0: from a / ah)
+  double ratio;
 };
 
 int lattice_weights(int lattice, double d0, Consts &c);

@@ -39,9 +39,12 @@ MFD_E_BUDGET = -7
 MFD_E_CANCELLED = -8
 MFD_E_TIMEOUT = -9
 
-LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7}
-DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3}
-QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9}
+LATTICES = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 3, "D3Q19": 4, "D2Q5II": 5, "D3Q7": 6, "D3Q9": 7,
+            "D3Q27": 8}
+DIMS = {"D1Q3": 1, "D2Q5": 2, "D2Q9": 2, "D3Q19": 3, "D2Q5II": 2, "D3Q7": 3, "D3Q9": 3,
+        "D3Q27": 3}
+QS = {"D1Q3": 3, "D2Q5": 5, "D2Q9": 9, "D3Q19": 19, "D2Q5II": 5, "D3Q7": 7, "D3Q9": 9,
+      "D3Q27": 27}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 FORMS = {"mmfd": 0, "mesofd": 1}
 EQS = {"lcde": 0, "burgers": 1, "nse": 2, "wave": 3}
@@ -119,6 +122,16 @@ _SIGS = {
     "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
     "mfd_set_theta_multigrid": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "mfd_set_rectangular": ([_H, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "mfd_general_create": ([C.POINTER(_H), C.POINTER(mfd_grid), C.c_int, _PD, _PD,
+                            C.POINTER(mfd_eq_params), C.c_int32, C.c_int32, _PD, C.c_double],
+                           C.c_int),
+    "mfd_general_destroy": ([_H], C.c_int),
+    "mfd_general_last_error": ([_H], C.c_char_p),
+    "mfd_general_set_stream": ([_H, C.c_void_p], C.c_int),
+    "mfd_general_set_level": ([_H, C.c_int32, _VP, C.c_int64, C.c_int], C.c_int),
+    "mfd_general_get_level": ([_H, C.c_int32, _VP, C.c_int64, C.c_int], C.c_int),
+    "mfd_general_step": ([_H, C.c_int64], C.c_int),
+    "mfd_general_synchronize": ([_H], C.c_int),
     "mfd_theta_stats": ([_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.c_int], C.c_int),
     "mfd_step_noalloc": ([_H, _VP, _VP, C.c_int64], C.c_int),
@@ -218,6 +231,90 @@ def _ptr_of(x):
     # torch tensor
     assert x.is_contiguous()
     return x.data_ptr(), 1 if x.is_cuda else 0, x.numel() * x.element_size()
+
+
+class General:
+    """Owner of one mfd_general handle: the MMFD scheme with stencil reach m
+    and n time levels for the linear CDE (marshalling only).  a: n rows of
+    2m + 1 coefficients (row l: level t - l dt, entry k + m)."""
+
+    def __init__(self, lattice, n, dx, a, dt, u=(), K=None, lambda_bar=0, precision="fp64",
+                 d0=1.0 / 3.0, spacing=None, d0v=None):
+        self.lattice = lattice
+        self.dim = DIMS[lattice]
+        n = tuple(int(v) for v in n)
+        assert len(n) == self.dim
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        assert a.ndim == 2 and a.shape[1] % 2 == 1
+        self.nl, self.m = a.shape[0], (a.shape[1] - 1) // 2
+        g = mfd_grid()
+        g.dim = self.dim
+        g.precision = PRECISIONS[precision]
+        g.form = FORMS["mmfd"]
+        g.boundary = BOUNDARIES["periodic"]
+        g.n = (C.c_int64 * 3)(*(list(n) + [1] * (3 - len(n))))
+        g.dx = float(dx)
+        p = mfd_eq_params()
+        p.u = _D3(*(list(u) + [0.0] * (3 - len(u))))
+        Kd = np.zeros((3, 3))
+        if K is not None:
+            K = np.asarray(K, dtype=np.float64)
+            Kd[: K.shape[0], : K.shape[1]] = K
+        p.K = (C.c_double * 9)(*Kd.ravel().tolist())
+        p.lambda_bar = int(lambda_bar)
+        p.beta = 1.0
+        dv = list(d0v) if d0v is not None else [d0]
+        dv3 = _d3((dv + [dv[0]] * 3)[:3])
+        sp = _d3((list(spacing) + [spacing[0]] * 3)[:3]) if spacing is not None else None
+        h = _H()
+        rc = lib.mfd_general_create(C.byref(h), C.byref(g), LATTICES[lattice], dv3, sp, C.byref(p),
+                                    self.m, self.nl, a.ctypes.data_as(_PD), float(dt))
+        if rc < 0:
+            raise MfdError(rc, "mfd_general_create")
+        self.warnings = [rc] if rc > 0 else []
+        self.h = h
+        self.n = n
+        self.N = int(np.prod(n))
+        self.dtype = np.float64 if precision == "fp64" else np.float32
+
+    def check(self, rc, what):
+        if rc < 0:
+            msg = lib.mfd_general_last_error(self.h)
+            raise MfdError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mfd_general_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle):
+        return self.check(lib.mfd_general_set_stream(self.h, C.c_void_p(stream_handle)),
+                          "mfd_general_set_stream")
+
+    def set_level(self, level, data):
+        a = np.ascontiguousarray(data, dtype=self.dtype)
+        assert a.size == self.N
+        return self.check(lib.mfd_general_set_level(self.h, int(level), a.ctypes.data_as(_VP),
+                                                    a.nbytes, 0), "mfd_general_set_level")
+
+    def get_level(self, level=0):
+        out = np.empty(self.N, dtype=self.dtype)
+        self.check(lib.mfd_general_get_level(self.h, int(level), out.ctypes.data_as(_VP),
+                                             out.nbytes, 0), "mfd_general_get_level")
+        return out
+
+    def step(self, nsteps=1):
+        return self.check(lib.mfd_general_step(self.h, int(nsteps)), "mfd_general_step")
+
+    def synchronize(self):
+        return self.check(lib.mfd_general_synchronize(self.h), "mfd_general_synchronize")
 
 
 class Solver:

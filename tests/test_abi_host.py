@@ -436,3 +436,24 @@ def test_rectangular_argument_checks(M):
         s.set_rectangular((0.5, 2.0), (0.3, 0.4))
     assert e.value.code == M.MFD_E_UNSUPPORTED
     s.close()
+
+
+def test_general_argument_checks(M):
+    """mfd_general_create refuses bad sizes and coefficients before it
+    allocates anything: m in [1, 3], n in [1, 4], finite coefficients with
+    A10 < 0 < A22, a known precision."""
+    a1 = [[0.25, 0.5, 0.25, 0.0, 0.0]]
+    bad = [
+        dict(a=np.zeros((1, 9))),                      # m = 4
+        dict(a=np.zeros((5, 3))),                      # n = 5
+        dict(a=[[np.nan, 1.0, 0.0]]),
+        dict(a=[[0.0, 1.0, 0.0]]),                     # A10 < 0 but A22 = 0
+        dict(a=a1, dt=0.0),
+        dict(a=a1, lattice="D2Q9", n=(8, 8), precision="fp16"),
+    ]
+    for kw in bad:
+        args = dict(lattice="D2Q9", n=(8, 8), dx=1.0, a=a1, dt=0.1, u=(0.1, 0.0),
+                    K=[[0.1, 0.0], [0.0, 0.1]])
+        args.update(kw)
+        with pytest.raises((M.MfdError, KeyError)):
+            M.General(**args)
