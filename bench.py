@@ -66,8 +66,8 @@ def parse():
     p.add_argument("--no-headline", action="store_true",
                    help="skip the headline (profiling of the other sections; value is then null)")
     p.add_argument("--sections",
-                   default="c3err,c2,variants,multiset,theta,big,c1,nse3d,source,wave,burgers,burgers_theta,"
-                           "batched,serving",
+                   default="c3err,c2,variants,multiset,theta,theta_mg,big,c1,nse3d,source,wave,"
+                           "burgers,burgers_theta,batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
