@@ -64,44 +64,6 @@ __global__ __launch_bounds__(256) void k_mg_smooth(const T *__restrict__ x, cons
   }
 }
 
-// out = A x
-template <class L, typename T>
-__global__ __launch_bounds__(256) void k_mg_apply(const T *__restrict__ x, T *__restrict__ out,
-                                                  MgOp<T> op) {
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
-  if (i >= op.nx || j >= op.ny) return;
-  const int64_t k = (int64_t)j * op.nx + i;
-  out[k] = op.den * x[k] - mg_nbr<L, T>(x, op, i, j);
-}
-
-// Rc(I, J) = sum_{a, b = -1..1} w_a w_b r(2I + a, 2J + b) / 16, w = (1, 2, 1),
-// r = R - A x on the fine level (op: the fine level's operator)
-template <class L, typename T>
-__global__ __launch_bounds__(256) void k_mg_restrict(const T *__restrict__ x,
-                                                     const T *__restrict__ R,
-                                                     T *__restrict__ Rc, MgOp<T> op, int ncx,
-                                                     int ncy) {
-  const int I = blockIdx.x * 64 + threadIdx.x, J = blockIdx.y * 4 + threadIdx.y;
-  if (I >= ncx || J >= ncy) return;
-  const int nx = op.nx, ny = op.ny;
-  T acc = 0;
-#pragma unroll
-  for (int b = -1; b <= 1; ++b) {
-    int j = 2 * J + b;
-    j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
-    T row = 0;
-#pragma unroll
-    for (int a = -1; a <= 1; ++a) {
-      int i = 2 * I + a;
-      i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
-      const T r = mg_resid<L, T>(x, R, op, i, j);
-      row = row + (a == 0 ? T(2) * r : r);
-    }
-    acc = acc + (b == 0 ? T(2) * row : row);
-  }
-  Rc[(int64_t)J * ncx + I] = acc * T(0.0625);
-}
-
 // x(i, j) += the bilinear interpolation of the coarse correction e at the
 // fine node: e(I, J) at (2I, 2J), the mean of the two (four) coarse nodes
 // around an edge (cell) midpoint
@@ -128,6 +90,96 @@ __global__ __launch_bounds__(256) void k_mg_prolong_add(const T *__restrict__ e,
   }
   const int64_t k = (int64_t)j * nx + i;
   x[k] = x[k] + v;
+}
+
+// r = R - A x
+template <class L, typename T>
+__global__ __launch_bounds__(256) void k_mg_residual(const T *__restrict__ x, const T *__restrict__ R,
+                                                     T *__restrict__ r, MgOp<T> op) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  if (i >= op.nx || j >= op.ny) return;
+  r[(int64_t)j * op.nx + i] = mg_resid<L, T>(x, R, op, i, j);
+}
+
+// Rc(I, J) = sum_{a, b = -1..1} w_a w_b r(2I + a, 2J + b) / 16, w = (1, 2, 1)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_restrict_r(const T *__restrict__ r, T *__restrict__ Rc,
+                                                       int nx, int ny, int ncx, int ncy) {
+  const int I = blockIdx.x * 64 + threadIdx.x, J = blockIdx.y * 4 + threadIdx.y;
+  if (I >= ncx || J >= ncy) return;
+  T acc = 0;
+#pragma unroll
+  for (int b = -1; b <= 1; ++b) {
+    int j = 2 * J + b;
+    j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+    T row = 0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a) {
+      int i = 2 * I + a;
+      i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
+      const T v = r[(int64_t)j * nx + i];
+      row = row + (a == 0 ? T(2) * v : v);
+    }
+    acc = acc + (b == 0 ? T(2) * row : row);
+  }
+  Rc[(int64_t)J * ncx + I] = acc * T(0.0625);
+}
+
+__device__ __forceinline__ double mg_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// binary64 sums of (R - A x)^2 and R^2: per workgroup (grid-stride rows),
+// then one workgroup adds the partials in a fixed order
+template <class L, typename T>
+__global__ __launch_bounds__(256) void k_mg_resid_norm(const T *__restrict__ x,
+                                                       const T *__restrict__ R, MgOp<T> op,
+                                                       double *__restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < op.nx) {
+    for (int j = blockIdx.y * 4 + threadIdx.y; j < op.ny; j += gridDim.y * 4) {
+      const double r = (double)mg_resid<L, T>(x, R, op, i, j);
+      const double b = (double)R[(int64_t)j * op.nx + i];
+      s0 += r * r;
+      s1 += b * b;
+    }
+  }
+  s0 = mg_wave_sum(s0);
+  s1 = mg_wave_sum(s1);
+  __shared__ double red[2][4];
+  const int t = threadIdx.y * 64 + threadIdx.x;
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = s0;
+    red[1][t >> 6] = s1;
+  }
+  __syncthreads();
+  if (t < 2) {
+    partial[2 * (blockIdx.y * gridDim.x + blockIdx.x) + t] =
+        ((red[t][0] + red[t][1]) + red[t][2]) + red[t][3];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mg_norm_final(const double *__restrict__ partial, int nblk,
+                                                       double *__restrict__ out) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    s0 += partial[2 * b];
+    s1 += partial[2 * b + 1];
+  }
+  s0 = mg_wave_sum(s0);
+  s1 = mg_wave_sum(s1);
+  __shared__ double red[2][4];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s0;
+    red[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    out[threadIdx.x] = ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) +
+                       red[threadIdx.x][3];
 }
 
 dim3 mg_grid(int nx, int ny) { return dim3((nx + 63) / 64, (ny + 3) / 4); }
@@ -179,36 +231,48 @@ hipError_t launch_mg_smooth(int lattice, const T *x, const T *R, T *out, const M
 }
 
 template <typename T>
-hipError_t launch_mg_apply(int lattice, const T *x, T *out, const MgOp<T> &op, hipStream_t st) {
-  if (lattice == 3)
-    hipLaunchKernelGGL((k_mg_apply<LatD2Q9, T>), mg_grid(op.nx, op.ny), dim3(64, 4), 0, st, x, out,
-                       op);
-  else if (lattice == 2)
-    hipLaunchKernelGGL((k_mg_apply<LatD2Q5, T>), mg_grid(op.nx, op.ny), dim3(64, 4), 0, st, x, out,
-                       op);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_mg_restrict(int lattice, const T *x, const T *R, T *Rc, const MgOp<T> &op,
-                              hipStream_t st) {
-  const int ncx = op.nx / 2, ncy = op.ny / 2;
-  if (lattice == 3)
-    hipLaunchKernelGGL((k_mg_restrict<LatD2Q9, T>), mg_grid(ncx, ncy), dim3(64, 4), 0, st, x, R,
-                       Rc, op, ncx, ncy);
-  else if (lattice == 2)
-    hipLaunchKernelGGL((k_mg_restrict<LatD2Q5, T>), mg_grid(ncx, ncy), dim3(64, 4), 0, st, x, R,
-                       Rc, op, ncx, ncy);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_mg_prolong_add(const T *e, T *x, int nx, int ny, hipStream_t st) {
   hipLaunchKernelGGL((k_mg_prolong_add<T>), mg_grid(nx, ny), dim3(64, 4), 0, st, e, x, nx, ny);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_residual(int lattice, const T *x, const T *R, T *r, const MgOp<T> &op,
+                              hipStream_t st) {
+  if (lattice == 3)
+    hipLaunchKernelGGL((k_mg_residual<LatD2Q9, T>), mg_grid(op.nx, op.ny), dim3(64, 4), 0, st, x, R,
+                       r, op);
+  else if (lattice == 2)
+    hipLaunchKernelGGL((k_mg_residual<LatD2Q5, T>), mg_grid(op.nx, op.ny), dim3(64, 4), 0, st, x, R,
+                       r, op);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_restrict_r(const T *r, T *Rc, int nx, int ny, hipStream_t st) {
+  const int ncx = nx / 2, ncy = ny / 2;
+  hipLaunchKernelGGL((k_mg_restrict_r<T>), mg_grid(ncx, ncy), dim3(64, 4), 0, st, r, Rc, nx, ny,
+                     ncx, ncy);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_resid_norm(int lattice, const T *x, const T *R, const MgOp<T> &op,
+                                double *partial, double *out, hipStream_t st) {
+  const int bx = (op.nx + 63) / 64;
+  int by = (op.ny + 3) / 4;
+  while (bx * by > kMgNormBlocks) by = (by + 1) / 2;
+  if (lattice == 3)
+    hipLaunchKernelGGL((k_mg_resid_norm<LatD2Q9, T>), dim3(bx, by), dim3(64, 4), 0, st, x, R, op,
+                       partial);
+  else if (lattice == 2)
+    hipLaunchKernelGGL((k_mg_resid_norm<LatD2Q5, T>), dim3(bx, by), dim3(64, 4), 0, st, x, R, op,
+                       partial);
+  else
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mg_norm_final, dim3(1), dim3(256), 0, st, partial, bx * by, out);
   return hipGetLastError();
 }
 
@@ -216,10 +280,12 @@ hipError_t launch_mg_prolong_add(const T *e, T *x, int nx, int ny, hipStream_t s
   template MgOp<T> mg_op<T>(const Consts &, int, int, int);                                     \
   template hipError_t launch_mg_smooth<T>(int, const T *, const T *, T *, const MgOp<T> &,     \
                                           double, bool, hipStream_t);                           \
-  template hipError_t launch_mg_apply<T>(int, const T *, T *, const MgOp<T> &, hipStream_t);    \
-  template hipError_t launch_mg_restrict<T>(int, const T *, const T *, T *, const MgOp<T> &,   \
+  template hipError_t launch_mg_prolong_add<T>(const T *, T *, int, int, hipStream_t);           \
+  template hipError_t launch_mg_residual<T>(int, const T *, const T *, T *, const MgOp<T> &,    \
                                             hipStream_t);                                       \
-  template hipError_t launch_mg_prolong_add<T>(const T *, T *, int, int, hipStream_t);
+  template hipError_t launch_mg_restrict_r<T>(const T *, T *, int, int, hipStream_t);           \
+  template hipError_t launch_mg_resid_norm<T>(int, const T *, const T *, const MgOp<T> &,       \
+                                              double *, double *, hipStream_t);
 MFD_MG_INST(float)
 MFD_MG_INST(double)
 #undef MFD_MG_INST

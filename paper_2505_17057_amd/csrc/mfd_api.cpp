@@ -115,11 +115,11 @@ int64_t Solver::device_bytes_needed() const {
   return b;
 }
 
-// the fine level's scratch, then three arrays (iterate, right-hand side,
-// scratch) of each coarser level
+// three arrays (iterate, right-hand side, scratch) of each coarser level (the
+// fine level works in the theta buffers)
 int64_t Solver::mg_bytes() const {
   if (cfg.kind != MFD_THETA || mg_levels < 2) return 0;
-  int64_t e = G.N;
+  int64_t e = 0;
   int64_t nx = G.n[0], ny = G.n[1];
   for (int l = 1; l < mg_levels; ++l) {
     nx /= 2;
@@ -611,8 +611,7 @@ int Solver::theta_mg_steps(int64_t nsteps) {
     T *m = B[kMgBuf];
     nxl[0] = (int)G.n[0];
     nyl[0] = (int)G.n[1];
-    tl[0] = m;
-    m += G.N;
+    tl[0] = B[6];  // the fine level's second iterate array
     Rl[0] = B[5];
     for (int l = 1; l < L; ++l) {
       nxl[l] = nxl[l - 1] / 2;
@@ -664,7 +663,9 @@ int Solver::theta_mg_steps(int64_t nsteps) {
           oth[l] = tl[l];
         }
         smooth(l, cur[l], oth[l], mg_pre, l > 0);
-        if (e == hipSuccess) e = launch_mg_restrict<T>(lat, cur[l], Rl[l], Rl[l + 1], op[l], stream);
+        // the residual into the free array, then its restriction
+        if (e == hipSuccess) e = launch_mg_residual<T>(lat, cur[l], Rl[l], oth[l], op[l], stream);
+        if (e == hipSuccess) e = launch_mg_restrict_r<T>(oth[l], Rl[l + 1], nxl[l], nyl[l], stream);
       }
       cur[L - 1] = xl[L - 1];
       oth[L - 1] = tl[L - 1];
@@ -677,8 +678,7 @@ int Solver::theta_mg_steps(int64_t nsteps) {
       if (e != hipSuccess) return hip(e, "multigrid cycle launch");
       ++k;
       if (tol_on) {
-        e = launch_mg_apply<T>(lat, cur[0], oth[0], op[0], stream);
-        if (e == hipSuccess) e = launch_sq_sums<T>(B[5], oth[0], B[5], N, part, out, stream);
+        e = launch_mg_resid_norm<T>(lat, cur[0], B[5], op[0], part, out, stream);
         if (e != hipSuccess) return hip(e, "multigrid residual launch");
         double h[2];
         int rc = copy_out(h, out, sizeof(h), 0);
@@ -691,9 +691,10 @@ int Solver::theta_mg_steps(int64_t nsteps) {
         break;
       }
     }
-    if (cur[0] != B[io]) {
-      e = hipMemcpyAsync(B[io], cur[0], (size_t)(N * sizeof(T)), hipMemcpyDeviceToDevice, stream);
-      if (e != hipSuccess) return hip(e, "multigrid result copy");
+    if (cur[0] != B[io]) {  // the result is kept in the io role
+      std::swap(buf[io], buf[6]);
+      std::swap(B[io], B[6]);
+      tl[0] = B[6];
     }
     std::swap(ic, io);
     ip = io;

@@ -28,14 +28,20 @@ MgOp<T> mg_op(const Consts &c, int level, int nx, int ny);
 template <typename T>
 hipError_t launch_mg_smooth(int lattice, const T *x, const T *R, T *out, const MgOp<T> &op,
                             double omega, bool zero, hipStream_t st);
-template <typename T>
-hipError_t launch_mg_apply(int lattice, const T *x, T *out, const MgOp<T> &op, hipStream_t st);
-// Rc = full-weighting restriction of R - A x (op: the fine level's)
-template <typename T>
-hipError_t launch_mg_restrict(int lattice, const T *x, const T *R, T *Rc, const MgOp<T> &op,
-                              hipStream_t st);
 // x += bilinear prolongation of the coarse correction e (x: nx x ny, e: half)
 template <typename T>
 hipError_t launch_mg_prolong_add(const T *e, T *x, int nx, int ny, hipStream_t st);
+// r = R - A x
+template <typename T>
+hipError_t launch_mg_residual(int lattice, const T *x, const T *R, T *r, const MgOp<T> &op,
+                              hipStream_t st);
+// Rc = full-weighting restriction of r (nx x ny) to (nx / 2) x (ny / 2)
+template <typename T>
+hipError_t launch_mg_restrict_r(const T *r, T *Rc, int nx, int ny, hipStream_t st);
+// out[0] = sum (R - A x)^2, out[1] = sum R^2 in binary64 (partial: 2 kMgNormBlocks doubles)
+constexpr int kMgNormBlocks = 2048;
+template <typename T>
+hipError_t launch_mg_resid_norm(int lattice, const T *x, const T *R, const MgOp<T> &op,
+                                double *partial, double *out, hipStream_t st);
 
 }  // namespace mfd
