@@ -1,6 +1,7 @@
 """The MMFD scheme of Eq. (2-2-1) with any stencil reach m and any number n
-of time levels, for the linear CDE (a linear EDF), on any lattice of
-Appendix A (rD3Q27 included), square or rectangular.
+of time levels: for the linear CDE (a linear EDF) on any lattice of
+Appendix A (rD3Q27 included), square or rectangular, and for Burgers'
+equation and the NSE (the nonlinear EDFs; the functions at the end).
 
 TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
 
@@ -142,3 +143,134 @@ def mmfd_step(spec, levels, a):
     for l in range(1, len(phis)):
         base = base + A[l] * phis[l]
     return (base + acc).ravel()
+
+
+# ------------------------------------------------ Burgers' equation and the NSE
+def _nl_spec(spec):
+    s = dict(spec)
+    s["levels"] = 2
+    s["a"] = (1.0, 0.0, 0.0)
+    s["ah"] = (0.0, 0.0, 0.0)
+    s.pop("ab", None)
+    s.pop("abh", None)
+    return s
+
+
+def nonlinear_literal_step(spec, levels, a, ab=None):
+    """Eq. (2-1) with the moments of Eq. (2-2) / (2-4) for Burgers' equation
+    or the NSE: f_j(x) = sum_l sum_k a[l][k] f^eq_j(x + k e_j, t - l dt), the
+    density (or scalar) from sum_j f_j with the set a, the momentum from
+    sum_j e_j f_j with the set ab (default a).  levels[l]: the fields of
+    level t - l dt (field-major)."""
+    a = np.asarray(a, dtype=np.float64)
+    ab = a if ab is None else np.asarray(ab, dtype=np.float64)
+    m = (a.shape[1] - 1) // 2
+    s = _nl_spec(spec)
+    n = tuple(spec["n"])
+    shape = tuple(reversed(n))
+    N = int(np.prod(n))
+    E, _, _ = _lattice(spec)
+    dim = O.DIMS[spec["lattice"]]
+    nse = spec.get("eq") == "nse"
+    pops = [O.init_populations(s, np.asarray(v, dtype=np.float64)).reshape(len(E), N)
+            for v in levels]
+    out = [np.zeros(shape) for _ in range(1 + dim if nse else 1)]
+    for j in range(len(E)):
+        for f, tab in enumerate([a] + ([ab] * dim if nse else [])):
+            e = 1 if f == 0 else int(E[j][f - 1])
+            if e == 0:
+                continue
+            fj = np.zeros(shape)
+            for l, P in enumerate(pops):
+                G = P[j].reshape(shape)
+                for kk in range(2 * m + 1):
+                    if tab[l, kk] != 0.0:
+                        fj = fj + tab[l, kk] * _shift(G, E[j], kk - m, n)
+            out[f] = out[f] + fj if e == 1 else out[f] - fj
+    return np.concatenate([o.ravel() for o in out])
+
+
+def nonlinear_mmfd_step(spec, levels, a, ab=None):
+    """Eq. (2-2-1) / (2-4-1) with reach m and n levels for Burgers' equation or
+    the NSE, on the pair parts F+-_p of each level (orc_pair_parts):
+      density / scalar: sum_l A_l phi_l + sum_l sum_p sum_k
+                        [a+_lk D2_{p,k} F+_p + a-_lk D1_{p,k} F-_p]
+      momentum j_a:     sum_l Ab_l j_l + sum_l sum_{p: e_pa != 0} e_pa sum_k
+                        [ab+_lk D2_{p,k} F-_p + ab-_lk D1_{p,k} F+_p]
+    with D2 g = (g(x + k e_p) - g) + (g(x - k e_p) - g), D1 g = g(x + k e_p)
+    - g(x - k e_p), accumulated level by level, pairs in lattice order, then
+    k, each product and sum rounded on its own (the GPU kernel's order)."""
+    a = np.asarray(a, dtype=np.float64)
+    ab = a if ab is None else np.asarray(ab, dtype=np.float64)
+    nl, w = a.shape
+    m = (w - 1) // 2
+    s = _nl_spec(spec)
+    n = tuple(spec["n"])
+    shape = tuple(reversed(n))
+    N = int(np.prod(n))
+    E, _, pairs = _lattice(spec)
+    dim = O.DIMS[spec["lattice"]]
+    nse = spec.get("eq") == "nse"
+    nf = 1 + dim if nse else 1
+
+    def sums(tab):
+        A, P, M = [], np.zeros((nl, m)), np.zeros((nl, m))
+        for l in range(nl):
+            t = 0.0
+            for kk in range(w):
+                t = t + float(tab[l, kk])
+            A.append(t)
+            for k in range(1, m + 1):
+                P[l, k - 1] = float(tab[l, m + k]) + float(tab[l, m - k])
+                M[l, k - 1] = float(tab[l, m + k]) - float(tab[l, m - k])
+        return A, P, M
+
+    A, ap, am = sums(a)
+    Ab, abp, abm = sums(ab)
+    parts = []
+    flds = []
+    for v in levels:
+        v = np.asarray(v, dtype=np.float64)
+        Fp, Fm = O.pair_parts(s, v)
+        parts.append((Fp.reshape((len(pairs),) + shape), Fm.reshape((len(pairs),) + shape)))
+        flds.append(v.reshape((nf,) + shape))
+
+    def d2(g, e, k):
+        return (_shift(g, e, k, n) - g) + (_shift(g, e, -k, n) - g)
+
+    def d1(g, e, k):
+        return _shift(g, e, k, n) - _shift(g, e, -k, n)
+
+    acc = np.zeros(shape)
+    for l in range(nl):
+        Fp, Fm = parts[l]
+        for p, j in enumerate(pairs):
+            for k in range(1, m + 1):
+                acc = acc + ap[l, k - 1] * d2(Fp[p], E[j], k)
+                acc = acc + am[l, k - 1] * d1(Fm[p], E[j], k)
+    base = A[0] * flds[0][0]
+    for l in range(1, nl):
+        base = base + A[l] * flds[l][0]
+    out = [base + acc]
+    for f in range(1, nf):
+        mo = np.zeros(shape)
+        for l in range(nl):
+            Fp, Fm = parts[l]
+            for p, j in enumerate(pairs):
+                e = int(E[j][f - 1])
+                if e == 0:
+                    continue
+                for k in range(1, m + 1):
+                    t1 = abp[l, k - 1] * d2(Fm[p], E[j], k)
+                    t2 = abm[l, k - 1] * d1(Fp[p], E[j], k)
+                    if e == 1:
+                        mo = mo + t1
+                        mo = mo + t2
+                    else:
+                        mo = mo - t1
+                        mo = mo - t2
+        bj = Ab[0] * flds[0][f]
+        for l in range(1, nl):
+            bj = bj + Ab[l] * flds[l][f]
+        out.append(bj + mo)
+    return np.concatenate([o.ravel() for o in out])

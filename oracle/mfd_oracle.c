@@ -1269,6 +1269,16 @@ int orc_edf_rect(int lattice, const double *d0v, double A, const double *B, cons
     return c.L.b;
 }
 
+/* the pair parts F+_p, F-_p of every node of one level (Eq. (2-5) applied to
+ * Eq. (3-3)), as the central form uses them: Fp[p * N + i], Fm[p * N + i] */
+int orc_pair_parts(const orc_params *P, const double *lev, double *Fp, double *Fm)
+{
+    orc_ctx c;
+    if (make_ctx(P, &c)) return -1;
+    pair_parts(P, &c, lev, Fp, Fm);
+    return c.L.npair;
+}
+
 /* Neumaier-compensated sum of n values */
 double orc_sum(const double *v, int64_t n)
 {

@@ -84,6 +84,7 @@ def lib():
             ("orc_mesofd_step", [P, D, D, D, D]),
             ("orc_theta_step", [P, D, D, D]),
             ("orc_tables", [P, D, D, D]),
+            ("orc_pair_parts", [P, D, D, D]),
             ("orc_wave_start", [P, D, D, D]),
             ("orc_mmfd_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
             ("orc_literal_source_step", [P, C.POINTER(Source), D, D, D, D, D]),
@@ -313,6 +314,19 @@ def theta_solve(spec, cur, tol, chunk, cap):
     _check(lib().orc_theta_solve(C.byref(P), _ptr(cur), _ptr(out), _ptr(work), float(tol),
                                  int(chunk), int(cap), C.byref(sw), C.byref(cv)), "theta_solve")
     return out, sw.value, bool(cv.value)
+
+
+def pair_parts(spec, lev):
+    """(Fp[p, N], Fm[p, N]): the pair parts of one level as the central form
+    uses them (orc_pair_parts)."""
+    P = make_params(spec)
+    lev = np.ascontiguousarray(lev, dtype=np.float64)
+    N = npoints(spec)
+    Fp = np.zeros(MAXP * N)
+    Fm = np.zeros(MAXP * N)
+    npair = lib().orc_pair_parts(C.byref(P), _ptr(lev), _ptr(Fp), _ptr(Fm))
+    _check(npair, "pair_parts")
+    return Fp[: npair * N].reshape(npair, N), Fm[: npair * N].reshape(npair, N)
 
 
 def tables(spec):
