@@ -659,35 +659,42 @@ int mfd_level_ptr(mfd_solver *s, int level, int field, int populations, void **p
 int mfd_linear_tables(mfd_solver *s, double *w, double *ubar, double *out6);
 
 /* ------------------------------------------------ general-scheme solver
- * The MMFD scheme of Eq. (2-2-1) with any stencil reach m and any number n
- * of time levels (the index ranges -m <= k <= m and the levels t - l dt,
- * l = 0 .. n - 1, of Eq. (2-1)) for the linear CDE (the linear EDF of
- * Eq. (TforMMFD-0)), on every lattice of Appendix A including rD3Q27,
- * square or rectangular, periodic:
- *   phi(t + dt) = sum_l A_l phi_l + sum_l sum_p sum_{k=1..m}
- *                 [(a_lk + a_l,-k) ubar+_p D2_{p,k} phi_l + (a_lk - a_l,-k) ubar-_p D1_{p,k} phi_l],
- * A_l = sum_k a_lk, D2_{p,k} g = g(x + k e_p) - 2 g + g(x - k e_p),
- * D1_{p,k} g = g(x + k e_p) - g(x - k e_p).  The EDF's diffusion tensor
- * follows the scheme's own moments of Eq. (4-2-00a) with the new level at
- * q = 0: C = (-A10 / A22) K dt / dx^2 - diag(d0) + lambda_bar u u (lattice
- * units), A10 = sum_lk -(l + 1) a_lk, A22 = (1/2) sum_lk k^2 a_lk.
- * mfd_general_create: grid (MMFD form, periodic, FP64 / FP32), lattice
- * (MFD_D1Q3 .. MFD_D3Q27), d0 (d0[0] on a square grid, one per axis with
- * spacing; NULL: 1/3), spacing (NULL: the square grid of grid->dx; else the
- * spacing per axis of a rectangular lattice), the linear CDE's u, K and
- * lambda_bar from eq, 1 <= m <= 3, 1 <= n <= 4, a: n rows of 2m + 1
- * (row l = level t - l dt, entry k + m), dt > 0.  Returns MFD_OK or
- * MFD_W_INCONSISTENT (A00 != 1 or A11 != A10) with *out set; MFD_E_ARG for
- * bad sizes or coefficients (A10 < 0 < A22 is required), MFD_E_UNSUPPORTED
- * for another form or boundary, MFD_E_OOM.  Levels: set_level(0) fills every
- * level with the data (phi^(-l) = phi^0), set_level(l) then overrides level
- * t - l dt; get_level(l) reads it (synchronous, host or device pointers, N
- * values of the grid's precision, x fastest).  step advances nsteps steps
- * on the solver's stream (the default stream unless set). */
+ * The MMFD scheme of Eq. (2-2-1) / (2-4-1) with any stencil reach m and any
+ * number n of time levels (the index ranges -m <= k <= m and the levels
+ * t - l dt, l = 0 .. n - 1, of Eq. (2-1)), periodic:
+ *   scalar / density: sum_l A_l phi_l + sum_l sum_p sum_{k=1..m}
+ *                     [(a_lk + a_l,-k) D2_{p,k} F+_p + (a_lk - a_l,-k) D1_{p,k} F-_p]
+ *   momentum (NSE):   sum_l Ab_l j_l + sum_l sum_p e_p sum_{k=1..m}
+ *                     [(ab_lk + ab_l,-k) D2_{p,k} F-_p + (ab_lk - ab_l,-k) D1_{p,k} F+_p]
+ * on the pair parts F+-_p of each level's EDF, A_l = sum_k a_lk,
+ * D2_{p,k} g = g(x + k e_p) - 2 g + g(x - k e_p), D1_{p,k} g = g(x + k e_p)
+ * - g(x - k e_p).  eq_code: MFD_LCDE (the linear EDF of Eq. (TforMMFD-0);
+ * every lattice including rD3Q27, square or rectangular; its diffusion
+ * tensor follows the scheme's own moments of Eq. (4-2-00a) with the new level
+ * at q = 0: C = (-A10 / A22) K dt / dx^2 - diag(d0) + lambda_bar u u in
+ * lattice units, A10 = sum_lk -(l + 1) a_lk, A22 = (1/2) sum_lk k^2 a_lk, so
+ * A10 < 0 < A22 is required), MFD_BURGERS or MFD_NSE (square lattices of up
+ * to 19 velocities; the NSE's viscosity follows the momentum set's own
+ * moments).  mfd_general_create: grid (MMFD form, periodic, FP64 / FP32),
+ * lattice (MFD_D1Q3 .. MFD_D3Q27), d0 (d0[0] on a square grid, one per axis
+ * with spacing; NULL: 1/3), spacing (NULL: the square grid of grid->dx; else
+ * the spacing per axis of a rectangular lattice, linear CDE only), eq_code,
+ * the equation's parameters (u, K, lambda_bar; beta; rho0, he_luo),
+ * 1 <= m <= 3, 1 <= n <= 4, a and ab (NSE momentum set; NULL: a): n rows
+ * of 2m + 1 (row l = level t - l dt, entry k + m), dt > 0.  Returns MFD_OK
+ * or MFD_W_INCONSISTENT (A00 != 1, or for the linear CDE A11 != A10) with
+ * *out set; MFD_E_ARG for bad sizes or coefficients, MFD_E_UNSUPPORTED for
+ * another form, boundary or equation, or a lattice / spacing the equation
+ * does not take, MFD_E_OOM.  Levels hold the equation's fields (1, or
+ * 1 + dim for the NSE: rho - rho0, then j), field-major, x fastest:
+ * set_level(0) fills every level with the data (phi^(-l) = phi^0),
+ * set_level(l) then overrides level t - l dt; get_level(l) reads it
+ * (synchronous, host or device pointers).  step advances nsteps steps on
+ * the solver's stream (the default stream unless set). */
 typedef struct mfd_general mfd_general;
 int mfd_general_create(mfd_general **out, const mfd_grid *grid, int lattice, const double d0[3],
-                       const double spacing[3], const mfd_eq_params *eq, int32_t m, int32_t n,
-                       const double *a, double dt);
+                       const double spacing[3], int eq_code, const mfd_eq_params *eq, int32_t m,
+                       int32_t n, const double *a, const double *ab, double dt);
 int mfd_general_destroy(mfd_general *g);
 const char *mfd_general_last_error(const mfd_general *g);
 int mfd_general_set_stream(mfd_general *g, void *stream);

@@ -22,6 +22,18 @@ struct GenC {
   T Cm[kGenMaxLevels][kGenMaxM][kHostMaxP];
 };
 
+// Burgers' equation and the NSE: per level l the base sums A_l (density /
+// scalar) and Ab_l (momentum), per level and k = 1..m the pair sums
+// a+ = a_lk + a_l,-k, a- = a_lk - a_l,-k and the momentum set's ab+, ab-
+// (the pair parts carry the weights); device memory
+template <typename T>
+struct GenNL {
+  int m, nl;
+  T A[kGenMaxLevels], Ab[kGenMaxLevels];
+  T ap[kGenMaxLevels][kGenMaxM], am[kGenMaxLevels][kGenMaxM];
+  T abp[kGenMaxLevels][kGenMaxM], abm[kGenMaxLevels][kGenMaxM];
+};
+
 // the levels t, t - dt, ... of one step, by value
 template <typename T>
 struct GenLevels {
@@ -33,5 +45,12 @@ struct GenLevels {
 template <typename T>
 hipError_t launch_general_step(int lattice, GenLevels<T> lev, T *out, const int64_t n[3],
                                const GenC<T> *gc, hipStream_t st);
+// the same for Burgers' equation (eq = kBurgers) and the NSE (kNSE, fields
+// field-major) on lattices of at most 19 velocities: each neighbour's pair
+// part from its moments (make_record, fplus, fminus of edf.h, as the
+// single-step kernels form them)
+template <typename T>
+hipError_t launch_general_nl_step(const Consts &c, GenLevels<T> lev, T *out, const int64_t n[3],
+                                  const GenNL<T> *g, hipStream_t st);
 
 }  // namespace mfd

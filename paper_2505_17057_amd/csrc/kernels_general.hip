@@ -1,4 +1,5 @@
-// The general MMFD step of Eq. (2-2-1) for a linear EDF (the linear CDE):
+// The general MMFD step of Eq. (2-2-1) for a linear EDF (the linear CDE), and
+// (k_general_nl, at the end) for Burgers' equation and the NSE:
 // any stencil reach m and number of levels n, any lattice (rD3Q27 included),
 // periodic wrap.  Each thread updates one node:
 //   out = sum_l A_l phi_l + sum_l sum_p sum_{k=1..m} [Cp_lkp D2_{p,k} phi_l
@@ -59,6 +60,104 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
   out[i0] = base + acc;
 }
 
+// Burgers' equation / the NSE: the pair parts of each neighbour formed from
+// its moments; the sums in the order of the oracle's pair-part form:
+//   density / scalar: acc over (level, pair, k) of a+ D2 F+ and a- D1 F-,
+//   momentum j_a: over (level, pair with e_pa != 0, k) of +-(ab+ D2 F- and
+//   ab- D1 F+), then the base terms level by level.
+template <class L, int EQ, typename T>
+__global__ __launch_bounds__(256) void k_general_nl(GenLevels<T> lev, T *__restrict__ out, int nx,
+                                                    int ny, int nz, KC<T> kc,
+                                                    const GenNL<T> *__restrict__ g) {
+  using R = Rec<L, EQ>;
+  constexpr int NF = R::NF, NR = R::NR, D = L::D;
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int m = g->m, nl = g->nl;
+  const int64_t plane = (int64_t)nx * ny, N = plane * nz;
+  const int64_t i0 = (int64_t)z * plane + (int64_t)y * nx + x;
+  T acc = 0, mo[D > 0 ? D : 1];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mo[a] = 0;
+  auto rec_at = [&](const T *f, int64_t i, T *r) {
+    T mm[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) mm[q] = f[q * N + i];
+    make_record<L, EQ>(mm, r, kc);
+  };
+  for (int l = 0; l < nl; ++l) {
+    const T *__restrict__ f = lev.p[l];
+    T r0[NR];
+    rec_at(f, i0, r0);
+    static_for<L::P>([&](auto PI) {
+      constexpr int P = decltype(PI)::value;
+      constexpr int J = L::PR[P];
+      constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+      const T p0 = fplus<L, EQ, J>(r0, kc), q0 = fminus<L, EQ, J>(r0, kc);
+      for (int k = 1; k <= m; ++k) {
+        const int64_t ip = (int64_t)gwrap(z + k * ez, nz) * plane +
+                           (int64_t)gwrap(y + k * ey, ny) * nx + gwrap(x + k * ex, nx);
+        const int64_t im = (int64_t)gwrap(z - k * ez, nz) * plane +
+                           (int64_t)gwrap(y - k * ey, ny) * nx + gwrap(x - k * ex, nx);
+        T rp[NR], rm[NR];
+        rec_at(f, ip, rp);
+        rec_at(f, im, rm);
+        const T pP = fplus<L, EQ, J>(rp, kc), pM = fplus<L, EQ, J>(rm, kc);
+        const T qP = fminus<L, EQ, J>(rp, kc), qM = fminus<L, EQ, J>(rm, kc);
+        acc = acc + g->ap[l][k - 1] * ((pP - p0) + (pM - p0));
+        acc = acc + g->am[l][k - 1] * (qP - qM);
+        if constexpr (EQ == kNSE) {
+          const T t1 = g->abp[l][k - 1] * ((qP - q0) + (qM - q0));
+          const T t2 = g->abm[l][k - 1] * (pP - pM);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (L::E[J][a] == 0) continue;
+            if (L::E[J][a] > 0) {
+              mo[a] = mo[a] + t1;
+              mo[a] = mo[a] + t2;
+            } else {
+              mo[a] = mo[a] - t1;
+              mo[a] = mo[a] - t2;
+            }
+          }
+        }
+      }
+    });
+  }
+  T base = g->A[0] * lev.p[0][i0];
+  for (int l = 1; l < nl; ++l) base = base + g->A[l] * lev.p[l][i0];
+  out[i0] = base + acc;
+  if constexpr (EQ == kNSE) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int64_t fi = (int64_t)(a + 1) * N + i0;
+      T bj = g->Ab[0] * lev.p[0][fi];
+      for (int l = 1; l < nl; ++l) bj = bj + g->Ab[l] * lev.p[l][fi];
+      out[fi] = bj + mo[a];
+    }
+  }
+}
+
+template <class L, int EQ, typename T>
+hipError_t gnl(const Consts &c, GenLevels<T> lev, T *out, const int64_t n[3], const GenNL<T> *g,
+               hipStream_t st) {
+  const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
+  hipLaunchKernelGGL((k_general_nl<L, EQ, T>), dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(64, 4),
+                     0, st, lev, out, nx, ny, nz, make_kc<T>(c), g);
+  return hipGetLastError();
+}
+
+template <class L, typename T>
+hipError_t gnl_eq(const Consts &c, GenLevels<T> lev, T *out, const int64_t n[3],
+                  const GenNL<T> *g, hipStream_t st) {
+  if (c.eq == kBurgers) return gnl<L, kBurgers, T>(c, lev, out, n, g, st);
+  if constexpr (L::D >= 2) {
+    if (c.eq == kNSE) return gnl<L, kNSE, T>(c, lev, out, n, g, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <class L, typename T>
 hipError_t gl(GenLevels<T> lev, T *out, const int64_t n[3], const GenC<T> *gc, hipStream_t st) {
   const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
@@ -86,6 +185,28 @@ hipError_t launch_general_step(int lattice, GenLevels<T> lev, T *out, const int6
   }
 }
 
+template <typename T>
+hipError_t launch_general_nl_step(const Consts &c, GenLevels<T> lev, T *out, const int64_t n[3],
+                                  const GenNL<T> *g, hipStream_t st) {
+  if (n[2] > 65535) return hipErrorInvalidValue;
+  switch (c.lattice) {
+    case 1: return gnl_eq<LatD1Q3, T>(c, lev, out, n, g, st);
+    case 2: return gnl_eq<LatD2Q5, T>(c, lev, out, n, g, st);
+    case 3: return gnl_eq<LatD2Q9, T>(c, lev, out, n, g, st);
+    case 4: return gnl_eq<LatD3Q19, T>(c, lev, out, n, g, st);
+    case 5: return gnl_eq<LatD2Q5II, T>(c, lev, out, n, g, st);
+    case 6: return gnl_eq<LatD3Q7, T>(c, lev, out, n, g, st);
+    case 7: return gnl_eq<LatD3Q9, T>(c, lev, out, n, g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_general_nl_step<float>(const Consts &, GenLevels<float>, float *,
+                                                  const int64_t *, const GenNL<float> *,
+                                                  hipStream_t);
+template hipError_t launch_general_nl_step<double>(const Consts &, GenLevels<double>, double *,
+                                                   const int64_t *, const GenNL<double> *,
+                                                   hipStream_t);
 template hipError_t launch_general_step<float>(int, GenLevels<float>, float *, const int64_t *,
                                                const GenC<float> *, hipStream_t);
 template hipError_t launch_general_step<double>(int, GenLevels<double>, double *, const int64_t *,

@@ -122,9 +122,9 @@ _SIGS = {
     "mfd_set_theta_tolerance": ([_H, C.c_double, C.c_int32], C.c_int),
     "mfd_set_theta_multigrid": ([_H, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "mfd_set_rectangular": ([_H, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
-    "mfd_general_create": ([C.POINTER(_H), C.POINTER(mfd_grid), C.c_int, _PD, _PD,
-                            C.POINTER(mfd_eq_params), C.c_int32, C.c_int32, _PD, C.c_double],
-                           C.c_int),
+    "mfd_general_create": ([C.POINTER(_H), C.POINTER(mfd_grid), C.c_int, _PD, _PD, C.c_int,
+                            C.POINTER(mfd_eq_params), C.c_int32, C.c_int32, _PD, _PD,
+                            C.c_double], C.c_int),
     "mfd_general_destroy": ([_H], C.c_int),
     "mfd_general_last_error": ([_H], C.c_char_p),
     "mfd_general_set_stream": ([_H, C.c_void_p], C.c_int),
@@ -235,11 +235,13 @@ def _ptr_of(x):
 
 class General:
     """Owner of one mfd_general handle: the MMFD scheme with stencil reach m
-    and n time levels for the linear CDE (marshalling only).  a: n rows of
-    2m + 1 coefficients (row l: level t - l dt, entry k + m)."""
+    and n time levels for the linear CDE, Burgers' equation or the NSE
+    (marshalling only).  a (and the NSE momentum set ab): n rows of 2m + 1
+    coefficients (row l: level t - l dt, entry k + m)."""
 
     def __init__(self, lattice, n, dx, a, dt, u=(), K=None, lambda_bar=0, precision="fp64",
-                 d0=1.0 / 3.0, spacing=None, d0v=None):
+                 d0=1.0 / 3.0, spacing=None, d0v=None, eq="lcde", ab=None, beta=1.0, rho0=0.0,
+                 he_luo=0):
         self.lattice = lattice
         self.dim = DIMS[lattice]
         n = tuple(int(v) for v in n)
@@ -262,19 +264,27 @@ class General:
             Kd[: K.shape[0], : K.shape[1]] = K
         p.K = (C.c_double * 9)(*Kd.ravel().tolist())
         p.lambda_bar = int(lambda_bar)
-        p.beta = 1.0
+        p.beta = float(beta)
+        p.rho0 = float(rho0)
+        p.he_luo = int(he_luo)
+        if ab is not None:
+            ab = np.ascontiguousarray(np.asarray(ab, dtype=np.float64))
+            assert ab.shape == a.shape
+        self.nf = 1 + self.dim if eq == "nse" else 1
         dv = list(d0v) if d0v is not None else [d0]
         dv3 = _d3((dv + [dv[0]] * 3)[:3])
         sp = _d3((list(spacing) + [spacing[0]] * 3)[:3]) if spacing is not None else None
         h = _H()
-        rc = lib.mfd_general_create(C.byref(h), C.byref(g), LATTICES[lattice], dv3, sp, C.byref(p),
-                                    self.m, self.nl, a.ctypes.data_as(_PD), float(dt))
+        rc = lib.mfd_general_create(C.byref(h), C.byref(g), LATTICES[lattice], dv3, sp, EQS[eq],
+                                    C.byref(p), self.m, self.nl, a.ctypes.data_as(_PD),
+                                    ab.ctypes.data_as(_PD) if ab is not None else None,
+                                    float(dt))
         if rc < 0:
             raise MfdError(rc, "mfd_general_create")
         self.warnings = [rc] if rc > 0 else []
         self.h = h
         self.n = n
-        self.N = int(np.prod(n))
+        self.N = self.nf * int(np.prod(n))
         self.dtype = np.float64 if precision == "fp64" else np.float32
 
     def check(self, rc, what):

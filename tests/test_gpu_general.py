@@ -118,3 +118,71 @@ def test_general_m1_matches_the_regular_solver(M, three):
     want = s.get_state()
     s.close()
     assert np.allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+NLC = [
+    dict(name="burgers-d2q9-m2", lattice="D2Q9", n=(66, 41), eq="burgers", m=2, nl=1),
+    dict(name="burgers-d1q3-m3-n2", lattice="D1Q3", n=(257,), eq="burgers", m=3, nl=2),
+    dict(name="nse-d2q9-m2-n2", lattice="D2Q9", n=(64, 45), eq="nse", m=2, nl=2),
+    dict(name="nse-d3q19-m1-n3", lattice="D3Q19", n=(17, 12, 9), eq="nse", m=1, nl=3),
+    dict(name="nse-d2q5-m3", lattice="D2Q5", n=(50, 37), eq="nse", m=3, nl=1),
+]
+
+
+def _nl_case(c, rng):
+    m, nl = c["m"], c["nl"]
+    a = _a(rng, m, nl)
+    ab = _a(rng, m, nl) if c["eq"] == "nse" else None
+    spec = dict(lattice=c["lattice"], eq=c["eq"], n=c["n"], dx=1.0, dt=1.0, rho0=1.0, beta=1.0)
+    N = int(np.prod(c["n"]))
+    nf = 1 + len(c["n"]) if c["eq"] == "nse" else 1
+    levels = [0.05 * rng.uniform(-1, 1, nf * N) for _ in range(nl)]
+    return spec, a, ab, levels
+
+
+def _nl_gpu(M, c, spec, a, ab, levels, steps, precision):
+    g = M.General(c["lattice"], c["n"], 1.0, a, 1.0, eq=c["eq"], ab=ab, rho0=1.0,
+                  precision=precision)
+    g.set_level(0, levels[0])
+    for l in range(1, len(levels)):
+        g.set_level(l, levels[l])
+    g.step(steps)
+    out = [g.get_level(l).astype(np.float64) for l in range(len(levels))]
+    g.close()
+    return out
+
+
+def _nl_oracle(spec, a, ab, levels, steps):
+    lev = [np.asarray(v, dtype=np.float64) for v in levels]
+    for _ in range(steps):
+        lev = [GN.nonlinear_mmfd_step(spec, lev, a, ab)] + lev[:-1]
+    return lev
+
+
+@pytest.mark.parametrize("case", NLC, ids=lambda c: c["name"])
+def test_general_nonlinear_fp64_bitwise(M, case):
+    rng = np.random.default_rng(61)
+    spec, a, ab, levels = _nl_case(case, rng)
+    want = _nl_oracle(spec, a, ab, levels, 4)
+    got = _nl_gpu(M, case, spec, a, ab, levels, 4, "fp64")
+    for l in range(case["nl"]):
+        assert np.array_equal(got[l], want[l]), l
+
+
+@pytest.mark.parametrize("case", [NLC[0], NLC[2]], ids=lambda c: c["name"])
+def test_general_nonlinear_fp32_within_1e5(M, case):
+    rng = np.random.default_rng(62)
+    spec, a, ab, levels = _nl_case(case, rng)
+    levels = [v.astype(np.float32).astype(np.float64) for v in levels]
+    want = _nl_oracle(spec, a, ab, levels, 4)
+    got = _nl_gpu(M, case, spec, a, ab, levels, 4, "fp32")
+    assert rel_l2(got[0], want[0]) < 1e-5
+
+
+def test_general_nonlinear_refusals(M):
+    """The nonlinear equations run on square lattices of up to 19 velocities."""
+    a = [[0.5, 0.2, 0.3]]
+    with pytest.raises(M.MfdError):
+        M.General("D3Q27", (6, 6, 6), 1.0, a, 1.0, eq="nse", rho0=1.0)
+    with pytest.raises(M.MfdError):
+        M.General("D2Q9", (8, 8), 1.0, a, 1.0, eq="burgers", spacing=(1.0, 2.0), d0v=(0.3, 0.3))
