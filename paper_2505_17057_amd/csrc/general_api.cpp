@@ -135,12 +135,13 @@ extern "C" int mfd_general_create(mfd_general **out, const mfd_grid *grid, int l
                                   const double d0[3], const double spacing[3], int eq_code,
                                   const mfd_eq_params *eq, int32_t m, int32_t n, const double *a,
                                   const double *ab, double dt) {
-  if (!out || !grid || !eq || !a) return MFD_E_ARG;
+  if (!out) return MFD_E_ARG;
+  *out = nullptr;
+  if (!grid || !eq || !a) return MFD_E_ARG;
   if (eq_code != MFD_LCDE && eq_code != MFD_BURGERS && eq_code != MFD_NSE) return MFD_E_UNSUPPORTED;
   // the nonlinear equations: square lattices of at most 19 velocities
   if (eq_code != MFD_LCDE && (spacing || lattice == MFD_D3Q27)) return MFD_E_UNSUPPORTED;
   if (eq_code == MFD_NSE && grid->dim < 2) return MFD_E_UNSUPPORTED;
-  *out = nullptr;
   if (grid->dim < 1 || grid->dim > 3 || grid->form != MFD_MMFD || grid->boundary != MFD_PERIODIC ||
       (grid->precision != MFD_FP64 && grid->precision != MFD_FP32))
     return MFD_E_UNSUPPORTED;
