@@ -66,8 +66,8 @@ def parse():
     p.add_argument("--no-headline", action="store_true",
                    help="skip the headline (profiling of the other sections; value is then null)")
     p.add_argument("--sections",
-                   default="c3err,c2,variants,multiset,theta,theta_mg,big,c1,nse3d,source,wave,"
-                           "burgers,burgers_theta,batched,serving",
+                   default="c3err,c2,variants,multiset,theta,theta_mg,nse_theta,general,rect,big,c1,"
+                           "nse3d,source,wave,burgers,burgers_theta,batched,serving",
                    help="comma-separated sections to run after the headline")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a 256 MiB device copy (HBM counter calibration)")
@@ -615,6 +615,120 @@ def bench_burgers_theta(M, torch, I, stream, theta=0.5, steps=200, chunk=4, cap=
     return out
 
 
+def bench_nse_theta(M, torch, I, stream, theta=0.5, steps=100, chunk=4, cap=64, courant=0.2):
+    """theta scheme for the 2D NSE (Picard sweeps with the linear parts'
+    own-node coefficient split per field) on the 1024^2 Taylor-Green vortex
+    with dt = 0.2 dx / U0 (four times the explicit recipe's), density set
+    s = 1 and momentum set s = 1 / (nu dt / (d0 dx^2) + 1/2), each step solved
+    to a tolerance (binary64 1e-12, binary32 1e-6): GLUPS at convergence,
+    sweeps per step, FP32 error against the FP64 run of the same steps."""
+    c = I.tgv_2d(n=1024, courant=courant)
+    s_j = 1.0 / (c["nu"] * c["dt"] / (D0 * c["dx"] ** 2) + 0.5)
+    fam = lambda s: ((s + 1) / 2, 1 - s, (s - 1) / 2)
+    N = 1024 * 1024
+    out, finals = {}, {}
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-12)):
+        sv = M.Solver("D2Q9", c["n"], c["dx"], prec, "mmfd")
+        sv.set_equation("nse", rho0=c["rho0"])
+        sv.set_scheme("theta", fam(1.0), ab=fam(s_j), theta=theta, theta_iters=cap, dt=c["dt"])
+        sv.set_theta_tolerance(tol, chunk)
+        sv.set_stream(stream.cuda_stream)
+        sv.set_state(c["state0"].astype(sv.dtype))
+        sv.step(3)
+        sv.set_state(c["state0"].astype(sv.dtype))
+        sv.theta_stats(reset=True)
+        ms = timed(torch, lambda: sv.step(steps))
+        st = sv.theta_stats()
+        finals[prec] = sv.get_state().astype(np.float64)
+        sv.close()
+        g = N * steps / (ms * 1e-3) / 1e9
+        sw = st["total_sweeps"] / max(st["steps"], 1)
+        out[prec] = dict(glups=round(g, 3), tolerance=tol, sweeps_per_step=round(sw, 2),
+                         max_sweeps=st["max_sweeps"], steps_stopped_by_cap=st["unconverged"],
+                         sweep_glups=round(g * sw, 2))
+    out.update(theta=theta, courant=courant, momentum_s=round(s_j, 4), chunk_sweeps=chunk,
+               sweep_cap=cap, steps=steps,
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(finals["fp32"] - finals["fp64"])
+                                         / np.linalg.norm(finals["fp64"])))
+    return out
+
+
+def bench_general(M, torch, I, stream):
+    """The general-scheme solver (mfd_general_*): the rD3Q27 linear CDE at
+    256^3 (reach 1, one level), the 2048^2 rD2Q9 linear CDE with reach 2 and
+    two levels, and the 1024^2 rD2Q9 Taylor-Green NSE with reach 2; GLUPS of
+    FP32 and FP64 and the FP32 error against FP64 after the same steps.
+    Tables: A00 = 1 and A10 = A11 = -1 (Eq. (4-2-00a)); each row k = -m..m."""
+    one = np.array([[1.0, 0.0, 0.0]])                                  # A22 = 1/2
+    two = np.array([[0.2, 0.6, 0.2, 0.0, 0.0], [-0.05, 0.1, -0.05, 0.0, 0.0]])  # A22 = 0.65
+    wide = np.array([[0.25, 0.5, 0.25, 0.0, 0.0]])                     # A22 = 3/4
+    tgv = I.tgv_2d(n=1024)
+    cases = [
+        ("lcde_d3q27_256_m1", "D3Q27", (256, 256, 256), one, 20),
+        ("lcde_d2q9_2048_m2_n2", "D2Q9", (2048, 2048), two, 100),
+        ("nse_d2q9_1024_m2", "D2Q9", (1024, 1024), wide, 100),
+    ]
+    out = {}
+    for name, lat, n, a, steps in cases:
+        N = int(np.prod(n))
+        dim = len(n)
+        nse = name.startswith("nse")
+        if nse:
+            state = tgv["state0"]
+        else:
+            x = np.indices(tuple(reversed(n)), dtype=np.float64)
+            state = np.exp(sum(np.cos(2 * np.pi * x[i] / n[dim - 1 - i]) for i in range(dim))).ravel()
+            del x
+        res, fin = {}, {}
+        for prec in ("fp32", "fp64"):
+            if nse:
+                g = M.General(lat, n, tgv["dx"], a, tgv["dt"], precision=prec, eq="nse", ab=a,
+                              rho0=tgv["rho0"])
+            else:
+                g = M.General(lat, n, 1.0, a, 1.0, u=[0.05, -0.03, 0.02][:dim],
+                              K=(np.eye(dim) * 0.1).tolist(), lambda_bar=1, precision=prec)
+            g.set_stream(stream.cuda_stream)
+            for l in range(a.shape[0]):
+                g.set_level(l, state)
+            g.step(2)
+            for l in range(a.shape[0]):
+                g.set_level(l, state)
+            ms = timed(torch, lambda: g.step(steps))
+            fin[prec] = g.get_level(0).astype(np.float64)
+            g.close()
+            res[prec + "_glups"] = round(N * steps / (ms * 1e-3) / 1e9, 2)
+        res.update(steps=steps, reach=(a.shape[1] - 1) // 2, levels=a.shape[0],
+                   fp32_rel_l2_vs_fp64=float(np.linalg.norm(fin["fp32"] - fin["fp64"])
+                                             / np.linalg.norm(fin["fp64"])))
+        out[name] = res
+    return out
+
+
+def bench_rect(M, torch, cfg, stream, N, steps=1000):
+    """The 2048^2 linear CDE on a rectangular rD2Q9 lattice (dy = 2 dx,
+    d0 = (1/3, 1/4)), autotuned plan: GLUPS of FP32 and FP64 and the FP32
+    error against FP64 (the kernels are the square lattice's)."""
+    out, fin = {}, {}
+    for prec in ("fp32", "fp64"):
+        s = M.Solver("D2Q9", cfg["n"], cfg["dx"], prec, "mmfd")
+        s.set_rectangular((cfg["dx"], 2 * cfg["dx"]), (1.0 / 3.0, 0.25))
+        s.set_equation("lcde", u=cfg["u"], K=cfg["K"], lambda_bar=cfg["lambda_bar"])
+        s.set_scheme("two_level", M.mfd_preset("srt")[0], dt=cfg["dt"])
+        s.set_stream(stream.cuda_stream)
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        s.autotune()
+        s.set_state(cfg["phi0"].astype(s.dtype))
+        ms = timed(torch, lambda: s.step(steps))
+        fin[prec] = s.get_state().astype(np.float64)
+        plan = s.launch_plan()
+        s.close()
+        out[prec] = dict(glups=round(N * steps / (ms * 1e-3) / 1e9, 2), plan=list(plan))
+    out.update(steps=steps, spacing=[cfg["dx"], 2 * cfg["dx"]], d0=[1.0 / 3.0, 0.25],
+               fp32_rel_l2_vs_fp64=float(np.linalg.norm(fin["fp32"] - fin["fp64"])
+                                         / np.linalg.norm(fin["fp64"])))
+    return out
+
+
 def bench_multiset(M, torch, cfg, stream, N, steps=1000):
     """Multiple-set (TRT-type) two-level linear CDE, Eq. (2-2-1b), on the
     2048^2 workload: base set SRT (a_-1 = 1), even set (1/2, 0, 1/2) and odd
@@ -967,6 +1081,15 @@ def main():
     if "theta" in sections:
         log("theta")
         extra["theta_d2q9_2048"] = bench_theta(M, torch, cfg, stream, N)
+    if "nse_theta" in sections:
+        log("NSE theta")
+        extra["nse_theta_tgv_1024"] = bench_nse_theta(M, torch, I, stream)
+    if "general" in sections:
+        log("general scheme")
+        extra["general_scheme"] = bench_general(M, torch, I, stream)
+    if "rect" in sections:
+        log("rectangular lattice")
+        extra["rect_lcde_d2q9_2048"] = bench_rect(M, torch, cfg, stream, N)
     if "theta_mg" in sections:
         log("theta, large steps: Jacobi vs multigrid")
         extra["theta_large_dt_d2q9_2048"] = bench_theta_mg(M, torch, cfg, stream, N)
