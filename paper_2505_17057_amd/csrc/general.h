@@ -40,17 +40,17 @@ struct GenLevels {
   const T *p[kGenMaxLevels];
 };
 
-// one step of every node: out = sum_l A_l phi_l + sum_l sum_p sum_k
+// one step of every node (m: the reach gc holds): out = sum_l A_l phi_l + sum_l sum_p sum_k
 // [Cp D2_{p,k} phi_l + Cm D1_{p,k} phi_l]; gc in device memory
 template <typename T>
-hipError_t launch_general_step(int lattice, GenLevels<T> lev, T *out, const int64_t n[3],
+hipError_t launch_general_step(int lattice, int m, GenLevels<T> lev, T *out, const int64_t n[3],
                                const GenC<T> *gc, hipStream_t st);
 // the same for Burgers' equation (eq = kBurgers) and the NSE (kNSE, fields
 // field-major) on lattices of at most 19 velocities: each neighbour's pair
 // part from its moments (make_record, fplus, fminus of edf.h, as the
 // single-step kernels form them)
 template <typename T>
-hipError_t launch_general_nl_step(const Consts &c, GenLevels<T> lev, T *out, const int64_t n[3],
-                                  const GenNL<T> *g, hipStream_t st);
+hipError_t launch_general_nl_step(const Consts &c, int m, GenLevels<T> lev, T *out,
+                                  const int64_t n[3], const GenNL<T> *g, hipStream_t st);
 
 }  // namespace mfd

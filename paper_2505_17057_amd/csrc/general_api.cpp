@@ -108,9 +108,9 @@ int general_steps(mfd_general *g, int64_t nsteps) {
     for (int l = 0; l < g->nl; ++l) lv.p[l] = (const T *)g->slot(l);
     hipError_t e =
         g->eq == MFD_LCDE
-            ? launch_general_step<T>(g->consts.lattice, lv, (T *)g->slot(g->nl), g->G.n,
+            ? launch_general_step<T>(g->consts.lattice, g->m, lv, (T *)g->slot(g->nl), g->G.n,
                                      (const GenC<T> *)g->d_gc, g->stream)
-            : launch_general_nl_step<T>(g->consts, lv, (T *)g->slot(g->nl), g->G.n,
+            : launch_general_nl_step<T>(g->consts, g->m, lv, (T *)g->slot(g->nl), g->G.n,
                                         (const GenNL<T> *)g->d_gc, g->stream);
     if (e != hipSuccess) return g->hip(e, "general step launch");
     // the new level becomes level 0; the oldest one's slot the spare

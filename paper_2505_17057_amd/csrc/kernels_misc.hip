@@ -467,18 +467,19 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const T *__restrict__ cu
   }
 }
 
+// out[q] = sum over the nblk rows of partial[b kRedQ + q], q < nq (<= kRedQ)
 __global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__ partial, int nblk,
-                                                      double *__restrict__ out) {
+                                                      int nq, double *__restrict__ out) {
   __shared__ double red[kRedQ][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = 0; q < kRedQ; ++q) {
+  for (int q = 0; q < nq; ++q) {
     double v = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) v += partial[b * kRedQ + q];
     v = wave_sum(v);
     if (lane == 0) red[q][wave] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kRedQ) {
+  if (threadIdx.x < nq) {
     const int q = threadIdx.x;
     out[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
   }
@@ -509,7 +510,7 @@ hipError_t launch_reduce(const T *cur, const T *prev, int nf, int64_t N, double 
       break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, nblk, kRedQ, out);
   return hipGetLastError();
 }
 
@@ -602,11 +603,12 @@ __global__ __launch_bounds__(256) void k_sq_partial(const T *__restrict__ a,
                                                     const T *__restrict__ b,
                                                     const T *__restrict__ cc, int64_t N,
                                                     double *__restrict__ partial) {
+  const int64_t o = blockIdx.y * N;
   double s0 = 0.0, s1 = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double d = (double)a[i] - (double)b[i];
-    const double r = (double)cc[i];
+    const double d = (double)a[o + i] - (double)b[o + i];
+    const double r = (double)cc[o + i];
     s0 += d * d;
     s1 += r * r;
   }
@@ -619,21 +621,22 @@ __global__ __launch_bounds__(256) void k_sq_partial(const T *__restrict__ a,
     red[1][wave] = s1;
   }
   __syncthreads();
-  if (threadIdx.x < kRedQ) {
+  if (threadIdx.x < 2) {
     const int q = threadIdx.x;
-    partial[blockIdx.x * kRedQ + q] =
-        q < 2 ? ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3] : 0.0;
+    partial[blockIdx.x * kRedQ + 2 * blockIdx.y + q] =
+        ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
   }
 }
 
 template <typename T>
-hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,
+hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int F, int64_t N, double *partial,
                           double *out, hipStream_t st) {
+  if (F < 1 || 2 * F > kRedQ) return hipErrorInvalidValue;
   int nblk = (int)((N + 255) / 256);
   if (nblk > kReduceBlocks) nblk = kReduceBlocks;
   if (nblk < 1) nblk = 1;
-  hipLaunchKernelGGL((k_sq_partial<T>), dim3(nblk), dim3(256), 0, st, a, b, c, N, partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL((k_sq_partial<T>), dim3(nblk, F), dim3(256), 0, st, a, b, c, N, partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, nblk, 2 * F, out);
   return hipGetLastError();
 }
 
@@ -642,15 +645,24 @@ hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double 
 //   R       = theta S(phi^n) + (1 - theta) (A0 phi^n),
 //   x_{k+1} = (R + (1 - theta) ((S(x_k) - A0 x_k) + dd x_k)) / den,
 // one rounding per operation in the order written.
+// Fields are stored one after another (field f at f N); blockIdx.y is the
+// field, whose constants come in PicardF.
+template <typename T>
+struct PicardF {
+  T A0[4], dd[4], inv_den[4];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_picard_rhs(const T *__restrict__ S0,
                                                     const T *__restrict__ phi, T *__restrict__ R,
-                                                    T th, T th1, T A0, int64_t N) {
+                                                    T th, T th1, PicardF<T> pf, int64_t N) {
+  const int64_t o = blockIdx.y * N;
+  const T A0 = pf.A0[blockIdx.y];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const T a = th * S0[i];
-    const T b = A0 * phi[i];
-    R[i] = a + th1 * b;
+    const T a = th * S0[o + i];
+    const T b = A0 * phi[o + i];
+    R[o + i] = a + th1 * b;
   }
 }
 
@@ -658,32 +670,48 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_picard_update(const T *__restrict__ Sx,
                                                        const T *__restrict__ x,
                                                        const T *__restrict__ R,
-                                                       T *__restrict__ out, T A0, T dd, T th1,
-                                                       T inv_den, int64_t N) {
+                                                       T *__restrict__ out, T th1, PicardF<T> pf,
+                                                       int64_t N) {
+  const int64_t o = blockIdx.y * N;
+  const T A0 = pf.A0[blockIdx.y], dd = pf.dd[blockIdx.y], inv_den = pf.inv_den[blockIdx.y];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const T xi = x[i];
-    const T t = (Sx[i] - A0 * xi) + dd * xi;
+    const T xi = x[o + i];
+    const T t = (Sx[o + i] - A0 * xi) + dd * xi;
     const T c = th1 * t;
-    out[i] = (R[i] + c) * inv_den;
+    out[o + i] = (R[o + i] + c) * inv_den;
   }
 }
 
 template <typename T>
-hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, double A0,
-                             int64_t N, hipStream_t st) {
-  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192);
-  hipLaunchKernelGGL((k_picard_rhs<T>), dim3(nblk), dim3(256), 0, st, S0, phi, R, (T)th, (T)th1,
-                     (T)A0, N);
+PicardF<T> picard_f(int F, const double *A0, const double *dd, const double *inv_den) {
+  PicardF<T> pf{};
+  for (int f = 0; f < F; ++f) {
+    pf.A0[f] = (T)A0[f];
+    pf.dd[f] = dd ? (T)dd[f] : (T)0;
+    pf.inv_den[f] = inv_den ? (T)inv_den[f] : (T)0;
+  }
+  return pf;
+}
+
+template <typename T>
+hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, int F,
+                             const double *A0, int64_t N, hipStream_t st) {
+  if (F < 1 || F > 4) return hipErrorInvalidValue;
+  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192 / F);
+  hipLaunchKernelGGL((k_picard_rhs<T>), dim3(nblk, F), dim3(256), 0, st, S0, phi, R, (T)th, (T)th1,
+                     picard_f<T>(F, A0, nullptr, nullptr), N);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, double A0, double dd,
-                                double th1, double inv_den, int64_t N, hipStream_t st) {
-  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192);
-  hipLaunchKernelGGL((k_picard_update<T>), dim3(nblk), dim3(256), 0, st, Sx, x, R, out, (T)A0,
-                     (T)dd, (T)th1, (T)inv_den, N);
+hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, int F,
+                                const double *A0, const double *dd, double th1,
+                                const double *inv_den, int64_t N, hipStream_t st) {
+  if (F < 1 || F > 4) return hipErrorInvalidValue;
+  const int nblk = (int)std::min<int64_t>((N + 255) / 256, 8192 / F);
+  hipLaunchKernelGGL((k_picard_update<T>), dim3(nblk, F), dim3(256), 0, st, Sx, x, R, out, (T)th1,
+                     picard_f<T>(F, A0, dd, inv_den), N);
   return hipGetLastError();
 }
 
@@ -734,10 +762,11 @@ hipError_t launch_wave_start(const Consts &c, const Grid &g, const T *phi0, cons
 }
 
 #define MFD_INST(T)                                                                               \
-  template hipError_t launch_picard_rhs<T>(const T *, const T *, T *, double, double, double,     \
-                                           int64_t, hipStream_t);                                 \
-  template hipError_t launch_picard_update<T>(const T *, const T *, const T *, T *, double,       \
-                                              double, double, double, int64_t, hipStream_t);      \
+  template hipError_t launch_picard_rhs<T>(const T *, const T *, T *, double, double, int,        \
+                                           const double *, int64_t, hipStream_t);                 \
+  template hipError_t launch_picard_update<T>(const T *, const T *, const T *, T *, int,          \
+                                              const double *, const double *, double,             \
+                                              const double *, int64_t, hipStream_t);              \
   template hipError_t launch_wave_start<T>(const Consts &, const Grid &, const T *,               \
                                            const double *, T *, double, double, const DirBC &,    \
                                            hipStream_t);                                          \
@@ -755,7 +784,7 @@ hipError_t launch_wave_start(const Consts &c, const Grid &g, const T *phi0, cons
                                             hipStream_t);                                         \
   template hipError_t launch_theta_gather<T>(T *const[4], const ThetaCtl *, int64_t,              \
                                              hipStream_t);                                        \
-  template hipError_t launch_sq_sums<T>(const T *, const T *, const T *, int64_t, double *,       \
+  template hipError_t launch_sq_sums<T>(const T *, const T *, const T *, int, int64_t, double *,  \
                                         double *, hipStream_t);
 MFD_INST(float)
 MFD_INST(double)

@@ -53,11 +53,15 @@ __global__ __launch_bounds__(256) void k_picard_plane(const T *__restrict__ x,
 // Each workgroup walks a contiguous run of tiles (XCD-aware: the runs of one
 // XCD are adjacent, so halo rows are shared in its L2) and loads the next
 // tile's moments while it updates the current one.
-template <class L, bool THREE, bool THREE_ST, int TX, int TY, bool FAST, typename T>
+// PIC: one Picard-Jacobi sweep of the theta step (the explicit step of the
+// iterate cur, then the per-field update of pe at the store).
+template <class L, bool THREE, bool THREE_ST, int TX, int TY, bool FAST, typename T,
+          bool PIC = false>
 __global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
                                                       const T *__restrict__ prev,
                                                       T *__restrict__ out, int nx, int ny,
-                                                      int tiles_x, int ntiles, KC<T> kc) {
+                                                      int tiles_x, int ntiles, KC<T> kc,
+                                                      PicardNse<T> pe) {
   using P = PfTile<L, THREE, THREE_ST, TX, TY, T, FAST>;
   __shared__ typename P::Lds sm;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -75,7 +79,8 @@ __global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
       for (int q = 0; q < P::NF; ++q) pcv[k][q] = g.pcv[k][q];
     __syncthreads();
     if (t + 1 < t1) P::load(cur, prev, nx, ny, ((t + 1) % tiles_x) * TX, ((t + 1) / tiles_x) * TY, g);
-    P::update(sm, pcv, out, nx, ny, (t % tiles_x) * TX, (t / tiles_x) * TY, kc);
+    P::update(sm, pcv, out, nx, ny, (t % tiles_x) * TX, (t / tiles_x) * TY, kc,
+              PIC ? &pe : nullptr);
     __syncthreads();
   }
 }
@@ -258,10 +263,12 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     const int grid = ntiles < groups ? ntiles : groups;
     if (nx >= TX + 2 && ny >= TY + 2)
       hipLaunchKernelGGL((k_nse_plane_pp<L, THREE, THREE_ST, TX, TY, true, T>), dim3(grid),
-                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc);
+                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc,
+                         PicardNse<T>{});
     else
       hipLaunchKernelGGL((k_nse_plane_pp<L, THREE, THREE_ST, TX, TY, false, T>), dim3(grid),
-                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc);
+                         dim3(256), 0, st, cur, prev, out, nx, ny, tx, ntiles, kc,
+                         PicardNse<T>{});
   } else if constexpr (L::D == 2) {
     constexpr int TX = 64, TY = 16;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
@@ -378,27 +385,71 @@ hipError_t picard_l(const Consts &c, const Grid &g, const T *x, const T *R, T *o
   }
   return hipGetLastError();
 }
+
+// the 2D NSE: the persistent tile kernel of the explicit step with the
+// per-field update at the store (the explicit step's launch shape)
+template <class L, typename T>
+hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
+                        const double *A0, const double *dd, double th1, const double *inv_den,
+                        hipStream_t st) {
+  const KC<T> kc = make_kc<T>(c);
+  PicardNse<T> pe{};
+  pe.R = R;
+  pe.th1 = (T)th1;
+  for (int q = 0; q < Rec<L, kNSE>::NF; ++q) {
+    pe.A0[q] = (T)A0[q];
+    pe.dd[q] = (T)dd[q];
+    pe.inv_den[q] = (T)inv_den[q];
+  }
+  const int nx = (int)g.n[0], ny = (int)g.n[1];
+  constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
+  const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+  const int ntiles = tx * ty;
+  constexpr int per_cu = (int)((160 * 1024) / sizeof(typename PfTile<L, false, false, TX, TY, T>::Lds));
+  constexpr int groups = kNumCUs * (per_cu < 1 ? 1 : per_cu);
+  const int grid = ntiles < groups ? ntiles : groups;
+  if (nx >= TX + 2 && ny >= TY + 2)
+    hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, true, T, true>), dim3(grid),
+                       dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
+  else
+    hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, false, T, true>), dim3(grid),
+                       dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
+  return hipGetLastError();
+}
 }  // namespace
 
 template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
-                               double A0, double dd, double th1, double inv_den, hipStream_t st) {
-  if (c.eq != kBurgers || c.three) return hipErrorInvalidValue;
+                               const double *A0, const double *dd, double th1,
+                               const double *inv_den, hipStream_t st) {
+  if (c.three) return hipErrorInvalidValue;
+  if (c.eq == kNSE) {
+    if (c.dim != 2) return hipErrorInvalidValue;
+    switch (c.lattice) {
+      case 2: return picard_nse_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+      case 3: return picard_nse_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+      case 5: return picard_nse_l<LatD2Q5II, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (c.eq != kBurgers) return hipErrorInvalidValue;
   switch (c.lattice) {
-    case 1: return picard_l<LatD1Q3, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
-    case 2: return picard_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
-    case 3: return picard_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
-    case 5: return picard_l<LatD2Q5II, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+    case 1: return picard_l<LatD1Q3, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
+    case 2: return picard_l<LatD2Q5, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
+    case 3: return picard_l<LatD2Q9, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
+    case 5: return picard_l<LatD2Q5II, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_picard_sweep<float>(const Consts &, const Grid &, const float *,
-                                               const float *, float *, double, double, double,
-                                               double, hipStream_t);
+                                               const float *, float *, const double *,
+                                               const double *, double, const double *,
+                                               hipStream_t);
 template hipError_t launch_picard_sweep<double>(const Consts &, const Grid &, const double *,
-                                                const double *, double *, double, double, double,
-                                                double, hipStream_t);
+                                                const double *, double *, const double *,
+                                                const double *, double, const double *,
+                                                hipStream_t);
 
 template hipError_t launch_mmfd_step<float>(const Consts &, const Grid &, const float *,
                                             const float *, float *, int, hipStream_t,

@@ -458,7 +458,7 @@ int Solver::theta_solve_steps(int64_t nsteps) {
         src = dst;
         ++k;
       }
-      e = launch_sq_sums<T>(src, before, B[5], G.N, part, out, stream);
+      e = launch_sq_sums<T>(src, before, B[5], 1, G.N, part, out, stream);
       if (e != hipSuccess) return hip(e, "theta residual launch");
       double h[2];
       int rc = copy_out(h, out, sizeof(h), 0);
@@ -524,16 +524,16 @@ int Solver::theta_picard_steps(int64_t nsteps) {
       inv_den[f] = 1.0 / den[f];
     }
   }
-  // Burgers on 1D / 2D grids: the sweep fused into the explicit step's tile
-  const bool fused = consts.eq == kBurgers && consts.dim <= 2;
+  // Burgers on 1D / 2D grids and the 2D NSE: the sweep fused into the
+  // explicit step's tile
+  const bool fused = (consts.eq == kBurgers && consts.dim <= 2) ||
+                     (consts.eq == kNSE && consts.dim == 2);
   double *part = (double *)buf[kRedBuf];
   double *out = part + kReduceBlocks * 8;
   const int64_t N = G.N;
   for (int64_t s = 0; s < nsteps; ++s) {
     hipError_t e = launch_mmfd_step<T>(consts, G, B[ic], nullptr, B[6], 1, stream);
-    for (int f = 0; f < F && e == hipSuccess; ++f)
-      e = launch_picard_rhs<T>(B[6] + f * N, B[ic] + f * N, B[5] + f * N, th, th1, A0[f], N,
-                               stream);
+    if (e == hipSuccess) e = launch_picard_rhs<T>(B[6], B[ic], B[5], th, th1, F, A0, N, stream);
     if (e != hipSuccess) return hip(e, "picard rhs launch");
     const T *src = B[ic];
     int k = 0;
@@ -543,13 +543,11 @@ int Solver::theta_picard_steps(int64_t nsteps) {
       for (int it = 0; it < K; ++it) {
         T *dst = (k % 2 == 0) ? B[io] : B[third];
         if (fused) {
-          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0[0], dd[0], th1, inv_den[0],
-                                     stream);
+          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0, dd, th1, inv_den, stream);
         } else {
           e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
-          for (int f = 0; f < F && e == hipSuccess; ++f)
-            e = launch_picard_update<T>(B[6] + f * N, src + f * N, B[5] + f * N, dst + f * N,
-                                        A0[f], dd[f], th1, inv_den[f], N, stream);
+          if (e == hipSuccess)
+            e = launch_picard_update<T>(B[6], src, B[5], dst, F, A0, dd, th1, inv_den, N, stream);
         }
         if (e != hipSuccess) return hip(e, "picard sweep launch");
         before = src;
@@ -557,18 +555,19 @@ int Solver::theta_picard_steps(int64_t nsteps) {
         ++k;
       }
       if (!tol_on) break;
-      // sum_f den_f^2 |x_k - x_(k-1)|_f^2 <= tol^2 sum_f |R|_f^2
+      // sum_f den_f^2 |x_k - x_(k-1)|_f^2 <= tol^2 sum_f |R|_f^2 (field f's two
+      // sums in out[2 f], out[2 f + 1]; one copy to the host)
+      e = launch_sq_sums<T>(src, before, B[5], F, N, part, out, stream);
+      if (e != hipSuccess) return hip(e, "picard residual launch");
+      double hsum[8];
+      const int rc = copy_out(hsum, out, 2 * F * sizeof(double), 0);
+      if (rc) return rc;
       double lhs = 0.0, rhs = 0.0;
       for (int f = 0; f < F; ++f) {
-        e = launch_sq_sums<T>(src + f * N, before + f * N, B[5] + f * N, N, part, out, stream);
-        if (e != hipSuccess) return hip(e, "picard residual launch");
-        double hsum[2];
-        int rc = copy_out(hsum, out, sizeof(hsum), 0);
-        if (rc) return rc;
-        if (!std::isfinite(hsum[0]) || !std::isfinite(hsum[1]))
+        if (!std::isfinite(hsum[2 * f]) || !std::isfinite(hsum[2 * f + 1]))
           return fail(MFD_E_UNSTABLE, "non-finite theta residual");
-        lhs = lhs + den[f] * den[f] * hsum[0];
-        rhs = rhs + hsum[1];
+        lhs = lhs + den[f] * den[f] * hsum[2 * f];
+        rhs = rhs + hsum[2 * f + 1];
       }
       conv = lhs <= theta_tol * theta_tol * rhs;
       if (conv || k >= cap) break;

@@ -331,21 +331,27 @@ hipError_t launch_theta_chunk(const Consts &c, const Grid &g, int K, T *const bu
                               hipStream_t st);
 template <typename T>
 hipError_t launch_theta_gather(T *const bufs[4], const ThetaCtl *ctl, int64_t N, hipStream_t st);
-// Picard-Jacobi theta step of Burgers' equation: the elementwise parts
+// Picard-Jacobi theta step of Burgers' equation and the NSE: the elementwise
+// parts of F (<= 4) fields of N nodes each (field f at offset f N), with the
+// per-field constants A0[f], dd[f], inv_den[f]
 template <typename T>
-hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, double A0,
-                             int64_t N, hipStream_t st);
+hipError_t launch_picard_rhs(const T *S0, const T *phi, T *R, double th, double th1, int F,
+                             const double *A0, int64_t N, hipStream_t st);
 template <typename T>
-hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, double A0, double dd,
-                                double th1, double inv_den, int64_t N, hipStream_t st);
-// one Picard-Jacobi sweep of Burgers' theta step fused with the explicit
-// step of the iterate (1D / 2D; hipErrorInvalidValue otherwise)
+hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, int F,
+                                const double *A0, const double *dd, double th1,
+                                const double *inv_den, int64_t N, hipStream_t st);
+// one Picard-Jacobi sweep of the theta step fused with the explicit step of
+// the iterate: Burgers' equation on 1D / 2D grids (field 0's constants) and
+// the NSE on 2D grids (per-field constants); hipErrorInvalidValue otherwise
 template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
-                               double A0, double dd, double th1, double inv_den, hipStream_t st);
-// sum (a - b)^2 and sum c^2 in binary64 (out[0], out[1]); partial as launch_reduce
+                               const double *A0, const double *dd, double th1,
+                               const double *inv_den, hipStream_t st);
+// per field f < F (<= 4; field f at offset f N): sum (a - b)^2 and sum c^2 in
+// binary64 (out[2 f], out[2 f + 1]); partial as launch_reduce
 template <typename T>
-hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int64_t N, double *partial,
+hipError_t launch_sq_sums(const T *a, const T *b, const T *c, int F, int64_t N, double *partial,
                           double *out, hipStream_t st);
 
 template <typename T>

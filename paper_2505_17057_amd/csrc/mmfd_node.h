@@ -296,6 +296,17 @@ __device__ __forceinline__ int wrap1(int i, int n) {
   return i - (i >= n ? n : 0);
 }
 
+// Sweep of the Picard-Jacobi iteration of the NSE's theta step, applied per
+// field q to the explicit step value S_q(x) of a node:
+// out_q = (R_q + th1 ((S_q - A0_q x_q) + dd_q x_q)) inv_den_q (the operations
+// and roundings of the separate elementwise update).
+template <typename T>
+struct PicardNse {
+  const T *R;
+  T A0[4], dd[4], inv_den[4];
+  T th1;
+};
+
 // FAST: nx >= TX + 2 and ny >= TY + 2, so every halo index is within one
 // period of the grid (cheap wrap); otherwise the general wrap.
 template <class L, bool THREE, bool THREE_ST, int TX, int TY, typename T, bool FAST = false>
@@ -381,7 +392,8 @@ struct PfTile {
 
   static __device__ __forceinline__ void update(const Lds &s, const T (&pcv)[KI][NF],
                                                 T *__restrict__ out, int nx, int ny, int x0,
-                                                int y0, const KC<T> &kc) {
+                                                int y0, const KC<T> &kc,
+                                                const PicardNse<T> *pe = nullptr) {
     const int64_t N = (int64_t)nx * ny;
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
@@ -411,6 +423,15 @@ struct PfTile {
         nse32_node<L, THREE>(at2, g0, cc, pc, oc, kc);
       } else {
         mmfd_node<L, kNSE, THREE, THREE_ST, T, false, true>(at, ath, cc, pc, oc, kc);
+      }
+      if (pe) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+          const T xi = cc[q];
+          const T t = (oc[q] - pe->A0[q] * xi) + pe->dd[q] * xi;
+          const T c = pe->th1 * t;
+          oc[q] = (pe->R[q * N + gi] + c) * pe->inv_den[q];
+        }
       }
 #pragma unroll
       for (int q = 0; q < NF; ++q) out[q * N + gi] = oc[q];
