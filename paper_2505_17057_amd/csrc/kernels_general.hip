@@ -22,43 +22,68 @@ namespace mfd {
 
 namespace {
 
+// fourth word of a raw buffer resource on gfx9-family parts (32-bit data
+// format, no stride, no swizzle)
+constexpr int kBufWord3 = 0x00020000;
+
 // offsets of the wrapped coordinates c + j, j = -M..M, on an axis of extent
 // n, times the axis stride; the branch on n is uniform over the launch
-template <int M>
-__device__ __forceinline__ void wrap_axis(int c, int n, int64_t stride, int64_t (&o)[2 * M + 1]) {
+template <int M, typename I>
+__device__ __forceinline__ void wrap_axis(int c, int n, int64_t stride, I (&o)[2 * M + 1]) {
   if (n >= M) {
 #pragma unroll
     for (int j = -M; j <= M; ++j) {
       int i = c + j;
       i = i < 0 ? i + n : (i >= n ? i - n : i);
-      o[j + M] = (int64_t)i * stride;
+      o[j + M] = (I)(i * stride);
     }
   } else {
 #pragma unroll
     for (int j = -M; j <= M; ++j) {
       const int i = (c + j) % n;
-      o[j + M] = (int64_t)(i < 0 ? i + n : i) * stride;
+      o[j + M] = (I)((i < 0 ? i + n : i) * stride);
     }
   }
 }
 
-template <int M>
+// Byte offsets of a node's neighbours within one field: 32-bit (I =
+// uint32_t) when a field spans less than 4 GiB, so a load is a uniform base
+// plus one 32-bit register offset; 64-bit otherwise.
+template <int M, typename T, typename I>
 struct GenIdx {
-  int64_t xo[2 * M + 1], yo[2 * M + 1], zo[2 * M + 1];
+  I xo[2 * M + 1], yo[2 * M + 1], zo[2 * M + 1];
   __device__ __forceinline__ GenIdx(int x, int y, int z, int nx, int ny, int nz) {
-    wrap_axis<M>(x, nx, 1, xo);
-    wrap_axis<M>(y, ny, nx, yo);
-    wrap_axis<M>(z, nz, (int64_t)nx * ny, zo);
+    wrap_axis<M>(x, nx, (int64_t)sizeof(T), xo);
+    wrap_axis<M>(y, ny, (int64_t)nx * sizeof(T), yo);
+    wrap_axis<M>(z, nz, (int64_t)nx * ny * sizeof(T), zo);
   }
   // the node x + sk e (sk = +-k)
   template <int EX, int EY, int EZ>
-  __device__ __forceinline__ int64_t at(int sk) const {
+  __device__ __forceinline__ I at(int sk) const {
     return zo[M + sk * EZ] + yo[M + sk * EY] + xo[M + sk * EX];
   }
-  __device__ __forceinline__ int64_t centre() const { return zo[M] + yo[M] + xo[M]; }
+  __device__ __forceinline__ I centre() const { return zo[M] + yo[M] + xo[M]; }
 };
 
-template <class L, int M, typename T>
+// load of the element at byte offset off of a field starting at base: a
+// buffer load (resource over the field's nb bytes, 32-bit offset) when I is
+// uint32_t, a global load otherwise
+template <typename T, typename I>
+__device__ __forceinline__ T ld(const T *base, uint32_t nb, I off) {
+  if constexpr (std::is_same<I, uint32_t>::value) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)nb, kBufWord3);
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  } else {
+    (void)nb;
+    return *(const T *)((const char *)base + off);
+  }
+}
+
+template <class L, int M, typename T, typename I>
 __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__restrict__ out, int nx,
                                                       int ny, int nz,
                                                       const GenC<T> *__restrict__ gc) {
@@ -66,19 +91,21 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
   const int z = blockIdx.z;
   if (x >= nx || y >= ny) return;
   const int nl = gc->nl;
-  const GenIdx<M> ix(x, y, z, nx, ny, nz);
-  const int64_t i0 = ix.centre();
+  const GenIdx<M, T, I> ix(x, y, z, nx, ny, nz);
+  const I i0 = ix.centre();
+  const uint32_t nb = (uint32_t)((int64_t)nx * ny * nz * (int64_t)sizeof(T));
   T acc = 0;
   for (int l = 0; l < nl; ++l) {
     const T *__restrict__ g = lev.p[l];
-    const T g0 = g[i0];
+    const T g0 = ld(g, nb, i0);
     static_for<L::P>([&](auto PI) {
       constexpr int P = decltype(PI)::value;
       constexpr int J = L::PR[P];
       constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
 #pragma unroll
       for (int k = 1; k <= M; ++k) {
-        const T gp = g[ix.template at<ex, ey, ez>(k)], gm = g[ix.template at<ex, ey, ez>(-k)];
+        const T gp = ld(g, nb, ix.template at<ex, ey, ez>(k));
+        const T gm = ld(g, nb, ix.template at<ex, ey, ez>(-k));
         const T d2 = (gp - g0) + (gm - g0);
         const T d1 = gp - gm;
         acc = acc + gc->Cp[l][k - 1][P] * d2;
@@ -86,9 +113,9 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
       }
     });
   }
-  T base = gc->A[0] * lev.p[0][i0];
-  for (int l = 1; l < nl; ++l) base = base + gc->A[l] * lev.p[l][i0];
-  out[i0] = base + acc;
+  T base = gc->A[0] * ld(lev.p[0], nb, i0);
+  for (int l = 1; l < nl; ++l) base = base + gc->A[l] * ld(lev.p[l], nb, i0);
+  *(T *)((char *)out + i0) = base + acc;
 }
 
 // Burgers' equation / the NSE: the pair parts of each neighbour formed from
@@ -96,7 +123,7 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
 //   density / scalar: acc over (level, pair, k) of a+ D2 F+ and a- D1 F-,
 //   momentum j_a: over (level, pair with e_pa != 0, k) of +-(ab+ D2 F- and
 //   ab- D1 F+), then the base terms level by level.
-template <class L, int EQ, int M, typename T>
+template <class L, int EQ, int M, typename T, typename I>
 __global__ __launch_bounds__(256) void k_general_nl(GenLevels<T> lev, T *__restrict__ out, int nx,
                                                     int ny, int nz, KC<T> kc,
                                                     const GenNL<T> *__restrict__ g) {
@@ -107,15 +134,16 @@ __global__ __launch_bounds__(256) void k_general_nl(GenLevels<T> lev, T *__restr
   if (x >= nx || y >= ny) return;
   const int nl = g->nl;
   const int64_t N = (int64_t)nx * ny * nz;
-  const GenIdx<M> ix(x, y, z, nx, ny, nz);
-  const int64_t i0 = ix.centre();
+  const GenIdx<M, T, I> ix(x, y, z, nx, ny, nz);
+  const I i0 = ix.centre();
+  const uint32_t nb = (uint32_t)(N * (int64_t)sizeof(T));
   T acc = 0, mo[D > 0 ? D : 1];
 #pragma unroll
   for (int a = 0; a < D; ++a) mo[a] = 0;
-  auto rec_at = [&](const T *f, int64_t i, T *r) {
+  auto rec_at = [&](const T *f, I i, T *r) {
     T mm[NF];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) mm[q] = f[q * N + i];
+    for (int q = 0; q < NF; ++q) mm[q] = ld(f + q * N, nb, i);
     make_record<L, EQ>(mm, r, kc);
   };
   for (int l = 0; l < nl; ++l) {
@@ -154,25 +182,31 @@ __global__ __launch_bounds__(256) void k_general_nl(GenLevels<T> lev, T *__restr
       }
     });
   }
-  T base = g->A[0] * lev.p[0][i0];
-  for (int l = 1; l < nl; ++l) base = base + g->A[l] * lev.p[l][i0];
-  out[i0] = base + acc;
+  T base = g->A[0] * ld(lev.p[0], nb, i0);
+  for (int l = 1; l < nl; ++l) base = base + g->A[l] * ld(lev.p[l], nb, i0);
+  *(T *)((char *)out + i0) = base + acc;
   if constexpr (EQ == kNSE) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const int64_t fi = (int64_t)(a + 1) * N + i0;
-      T bj = g->Ab[0] * lev.p[0][fi];
-      for (int l = 1; l < nl; ++l) bj = bj + g->Ab[l] * lev.p[l][fi];
-      out[fi] = bj + mo[a];
+      const int64_t fo = (int64_t)(a + 1) * N;
+      T bj = g->Ab[0] * ld(lev.p[0] + fo, nb, i0);
+      for (int l = 1; l < nl; ++l) bj = bj + g->Ab[l] * ld(lev.p[l] + fo, nb, i0);
+      *(T *)((char *)(out + fo) + i0) = bj + mo[a];
     }
   }
 }
 
+// the reach m and the offset width (32-bit when a field spans < 4 GiB) as
+// template arguments
 #define MFD_GEN_LAUNCH(KERNEL, ...)                                                          \
-  switch (m) {                                                                             \
-    case 1: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 1, T>), grid, block, 0, st, ARGS); break; \
-    case 2: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 2, T>), grid, block, 0, st, ARGS); break; \
-    case 3: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 3, T>), grid, block, 0, st, ARGS); break; \
+  const bool small = (int64_t)nx * ny * nz * (int64_t)sizeof(T) < ((int64_t)1 << 32);        \
+  switch (m * 2 + (small ? 1 : 0)) {                                                       \
+    case 2: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 1, T, int64_t>), grid, block, 0, st, ARGS); break; \
+    case 3: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 1, T, uint32_t>), grid, block, 0, st, ARGS); break; \
+    case 4: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 2, T, int64_t>), grid, block, 0, st, ARGS); break; \
+    case 5: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 2, T, uint32_t>), grid, block, 0, st, ARGS); break; \
+    case 6: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 3, T, int64_t>), grid, block, 0, st, ARGS); break; \
+    case 7: hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 3, T, uint32_t>), grid, block, 0, st, ARGS); break; \
     default: return hipErrorInvalidValue;                                                  \
   }
 
