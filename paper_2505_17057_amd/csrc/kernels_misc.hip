@@ -467,22 +467,40 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const T *__restrict__ cu
   }
 }
 
-// out[q] = sum over the nblk rows of partial[b kRedQ + q], q < nq (<= kRedQ)
+// out[q] = sum over the nblk rows of partial[b kRedQ + q], q < nq (<= kRedQ):
+// thread t adds rows t, t + 256, ... in order (all quantities of a row in one
+// pass, so the loads of the quantities overlap), then per quantity a wave sum
+// and the four waves in a fixed order.
 __global__ __launch_bounds__(256) void k_reduce_final(const double *__restrict__ partial, int nblk,
                                                       int nq, double *__restrict__ out) {
   __shared__ double red[kRedQ][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = 0; q < nq; ++q) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) v += partial[b * kRedQ + q];
-    v = wave_sum(v);
-    if (lane == 0) red[q][wave] = v;
+  double v[kRedQ];
+#pragma unroll
+  for (int q = 0; q < kRedQ; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+    for (int q = 0; q < kRedQ; ++q)
+      if (q < nq) v[q] += partial[b * kRedQ + q];
+  }
+#pragma unroll
+  for (int q = 0; q < kRedQ; ++q) {
+    if (q < nq) {
+      const double w = wave_sum(v[q]);
+      if (lane == 0) red[q][wave] = w;
+    }
   }
   __syncthreads();
   if (threadIdx.x < nq) {
     const int q = threadIdx.x;
     out[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
   }
+}
+
+hipError_t launch_final_sums(const double *partial, int rows, int nq, double *out, hipStream_t st) {
+  if (rows < 1 || rows > kReduceBlocks || nq < 1 || nq > kRedQ) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partial, rows, nq, out);
+  return hipGetLastError();
 }
 
 template <typename T>

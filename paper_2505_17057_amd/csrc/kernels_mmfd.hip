@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_picard_plane(const T *__restrict__ x,
 // PIC: one Picard-Jacobi sweep of the theta step (the explicit step of the
 // iterate cur, then the per-field update of pe at the store).
 template <class L, bool THREE, bool THREE_ST, int TX, int TY, bool FAST, typename T,
-          bool PIC = false>
+          bool PIC = false, bool SUMS = false>
 __global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
                                                       const T *__restrict__ prev,
                                                       T *__restrict__ out, int nx, int ny,
@@ -67,7 +67,14 @@ __global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int t0 = w * per, t1 = min(ntiles, t0 + per);
-  if (t0 >= t1) return;  // the whole workgroup: no barrier is skipped by part of it
+  constexpr bool sums = PIC && SUMS;
+  double sq[2 * P::NF];
+#pragma unroll
+  for (int q = 0; q < 2 * P::NF; ++q) sq[q] = 0.0;
+  if (t0 >= t1) {  // the whole workgroup: no barrier is skipped by part of it
+    if (sums && threadIdx.x < 2 * P::NF) pe.part[blockIdx.x * 8 + threadIdx.x] = 0.0;
+    return;
+  }
   typename P::Regs g;
   P::load(cur, prev, nx, ny, (t0 % tiles_x) * TX, (t0 / tiles_x) * TY, g);
   for (int t = t0; t < t1; ++t) {
@@ -80,8 +87,26 @@ __global__ __launch_bounds__(256) void k_nse_plane_pp(const T *__restrict__ cur,
     __syncthreads();
     if (t + 1 < t1) P::load(cur, prev, nx, ny, ((t + 1) % tiles_x) * TX, ((t + 1) / tiles_x) * TY, g);
     P::update(sm, pcv, out, nx, ny, (t % tiles_x) * TX, (t / tiles_x) * TY, kc,
-              PIC ? &pe : nullptr);
+              PIC ? &pe : nullptr, sums ? sq : nullptr);
     __syncthreads();
+  }
+  if constexpr (sums) {
+    {  // the workgroup's row: wave sums, then the four waves in order
+      __shared__ double red[2 * P::NF][4];
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+      for (int q = 0; q < 2 * P::NF; ++q) {
+        double v = sq[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[q][wave] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < 2 * P::NF) {
+        const int q = threadIdx.x;
+        pe.part[blockIdx.x * 8 + q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+      }
+    }
   }
 }
 
@@ -391,7 +416,7 @@ hipError_t picard_l(const Consts &c, const Grid &g, const T *x, const T *R, T *o
 template <class L, typename T>
 hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                         const double *A0, const double *dd, double th1, const double *inv_den,
-                        hipStream_t st) {
+                        double *part, int *rows, hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
   PicardNse<T> pe{};
   pe.R = R;
@@ -408,12 +433,26 @@ hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, 
   constexpr int per_cu = (int)((160 * 1024) / sizeof(typename PfTile<L, false, false, TX, TY, T>::Lds));
   constexpr int groups = kNumCUs * (per_cu < 1 ? 1 : per_cu);
   const int grid = ntiles < groups ? ntiles : groups;
-  if (nx >= TX + 2 && ny >= TY + 2)
+  // the residual sums ride along when the workgroups' rows fit the scratch
+  if (part && grid <= kReduceBlocks) {
+    pe.part = part;
+    *rows = grid;
+  }
+  const bool fast = nx >= TX + 2 && ny >= TY + 2;
+  if (pe.part) {
+    if (fast)
+      hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, true, T, true, true>),
+                         dim3(grid), dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
+    else
+      hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, false, T, true, true>),
+                         dim3(grid), dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
+  } else if (fast) {
     hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, true, T, true>), dim3(grid),
                        dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
-  else
+  } else {
     hipLaunchKernelGGL((k_nse_plane_pp<L, false, false, TX, TY, false, T, true>), dim3(grid),
                        dim3(256), 0, st, x, nullptr, out, nx, ny, tx, ntiles, kc, pe);
+  }
   return hipGetLastError();
 }
 }  // namespace
@@ -421,14 +460,18 @@ hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, 
 template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                                const double *A0, const double *dd, double th1,
-                               const double *inv_den, hipStream_t st) {
+                               const double *inv_den, double *part, int *rows, hipStream_t st) {
+  *rows = 0;
   if (c.three) return hipErrorInvalidValue;
   if (c.eq == kNSE) {
     if (c.dim != 2) return hipErrorInvalidValue;
     switch (c.lattice) {
-      case 2: return picard_nse_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
-      case 3: return picard_nse_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
-      case 5: return picard_nse_l<LatD2Q5II, T>(c, g, x, R, out, A0, dd, th1, inv_den, st);
+      case 2:
+        return picard_nse_l<LatD2Q5, T>(c, g, x, R, out, A0, dd, th1, inv_den, part, rows, st);
+      case 3:
+        return picard_nse_l<LatD2Q9, T>(c, g, x, R, out, A0, dd, th1, inv_den, part, rows, st);
+      case 5:
+        return picard_nse_l<LatD2Q5II, T>(c, g, x, R, out, A0, dd, th1, inv_den, part, rows, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -444,12 +487,12 @@ hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const
 
 template hipError_t launch_picard_sweep<float>(const Consts &, const Grid &, const float *,
                                                const float *, float *, const double *,
-                                               const double *, double, const double *,
-                                               hipStream_t);
+                                               const double *, double, const double *, double *,
+                                               int *, hipStream_t);
 template hipError_t launch_picard_sweep<double>(const Consts &, const Grid &, const double *,
                                                 const double *, double *, const double *,
-                                                const double *, double, const double *,
-                                                hipStream_t);
+                                                const double *, double, const double *, double *,
+                                                int *, hipStream_t);
 
 template hipError_t launch_mmfd_step<float>(const Consts &, const Grid &, const float *,
                                             const float *, float *, int, hipStream_t,

@@ -540,10 +540,12 @@ int Solver::theta_picard_steps(int64_t nsteps) {
     bool conv = false;
     while (true) {
       const T *before = src;
+      int rows = 0;  // residual rows the chunk's last sweep wrote (fused NSE sweep)
       for (int it = 0; it < K; ++it) {
         T *dst = (k % 2 == 0) ? B[io] : B[third];
         if (fused) {
-          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0, dd, th1, inv_den, stream);
+          e = launch_picard_sweep<T>(consts, G, src, B[5], dst, A0, dd, th1, inv_den,
+                                     tol_on && it == K - 1 ? part : nullptr, &rows, stream);
         } else {
           e = launch_mmfd_step<T>(consts, G, src, nullptr, B[6], 1, stream);
           if (e == hipSuccess)
@@ -557,7 +559,8 @@ int Solver::theta_picard_steps(int64_t nsteps) {
       if (!tol_on) break;
       // sum_f den_f^2 |x_k - x_(k-1)|_f^2 <= tol^2 sum_f |R|_f^2 (field f's two
       // sums in out[2 f], out[2 f + 1]; one copy to the host)
-      e = launch_sq_sums<T>(src, before, B[5], F, N, part, out, stream);
+      e = rows > 0 ? launch_final_sums(part, rows, 2 * F, out, stream)
+                   : launch_sq_sums<T>(src, before, B[5], F, N, part, out, stream);
       if (e != hipSuccess) return hip(e, "picard residual launch");
       double hsum[8];
       const int rc = copy_out(hsum, out, 2 * F * sizeof(double), 0);

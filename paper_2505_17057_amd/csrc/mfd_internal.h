@@ -344,10 +344,15 @@ hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, int
 // one Picard-Jacobi sweep of the theta step fused with the explicit step of
 // the iterate: Burgers' equation on 1D / 2D grids (field 0's constants) and
 // the NSE on 2D grids (per-field constants); hipErrorInvalidValue otherwise
+// part (may be null): where the kernel supports it (the 2D NSE), the sweep
+// also writes per-workgroup binary64 rows of (x_new - x)^2 and R^2 per field
+// (8 doubles a row) and sets *rows to their count (else *rows = 0)
 template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                                const double *A0, const double *dd, double th1,
-                               const double *inv_den, hipStream_t st);
+                               const double *inv_den, double *part, int *rows, hipStream_t st);
+// out[q] = sum of the rows' quantity q (q < nq <= 8) in a fixed order
+hipError_t launch_final_sums(const double *partial, int rows, int nq, double *out, hipStream_t st);
 // per field f < F (<= 4; field f at offset f N): sum (a - b)^2 and sum c^2 in
 // binary64 (out[2 f], out[2 f + 1]); partial as launch_reduce
 template <typename T>

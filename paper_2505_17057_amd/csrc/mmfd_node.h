@@ -300,11 +300,14 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 // field q to the explicit step value S_q(x) of a node:
 // out_q = (R_q + th1 ((S_q - A0_q x_q) + dd_q x_q)) inv_den_q (the operations
 // and roundings of the separate elementwise update).
+// part (may be null): the sweep also adds, per field, (x_new - x)^2 and R^2
+// in binary64 into per-workgroup partial sums (rows of 8 doubles).
 template <typename T>
 struct PicardNse {
   const T *R;
   T A0[4], dd[4], inv_den[4];
   T th1;
+  double *part;
 };
 
 // FAST: nx >= TX + 2 and ny >= TY + 2, so every halo index is within one
@@ -393,7 +396,8 @@ struct PfTile {
   static __device__ __forceinline__ void update(const Lds &s, const T (&pcv)[KI][NF],
                                                 T *__restrict__ out, int nx, int ny, int x0,
                                                 int y0, const KC<T> &kc,
-                                                const PicardNse<T> *pe = nullptr) {
+                                                const PicardNse<T> *pe = nullptr,
+                                                double *sq = nullptr) {
     const int64_t N = (int64_t)nx * ny;
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
@@ -430,7 +434,13 @@ struct PfTile {
           const T xi = cc[q];
           const T t = (oc[q] - pe->A0[q] * xi) + pe->dd[q] * xi;
           const T c = pe->th1 * t;
-          oc[q] = (pe->R[q * N + gi] + c) * pe->inv_den[q];
+          const T Rq = pe->R[q * N + gi];
+          oc[q] = (Rq + c) * pe->inv_den[q];
+          if (sq) {
+            const double d = (double)oc[q] - (double)xi;
+            sq[2 * q] += d * d;
+            sq[2 * q + 1] += (double)Rq * (double)Rq;
+          }
         }
       }
 #pragma unroll
