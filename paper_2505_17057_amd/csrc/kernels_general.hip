@@ -118,6 +118,101 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
   *(T *)((char *)out + i0) = base + acc;
 }
 
+// The linear CDE on 2D and 3D grids with R nodes per thread along the column
+// axis (y in 2D, z in 3D): a level's values at the thread's nodes and all
+// their neighbours (a (2m+1) x (R+2m) box in 2D, (2m+1)^2 x (R+2m) in 3D)
+// are loaded once per thread and level, so a value that several of the
+// thread's nodes use is loaded once.  Each node's sums are formed exactly as
+// k_general_step forms them (same terms, same order), so the results are the
+// same bit for bit.
+template <int LO, int CNT, typename I>
+__device__ __forceinline__ void wrap_range(int c, int n, int64_t stride, bool fast, I (&o)[CNT]) {
+#pragma unroll
+  for (int j = 0; j < CNT; ++j) {
+    int i = c + LO + j;
+    if (fast) {
+      i = i < 0 ? i + n : (i >= n ? i - n : i);
+    } else {
+      i %= n;
+      i = i < 0 ? i + n : i;
+    }
+    o[j] = (I)(i * stride);
+  }
+}
+
+template <class L, int M, int R, typename T, typename I>
+__global__ __launch_bounds__(256) void k_general_col(GenLevels<T> lev, T *__restrict__ out, int nx,
+                                                     int ny, int nz,
+                                                     const GenC<T> *__restrict__ gc) {
+  constexpr int D = L::D;
+  static_assert(D == 2 || D == 3, "column kernel: 2D and 3D lattices");
+  constexpr int S = 2 * M + 1, W = R + 2 * M;  // stencil width, column window
+  constexpr int BY = D == 2 ? W : S, BZ = D == 3 ? W : 1;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = D == 2 ? (blockIdx.y * 4 + threadIdx.y) * R : blockIdx.y * 4 + threadIdx.y;
+  const int z = D == 3 ? blockIdx.z * R : 0;
+  if (x >= nx || y >= ny) return;
+  const int nw = D == 2 ? ny : nz, w0 = D == 2 ? y : z;
+  const bool fast = nx >= M + R && ny >= M + R && nz >= M + R;
+  I xo[S], yo[BY], zo[BZ];
+  wrap_range<-M, S>(x, nx, (int64_t)sizeof(T), fast, xo);
+  if constexpr (D == 2) {
+    wrap_range<-M, W>(y, ny, (int64_t)nx * sizeof(T), fast, yo);
+    zo[0] = 0;
+  } else {
+    wrap_range<-M, S>(y, ny, (int64_t)nx * sizeof(T), fast, yo);
+    wrap_range<-M, W>(z, nz, (int64_t)nx * ny * sizeof(T), fast, zo);
+  }
+  const uint32_t nb = (uint32_t)((int64_t)nx * ny * nz * (int64_t)sizeof(T));
+  const int nl = gc->nl;
+  T acc[R], base[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0;
+  for (int l = 0; l < nl; ++l) {
+    const T *__restrict__ g = lev.p[l];
+    T v[S][BY][BZ];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < BY; ++b)
+#pragma unroll
+        for (int c = 0; c < BZ; ++c) v[a][b][c] = ld(g, nb, (I)(zo[c] + yo[b] + xo[a]));
+    // value at the offset (dx, dy, dz) from the thread's node r
+    auto at = [&](int r, int dx, int dy, int dz) -> T {
+      if constexpr (D == 2) return v[M + dx][M + r + dy][0];
+      else return v[M + dx][M + dy][M + r + dz];
+    };
+    const T Al = gc->A[l];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T g0 = at(r, 0, 0, 0);
+      T a_r = acc[r];
+      static_for<L::P>([&](auto PI) {
+        constexpr int P = decltype(PI)::value;
+        constexpr int J = L::PR[P];
+        constexpr int ex = L::E[J][0], ey = L::E[J][1], ez = L::E[J][2];
+#pragma unroll
+        for (int k = 1; k <= M; ++k) {
+          const T gp = at(r, k * ex, k * ey, k * ez), gm = at(r, -k * ex, -k * ey, -k * ez);
+          const T d2 = (gp - g0) + (gm - g0);
+          const T d1 = gp - gm;
+          a_r = a_r + gc->Cp[l][k - 1][P] * d2;
+          a_r = a_r + gc->Cm[l][k - 1][P] * d1;
+        }
+      });
+      acc[r] = a_r;
+      base[r] = l == 0 ? Al * g0 : base[r] + Al * g0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (w0 + r < nw) {
+      const I o = D == 2 ? (I)(yo[M + r] + xo[M]) : (I)(zo[M + r] + yo[M] + xo[M]);
+      *(T *)((char *)out + o) = base[r] + acc[r];
+    }
+  }
+}
+
 // Burgers' equation / the NSE: the pair parts of each neighbour formed from
 // its moments; the sums in the order of the oracle's pair-part form:
 //   density / scalar: acc over (level, pair, k) of a+ D2 F+ and a- D1 F-,
@@ -232,15 +327,57 @@ hipError_t gnl_eq(const Consts &c, int m, GenLevels<T> lev, T *out, const int64_
   return hipErrorInvalidValue;
 }
 
+// nodes per thread of the column kernel (1: the one-node kernel)
+template <class L>
+constexpr int col_nodes(int m) {
+  return L::D == 2 ? (m == 1 ? 8 : m == 2 ? 4 : 2) : L::D == 3 && m == 1 ? 4 : 1;
+}
+
+template <class L, int M, int R, typename T>
+hipError_t gcol(GenLevels<T> lev, T *out, int nx, int ny, int nz, const GenC<T> *gc,
+                hipStream_t st) {
+  const dim3 block(64, 4);
+  const dim3 grid((nx + 63) / 64, L::D == 2 ? (ny + 4 * R - 1) / (4 * R) : (ny + 3) / 4,
+                  L::D == 3 ? (nz + R - 1) / R : 1);
+  const bool small = (int64_t)nx * ny * nz * (int64_t)sizeof(T) < ((int64_t)1 << 32);
+  if (small)
+    hipLaunchKernelGGL((k_general_col<L, M, R, T, uint32_t>), grid, block, 0, st, lev, out, nx, ny,
+                       nz, gc);
+  else
+    hipLaunchKernelGGL((k_general_col<L, M, R, T, int64_t>), grid, block, 0, st, lev, out, nx, ny,
+                       nz, gc);
+  return hipGetLastError();
+}
+
+template <class L, int M, typename T>
+hipError_t gl_m(GenLevels<T> lev, T *out, int nx, int ny, int nz, const GenC<T> *gc,
+                hipStream_t st) {
+  constexpr int R = col_nodes<L>(M);
+  if constexpr (R > 1) {
+    return gcol<L, M, R, T>(lev, out, nx, ny, nz, gc, st);
+  } else {
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz), block(64, 4);
+    const bool small = (int64_t)nx * ny * nz * (int64_t)sizeof(T) < ((int64_t)1 << 32);
+    if (small)
+      hipLaunchKernelGGL((k_general_step<L, M, T, uint32_t>), grid, block, 0, st, lev, out, nx,
+                         ny, nz, gc);
+    else
+      hipLaunchKernelGGL((k_general_step<L, M, T, int64_t>), grid, block, 0, st, lev, out, nx, ny,
+                         nz, gc);
+    return hipGetLastError();
+  }
+}
+
 template <class L, typename T>
 hipError_t gl(int m, GenLevels<T> lev, T *out, const int64_t n[3], const GenC<T> *gc,
               hipStream_t st) {
   const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
-  const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz), block(64, 4);
-#define ARGS lev, out, nx, ny, nz, gc
-  MFD_GEN_LAUNCH(k_general_step, L)
-#undef ARGS
-  return hipGetLastError();
+  switch (m) {
+    case 1: return gl_m<L, 1, T>(lev, out, nx, ny, nz, gc, st);
+    case 2: return gl_m<L, 2, T>(lev, out, nx, ny, nz, gc, st);
+    case 3: return gl_m<L, 3, T>(lev, out, nx, ny, nz, gc, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 #undef MFD_GEN_LAUNCH
