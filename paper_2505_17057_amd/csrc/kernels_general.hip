@@ -153,7 +153,9 @@ __global__ __launch_bounds__(256) void k_general_col(GenLevels<T> lev, T *__rest
   const int z = D == 3 ? blockIdx.z * R : 0;
   if (x >= nx || y >= ny) return;
   const int nw = D == 2 ? ny : nz, w0 = D == 2 ? y : z;
-  const bool fast = nx >= M + R && ny >= M + R && nz >= M + R;
+  // one conditional add or subtract wraps c + j (-M <= j < R + M) when the
+  // axis has at least M + R nodes; else the remainder
+  const bool fast = nx >= M + R && ny >= M + R && (D == 2 || nz >= M + R);
   I xo[S], yo[BY], zo[BZ];
   wrap_range<-M, S>(x, nx, (int64_t)sizeof(T), fast, xo);
   if constexpr (D == 2) {

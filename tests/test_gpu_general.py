@@ -37,6 +37,11 @@ CASES = [
          d0v=(0.3, 0.45)),
     dict(name="rect-d3q27-m1-n2", lattice="D3Q27", n=(16, 12, 10), m=1, nl=2,
          spacing=(1.0, 0.5, 2.0), d0v=(0.3, 0.4, 0.5)),
+    # extents below m + (nodes per thread): the wrap by remainder
+    dict(name="tiny-d2q9-m3-n2", lattice="D2Q9", n=(5, 4), m=3, nl=2),
+    dict(name="tiny-d2q9-m1", lattice="D2Q9", n=(70, 6), m=1, nl=1),
+    dict(name="tiny-d3q27-m1", lattice="D3Q27", n=(6, 5, 3), m=1, nl=1),
+    dict(name="tiny-d2q5-m2", lattice="D2Q5", n=(3, 2), m=2, nl=1),
 ]
 
 
