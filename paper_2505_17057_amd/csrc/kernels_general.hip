@@ -293,6 +293,111 @@ __global__ __launch_bounds__(256) void k_general_nl(GenLevels<T> lev, T *__restr
   }
 }
 
+// Burgers' equation / the NSE on 2D grids: a TX x TY tile per workgroup; per
+// level, every node of the tile and its m-wide halo forms its record and its
+// pair parts F+-_p once into LDS (one evaluation per node instead of one per
+// neighbour that uses it), then each node of the tile adds its terms reading
+// the parts from LDS.  The terms and their order are k_general_nl's, and the
+// parts are the same function of the same moments, so the results are the
+// same bit for bit.
+template <class L, int EQ, int M, typename T>
+__global__ __launch_bounds__(256) void k_general_nl_tile(GenLevels<T> lev, T *__restrict__ out,
+                                                         int nx, int ny, int tiles_x, KC<T> kc,
+                                                         const GenNL<T> *__restrict__ g) {
+  using R = Rec<L, EQ>;
+  constexpr int NF = R::NF, NR = R::NR, D = L::D, P = L::P;
+  constexpr int TX = 64, TY = 8, HX = TX + 2 * M, HY = TY + 2 * M;
+  constexpr int KI = TX * TY / 256;  // tile nodes per thread
+  static_assert(D == 2, "2D lattices");
+  __shared__ T pf[2 * P][HY][HX];
+  const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
+  const int64_t N = (int64_t)nx * ny;
+  const int nl = g->nl;
+  T acc[KI], mo[KI][D];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    acc[i] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) mo[i][a] = 0;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const T *__restrict__ f = lev.p[l];
+    if (l > 0) __syncthreads();  // the previous level's parts are read
+    for (int i = threadIdx.x; i < HX * HY; i += 256) {
+      const int lx = i % HX, ly = i / HX;
+      int gx = (x0 - M + lx) % nx, gy = (y0 - M + ly) % ny;
+      gx = gx < 0 ? gx + nx : gx;
+      gy = gy < 0 ? gy + ny : gy;
+      const int64_t gi = (int64_t)gy * nx + gx;
+      T mm[NF], r[NR];
+#pragma unroll
+      for (int q = 0; q < NF; ++q) mm[q] = f[q * N + gi];
+      make_record<L, EQ>(mm, r, kc);
+      static_for<P>([&](auto PI) {
+        constexpr int PP = decltype(PI)::value;
+        constexpr int J = L::PR[PP];
+        pf[2 * PP][ly][lx] = fplus<L, EQ, J>(r, kc);
+        pf[2 * PP + 1][ly][lx] = fminus<L, EQ, J>(r, kc);
+      });
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+      const int t = threadIdx.x + 256 * i;
+      const int cx = t % TX + M, cy = t / TX + M;
+      static_for<P>([&](auto PI) {
+        constexpr int PP = decltype(PI)::value;
+        constexpr int J = L::PR[PP];
+        constexpr int ex = L::E[J][0], ey = L::E[J][1];
+        const T p0 = pf[2 * PP][cy][cx], q0 = pf[2 * PP + 1][cy][cx];
+#pragma unroll
+        for (int k = 1; k <= M; ++k) {
+          const T pP = pf[2 * PP][cy + k * ey][cx + k * ex];
+          const T pM = pf[2 * PP][cy - k * ey][cx - k * ex];
+          const T qP = pf[2 * PP + 1][cy + k * ey][cx + k * ex];
+          const T qM = pf[2 * PP + 1][cy - k * ey][cx - k * ex];
+          acc[i] = acc[i] + g->ap[l][k - 1] * ((pP - p0) + (pM - p0));
+          acc[i] = acc[i] + g->am[l][k - 1] * (qP - qM);
+          if constexpr (EQ == kNSE) {
+            const T t1 = g->abp[l][k - 1] * ((qP - q0) + (qM - q0));
+            const T t2 = g->abm[l][k - 1] * (pP - pM);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              if (L::E[J][a] == 0) continue;
+              if (L::E[J][a] > 0) {
+                mo[i][a] = mo[i][a] + t1;
+                mo[i][a] = mo[i][a] + t2;
+              } else {
+                mo[i][a] = mo[i][a] - t1;
+                mo[i][a] = mo[i][a] - t2;
+              }
+            }
+          }
+        }
+      });
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int t = threadIdx.x + 256 * i;
+    const int gx = x0 + t % TX, gy = y0 + t / TX;
+    if (gx >= nx || gy >= ny) continue;
+    const int64_t i0 = (int64_t)gy * nx + gx;
+    T base = g->A[0] * lev.p[0][i0];
+    for (int l = 1; l < nl; ++l) base = base + g->A[l] * lev.p[l][i0];
+    out[i0] = base + acc[i];
+    if constexpr (EQ == kNSE) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int64_t fi = (int64_t)(a + 1) * N + i0;
+        T bj = g->Ab[0] * lev.p[0][fi];
+        for (int l = 1; l < nl; ++l) bj = bj + g->Ab[l] * lev.p[l][fi];
+        out[fi] = bj + mo[i][a];
+      }
+    }
+  }
+}
+
 // the reach m and the offset width (32-bit when a field spans < 4 GiB) as
 // template arguments
 #define MFD_GEN_LAUNCH(KERNEL, ...)                                                          \
@@ -311,6 +416,17 @@ template <class L, int EQ, typename T>
 hipError_t gnl(const Consts &c, int m, GenLevels<T> lev, T *out, const int64_t n[3],
                const GenNL<T> *g, hipStream_t st) {
   const int nx = (int)n[0], ny = (int)n[1], nz = (int)n[2];
+  if constexpr (L::D == 2) {  // the LDS tile of pair parts
+    const int tiles_x = (nx + 63) / 64, nt = tiles_x * ((ny + 7) / 8);
+    const KC<T> kc = make_kc<T>(c);
+    switch (m) {
+      case 1: hipLaunchKernelGGL((k_general_nl_tile<L, EQ, 1, T>), dim3(nt), dim3(256), 0, st, lev, out, nx, ny, tiles_x, kc, g); break;
+      case 2: hipLaunchKernelGGL((k_general_nl_tile<L, EQ, 2, T>), dim3(nt), dim3(256), 0, st, lev, out, nx, ny, tiles_x, kc, g); break;
+      case 3: hipLaunchKernelGGL((k_general_nl_tile<L, EQ, 3, T>), dim3(nt), dim3(256), 0, st, lev, out, nx, ny, tiles_x, kc, g); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz), block(64, 4);
   const KC<T> kc = make_kc<T>(c);
 #define ARGS lev, out, nx, ny, nz, kc, g
