@@ -114,8 +114,35 @@ def stats_table(db_path, top=15, by_grid=False):
     return "\n".join(L)
 
 
+def counters_table(db_paths, pattern):
+    """Markdown table: per kernel (name containing `pattern`) and launch grid,
+    the dispatch count and the mean per dispatch of every counter the result
+    databases hold (raw values: KiB for FETCH_SIZE / WRITE_SIZE)."""
+    acc = defaultdict(lambda: defaultdict(list))
+    names = set()
+    for path in db_paths:
+        db = sqlite3.connect(path)
+        q = "select kernel_name, grid_size, counter_name, value from counters_collection"
+        for name, grid, cn, val in db.execute(q):
+            if pattern in name:
+                acc[(name, int(grid))][cn].append(float(val))
+                names.add(cn)
+    cols = sorted(names)
+    out = ["| kernel [grid] | dispatches | " + " | ".join(cols) + " |",
+           "|---|---|" + "---|" * len(cols)]
+    for (name, grid), cs in sorted(acc.items()):
+        n = max(len(v) for v in cs.values())
+        vals = ["%.6g" % statistics.fmean(cs[c]) if cs.get(c) else "" for c in cols]
+        out.append("| %s [grid %d] | %d | %s |" % (name, grid, n, " | ".join(vals)))
+    return "\n".join(out)
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "counters":
+        # python -m paper_2505_17057_amd.profiling counters PATTERN DB [DB ...]
+        print(counters_table(argv[2:], argv[1]))
+        return
     if argv and argv[0] == "stats":
         # python -m paper_2505_17057_amd.profiling stats RESULTS.db [TOP] [TITLE] [COMMAND]
         top = int(argv[2]) if len(argv) > 2 else 15
