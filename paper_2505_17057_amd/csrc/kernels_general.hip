@@ -6,9 +6,11 @@
 //                                                  + Cm_lkp D1_{p,k} phi_l],
 //   D2_{p,k} g = (g(x + k e_p) - g(x)) + (g(x - k e_p) - g(x)),
 //   D1_{p,k} g = g(x + k e_p) - g(x - k e_p),
-// accumulated level by level, pairs in lattice order, then k, each product
-// and sum rounded on its own (no fused multiply-add), then the base terms
-// level by level and their sum with the accumulator.  The constants are read
+// accumulated level by level, pairs in lattice order, then k, then the base
+// terms level by level and their sum with the accumulator; in binary64 each
+// product and sum is rounded on its own (the oracle's operations, so the
+// results agree bit for bit), in binary32 the linear CDE's multiply-adds are
+// fused.  The constants are read
 // from device memory (uniform loads: the rD3Q27 tables exceed what the
 // kernel argument block comfortably holds); the neighbours come through the
 // caches (one load per neighbour and level).  The reach m is a template
@@ -21,6 +23,14 @@
 namespace mfd {
 
 namespace {
+
+// acc + c d: binary64 rounds the product and the sum on their own (the
+// oracle's operations); binary32 fuses them (one rounding, one instruction)
+template <typename T>
+__device__ __forceinline__ T gmac(T acc, T c, T d) {
+  if constexpr (std::is_same<T, float>::value) return __builtin_fmaf(c, d, acc);
+  else return acc + c * d;
+}
 
 // fourth word of a raw buffer resource on gfx9-family parts (32-bit data
 // format, no stride, no swizzle)
@@ -108,13 +118,13 @@ __global__ __launch_bounds__(256) void k_general_step(GenLevels<T> lev, T *__res
         const T gm = ld(g, nb, ix.template at<ex, ey, ez>(-k));
         const T d2 = (gp - g0) + (gm - g0);
         const T d1 = gp - gm;
-        acc = acc + gc->Cp[l][k - 1][P] * d2;
-        acc = acc + gc->Cm[l][k - 1][P] * d1;
+        acc = gmac(acc, gc->Cp[l][k - 1][P], d2);
+        acc = gmac(acc, gc->Cm[l][k - 1][P], d1);
       }
     });
   }
   T base = gc->A[0] * ld(lev.p[0], nb, i0);
-  for (int l = 1; l < nl; ++l) base = base + gc->A[l] * ld(lev.p[l], nb, i0);
+  for (int l = 1; l < nl; ++l) base = gmac(base, gc->A[l], ld(lev.p[l], nb, i0));
   *(T *)((char *)out + i0) = base + acc;
 }
 
@@ -198,12 +208,12 @@ __global__ __launch_bounds__(256) void k_general_col(GenLevels<T> lev, T *__rest
           const T gp = at(r, k * ex, k * ey, k * ez), gm = at(r, -k * ex, -k * ey, -k * ez);
           const T d2 = (gp - g0) + (gm - g0);
           const T d1 = gp - gm;
-          a_r = a_r + gc->Cp[l][k - 1][P] * d2;
-          a_r = a_r + gc->Cm[l][k - 1][P] * d1;
+          a_r = gmac(a_r, gc->Cp[l][k - 1][P], d2);
+          a_r = gmac(a_r, gc->Cm[l][k - 1][P], d1);
         }
       });
       acc[r] = a_r;
-      base[r] = l == 0 ? Al * g0 : base[r] + Al * g0;
+      base[r] = l == 0 ? Al * g0 : gmac(base[r], Al, g0);
     }
   }
 #pragma unroll
