@@ -131,6 +131,9 @@ NLC = [
     dict(name="nse-d2q9-m2-n2", lattice="D2Q9", n=(64, 45), eq="nse", m=2, nl=2),
     dict(name="nse-d3q19-m1-n3", lattice="D3Q19", n=(17, 12, 9), eq="nse", m=1, nl=3),
     dict(name="nse-d2q5-m3", lattice="D2Q5", n=(50, 37), eq="nse", m=3, nl=1),
+    # extents below the reach: the tile's halo wraps more than once
+    dict(name="tiny-nse-d2q9-m3-n2", lattice="D2Q9", n=(5, 3), eq="nse", m=3, nl=2),
+    dict(name="tiny-burgers-d2q9-m2", lattice="D2Q9", n=(66, 2), eq="burgers", m=2, nl=1),
 ]
 
 
