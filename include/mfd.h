@@ -681,7 +681,8 @@ int mfd_linear_tables(mfd_solver *s, double *w, double *ubar, double *out6);
  * the spacing per axis of a rectangular lattice, linear CDE only), eq_code,
  * the equation's parameters (u, K, lambda_bar; beta; rho0, he_luo),
  * 1 <= m <= 3, 1 <= n <= 4, a and ab (NSE momentum set; NULL: a): n rows
- * of 2m + 1 (row l = level t - l dt, entry k + m), dt > 0.  Returns MFD_OK
+ * of 2m + 1 (row l = level t - l dt, entry k + m), dt > 0; n[1] <= 262140
+ * and n[2] <= 65535 (launch-grid limits).  Returns MFD_OK
  * or MFD_W_INCONSISTENT (A00 != 1, or for the linear CDE A11 != A10) with
  * *out set; MFD_E_ARG for bad sizes or coefficients, MFD_E_UNSUPPORTED for
  * another form, boundary or equation, or a lattice / spacing the equation

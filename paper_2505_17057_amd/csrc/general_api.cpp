@@ -148,7 +148,7 @@ extern "C" int mfd_general_create(mfd_general **out, const mfd_grid *grid, int l
   if (m < 1 || m > kGenMaxM || n < 1 || n > kGenMaxLevels || !(dt > 0.0)) return MFD_E_ARG;
   for (int x = 0; x < 3; ++x)
     if (grid->n[x] < 1 || (x >= grid->dim && grid->n[x] != 1)) return MFD_E_ARG;
-  if (grid->n[2] > 65535) return MFD_E_ARG;
+  if (grid->n[1] > 4 * 65535 || grid->n[2] > 65535) return MFD_E_ARG;  // launch-grid limits
   for (int i = 0; i < n * (2 * m + 1); ++i)
     if (!std::isfinite(a[i]) || (ab && !std::isfinite(ab[i]))) return MFD_E_ARG;
   // the scheme's moments (Eq. (4-2-00a), the new level at q = 0)

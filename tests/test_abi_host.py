@@ -441,7 +441,7 @@ def test_rectangular_argument_checks(M):
 def test_general_argument_checks(M):
     """mfd_general_create refuses bad sizes and coefficients before it
     allocates anything: m in [1, 3], n in [1, 4], finite coefficients with
-    A10 < 0 < A22, a known precision."""
+    A10 < 0 < A22, a known precision, extents within the launch grid."""
     a1 = [[0.25, 0.5, 0.25, 0.0, 0.0]]
     bad = [
         dict(a=np.zeros((1, 9))),                      # m = 4
@@ -450,10 +450,15 @@ def test_general_argument_checks(M):
         dict(a=[[0.0, 1.0, 0.0]]),                     # A10 < 0 but A22 = 0
         dict(a=a1, dt=0.0),
         dict(a=a1, lattice="D2Q9", n=(8, 8), precision="fp16"),
+        dict(a=a1, lattice="D2Q9", n=(1, 4 * 65535 + 1)),  # beyond the launch grid
+        dict(a=a1, lattice="D3Q19", n=(1, 1, 65536), u=(0.1, 0.0, 0.0),
+             K=np.eye(3).tolist()),
     ]
     for kw in bad:
         args = dict(lattice="D2Q9", n=(8, 8), dx=1.0, a=a1, dt=0.1, u=(0.1, 0.0),
                     K=[[0.1, 0.0], [0.0, 0.1]])
         args.update(kw)
-        with pytest.raises((M.MfdError, KeyError)):
+        with pytest.raises((M.MfdError, KeyError)) as ei:
             M.General(**args)
+        if ei.type is M.MfdError:
+            assert ei.value.code == M.MFD_E_ARG, kw
