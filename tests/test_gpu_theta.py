@@ -193,6 +193,7 @@ NSE_TH = [
     dict(name="nse-d2q9", lattice="D2Q9", n=(96, 70)),
     dict(name="nse-d2q5", lattice="D2Q5", n=(64, 40)),
     dict(name="nse-d3q19", lattice="D3Q19", n=(14, 11, 9)),
+    dict(name="nse-d2q5ii", lattice="D2Q5II", n=(70, 19)),
 ]
 
 
