@@ -416,15 +416,18 @@ hipError_t picard_l(const Consts &c, const Grid &g, const T *x, const T *R, T *o
 template <class L, typename T>
 hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                         const double *A0, const double *dd, double th1, const double *inv_den,
-                        double *part, int *rows, hipStream_t st) {
+                        double *part, int *rows, hipStream_t st, bool rhs = false,
+                        double th = 0.0) {
   const KC<T> kc = make_kc<T>(c);
   PicardNse<T> pe{};
   pe.R = R;
   pe.th1 = (T)th1;
+  pe.th = (T)th;
+  pe.rhs = rhs ? 1 : 0;
   for (int q = 0; q < Rec<L, kNSE>::NF; ++q) {
     pe.A0[q] = (T)A0[q];
-    pe.dd[q] = (T)dd[q];
-    pe.inv_den[q] = (T)inv_den[q];
+    pe.dd[q] = dd ? (T)dd[q] : (T)0;
+    pe.inv_den[q] = inv_den ? (T)inv_den[q] : (T)0;
   }
   const int nx = (int)g.n[0], ny = (int)g.n[1];
   constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
@@ -458,6 +461,25 @@ hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, 
 }  // namespace
 
 template <typename T>
+hipError_t launch_picard_rhs_step(const Consts &c, const Grid &g, const T *x, T *R,
+                                  const double *A0, double th, double th1, hipStream_t st) {
+  if (c.three || c.eq != kNSE || c.dim != 2) return hipErrorInvalidValue;
+  int rows = 0;
+  switch (c.lattice) {
+    case 2:
+      return picard_nse_l<LatD2Q5, T>(c, g, x, nullptr, R, A0, nullptr, th1, nullptr, nullptr,
+                                      &rows, st, true, th);
+    case 3:
+      return picard_nse_l<LatD2Q9, T>(c, g, x, nullptr, R, A0, nullptr, th1, nullptr, nullptr,
+                                      &rows, st, true, th);
+    case 5:
+      return picard_nse_l<LatD2Q5II, T>(c, g, x, nullptr, R, A0, nullptr, th1, nullptr, nullptr,
+                                        &rows, st, true, th);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                                const double *A0, const double *dd, double th1,
                                const double *inv_den, double *part, int *rows, hipStream_t st) {
@@ -485,6 +507,12 @@ hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const
   }
 }
 
+template hipError_t launch_picard_rhs_step<float>(const Consts &, const Grid &, const float *,
+                                                  float *, const double *, double, double,
+                                                  hipStream_t);
+template hipError_t launch_picard_rhs_step<double>(const Consts &, const Grid &, const double *,
+                                                   double *, const double *, double, double,
+                                                   hipStream_t);
 template hipError_t launch_picard_sweep<float>(const Consts &, const Grid &, const float *,
                                                const float *, float *, const double *,
                                                const double *, double, const double *, double *,

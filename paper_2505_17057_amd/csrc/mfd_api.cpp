@@ -532,8 +532,13 @@ int Solver::theta_picard_steps(int64_t nsteps) {
   double *out = part + kReduceBlocks * 8;
   const int64_t N = G.N;
   for (int64_t s = 0; s < nsteps; ++s) {
-    hipError_t e = launch_mmfd_step<T>(consts, G, B[ic], nullptr, B[6], 1, stream);
-    if (e == hipSuccess) e = launch_picard_rhs<T>(B[6], B[ic], B[5], th, th1, F, A0, N, stream);
+    hipError_t e;
+    if (fused && consts.eq == kNSE) {
+      e = launch_picard_rhs_step<T>(consts, G, B[ic], B[5], A0, th, th1, stream);
+    } else {
+      e = launch_mmfd_step<T>(consts, G, B[ic], nullptr, B[6], 1, stream);
+      if (e == hipSuccess) e = launch_picard_rhs<T>(B[6], B[ic], B[5], th, th1, F, A0, N, stream);
+    }
     if (e != hipSuccess) return hip(e, "picard rhs launch");
     const T *src = B[ic];
     int k = 0;

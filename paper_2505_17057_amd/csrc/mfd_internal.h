@@ -351,6 +351,12 @@ template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                                const double *A0, const double *dd, double th1,
                                const double *inv_den, double *part, int *rows, hipStream_t st);
+// the 2D NSE's theta right-hand side R = theta S(x) + (1 - theta) (A0 x) per
+// field, formed at the store of the explicit step (hipErrorInvalidValue for
+// other equations and grids)
+template <typename T>
+hipError_t launch_picard_rhs_step(const Consts &c, const Grid &g, const T *x, T *R,
+                                  const double *A0, double th, double th1, hipStream_t st);
 // out[q] = sum of the rows' quantity q (q < nq <= 8) in a fixed order
 hipError_t launch_final_sums(const double *partial, int rows, int nq, double *out, hipStream_t st);
 // per field f < F (<= 4; field f at offset f N): sum (a - b)^2 and sum c^2 in

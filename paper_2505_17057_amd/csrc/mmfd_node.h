@@ -302,11 +302,14 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 // and roundings of the separate elementwise update).
 // part (may be null): the sweep also adds, per field, (x_new - x)^2 and R^2
 // in binary64 into per-workgroup partial sums (rows of 8 doubles).
+// rhs: instead of a sweep, the step's right-hand side
+// R_q = th S_q(x) + th1 (A0_q x_q) (the operations of the separate pass).
 template <typename T>
 struct PicardNse {
   const T *R;
   T A0[4], dd[4], inv_den[4];
-  T th1;
+  T th1, th;
+  int rhs;
   double *part;
 };
 
@@ -428,7 +431,14 @@ struct PfTile {
       } else {
         mmfd_node<L, kNSE, THREE, THREE_ST, T, false, true>(at, ath, cc, pc, oc, kc);
       }
-      if (pe) {
+      if (pe && pe->rhs) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+          const T a = pe->th * oc[q];
+          const T b = pe->A0[q] * cc[q];
+          oc[q] = a + pe->th1 * b;
+        }
+      } else if (pe) {
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
           const T xi = cc[q];
