@@ -502,22 +502,39 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
   __shared__ T hrec[THREE_ST ? NR : 1][THREE_ST ? HY : 1][THREE_ST ? HX : 1];
   const int64_t N = (int64_t)nx * ny;
 
-  for (int i = threadIdx.x; i < HX * HY; i += 256) {
-    const int lx = i % HX, ly = i / HX;
-    const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - HYL + ly, ny);
-    const int64_t gi = (int64_t)gy * nx + gx;
-    T m[NF], r[NR];
+  // every load of the thread's halo-tile nodes is issued before the first
+  // record is formed (the loads' latencies overlap)
+  constexpr int KH = (HX * HY + 255) / 256;
+  T mv[KH][NF], hv[THREE_ST ? KH : 1][NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) m[f] = cur[f * N + gi];
-    make_record<L, EQ>(m, r, kc);
+  for (int j = 0; j < KH; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < HX * HY) {
+      const int lx = i % HX, ly = i / HX;
+      const int gx = wrapi(x0 - 1 + lx, nx), gy = wrapi(y0 - HYL + ly, ny);
+      const int64_t gi = (int64_t)gy * nx + gx;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
-    if constexpr (THREE_ST) {
+      for (int f = 0; f < NF; ++f) mv[j][f] = cur[f * N + gi];
+      if constexpr (THREE_ST) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) m[f] = prev[f * N + gi];
-      make_record<L, EQ>(m, r, kc);
+        for (int f = 0; f < NF; ++f) hv[j][f] = prev[f * N + gi];
+      }
+    }
+  }
 #pragma unroll
-      for (int k = 0; k < NR; ++k) hrec[k][ly][lx] = r[k];
+  for (int j = 0; j < KH; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < HX * HY) {
+      const int lx = i % HX, ly = i / HX;
+      T r[NR];
+      make_record<L, EQ>(mv[j], r, kc);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) rec[k][ly][lx] = r[k];
+      if constexpr (THREE_ST) {
+        make_record<L, EQ>(hv[j], r, kc);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) hrec[k][ly][lx] = r[k];
+      }
     }
   }
   __syncthreads();
