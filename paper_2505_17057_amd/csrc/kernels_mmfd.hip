@@ -393,18 +393,34 @@ hipError_t launch_mmfd_step(const Consts &c, const Grid &g, const T *cur, const 
 namespace {
 template <class L, typename T>
 hipError_t picard_l(const Consts &c, const Grid &g, const T *x, const T *R, T *out, double A0,
-                    double dd, double th1, double inv_den, hipStream_t st) {
+                    double dd, double th1, double inv_den, double *part, int *rows,
+                    hipStream_t st) {
   const KC<T> kc = make_kc<T>(c);
-  const PicardEp<T> pe{R, (T)A0, (T)dd, (T)th1, (T)inv_den};
+  PicardEp<T> pe{R, (T)A0, (T)dd, (T)th1, (T)inv_den, nullptr};
   const int nx = (int)g.n[0], ny = (int)g.n[1];
   if constexpr (L::D == 1) {
     constexpr int TX = 1024, TY = 1;
     const int tx = (nx + TX - 1) / TX;
+    if (part && tx <= kReduceBlocks) {  // one row of residual sums per workgroup
+      pe.part = part;
+      *rows = tx;
+    }
     hipLaunchKernelGGL((k_picard_plane<L, true, TX, TY, T>), dim3(tx), dim3(256), 0, st, x, out,
                        nx, 1, tx, tx, kc, pe);
   } else {
     constexpr int TX = 64, TY = 16;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    const int ty2 = (ny + 2 * TY - 1) / (2 * TY);
+    if (part && tx * ty <= kReduceBlocks) {
+      pe.part = part;
+      *rows = tx * ty;
+    } else if (part && tx * ty2 <= kReduceBlocks) {  // taller tiles: one row per workgroup
+      pe.part = part;
+      *rows = tx * ty2;
+      hipLaunchKernelGGL((k_picard_plane<L, true, TX, 2 * TY, T>), dim3(tx * ty2), dim3(256), 0,
+                         st, x, out, nx, ny, tx, tx * ty2, kc, pe);
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_picard_plane<L, true, TX, TY, T>), dim3(tx * ty), dim3(256), 0, st, x,
                        out, nx, ny, tx, tx * ty, kc, pe);
   }
@@ -499,10 +515,15 @@ hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const
   }
   if (c.eq != kBurgers) return hipErrorInvalidValue;
   switch (c.lattice) {
-    case 1: return picard_l<LatD1Q3, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
-    case 2: return picard_l<LatD2Q5, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
-    case 3: return picard_l<LatD2Q9, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
-    case 5: return picard_l<LatD2Q5II, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], st);
+    case 1:
+      return picard_l<LatD1Q3, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], part, rows, st);
+    case 2:
+      return picard_l<LatD2Q5, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], part, rows, st);
+    case 3:
+      return picard_l<LatD2Q9, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], part, rows, st);
+    case 5:
+      return picard_l<LatD2Q5II, T>(c, g, x, R, out, A0[0], dd[0], th1, inv_den[0], part, rows,
+                                    st);
     default: return hipErrorInvalidValue;
   }
 }

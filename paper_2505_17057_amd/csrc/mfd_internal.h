@@ -344,9 +344,9 @@ hipError_t launch_picard_update(const T *Sx, const T *x, const T *R, T *out, int
 // one Picard-Jacobi sweep of the theta step fused with the explicit step of
 // the iterate: Burgers' equation on 1D / 2D grids (field 0's constants) and
 // the NSE on 2D grids (per-field constants); hipErrorInvalidValue otherwise
-// part (may be null): where the kernel supports it (the 2D NSE), the sweep
-// also writes per-workgroup binary64 rows of (x_new - x)^2 and R^2 per field
-// (8 doubles a row) and sets *rows to their count (else *rows = 0)
+// part (may be null): the sweep also writes per-workgroup binary64 rows of
+// (x_new - x)^2 and R^2 per field (8 doubles a row) and sets *rows to their
+// count, when the workgroups fit kReduceBlocks rows (else *rows = 0)
 template <typename T>
 hipError_t launch_picard_sweep(const Consts &c, const Grid &g, const T *x, const T *R, T *out,
                                const double *A0, const double *dd, double th1,

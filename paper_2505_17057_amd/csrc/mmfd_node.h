@@ -478,10 +478,13 @@ __device__ __forceinline__ void mmfd_plane_tile_pf(const T *__restrict__ cur,
 // Sweep of the Picard-Jacobi iteration of Burgers' theta step, applied to
 // the explicit step value S(x) of a node: out = (R + th1 ((S - A0 x) +
 // dd x)) inv_den (the operations and roundings of the separate update).
+// part (may be null): the sweep also forms (x_new - x)^2 and R^2 in binary64
+// and writes the workgroup's sums to row blockIdx.x (8 doubles a row).
 template <typename T>
 struct PicardEp {
   const T *R;
   T A0, dd, th1, inv_den;
+  double *part;
 };
 
 template <class L, int EQ, bool THREE, bool THREE_ST, int TX, int TY, typename T>
@@ -539,6 +542,7 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
   }
   __syncthreads();
 
+  double sq0 = 0.0, sq1 = 0.0;  // residual sums of a Picard sweep with pe->part
   for (int i = threadIdx.x; i < TX * TY; i += 256) {
     const int lx = i % TX, ly = i / TX;
     const int gx = x0 + lx, gy = y0 + ly;
@@ -567,11 +571,35 @@ __device__ __forceinline__ void mmfd_plane_tile(const T *__restrict__ cur,
         const T xi = cc[0];
         const T t = (oc[0] - pe->A0 * xi) + pe->dd * xi;
         const T c = pe->th1 * t;
-        oc[0] = (pe->R[gi] + c) * pe->inv_den;
+        const T Ri = pe->R[gi];
+        oc[0] = (Ri + c) * pe->inv_den;
+        if (pe->part) {
+          const double d = (double)oc[0] - (double)xi;
+          sq0 += d * d;
+          sq1 += (double)Ri * (double)Ri;
+        }
       }
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f * N + gi] = oc[f];
+  }
+  if (pe && pe->part) {  // the workgroup's row: wave sums, then the four waves in order
+    __shared__ double red[2][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sq0 += __shfl_xor(sq0, o, 64);
+      sq1 += __shfl_xor(sq1, o, 64);
+    }
+    if (lane == 0) {
+      red[0][wave] = sq0;
+      red[1][wave] = sq1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      const int q = threadIdx.x;
+      pe->part[blockIdx.x * 8 + q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+    }
   }
   }
 }
