@@ -279,7 +279,7 @@ hipError_t launch_cfg(const Consts &c, const Grid &g, const T *cur, const T *pre
     hipLaunchKernelGGL((k_mmfd_plane<L, EQ, THREE, THREE_ST, TX, TY, T>), dim3(tx), dim3(256), 0,
                        st, cur, prev, out, nx, 1, tx, tx, kc, bc);
   } else if constexpr (L::D == 2 && EQ == kNSE) {
-    constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
+    constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 4;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
     const int ntiles = tx * ty;
     // persistent groups: as many as the tile's LDS lets reside on each CU
@@ -446,7 +446,7 @@ hipError_t picard_nse_l(const Consts &c, const Grid &g, const T *x, const T *R, 
     pe.inv_den[q] = inv_den ? (T)inv_den[q] : (T)0;
   }
   const int nx = (int)g.n[0], ny = (int)g.n[1];
-  constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 8;
+  constexpr int TX = 64, TY = sizeof(T) == 4 ? 16 : 4;
   const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
   const int ntiles = tx * ty;
   constexpr int per_cu = (int)((160 * 1024) / sizeof(typename PfTile<L, false, false, TX, TY, T>::Lds));
