@@ -541,7 +541,11 @@ int theta_fused_rows(const Consts &c, const Grid &g, int K, int elem) {
   if (kThetaW - 2 * halo < 8 || g.n[0] < kThetaW) return 0;
   for (int h : {64, 48, 32}) {
     if (h - 2 * halo < 8 || g.n[1] < h) continue;
-    if ((size_t)3 * h * kThetaW * elem > 64 * 1024) continue;
+    // three W x h arrays; at most half of the 160 KiB of a CU (two workgroups)
+    if ((size_t)3 * h * kThetaW * elem > 80 * 1024) continue;
+    // at least a fifth of the window stored (else the recomputed halo costs
+    // more than the separate sweeps save)
+    if (5 * (kThetaW - 2 * halo) * (h - 2 * halo) < kThetaW * h) continue;
     return h;
   }
   return 0;
