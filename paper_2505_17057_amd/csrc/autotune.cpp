@@ -165,13 +165,23 @@ int Solver::autotune(int32_t *chosen) {
                    [](const std::pair<float, TbPlan> &a, const std::pair<float, TbPlan> &b) {
                      return a.first < b.first;
                    });
+  // the finalists are timed in three interleaved rounds and each keeps its
+  // fastest round, so a drift of the clocks during the refinement does not
+  // decide between plans a few per cent apart
+  const size_t nfin = std::min<size_t>(timed.size(), 4);
+  std::vector<float> fin_ms(nfin, 1e30f);
+  for (int round = 0; round < 3 && !rc; ++round) {
+    for (size_t i = 0; i < nfin && !rc; ++i) {
+      float ms = 0.f;
+      rc = time_plan(timed[i].second, 4 * trial0, &ms);
+      if (!rc) fin_ms[i] = std::min(fin_ms[i], ms);
+    }
+  }
   float best_ms = 1e30f;
   TbPlan best{1, 0};
-  for (size_t i = 0; i < timed.size() && i < 4 && !rc; ++i) {
-    float ms = 0.f;
-    rc = time_plan(timed[i].second, 4 * trial0, &ms);
-    if (!rc && ms < best_ms) {
-      best_ms = ms;
+  for (size_t i = 0; i < nfin; ++i) {
+    if (fin_ms[i] < best_ms) {
+      best_ms = fin_ms[i];
       best = timed[i].second;
     }
   }
