@@ -539,7 +539,7 @@ int theta_fused_rows(const Consts &c, const Grid &g, int K, int elem) {
   if (c.dim != 2 || (c.lattice != 2 && c.lattice != 3) || K < 1) return 0;
   const int halo = K + 1;
   if (kThetaW - 2 * halo < 8 || g.n[0] < kThetaW) return 0;
-  for (int h : {64, 48, 32}) {
+  for (int h : {96, 64, 48, 32}) {
     if (h - 2 * halo < 8 || g.n[1] < h) continue;
     // three W x h arrays; at most half of the 160 KiB of a CU (two workgroups)
     if ((size_t)3 * h * kThetaW * elem > 80 * 1024) continue;
